@@ -1,0 +1,306 @@
+"""CPU oracle for the resilient HHG multigrid hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``.  The product package never imports
+it, and it shares no code with the GPU path.
+
+The numerics live in ``hhg_oracle.c`` (plain C + OpenMP, FP64 unless stated);
+this module only marshals numpy arrays.  Vectors are over the interior nodes in
+global lexicographic order, element arrays in cell-lexicographic x 6 Kuhn
+permutation order (see ``paper_1506_06185_amd.inputs``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hhg_oracle.c")
+_LIB = os.path.join(_HERE, "libhhg_oracle.so")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_lp = C.POINTER(C.c_longlong)
+_up = C.POINTER(C.c_ubyte)
+_vp = C.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-D_POSIX_C_SOURCE=199309L", "-shared", "-fPIC",
+               "-Wall", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    L = C.CDLL(_LIB)
+    sig = {
+        "ohhg_create": (_vp, [C.c_int, C.c_int, C.c_int, _dp]),
+        "ohhg_destroy": (None, [_vp]),
+        "ohhg_threads": (C.c_int, []),
+        "ohhg_setup_seconds": (C.c_double, [_vp]),
+        "ohhg_ndof": (C.c_longlong, [_vp, C.c_int]),
+        "ohhg_nelem": (C.c_longlong, [_vp, C.c_int]),
+        "ohhg_cells": (C.c_int, [_vp, C.c_int]),
+        "ohhg_elements": (None, [_vp, C.c_int, _ip, _lp]),
+        "ohhg_coeff": (None, [_vp, C.c_int, _dp]),
+        "ohhg_volume_sum": (C.c_double, [_vp, C.c_int]),
+        "ohhg_check_freudenthal": (C.c_int, [_vp, C.c_int]),
+        "ohhg_matrix": (_vp, [_vp, C.c_int, C.c_int]),
+        "ohhg_matrix_rows": (C.c_longlong, [_vp]),
+        "ohhg_matrix_cols": (C.c_longlong, [_vp]),
+        "ohhg_matrix_nnz": (C.c_longlong, [_vp]),
+        "ohhg_matrix_copy": (None, [_vp, _lp, _ip, _dp]),
+        "ohhg_matrix_free": (None, [_vp]),
+        "ohhg_tet_mask": (None, [_vp, C.c_int, C.c_int, C.c_int, _up]),
+        "ohhg_containment_counts": (None, [_vp, C.c_int, _ip]),
+        "ohhg_apply_A": (None, [_vp, C.c_int, _dp, _dp]),
+        "ohhg_apply_M": (None, [_vp, C.c_int, _dp, _dp]),
+        "ohhg_residual": (None, [_vp, C.c_int, _dp, _dp, _dp]),
+        "ohhg_smooth": (None, [_vp, C.c_int, _dp, _dp, C.c_double, C.c_int]),
+        "ohhg_restrict": (None, [_vp, C.c_int, _dp, _dp]),
+        "ohhg_prolong_add": (None, [_vp, C.c_int, _dp, _dp]),
+        "ohhg_coarse_solve": (C.c_int, [_vp, _dp, _dp, C.c_double]),
+        "ohhg_vcycle": (C.c_double, [_vp, _dp, _dp, C.c_double, C.c_int, C.c_int]),
+        "ohhg_solve": (C.c_int, [_vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 C.c_double, _dp]),
+        "ohhg_solve_mixed": (C.c_int, [_vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_double,
+                                       C.c_int, C.c_double, _dp]),
+        "ohhg_inject_fault": (None, [_vp, C.c_int, _dp]),
+        "ohhg_recover_local": (None, [_vp, _ip, C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int,
+                                      C.c_int, _dp]),
+        "ohhg_dd_intact": (None, [_vp, _ip, C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int, C.c_int]),
+        "ohhg_grad_k": (None, [_vp, _dp, _dp, _dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def threads() -> int:
+    return int(lib().ohhg_threads())
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Problem:
+    """Poisson / variable-coefficient problem on the n^3 x 6 Kuhn macro mesh.
+
+    ``level`` counts refinements of the macro mesh (N = n_sub 2^level cells per
+    axis); the multigrid hierarchy runs from ``coarse_level`` (default 2, one
+    inner node per macro tetrahedron) to ``level``.  ``k`` is the per-element
+    coefficient on the finest level (None: k = 1).
+    """
+
+    def __init__(self, n_sub: int, level: int, coarse_level: int = 2, k=None):
+        self.n_sub, self.level, self.coarse_level = int(n_sub), int(level), int(coarse_level)
+        self._k = None if k is None else _f64(k)
+        kp = None if self._k is None else _d(self._k)
+        self._h = lib().ohhg_create(self.n_sub, self.level, self.coarse_level, kp)
+        if not self._h:
+            raise ValueError("invalid oracle problem parameters")
+        self.N = self.n_sub << self.level
+        self.ndof = int(lib().ohhg_ndof(self._h, self.level))
+        self.n_tets = 6 * self.n_sub ** 3
+
+    def close(self):
+        if self._h:
+            lib().ohhg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- mesh ---------------------------------------------------------------
+    @property
+    def setup_seconds(self) -> float:
+        return float(lib().ohhg_setup_seconds(self._h))
+
+    def ndof_at(self, level: int) -> int:
+        return int(lib().ohhg_ndof(self._h, level))
+
+    def nelem_at(self, level: int) -> int:
+        return int(lib().ohhg_nelem(self._h, level))
+
+    def elements(self, level: int):
+        ne = self.nelem_at(level)
+        ev = np.empty((ne, 4), dtype=np.int32)
+        ecl = np.empty(ne, dtype=np.int64)
+        lib().ohhg_elements(self._h, level, ev.ctypes.data_as(_ip), ecl.ctypes.data_as(_lp))
+        return ev, ecl
+
+    def coeff(self, level: int) -> np.ndarray:
+        k = np.empty(self.nelem_at(level))
+        lib().ohhg_coeff(self._h, level, _d(k))
+        return k
+
+    def volume_sum(self, level: int) -> float:
+        return float(lib().ohhg_volume_sum(self._h, level))
+
+    def check_freudenthal(self, level: int) -> bool:
+        return bool(lib().ohhg_check_freudenthal(self._h, level))
+
+    def tet_mask(self, tet: int, closure: bool = False, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        m = np.empty(self.ndof_at(level), dtype=np.uint8)
+        lib().ohhg_tet_mask(self._h, level, int(tet), int(bool(closure)), m.ctypes.data_as(_up))
+        return m.astype(bool)
+
+    def containment_counts(self, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        c = np.empty(self.ndof_at(level), dtype=np.int32)
+        lib().ohhg_containment_counts(self._h, level, c.ctypes.data_as(_ip))
+        return c
+
+    # -- matrices -----------------------------------------------------------
+    def matrix(self, level: int, which: str = "A", full: bool = False):
+        """scipy CSR of A (stiffness), M (mass) or P (level-1 -> level)."""
+        import scipy.sparse as sp
+
+        code = {"A": 0, "M": 1, "P": 2}[which] + (3 if full else 0)
+        h = lib().ohhg_matrix(self._h, level, code)
+        try:
+            n = int(lib().ohhg_matrix_rows(h))
+            m = int(lib().ohhg_matrix_cols(h))
+            nnz = int(lib().ohhg_matrix_nnz(h))
+            ptr = np.empty(n + 1, dtype=np.int64)
+            col = np.empty(nnz, dtype=np.int32)
+            val = np.empty(nnz, dtype=np.float64)
+            lib().ohhg_matrix_copy(h, ptr.ctypes.data_as(_lp), col.ctypes.data_as(_ip), _d(val))
+        finally:
+            lib().ohhg_matrix_free(h)
+        return sp.csr_matrix((val, col, ptr), shape=(n, m))
+
+    # -- operators ----------------------------------------------------------
+    def apply_A(self, u, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        u = _f64(u)
+        out = np.empty_like(u)
+        lib().ohhg_apply_A(self._h, level, _d(u), _d(out))
+        return out
+
+    def apply_M(self, u, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        u = _f64(u)
+        out = np.empty_like(u)
+        lib().ohhg_apply_M(self._h, level, _d(u), _d(out))
+        return out
+
+    def residual(self, u, b, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        u, b = _f64(u), _f64(b)
+        r = np.empty_like(u)
+        lib().ohhg_residual(self._h, level, _d(u), _d(b), _d(r))
+        return r
+
+    def smooth(self, u, b, omega: float = 1.25, colours: int = 3, level: int | None = None) -> np.ndarray:
+        """Returns u after a red (1), black (2) or red+black (3) SOR pass."""
+        level = self.level if level is None else level
+        u = _f64(u).copy()
+        b = _f64(b)
+        lib().ohhg_smooth(self._h, level, _d(u), _d(b), float(omega), int(colours))
+        return u
+
+    def restrict(self, r, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        r = _f64(r)
+        bc = np.empty(self.ndof_at(level - 1))
+        lib().ohhg_restrict(self._h, level, _d(r), _d(bc))
+        return bc
+
+    def prolong_add(self, ec, u, level: int | None = None) -> np.ndarray:
+        level = self.level if level is None else level
+        ec = _f64(ec)
+        u = _f64(u).copy()
+        lib().ohhg_prolong_add(self._h, level, _d(ec), _d(u))
+        return u
+
+    def coarse_solve(self, b, rtol: float = 1e-14):
+        b = _f64(b)
+        x = np.zeros_like(b)
+        it = lib().ohhg_coarse_solve(self._h, _d(b), _d(x), float(rtol))
+        return x, int(it)
+
+    def vcycle(self, u, b, omega: float = 1.25, nu1: int = 2, nu2: int = 1):
+        u = _f64(u).copy()
+        b = _f64(b)
+        rn = lib().ohhg_vcycle(self._h, _d(u), _d(b), float(omega), int(nu1), int(nu2))
+        return u, float(rn)
+
+    def solve(self, b, u0=None, omega: float = 1.25, nu1: int = 2, nu2: int = 1, rtol: float = 1e-8,
+              max_cycles: int = 100, r0: float = 0.0):
+        """V-cycles until ||b - A u|| <= rtol * r0; returns (u, cycles, history)."""
+        b = _f64(b)
+        u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
+        hist = np.zeros(max_cycles + 1)
+        c = lib().ohhg_solve(self._h, _d(u), _d(b), float(omega), int(nu1), int(nu2), float(rtol),
+                             int(max_cycles), float(r0), _d(hist))
+        n = max_cycles if c < 0 else c
+        return u, int(c), hist[: n + 1].copy()
+
+    def solve_mixed(self, b, u0=None, omega: float = 1.25, nu1: int = 2, nu2: int = 1,
+                    rtol: float = 1e-8, max_steps: int = 100, r0: float = 0.0):
+        b = _f64(b)
+        u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
+        hist = np.zeros(max_steps + 1)
+        c = lib().ohhg_solve_mixed(self._h, _d(u), _d(b), float(omega), int(nu1), int(nu2),
+                                   float(rtol), int(max_steps), float(r0), _d(hist))
+        n = max_steps if c < 0 else c
+        return u, int(c), hist[: n + 1].copy()
+
+    # -- fault and recovery -------------------------------------------------
+    def inject_fault(self, tet: int, u) -> np.ndarray:
+        u = _f64(u).copy()
+        lib().ohhg_inject_fault(self._h, int(tet), _d(u))
+        return u
+
+    def recover_local(self, tets, u, b, n_cycles: int = 3, omega: float = 1.25, nu1: int = 2,
+                      nu2: int = 1):
+        tets = np.ascontiguousarray(np.atleast_1d(tets), dtype=np.int32)
+        u = _f64(u).copy()
+        b = _f64(b)
+        res = np.zeros(max(n_cycles, 1))
+        lib().ohhg_recover_local(self._h, tets.ctypes.data_as(_ip), len(tets), _d(u), _d(b),
+                                 int(n_cycles), float(omega), int(nu1), int(nu2), _d(res))
+        return u, res[:n_cycles].copy()
+
+    def dd_intact(self, tets, u, b, n_cycles: int, omega: float = 1.25, nu1: int = 2, nu2: int = 1):
+        tets = np.ascontiguousarray(np.atleast_1d(tets), dtype=np.int32)
+        u = _f64(u).copy()
+        b = _f64(b)
+        lib().ohhg_dd_intact(self._h, tets.ctypes.data_as(_ip), len(tets), _d(u), _d(b),
+                             int(n_cycles), float(omega), int(nu1), int(nu2))
+        return u
+
+    # -- gradients ----------------------------------------------------------
+    def grad_k(self, u, lam) -> np.ndarray:
+        u, lam = _f64(u), _f64(lam)
+        out = np.empty(self.nelem_at(self.level))
+        lib().ohhg_grad_k(self._h, _d(u), _d(lam), _d(out))
+        return out

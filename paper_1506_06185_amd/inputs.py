@@ -1,0 +1,117 @@
+"""Seeded synthetic inputs for the unit-cube workloads.
+
+This module is shared by the GPU path's callers (tests, benchmark) and by the
+oracle-side tests.  It holds no multigrid arithmetic: only random draws and
+point evaluations of the source function, returned in the user-facing orders
+
+* interior nodes: global lexicographic, index = (x-1) + (N-1)*((y-1) + (N-1)*(z-1)),
+  x fastest, with N = n_sub * 2**level cells per axis and h = 1/N;
+* elements: cell-lexicographic (cx + N*(cy + N*cz)) times 6 Kuhn permutations
+  in the order (0,1,2), (0,2,1), (1,0,2), (1,2,0), (2,0,1), (2,1,0).
+
+Every random draw uses ``numpy.random.default_rng([seed, stream])`` with one
+stream per quantity, so any input can be rebuilt from (seed, shape) alone.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+STREAM_FAULT_TET = 1
+STREAM_UNIFORM_RHS = 2
+STREAM_LOG_K = 3
+STREAM_U_OBS = 4
+STREAM_FD_DIRS = 5
+STREAM_BATCH_SIZES = 6
+STREAM_BATCH_FAULTS = 7
+
+
+def rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng([int(seed), int(stream)])
+
+
+def cells_per_axis(n_sub: int, level: int) -> int:
+    return int(n_sub) << int(level)
+
+
+def n_interior(n_sub: int, level: int) -> int:
+    return (cells_per_axis(n_sub, level) - 1) ** 3
+
+
+def n_macro_tets(n_sub: int) -> int:
+    return 6 * n_sub ** 3
+
+
+def n_elements(n_sub: int, level: int) -> int:
+    return 6 * cells_per_axis(n_sub, level) ** 3
+
+
+def interior_axis(n_sub: int, level: int) -> np.ndarray:
+    """Coordinates 1/N .. (N-1)/N of the interior grid lines."""
+    N = cells_per_axis(n_sub, level)
+    return np.arange(1, N, dtype=np.float64) / N
+
+
+def sine_source(n_sub: int, level: int) -> np.ndarray:
+    """f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) at the interior nodes (lex order).
+
+    It is the source whose exact solution of -Laplace(u) = f with u = 0 on the
+    cube's boundary is u = sin(pi x) sin(pi y) sin(pi z).
+    """
+    s = np.sin(math.pi * interior_axis(n_sub, level))
+    f = (3.0 * math.pi ** 2) * (s[None, None, :] * s[None, :, None] * s[:, None, None])
+    return np.ascontiguousarray(f.reshape(-1))
+
+
+def sine_solution(n_sub: int, level: int) -> np.ndarray:
+    """u = sin(pi x) sin(pi y) sin(pi z) at the interior nodes (lex order)."""
+    s = np.sin(math.pi * interior_axis(n_sub, level))
+    u = s[None, None, :] * s[None, :, None] * s[:, None, None]
+    return np.ascontiguousarray(u.reshape(-1))
+
+
+def uniform_load(n_sub: int, level: int, seed: int = 0) -> np.ndarray:
+    """Load vector entries drawn from U[-1, 1] (used directly as b)."""
+    return rng(seed, STREAM_UNIFORM_RHS).uniform(-1.0, 1.0, n_interior(n_sub, level))
+
+
+def lognormal_k(n_sub: int, level: int, seed: int = 0, sigma: float = 0.5) -> np.ndarray:
+    """Per-element diffusion coefficient k = exp(sigma * Z), Z ~ N(0, 1)."""
+    z = rng(seed, STREAM_LOG_K).standard_normal(n_elements(n_sub, level))
+    return np.exp(sigma * z)
+
+
+def gaussian_obs(n_sub: int, level: int, seed: int = 0) -> np.ndarray:
+    """Observation u_obs ~ N(0, 1) per interior node."""
+    return rng(seed, STREAM_U_OBS).standard_normal(n_interior(n_sub, level))
+
+
+def fd_directions(size: int, count: int, seed: int = 0, offset: int = 0) -> np.ndarray:
+    """`count` directions of length `size`, N(0,1) entries, each scaled to unit 2-norm.
+
+    ``offset`` skips that many earlier directions of the same stream so that
+    the directions for f and for k are distinct draws.
+    """
+    g = rng(seed, STREAM_FD_DIRS)
+    if offset:
+        g.standard_normal((offset, size))
+    d = g.standard_normal((count, size))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d
+
+
+def fault_tet(n_sub: int, seed: int = 0) -> int:
+    """Macro tetrahedron that fails (uniform over the 6 n^3 macro-tets)."""
+    return int(rng(seed, STREAM_FAULT_TET).integers(n_macro_tets(n_sub)))
+
+
+def batch_levels(count: int, seed: int = 0, lo: int = 5, hi: int = 7) -> np.ndarray:
+    """Refinement levels of a batch of independent n_sub = 2 problems, uniform in [lo, hi]."""
+    return rng(seed, STREAM_BATCH_SIZES).integers(lo, hi + 1, size=count)
+
+
+def batch_faults(n_faults: int, n_sub: int, seed: int = 0) -> np.ndarray:
+    """Distinct faulty macro-tets for the concurrent-recovery workload."""
+    g = rng(seed, STREAM_BATCH_FAULTS)
+    return np.sort(g.choice(n_macro_tets(n_sub), size=n_faults, replace=False))
