@@ -1,0 +1,210 @@
+/*
+ * hhgr.h -- C ABI of the MI355X hierarchical-hybrid-grid (HHG) multigrid
+ * library with fault recovery (Huber, Gmeiner, Ruede, Wohlmuth, "Resilience
+ * for Multigrid Software at the Extreme Scale").
+ *
+ * Problem (Sec. 2.1, eqs. (1)-(2)): -div(k grad u) = f on the unit cube with
+ * u = 0 on its boundary, conforming P1 finite elements on a hierarchy of
+ * uniformly refined tetrahedral meshes.  The base mesh splits the cube into
+ * n^3 subcubes, each into 6 Kuhn tetrahedra (the macro tetrahedra, one per
+ * process in the paper); level L is L uniform refinements of it, so a level
+ * has N = n 2^L cells per axis and h = 1/N.  The paper's coarsest level, with
+ * one inner node per macro tetrahedron, is level 2 here.
+ *
+ * Data orders seen by callers
+ *   vectors  (FP64, length (N-1)^3): interior grid node (x,y,z), 1 <= x,y,z <= N-1,
+ *            at index (x-1) + (N-1)*((y-1) + (N-1)*(z-1)), x fastest;
+ *   elements (FP64, length 6 N^3): element 6*cell + perm, cell = cx + N*(cy + N*cz)
+ *            is its lowest corner and perm indexes its axis steps in the order
+ *            (0,1,2),(0,2,1),(1,0,2),(1,2,0),(2,0,1),(2,1,0);
+ *   macro tetrahedra: tet id = 6*subcube + perm in the same way on the n^3 grid.
+ *
+ * Memory and streams
+ *   The caller owns every device buffer: the workspace handed to hhgr_create
+ *   (size from hhgr_workspace_bytes) and all vectors.  The library borrows the
+ *   workspace for the lifetime of the context and never allocates device
+ *   memory; it allocates a few bytes of pinned host memory per context for
+ *   residual read-back.  Work is enqueued on the stream given at creation;
+ *   calls that return a host scalar synchronise that stream.  Device pointers
+ *   passed to a call must stay valid until that stream reaches the call.
+ *
+ * Errors
+ *   Every int-returning call returns HHGR_OK or a negative code; no exception
+ *   crosses the ABI.  hhgr_last_error() returns a thread-local description of
+ *   the last failure on the calling thread.
+ */
+#ifndef HHGR_H
+#define HHGR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hhgr_ctx hhgr_ctx;
+typedef struct hhgr_batch hhgr_batch;
+
+enum {
+    HHGR_OK = 0,
+    HHGR_EINVAL = -1,  /* bad argument: level, tet id, null pointer, size */
+    HHGR_ENOMEM = -2,  /* workspace smaller than hhgr_workspace_bytes */
+    HHGR_EHIP = -3,    /* a HIP runtime call failed */
+    HHGR_ESTATE = -4,  /* call not valid in the current state (e.g. no right-hand side yet) */
+    HHGR_ENOCONV = -5  /* max_cycles reached before the tolerance; outputs still filled */
+};
+
+enum { HHGR_FP64 = 0, HHGR_MIXED = 1 };
+enum { HHGR_RHS_LOAD = 0, HHGR_RHS_NODAL_F = 1 };
+
+/* Solver description.  hhgr_desc_default fills the defaults shown. */
+typedef struct {
+    int n_sub;          /* subcubes per axis (>= 1); 6 n^3 macro tetrahedra            */
+    int level;          /* finest level L, coarse_level+1 <= L <= 9                      */
+    int coarse_level;   /* coarsest level, default 2 (Sec. 2.1: one inner node per tet) */
+    int nu_pre;         /* pre-smoothing sweeps, default 2                              */
+    int nu_post;        /* post-smoothing sweeps, default 1                             */
+    double omega;       /* SOR factor of the red-black smoother, default 1.25 (1 = GS)  */
+    int precision;      /* HHGR_FP64 or HHGR_MIXED (FP32 cycle, FP64 refinement)        */
+    int variable_coeff; /* 0: k = 1; 1: per-element k from hhgr_set_coeff               */
+    int max_faults;     /* faulty tetrahedra recoverable at once, 0..8, default 8       */
+} hhgr_desc;
+
+/* Convergence report.  history (optional, caller-owned, history_cap entries)
+ * receives ||b - A u|| / ||b|| before the first and after every cycle. */
+typedef struct {
+    int cycles;
+    double rel_res;
+    double *history;
+    int history_cap;
+} hhgr_report;
+
+void hhgr_desc_default(hhgr_desc *desc);
+
+/* Size in bytes of the device workspace a context with this description
+ * needs.  Host-only, no HIP calls.  EINVAL for an invalid description. */
+int hhgr_workspace_bytes(const hhgr_desc *desc, size_t *bytes);
+
+/* Mesh and level setup (Sec. 2.1; Sec. 3.1 data structures): builds the macro
+ * mesh, the volume/face/edge/vertex containers of every level with their ghost
+ * copies, and uploads the index tables into dev_ws (device memory of at least
+ * hhgr_workspace_bytes bytes, 256-byte aligned), all on hip_stream (a
+ * hipStream_t, NULL = default stream).  The solution starts at zero.
+ * EINVAL/ENOMEM/EHIP on failure; *out is then NULL. */
+int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out);
+void hhgr_destroy(hhgr_ctx *ctx);
+
+/* Sizes: interior unknowns (N-1)^3, macro tetrahedra 6 n^3, elements 6 N^3. */
+int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n_elems);
+
+/* Right-hand side of eq. (2) from a device vector in the vector order above.
+ * kind = HHGR_RHS_LOAD: the vector is the load vector b itself;
+ * kind = HHGR_RHS_NODAL_F: the vector holds nodal values of f (zero on the
+ * boundary) and b = M f with the consistent P1 mass matrix.  Also records
+ * ||b|| as the reference for relative residuals. */
+int hhgr_set_rhs(hhgr_ctx *ctx, const double *dev_vec, int kind);
+
+/* Per-element diffusion coefficient (device, element order, length 6 N^3,
+ * positive); needs variable_coeff = 1.  Coarse levels use the mean over the
+ * 8 children of each coarse element (the Galerkin-consistent choice). */
+int hhgr_set_coeff(hhgr_ctx *ctx, const double *dev_k);
+
+/* Copy a device vector into / out of the solver's containers (vector order). */
+int hhgr_set_solution(hhgr_ctx *ctx, const double *dev_u);
+int hhgr_get_solution(const hhgr_ctx *ctx, double *dev_u);
+
+/* n multigrid V-cycles of the correction scheme (Sec. 2.1): red-black SOR
+ * smoothing, restriction by the transpose of linear interpolation,
+ * Jacobi-PCG on the coarsest level, linear interpolation of the correction.
+ * With precision = HHGR_MIXED one cycle is one refinement step
+ * u += V32(b - A u) with the residual and update in FP64.  rel_res_out
+ * (optional) receives ||b - A u|| / ||b||.  ESTATE without a right-hand side. */
+int hhgr_vcycle(hhgr_ctx *ctx, int n, double *rel_res_out);
+
+/* V-cycles until ||b - A u|| <= rel_tol ||b|| or max_cycles (Sec. 2.2: the
+ * solution process continues with multigrid cycles).  ENOCONV if max_cycles
+ * was reached; the report is filled either way. */
+int hhgr_solve(hhgr_ctx *ctx, double rel_tol, int max_cycles, hhgr_report *report);
+
+/* Fail-stop fault of one macro tetrahedron (Sec. 2.2): the unknowns strictly
+ * inside it and its ghost copies of face/edge/vertex values are lost and set to
+ * zero; the face, edge and vertex containers (stored redundantly) survive.
+ * Only between cycles.  EINVAL for a bad tet id. */
+int hhgr_inject_fault(hhgr_ctx *ctx, int tet);
+
+/* Local recovery (Sec. 4; Alg. 1, lines 4-5 and a)): restores the tetrahedron's
+ * ghost copies from the surviving interface containers (eq. (4), row 4), sets
+ * its interior to zero and runs n_cycles multigrid V-cycles restricted to the
+ * tetrahedron's interior on every level for A_FF u_F = f_F - A_FG u_G (a
+ * Dirichlet problem; coarsest level: one unknown, solved exactly).
+ * local_rel_res_out (optional) receives the local residual relative to the
+ * local right-hand side.  ESTATE without a right-hand side. */
+int hhgr_recover_local(hhgr_ctx *ctx, int tet, int n_cycles, double *local_rel_res_out);
+
+/* Dirichlet-Dirichlet recovery (Alg. 1): for the listed faulty tetrahedra,
+ * restores their ghost copies and zeroes their interiors, then runs
+ * concurrently (two streams) n_intact V-cycles on the intact part with the
+ * closures of the faulty tetrahedra frozen as Dirichlet data and n_local
+ * local V-cycles on each faulty tetrahedron.  Returns after both finish.
+ * n_tets <= max_faults.  ESTATE without a right-hand side. */
+int hhgr_recover_dd(hhgr_ctx *ctx, const int *tets, int n_tets, int n_intact, int n_local);
+
+/* Adjoint gradients for J = 1/2 ||u - u_obs||^2 with A(k) u = M f: given
+ * dev_g = u - u_obs (device, vector order), solves A lambda = g with the same
+ * multigrid (A is symmetric) to rel_tol and returns dJ/df = M lambda (vector
+ * order) and, when variable_coeff = 1 and dev_dJdk != NULL,
+ * dJ/dk_T = -lambda^T A_T u (element order, A_T the unit-coefficient element
+ * stiffness).  The current solution u is used and left unchanged.  ENOCONV
+ * if the adjoint solve did not converge in max_cycles. */
+int hhgr_adjoint_grad(hhgr_ctx *ctx, const double *dev_g, double rel_tol, int max_cycles, double *dev_dJdf,
+                      double *dev_dJdk);
+
+/* Apply the consistent P1 mass matrix M to a device vector (vector order). */
+int hhgr_mass_apply(hhgr_ctx *ctx, const double *dev_x, double *dev_y);
+
+/* Batched solves: independent contexts (each with its own workspace and
+ * right-hand side) run their V-cycles as concurrent branches of captured HIP
+ * graphs on hip_stream; every member stops at its own tolerance.  The batch
+ * borrows the contexts.  reps: one report per member (may be NULL). */
+int hhgr_batch_create(hhgr_ctx **ctxs, int n, void *hip_stream, hhgr_batch **out);
+int hhgr_batch_run(hhgr_batch *batch, double rel_tol, int max_cycles, hhgr_report *reps);
+void hhgr_batch_destroy(hhgr_batch *batch);
+
+/* Execution controls.  use_graph = 1 replays a captured HIP graph per
+ * V-cycle instead of launching kernel by kernel (same results). */
+int hhgr_set_graph(hhgr_ctx *ctx, int use_graph);
+
+/* Autotuner: times the candidate workgroup sizes of the structured volume
+ * kernels on every level and keeps the fastest per (kernel, level,
+ * precision).  cache_path (optional) is a text file read before and written
+ * after tuning, keyed by device name.  Enqueues work and synchronises. */
+int hhgr_autotune(hhgr_ctx *ctx, const char *cache_path);
+
+/* Kernel timing for roofline reports: when enabled, every launch of the
+ * finest-level volume smoother kernel is bracketed by HIP events on the
+ * context's stream; hhgr_kernel_stats returns the launch count and mean
+ * duration in milliseconds since the last enable and the bytes the
+ * algorithm moves per launch. */
+int hhgr_kernel_timing(hhgr_ctx *ctx, int enable);
+int hhgr_kernel_stats(hhgr_ctx *ctx, long long *launches, double *mean_ms, double *algorithmic_bytes);
+
+/* Single multigrid operator on level `level`, for testing the kernels one by
+ * one (Sec. 2.1 components).  Vectors are device FP64 in the vector order of
+ * that level (length (N_level - 1)^3).  Clobbers the context's vectors on the
+ * levels involved.
+ *   op 0: out = in1 - A in0                     (residual)
+ *   op 1: out = in0 after one red SOR pass with right-hand side in1
+ *   op 2: out = in0 after one black pass;  op 3: red then black (one sweep)
+ *   op 4: out (level-1) = P^T in0               (restriction)
+ *   op 5: out = in1 + P in0, in0 on level-1     (interpolation and correction)
+ *   op 6: out = coarsest-level PCG solution for right-hand side in0 (level = coarse_level)
+ * EINVAL for a bad op/level combination. */
+int hhgr_debug_op(hhgr_ctx *ctx, int op, int level, const double *in0, const double *in1, double *out);
+
+const char *hhgr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HHGR_H */

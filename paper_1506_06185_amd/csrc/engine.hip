@@ -1,0 +1,1418 @@
+// Solver engine and C ABI of the HHG multigrid library (declarations and
+// semantics in include/hhgr.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/hhgr.h"
+#include "kernels.hpp"
+#include "topology.hpp"
+
+namespace hhgr {
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) return fail(HHGR_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHKLAUNCH()                                                                                   \
+    do {                                                                                              \
+        hipError_t e_ = hipGetLastError();                                                            \
+        if (e_ != hipSuccess) return fail(HHGR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kBS[3] = {128, 256, 512};
+constexpr double kCoarseRtol = 1e-14;
+constexpr int kCoarseMaxit = 2000;
+constexpr int kMaxLevels = 10;
+
+// bump allocator over the caller's workspace; with base == nullptr it only sizes
+struct Carver {
+    char *base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += std::max<size_t>(n, 1) * sizeof(T);
+        return p;
+    }
+};
+
+struct LevelDev {
+    int l = 0, m = 0, M = 0, N = 0;
+    double h = 0;
+    long long C = 0, C_pad = 0, ifc_base = 0, n_slots = 0;
+    int n_ifc = 0, n_ifc_red = 0;
+    int2 *ch_int[3] = {}, *ch_full[3] = {};
+    int n_int[3] = {}, n_full[3] = {};
+    int bs_sel = 1;  // colour pass
+    int *nbr = nullptr, *gptr = nullptr, *gidx = nullptr, *rst = nullptr, *prl = nullptr, *nb15 = nullptr;
+    int *ifc_dof = nullptr, *ifc_xyz = nullptr, *tg_dst = nullptr, *tg_src = nullptr;
+    std::vector<int> tg_ptr;
+    double *u = nullptr, *b = nullptr, *r = nullptr;
+    float *u32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+    double *w[3] = {}, *wi = nullptr;
+    float *w32[3] = {}, *wi32 = nullptr;
+    double *kc = nullptr;
+    VolDesc *vd_all = nullptr, *vd_masked = nullptr, *vd_loc = nullptr;
+    int n_masked = 0, n_loc = 0;
+    unsigned char *frozen = nullptr;
+    double *lu = nullptr, *lb = nullptr, *lr = nullptr;  // local hierarchy (levels < L)
+};
+
+template <typename T>
+struct LevView {
+    T *u = nullptr, *b = nullptr, *r = nullptr;
+    Weights<T> w;
+    const VolDesc *vd = nullptr;
+    int nvol = 0;
+    bool ifc = false;
+    const unsigned char *frozen = nullptr;
+};
+
+template <typename T>
+struct HView {
+    LevView<T> lv[kMaxLevels];
+    int L = 0, Lc = 0;
+    bool local = false;
+    const unsigned char *cfrozen = nullptr;
+    double *partial = nullptr;
+    bool timed = false;
+};
+
+}  // namespace
+}  // namespace hhgr
+
+using namespace hhgr;
+
+struct hhgr_ctx {
+    hhgr_desc d{};
+    Topology topo;
+    std::vector<LevelDev> lev;
+    int L = 0, Lc = 0, n_tets = 0;
+    long long n_dofs = 0, n_elems = 0;
+    hipStream_t stream = nullptr, stream2 = nullptr;
+    hipStream_t cap = nullptr;  // graphs are captured here (the caller's stream may be the legacy default stream)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    double *partial[2] = {};
+    int partial_cap = 0;
+    double *dnorm = nullptr;
+    double *hnorm = nullptr;  // pinned
+    int *tetinfo = nullptr;
+    // coarsest level
+    long long *cslot = nullptr;
+    int *ccol = nullptr, *cptr = nullptr, *cidx = nullptr, *cpos = nullptr, *citers = nullptr;
+    double *cval = nullptr;
+    unsigned char *cfrozen = nullptr;
+    int cn = 0;
+    std::vector<double> cval_host;
+    // adjoint temporaries
+    double *aux_u = nullptr, *aux_b = nullptr, *user_u = nullptr, *user_l = nullptr;
+    double bnorm = 0.0;
+    bool rhs_set = false, coeff_set = false;
+    bool vk = false, mixed = false;
+    // graphs
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_ok = false;
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+struct hhgr_batch {
+    std::vector<hhgr_ctx *> ctx;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> ev;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> active_in_graph;
+    double *hnorm = nullptr;  // pinned, one per member
+};
+
+namespace hhgr {
+namespace {
+
+// ----------------------------------------------------------------------------
+// layout of the workspace (sizing and carving share this code)
+// ----------------------------------------------------------------------------
+void carve(hhgr_ctx &c, Carver &cv) {
+    const Topology &tp = c.topo;
+    const int nf = std::max(c.d.max_faults, 1);
+    c.lev.assign(c.L + 1, LevelDev());
+    int max_blocks = 0;
+    for (int l = c.Lc; l <= c.L; l++) {
+        const TopoLevel &T = tp.lev[l];
+        LevelDev &D = c.lev[l];
+        D.l = l;
+        D.m = T.m;
+        D.M = T.M;
+        D.N = T.N;
+        D.h = T.h;
+        D.C = T.C;
+        D.C_pad = T.C_pad;
+        D.ifc_base = T.ifc_base;
+        D.n_slots = T.n_slots;
+        D.n_ifc = T.n_ifc;
+        D.n_ifc_red = T.n_ifc_red;
+        for (int q = 0; q < 3; q++) {
+            // chunk tables per candidate workgroup size, rebuilt from the plane sizes
+            int nint = 0, nfull = 0;
+            for (int k = 0; k <= T.m; k++) {
+                long long s = T.M - k, P = s * (s + 1) / 2;
+                nfull += (int)((P + kBS[q] - 1) / kBS[q]);
+                if (k >= 1 && k <= T.m - 3) {
+                    long long lo = s, hi = row_start((int)s, T.m - 1 - k);
+                    nint += (int)((hi - lo + kBS[q] - 1) / kBS[q]);
+                }
+            }
+            D.n_int[q] = nint;
+            D.n_full[q] = nfull;
+            D.ch_int[q] = cv.take<int2>(nint);
+            D.ch_full[q] = cv.take<int2>(nfull);
+            int nib = ((T.n_ifc + kBS[q] - 1) / kBS[q] + 7) & ~7;
+            max_blocks = std::max(max_blocks, nib + nfull * c.n_tets);
+        }
+        D.nbr = cv.take<int>(6 * (size_t)T.n_ifc);
+        D.gptr = cv.take<int>(T.n_ifc + 1);
+        D.gidx = cv.take<int>(T.gidx.size());
+        if (l > c.Lc) D.prl = cv.take<int>(2 * (size_t)T.n_ifc);
+        if (l < c.L) D.rst = cv.take<int>(15 * (size_t)T.n_ifc);
+        if (l == c.L) D.nb15 = cv.take<int>(15 * (size_t)T.n_ifc);
+        D.ifc_dof = cv.take<int>(T.n_ifc);
+        D.ifc_xyz = cv.take<int>(3 * (size_t)T.n_ifc);
+        D.tg_dst = cv.take<int>(T.tg_dst.size());
+        D.tg_src = cv.take<int>(T.tg_src.size());
+        D.tg_ptr = T.tg_ptr;
+        D.u = cv.take<double>(T.n_slots);
+        D.b = cv.take<double>(T.n_slots);
+        D.r = cv.take<double>(T.n_slots);
+        if (c.mixed) {
+            D.u32 = cv.take<float>(T.n_slots);
+            D.b32 = cv.take<float>(T.n_slots);
+            D.r32 = cv.take<float>(T.n_slots);
+        }
+        if (c.vk) {
+            for (int s = 0; s < 3; s++) D.w[s] = cv.take<double>(T.n_slots);
+            D.wi = cv.take<double>(6 * (size_t)T.n_ifc);
+            if (c.mixed) {
+                for (int s = 0; s < 3; s++) D.w32[s] = cv.take<float>(T.n_slots);
+                D.wi32 = cv.take<float>(6 * (size_t)T.n_ifc);
+            }
+            D.kc = cv.take<double>(6 * (size_t)T.N * T.N * T.N);
+        }
+        D.vd_all = cv.take<VolDesc>(c.n_tets);
+        D.vd_masked = cv.take<VolDesc>(c.n_tets);
+        D.vd_loc = cv.take<VolDesc>(nf);
+        D.frozen = cv.take<unsigned char>(T.n_ifc);
+        if (l < c.L) {
+            D.lu = cv.take<double>((size_t)nf * T.C_pad);
+            D.lb = cv.take<double>((size_t)nf * T.C_pad);
+            D.lr = cv.take<double>((size_t)nf * T.C_pad);
+        }
+    }
+    c.partial_cap = max_blocks;
+    c.partial[0] = cv.take<double>(max_blocks);
+    c.partial[1] = cv.take<double>(max_blocks);
+    c.dnorm = cv.take<double>(8);
+    c.tetinfo = cv.take<int>(6 * (size_t)c.n_tets);
+    c.cn = tp.coarse.n;
+    c.cslot = cv.take<long long>(c.cn);
+    c.ccol = cv.take<int>(7 * (size_t)c.cn);
+    c.cval = cv.take<double>(7 * (size_t)c.cn);
+    c.cptr = cv.take<int>(c.cn + 1);
+    c.cidx = cv.take<int>(tp.coarse.cidx.size());
+    c.cpos = cv.take<int>(3 * (size_t)c.cn);
+    c.cfrozen = cv.take<unsigned char>(c.cn);
+    c.citers = cv.take<int>(4);
+    const TopoLevel &TL = tp.lev[c.L];
+    c.aux_u = cv.take<double>(TL.n_slots);
+    c.aux_b = cv.take<double>(TL.n_slots);
+    if (c.vk) {
+        c.user_u = cv.take<double>(c.n_dofs);
+        c.user_l = cv.take<double>(c.n_dofs);
+    }
+}
+
+std::string check_desc(const hhgr_desc *d) {
+    if (!d) return "null descriptor";
+    if (d->n_sub < 1 || d->n_sub > 8) return "n_sub must be in 1..8";
+    if (d->coarse_level < 2) return "coarse_level must be >= 2";
+    if (d->level <= d->coarse_level || d->level > 9) return "need coarse_level < level <= 9";
+    if (d->nu_pre < 0 || d->nu_post < 0 || d->nu_pre + d->nu_post < 1) return "need nu_pre, nu_post >= 0, sum >= 1";
+    if (!(d->omega > 0.0 && d->omega < 2.0)) return "omega must be in (0, 2)";
+    if (d->precision != HHGR_FP64 && d->precision != HHGR_MIXED) return "bad precision";
+    if (d->variable_coeff != 0 && d->variable_coeff != 1) return "variable_coeff must be 0 or 1";
+    if (d->max_faults < 0 || d->max_faults > 8) return "max_faults must be in 0..8";
+    return "";
+}
+
+// ----------------------------------------------------------------------------
+// launch geometry
+// ----------------------------------------------------------------------------
+VolGeom vgeom(const LevelDev &D, const VolDesc *vd, int nvol, bool full, int bsq = -1) {
+    const int q = bsq < 0 ? D.bs_sel : bsq;
+    VolGeom g;
+    g.vd = vd;
+    g.chunks = full ? D.ch_full[q] : D.ch_int[q];
+    g.nchunks = full ? D.n_full[q] : D.n_int[q];
+    g.nvol = nvol;
+    g.M = D.M;
+    g.bs = kBS[q];
+    return g;
+}
+
+IfcGeom igeom(const LevelDev &D, int i0, int i1, const unsigned char *frozen, bool scatter) {
+    IfcGeom g;
+    g.i0 = i0;
+    g.i1 = i1;
+    g.base = D.ifc_base;
+    g.stride = D.n_ifc;
+    g.nbr = D.nbr;
+    g.gptr = scatter ? D.gptr : nullptr;
+    g.gidx = scatter ? D.gidx : nullptr;
+    g.frozen = frozen;
+    return g;
+}
+
+IfcGeom ig_none() { return IfcGeom(); }
+
+template <typename T>
+Weights<T> weights(const LevelDev &D);
+template <>
+Weights<double> weights<double>(const LevelDev &D) {
+    Weights<double> w;
+    w.w0 = D.w[0];
+    w.w1 = D.w[1];
+    w.w2 = D.w[2];
+    w.wi = D.wi;
+    return w;
+}
+template <>
+Weights<float> weights<float>(const LevelDev &D) {
+    Weights<float> w;
+    w.w0 = D.w32[0];
+    w.w1 = D.w32[1];
+    w.w2 = D.w32[2];
+    w.wi = D.wi32;
+    return w;
+}
+
+template <typename T>
+T *lvec(LevelDev &D, int which);
+template <>
+double *lvec<double>(LevelDev &D, int which) {
+    return which == 0 ? D.u : which == 1 ? D.b : D.r;
+}
+template <>
+float *lvec<float>(LevelDev &D, int which) {
+    return which == 0 ? D.u32 : which == 1 ? D.b32 : D.r32;
+}
+
+// global (all tetrahedra) or masked (intact tetrahedra, frozen interface) view
+template <typename T>
+HView<T> global_view(hhgr_ctx &c, bool masked, int stream_idx) {
+    HView<T> V;
+    V.L = c.L;
+    V.Lc = c.Lc;
+    V.local = false;
+    V.cfrozen = masked ? c.cfrozen : nullptr;
+    V.partial = c.partial[stream_idx];
+    V.timed = !masked;
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        LevView<T> &v = V.lv[l];
+        v.u = lvec<T>(D, 0);
+        v.b = lvec<T>(D, 1);
+        v.r = lvec<T>(D, 2);
+        v.w = weights<T>(D);
+        v.vd = masked ? D.vd_masked : D.vd_all;
+        v.nvol = masked ? D.n_masked : c.n_tets;
+        v.ifc = true;
+        v.frozen = masked ? D.frozen : nullptr;
+    }
+    return V;
+}
+
+// local hierarchy of the faulty tetrahedra currently in vd_loc (FP64)
+HView<double> local_view(hhgr_ctx &c, int stream_idx) {
+    HView<double> V;
+    V.L = c.L;
+    V.Lc = c.Lc;
+    V.local = true;
+    V.partial = c.partial[stream_idx];
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        LevView<double> &v = V.lv[l];
+        if (l == c.L) {
+            v.u = D.u;
+            v.b = D.b;
+            v.r = D.r;
+        } else {
+            v.u = D.lu;
+            v.b = D.lb;
+            v.r = D.lr;
+        }
+        v.w = weights<double>(D);
+        v.vd = D.vd_loc;
+        v.nvol = D.n_loc;
+        v.ifc = false;
+    }
+    return V;
+}
+
+// ----------------------------------------------------------------------------
+// V-cycle
+// ----------------------------------------------------------------------------
+void timed_begin(hhgr_ctx &c, hipStream_t s) {
+    if (c.tev_used + 2 > c.tev.size()) {
+        for (int q = 0; q < 64; q++) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) == hipSuccess) c.tev.push_back(e);
+        }
+    }
+    if (c.tev_used + 2 <= c.tev.size()) hipEventRecord(c.tev[c.tev_used], s);
+}
+void timed_end(hhgr_ctx &c, hipStream_t s) {
+    if (c.tev_used + 2 <= c.tev.size()) {
+        hipEventRecord(c.tev[c.tev_used + 1], s);
+        c.tev_used += 2;
+    }
+}
+
+template <typename T>
+void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
+    const LevelDev &D = c.lev[l];
+    const LevView<T> &v = V.lv[l];
+    const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+    for (int colour = 0; colour < 2; colour++) {
+        const IfcGeom ig = v.ifc ? igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc,
+                                         v.frozen, true)
+                                 : ig_none();
+        const bool timed = c.timing && V.timed && l == c.L;
+        if (timed) timed_begin(c, s);
+        launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, colour, zero, zero && colour == 0);
+        if (timed) timed_end(c, s);
+    }
+}
+
+template <typename T>
+void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
+    const LevelDev &D = c.lev[c.Lc];
+    const LevView<T> &v = V.lv[c.Lc];
+    if (V.local) {
+        launch_local_coarse<T>(s, v.vd, v.nvol, D.M, v.b, v.u, v.w, c.vk, D.h);
+    } else {
+        launch_coarse_pcg<T>(s, c.cn, c.cslot, c.ccol, c.cval, V.cfrozen, v.b, v.u, c.cptr, c.cidx, kCoarseRtol,
+                             kCoarseMaxit, c.citers);
+    }
+}
+
+template <typename T>
+void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
+    if (l == V.Lc) {
+        coarse_solve(c, V, s);
+        return;
+    }
+    LevelDev &D = c.lev[l];
+    LevelDev &Dc = c.lev[l - 1];
+    const LevView<T> &v = V.lv[l];
+    const LevView<T> &vc = V.lv[l - 1];
+    for (int k = 0; k < c.d.nu_pre; k++) sweep(c, V, l, zero && k == 0, s);
+    if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, V.local && l < c.L ? (long long)c.d.max_faults * D.C_pad : D.n_slots, T(0));
+    const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+    const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
+    launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
+    const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
+    const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
+    launch_restrict<T>(s, vgc, v.vd, D.M, igc, Dc.rst, v.r, vc.b);
+    vcycle(c, V, l - 1, true, s);
+    const IfcGeom igp = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, true) : ig_none();
+    launch_prolong<T>(s, vg, vc.vd, Dc.M, igp, D.prl, vc.u, v.u);
+    for (int k = 0; k < c.d.nu_post; k++) sweep(c, V, l, false, s);
+}
+
+// ||b - A u||^2 (or with TO output: r = b - A u written as TO) on level L of a view
+template <typename TO>
+void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t s, double *dst) {
+    const LevelDev &D = c.lev[c.L];
+    const LevView<double> &v = V.lv[c.L];
+    const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+    const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
+    const int nb = launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
+    if (nb > 0)
+        launch_reduce(s, V.partial, nb, dst);
+    else
+        launch_fill<double>(s, dst, 1, 0.0);
+}
+
+// one FP64 cycle + residual norm into dnorm[slot]
+void step_fp64(hhgr_ctx &c, const HView<double> &V, hipStream_t s, int slot) {
+    vcycle<double>(c, V, c.L, false, s);
+    finest_residual<double>(c, V, (double *)nullptr, s, c.dnorm + slot);
+}
+
+// mixed step: e32 = V32(b32) from zero, u += e32, then b32 = round32(b - A u) and its norm
+void step_mixed(hhgr_ctx &c, const HView<double> &V64, const HView<float> &V32, hipStream_t s, int slot) {
+    vcycle<float>(c, V32, c.L, true, s);
+    LevelDev &D = c.lev[c.L];
+    const VolGeom vf = vgeom(D, V64.lv[c.L].vd, V64.lv[c.L].nvol, true);
+    launch_update_add(s, vf, igeom(D, 0, D.n_ifc, nullptr, false), D.u, D.u32);
+    finest_residual<float>(c, V64, D.b32, s, c.dnorm + slot);
+}
+
+int read_norm(hhgr_ctx &c, int slot, double *out) {
+    HIPCHK(hipMemcpyAsync(c.hnorm + slot, c.dnorm + slot, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    *out = std::sqrt(std::max(c.hnorm[slot], 0.0));
+    return HHGR_OK;
+}
+
+void invalidate_graph(hhgr_ctx &c) {
+    if (c.gexec) hipGraphExecDestroy(c.gexec);
+    c.gexec = nullptr;
+    c.graph_ok = false;
+}
+
+// enqueue one global step (FP64 cycle or mixed refinement step) ending with
+// the residual norm in dnorm[0] copied to hnorm[0]
+void enqueue_step(hhgr_ctx &c, hipStream_t s) {
+    HView<double> V64 = global_view<double>(c, false, 0);
+    if (c.mixed) {
+        HView<float> V32 = global_view<float>(c, false, 0);
+        step_mixed(c, V64, V32, s, 0);
+    } else {
+        step_fp64(c, V64, s, 0);
+    }
+    hipMemcpyAsync(c.hnorm, c.dnorm, sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+int run_step(hhgr_ctx &c) {
+    if (c.use_graph && !c.timing) {
+        if (!c.graph_ok) {
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(c.cap, hipStreamCaptureModeRelaxed));
+            enqueue_step(c, c.cap);
+            HIPCHK(hipStreamEndCapture(c.cap, &g));
+            hipError_t e = hipGraphInstantiate(&c.gexec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(HHGR_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            c.graph_ok = true;
+        }
+        HIPCHK(hipGraphLaunch(c.gexec, c.stream));
+    } else {
+        enqueue_step(c, c.stream);
+        CHKLAUNCH();
+    }
+    return HHGR_OK;
+}
+
+// in mixed mode the residual (and b32) of the current u must be ready before a step
+void prime_mixed(hhgr_ctx &c, hipStream_t s) {
+    HView<double> V64 = global_view<double>(c, false, 0);
+    finest_residual<float>(c, V64, c.lev[c.L].b32, s, c.dnorm);
+}
+
+void set_loc(hhgr_ctx &c, const std::vector<int> &tets) {
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        std::vector<VolDesc> h(tets.size());
+        for (size_t f = 0; f < tets.size(); f++) {
+            h[f].vec = (l == c.L ? (long long)tets[f] : (long long)f) * D.C_pad;
+            h[f].w = (long long)tets[f] * D.C_pad;
+            h[f].tet = tets[f];
+            h[f].pad = 0;
+        }
+        hipMemcpyAsync(D.vd_loc, h.data(), h.size() * sizeof(VolDesc), hipMemcpyHostToDevice, c.stream);
+        hipStreamSynchronize(c.stream);
+        D.n_loc = (int)tets.size();
+    }
+}
+
+// restore ghost copies of tet t on the finest level from the interface masters,
+// after zeroing its closure (interior re-initialised with zero)
+void restore_tet(hhgr_ctx &c, int t, hipStream_t s) {
+    LevelDev &D = c.lev[c.L];
+    launch_fill<double>(s, D.u + (long long)t * D.C_pad, D.C, 0.0);
+    const int a = D.tg_ptr[t], b = D.tg_ptr[t + 1];
+    launch_ghost_refresh<double>(s, D.tg_dst + a, D.tg_src + a, b - a, D.u);
+}
+
+int upload(hhgr_ctx &c, void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return HHGR_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
+    return HHGR_OK;
+}
+
+}  // namespace
+}  // namespace hhgr
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+void hhgr_desc_default(hhgr_desc *d) {
+    if (!d) return;
+    d->n_sub = 2;
+    d->level = 7;
+    d->coarse_level = 2;
+    d->nu_pre = 2;
+    d->nu_post = 1;
+    d->omega = 1.25;
+    d->precision = HHGR_FP64;
+    d->variable_coeff = 0;
+    d->max_faults = 8;
+}
+
+const char *hhgr_last_error(void) { return g_err.c_str(); }
+
+int hhgr_workspace_bytes(const hhgr_desc *desc, size_t *bytes) {
+    std::string e = check_desc(desc);
+    if (!e.empty()) return fail(HHGR_EINVAL, e);
+    if (!bytes) return fail(HHGR_EINVAL, "null bytes pointer");
+    hhgr_ctx c;
+    c.d = *desc;
+    c.L = desc->level;
+    c.Lc = desc->coarse_level;
+    c.n_tets = 6 * desc->n_sub * desc->n_sub * desc->n_sub;
+    long long N = (long long)desc->n_sub << desc->level;
+    c.n_dofs = (N - 1) * (N - 1) * (N - 1);
+    c.vk = desc->variable_coeff != 0;
+    c.mixed = desc->precision == HHGR_MIXED;
+    std::string te = c.topo.build(desc->n_sub, c.L, c.Lc, 256);
+    if (!te.empty()) return fail(HHGR_EINVAL, te);
+    Carver cv;
+    carve(c, cv);
+    *bytes = cv.off + 256;
+    return HHGR_OK;
+}
+
+int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out) {
+    if (!out) return fail(HHGR_EINVAL, "null output pointer");
+    *out = nullptr;
+    std::string e = check_desc(desc);
+    if (!e.empty()) return fail(HHGR_EINVAL, e);
+    if (!dev_ws) return fail(HHGR_EINVAL, "null workspace");
+    if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0) return fail(HHGR_EINVAL, "workspace must be 256-byte aligned");
+    hhgr_ctx *c = new hhgr_ctx();
+    c->d = *desc;
+    c->L = desc->level;
+    c->Lc = desc->coarse_level;
+    c->n_tets = 6 * desc->n_sub * desc->n_sub * desc->n_sub;
+    long long N = (long long)desc->n_sub << desc->level;
+    c->n_dofs = (N - 1) * (N - 1) * (N - 1);
+    c->n_elems = 6 * N * N * N;
+    c->vk = desc->variable_coeff != 0;
+    c->mixed = desc->precision == HHGR_MIXED;
+    c->stream = (hipStream_t)hip_stream;
+    std::string te = c->topo.build(desc->n_sub, c->L, c->Lc, 256);
+    if (!te.empty()) {
+        delete c;
+        return fail(HHGR_EINVAL, te);
+    }
+    Carver sz;
+    carve(*c, sz);
+    if (sz.off + 256 > ws_bytes) {
+        delete c;
+        return fail(HHGR_ENOMEM, "workspace too small");
+    }
+    Carver cv;
+    cv.base = (char *)dev_ws;
+    carve(*c, cv);
+    c->ws = dev_ws;
+    c->ws_bytes = ws_bytes;
+    auto bail = [&](int code) {
+        hhgr_destroy(c);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(HHGR_EHIP, "stream create"));
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(HHGR_EHIP, "event create"));
+    if (hipHostMalloc((void **)&c->hnorm, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(HHGR_EHIP, "pinned host allocation"));
+
+    const Topology &tp = c->topo;
+    // host-side staging of all tables; kept alive until the final synchronise
+    std::vector<std::vector<int2>> chunk_store;
+    std::vector<std::vector<VolDesc>> vd_store;
+    int rc = HHGR_OK;
+    for (int l = c->Lc; l <= c->L && rc == HHGR_OK; l++) {
+        const TopoLevel &T = tp.lev[l];
+        LevelDev &D = c->lev[l];
+        for (int q = 0; q < 3; q++) {
+            std::vector<int2> ci, cf;
+            for (int k = 0; k <= T.m; k++) {
+                int s = T.M - k;
+                long long P = (long long)s * (s + 1) / 2;
+                for (long long o = 0; o < P; o += kBS[q]) cf.push_back(make_int2(k, (int)o));
+                if (k >= 1 && k <= T.m - 3) {
+                    long long lo = s, hi = row_start(s, T.m - 1 - k);
+                    for (long long o = lo; o < hi; o += kBS[q]) ci.push_back(make_int2(k, (int)o));
+                }
+            }
+            chunk_store.push_back(ci);
+            rc = rc ? rc : upload(*c, D.ch_int[q], chunk_store.back().data(), ci.size() * sizeof(int2));
+            chunk_store.push_back(cf);
+            rc = rc ? rc : upload(*c, D.ch_full[q], chunk_store.back().data(), cf.size() * sizeof(int2));
+        }
+        rc = rc ? rc : upload(*c, D.nbr, T.nbr.data(), T.nbr.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, D.gptr, T.gptr.data(), T.gptr.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, D.gidx, T.gidx.data(), T.gidx.size() * sizeof(int));
+        if (D.prl) rc = rc ? rc : upload(*c, D.prl, T.prl.data(), T.prl.size() * sizeof(int));
+        if (D.rst) rc = rc ? rc : upload(*c, D.rst, T.rst.data(), T.rst.size() * sizeof(int));
+        if (D.nb15) rc = rc ? rc : upload(*c, D.nb15, T.nb15.data(), T.nb15.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, D.ifc_dof, T.ifc_dof.data(), T.ifc_dof.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, D.ifc_xyz, T.ifc_X.data(), T.ifc_X.size() * 3 * sizeof(int));
+        rc = rc ? rc : upload(*c, D.tg_dst, T.tg_dst.data(), T.tg_dst.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, D.tg_src, T.tg_src.data(), T.tg_src.size() * sizeof(int));
+        std::vector<VolDesc> vd(c->n_tets);
+        for (int t = 0; t < c->n_tets; t++) vd[t] = VolDesc{(long long)t * T.C_pad, (long long)t * T.C_pad, t, 0};
+        vd_store.push_back(vd);
+        rc = rc ? rc : upload(*c, D.vd_all, vd_store.back().data(), vd.size() * sizeof(VolDesc));
+        // zero every vector (also the Dirichlet ghosts and the zero slot)
+        launch_fill<double>(c->stream, D.u, T.n_slots, 0.0);
+        launch_fill<double>(c->stream, D.b, T.n_slots, 0.0);
+        launch_fill<double>(c->stream, D.r, T.n_slots, 0.0);
+        if (c->mixed) {
+            launch_fill<float>(c->stream, D.u32, T.n_slots, 0.0f);
+            launch_fill<float>(c->stream, D.b32, T.n_slots, 0.0f);
+            launch_fill<float>(c->stream, D.r32, T.n_slots, 0.0f);
+        }
+        if (D.lu) {
+            const long long n = (long long)std::max(c->d.max_faults, 1) * T.C_pad;
+            launch_fill<double>(c->stream, D.lu, n, 0.0);
+            launch_fill<double>(c->stream, D.lb, n, 0.0);
+            launch_fill<double>(c->stream, D.lr, n, 0.0);
+        }
+        launch_fill<unsigned char>(c->stream, D.frozen, T.n_ifc, 0);
+        if (c->vk) {
+            for (int s = 0; s < 3; s++) launch_fill<double>(c->stream, D.w[s], T.n_slots, 0.0);
+            if (c->mixed)
+                for (int s = 0; s < 3; s++) launch_fill<float>(c->stream, D.w32[s], T.n_slots, 0.0f);
+        }
+    }
+    std::vector<int> tinfo(6 * (size_t)c->n_tets);
+    for (int t = 0; t < c->n_tets; t++)
+        for (int a = 0; a < 3; a++) {
+            tinfo[6 * t + a] = tp.V0[t][a];
+            tinfo[6 * t + 3 + a] = tp.perm[t][a];
+        }
+    rc = rc ? rc : upload(*c, c->tetinfo, tinfo.data(), tinfo.size() * sizeof(int));
+    const CoarseSystem &cs = tp.coarse;
+    std::vector<int> cpos(3 * (size_t)cs.n);
+    {
+        const TopoLevel &T = tp.lev[c->Lc];
+        int nv = 0;
+        for (int q = 0; q < cs.n; q++) {
+            if (cs.is_vol[q]) {
+                nv++;
+            }
+        }
+        (void)nv;
+        // positions: volume unknowns from their slot, interface from the table
+        for (int q = 0; q < cs.n; q++) {
+            std::array<int, 3> X{0, 0, 0};
+            if (!cs.is_vol[q]) {
+                X = T.ifc_X[cs.ifc[q]];
+            } else {
+                const int t = cs.tet[q];
+                const long long loc = cs.slot[q] - (long long)t * T.C_pad;
+                // decode closure index loc
+                int k = 0;
+                while (plane_start(T.M, k + 1) <= loc) k++;
+                long long o = loc - plane_start(T.M, k);
+                int s = T.M - k, j = 0;
+                while (j + 1 < s && row_start(s, j + 1) <= o) j++;
+                int i = (int)(o - row_start(s, j));
+                for (int a = 0; a < 3; a++) X[a] = T.m * tp.V0[t][a] + k;
+                X[tp.perm[t][0]] += i + j;
+                X[tp.perm[t][1]] += j;
+            }
+            cpos[3 * q] = X[0];
+            cpos[3 * q + 1] = X[1];
+            cpos[3 * q + 2] = X[2];
+        }
+    }
+    c->cval_host = cs.val;
+    rc = rc ? rc : upload(*c, c->cslot, cs.slot.data(), cs.slot.size() * sizeof(long long));
+    rc = rc ? rc : upload(*c, c->ccol, cs.col.data(), cs.col.size() * sizeof(int));
+    rc = rc ? rc : upload(*c, c->cval, c->cval_host.data(), c->cval_host.size() * sizeof(double));
+    rc = rc ? rc : upload(*c, c->cptr, cs.cptr.data(), cs.cptr.size() * sizeof(int));
+    rc = rc ? rc : upload(*c, c->cidx, cs.cidx.data(), cs.cidx.size() * sizeof(int));
+    rc = rc ? rc : upload(*c, c->cpos, cpos.data(), cpos.size() * sizeof(int));
+    launch_fill<unsigned char>(c->stream, c->cfrozen, cs.n, 0);
+    launch_fill<double>(c->stream, c->dnorm, 8, 0.0);
+    if (rc != HHGR_OK) return bail(rc);
+    if (hipGetLastError() != hipSuccess) return bail(fail(HHGR_EHIP, "kernel launch during setup"));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(HHGR_EHIP, "setup synchronise"));
+    *out = c;
+    return HHGR_OK;
+}
+
+void hhgr_destroy(hhgr_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream2) {
+        hipStreamSynchronize(c->stream2);
+        hipStreamDestroy(c->stream2);
+    }
+    if (c->cap) hipStreamDestroy(c->cap);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
+    for (hipEvent_t e : c->tev) hipEventDestroy(e);
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->hnorm) hipHostFree(c->hnorm);
+    delete c;
+}
+
+int hhgr_sizes(const hhgr_ctx *c, long long *n_dofs, int *n_tets, long long *n_elems) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (n_dofs) *n_dofs = c->n_dofs;
+    if (n_tets) *n_tets = c->n_tets;
+    if (n_elems) *n_elems = c->n_elems;
+    return HHGR_OK;
+}
+
+int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
+    if (!c || !dev_vec) return fail(HHGR_EINVAL, "null argument");
+    if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F) return fail(HHGR_EINVAL, "bad rhs kind");
+    LevelDev &D = c->lev[c->L];
+    const VolGeom vfull = vgeom(D, D.vd_all, c->n_tets, true);
+    const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
+    const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
+    if (kind == HHGR_RHS_LOAD) {
+        launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.b);
+    } else {
+        launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.r);
+        launch_mass(c->stream, vint, ig, D.nb15, D.r, D.b, D.h);
+    }
+    // ||b||: residual of the zero vector
+    launch_fill<double>(c->stream, c->aux_u, D.n_slots, 0.0);
+    HView<double> V = global_view<double>(*c, false, 0);
+    V.lv[c->L].u = c->aux_u;
+    finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm + 1);
+    CHKLAUNCH();
+    double bn;
+    int rc = read_norm(*c, 1, &bn);
+    if (rc) return rc;
+    c->bnorm = bn;
+    c->rhs_set = true;
+    return HHGR_OK;
+}
+
+int hhgr_set_coeff(hhgr_ctx *c, const double *dev_k) {
+    if (!c || !dev_k) return fail(HHGR_EINVAL, "null argument");
+    if (!c->vk) return fail(HHGR_ESTATE, "context created with variable_coeff = 0");
+    invalidate_graph(*c);
+    LevelDev &F = c->lev[c->L];
+    HIPCHK(hipMemcpyAsync(F.kc, dev_k, sizeof(double) * 6 * (size_t)F.N * F.N * F.N, hipMemcpyDeviceToDevice,
+                          c->stream));
+    for (int l = c->L - 1; l >= c->Lc; l--) launch_coarsen_k(c->stream, c->lev[l + 1].kc, c->lev[l + 1].N, c->lev[l].kc, c->lev[l].N);
+    for (int l = c->Lc; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        launch_vol_weights(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N, D.h, D.kc, D.w[0],
+                           D.w[1], D.w[2]);
+        launch_ifc_weights(c->stream, D.n_ifc, D.ifc_xyz, D.N, D.h, D.kc, D.wi);
+        if (c->mixed) {
+            for (int s = 0; s < 3; s++) launch_cast<double, float>(c->stream, D.w[s], D.w32[s], D.n_slots);
+            launch_cast<double, float>(c->stream, D.wi, D.wi32, 6LL * D.n_ifc);
+        }
+    }
+    const LevelDev &Dc = c->lev[c->Lc];
+    launch_coarse_vals(c->stream, c->cn, c->cpos, c->ccol, Dc.N, Dc.h, Dc.kc, c->cval);
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->coeff_set = true;
+    return HHGR_OK;
+}
+
+int hhgr_set_solution(hhgr_ctx *c, const double *dev_u) {
+    if (!c || !dev_u) return fail(HHGR_EINVAL, "null argument");
+    LevelDev &D = c->lev[c->L];
+    launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N,
+                                 igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, dev_u, D.u);
+    CHKLAUNCH();
+    return HHGR_OK;
+}
+
+int hhgr_get_solution(const hhgr_ctx *cc, double *dev_u) {
+    hhgr_ctx *c = const_cast<hhgr_ctx *>(cc);
+    if (!c || !dev_u) return fail(HHGR_EINVAL, "null argument");
+    LevelDev &D = c->lev[c->L];
+    launch_slots_to_user<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N,
+                                 igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, D.u, dev_u);
+    CHKLAUNCH();
+    return HHGR_OK;
+}
+
+static int check_ready(hhgr_ctx *c) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (!c->rhs_set) return fail(HHGR_ESTATE, "no right-hand side set");
+    if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
+    return HHGR_OK;
+}
+
+int hhgr_vcycle(hhgr_ctx *c, int n, double *rel_res_out) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (n < 0) return fail(HHGR_EINVAL, "negative cycle count");
+    if (c->mixed) {
+        prime_mixed(*c, c->stream);
+        CHKLAUNCH();
+    }
+    for (int q = 0; q < n; q++) {
+        rc = run_step(*c);
+        if (rc) return rc;
+    }
+    if (rel_res_out) {
+        double rn;
+        if (n == 0 || c->timing || !c->use_graph) {
+            if (n == 0) {
+                HView<double> V = global_view<double>(*c, false, 0);
+                finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm);
+            }
+            rc = read_norm(*c, 0, &rn);
+            if (rc) return rc;
+        } else {
+            HIPCHK(hipStreamSynchronize(c->stream));
+            rn = std::sqrt(std::max(c->hnorm[0], 0.0));
+        }
+        *rel_res_out = c->bnorm > 0 ? rn / c->bnorm : 0.0;
+    }
+    return HHGR_OK;
+}
+
+int hhgr_solve(hhgr_ctx *c, double rel_tol, int max_cycles, hhgr_report *rep) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (max_cycles < 0) return fail(HHGR_EINVAL, "negative max_cycles");
+    HView<double> V = global_view<double>(*c, false, 0);
+    if (c->mixed)
+        prime_mixed(*c, c->stream);
+    else
+        finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm);
+    CHKLAUNCH();
+    double rn;
+    rc = read_norm(*c, 0, &rn);
+    if (rc) return rc;
+    double rel = c->bnorm > 0 ? rn / c->bnorm : 0.0;
+    if (rep && rep->history && rep->history_cap > 0) rep->history[0] = rel;
+    int cyc = 0;
+    while (rel > rel_tol && cyc < max_cycles) {
+        rc = run_step(*c);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(c->stream));
+        rn = std::sqrt(std::max(c->hnorm[0], 0.0));
+        rel = c->bnorm > 0 ? rn / c->bnorm : 0.0;
+        cyc++;
+        if (rep && rep->history && cyc < rep->history_cap) rep->history[cyc] = rel;
+        if (!std::isfinite(rel)) break;
+    }
+    if (rep) {
+        rep->cycles = cyc;
+        rep->rel_res = rel;
+    }
+    return rel <= rel_tol ? HHGR_OK : fail(HHGR_ENOCONV, "tolerance not reached in max_cycles");
+}
+
+int hhgr_inject_fault(hhgr_ctx *c, int tet) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (tet < 0 || tet >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
+    LevelDev &D = c->lev[c->L];
+    launch_fill<double>(c->stream, D.u + (long long)tet * D.C_pad, D.C, 0.0);
+    CHKLAUNCH();
+    return HHGR_OK;
+}
+
+int hhgr_recover_local(hhgr_ctx *c, int tet, int n_cycles, double *local_rel) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (tet < 0 || tet >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
+    if (n_cycles < 0) return fail(HHGR_EINVAL, "negative cycle count");
+    if (c->d.max_faults < 1) return fail(HHGR_ESTATE, "context created with max_faults = 0");
+    set_loc(*c, {tet});
+    restore_tet(*c, tet, c->stream);
+    HView<double> V = local_view(*c, 0);
+    finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm + 2);
+    for (int q = 0; q < n_cycles; q++) vcycle<double>(*c, V, c->L, false, c->stream);
+    finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm + 3);
+    CHKLAUNCH();
+    double r0, r1;
+    rc = read_norm(*c, 2, &r0);
+    if (rc) return rc;
+    rc = read_norm(*c, 3, &r1);
+    if (rc) return rc;
+    if (local_rel) *local_rel = r0 > 0 ? r1 / r0 : 0.0;
+    return HHGR_OK;
+}
+
+int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int n_local) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!tets || n_tets < 1 || n_tets > c->d.max_faults) return fail(HHGR_EINVAL, "need 1..max_faults tets");
+    if (n_intact < 0 || n_local < 0) return fail(HHGR_EINVAL, "negative cycle count");
+    std::vector<int> ft(tets, tets + n_tets);
+    std::vector<char> isf(c->n_tets, 0);
+    for (int t : ft) {
+        if (t < 0 || t >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
+        if (isf[t]) return fail(HHGR_EINVAL, "duplicate tet id");
+        isf[t] = 1;
+    }
+    invalidate_graph(*c);
+    // masks: intact volumes, frozen interface nodes (closures of faulty tets)
+    std::vector<std::vector<VolDesc>> vds(c->L + 1);
+    std::vector<std::vector<unsigned char>> frz(c->L + 1);
+    for (int l = c->Lc; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        const TopoLevel &T = c->topo.lev[l];
+        for (int t = 0; t < c->n_tets; t++)
+            if (!isf[t]) vds[l].push_back(VolDesc{(long long)t * D.C_pad, (long long)t * D.C_pad, t, 0});
+        frz[l].assign(D.n_ifc, 0);
+        for (int t : ft)
+            for (int q = T.tg_ptr[t]; q < T.tg_ptr[t + 1]; q++) {
+                long long s = T.tg_src[q];
+                if (s >= T.ifc_base && s < T.ifc_base + T.n_ifc) frz[l][s - T.ifc_base] = 1;
+            }
+        D.n_masked = (int)vds[l].size();
+        rc = upload(*c, D.vd_masked, vds[l].data(), vds[l].size() * sizeof(VolDesc));
+        if (rc) return rc;
+        rc = upload(*c, D.frozen, frz[l].data(), frz[l].size());
+        if (rc) return rc;
+    }
+    const CoarseSystem &cs = c->topo.coarse;
+    std::vector<unsigned char> cf(cs.n, 0);
+    for (int q = 0; q < cs.n; q++)
+        cf[q] = cs.is_vol[q] ? (unsigned char)isf[cs.tet[q]] : frz[c->Lc][cs.ifc[q]];
+    rc = upload(*c, c->cfrozen, cf.data(), cf.size());
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    set_loc(*c, ft);
+    for (int t : ft) restore_tet(*c, t, c->stream);
+    // corrections of the masked cycles start from zero everywhere below the finest level
+    for (int l = c->Lc; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        if (l < c->L) launch_fill<double>(c->stream, D.u, D.n_slots, 0.0);
+        if (c->mixed) launch_fill<float>(c->stream, D.u32, D.n_slots, 0.0f);
+    }
+    HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    // intact side on the main stream
+    HView<double> V64 = global_view<double>(*c, true, 0);
+    if (c->mixed) {
+        HView<float> V32 = global_view<float>(*c, true, 0);
+        finest_residual<float>(*c, V64, c->lev[c->L].b32, c->stream, c->dnorm + 4);
+        for (int q = 0; q < n_intact; q++) step_mixed(*c, V64, V32, c->stream, 4);
+    } else {
+        for (int q = 0; q < n_intact; q++) vcycle<double>(*c, V64, c->L, false, c->stream);
+    }
+    // faulty side on the second stream
+    HView<double> VL = local_view(*c, 1);
+    for (int q = 0; q < n_local; q++) vcycle<double>(*c, VL, c->L, false, c->stream2);
+    HIPCHK(hipEventRecord(c->ev_join, c->stream2));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c->stream));
+    // leave the masks inactive and the coarse corrections consistent for global cycles
+    for (int l = c->Lc; l <= c->L; l++) c->lev[l].n_masked = 0;
+    return HHGR_OK;
+}
+
+int hhgr_mass_apply(hhgr_ctx *c, const double *dev_x, double *dev_y) {
+    if (!c || !dev_x || !dev_y) return fail(HHGR_EINVAL, "null argument");
+    LevelDev &D = c->lev[c->L];
+    const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
+    launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
+                                 dev_x, c->aux_b);
+    launch_mass(c->stream, vgeom(D, D.vd_all, c->n_tets, false), ig, D.nb15, c->aux_b, c->aux_u, D.h);
+    launch_slots_to_user<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
+                                 c->aux_u, dev_y);
+    CHKLAUNCH();
+    return HHGR_OK;
+}
+
+int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_cycles, double *dev_dJdf,
+                      double *dev_dJdk) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!dev_g) return fail(HHGR_EINVAL, "null g");
+    if (dev_dJdk && !c->vk) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
+    LevelDev &D = c->lev[c->L];
+    const long long ns = D.n_slots;
+    const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
+    const VolGeom vfull = vgeom(D, D.vd_all, c->n_tets, true), vint = vgeom(D, D.vd_all, c->n_tets, false);
+    // save u and b, solve A lambda = g from zero in FP64
+    HIPCHK(hipMemcpyAsync(c->aux_u, D.u, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->aux_b, D.b, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (dev_dJdk)
+        launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_u);
+    launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_g, D.b);
+    launch_fill<double>(c->stream, D.u, ns, 0.0);
+    const double bnorm_saved = c->bnorm;
+    const bool mixed_saved = c->mixed;
+    c->mixed = false;
+    invalidate_graph(*c);
+    {
+        HView<double> V = global_view<double>(*c, false, 0);
+        launch_fill<double>(c->stream, D.r, ns, 0.0);
+        HView<double> Vz = V;
+        Vz.lv[c->L].u = D.r;
+        finest_residual<double>(*c, Vz, (double *)nullptr, c->stream, c->dnorm + 1);
+    }
+    CHKLAUNCH();
+    double gn;
+    rc = read_norm(*c, 1, &gn);
+    int result = HHGR_OK;
+    if (!rc) {
+        c->bnorm = gn;
+        hhgr_report rep{0, 0.0, nullptr, 0};
+        result = gn > 0 ? hhgr_solve(c, rel_tol, max_cycles, &rep) : HHGR_OK;
+        if (dev_dJdf) {
+            launch_mass(c->stream, vint, ig, D.nb15, D.u, D.r, D.h);
+            launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.r, dev_dJdf);
+        }
+        if (dev_dJdk) {
+            launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_l);
+            launch_grad_k(c->stream, c->user_u, c->user_l, D.N, D.h, dev_dJdk);
+        }
+    }
+    // restore the forward state
+    hipMemcpyAsync(D.u, c->aux_u, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    hipMemcpyAsync(D.b, c->aux_b, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    c->bnorm = bnorm_saved;
+    c->mixed = mixed_saved;
+    invalidate_graph(*c);
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (rc) return rc;
+    return result;
+}
+
+int hhgr_set_graph(hhgr_ctx *c, int use_graph) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    c->use_graph = use_graph != 0;
+    invalidate_graph(*c);
+    return HHGR_OK;
+}
+
+int hhgr_kernel_timing(hhgr_ctx *c, int enable) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->timing = enable != 0;
+    c->tev_used = 0;
+    return HHGR_OK;
+}
+
+int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double *alg_bytes) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    long long n = 0;
+    for (size_t q = 0; q + 1 < c->tev_used; q += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->tev[q], c->tev[q + 1]) == hipSuccess) {
+            tot += ms;
+            n++;
+        }
+    }
+    if (launches) *launches = n;
+    if (mean_ms) *mean_ms = n ? tot / n : 0.0;
+    // one colour pass over the finest volumes reads the other colour's u, its own
+    // b and old u and writes its own u: 4 words per updated node, 2 per node
+    const double w = c->mixed ? 4.0 : 8.0;
+    if (alg_bytes) *alg_bytes = 2.0 * w * (double)c->n_dofs;
+    return HHGR_OK;
+}
+
+int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    hipDeviceProp_t prop;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    std::string devname = prop.gcnArchName;
+    std::map<std::string, int> cache;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string key;
+        int v;
+        while (in >> key >> v) cache[key] = v;
+    }
+    invalidate_graph(*c);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int l = c->Lc + 1; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        std::ostringstream ks;
+        ks << devname << ":n" << c->d.n_sub << ":l" << l << ":" << (c->mixed ? "f32" : "f64") << ":vk" << c->vk;
+        auto it = cache.find(ks.str());
+        if (it != cache.end()) {
+            D.bs_sel = it->second;
+            continue;
+        }
+        double best = 1e30;
+        int bq = 1;
+        for (int q = 0; q < 3; q++) {
+            const VolGeom vg = vgeom(D, D.vd_all, c->n_tets, false, q);
+            const IfcGeom ig = igeom(D, 0, D.n_ifc_red, nullptr, false);
+            auto run = [&]() {
+                if (c->mixed)
+                    launch_colour<float>(c->stream, vg, ig, D.r32, D.b32, weights<float>(D), c->vk, D.h, c->d.omega, 0,
+                                         false, false);
+                else
+                    launch_colour<double>(c->stream, vg, ig, D.r, D.b, weights<double>(D), c->vk, D.h, c->d.omega, 0,
+                                          false, false);
+            };
+            run();
+            HIPCHK(hipEventRecord(e0, c->stream));
+            const int reps = l >= 6 ? 5 : 20;
+            for (int r = 0; r < reps; r++) run();
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bq = q;
+            }
+        }
+        D.bs_sel = bq;
+        cache[ks.str()] = bq;
+        // scratch vector used for timing goes back to zero
+        launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
+        if (c->mixed) launch_fill<float>(c->stream, D.r32, D.n_slots, 0.0f);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (cache_path) {
+        std::ofstream o(cache_path);
+        for (auto &kv : cache) o << kv.first << " " << kv.second << "\n";
+    }
+    return HHGR_OK;
+}
+
+int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *in1, double *out) {
+    if (!c || !in0 || !out) return fail(HHGR_EINVAL, "null argument");
+    if (l < c->Lc || l > c->L || op < 0 || op > 6) return fail(HHGR_EINVAL, "bad op or level");
+    if ((op == 4 || op == 5) && l <= c->Lc) return fail(HHGR_EINVAL, "transfer needs level > coarse_level");
+    if (op == 6 && l != c->Lc) return fail(HHGR_EINVAL, "coarse solve needs level = coarse_level");
+    if ((op <= 3 || op == 5) && !in1) return fail(HHGR_EINVAL, "null second input");
+    if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
+    invalidate_graph(*c);
+    hipStream_t s = c->stream;
+    auto to_slots = [&](const double *user, double *vec, LevelDev &D) {
+        launch_user_to_slots<double>(s, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N,
+                                     igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, user, vec);
+    };
+    auto to_user = [&](const double *vec, double *user, LevelDev &D) {
+        launch_slots_to_user<double>(s, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N,
+                                     igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, vec, user);
+    };
+    LevelDev &D = c->lev[l];
+    const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
+    const Weights<double> w = weights<double>(D);
+    switch (op) {
+    case 0:
+        to_slots(in0, D.u, D);
+        to_slots(in1, D.b, D);
+        launch_residual<double, double>(s, vint, igeom(D, 0, D.n_ifc, nullptr, false), D.u, D.b, w, c->vk, D.h, D.r,
+                                        nullptr);
+        to_user(D.r, out, D);
+        break;
+    case 1:
+    case 2:
+    case 3:
+        to_slots(in0, D.u, D);
+        to_slots(in1, D.b, D);
+        for (int colour = 0; colour < 2; colour++) {
+            if (!((op == 3) || (op == 1 && colour == 0) || (op == 2 && colour == 1))) continue;
+            const IfcGeom ig = igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc, nullptr, true);
+            launch_colour<double>(s, vint, ig, D.u, D.b, w, c->vk, D.h, c->d.omega, colour, false, false);
+        }
+        to_user(D.u, out, D);
+        break;
+    case 4: {
+        LevelDev &Dc = c->lev[l - 1];
+        to_slots(in0, D.r, D);
+        launch_restrict<double>(s, vgeom(Dc, Dc.vd_all, c->n_tets, false), D.vd_all, D.M,
+                                igeom(Dc, 0, Dc.n_ifc, nullptr, false), Dc.rst, D.r, Dc.b);
+        to_user(Dc.b, out, Dc);
+        break;
+    }
+    case 5: {
+        LevelDev &Dc = c->lev[l - 1];
+        to_slots(in0, Dc.u, Dc);
+        to_slots(in1, D.u, D);
+        launch_prolong<double>(s, vint, Dc.vd_all, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true), D.prl, Dc.u, D.u);
+        to_user(D.u, out, D);
+        break;
+    }
+    case 6:
+        to_slots(in0, D.b, D);
+        launch_coarse_pcg<double>(s, c->cn, c->cslot, c->ccol, c->cval, nullptr, D.b, D.u, c->cptr, c->cidx,
+                                  kCoarseRtol, kCoarseMaxit, c->citers);
+        to_user(D.u, out, D);
+        break;
+    }
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(s));
+    return HHGR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch: members' steps as parallel branches of one captured graph
+// ---------------------------------------------------------------------------
+int hhgr_batch_create(hhgr_ctx **ctxs, int n, void *hip_stream, hhgr_batch **out) {
+    if (!out) return fail(HHGR_EINVAL, "null output");
+    *out = nullptr;
+    if (!ctxs || n < 1) return fail(HHGR_EINVAL, "need at least one member");
+    for (int q = 0; q < n; q++)
+        if (!ctxs[q]) return fail(HHGR_EINVAL, "null member");
+    hhgr_batch *b = new hhgr_batch();
+    b->ctx.assign(ctxs, ctxs + n);
+    b->stream = (hipStream_t)hip_stream;
+    b->branch.resize(n);
+    b->ev.resize(2 * n + 1);
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        hhgr_batch_destroy(b);
+        return fail(HHGR_EHIP, "stream create");
+    }
+    for (int q = 0; q < n; q++) {
+        if (hipStreamCreateWithFlags(&b->branch[q], hipStreamNonBlocking) != hipSuccess) {
+            hhgr_batch_destroy(b);
+            return fail(HHGR_EHIP, "stream create");
+        }
+    }
+    for (auto &e : b->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            hhgr_batch_destroy(b);
+            return fail(HHGR_EHIP, "event create");
+        }
+    if (hipHostMalloc((void **)&b->hnorm, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
+        hhgr_batch_destroy(b);
+        return fail(HHGR_EHIP, "pinned host allocation");
+    }
+    *out = b;
+    return HHGR_OK;
+}
+
+void hhgr_batch_destroy(hhgr_batch *b) {
+    if (!b) return;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    for (auto s : b->branch)
+        if (s) hipStreamDestroy(s);
+    if (b->cap) hipStreamDestroy(b->cap);
+    for (auto e : b->ev)
+        if (e) hipEventDestroy(e);
+    if (b->hnorm) hipHostFree(b->hnorm);
+    delete b;
+}
+
+int hhgr_batch_run(hhgr_batch *b, double rel_tol, int max_cycles, hhgr_report *reps) {
+    if (!b) return fail(HHGR_EINVAL, "null batch");
+    const int n = (int)b->ctx.size();
+    std::vector<double> rel(n, 0.0);
+    std::vector<int> cyc(n, 0), active;
+    // initial residuals (and FP32 right-hand sides of mixed members)
+    for (int q = 0; q < n; q++) {
+        hhgr_ctx *c = b->ctx[q];
+        int rc = check_ready(c);
+        if (rc) return rc;
+        HView<double> V = global_view<double>(*c, false, 0);
+        if (c->mixed)
+            prime_mixed(*c, b->stream);
+        else
+            finest_residual<double>(*c, V, (double *)nullptr, b->stream, c->dnorm);
+        HIPCHK(hipMemcpyAsync(b->hnorm + q, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    }
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int q = 0; q < n; q++) {
+        rel[q] = b->ctx[q]->bnorm > 0 ? std::sqrt(std::max(b->hnorm[q], 0.0)) / b->ctx[q]->bnorm : 0.0;
+        if (reps && reps[q].history && reps[q].history_cap > 0) reps[q].history[0] = rel[q];
+        if (rel[q] > rel_tol && max_cycles > 0) active.push_back(q);
+    }
+    while (!active.empty()) {
+        if (active != b->active_in_graph || !b->gexec) {
+            if (b->gexec) hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+            HIPCHK(hipEventRecord(b->ev[0], b->cap));
+            for (size_t a = 0; a < active.size(); a++) {
+                const int q = active[a];
+                hhgr_ctx *c = b->ctx[q];
+                hipStream_t s = b->branch[q];
+                hipStreamWaitEvent(s, b->ev[0], 0);
+                HView<double> V64 = global_view<double>(*c, false, 0);
+                if (c->mixed) {
+                    HView<float> V32 = global_view<float>(*c, false, 0);
+                    step_mixed(*c, V64, V32, s, 0);
+                } else {
+                    step_fp64(*c, V64, s, 0);
+                }
+                hipMemcpyAsync(b->hnorm + q, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, s);
+                hipEventRecord(b->ev[1 + q], s);
+                hipStreamWaitEvent(b->cap, b->ev[1 + q], 0);
+            }
+            hipError_t ce = hipStreamEndCapture(b->cap, &g);
+            if (ce != hipSuccess) return fail(HHGR_EHIP, std::string("batch capture: ") + hipGetErrorString(ce));
+            ce = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ce != hipSuccess) return fail(HHGR_EHIP, std::string("batch instantiate: ") + hipGetErrorString(ce));
+            b->active_in_graph = active;
+        }
+        HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        std::vector<int> next;
+        for (int q : active) {
+            cyc[q]++;
+            rel[q] = b->ctx[q]->bnorm > 0 ? std::sqrt(std::max(b->hnorm[q], 0.0)) / b->ctx[q]->bnorm : 0.0;
+            if (reps && reps[q].history && cyc[q] < reps[q].history_cap) reps[q].history[cyc[q]] = rel[q];
+            if (rel[q] > rel_tol && cyc[q] < max_cycles && std::isfinite(rel[q])) next.push_back(q);
+        }
+        active.swap(next);
+    }
+    bool all = true;
+    for (int q = 0; q < n; q++) {
+        if (reps) {
+            reps[q].cycles = cyc[q];
+            reps[q].rel_res = rel[q];
+        }
+        all = all && rel[q] <= rel_tol;
+    }
+    return all ? HHGR_OK : fail(HHGR_ENOCONV, "some batch members did not converge");
+}
+
+}  // extern "C"

@@ -1,0 +1,310 @@
+"""Python binding of libhhgr.so (the C ABI in include/hhgr.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch provides the device memory (the workspace and all vectors)
+and the stream; tensors must be CUDA (HIP) tensors of dtype float64.
+
+``lib()`` returns the ctypes library whose functions carry the C names
+(``hhgr_create``, ``hhgr_vcycle``, ...); ``Context`` wraps one solver context
+with methods named after the C calls without the prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhhgr.so")
+
+HHGR_OK, HHGR_EINVAL, HHGR_ENOMEM, HHGR_EHIP, HHGR_ESTATE, HHGR_ENOCONV = 0, -1, -2, -3, -4, -5
+HHGR_FP64, HHGR_MIXED = 0, 1
+HHGR_RHS_LOAD, HHGR_RHS_NODAL_F = 0, 1
+_CODES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENOCONV"}
+
+
+class HHGRError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hhgr error {_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [("n_sub", C.c_int), ("level", C.c_int), ("coarse_level", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("omega", C.c_double), ("precision", C.c_int),
+                ("variable_coeff", C.c_int), ("max_faults", C.c_int)]
+
+
+class Report(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("rel_res", C.c_double), ("history", C.POINTER(C.c_double)),
+                ("history_cap", C.c_int)]
+
+
+_lib = None
+_vp, _dp, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+
+
+def lib():
+    """Load the in-tree library; fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1506_06185_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "hhgr_desc_default": (None, [C.POINTER(Desc)]),
+        "hhgr_workspace_bytes": (C.c_int, [C.POINTER(Desc), C.POINTER(C.c_size_t)]),
+        "hhgr_create": (C.c_int, [C.POINTER(Desc), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+        "hhgr_destroy": (None, [_vp]),
+        "hhgr_sizes": (C.c_int, [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
+        "hhgr_set_rhs": (C.c_int, [_vp, _vp, C.c_int]),
+        "hhgr_set_coeff": (C.c_int, [_vp, _vp]),
+        "hhgr_set_solution": (C.c_int, [_vp, _vp]),
+        "hhgr_get_solution": (C.c_int, [_vp, _vp]),
+        "hhgr_vcycle": (C.c_int, [_vp, C.c_int, _dp]),
+        "hhgr_solve": (C.c_int, [_vp, C.c_double, C.c_int, C.POINTER(Report)]),
+        "hhgr_inject_fault": (C.c_int, [_vp, C.c_int]),
+        "hhgr_recover_local": (C.c_int, [_vp, C.c_int, C.c_int, _dp]),
+        "hhgr_recover_dd": (C.c_int, [_vp, _ip, C.c_int, C.c_int, C.c_int]),
+        "hhgr_adjoint_grad": (C.c_int, [_vp, _vp, C.c_double, C.c_int, _vp, _vp]),
+        "hhgr_mass_apply": (C.c_int, [_vp, _vp, _vp]),
+        "hhgr_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]),
+        "hhgr_batch_run": (C.c_int, [_vp, C.c_double, C.c_int, C.POINTER(Report)]),
+        "hhgr_batch_destroy": (None, [_vp]),
+        "hhgr_set_graph": (C.c_int, [_vp, C.c_int]),
+        "hhgr_autotune": (C.c_int, [_vp, C.c_char_p]),
+        "hhgr_kernel_timing": (C.c_int, [_vp, C.c_int]),
+        "hhgr_kernel_stats": (C.c_int, [_vp, C.POINTER(C.c_longlong), _dp, _dp]),
+        "hhgr_debug_op": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
+        "hhgr_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_destroy", "hhgr_sizes",
+            "hhgr_set_rhs", "hhgr_set_coeff", "hhgr_set_solution", "hhgr_get_solution", "hhgr_vcycle",
+            "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_adjoint_grad",
+            "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_set_graph",
+            "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_last_error")
+
+
+def _check(rc: int, allow=()):
+    if rc != HHGR_OK and rc not in allow:
+        msg = lib().hhgr_last_error()
+        raise HHGRError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def make_desc(n_sub=2, level=7, coarse_level=2, nu_pre=2, nu_post=1, omega=1.25, precision="fp64",
+              variable_coeff=False, max_faults=8) -> Desc:
+    d = Desc()
+    lib().hhgr_desc_default(C.byref(d))
+    d.n_sub, d.level, d.coarse_level = int(n_sub), int(level), int(coarse_level)
+    d.nu_pre, d.nu_post, d.omega = int(nu_pre), int(nu_post), float(omega)
+    d.precision = {"fp64": HHGR_FP64, "mixed": HHGR_MIXED}[precision]
+    d.variable_coeff = int(bool(variable_coeff))
+    d.max_faults = int(max_faults)
+    return d
+
+
+def workspace_bytes(desc: Desc) -> int:
+    n = C.c_size_t(0)
+    _check(lib().hhgr_workspace_bytes(C.byref(desc), C.byref(n)))
+    return int(n.value)
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """One solver context; the workspace is a torch uint8 device tensor it keeps alive."""
+
+    def __init__(self, device=None, stream=None, **desc_kw):
+        self.desc = make_desc(**desc_kw)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = workspace_bytes(self.desc)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = _vp()
+        _check(lib().hhgr_create(C.byref(self.desc), self._ws_ptr, nbytes, self.stream.cuda_stream, C.byref(h)))
+        self._h = h
+        nd, nt, ne = C.c_longlong(), C.c_int(), C.c_longlong()
+        _check(lib().hhgr_sizes(self._h, C.byref(nd), C.byref(nt), C.byref(ne)))
+        self.n_dofs, self.n_tets, self.n_elems = int(nd.value), int(nt.value), int(ne.value)
+        self.workspace_nbytes = nbytes
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hhgr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self):
+        return torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+
+    def set_rhs(self, vec: torch.Tensor, kind: int = HHGR_RHS_LOAD):
+        _check(lib().hhgr_set_rhs(self._h, _ptr(vec), int(kind)))
+        self._keep_rhs = vec
+
+    def set_coeff(self, k: torch.Tensor):
+        _check(lib().hhgr_set_coeff(self._h, _ptr(k)))
+
+    def set_solution(self, u: torch.Tensor):
+        _check(lib().hhgr_set_solution(self._h, _ptr(u)))
+        self.stream.synchronize()
+
+    def get_solution(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self._vec() if out is None else out
+        _check(lib().hhgr_get_solution(self._h, _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def vcycle(self, n: int = 1) -> float:
+        rel = C.c_double(0.0)
+        _check(lib().hhgr_vcycle(self._h, int(n), C.byref(rel)))
+        return float(rel.value)
+
+    def solve(self, rel_tol: float = 1e-8, max_cycles: int = 100, raise_on_noconv: bool = True):
+        import numpy as np
+
+        hist = (C.c_double * (max_cycles + 1))()
+        rep = Report(0, 0.0, C.cast(hist, _dp), max_cycles + 1)
+        rc = lib().hhgr_solve(self._h, float(rel_tol), int(max_cycles), C.byref(rep))
+        _check(rc, allow=() if raise_on_noconv else (HHGR_ENOCONV,))
+        return int(rep.cycles), float(rep.rel_res), np.array(hist[: rep.cycles + 1])
+
+    def inject_fault(self, tet: int):
+        _check(lib().hhgr_inject_fault(self._h, int(tet)))
+
+    def recover_local(self, tet: int, n_cycles: int = 3) -> float:
+        rel = C.c_double(0.0)
+        _check(lib().hhgr_recover_local(self._h, int(tet), int(n_cycles), C.byref(rel)))
+        return float(rel.value)
+
+    def recover_dd(self, tets, n_intact: int, n_local: int):
+        arr = (C.c_int * len(tets))(*[int(t) for t in tets])
+        _check(lib().hhgr_recover_dd(self._h, arr, len(tets), int(n_intact), int(n_local)))
+
+    def adjoint_grad(self, g: torch.Tensor, rel_tol: float = 1e-13, max_cycles: int = 100, want_k: bool = True):
+        dJdf = self._vec()
+        dJdk = torch.empty(self.n_elems, dtype=torch.float64, device=self.device) if want_k else None
+        _check(lib().hhgr_adjoint_grad(self._h, _ptr(g), float(rel_tol), int(max_cycles), _ptr(dJdf),
+                                       _ptr(dJdk) if dJdk is not None else None))
+        return dJdf, dJdk
+
+    def mass_apply(self, x: torch.Tensor) -> torch.Tensor:
+        y = self._vec()
+        _check(lib().hhgr_mass_apply(self._h, _ptr(x), _ptr(y)))
+        self.stream.synchronize()
+        return y
+
+    def set_graph(self, on: bool = True):
+        _check(lib().hhgr_set_graph(self._h, int(bool(on))))
+
+    def autotune(self, cache_path: str | None = None):
+        _check(lib().hhgr_autotune(self._h, cache_path.encode() if cache_path else None))
+
+    def kernel_timing(self, on: bool = True):
+        _check(lib().hhgr_kernel_timing(self._h, int(bool(on))))
+
+    def kernel_stats(self):
+        n, ms, by = C.c_longlong(), C.c_double(), C.c_double()
+        _check(lib().hhgr_kernel_stats(self._h, C.byref(n), C.byref(ms), C.byref(by)))
+        return int(n.value), float(ms.value), float(by.value)
+
+
+def debug_op(ctx: "Context", op: int, level: int, in0: torch.Tensor, in1: torch.Tensor | None = None):
+    """One multigrid operator on one level (see hhgr_debug_op); returns the output vector."""
+    n_out_level = level - 1 if op == 4 else level
+    N = ctx.desc.n_sub << n_out_level
+    out = torch.empty((N - 1) ** 3, dtype=torch.float64, device=ctx.device)
+    _check(lib().hhgr_debug_op(ctx.handle, int(op), int(level), _ptr(in0), _ptr(in1) if in1 is not None else None,
+                               _ptr(out)))
+    return out
+
+
+class Batch:
+    """Concurrent solves of independent contexts (graph branches)."""
+
+    def __init__(self, contexts, stream=None):
+        self.contexts = list(contexts)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        arr = (_vp * len(self.contexts))(*[c.handle for c in self.contexts])
+        h = _vp()
+        _check(lib().hhgr_batch_create(arr, len(self.contexts), self.stream.cuda_stream, C.byref(h)))
+        self._h = h
+
+    def run(self, rel_tol: float = 1e-8, max_cycles: int = 100, raise_on_noconv: bool = True):
+        import numpy as np
+
+        n = len(self.contexts)
+        hists = [(C.c_double * (max_cycles + 1))() for _ in range(n)]
+        reps = (Report * n)(*[Report(0, 0.0, C.cast(h, _dp), max_cycles + 1) for h in hists])
+        rc = lib().hhgr_batch_run(self._h, float(rel_tol), int(max_cycles), reps)
+        _check(rc, allow=() if raise_on_noconv else (HHGR_ENOCONV,))
+        return [(int(r.cycles), float(r.rel_res), np.array(h[: r.cycles + 1])) for r, h in zip(reps, hists)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hhgr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kappa(k_faulty: int, k_free: int, k_F: int) -> float:
+    """Relative cycle advantage, eq. (3): (k_faulty - k_free) / k_F."""
+    return (k_faulty - k_free) / k_F
+
+
+class HHGSolve(torch.autograd.Function):
+    """u = A(k)^{-1} M f on a context created with variable_coeff=True.
+
+    forward(ctx_obj, f, k) -> u; backward returns dJ/df = M lambda and
+    dJ/dk_T = -lambda^T A_T u with A lambda = dJ/du (adjoint multigrid solve).
+    """
+
+    @staticmethod
+    def forward(fctx, ctx_obj: Context, f: torch.Tensor, k: torch.Tensor, rel_tol: float = 1e-13,
+                max_cycles: int = 100):
+        ctx_obj.set_coeff(k.contiguous())
+        ctx_obj.set_rhs(f.contiguous(), HHGR_RHS_NODAL_F)
+        ctx_obj.set_solution(torch.zeros_like(f))
+        ctx_obj.solve(rel_tol, max_cycles)
+        u = ctx_obj.get_solution()
+        fctx.ctx_obj = ctx_obj
+        fctx.rel_tol, fctx.max_cycles = rel_tol, max_cycles
+        return u
+
+    @staticmethod
+    def backward(fctx, g: torch.Tensor):
+        c = fctx.ctx_obj
+        dJdf, dJdk = c.adjoint_grad(g.contiguous(), fctx.rel_tol, fctx.max_cycles, want_k=True)
+        c.stream.synchronize()
+        return None, dJdf, dJdk, None, None

@@ -1,0 +1,50 @@
+"""CPU checks of the C ABI library: it loads, exports every symbol that
+include/hhgr.h declares, validates descriptions and sizes workspaces (no GPU
+calls), and the host topology/index arithmetic passes its checks."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "hhgr.h")).read()
+    return sorted(set(re.findall(r"\b(hhgr_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1506_06185_amd import hhgr
+
+    L = hhgr.lib()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert not missing, missing
+    assert set(syms) == set(hhgr.EXPORTED)
+
+
+def test_workspace_sizing_and_validation():
+    from paper_1506_06185_amd import hhgr
+
+    d = hhgr.make_desc(n_sub=2, level=7)
+    n7 = hhgr.workspace_bytes(d)
+    assert 0.5e9 < n7 < 2e9
+    d8 = hhgr.make_desc(n_sub=2, level=8, precision="mixed")
+    assert hhgr.workspace_bytes(d8) > 7 * n7
+    for bad in (dict(level=2), dict(n_sub=0), dict(omega=2.5), dict(max_faults=9), dict(nu_pre=0, nu_post=0)):
+        with pytest.raises(hhgr.HHGRError) as e:
+            hhgr.workspace_bytes(hhgr.make_desc(**bad))
+        assert e.value.code == hhgr.HHGR_EINVAL
+
+
+@pytest.mark.parametrize("args", ["1 4", "2 5", "3 4"])
+def test_topology_host_checks(args, tmp_path):
+    exe = str(tmp_path / "topocheck")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-o", exe, os.path.join(ROOT, "tests/host/topology_check.cpp"),
+                    os.path.join(ROOT, "paper_1506_06185_amd/csrc/topology.cpp")], check=True)
+    out = subprocess.run([exe] + args.split(), capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "ok" in out.stdout

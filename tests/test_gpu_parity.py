@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element on the same seeded inputs.  Tolerances: per operator and per
+iterate 1e-12 relative (only summation order differs); converged FP64
+solutions 1e-10; mixed precision after refinement 1e-9."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_06185_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_1506_06185_amd import hhgr
+
+    hhgr.lib()
+    return hhgr
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# several tiles and ragged chunk tails per plane; n_sub = 1, 2, 3 meshes
+OP_CASES = [(1, 5), (2, 4), (3, 3)]
+
+
+@pytest.mark.parametrize("n_sub,level", OP_CASES)
+def test_operator_parity(dev, hh, oracle_problem, n_sub, level):
+    print(f"\n[op parity] n_sub={n_sub} level={level}", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    p = oracle_problem(n_sub, level)
+    g = np.random.default_rng(10 * n_sub + level)
+    nd = p.ndof
+    u, b = g.standard_normal(nd), g.standard_normal(nd)
+    # residual
+    r = N(hh.debug_op(ctx, 0, level, T(u, dev), T(b, dev)))
+    assert rel(r, p.residual(u, b)) < 1e-13
+    # colour passes and one full sweep
+    for op, colours in ((1, 1), (2, 2), (3, 3)):
+        us = N(hh.debug_op(ctx, op, level, T(u, dev), T(b, dev)))
+        assert rel(us, p.smooth(u, b, omega=1.25, colours=colours)) < 1e-13, op
+    # restriction, prolongation on every level pair
+    for l in range(level, 2, -1):
+        nf, nc = p.ndof_at(l), p.ndof_at(l - 1)
+        rf = g.standard_normal(nf)
+        bc = N(hh.debug_op(ctx, 4, l, T(rf, dev)))
+        assert rel(bc, p.restrict(rf, level=l)) < 1e-14
+        ec, uf = g.standard_normal(nc), g.standard_normal(nf)
+        up = N(hh.debug_op(ctx, 5, l, T(ec, dev), T(uf, dev)))
+        assert rel(up, p.prolong_add(ec, uf, level=l)) < 1e-15
+    # coarsest-level PCG
+    bc = g.standard_normal(p.ndof_at(2))
+    x = N(hh.debug_op(ctx, 6, 2, T(bc, dev)))
+    xo, _ = p.coarse_solve(bc)
+    assert rel(x, xo) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_sub,level", [(1, 4), (2, 4), (2, 5), (3, 3)])
+def test_vcycle_iterates(dev, hh, oracle_problem, n_sub, level):
+    print(f"\n[vcycle parity] n_sub={n_sub} level={level}", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    p = oracle_problem(n_sub, level)
+    g = np.random.default_rng(7)
+    b = g.standard_normal(p.ndof)
+    u = g.standard_normal(p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(T(u, dev))
+    for it in range(3):
+        relres = ctx.vcycle(1)
+        u, rn = p.vcycle(u, b)
+        assert rel(N(ctx.get_solution()), u) < 1e-12, it
+        assert relres == pytest.approx(rn / np.linalg.norm(b), rel=1e-10)
+    ctx.close()
+
+
+def test_solve_c1(dev, hh, oracle_problem):
+    # 6 macro tets, level 4, sine source, V(2,1) to 1e-8
+    n_sub, level = 1, 4
+    print("\n[solve C1]", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    f = inputs.sine_source(n_sub, level)
+    ctx.set_rhs(T(f, dev), hh.HHGR_RHS_NODAL_F)
+    cyc, rr, hist = ctx.solve(1e-8, 50)
+    p = oracle_problem(n_sub, level)
+    b = p.apply_M(f)
+    uo, co, ho = p.solve(b, rtol=1e-8)
+    assert cyc == co
+    # residual norms are exact up to ~1e-16 ||b|| of rounding in b - A u
+    assert np.allclose(hist, ho, rtol=1e-9, atol=1e-13)
+    assert rel(N(ctx.get_solution()), uo) < 1e-12
+    # converged solutions agree to 1e-10
+    ctx.solve(1e-13, 60)
+    ut, _, _ = p.solve(b, rtol=1e-13, max_cycles=60)
+    assert rel(N(ctx.get_solution()), ut) < 1e-10
+    ctx.close()
+
+
+def test_mass_apply(dev, hh, oracle_problem):
+    n_sub, level = 2, 4
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    x = np.random.default_rng(3).standard_normal(oracle_problem(n_sub, level).ndof)
+    y = N(ctx.mass_apply(T(x, dev)))
+    assert rel(y, oracle_problem(n_sub, level).apply_M(x)) < 1e-14
+    ctx.close()
+
+
+def test_fault_and_local_recovery(dev, hh, oracle_problem):
+    n_sub, level, kF = 2, 5, 5
+    print("\n[fault + recover_local]", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    p = oracle_problem(n_sub, level)
+    f = inputs.sine_source(n_sub, level)
+    b = p.apply_M(f)
+    ctx.set_rhs(T(f, dev), hh.HHGR_RHS_NODAL_F)
+    ctx.vcycle(kF)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=kF)
+    t = inputs.fault_tet(n_sub, seed=0)
+    ctx.inject_fault(t)
+    u = p.inject_fault(t, u)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    lr = ctx.recover_local(t, 3)
+    u, res = p.recover_local(t, u, b, n_cycles=3)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    assert lr == pytest.approx(res[-1], rel=1e-8)
+    cyc, rr, hist = ctx.solve(1e-8, 50)
+    uo, co, _ = p.solve(b, u0=u, rtol=1e-8, r0=np.linalg.norm(b))
+    assert cyc == co
+    assert rel(N(ctx.get_solution()), uo) < 1e-11
+    ctx.close()
+
+
+def test_dirichlet_dirichlet_recovery(dev, hh, oracle_problem):
+    n_sub, level = 2, 5
+    print("\n[recover_dd]", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    p = oracle_problem(n_sub, level)
+    b = inputs.uniform_load(n_sub, level, seed=1)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.vcycle(4)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=4)
+    tets = inputs.batch_faults(2, n_sub, seed=0)
+    for t in tets:
+        ctx.inject_fault(int(t))
+        u = p.inject_fault(int(t), u)
+    ctx.recover_dd([int(t) for t in tets], 2, 4)
+    u = p.dd_intact(tets, u, b, 2)
+    u, _ = p.recover_local(tets, u, b, n_cycles=4)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    # back to global cycles
+    ctx.vcycle(2)
+    u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=2)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    ctx.close()
+
+
+def test_mixed_precision(dev, hh, oracle_problem):
+    n_sub, level = 2, 5
+    print("\n[mixed]", flush=True)
+    p = oracle_problem(n_sub, level)
+    b = inputs.uniform_load(n_sub, level, seed=0)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, precision="mixed")
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    # first refinement step equals the oracle's FP32 step to FP32 rounding
+    ctx.vcycle(1)
+    u1, _, _ = p.solve_mixed(b, rtol=0.0, max_steps=1)
+    assert rel(N(ctx.get_solution()), u1) < 1e-5
+    cyc, rr, hist = ctx.solve(1e-12, 60)
+    u64, _, _ = p.solve(b, rtol=1e-13, max_cycles=60)
+    err = np.linalg.norm(N(ctx.get_solution()) - u64) / np.linalg.norm(u64)
+    assert err < 1e-9, err
+    ctx.close()
+
+
+def test_variable_coefficient_parity(dev, hh):
+    n_sub, level = 2, 4
+    print("\n[variable k]", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=0)
+    p = oracle.Problem(n_sub, level, k=k)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
+    ctx.set_coeff(T(k, dev))
+    g = np.random.default_rng(5)
+    u, b = g.standard_normal(p.ndof), g.standard_normal(p.ndof)
+    assert rel(N(hh.debug_op(ctx, 0, level, T(u, dev), T(b, dev))), p.residual(u, b)) < 1e-13
+    assert rel(N(hh.debug_op(ctx, 3, level, T(u, dev), T(b, dev))), p.smooth(u, b, 1.25, 3)) < 1e-13
+    bc = g.standard_normal(p.ndof_at(2))
+    assert rel(N(hh.debug_op(ctx, 6, 2, T(bc, dev))), p.coarse_solve(bc)[0]) < 1e-12
+    ctx.close()
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
+    ctx.set_coeff(T(k, dev))
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.vcycle(2)
+    uo, _, _ = p.solve(b, rtol=0.0, max_cycles=2)
+    assert rel(N(ctx.get_solution()), uo) < 1e-12
+    ctx.solve(1e-13, 60)
+    uo, _, _ = p.solve(b, rtol=1e-13, max_cycles=60)
+    assert rel(N(ctx.get_solution()), uo) < 1e-10
+    ctx.close()
+
+
+def test_adjoint_gradients(dev, hh):
+    n_sub, level = 1, 4
+    print("\n[adjoint]", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=0)
+    f = inputs.sine_source(n_sub, level)
+    uobs = inputs.gaussian_obs(n_sub, level, seed=0)
+    p = oracle.Problem(n_sub, level, k=k)
+    b = p.apply_M(f)
+    u, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+    lam, _, _ = p.solve(u - uobs, rtol=1e-13, max_cycles=80)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
+    fT = T(f, dev)
+    kT = T(k, dev)
+    uT = hh.HHGSolve.apply(ctx, fT.requires_grad_(True), kT.requires_grad_(True), 1e-13, 80)
+    assert rel(N(uT), u) < 1e-10
+    J = 0.5 * ((uT - T(uobs, dev)) ** 2).sum()
+    J.backward()
+    assert rel(N(fT.grad), p.apply_M(lam)) < 1e-9
+    assert rel(N(kT.grad), p.grad_k(u, lam)) < 1e-9
+    ctx.close()
+
+
+def test_batch_matches_sequential(dev, hh, oracle_problem):
+    print("\n[batch]", flush=True)
+    cases = [(2, 4), (2, 5), (1, 5)]
+    ctxs, refs = [], []
+    for q, (n_sub, level) in enumerate(cases):
+        c = hh.Context(device=dev, n_sub=n_sub, level=level)
+        b = inputs.uniform_load(n_sub, level, seed=q)
+        c.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+        ctxs.append(c)
+        refs.append(oracle_problem(n_sub, level).solve(b, rtol=1e-10, max_cycles=60))
+    batch = hh.Batch(ctxs)
+    out = batch.run(1e-10, 60)
+    for c, (cyc, rr, hist), (uo, co, ho) in zip(ctxs, out, refs):
+        assert cyc == co
+        assert rel(N(c.get_solution()), uo) < 1e-12
+    batch.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_graph_replay_matches_eager(dev, hh):
+    n_sub, level = 2, 5
+    print("\n[graph]", flush=True)
+    b = inputs.uniform_load(n_sub, level, seed=2)
+    res = []
+    for graph in (False, True):
+        ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+        ctx.set_graph(graph)
+        ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+        for _ in range(4):  # several replays with host reads in between
+            ctx.vcycle(1)
+        res.append(N(ctx.get_solution()))
+        ctx.close()
+    assert rel(res[1], res[0]) < 1e-14
