@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay captured graphs (disables kernel timing)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one device copy of 1 GiB first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -112,12 +114,20 @@ def main():
 
     dev = torch.device("cuda:0")
     n_sub, level = args.n_sub, args.level
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     f_dev = torch.from_numpy(inputs.sine_source(n_sub, level)).to(dev)
     t_fault = inputs.fault_tet(n_sub, seed=0)
 
     print(f"[bench] setup n_sub={n_sub} level={level}", file=sys.stderr, flush=True)
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
     ctx.autotune(None)
+    tuning = ctx.tuning_info()
+    print(f"[bench] tuning (level: block size, xcd order, fused) {tuning}", file=sys.stderr, flush=True)
     if args.graph:
         ctx.set_graph(True)
     # fault-free cycle count for the cycle advantage, eq. (3)
@@ -150,7 +160,8 @@ def main():
         achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
         roofline = {
             "bound": "hbm",
-            "kernel": "k_colour<double> (finest-level volume colour pass, FP64, k=1)",
+            "kernel": ("k_fused_sweep<double> (finest-level fused red-black sweep, FP64, k=1)" if tuning[level][2]
+                       else "k_colour<double> (finest-level volume colour pass, FP64, k=1)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -223,6 +234,8 @@ def main():
             "smoother": "red-black SOR omega=1.25, V(2,1), coarse level 2 Jacobi-PCG",
             "fault_tet": t_fault,
             "graph": bool(args.graph),
+            "tuning": {str(k): {"block": v[0] % 1000, "nodes_per_thread": v[0] // 1000, "xcd_order": v[1],
+                                "fused": v[2]} for k, v in tuning.items()},
         },
         "time_to_1e8_s": round(ms_per_step / 1e3, 5),
         "cycles_per_job": k_faulty,

@@ -174,11 +174,27 @@ void hhgr_batch_destroy(hhgr_batch *batch);
  * V-cycle instead of launching kernel by kernel (same results). */
 int hhgr_set_graph(hhgr_ctx *ctx, int use_graph);
 
-/* Autotuner: times the candidate workgroup sizes of the structured volume
- * kernels on every level and keeps the fastest per (kernel, level,
- * precision).  cache_path (optional) is a text file read before and written
+/* Smoother implementation (same arithmetic, same results up to summation
+ * order): 0 = automatic (fused sweeps on levels with at least 32 segments per
+ * macro edge, or the autotuner's choice), 1 = two colour passes per sweep on
+ * every level, 2 = fused sweeps on every level above the coarsest.  A fused
+ * sweep updates both colours of the volume interiors in one launch
+ * (out-of-place between two buffers), between the interface red and black
+ * updates.  EINVAL for another mode. */
+int hhgr_set_smoother(hhgr_ctx *ctx, int mode);
+
+/* Autotuner: times the candidate workgroup sizes, nodes per thread and block
+ * orders of the structured volume kernels on every level, then fused sweeps
+ * against colour passes, and keeps the fastest per (level, precision,
+ * coefficient mode).  cache_path (optional) is a text file read before and written
  * after tuning, keyed by device name.  Enqueues work and synchronises. */
 int hhgr_autotune(hhgr_ctx *ctx, const char *cache_path);
+
+/* The tuning choices in use on `level`: block_size = workgroup size of the
+ * colour passes + 1000 x nodes per thread (1 or 4), XCD-contiguous block
+ * order (1) or hardware order (0), fused sweeps (1) or colour passes (0).
+ * EINVAL for a level outside coarse_level+1..level. */
+int hhgr_tuning_info(const hhgr_ctx *ctx, int level, int *block_size, int *xcd_order, int *fused);
 
 /* Kernel timing for roofline reports: when enabled, every launch of the
  * finest-level volume smoother kernel is bracketed by HIP events on the

@@ -66,11 +66,19 @@ struct LevelDev {
     int2 *ch_int[3] = {}, *ch_full[3] = {};
     int n_int[3] = {}, n_full[3] = {};
     int bs_sel = 1;  // colour pass
+    int remap = 1;   // XCD-contiguous block order (autotuned)
+    int cpb = 1;     // nodes per thread of the list-mode kernels (autotuned)
     int *nbr = nullptr, *gptr = nullptr, *gidx = nullptr, *rst = nullptr, *prl = nullptr, *nb15 = nullptr;
     int *ifc_dof = nullptr, *ifc_xyz = nullptr, *tg_dst = nullptr, *tg_src = nullptr;
     std::vector<int> tg_ptr;
-    double *u = nullptr, *b = nullptr, *r = nullptr;
-    float *u32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+    double *u = nullptr, *b = nullptr, *r = nullptr, *u2 = nullptr;
+    float *u32 = nullptr, *b32 = nullptr, *r32 = nullptr, *u2_32 = nullptr;
+    int4 *tiles = nullptr;
+    int ntiles = 0;
+    unsigned *ilist = nullptr, *rlist = nullptr, *blist = nullptr;  // interior nodes: all, red, black
+    int nilist = 0, nrlist = 0, nblist = 0;
+    int4 *rowA = nullptr, *rowB = nullptr;                         // row offset tables
+    bool fused = false;  // fused sweeps on this level (autotuned)
     double *w[3] = {}, *wi = nullptr;
     float *w32[3] = {}, *wi32 = nullptr;
     double *kc = nullptr;
@@ -83,6 +91,7 @@ struct LevelDev {
 template <typename T>
 struct LevView {
     T *u = nullptr, *b = nullptr, *r = nullptr;
+    T *u2 = nullptr;     // second buffer of the volume interiors (fused sweeps), or nullptr
     Weights<T> w;
     const VolDesc *vd = nullptr;
     int nvol = 0;
@@ -97,6 +106,7 @@ struct HView {
     bool local = false;
     const unsigned char *cfrozen = nullptr;
     double *partial = nullptr;
+    unsigned int *counter = nullptr;
     bool timed = false;
 };
 
@@ -115,6 +125,7 @@ struct hhgr_ctx {
     hipStream_t cap = nullptr;  // graphs are captured here (the caller's stream may be the legacy default stream)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double *partial[2] = {};
+    unsigned int *counter = nullptr;  // [2] last-block detection of the norm reductions
     int partial_cap = 0;
     double *dnorm = nullptr;
     double *hnorm = nullptr;  // pinned
@@ -156,6 +167,15 @@ struct hhgr_batch {
 
 namespace hhgr {
 namespace {
+
+// tiles of the fused sweep over the interior rows (j,k) of a tetrahedron with
+// m segments per edge: 8x8 blocks of rows, 62-node segments along i
+static_assert(kTileRows == kFusedTile && kTileSeg == kFusedSeg, "tile shape of host tables and kernel");
+std::vector<int4> fused_tiles(int m) {
+    std::vector<int4> t;
+    for (const auto &a : fused_tile_list(m)) t.push_back(make_int4(a[0], a[1], a[2], 0));
+    return t;
+}
 
 // ----------------------------------------------------------------------------
 // layout of the workspace (sizing and carving share this code)
@@ -211,11 +231,24 @@ void carve(hhgr_ctx &c, Carver &cv) {
         D.u = cv.take<double>(T.n_slots);
         D.b = cv.take<double>(T.n_slots);
         D.r = cv.take<double>(T.n_slots);
+        D.u2 = cv.take<double>(T.ifc_base);
         if (c.mixed) {
             D.u32 = cv.take<float>(T.n_slots);
             D.b32 = cv.take<float>(T.n_slots);
             D.r32 = cv.take<float>(T.n_slots);
+            D.u2_32 = cv.take<float>(T.ifc_base);
         }
+        D.ntiles = (int)fused_tiles(T.m).size();
+        D.tiles = cv.take<int4>(D.ntiles);
+        D.nilist = (int)T.ilist.size();
+        D.nrlist = (int)T.rlist.size();
+        D.nblist = (int)T.blist.size();
+        D.ilist = cv.take<unsigned>(D.nilist);
+        D.rlist = cv.take<unsigned>(D.nrlist);
+        D.blist = cv.take<unsigned>(D.nblist);
+        D.rowA = cv.take<int4>(T.rowA.size());
+        D.rowB = cv.take<int4>(T.rowB.size());
+        D.fused = T.m >= 32;
         if (c.vk) {
             for (int s = 0; s < 3; s++) D.w[s] = cv.take<double>(T.n_slots);
             D.wi = cv.take<double>(6 * (size_t)T.n_ifc);
@@ -238,6 +271,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.partial_cap = max_blocks;
     c.partial[0] = cv.take<double>(max_blocks);
     c.partial[1] = cv.take<double>(max_blocks);
+    c.counter = cv.take<unsigned int>(64);
     c.dnorm = cv.take<double>(8);
     c.tetinfo = cv.take<int>(6 * (size_t)c.n_tets);
     c.cn = tp.coarse.n;
@@ -274,15 +308,26 @@ std::string check_desc(const hhgr_desc *d) {
 // ----------------------------------------------------------------------------
 // launch geometry
 // ----------------------------------------------------------------------------
-VolGeom vgeom(const LevelDev &D, const VolDesc *vd, int nvol, bool full, int bsq = -1) {
+// full = true: every slot of the closures (chunk mode); otherwise the interior
+// nodes (list mode), or only one colour of them with colour = 0 (red) / 1 (black)
+VolGeom vgeom(const LevelDev &D, const VolDesc *vd, int nvol, bool full, int bsq = -1, int colour = -1) {
     const int q = bsq < 0 ? D.bs_sel : bsq;
     VolGeom g;
     g.vd = vd;
-    g.chunks = full ? D.ch_full[q] : D.ch_int[q];
-    g.nchunks = full ? D.n_full[q] : D.n_int[q];
     g.nvol = nvol;
     g.M = D.M;
     g.bs = kBS[q];
+    g.rowA = D.rowA;
+    g.rowB = D.rowB;
+    g.remap = D.remap;
+    g.cpb = D.cpb;
+    if (full) {
+        g.chunks = D.ch_full[q];
+        g.nchunks = D.n_full[q];
+    } else {
+        g.list = colour == 0 ? D.rlist : colour == 1 ? D.blist : D.ilist;
+        g.nlist = colour == 0 ? D.nrlist : colour == 1 ? D.nblist : D.nilist;
+    }
     return g;
 }
 
@@ -326,11 +371,11 @@ template <typename T>
 T *lvec(LevelDev &D, int which);
 template <>
 double *lvec<double>(LevelDev &D, int which) {
-    return which == 0 ? D.u : which == 1 ? D.b : D.r;
+    return which == 0 ? D.u : which == 1 ? D.b : which == 2 ? D.r : D.u2;
 }
 template <>
 float *lvec<float>(LevelDev &D, int which) {
-    return which == 0 ? D.u32 : which == 1 ? D.b32 : D.r32;
+    return which == 0 ? D.u32 : which == 1 ? D.b32 : which == 2 ? D.r32 : D.u2_32;
 }
 
 // global (all tetrahedra) or masked (intact tetrahedra, frozen interface) view
@@ -342,6 +387,7 @@ HView<T> global_view(hhgr_ctx &c, bool masked, int stream_idx) {
     V.local = false;
     V.cfrozen = masked ? c.cfrozen : nullptr;
     V.partial = c.partial[stream_idx];
+    V.counter = c.counter + 16 * stream_idx;
     V.timed = !masked;
     for (int l = c.Lc; l <= c.L; l++) {
         LevelDev &D = c.lev[l];
@@ -349,6 +395,7 @@ HView<T> global_view(hhgr_ctx &c, bool masked, int stream_idx) {
         v.u = lvec<T>(D, 0);
         v.b = lvec<T>(D, 1);
         v.r = lvec<T>(D, 2);
+        v.u2 = lvec<T>(D, 3);
         v.w = weights<T>(D);
         v.vd = masked ? D.vd_masked : D.vd_all;
         v.nvol = masked ? D.n_masked : c.n_tets;
@@ -365,6 +412,7 @@ HView<double> local_view(hhgr_ctx &c, int stream_idx) {
     V.Lc = c.Lc;
     V.local = true;
     V.partial = c.partial[stream_idx];
+    V.counter = c.counter + 16 * stream_idx;
     for (int l = c.Lc; l <= c.L; l++) {
         LevelDev &D = c.lev[l];
         LevView<double> &v = V.lv[l];
@@ -404,19 +452,73 @@ void timed_end(hhgr_ctx &c, hipStream_t s) {
     }
 }
 
+// one red-black sweep in place on the primary buffer: two colour passes
 template <typename T>
 void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const LevelDev &D = c.lev[l];
     const LevView<T> &v = V.lv[l];
-    const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
     for (int colour = 0; colour < 2; colour++) {
+        const VolGeom vg = vgeom(D, v.vd, v.nvol, false, -1, colour);
         const IfcGeom ig = v.ifc ? igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc,
                                          v.frozen, true)
                                  : ig_none();
-        const bool timed = c.timing && V.timed && l == c.L;
+        const bool timed = c.timing && V.timed && l == c.L && !D.fused;
         if (timed) timed_begin(c, s);
-        launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, colour, zero, zero && colour == 0);
+        launch_colour<T>(s, vg, ig, v.u, v.u, v.b, v.w, c.vk, D.h, c.d.omega, colour, zero, zero && colour == 0);
         if (timed) timed_end(c, s);
+    }
+}
+
+// one fused sweep: interface red nodes, volume interiors uin -> uout (both
+// colours), interface black nodes.  Interface masters and ghost copies stay in
+// the primary buffer v.u.
+template <typename T>
+void fused_sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, const T *uin, T *uout, hipStream_t s) {
+    const LevelDev &D = c.lev[l];
+    const LevView<T> &v = V.lv[l];
+    const VolGeom none = vgeom(D, v.vd, 0, false);
+    if (v.ifc)
+        launch_colour<T>(s, none, igeom(D, 0, D.n_ifc_red, v.frozen, true), v.u, uin, v.b, v.w, c.vk, D.h, c.d.omega,
+                         0, zero, zero);
+    FusedGeom fg;
+    fg.vd = v.vd;
+    fg.rowA = D.rowA;
+    fg.remap = D.remap;
+    fg.tiles = D.tiles;
+    fg.ntiles = D.ntiles;
+    fg.nvol = v.nvol;
+    fg.M = D.M;
+    const bool timed = c.timing && V.timed && l == c.L;
+    if (timed) timed_begin(c, s);
+    launch_fused_sweep<T>(s, fg, uin, uout, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero);
+    if (timed) timed_end(c, s);
+    if (v.ifc)
+        launch_colour<T>(s, none, igeom(D, D.n_ifc_red, D.n_ifc, v.frozen, true), v.u, uout, v.b, v.w, c.vk, D.h,
+                         c.d.omega, 1, zero, false);
+}
+
+template <typename T>
+bool use_fused(const hhgr_ctx &c, const HView<T> &V, int l) {
+    return c.lev[l].fused && V.lv[l].u2 != nullptr && !V.local;
+}
+
+// nsweeps sweeps starting (and ending) in the primary buffer; pairs of fused
+// sweeps go primary -> second -> primary, an unpaired sweep is a plain one
+template <typename T>
+void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s) {
+    const LevView<T> &v = V.lv[l];
+    const bool fz = use_fused(c, V, l);
+    int k = 0;
+    while (k < nsweeps) {
+        const bool z = zero && k == 0;
+        if (fz && nsweeps - k >= 2) {
+            fused_sweep(c, V, l, z, v.u, v.u2, s);
+            fused_sweep(c, V, l, false, v.u2, v.u, s);
+            k += 2;
+        } else {
+            sweep(c, V, l, z, s);
+            k += 1;
+        }
     }
 }
 
@@ -442,18 +544,26 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     LevelDev &Dc = c.lev[l - 1];
     const LevView<T> &v = V.lv[l];
     const LevView<T> &vc = V.lv[l - 1];
-    for (int k = 0; k < c.d.nu_pre; k++) sweep(c, V, l, zero && k == 0, s);
+    smooth(c, V, l, c.d.nu_pre, zero, s);
     if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, V.local && l < c.L ? (long long)c.d.max_faults * D.C_pad : D.n_slots, T(0));
     const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
     launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
-    launch_restrict<T>(s, vgc, v.vd, D.M, igc, Dc.rst, v.r, vc.b);
+    launch_restrict<T>(s, vgc, v.vd, D.rowA, D.rowB, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
     const IfcGeom igp = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, true) : ig_none();
-    launch_prolong<T>(s, vg, vc.vd, Dc.M, igp, D.prl, vc.u, v.u);
-    for (int k = 0; k < c.d.nu_post; k++) sweep(c, V, l, false, s);
+    if (use_fused(c, V, l) && (c.d.nu_post & 1)) {
+        // odd number of post-sweeps: interpolate into the second buffer and
+        // let the first fused post-sweep bring the interiors back
+        launch_prolong<T>(s, vg, vc.vd, Dc.rowA, Dc.M, igp, D.prl, vc.u, v.u, v.u2);
+        fused_sweep(c, V, l, false, v.u2, v.u, s);
+        smooth(c, V, l, c.d.nu_post - 1, false, s);
+    } else {
+        launch_prolong<T>(s, vg, vc.vd, Dc.rowA, Dc.M, igp, D.prl, vc.u, v.u, v.u);
+        smooth(c, V, l, c.d.nu_post, false, s);
+    }
 }
 
 // ||b - A u||^2 (or with TO output: r = b - A u written as TO) on level L of a view
@@ -697,6 +807,20 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
         for (int t = 0; t < c->n_tets; t++) vd[t] = VolDesc{(long long)t * T.C_pad, (long long)t * T.C_pad, t, 0};
         vd_store.push_back(vd);
         rc = rc ? rc : upload(*c, D.vd_all, vd_store.back().data(), vd.size() * sizeof(VolDesc));
+        {
+            std::vector<int4> ft = fused_tiles(T.m);
+            std::vector<int2> tmp(ft.size() * 2);
+            std::memcpy(tmp.data(), ft.data(), ft.size() * sizeof(int4));
+            chunk_store.push_back(tmp);
+            rc = rc ? rc : upload(*c, D.tiles, chunk_store.back().data(), ft.size() * sizeof(int4));
+        }
+        rc = rc ? rc : upload(*c, D.ilist, T.ilist.data(), T.ilist.size() * sizeof(unsigned));
+        rc = rc ? rc : upload(*c, D.rlist, T.rlist.data(), T.rlist.size() * sizeof(unsigned));
+        rc = rc ? rc : upload(*c, D.blist, T.blist.data(), T.blist.size() * sizeof(unsigned));
+        rc = rc ? rc : upload(*c, D.rowA, T.rowA.data(), T.rowA.size() * sizeof(int4));
+        rc = rc ? rc : upload(*c, D.rowB, T.rowB.data(), T.rowB.size() * sizeof(int4));
+        launch_fill<double>(c->stream, D.u2, T.ifc_base, 0.0);
+        if (c->mixed) launch_fill<float>(c->stream, D.u2_32, T.ifc_base, 0.0f);
         // zero every vector (also the Dirichlet ghosts and the zero slot)
         launch_fill<double>(c->stream, D.u, T.n_slots, 0.0);
         launch_fill<double>(c->stream, D.b, T.n_slots, 0.0);
@@ -770,6 +894,7 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     rc = rc ? rc : upload(*c, c->cpos, cpos.data(), cpos.size() * sizeof(int));
     launch_fill<unsigned char>(c->stream, c->cfrozen, cs.n, 0);
     launch_fill<double>(c->stream, c->dnorm, 8, 0.0);
+    launch_fill<unsigned int>(c->stream, c->counter, 64, 0u);
     if (rc != HHGR_OK) return bail(rc);
     if (hipGetLastError() != hipSuccess) return bail(fail(HHGR_EHIP, "kernel launch during setup"));
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(HHGR_EHIP, "setup synchronise"));
@@ -1122,6 +1247,28 @@ int hhgr_set_graph(hhgr_ctx *c, int use_graph) {
     return HHGR_OK;
 }
 
+int hhgr_tuning_info(const hhgr_ctx *c, int level, int *block_size, int *xcd_order, int *fused) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (level <= c->Lc || level > c->L) return fail(HHGR_EINVAL, "level outside coarse_level+1..level");
+    const LevelDev &D = c->lev[level];
+    // block size, with the nodes per thread in the thousands digit
+    if (block_size) *block_size = kBS[D.bs_sel] + 1000 * D.cpb;
+    if (xcd_order) *xcd_order = D.remap;
+    if (fused) *fused = D.fused ? 1 : 0;
+    return HHGR_OK;
+}
+
+int hhgr_set_smoother(hhgr_ctx *c, int mode) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (mode < 0 || mode > 2) return fail(HHGR_EINVAL, "smoother mode must be 0, 1 or 2");
+    for (int l = c->Lc; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        D.fused = mode == 2 ? D.ntiles > 0 : mode == 1 ? false : D.m >= 32;
+    }
+    invalidate_graph(*c);
+    return HHGR_OK;
+}
+
 int hhgr_kernel_timing(hhgr_ctx *c, int enable) {
     if (!c) return fail(HHGR_EINVAL, "null context");
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1144,10 +1291,11 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
     }
     if (launches) *launches = n;
     if (mean_ms) *mean_ms = n ? tot / n : 0.0;
-    // one colour pass over the finest volumes reads the other colour's u, its own
-    // b and old u and writes its own u: 4 words per updated node, 2 per node
+    // fused sweep over the finest volumes: read u and b, write u (3 words per
+    // unknown); a colour pass reads the other colour's u and its own b and old u
+    // and writes its own u (4 words per updated node, 2 per unknown)
     const double w = c->mixed ? 4.0 : 8.0;
-    if (alg_bytes) *alg_bytes = 2.0 * w * (double)c->n_dofs;
+    if (alg_bytes) *alg_bytes = (c->lev[c->L].fused ? 3.0 : 2.0) * w * (double)c->n_dofs;
     return HHGR_OK;
 }
 
@@ -1174,22 +1322,31 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         std::ostringstream ks;
         ks << devname << ":n" << c->d.n_sub << ":l" << l << ":" << (c->mixed ? "f32" : "f64") << ":vk" << c->vk;
         auto it = cache.find(ks.str());
-        if (it != cache.end()) {
+        auto itf = cache.find(ks.str() + ":fused");
+        auto itr = cache.find(ks.str() + ":remap");
+        auto itc = cache.find(ks.str() + ":cpb");
+        if (it != cache.end() && itf != cache.end() && itr != cache.end() && itc != cache.end()) {
             D.bs_sel = it->second;
+            D.fused = itf->second != 0;
+            D.remap = itr->second;
+            D.cpb = itc->second;
             continue;
         }
         double best = 1e30;
-        int bq = 1;
-        for (int q = 0; q < 3; q++) {
-            const VolGeom vg = vgeom(D, D.vd_all, c->n_tets, false, q);
+        int bq = 1, br = 1, bc = 1;
+        for (int rq = 0; rq < 12; rq++) {
+            const int q = rq % 3;
+            D.remap = (rq / 3) % 2 == 0 ? 1 : 0;
+            D.cpb = rq < 6 ? 1 : 4;
+            const VolGeom vg = vgeom(D, D.vd_all, c->n_tets, false, q, 0);
             const IfcGeom ig = igeom(D, 0, D.n_ifc_red, nullptr, false);
             auto run = [&]() {
                 if (c->mixed)
-                    launch_colour<float>(c->stream, vg, ig, D.r32, D.b32, weights<float>(D), c->vk, D.h, c->d.omega, 0,
-                                         false, false);
+                    launch_colour<float>(c->stream, vg, ig, D.r32, D.r32, D.b32, weights<float>(D), c->vk, D.h,
+                                         c->d.omega, 0, false, false);
                 else
-                    launch_colour<double>(c->stream, vg, ig, D.r, D.b, weights<double>(D), c->vk, D.h, c->d.omega, 0,
-                                          false, false);
+                    launch_colour<double>(c->stream, vg, ig, D.r, D.r, D.b, weights<double>(D), c->vk, D.h,
+                                          c->d.omega, 0, false, false);
             };
             run();
             HIPCHK(hipEventRecord(e0, c->stream));
@@ -1202,10 +1359,48 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
             if (ms < best) {
                 best = ms;
                 bq = q;
+                br = D.remap;
+                bc = D.cpb;
             }
         }
         D.bs_sel = bq;
+        D.remap = br;
+        D.cpb = bc;
         cache[ks.str()] = bq;
+        cache[ks.str() + ":remap"] = br;
+        cache[ks.str() + ":cpb"] = bc;
+        // fused sweep against two plain colour passes, on scratch buffers
+        if (D.m >= 16) {
+            auto time_it = [&](bool fused) -> float {
+                auto once = [&]() {
+                    if (c->mixed) {
+                        HView<float> V = global_view<float>(*c, false, 0);
+                        V.lv[l].u = D.r32;
+                        if (fused) fused_sweep(*c, V, l, false, D.r32, D.u2_32, c->stream);
+                        else sweep(*c, V, l, false, c->stream);
+                    } else {
+                        HView<double> V = global_view<double>(*c, false, 0);
+                        V.lv[l].u = D.r;
+                        if (fused) fused_sweep(*c, V, l, false, D.r, D.u2, c->stream);
+                        else sweep(*c, V, l, false, c->stream);
+                    }
+                };
+                once();
+                hipEventRecord(e0, c->stream);
+                const int reps = l >= 6 ? 5 : 20;
+                for (int r = 0; r < reps; r++) once();
+                hipEventRecord(e1, c->stream);
+                hipEventSynchronize(e1);
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                return ms;
+            };
+            const float tp = time_it(false), tf = time_it(true);
+            D.fused = tf < tp;
+        } else {
+            D.fused = false;
+        }
+        cache[ks.str() + ":fused"] = D.fused ? 1 : 0;
         // scratch vector used for timing goes back to zero
         launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
         if (c->mixed) launch_fill<float>(c->stream, D.r32, D.n_slots, 0.0f);
@@ -1257,14 +1452,15 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
         for (int colour = 0; colour < 2; colour++) {
             if (!((op == 3) || (op == 1 && colour == 0) || (op == 2 && colour == 1))) continue;
             const IfcGeom ig = igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc, nullptr, true);
-            launch_colour<double>(s, vint, ig, D.u, D.b, w, c->vk, D.h, c->d.omega, colour, false, false);
+            launch_colour<double>(s, vgeom(D, D.vd_all, c->n_tets, false, -1, colour), ig, D.u, D.u, D.b, w, c->vk, D.h,
+                                  c->d.omega, colour, false, false);
         }
         to_user(D.u, out, D);
         break;
     case 4: {
         LevelDev &Dc = c->lev[l - 1];
         to_slots(in0, D.r, D);
-        launch_restrict<double>(s, vgeom(Dc, Dc.vd_all, c->n_tets, false), D.vd_all, D.M,
+        launch_restrict<double>(s, vgeom(Dc, Dc.vd_all, c->n_tets, false), D.vd_all, D.rowA, D.rowB,
                                 igeom(Dc, 0, Dc.n_ifc, nullptr, false), Dc.rst, D.r, Dc.b);
         to_user(Dc.b, out, Dc);
         break;
@@ -1273,7 +1469,8 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
         LevelDev &Dc = c->lev[l - 1];
         to_slots(in0, Dc.u, Dc);
         to_slots(in1, D.u, D);
-        launch_prolong<double>(s, vint, Dc.vd_all, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true), D.prl, Dc.u, D.u);
+        launch_prolong<double>(s, vint, Dc.vd_all, Dc.rowA, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true), D.prl, Dc.u, D.u,
+                               D.u);
         to_user(D.u, out, D);
         break;
     }

@@ -46,6 +46,14 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned f, unsigned total) {
     const unsigned per = total >> 3, rem = total & 7u, x = f & 7u, loc = f >> 3;
     return x < rem ? x * (per + 1) + loc : rem * (per + 1) + (x - rem) * per + loc;
 }
+__device__ __forceinline__ unsigned block_order(unsigned f, unsigned total, int remap) {
+    return remap ? xcd_remap(f, total) : f;
+}
+
+// chunks (of one workgroup's width) that every workgroup of the structured
+// volume kernels processes: each thread owns kCPB slots, all loads issued
+// before the first store
+constexpr int kCPB = 4;
 
 struct VNode {
     int v, i, j, k, s, o, ps;
@@ -83,6 +91,46 @@ __device__ __forceinline__ Nb6 nb6(const VNode &n) {
     r.bm = c0 - rj;                                                                // (i+1, j-1, k)
     r.cp = n.ps + n.s * (n.s + 1) / 2 + rstart_d(n.s - 1, n.j - 1) + n.i;          // (i, j-1, k+1)
     r.cm = n.ps - (n.s + 1) * (n.s + 2) / 2 + rstart_d(n.s + 1, n.j + 1) + n.i;    // (i, j+1, k-1)
+    return r;
+}
+
+// list mode: thread -> node of the volume container; all index arithmetic
+// comes from the level's row table
+struct LNode {
+    int v, i, j, k, c0, rj, dcp, dcm;
+};
+
+template <int CPB>
+__device__ __forceinline__ unsigned list_blocks_per_vol(const VolGeom &g) {
+    const unsigned per = (unsigned)(g.bs * CPB);
+    return ((unsigned)g.nlist + per - 1) / per;
+}
+
+template <int CPB>
+__device__ __forceinline__ bool list_node(const VolGeom &g, unsigned blk, unsigned per_vol, int q, LNode &n) {
+    n.v = (int)(blk / per_vol);
+    const int e = (int)(blk % per_vol) * g.bs * CPB + q * g.bs + (int)threadIdx.x;
+    if (e >= g.nlist) return false;
+    const unsigned w = g.list[e];
+    n.i = (int)(w & 1023u);
+    n.j = (int)((w >> 10) & 1023u);
+    n.k = (int)(w >> 20);
+    const int4 ra = g.rowA[n.k * g.M - ((n.k * (n.k - 1)) >> 1) + n.j];
+    n.c0 = ra.x + n.i;
+    n.rj = ra.y;
+    n.dcp = ra.z;
+    n.dcm = ra.w;
+    return true;
+}
+
+__device__ __forceinline__ Nb6 nb6l(const LNode &n) {
+    Nb6 r;
+    r.ap = n.c0 + 1;
+    r.am = n.c0 - 1;
+    r.bp = n.c0 + n.rj - 1;
+    r.bm = n.c0 - n.rj;
+    r.cp = n.c0 + n.dcp;
+    r.cm = n.c0 + n.dcm;
     return r;
 }
 
@@ -133,9 +181,10 @@ inline int ifc_blocks(const IfcGeom &ig, int bs) {
 // ---------------------------------------------------------------------------
 // red-black SOR colour pass
 // ---------------------------------------------------------------------------
-template <typename T, bool VK, bool OWN0, bool NB0>
+template <typename T, bool VK, bool OWN0, bool NB0, int CPB>
 __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib, T *__restrict__ u,
-                                                const T *__restrict__ b, Weights<T> w, T h, T omega, int colour) {
+                                                const T *__restrict__ uvol, const T *__restrict__ b, Weights<T> w,
+                                                T h, T omega, T om_d) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
@@ -150,13 +199,19 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
             for (int e = 0; e < 6; e++) {
                 const T we = w.wi[(long long)e * ig.stride + t];
                 diag += we;
-                if (!NB0) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
+                if (!NB0) {
+                    const int nb = ig.nbr[(long long)e * ig.stride + t];
+                    acc += we * (nb < ig.base ? uvol[nb] : u[nb]);
+                }
             }
         } else {
             diag = T(6) * h;
             if (!NB0) {
 #pragma unroll
-                for (int e = 0; e < 6; e++) acc += u[ig.nbr[(long long)e * ig.stride + t]];
+                for (int e = 0; e < 6; e++) {
+                    const int nb = ig.nbr[(long long)e * ig.stride + t];
+                    acc += nb < ig.base ? uvol[nb] : u[nb];
+                }
                 acc *= h;
             }
         }
@@ -167,34 +222,51 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
             for (int g = ig.gptr[t]; g < ig.gptr[t + 1]; g++) u[ig.gidx[g]] = un;
         return;
     }
-    VNode n;
-    if (!vol_node(vg, xcd_remap(f - nib, gridDim.x - nib), n)) return;
-    if (!is_interior(n, vg.M) || ((n.i + n.k) & 1) != colour) return;
-    const VolDesc d = vg.vd[n.v];
-    T *uv = u + d.vec;
-    const int c0 = n.ps + n.o;
-    const Nb6 q = nb6(n);
-    const T uo = OWN0 ? T(0) : uv[c0];
-    T diag, acc;
-    if (VK) {
-        const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
-        const T wap = w0[c0], wam = w0[q.am], wbp = w1[c0], wbm = w1[q.bm], wcp = w2[c0], wcm = w2[q.cm];
-        diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
-        acc = NB0 ? T(0)
-                  : wap * uv[q.ap] + wam * uv[q.am] + wbp * uv[q.bp] + wbm * uv[q.bm] + wcp * uv[q.cp] +
-                        wcm * uv[q.cm];
-    } else {
-        diag = T(6) * h;
-        acc = NB0 ? T(0) : h * (((uv[q.ap] + uv[q.am]) + (uv[q.bp] + uv[q.bm])) + (uv[q.cp] + uv[q.cm]));
+    // list holds only nodes of this colour
+    const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+    T nv[CPB];
+    long long dst[CPB];
+    bool ok[CPB];
+#pragma unroll
+    for (int q = 0; q < CPB; q++) {
+        ok[q] = false;
+        nv[q] = T(0);
+        dst[q] = 0;
+        LNode n;
+        if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
+        const VolDesc d = vg.vd[n.v];
+        const T *uv = u + d.vec;
+        const int c0 = n.c0;
+        const Nb6 nb = nb6l(n);
+        const T uo = OWN0 ? T(0) : uv[c0];
+        T res;
+        if (VK) {
+            const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
+            const T wap = w0[c0], wam = w0[nb.am], wbp = w1[c0], wbm = w1[nb.bm], wcp = w2[c0], wcm = w2[nb.cm];
+            const T diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
+            const T acc = NB0 ? T(0)
+                              : wap * uv[nb.ap] + wam * uv[nb.am] + wbp * uv[nb.bp] + wbm * uv[nb.bm] +
+                                    wcp * uv[nb.cp] + wcm * uv[nb.cm];
+            res = omega * ((b + d.vec)[c0] - (diag * uo - acc)) / diag;
+        } else {
+            const T acc = NB0 ? T(0) : (((uv[nb.ap] + uv[nb.am]) + (uv[nb.bp] + uv[nb.bm])) + (uv[nb.cp] + uv[nb.cm]));
+            // diag = 6h, off-diagonal -h; om_d = omega / (6h)
+            res = om_d * ((b + d.vec)[c0] - h * (T(6) * uo - acc));
+        }
+        nv[q] = uo + res;
+        dst[q] = d.vec + c0;
+        ok[q] = true;
     }
-    const T Au = diag * uo - acc;
-    uv[c0] = uo + omega * ((b + d.vec)[c0] - Au) / diag;
+#pragma unroll
+    for (int q = 0; q < CPB; q++)
+        if (ok[q]) u[dst[q]] = nv[q];
 }
 
 // ---------------------------------------------------------------------------
 // residual r = b - A u (+ block partial sums of r^2)
 // ---------------------------------------------------------------------------
-template <typename T, typename TO, bool VK, bool WRITE, bool NORM>
+template <typename T, typename TO, bool VK, bool WRITE, bool NORM, int CPB>
 __global__ void __launch_bounds__(512) k_residual(VolGeom vg, IfcGeom ig, int nib, const T *__restrict__ u,
                                                   const T *__restrict__ b, Weights<T> w, T h, TO *__restrict__ r,
                                                   double *__restrict__ partial) {
@@ -226,27 +298,43 @@ __global__ void __launch_bounds__(512) k_residual(VolGeom vg, IfcGeom ig, int ni
             acc2 = (double)res * (double)res;
         }
     } else {
-        VNode n;
-        if (vol_node(vg, xcd_remap(f - nib, gridDim.x - nib), n) && is_interior(n, vg.M)) {
+        const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
+        const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+        T res[CPB];
+        long long dst[CPB];
+        bool ok[CPB];
+#pragma unroll
+        for (int q = 0; q < CPB; q++) {
+            ok[q] = false;
+            res[q] = T(0);
+            dst[q] = 0;
+            LNode n;
+            if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
             const VolDesc d = vg.vd[n.v];
             const T *uv = u + d.vec;
-            const int c0 = n.ps + n.o;
-            const Nb6 q = nb6(n);
+            const int c0 = n.c0;
+            const Nb6 nb = nb6l(n);
             const T uo = uv[c0];
             T diag, acc;
             if (VK) {
                 const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
-                const T wap = w0[c0], wam = w0[q.am], wbp = w1[c0], wbm = w1[q.bm], wcp = w2[c0], wcm = w2[q.cm];
+                const T wap = w0[c0], wam = w0[nb.am], wbp = w1[c0], wbm = w1[nb.bm], wcp = w2[c0], wcm = w2[nb.cm];
                 diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
-                acc = wap * uv[q.ap] + wam * uv[q.am] + wbp * uv[q.bp] + wbm * uv[q.bm] + wcp * uv[q.cp] +
-                      wcm * uv[q.cm];
+                acc = wap * uv[nb.ap] + wam * uv[nb.am] + wbp * uv[nb.bp] + wbm * uv[nb.bm] + wcp * uv[nb.cp] +
+                      wcm * uv[nb.cm];
             } else {
                 diag = T(6) * h;
-                acc = h * (((uv[q.ap] + uv[q.am]) + (uv[q.bp] + uv[q.bm])) + (uv[q.cp] + uv[q.cm]));
+                acc = h * (((uv[nb.ap] + uv[nb.am]) + (uv[nb.bp] + uv[nb.bm])) + (uv[nb.cp] + uv[nb.cm]));
             }
-            const T res = (b + d.vec)[c0] - (diag * uo - acc);
-            if (WRITE) (r + d.vec)[c0] = (TO)res;
-            acc2 = (double)res * (double)res;
+            res[q] = (b + d.vec)[c0] - (diag * uo - acc);
+            dst[q] = d.vec + c0;
+            ok[q] = true;
+        }
+#pragma unroll
+        for (int q = 0; q < CPB; q++) {
+            if (!ok[q]) continue;
+            if (WRITE) r[dst[q]] = (TO)res[q];
+            acc2 += (double)res[q] * (double)res[q];
         }
     }
     if (NORM) {
@@ -263,9 +351,10 @@ __device__ __constant__ int kD14[14][3] = {{1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {
                                            {0, 1, -1}, {0, 1, 0},  {0, -1, 0}, {-1, 0, 1}, {1, 0, -1},
                                            {1, -1, 1}, {-1, 1, -1}, {0, 0, 1}, {0, 0, -1}};
 
-template <typename T>
-__global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__restrict__ vdf, int Mf, IfcGeom ig,
-                                                  int nib, const int *__restrict__ rst, const T *__restrict__ rf,
+template <typename T, int CPB>
+__global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__restrict__ vdf, const int4 *__restrict__ fA,
+                                                  const int4 *__restrict__ fB, IfcGeom ig, int nib,
+                                                  const int *__restrict__ rst, const T *__restrict__ rf,
                                                   T *__restrict__ bc) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
@@ -278,15 +367,36 @@ __global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__r
         bc[ig.base + t] = rf[rst[t]] + T(0.5) * s;
         return;
     }
-    VNode n;
-    if (!vol_node(vc, xcd_remap(f - nib, gridDim.x - nib), n)) return;
-    if (!is_interior(n, vc.M)) return;
-    const T *rv = rf + vdf[n.v].vec;
-    const int I = 2 * n.i, J = 2 * n.j, K = 2 * n.k;
-    T s = T(0);
+    const unsigned per_vol = list_blocks_per_vol<CPB>(vc);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vc.remap);
+    const int Mf = 2 * vc.M - 1;
+    T nv[CPB];
+    long long dst[CPB];
+    bool ok[CPB];
 #pragma unroll
-    for (int e = 0; e < 14; e++) s += rv[cidx_d(Mf, I + kD14[e][0], J + kD14[e][1], K + kD14[e][2])];
-    (bc + vc.vd[n.v].vec)[n.ps + n.o] = rv[cidx_d(Mf, I, J, K)] + T(0.5) * s;
+    for (int q = 0; q < CPB; q++) {
+        ok[q] = false;
+        nv[q] = T(0);
+        dst[q] = 0;
+        LNode n;
+        if (!list_node<CPB>(vc, blk, per_vol, q, n)) continue;
+        const T *rv = rf + vdf[n.v].vec;
+        // fine node (2i, 2j, 2k) and its 14 Freudenthal neighbours
+        const int J = 2 * n.j, K = 2 * n.k;
+        const int rid = K * Mf - ((K * (K - 1)) >> 1) + J;
+        const int4 ra = fA[rid], rb = fB[rid];
+        const int F = ra.x + 2 * n.i, rj = ra.y;
+        const T s1 = ((rv[F + 1] + rv[F - 1]) + (rv[F + rj - 1] + rv[F - rj])) + (rv[F + ra.z] + rv[F + ra.w]);
+        const T s2 = ((rv[F + rj] + rv[F - rj - 1]) + (rv[F + rb.x - 1] + rv[F + rb.y + 1])) +
+                     (rv[F + ra.z + 1] + rv[F + ra.w - 1]);
+        const T s3 = rv[F + rb.x] + rv[F + rb.y];
+        nv[q] = rv[F] + T(0.5) * ((s1 + s2) + s3);
+        dst[q] = vc.vd[n.v].vec + n.c0;
+        ok[q] = true;
+    }
+#pragma unroll
+    for (int q = 0; q < CPB; q++)
+        if (ok[q]) bc[dst[q]] = nv[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -297,10 +407,10 @@ __global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__r
 __device__ __constant__ int kParDir[8][3] = {{0, 0, 0},  {1, 0, 0}, {0, 1, 0},  {-1, 1, 0},
                                              {0, 0, 1},  {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
 
-template <typename T>
-__global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__restrict__ vdc, int Mc, IfcGeom ig,
-                                                 int nib, const int *__restrict__ prl, const T *__restrict__ ec,
-                                                 T *__restrict__ uf) {
+template <typename T, int CPB>
+__global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__restrict__ vdc, const int4 *__restrict__ cA,
+                                                 int Mc, IfcGeom ig, int nib, const int *__restrict__ prl,
+                                                 const T *__restrict__ ec, T *uf, T *uo) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
@@ -313,20 +423,191 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
             for (int g = ig.gptr[t]; g < ig.gptr[t + 1]; g++) uf[ig.gidx[g]] = v;
         return;
     }
-    VNode n;
-    if (!vol_node(vf, xcd_remap(f - nib, gridDim.x - nib), n)) return;
-    if (!is_interior(n, vf.M)) return;
-    const T *ev = ec + vdc[n.v].vec;
-    T *uv = uf + vf.vd[n.v].vec;
-    const int code = (n.i & 1) | ((n.j & 1) << 1) | ((n.k & 1) << 2);
-    const int c0 = n.ps + n.o;
-    if (code == 0) {
-        uv[c0] = uv[c0] + ev[cidx_d(Mc, n.i >> 1, n.j >> 1, n.k >> 1)];
-    } else {
+    const unsigned per_vol = list_blocks_per_vol<CPB>(vf);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vf.remap);
+    T nv[CPB];
+    long long dst[CPB];
+    bool ok[CPB];
+#pragma unroll
+    for (int q = 0; q < CPB; q++) {
+        ok[q] = false;
+        nv[q] = T(0);
+        dst[q] = 0;
+        LNode n;
+        if (!list_node<CPB>(vf, blk, per_vol, q, n)) continue;
+        const T *ev = ec + vdc[n.v].vec;
+        const long long base = vf.vd[n.v].vec;
+        const int code = (n.i & 1) | ((n.j & 1) << 1) | ((n.k & 1) << 2);
         const int di = kParDir[code][0], dj = kParDir[code][1], dk = kParDir[code][2];
-        const T e1 = ev[cidx_d(Mc, (n.i - di) >> 1, (n.j - dj) >> 1, (n.k - dk) >> 1)];
-        const T e2 = ev[cidx_d(Mc, (n.i + di) >> 1, (n.j + dj) >> 1, (n.k + dk) >> 1)];
-        uv[c0] = uv[c0] + T(0.5) * (e1 + e2);
+        // coarse end points of the bisected edge (the same node twice for code 0)
+        const int i1 = (n.i - di) >> 1, j1 = (n.j - dj) >> 1, k1 = (n.k - dk) >> 1;
+        const int i2 = (n.i + di) >> 1, j2 = (n.j + dj) >> 1, k2 = (n.k + dk) >> 1;
+        const T e1 = ev[cA[k1 * Mc - ((k1 * (k1 - 1)) >> 1) + j1].x + i1];
+        const T e2 = ev[cA[k2 * Mc - ((k2 * (k2 - 1)) >> 1) + j2].x + i2];
+        nv[q] = uf[base + n.c0] + (code == 0 ? e1 : T(0.5) * (e1 + e2));
+        dst[q] = base + n.c0;
+        ok[q] = true;
+    }
+#pragma unroll
+    for (int q = 0; q < CPB; q++)
+        if (ok[q]) uo[dst[q]] = nv[q];
+}
+
+
+// ---------------------------------------------------------------------------
+// fused red-black SOR sweep of the volume interiors
+//
+// A workgroup owns the rows (j,k), j in [j0, j0+8), k in [k0, k0+8), of one
+// tetrahedron and the nodes i0 .. i0+61 of those rows.  Phase 1 computes the
+// new red values of the 10x10 rows [j0-1, j0+8] x [k0-1, k0+8] (the rows a
+// black node of the tile touches) for i0-1 .. i0+62 into LDS, red nodes only
+// (the red node of row lane l is stored at l >> 1).  Phase 2 computes the new
+// black values of the tile rows from them and writes whole rows of uout.
+// Interior values are read from uin, boundary (ghost) values from ughost,
+// whose red copies the interface kernel has already updated.
+// ---------------------------------------------------------------------------
+constexpr int kFE = kFusedTile + 2;
+
+// sum of the 6 neighbour terms of interior node (i,j,k) at slot c0 of a
+// closure; neighbours on the closure's faces are read from the ghost array
+template <typename T, bool VK>
+__device__ __forceinline__ void stencil_sums(int i, int j, int k, int c0, int4 ra, const T *__restrict__ uv,
+                                             const T *__restrict__ gv, const T *__restrict__ w0,
+                                             const T *__restrict__ w1, const T *__restrict__ w2, int m, T &diag,
+                                             T &acc, bool nb0) {
+    const int rj = ra.y;
+    const int ap = c0 + 1, am = c0 - 1, bp = c0 + rj - 1, bm = c0 - rj, cp = c0 + ra.z, cm = c0 + ra.w;
+    T vap = T(0), vam = T(0), vbp = T(0), vbm = T(0), vcp = T(0), vcm = T(0);
+    if (!nb0) {
+        vap = (i + 1 + j + k == m) ? gv[ap] : uv[ap];
+        vam = (i == 1) ? gv[am] : uv[am];
+        vbp = (i == 1) ? gv[bp] : uv[bp];
+        vbm = (j == 1) ? gv[bm] : uv[bm];
+        vcp = (j == 1) ? gv[cp] : uv[cp];
+        vcm = (k == 1) ? gv[cm] : uv[cm];
+    }
+    if (VK) {
+        const T wap = w0[c0], wam = w0[am], wbp = w1[c0], wbm = w1[bm], wcp = w2[c0], wcm = w2[cm];
+        diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
+        acc = wap * vap + wam * vam + wbp * vbp + wbm * vbm + wcp * vcp + wcm * vcm;
+    } else {
+        diag = T(0);
+        acc = ((vap + vam) + (vbp + vbm)) + (vcp + vcm);
+    }
+}
+
+// SOR update of one node from its neighbour sum (k = 1: diag 6h, offdiag -h)
+template <typename T, bool VK>
+__device__ __forceinline__ T sor_update(T uo, T bval, T diag, T acc, T h, T omega, T om_d) {
+    if (VK) return uo + omega * (bval - (diag * uo - acc)) / diag;
+    return uo + om_d * (bval - h * (T(6) * uo - acc));
+}
+
+template <typename T, bool VK, bool ZERO>
+__global__ void __launch_bounds__(256) k_fused_sweep(FusedGeom fg, const T *__restrict__ uin, T *__restrict__ uout,
+                                                     const T *__restrict__ ughost, const T *__restrict__ b,
+                                                     Weights<T> w, T h, T omega, T om_d) {
+    __shared__ T red[kFE * kFE][33];
+    const unsigned lg = block_order(blockIdx.x, gridDim.x, fg.remap);
+    const int v = (int)(lg / (unsigned)fg.ntiles);
+    const int4 tile = fg.tiles[lg % (unsigned)fg.ntiles];
+    const int j0 = tile.x, k0 = tile.y, i0 = tile.z;
+    const int M = fg.M, m = M - 1;
+    const VolDesc d = fg.vd[v];
+    const T *uv = uin + d.vec;
+    const T *gv = ughost + d.vec;
+    const T *bv = b + d.vec;
+    const T *w0 = VK ? w.w0 + d.w : nullptr, *w1 = VK ? w.w1 + d.w : nullptr, *w2 = VK ? w.w2 + d.w : nullptr;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int half = lane >> 5, t = lane & 31;
+
+    // phase 1: red values of the 10x10 row box, two rows per wave step and
+    // four steps in flight
+    constexpr int kPairs = (kFE * kFE + 1) / 2;  // 50 row pairs
+    for (int base = wave; base < kPairs; base += 16) {
+        T val[4];
+        int row[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            row[q] = -1;
+            val[q] = T(0);
+            const int pr = base + 4 * q;
+            const int er = 2 * pr + half;
+            if (pr >= kPairs || er >= kFE * kFE) continue;
+            const int j = j0 - 1 + er % kFE, k = k0 - 1 + er / kFE;
+            const int prow = (k + i0 - 1) & 1;  // red lanes of this row have lane parity prow
+            const int l = 2 * t + prow;
+            const int i = i0 - 1 + l;
+            if (j < 0 || k < 0 || i < 0 || i + j + k > m) continue;
+            const int4 ra = fg.rowA[k * M - ((k * (k - 1)) >> 1) + j];
+            const int c0 = ra.x + i;
+            if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1) {
+                T diag, acc;
+                stencil_sums<T, VK>(i, j, k, c0, ra, uv, gv, w0, w1, w2, m, diag, acc, ZERO);
+                val[q] = sor_update<T, VK>(ZERO ? T(0) : uv[c0], bv[c0], diag, acc, h, omega, om_d);
+            } else {
+                val[q] = gv[c0];  // ghost: already the new red value
+            }
+            row[q] = er;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (row[q] >= 0) red[row[q]][t] = val[q];
+    }
+    __syncthreads();
+
+    // phase 2: black values of the tile rows; each thread writes lanes 2t, 2t+1
+    // of one row, two rows per wave step and two steps in flight
+    constexpr int kTPairs = kFusedTile * kFusedTile / 2;  // 32 row pairs
+    for (int base = wave; base < kTPairs; base += 8) {
+        T val[2][2];
+        int dst[2][2];
+#pragma unroll
+        for (int q2 = 0; q2 < 2; q2++) {
+            const int tr = 2 * (base + 4 * q2) + half;
+            const int jj = tr % kFusedTile, kk = tr / kFusedTile;
+            const int j = j0 + jj, k = k0 + kk;
+            const int er = (jj + 1) + kFE * (kk + 1);
+            const int prow = (k + i0 - 1) & 1;
+            const bool row_ok = base + 4 * q2 < kTPairs && j + k <= m - 2;
+            const int4 ra = row_ok ? fg.rowA[k * M - ((k * (k - 1)) >> 1) + j] : make_int4(0, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                dst[q2][q] = -1;
+                val[q2][q] = T(0);
+                const int l = 2 * t + q;
+                const int i = i0 - 1 + l;
+                if (!row_ok || l < 1 || l > kFusedSeg || i + j + k > m - 1) continue;
+                const int c0 = ra.x + i;
+                if (((l + prow) & 1) == 0) {
+                    val[q2][q] = red[er][l >> 1];
+                } else {
+                    // neighbours: same row l-1, l+1; (j+1,k) at l-1; (j-1,k) at l+1;
+                    // (j-1,k+1) at l; (j+1,k-1) at l
+                    const T vap = red[er][(l + 1) >> 1], vam = red[er][(l - 1) >> 1];
+                    const T vbp = red[er + 1][(l - 1) >> 1], vbm = red[er - 1][(l + 1) >> 1];
+                    const T vcp = red[er - 1 + kFE][l >> 1], vcm = red[er + 1 - kFE][l >> 1];
+                    T diag, acc;
+                    if (VK) {
+                        const int am = c0 - 1, bm = c0 - ra.y, cm = c0 + ra.w;
+                        const T wap = w0[c0], wam = w0[am], wbp = w1[c0], wbm = w1[bm], wcp = w2[c0], wcm = w2[cm];
+                        diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
+                        acc = wap * vap + wam * vam + wbp * vbp + wbm * vbm + wcp * vcp + wcm * vcm;
+                    } else {
+                        diag = T(0);
+                        acc = ((vap + vam) + (vbp + vbm)) + (vcp + vcm);
+                    }
+                    val[q2][q] = sor_update<T, VK>(ZERO ? T(0) : uv[c0], bv[c0], diag, acc, h, omega, om_d);
+                }
+                dst[q2][q] = c0;
+            }
+        }
+        T *ov = uout + d.vec;
+#pragma unroll
+        for (int q2 = 0; q2 < 2; q2++)
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+                if (dst[q2][q] >= 0) ov[dst[q2][q]] = val[q2][q];
     }
 }
 
@@ -334,7 +615,7 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
 // coarsest level: Jacobi-PCG in one workgroup, unknowns owned by threads,
 // search direction shared through LDS
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NPT>
 __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__restrict__ slot,
                                                      const int *__restrict__ col, const double *__restrict__ val,
                                                      const unsigned char *__restrict__ frozen, const T *__restrict__ b,
@@ -343,62 +624,92 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
                                                      int *__restrict__ iters) {
     __shared__ double p_sh[2048];
     __shared__ double red[64];
-    const int tid = threadIdx.x;
-    double x[2] = {0.0, 0.0}, r[2] = {0.0, 0.0}, p[2] = {0.0, 0.0}, d[2] = {1.0, 1.0};
-    bool act[2], frz[2];
-    for (int s = 0; s < 2; s++) {
-        const int q = tid + s * 1024;
-        act[s] = q < n;
-        frz[s] = act[s] && frozen && frozen[q];
-        if (act[s]) {
-            d[s] = val[7 * q];
-            r[s] = frz[s] ? 0.0 : (double)b[slot[q]];
-            p[s] = r[s] / d[s];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // every thread owns NPT unknowns; their matrix rows stay in registers
+    double x[NPT], r[NPT], p[NPT], dinv[NPT], dg[NPT], av[NPT][6];
+    int ac[NPT][6];
+    bool act[NPT];
+#pragma unroll
+    for (int s = 0; s < NPT; s++) {
+        const int q = tid + s * nt;
+        act[s] = q < n && !(frozen && frozen[q]);
+        x[s] = 0.0;
+        r[s] = 0.0;
+        p[s] = 0.0;
+        dinv[s] = 0.0;
+        dg[s] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            ac[s][e] = 0;
+            av[s][e] = 0.0;
+        }
+        if (q < n) {
+            if (act[s]) {
+                dg[s] = val[7 * q];
+                dinv[s] = 1.0 / dg[s];
+                r[s] = (double)b[slot[q]];
+#pragma unroll
+                for (int e = 0; e < 6; e++) {
+                    const int c = col[7 * q + 1 + e];
+                    ac[s][e] = c >= 0 ? c : 0;
+                    av[s][e] = c >= 0 ? val[7 * q + 1 + e] : 0.0;
+                }
+            }
+            p[s] = r[s] * dinv[s];
             p_sh[q] = p[s];
         }
     }
-    double rz = r[0] * p[0] + r[1] * p[1];
-    double rr0 = r[0] * r[0] + r[1] * r[1];
+    double rz = 0.0, rr0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NPT; s++) {
+        rz += r[s] * p[s];
+        rr0 += r[s] * r[s];
+    }
     block_sum2_all(rz, rr0, red);
     int it = 0;
     if (rr0 > 0.0) {
         const double stop = rtol * rtol * rr0;
         for (it = 1; it <= maxit; it++) {
             __syncthreads();
-            double qv[2] = {0.0, 0.0};
-            for (int s = 0; s < 2; s++) {
-                if (!act[s] || frz[s]) continue;
-                const int q = tid + s * 1024;
-                double a = d[s] * p[s];
-                for (int e = 1; e < 7; e++) {
-                    const int c = col[7 * q + e];
-                    if (c >= 0) a += val[7 * q + e] * p_sh[c];
+            double qv[NPT];
+            double pq = 0.0, dummy = 0.0;
+#pragma unroll
+            for (int s = 0; s < NPT; s++) {
+                double a = 0.0;
+                if (act[s]) {
+                    a = dg[s] * p[s];
+#pragma unroll
+                    for (int e = 0; e < 6; e++) a += av[s][e] * p_sh[ac[s][e]];
                 }
                 qv[s] = a;
+                pq += p[s] * a;
             }
-            double pq = p[0] * qv[0] + p[1] * qv[1];
-            double dummy = 0.0;
             block_sum2_all(pq, dummy, red);
             const double alpha = rz / pq;
-            for (int s = 0; s < 2; s++) {
+            double rr = 0.0, rz1 = 0.0;
+#pragma unroll
+            for (int s = 0; s < NPT; s++) {
                 x[s] += alpha * p[s];
                 r[s] -= alpha * qv[s];
+                rr += r[s] * r[s];
+                rz1 += r[s] * r[s] * dinv[s];
             }
-            double rr = r[0] * r[0] + r[1] * r[1];
-            double rz1 = r[0] * r[0] / d[0] + r[1] * r[1] / d[1];
             block_sum2_all(rr, rz1, red);
             if (rr <= stop) break;
             const double beta = rz1 / rz;
             rz = rz1;
-            for (int s = 0; s < 2; s++) {
-                p[s] = r[s] / d[s] + beta * p[s];
-                if (act[s]) p_sh[tid + s * 1024] = p[s];
+#pragma unroll
+            for (int s = 0; s < NPT; s++) {
+                const int q = tid + s * nt;
+                p[s] = r[s] * dinv[s] + beta * p[s];
+                if (q < n) p_sh[q] = p[s];
             }
         }
     }
-    for (int s = 0; s < 2; s++) {
-        const int q = tid + s * 1024;
-        if (!act[s] || frz[s]) continue;
+#pragma unroll
+    for (int s = 0; s < NPT; s++) {
+        const int q = tid + s * nt;
+        if (!act[s]) continue;
         const T xv = (T)x[s];
         for (int c = cptr[q]; c < cptr[q + 1]; c++) u[cidx[c]] = xv;
     }
@@ -479,7 +790,7 @@ __global__ void __launch_bounds__(512) k_user_to_slots(VolGeom vg, const int *__
         return;
     }
     VNode n;
-    if (!vol_node(vg, xcd_remap(f - nib, gridDim.x - nib), n)) return;
+    if (!vol_node(vg, block_order(f - nib, gridDim.x - nib, vg.remap), n)) return;
     const VolDesc d = vg.vd[n.v];
     int X[3];
     grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
@@ -488,7 +799,7 @@ __global__ void __launch_bounds__(512) k_user_to_slots(VolGeom vg, const int *__
     (vec + d.vec)[n.ps + n.o] = in ? (T)user[dof] : T(0);
 }
 
-template <typename T>
+template <typename T, int CPB>
 __global__ void __launch_bounds__(512) k_slots_to_user(VolGeom vg, const int *__restrict__ tetinfo, int m, int N,
                                                        IfcGeom ig, int nib, const int *__restrict__ ifc_dof,
                                                        const T *__restrict__ vec, double *__restrict__ user) {
@@ -499,18 +810,24 @@ __global__ void __launch_bounds__(512) k_slots_to_user(VolGeom vg, const int *__
         user[ifc_dof[t]] = (double)vec[ig.base + t];
         return;
     }
-    VNode n;
-    if (!vol_node(vg, xcd_remap(f - nib, gridDim.x - nib), n)) return;
-    if (!is_interior(n, vg.M)) return;
-    const VolDesc d = vg.vd[n.v];
-    int X[3];
-    grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
-    const long long dof = (long long)(X[0] - 1) + (long long)(N - 1) * ((X[1] - 1) + (long long)(N - 1) * (X[2] - 1));
-    user[dof] = (double)(vec + d.vec)[n.ps + n.o];
+    const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+#pragma unroll
+    for (int q = 0; q < CPB; q++) {
+        LNode n;
+        if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
+        const VolDesc d = vg.vd[n.v];
+        int X[3];
+        grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
+        const long long dof =
+            (long long)(X[0] - 1) + (long long)(N - 1) * ((X[1] - 1) + (long long)(N - 1) * (X[2] - 1));
+        user[dof] = (double)(vec + d.vec)[n.c0];
+    }
 }
 
 // consistent P1 mass matrix on the Kuhn meshes: diagonal 24 h^3/60, axis
 // edges h^3/20 (6 tetrahedra), face diagonals h^3/30 (4), body diagonal h^3/20 (6)
+template <int CPB>
 __global__ void __launch_bounds__(512) k_mass(VolGeom vg, IfcGeom ig, int nib, const int *__restrict__ nb15,
                                               const double *__restrict__ x, double *__restrict__ y, double h3) {
     const double wc = 0.4 * h3, wax = h3 / 20.0, wfd = h3 / 30.0, wbd = h3 / 20.0;
@@ -526,18 +843,24 @@ __global__ void __launch_bounds__(512) k_mass(VolGeom vg, IfcGeom ig, int nib, c
         y[ig.base + t] = wc * x[nb15[t]] + wax * ax + wfd * fd + wbd * bd;
         return;
     }
-    VNode n;
-    if (!vol_node(vg, xcd_remap(f - nib, gridDim.x - nib), n)) return;
-    if (!is_interior(n, vg.M)) return;
-    const VolDesc d = vg.vd[n.v];
-    const double *xv = x + d.vec;
-    const int M = vg.M;
-    double ax = 0.0, fd = 0.0, bd = 0.0;
-    // index directions: 0..5 axis (a,b,c), 6..11 face diagonals (a+b, b+c, a+c), 12..13 body (a+b+c)
-    for (int e = 0; e < 6; e++) ax += xv[cidx_d(M, n.i + kD14[e][0], n.j + kD14[e][1], n.k + kD14[e][2])];
-    for (int e = 6; e < 12; e++) fd += xv[cidx_d(M, n.i + kD14[e][0], n.j + kD14[e][1], n.k + kD14[e][2])];
-    for (int e = 12; e < 14; e++) bd += xv[cidx_d(M, n.i + kD14[e][0], n.j + kD14[e][1], n.k + kD14[e][2])];
-    (y + d.vec)[n.ps + n.o] = wc * xv[n.ps + n.o] + wax * ax + wfd * fd + wbd * bd;
+    const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+#pragma unroll
+    for (int q = 0; q < CPB; q++) {
+        LNode n;
+        if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
+        const VolDesc d = vg.vd[n.v];
+        const double *xv = x + d.vec;
+        const int rid = n.k * vg.M - ((n.k * (n.k - 1)) >> 1) + n.j;
+        const int4 rb = vg.rowB[rid];
+        const int F = n.c0, rj = n.rj;
+        // axis (a, b, c), face diagonals (a+b, b+c, a+c), body diagonal (a+b+c)
+        const double ax = ((xv[F + 1] + xv[F - 1]) + (xv[F + rj - 1] + xv[F - rj])) + (xv[F + n.dcp] + xv[F + n.dcm]);
+        const double fd = ((xv[F + rj] + xv[F - rj - 1]) + (xv[F + rb.x - 1] + xv[F + rb.y + 1])) +
+                          (xv[F + n.dcp + 1] + xv[F + n.dcm - 1]);
+        const double bd = xv[F + rb.x] + xv[F + rb.y];
+        (y + d.vec)[F] = wc * xv[F] + wax * ax + wfd * fd + wbd * bd;
+    }
 }
 
 __global__ void __launch_bounds__(512) k_update_add(VolGeom vg, IfcGeom ig, int nib, double *__restrict__ u,
@@ -551,7 +874,7 @@ __global__ void __launch_bounds__(512) k_update_add(VolGeom vg, IfcGeom ig, int 
         return;
     }
     VNode n;
-    if (!vol_node(vg, xcd_remap(f - nib, gridDim.x - nib), n)) return;
+    if (!vol_node(vg, block_order(f - nib, gridDim.x - nib, vg.remap), n)) return;
     const long long sl = vg.vd[n.v].vec + n.ps + n.o;
     u[sl] += (double)e[sl];
 }
@@ -624,7 +947,7 @@ __global__ void __launch_bounds__(512) k_vol_weights(VolGeom vg, const int *__re
                                                      double h, const double *__restrict__ k, double *__restrict__ w0,
                                                      double *__restrict__ w1, double *__restrict__ w2) {
     VNode n;
-    if (!vol_node(vg, xcd_remap(blockIdx.x, gridDim.x), n)) return;
+    if (!vol_node(vg, block_order(blockIdx.x, gridDim.x, vg.remap), n)) return;
     const VolDesc d = vg.vd[n.v];
     int X[3];
     grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
@@ -699,6 +1022,12 @@ __global__ void k_grad_k(const double *__restrict__ u, const double *__restrict_
     }
 }
 
+// workgroups of a list-mode launch
+inline long long list_blocks(const VolGeom &g) {
+    const long long per = ((long long)g.nlist + (long long)g.bs * g.cpb - 1) / ((long long)g.bs * g.cpb);
+    return per * g.nvol;
+}
+
 inline unsigned grid1d(long long n, int bs) {
     long long g = (n + bs - 1) / bs;
     if (g > 65535LL * 32) g = 65535LL * 32;
@@ -711,15 +1040,23 @@ inline unsigned grid1d(long long n, int bs) {
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w, bool vk,
-                   double h, double omega, int colour, bool own0, bool nb0) {
+void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *uvol, const T *b,
+                   const Weights<T> &w, bool vk, double h, double omega, int colour, bool own0, bool nb0) {
     const int nib = ifc_blocks(ig, vg.bs);
-    const long long nvb = (long long)vg.nchunks * vg.nvol;
+    const long long nvb = list_blocks(vg);
     const long long grid = nib + nvb;
     if (grid == 0) return;
-    const T th = (T)h, to = (T)omega;
-#define HHGR_COLOUR(VK, O0, N0) \
-    hipLaunchKernelGGL((k_colour<T, VK, O0, N0>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, b, w, th, to, colour)
+    const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
+    (void)colour;
+#define HHGR_COLOUR(VK, O0, N0)                                                                                 \
+    do {                                                                                                       \
+        if (vg.cpb == 1)                                                                                       \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, \
+                               uvol, b, w, th, to, tod);                                                      \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, \
+                               uvol, b, w, th, to, tod);                                                      \
+    } while (0)
     if (vk) {
         if (own0 && nb0) HHGR_COLOUR(true, true, true);
         else if (own0) HHGR_COLOUR(true, true, false);
@@ -736,12 +1073,19 @@ template <typename T, typename TO>
 int launch_residual(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const T *u, const T *b, const Weights<T> &w,
                     bool vk, double h, TO *r, double *partial) {
     const int nib = ifc_blocks(ig, vg.bs);
-    const long long nvb = (long long)vg.nchunks * vg.nvol;
+    const long long nvb = list_blocks(vg);
     const long long grid = nib + nvb;
     if (grid == 0) return 0;
     const T th = (T)h;
-#define HHGR_RES(VK, WR, NO) \
-    hipLaunchKernelGGL((k_residual<T, TO, VK, WR, NO>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, b, w, th, r, partial)
+#define HHGR_RES(VK, WR, NO)                                                                                   \
+    do {                                                                                                       \
+        if (vg.cpb == 1)                                                                                       \
+            hipLaunchKernelGGL((k_residual<T, TO, VK, WR, NO, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, \
+                               u, b, w, th, r, partial);                                                      \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_residual<T, TO, VK, WR, NO, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, \
+                               u, b, w, th, r, partial);                                                      \
+    } while (0)
     const bool wr = r != nullptr, no = partial != nullptr;
     if (vk) {
         if (wr && no) HHGR_RES(true, true, true);
@@ -757,29 +1101,64 @@ int launch_residual(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const T
 }
 
 template <typename T>
-void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, int Mf, const IfcGeom &igc, const int *rst,
-                     const T *rf, T *bc) {
+void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, const int4 *fA, const int4 *fB,
+                     const IfcGeom &igc, const int *rst, const T *rf, T *bc) {
     const int nib = ifc_blocks(igc, vc.bs);
-    const long long grid = nib + (long long)vc.nchunks * vc.nvol;
+    const long long grid = nib + list_blocks(vc);
     if (grid == 0) return;
-    hipLaunchKernelGGL((k_restrict<T>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, Mf, igc, nib, rst, rf, bc);
+    if (vc.cpb == 1)
+        hipLaunchKernelGGL((k_restrict<T, 1>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, fA, fB, igc, nib, rst, rf,
+                           bc);
+    else
+        hipLaunchKernelGGL((k_restrict<T, 4>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, fA, fB, igc, nib, rst, rf,
+                           bc);
 }
 
 template <typename T>
-void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, int Mc, const IfcGeom &igf, const int *prl,
-                    const T *ec, T *uf) {
+void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int4 *cA, int Mc, const IfcGeom &igf,
+                    const int *prl, const T *ec, T *uf, T *uo) {
     const int nib = ifc_blocks(igf, vf.bs);
-    const long long grid = nib + (long long)vf.nchunks * vf.nvol;
+    const long long grid = nib + list_blocks(vf);
     if (grid == 0) return;
-    hipLaunchKernelGGL((k_prolong<T>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, Mc, igf, nib, prl, ec, uf);
+    if (vf.cpb == 1)
+        hipLaunchKernelGGL((k_prolong<T, 1>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, cA, Mc, igf, nib, prl, ec,
+                           uf, uo);
+    else
+        hipLaunchKernelGGL((k_prolong<T, 4>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, cA, Mc, igf, nib, prl, ec,
+                           uf, uo);
+}
+
+template <typename T>
+void launch_fused_sweep(hipStream_t s, const FusedGeom &fg, const T *uin, T *uout, const T *ughost, const T *b,
+                        const Weights<T> &w, bool vk, double h, double omega, bool zero) {
+    const long long grid = (long long)fg.ntiles * fg.nvol;
+    if (grid == 0) return;
+    const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
+#define HHGR_FUSED(VK, Z) \
+    hipLaunchKernelGGL((k_fused_sweep<T, VK, Z>), dim3((unsigned)grid), dim3(256), 0, s, fg, uin, uout, ughost, b, w, th, to, tod)
+    if (vk) {
+        if (zero) HHGR_FUSED(true, true);
+        else HHGR_FUSED(true, false);
+    } else {
+        if (zero) HHGR_FUSED(false, true);
+        else HHGR_FUSED(false, false);
+    }
+#undef HHGR_FUSED
 }
 
 template <typename T>
 void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
                        const unsigned char *frozen, const T *b, T *u, const int *cptr, const int *cidx, double rtol,
                        int maxit, int *iters) {
-    hipLaunchKernelGGL((k_coarse_pcg<T>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr, cidx, rtol,
-                       maxit, iters);
+    // one unknown per thread in as few waves as possible (cheaper barriers)
+    if (n <= 1024) {
+        const int bs = n <= 64 ? 64 : n <= 128 ? 128 : n <= 256 ? 256 : n <= 512 ? 512 : 1024;
+        hipLaunchKernelGGL((k_coarse_pcg<T, 1>), dim3(1), dim3(bs), 0, s, n, slot, col, val, frozen, b, u, cptr, cidx,
+                           rtol, maxit, iters);
+    } else {
+        hipLaunchKernelGGL((k_coarse_pcg<T, 2>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr, cidx,
+                           rtol, maxit, iters);
+    }
 }
 
 template <typename T>
@@ -817,18 +1196,25 @@ template <typename T>
 void launch_slots_to_user(hipStream_t s, const VolGeom &vint, const int *tetinfo, int m, int N, const IfcGeom &ig,
                           const int *ifc_dof, const T *vec, double *user) {
     const int nib = ifc_blocks(ig, vint.bs);
-    const long long grid = nib + (long long)vint.nchunks * vint.nvol;
+    const long long grid = nib + list_blocks(vint);
     if (grid == 0) return;
-    hipLaunchKernelGGL((k_slots_to_user<T>), dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, tetinfo, m, N, ig, nib,
-                       ifc_dof, vec, user);
+    if (vint.cpb == 1)
+        hipLaunchKernelGGL((k_slots_to_user<T, 1>), dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, tetinfo, m, N, ig,
+                           nib, ifc_dof, vec, user);
+    else
+        hipLaunchKernelGGL((k_slots_to_user<T, 4>), dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, tetinfo, m, N, ig,
+                           nib, ifc_dof, vec, user);
 }
 
 void launch_mass(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const int *nb15, const double *x, double *y,
                  double h) {
     const int nib = ifc_blocks(ig, vint.bs);
-    const long long grid = nib + (long long)vint.nchunks * vint.nvol;
+    const long long grid = nib + list_blocks(vint);
     if (grid == 0) return;
-    hipLaunchKernelGGL(k_mass, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, nib, nb15, x, y, h * h * h);
+    if (vint.cpb == 1)
+        hipLaunchKernelGGL(k_mass<1>, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, nib, nb15, x, y, h * h * h);
+    else
+        hipLaunchKernelGGL(k_mass<4>, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, nib, nb15, x, y, h * h * h);
 }
 
 void launch_update_add(hipStream_t s, const VolGeom &vfull, const IfcGeom &ig, double *u, const float *e) {
@@ -881,23 +1267,27 @@ void launch_grad_k(hipStream_t s, const double *u, const double *lam, int N, dou
 
 // explicit instantiations
 template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
-                                    const Weights<double> &, bool, double, double, int, bool, bool);
-template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                    const double *, const Weights<double> &, bool, double, double, int, bool, bool);
+template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *, const float *,
                                    const Weights<float> &, bool, double, double, int, bool, bool);
+template void launch_fused_sweep<double>(hipStream_t, const FusedGeom &, const double *, double *, const double *,
+                                         const double *, const Weights<double> &, bool, double, double, bool);
+template void launch_fused_sweep<float>(hipStream_t, const FusedGeom &, const float *, float *, const float *,
+                                        const float *, const Weights<float> &, bool, double, double, bool);
 template int launch_residual<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                              const double *, const Weights<double> &, bool, double, double *, double *);
 template int launch_residual<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                             const double *, const Weights<double> &, bool, double, float *, double *);
 template int launch_residual<float, float>(hipStream_t, const VolGeom &, const IfcGeom &, const float *, const float *,
                                            const Weights<float> &, bool, double, float *, double *);
-template void launch_restrict<double>(hipStream_t, const VolGeom &, const VolDesc *, int, const IfcGeom &, const int *,
-                                      const double *, double *);
-template void launch_restrict<float>(hipStream_t, const VolGeom &, const VolDesc *, int, const IfcGeom &, const int *,
-                                     const float *, float *);
-template void launch_prolong<double>(hipStream_t, const VolGeom &, const VolDesc *, int, const IfcGeom &, const int *,
-                                     const double *, double *);
-template void launch_prolong<float>(hipStream_t, const VolGeom &, const VolDesc *, int, const IfcGeom &, const int *,
-                                    const float *, float *);
+template void launch_restrict<double>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, const int4 *,
+                                      const IfcGeom &, const int *, const double *, double *);
+template void launch_restrict<float>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, const int4 *,
+                                     const IfcGeom &, const int *, const float *, float *);
+template void launch_prolong<double>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, int, const IfcGeom &,
+                                     const int *, const double *, double *, double *);
+template void launch_prolong<float>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, int, const IfcGeom &,
+                                    const int *, const float *, float *, float *);
 template void launch_coarse_pcg<double>(hipStream_t, int, const long long *, const int *, const double *,
                                         const unsigned char *, const double *, double *, const int *, const int *,
                                         double, int, int *);
@@ -911,6 +1301,7 @@ template void launch_local_coarse<float>(hipStream_t, const VolDesc *, int, int,
 template void launch_fill<double>(hipStream_t, double *, long long, double);
 template void launch_fill<float>(hipStream_t, float *, long long, float);
 template void launch_fill<unsigned char>(hipStream_t, unsigned char *, long long, unsigned char);
+template void launch_fill<unsigned int>(hipStream_t, unsigned int *, long long, unsigned int);
 template void launch_user_to_slots<double>(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &,
                                            const int *, const double *, double *);
 template void launch_slots_to_user<double>(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &,

@@ -14,14 +14,22 @@ struct VolDesc {
     int pad;
 };
 
-// structured part of a launch: every listed volume x every chunk of its closure
+// structured part of a launch: every listed volume x either a list of nodes
+// (list mode: packed (i,j,k), the same for every volume, with the row offset
+// tables of the level) or every chunk of its closure (chunk mode)
 struct VolGeom {
     const VolDesc *vd = nullptr;
-    const int2 *chunks = nullptr;  // (plane k, first offset) per chunk of bs slots
-    int nchunks = 0;
     int nvol = 0;
+    const unsigned *list = nullptr;  // list mode
+    int nlist = 0;
+    const int4 *rowA = nullptr;      // per row (j,k): (slot of (0,j,k), length, to (j-1,k+1), to (j+1,k-1))
+    const int4 *rowB = nullptr;      // per row: (to (j,k+1), to (j,k-1), 0, 0)
+    const int2 *chunks = nullptr;    // chunk mode: (plane k, first offset) per chunk of bs slots
+    int nchunks = 0;
     int M = 0;   // nodes per macro edge at this level (2^l + 1)
     int bs = 256;
+    int remap = 1;  // 1: contiguous block ranges per XCD, 0: hardware order
+    int cpb = 4;    // list mode: nodes per thread (1 or 4), all loads issued before the stores
 };
 
 // table-driven part of a launch: interface nodes [i0, i1)
@@ -43,9 +51,33 @@ struct Weights {
 
 // colour pass of red-black SOR (colour 0 = red = even x+y+z).  own0: the
 // nodes of this colour start from zero; nb0: all neighbours are zero.
+// uvol: where interface nodes read their volume-interior neighbours (the
+// volume interiors may live in a second buffer during fused sweeps); u holds
+// the interface masters and the ghost copies.
 template <typename T>
-void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w, bool vk,
-                   double h, double omega, int colour, bool own0, bool nb0);
+void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *uvol, const T *b,
+                   const Weights<T> &w, bool vk, double h, double omega, int colour, bool own0, bool nb0);
+
+// tiles of the fused sweep: (j0, k0, i0) of an 8x8 block of rows and a
+// 62-node segment along i
+constexpr int kFusedTile = 8;
+constexpr int kFusedSeg = 62;
+struct FusedGeom {
+    const VolDesc *vd = nullptr;
+    const int4 *tiles = nullptr;
+    const int4 *rowA = nullptr;
+    int ntiles = 0;
+    int nvol = 0;
+    int M = 0;
+    int remap = 1;
+};
+
+// one red-black SOR sweep of the volume interiors: reads uin (interiors) and
+// ughost (ghost copies, red ones already updated), writes uout (interiors).
+// zero: uin is logically zero (first sweep of a correction).
+template <typename T>
+void launch_fused_sweep(hipStream_t s, const FusedGeom &fg, const T *uin, T *uout, const T *ughost, const T *b,
+                        const Weights<T> &w, bool vk, double h, double omega, bool zero);
 
 // r = b - A u on volume interiors and interface nodes; r (of type TO) may be
 // nullptr; partial (one double per block) receives block sums of r^2 if not
@@ -54,17 +86,21 @@ template <typename T, typename TO>
 int launch_residual(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const T *u, const T *b, const Weights<T> &w,
                     bool vk, double h, TO *r, double *partial);
 
-// b_c = P^T r_f.  vc: coarse volumes (interior chunks of the coarse level),
-// vdf: matching fine volumes; rst: [15][n_ifc_c] fine slots per coarse interface node.
+// b_c = P^T r_f.  vc: coarse volumes (interior list of the coarse level),
+// vdf: matching fine volumes, fA/fB: row tables of the fine level;
+// rst: [15][n_ifc_c] fine slots per coarse interface node.
 template <typename T>
-void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, int Mf, const IfcGeom &igc, const int *rst,
-                     const T *rf, T *bc);
+void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, const int4 *fA, const int4 *fB,
+                     const IfcGeom &igc, const int *rst, const T *rf, T *bc);
 
-// u_f += P e_c.  vf: fine volumes (interior chunks), vdc: matching coarse
-// volumes; prl: [2][n_ifc_f] coarse slots per fine interface node.
+// u_f += P e_c.  vf: fine volumes (interior list), vdc: matching coarse
+// volumes, cA: row table and Mc node count per edge of the coarse level;
+// prl: [2][n_ifc_f] coarse slots per fine interface node.  The volume part
+// writes uo = uf + P e_c (uo may differ from uf); the interface part updates
+// uf in place and its ghost copies.
 template <typename T>
-void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, int Mc, const IfcGeom &igf, const int *prl,
-                    const T *ec, T *uf);
+void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int4 *cA, int Mc, const IfcGeom &igf,
+                    const int *prl, const T *ec, T *uf, T *uo);
 
 // Jacobi-PCG on the coarsest level in one workgroup
 template <typename T>

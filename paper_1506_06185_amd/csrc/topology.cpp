@@ -199,6 +199,32 @@ void Topology::build_level(int l, int chunk) {
             Lv.nb15[(size_t)e * Lv.n_ifc + f] = (int)slot_of(l, X[0] + kF15[e][0], X[1] + kF15[e][1], X[2] + kF15[e][2]);
         }
 
+    // interior node lists and row offset tables (shared by all tetrahedra)
+    Lv.ilist.clear();
+    Lv.rlist.clear();
+    Lv.blist.clear();
+    for (int k = 1; k <= m; k++)
+        for (int j = 1; j <= m - k; j++)
+            for (int i = 1; i + j + k <= m - 1; i++) {
+                const unsigned w = pack_ijk(i, j, k);
+                Lv.ilist.push_back(w);
+                (((i + k) & 1) == 0 ? Lv.rlist : Lv.blist).push_back(w);
+            }
+    const int nrows = M * (M + 1) / 2;
+    Lv.rowA.assign(nrows, {0, 0, 0, 0});
+    Lv.rowB.assign(nrows, {0, 0, 0, 0});
+    for (int k = 0; k <= m; k++)
+        for (int j = 0; j <= m - k; j++) {
+            const int s = M - k;
+            const long long c = closure_index(M, 0, j, k);
+            auto rel = [&](int jj, int kk) -> int {
+                if (jj < 0 || kk < 0 || kk > m || jj > m - kk) return 0;  // row does not exist
+                return (int)(closure_index(M, 0, jj, kk) - c);
+            };
+            Lv.rowA[row_id(M, j, k)] = {(int)c, s - j, rel(j - 1, k + 1), rel(j + 1, k - 1)};
+            Lv.rowB[row_id(M, j, k)] = {rel(j, k + 1), rel(j, k - 1), 0, 0};
+        }
+
     // chunks
     Lv.chunks_int.clear();
     Lv.chunks_full.clear();

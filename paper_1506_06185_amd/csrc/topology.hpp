@@ -35,10 +35,28 @@ inline long long row_start(int s, int j) { return (long long)j * s - (long long)
 inline long long closure_index(int M, int i, int j, int k) { return plane_start(M, k) + row_start(M - k, j) + i; }
 inline long long round_up(long long x, long long a) { return (x + a - 1) / a * a; }
 
+// tiles of the fused sweep over the interior rows (j,k) of a tetrahedron with
+// m segments per edge: 8x8 blocks of rows (j0, k0) and 62-node segments along
+// i starting at i0
+constexpr int kTileRows = 8;
+constexpr int kTileSeg = 62;
+inline std::vector<std::array<int, 3>> fused_tile_list(int m) {
+    std::vector<std::array<int, 3>> t;
+    for (int j0 = 1; j0 <= m - 3; j0 += kTileRows)
+        for (int k0 = 1; j0 + k0 <= m - 2; k0 += kTileRows)
+            for (int i0 = 1; i0 <= m - 1 - j0 - k0; i0 += kTileSeg) t.push_back({j0, k0, i0});
+    return t;
+}
+
 struct Chunk {
     int k;   // plane
     int o0;  // first offset within the plane
 };
+
+// node (i,j,k) of a volume container packed into one word for the node lists
+inline unsigned pack_ijk(int i, int j, int k) { return (unsigned)i | ((unsigned)j << 10) | ((unsigned)k << 20); }
+// index of row (j,k) of a closure with M nodes per edge, rows ordered like the slots
+inline int row_id(int M, int j, int k) { return k * M - k * (k - 1) / 2 + j; }
 
 struct TopoLevel {
     int l = 0, m = 0, M = 0, N = 0;
@@ -59,6 +77,12 @@ struct TopoLevel {
     std::vector<int> nb15;           // [15][n_ifc]: same-level slots of centre + 14 Freudenthal nbrs
     // ghost refresh of one tetrahedron: pairs (ghost slot, master slot), per tet CSR
     std::vector<int> tg_ptr, tg_dst, tg_src;
+    // interior nodes of a volume container (the same for every tetrahedron), in
+    // slot order: all, red (even i+k), black
+    std::vector<unsigned> ilist, rlist, blist;
+    // per row (j,k): rowA = (slot of (0,j,k), row length, offset to (i,j-1,k+1),
+    // offset to (i,j+1,k-1)); rowB = (offset to (i,j,k+1), offset to (i,j,k-1), 0, 0)
+    std::vector<std::array<int, 4>> rowA, rowB;
 };
 
 // coarsest-level direct data (Jacobi-PCG in one workgroup)

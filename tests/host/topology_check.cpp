@@ -47,7 +47,55 @@ static void grid_pos(const Topology &tp, int t, int m, int i, int j, int k, int 
     X[tp.perm[t][1]] += j;
 }
 
+// replica of k_fused_sweep's index logic: every interior node written once,
+// every LDS read backed by a phase-1 store of an existing node
+static void check_fused(int m) {
+    const int M = m + 1, FE = kTileRows + 2;
+    std::vector<int> written((size_t)tetnum_d(M), 0);
+    for (const auto &tl : fused_tile_list(m)) {
+        const int j0 = tl[0], k0 = tl[1], i0 = tl[2];
+        std::vector<char> have(FE * FE * 33, 0);
+        for (int er = 0; er < FE * FE; er++)
+            for (int t = 0; t < 32; t++) {
+                const int j = j0 - 1 + er % FE, k = k0 - 1 + er / FE;
+                const int prow = (k + i0 - 1) & 1, l = 2 * t + prow, i = i0 - 1 + l;
+                if (l > 63 || j < 0 || k < 0 || i < 0 || i + j + k > m) continue;
+                CHECK(((i + k) & 1) == 0, "phase-1 node is red");
+                CHECK(cidx_d(M, i, j, k) >= 0 && cidx_d(M, i, j, k) < tetnum_d(M), "phase-1 index");
+                have[er * 33 + t] = 1;
+            }
+        for (int tr = 0; tr < kTileRows * kTileRows; tr++) {
+            const int jj = tr % kTileRows, kk = tr / kTileRows, j = j0 + jj, k = k0 + kk;
+            if (j + k > m - 2) continue;
+            const int er = (jj + 1) + FE * (kk + 1), prow = (k + i0 - 1) & 1;
+            for (int l = 1; l <= kTileSeg; l++) {
+                const int i = i0 - 1 + l;
+                if (i + j + k > m - 1) continue;
+                CHECK(i >= 1 && j >= 1 && k >= 1, "phase-2 node interior");
+                written[cidx_d(M, i, j, k)]++;
+                if (((l + prow) & 1) == 0) {
+                    CHECK(have[er * 33 + (l >> 1)], "red value present");
+                } else {
+                    const int reads[6][2] = {{er, (l + 1) >> 1}, {er, (l - 1) >> 1}, {er + 1, (l - 1) >> 1},
+                                             {er - 1, (l + 1) >> 1}, {er - 1 + FE, l >> 1}, {er + 1 - FE, l >> 1}};
+                    for (auto &rd : reads) {
+                        CHECK(rd[0] >= 0 && rd[0] < FE * FE && rd[1] >= 0 && rd[1] < 32, "LDS index in range");
+                        CHECK(have[rd[0] * 33 + rd[1]], "black neighbour read a stored red value m=%d", m);
+                    }
+                }
+            }
+        }
+    }
+    for (int k = 0; k <= m; k++)
+        for (int j = 0; j <= m - k; j++)
+            for (int i = 0; i <= m - k - j; i++) {
+                bool interior = i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1;
+                CHECK(written[cidx_d(M, i, j, k)] == (interior ? 1 : 0), "fused coverage m=%d (%d,%d,%d)", m, i, j, k);
+            }
+}
+
 int main(int argc, char **argv) {
+    for (int lv = 2; lv <= 9; lv++) check_fused(1 << lv);
     int n_sub = argc > 1 ? std::atoi(argv[1]) : 2;
     int L = argc > 2 ? std::atoi(argv[2]) : 5;
     // decode of every plane offset for the largest supported plane size
@@ -108,6 +156,23 @@ int main(int argc, char **argv) {
                 if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= M - 2) nint++;
             }
         CHECK(nint == (long long)(m - 1) * (m - 2) * (m - 3) / 6, "interior chunks cover the interior l=%d", l);
+        // node lists and row tables used by the list-mode kernels
+        CHECK(T.ilist.size() == T.rlist.size() + T.blist.size(), "colour lists partition the interior");
+        CHECK((long long)T.ilist.size() == (long long)(m - 1) * (m - 2) * (m - 3) / 6, "interior list size");
+        for (unsigned wv : T.ilist) {
+            const int i = wv & 1023, j = (wv >> 10) & 1023, k = (int)(wv >> 20);
+            const auto &ra = T.rowA[row_id(M, j, k)];
+            const auto &rb = T.rowB[row_id(M, j, k)];
+            const int c0 = ra[0] + i, rj = ra[1];
+            CHECK(c0 == closure_index(M, i, j, k), "rowA slot");
+            const int offs[14] = {c0 + 1, c0 - 1, c0 + rj - 1, c0 - rj, c0 + ra[2], c0 + ra[3], c0 + rj,
+                                  c0 - (rj + 1), c0 + rb[0] - 1, c0 + rb[1] + 1, c0 + ra[2] + 1, c0 + ra[3] - 1,
+                                  c0 + rb[0], c0 + rb[1]};
+            for (int e2 = 0; e2 < 14; e2++)
+                CHECK(offs[e2] == cidx_d(M, i + kD14[e2][0], j + kD14[e2][1], k + kD14[e2][2]), "row offsets dir %d", e2);
+        }
+        for (unsigned wv : T.rlist) CHECK((((wv & 1023) + (wv >> 20)) & 1) == 0, "red list colour");
+        for (unsigned wv : T.blist) CHECK((((wv & 1023) + (wv >> 20)) & 1) == 1, "black list colour");
         // volume neighbour arithmetic vs topology lookup, every tet, every interior node
         for (int t = 0; t < tp.n_tets; t++) {
             const long long base = (long long)t * T.C_pad;
