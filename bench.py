@@ -127,7 +127,7 @@ def main():
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
     ctx.autotune(None)
     tuning = ctx.tuning_info()
-    print(f"[bench] tuning (level: block size, xcd order, fused) {tuning}", file=sys.stderr, flush=True)
+    print(f"[bench] tuning (level: block size, xcd order, nodes per thread) {tuning}", file=sys.stderr, flush=True)
     if args.graph:
         ctx.set_graph(True)
     # fault-free cycle count for the cycle advantage, eq. (3)
@@ -160,8 +160,7 @@ def main():
         achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
         roofline = {
             "bound": "hbm",
-            "kernel": ("k_fused_sweep<double> (finest-level fused red-black sweep, FP64, k=1)" if tuning[level][2]
-                       else "k_colour<double> (finest-level volume colour pass, FP64, k=1)"),
+            "kernel": "k_colour<double> (finest-level colour pass, FP64, k=1)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -234,8 +233,8 @@ def main():
             "smoother": "red-black SOR omega=1.25, V(2,1), coarse level 2 Jacobi-PCG",
             "fault_tet": t_fault,
             "graph": bool(args.graph),
-            "tuning": {str(k): {"block": v[0] % 1000, "nodes_per_thread": v[0] // 1000, "xcd_order": v[1],
-                                "fused": v[2]} for k, v in tuning.items()},
+            "tuning": {str(k): {"block": v[0], "xcd_order": v[1], "nodes_per_thread": v[2]}
+                       for k, v in tuning.items()},
         },
         "time_to_1e8_s": round(ms_per_step / 1e3, 5),
         "cycles_per_job": k_faulty,

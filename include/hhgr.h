@@ -132,13 +132,14 @@ int hhgr_solve(hhgr_ctx *ctx, double rel_tol, int max_cycles, hhgr_report *repor
  * Only between cycles.  EINVAL for a bad tet id. */
 int hhgr_inject_fault(hhgr_ctx *ctx, int tet);
 
-/* Local recovery (Sec. 4; Alg. 1, lines 4-5 and a)): restores the tetrahedron's
+/* Local recovery (Sec. 4; Alg. 1 a)): restores the tetrahedron's
  * ghost copies from the surviving interface containers (eq. (4), row 4), sets
  * its interior to zero and runs n_cycles multigrid V-cycles restricted to the
  * tetrahedron's interior on every level for A_FF u_F = f_F - A_FG u_G (a
  * Dirichlet problem; coarsest level: one unknown, solved exactly).
  * local_rel_res_out (optional) receives the local residual relative to the
- * local right-hand side.  ESTATE without a right-hand side. */
+ * local right-hand side.  ESTATE without a right-hand side or with
+ * coarse_level != 2. */
 int hhgr_recover_local(hhgr_ctx *ctx, int tet, int n_cycles, double *local_rel_res_out);
 
 /* Dirichlet-Dirichlet recovery (Alg. 1): for the listed faulty tetrahedra,
@@ -146,7 +147,8 @@ int hhgr_recover_local(hhgr_ctx *ctx, int tet, int n_cycles, double *local_rel_r
  * concurrently (two streams) n_intact V-cycles on the intact part with the
  * closures of the faulty tetrahedra frozen as Dirichlet data and n_local
  * local V-cycles on each faulty tetrahedron.  Returns after both finish.
- * n_tets <= max_faults.  ESTATE without a right-hand side. */
+ * n_tets <= max_faults.  ESTATE without a right-hand side or with
+ * coarse_level != 2. */
 int hhgr_recover_dd(hhgr_ctx *ctx, const int *tets, int n_tets, int n_intact, int n_local);
 
 /* Adjoint gradients for J = 1/2 ||u - u_obs||^2 with A(k) u = M f: given
@@ -174,27 +176,23 @@ void hhgr_batch_destroy(hhgr_batch *batch);
  * V-cycle instead of launching kernel by kernel (same results). */
 int hhgr_set_graph(hhgr_ctx *ctx, int use_graph);
 
-/* Smoother implementation (same arithmetic, same results up to summation
- * order): 0 = automatic (fused sweeps on levels with at least 32 segments per
- * macro edge, or the autotuner's choice), 1 = two colour passes per sweep on
- * every level, 2 = fused sweeps on every level above the coarsest.  A fused
- * sweep updates both colours of the volume interiors in one launch
- * (out-of-place between two buffers), between the interface red and black
- * updates.  EINVAL for another mode. */
-int hhgr_set_smoother(hhgr_ctx *ctx, int mode);
-
 /* Autotuner: times the candidate workgroup sizes, nodes per thread and block
- * orders of the structured volume kernels on every level, then fused sweeps
- * against colour passes, and keeps the fastest per (level, precision,
- * coefficient mode).  cache_path (optional) is a text file read before and written
+ * orders of the volume colour pass on every level and keeps the fastest per
+ * (level, precision, coefficient mode) for all volume kernels of that level.  cache_path (optional) is a text file read before and written
  * after tuning, keyed by device name.  Enqueues work and synchronises. */
 int hhgr_autotune(hhgr_ctx *ctx, const char *cache_path);
 
-/* The tuning choices in use on `level`: block_size = workgroup size of the
- * colour passes + 1000 x nodes per thread (1 or 4), XCD-contiguous block
- * order (1) or hardware order (0), fused sweeps (1) or colour passes (0).
- * EINVAL for a level outside coarse_level+1..level. */
-int hhgr_tuning_info(const hhgr_ctx *ctx, int level, int *block_size, int *xcd_order, int *fused);
+/* The tuning choices in use on `level` (any output may be NULL): workgroup
+ * size of the volume kernels, XCD-contiguous block order (1) or hardware
+ * order (0), nodes per thread (1 or 4).  EINVAL for a level outside
+ * coarse_level+1..level. */
+int hhgr_tuning_info(const hhgr_ctx *ctx, int level, int *block_size, int *xcd_order, int *nodes_per_thread);
+
+/* Set the tuning choices of one level (level = 0: every level above the
+ * coarsest) instead of the autotuner's: block_size 128, 256 or 512,
+ * xcd_order 0 or 1, nodes_per_thread 1 or 4.  Results do not depend on them.
+ * EINVAL for other values. */
+int hhgr_set_tuning(hhgr_ctx *ctx, int level, int block_size, int xcd_order, int nodes_per_thread);
 
 /* Kernel timing for roofline reports: when enabled, every launch of the
  * finest-level volume smoother kernel is bracketed by HIP events on the

@@ -63,22 +63,21 @@ struct LevelDev {
     double h = 0;
     long long C = 0, C_pad = 0, ifc_base = 0, n_slots = 0;
     int n_ifc = 0, n_ifc_red = 0;
-    int2 *ch_int[3] = {}, *ch_full[3] = {};
-    int n_int[3] = {}, n_full[3] = {};
     int bs_sel = 1;  // colour pass
     int remap = 1;   // XCD-contiguous block order (autotuned)
     int cpb = 1;     // nodes per thread of the list-mode kernels (autotuned)
     int *nbr = nullptr, *gptr = nullptr, *gidx = nullptr, *rst = nullptr, *prl = nullptr, *nb15 = nullptr;
     int *ifc_dof = nullptr, *ifc_xyz = nullptr, *tg_dst = nullptr, *tg_src = nullptr;
     std::vector<int> tg_ptr;
-    double *u = nullptr, *b = nullptr, *r = nullptr, *u2 = nullptr;
-    float *u32 = nullptr, *b32 = nullptr, *r32 = nullptr, *u2_32 = nullptr;
-    int4 *tiles = nullptr;
-    int ntiles = 0;
-    unsigned *ilist = nullptr, *rlist = nullptr, *blist = nullptr;  // interior nodes: all, red, black
-    int nilist = 0, nrlist = 0, nblist = 0;
-    int4 *rowA = nullptr, *rowB = nullptr;                         // row offset tables
-    bool fused = false;  // fused sweeps on this level (autotuned)
+    double *u = nullptr, *b = nullptr, *r = nullptr;
+    float *u32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+    // node lists: interior (all, red, black), every closure node
+    unsigned *ilist = nullptr, *rlist = nullptr, *blist = nullptr, *flist = nullptr;
+    int nilist = 0, nrlist = 0, nblist = 0, nflist = 0;
+    int2 *rowC = nullptr;  // row table of the colour-split closure layout
+    int4 *rowN = nullptr;  // neighbour bases per (colour, row)
+    int nrows = 0;
+    int4 lc_sl{0, 0, 0, 0};  // slots of (1,1,1) and its -a, -b, -c neighbours (local coarsest level)
     double *w[3] = {}, *wi = nullptr;
     float *w32[3] = {}, *wi32 = nullptr;
     double *kc = nullptr;
@@ -91,7 +90,6 @@ struct LevelDev {
 template <typename T>
 struct LevView {
     T *u = nullptr, *b = nullptr, *r = nullptr;
-    T *u2 = nullptr;     // second buffer of the volume interiors (fused sweeps), or nullptr
     Weights<T> w;
     const VolDesc *vd = nullptr;
     int nvol = 0;
@@ -168,15 +166,6 @@ struct hhgr_batch {
 namespace hhgr {
 namespace {
 
-// tiles of the fused sweep over the interior rows (j,k) of a tetrahedron with
-// m segments per edge: 8x8 blocks of rows, 62-node segments along i
-static_assert(kTileRows == kFusedTile && kTileSeg == kFusedSeg, "tile shape of host tables and kernel");
-std::vector<int4> fused_tiles(int m) {
-    std::vector<int4> t;
-    for (const auto &a : fused_tile_list(m)) t.push_back(make_int4(a[0], a[1], a[2], 0));
-    return t;
-}
-
 // ----------------------------------------------------------------------------
 // layout of the workspace (sizing and carving share this code)
 // ----------------------------------------------------------------------------
@@ -199,23 +188,12 @@ void carve(hhgr_ctx &c, Carver &cv) {
         D.n_slots = T.n_slots;
         D.n_ifc = T.n_ifc;
         D.n_ifc_red = T.n_ifc_red;
-        for (int q = 0; q < 3; q++) {
-            // chunk tables per candidate workgroup size, rebuilt from the plane sizes
-            int nint = 0, nfull = 0;
-            for (int k = 0; k <= T.m; k++) {
-                long long s = T.M - k, P = s * (s + 1) / 2;
-                nfull += (int)((P + kBS[q] - 1) / kBS[q]);
-                if (k >= 1 && k <= T.m - 3) {
-                    long long lo = s, hi = row_start((int)s, T.m - 1 - k);
-                    nint += (int)((hi - lo + kBS[q] - 1) / kBS[q]);
-                }
-            }
-            D.n_int[q] = nint;
-            D.n_full[q] = nfull;
-            D.ch_int[q] = cv.take<int2>(nint);
-            D.ch_full[q] = cv.take<int2>(nfull);
-            int nib = ((T.n_ifc + kBS[q] - 1) / kBS[q] + 7) & ~7;
-            max_blocks = std::max(max_blocks, nib + nfull * c.n_tets);
+        {
+            // most blocks of a launch with per-block partial sums: smallest
+            // workgroup, one node per thread, the longest node list
+            const int nib = ((T.n_ifc + kBS[0] - 1) / kBS[0] + 7) & ~7;
+            const long long nb = nib + (long long)((T.flist.size() + kBS[0] - 1) / kBS[0]) * c.n_tets;
+            max_blocks = (int)std::max<long long>(max_blocks, nb);
         }
         D.nbr = cv.take<int>(6 * (size_t)T.n_ifc);
         D.gptr = cv.take<int>(T.n_ifc + 1);
@@ -231,24 +209,27 @@ void carve(hhgr_ctx &c, Carver &cv) {
         D.u = cv.take<double>(T.n_slots);
         D.b = cv.take<double>(T.n_slots);
         D.r = cv.take<double>(T.n_slots);
-        D.u2 = cv.take<double>(T.ifc_base);
         if (c.mixed) {
             D.u32 = cv.take<float>(T.n_slots);
             D.b32 = cv.take<float>(T.n_slots);
             D.r32 = cv.take<float>(T.n_slots);
-            D.u2_32 = cv.take<float>(T.ifc_base);
         }
-        D.ntiles = (int)fused_tiles(T.m).size();
-        D.tiles = cv.take<int4>(D.ntiles);
         D.nilist = (int)T.ilist.size();
         D.nrlist = (int)T.rlist.size();
         D.nblist = (int)T.blist.size();
+        D.nflist = (int)T.flist.size();
         D.ilist = cv.take<unsigned>(D.nilist);
         D.rlist = cv.take<unsigned>(D.nrlist);
         D.blist = cv.take<unsigned>(D.nblist);
-        D.rowA = cv.take<int4>(T.rowA.size());
-        D.rowB = cv.take<int4>(T.rowB.size());
-        D.fused = T.m >= 32;
+        D.flist = cv.take<unsigned>(D.nflist);
+        D.nrows = (int)T.rowC.size();
+        D.rowC = cv.take<int2>(T.rowC.size());
+        D.rowN = cv.take<int4>(2 * T.rowN.size());
+        if (l == c.Lc) {
+            const ClosureLayout &ly = T.lay;
+            D.lc_sl = make_int4((int)ly.index(1, 1, 1), (int)ly.index(0, 1, 1), (int)ly.index(2, 0, 1),
+                                (int)ly.index(1, 2, 0));
+        }
         if (c.vk) {
             for (int s = 0; s < 3; s++) D.w[s] = cv.take<double>(T.n_slots);
             D.wi = cv.take<double>(6 * (size_t)T.n_ifc);
@@ -308,8 +289,8 @@ std::string check_desc(const hhgr_desc *d) {
 // ----------------------------------------------------------------------------
 // launch geometry
 // ----------------------------------------------------------------------------
-// full = true: every slot of the closures (chunk mode); otherwise the interior
-// nodes (list mode), or only one colour of them with colour = 0 (red) / 1 (black)
+// full = true: every node of the closures; otherwise the interior nodes, or
+// only one colour of them with colour = 0 (red) / 1 (black)
 VolGeom vgeom(const LevelDev &D, const VolDesc *vd, int nvol, bool full, int bsq = -1, int colour = -1) {
     const int q = bsq < 0 ? D.bs_sel : bsq;
     VolGeom g;
@@ -317,13 +298,14 @@ VolGeom vgeom(const LevelDev &D, const VolDesc *vd, int nvol, bool full, int bsq
     g.nvol = nvol;
     g.M = D.M;
     g.bs = kBS[q];
-    g.rowA = D.rowA;
-    g.rowB = D.rowB;
+    g.rowC = D.rowC;
+    g.rowN = D.rowN;
+    g.nrows = D.nrows;
     g.remap = D.remap;
     g.cpb = D.cpb;
     if (full) {
-        g.chunks = D.ch_full[q];
-        g.nchunks = D.n_full[q];
+        g.list = D.flist;
+        g.nlist = D.nflist;
     } else {
         g.list = colour == 0 ? D.rlist : colour == 1 ? D.blist : D.ilist;
         g.nlist = colour == 0 ? D.nrlist : colour == 1 ? D.nblist : D.nilist;
@@ -371,11 +353,11 @@ template <typename T>
 T *lvec(LevelDev &D, int which);
 template <>
 double *lvec<double>(LevelDev &D, int which) {
-    return which == 0 ? D.u : which == 1 ? D.b : which == 2 ? D.r : D.u2;
+    return which == 0 ? D.u : which == 1 ? D.b : D.r;
 }
 template <>
 float *lvec<float>(LevelDev &D, int which) {
-    return which == 0 ? D.u32 : which == 1 ? D.b32 : which == 2 ? D.r32 : D.u2_32;
+    return which == 0 ? D.u32 : which == 1 ? D.b32 : D.r32;
 }
 
 // global (all tetrahedra) or masked (intact tetrahedra, frozen interface) view
@@ -395,7 +377,6 @@ HView<T> global_view(hhgr_ctx &c, bool masked, int stream_idx) {
         v.u = lvec<T>(D, 0);
         v.b = lvec<T>(D, 1);
         v.r = lvec<T>(D, 2);
-        v.u2 = lvec<T>(D, 3);
         v.w = weights<T>(D);
         v.vd = masked ? D.vd_masked : D.vd_all;
         v.nvol = masked ? D.n_masked : c.n_tets;
@@ -452,7 +433,7 @@ void timed_end(hhgr_ctx &c, hipStream_t s) {
     }
 }
 
-// one red-black sweep in place on the primary buffer: two colour passes
+// one red-black sweep in place: two colour passes
 template <typename T>
 void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const LevelDev &D = c.lev[l];
@@ -462,64 +443,16 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
         const IfcGeom ig = v.ifc ? igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc,
                                          v.frozen, true)
                                  : ig_none();
-        const bool timed = c.timing && V.timed && l == c.L && !D.fused;
+        const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
-        launch_colour<T>(s, vg, ig, v.u, v.u, v.b, v.w, c.vk, D.h, c.d.omega, colour, zero, zero && colour == 0);
+        launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero, zero && colour == 0);
         if (timed) timed_end(c, s);
     }
 }
 
-// one fused sweep: interface red nodes, volume interiors uin -> uout (both
-// colours), interface black nodes.  Interface masters and ghost copies stay in
-// the primary buffer v.u.
-template <typename T>
-void fused_sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, const T *uin, T *uout, hipStream_t s) {
-    const LevelDev &D = c.lev[l];
-    const LevView<T> &v = V.lv[l];
-    const VolGeom none = vgeom(D, v.vd, 0, false);
-    if (v.ifc)
-        launch_colour<T>(s, none, igeom(D, 0, D.n_ifc_red, v.frozen, true), v.u, uin, v.b, v.w, c.vk, D.h, c.d.omega,
-                         0, zero, zero);
-    FusedGeom fg;
-    fg.vd = v.vd;
-    fg.rowA = D.rowA;
-    fg.remap = D.remap;
-    fg.tiles = D.tiles;
-    fg.ntiles = D.ntiles;
-    fg.nvol = v.nvol;
-    fg.M = D.M;
-    const bool timed = c.timing && V.timed && l == c.L;
-    if (timed) timed_begin(c, s);
-    launch_fused_sweep<T>(s, fg, uin, uout, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero);
-    if (timed) timed_end(c, s);
-    if (v.ifc)
-        launch_colour<T>(s, none, igeom(D, D.n_ifc_red, D.n_ifc, v.frozen, true), v.u, uout, v.b, v.w, c.vk, D.h,
-                         c.d.omega, 1, zero, false);
-}
-
-template <typename T>
-bool use_fused(const hhgr_ctx &c, const HView<T> &V, int l) {
-    return c.lev[l].fused && V.lv[l].u2 != nullptr && !V.local;
-}
-
-// nsweeps sweeps starting (and ending) in the primary buffer; pairs of fused
-// sweeps go primary -> second -> primary, an unpaired sweep is a plain one
 template <typename T>
 void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s) {
-    const LevView<T> &v = V.lv[l];
-    const bool fz = use_fused(c, V, l);
-    int k = 0;
-    while (k < nsweeps) {
-        const bool z = zero && k == 0;
-        if (fz && nsweeps - k >= 2) {
-            fused_sweep(c, V, l, z, v.u, v.u2, s);
-            fused_sweep(c, V, l, false, v.u2, v.u, s);
-            k += 2;
-        } else {
-            sweep(c, V, l, z, s);
-            k += 1;
-        }
-    }
+    for (int k = 0; k < nsweeps; k++) sweep(c, V, l, zero && k == 0, s);
 }
 
 template <typename T>
@@ -527,7 +460,7 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     const LevelDev &D = c.lev[c.Lc];
     const LevView<T> &v = V.lv[c.Lc];
     if (V.local) {
-        launch_local_coarse<T>(s, v.vd, v.nvol, D.M, v.b, v.u, v.w, c.vk, D.h);
+        launch_local_coarse<T>(s, v.vd, v.nvol, D.lc_sl, v.b, v.u, v.w, c.vk, D.h);
     } else {
         launch_coarse_pcg<T>(s, c.cn, c.cslot, c.ccol, c.cval, V.cfrozen, v.b, v.u, c.cptr, c.cidx, kCoarseRtol,
                              kCoarseMaxit, c.citers);
@@ -551,19 +484,11 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
-    launch_restrict<T>(s, vgc, v.vd, D.rowA, D.rowB, igc, Dc.rst, v.r, vc.b);
+    launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
     const IfcGeom igp = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, true) : ig_none();
-    if (use_fused(c, V, l) && (c.d.nu_post & 1)) {
-        // odd number of post-sweeps: interpolate into the second buffer and
-        // let the first fused post-sweep bring the interiors back
-        launch_prolong<T>(s, vg, vc.vd, Dc.rowA, Dc.M, igp, D.prl, vc.u, v.u, v.u2);
-        fused_sweep(c, V, l, false, v.u2, v.u, s);
-        smooth(c, V, l, c.d.nu_post - 1, false, s);
-    } else {
-        launch_prolong<T>(s, vg, vc.vd, Dc.rowA, Dc.M, igp, D.prl, vc.u, v.u, v.u);
-        smooth(c, V, l, c.d.nu_post, false, s);
-    }
+    launch_prolong<T>(s, vg, vc.vd, Dc.rowC, Dc.M, igp, D.prl, vc.u, v.u);
+    smooth(c, V, l, c.d.nu_post, false, s);
 }
 
 // ||b - A u||^2 (or with TO output: r = b - A u written as TO) on level L of a view
@@ -590,8 +515,7 @@ void step_fp64(hhgr_ctx &c, const HView<double> &V, hipStream_t s, int slot) {
 void step_mixed(hhgr_ctx &c, const HView<double> &V64, const HView<float> &V32, hipStream_t s, int slot) {
     vcycle<float>(c, V32, c.L, true, s);
     LevelDev &D = c.lev[c.L];
-    const VolGeom vf = vgeom(D, V64.lv[c.L].vd, V64.lv[c.L].nvol, true);
-    launch_update_add(s, vf, igeom(D, 0, D.n_ifc, nullptr, false), D.u, D.u32);
+    launch_update_add(s, V64.lv[c.L].vd, V64.lv[c.L].nvol, D.C_pad, igeom(D, 0, D.n_ifc, nullptr, false), D.u, D.u32);
     finest_residual<float>(c, V64, D.b32, s, c.dnorm + slot);
 }
 
@@ -667,7 +591,7 @@ void set_loc(hhgr_ctx &c, const std::vector<int> &tets) {
 // after zeroing its closure (interior re-initialised with zero)
 void restore_tet(hhgr_ctx &c, int t, hipStream_t s) {
     LevelDev &D = c.lev[c.L];
-    launch_fill<double>(s, D.u + (long long)t * D.C_pad, D.C, 0.0);
+    launch_fill<double>(s, D.u + (long long)t * D.C_pad, D.C_pad, 0.0);
     const int a = D.tg_ptr[t], b = D.tg_ptr[t + 1];
     launch_ghost_refresh<double>(s, D.tg_dst + a, D.tg_src + a, b - a, D.u);
 }
@@ -714,7 +638,7 @@ int hhgr_workspace_bytes(const hhgr_desc *desc, size_t *bytes) {
     c.n_dofs = (N - 1) * (N - 1) * (N - 1);
     c.vk = desc->variable_coeff != 0;
     c.mixed = desc->precision == HHGR_MIXED;
-    std::string te = c.topo.build(desc->n_sub, c.L, c.Lc, 256);
+    std::string te = c.topo.build(desc->n_sub, c.L, c.Lc);
     if (!te.empty()) return fail(HHGR_EINVAL, te);
     Carver cv;
     carve(c, cv);
@@ -740,7 +664,7 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     c->vk = desc->variable_coeff != 0;
     c->mixed = desc->precision == HHGR_MIXED;
     c->stream = (hipStream_t)hip_stream;
-    std::string te = c->topo.build(desc->n_sub, c->L, c->Lc, 256);
+    std::string te = c->topo.build(desc->n_sub, c->L, c->Lc);
     if (!te.empty()) {
         delete c;
         return fail(HHGR_EINVAL, te);
@@ -771,28 +695,12 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
 
     const Topology &tp = c->topo;
     // host-side staging of all tables; kept alive until the final synchronise
-    std::vector<std::vector<int2>> chunk_store;
     std::vector<std::vector<VolDesc>> vd_store;
+    std::vector<std::vector<int4>> rown_store;
     int rc = HHGR_OK;
     for (int l = c->Lc; l <= c->L && rc == HHGR_OK; l++) {
         const TopoLevel &T = tp.lev[l];
         LevelDev &D = c->lev[l];
-        for (int q = 0; q < 3; q++) {
-            std::vector<int2> ci, cf;
-            for (int k = 0; k <= T.m; k++) {
-                int s = T.M - k;
-                long long P = (long long)s * (s + 1) / 2;
-                for (long long o = 0; o < P; o += kBS[q]) cf.push_back(make_int2(k, (int)o));
-                if (k >= 1 && k <= T.m - 3) {
-                    long long lo = s, hi = row_start(s, T.m - 1 - k);
-                    for (long long o = lo; o < hi; o += kBS[q]) ci.push_back(make_int2(k, (int)o));
-                }
-            }
-            chunk_store.push_back(ci);
-            rc = rc ? rc : upload(*c, D.ch_int[q], chunk_store.back().data(), ci.size() * sizeof(int2));
-            chunk_store.push_back(cf);
-            rc = rc ? rc : upload(*c, D.ch_full[q], chunk_store.back().data(), cf.size() * sizeof(int2));
-        }
         rc = rc ? rc : upload(*c, D.nbr, T.nbr.data(), T.nbr.size() * sizeof(int));
         rc = rc ? rc : upload(*c, D.gptr, T.gptr.data(), T.gptr.size() * sizeof(int));
         rc = rc ? rc : upload(*c, D.gidx, T.gidx.data(), T.gidx.size() * sizeof(int));
@@ -807,20 +715,21 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
         for (int t = 0; t < c->n_tets; t++) vd[t] = VolDesc{(long long)t * T.C_pad, (long long)t * T.C_pad, t, 0};
         vd_store.push_back(vd);
         rc = rc ? rc : upload(*c, D.vd_all, vd_store.back().data(), vd.size() * sizeof(VolDesc));
-        {
-            std::vector<int4> ft = fused_tiles(T.m);
-            std::vector<int2> tmp(ft.size() * 2);
-            std::memcpy(tmp.data(), ft.data(), ft.size() * sizeof(int4));
-            chunk_store.push_back(tmp);
-            rc = rc ? rc : upload(*c, D.tiles, chunk_store.back().data(), ft.size() * sizeof(int4));
-        }
         rc = rc ? rc : upload(*c, D.ilist, T.ilist.data(), T.ilist.size() * sizeof(unsigned));
         rc = rc ? rc : upload(*c, D.rlist, T.rlist.data(), T.rlist.size() * sizeof(unsigned));
         rc = rc ? rc : upload(*c, D.blist, T.blist.data(), T.blist.size() * sizeof(unsigned));
-        rc = rc ? rc : upload(*c, D.rowA, T.rowA.data(), T.rowA.size() * sizeof(int4));
-        rc = rc ? rc : upload(*c, D.rowB, T.rowB.data(), T.rowB.size() * sizeof(int4));
-        launch_fill<double>(c->stream, D.u2, T.ifc_base, 0.0);
-        if (c->mixed) launch_fill<float>(c->stream, D.u2_32, T.ifc_base, 0.0f);
+        rc = rc ? rc : upload(*c, D.flist, T.flist.data(), T.flist.size() * sizeof(unsigned));
+        rc = rc ? rc : upload(*c, D.rowC, T.rowC.data(), T.rowC.size() * sizeof(int2));
+        {
+            std::vector<int4> rn(2 * T.rowN.size());
+            for (size_t q = 0; q < T.rowN.size(); q++) {
+                const auto &e = T.rowN[q];
+                rn[2 * q] = make_int4(e[0], e[1], e[2], e[3]);
+                rn[2 * q + 1] = make_int4(e[4], e[5], e[6], e[7]);
+            }
+            rown_store.push_back(std::move(rn));
+            rc = rc ? rc : upload(*c, D.rowN, rown_store.back().data(), rown_store.back().size() * sizeof(int4));
+        }
         // zero every vector (also the Dirichlet ghosts and the zero slot)
         launch_fill<double>(c->stream, D.u, T.n_slots, 0.0);
         launch_fill<double>(c->stream, D.b, T.n_slots, 0.0);
@@ -852,39 +761,8 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     rc = rc ? rc : upload(*c, c->tetinfo, tinfo.data(), tinfo.size() * sizeof(int));
     const CoarseSystem &cs = tp.coarse;
     std::vector<int> cpos(3 * (size_t)cs.n);
-    {
-        const TopoLevel &T = tp.lev[c->Lc];
-        int nv = 0;
-        for (int q = 0; q < cs.n; q++) {
-            if (cs.is_vol[q]) {
-                nv++;
-            }
-        }
-        (void)nv;
-        // positions: volume unknowns from their slot, interface from the table
-        for (int q = 0; q < cs.n; q++) {
-            std::array<int, 3> X{0, 0, 0};
-            if (!cs.is_vol[q]) {
-                X = T.ifc_X[cs.ifc[q]];
-            } else {
-                const int t = cs.tet[q];
-                const long long loc = cs.slot[q] - (long long)t * T.C_pad;
-                // decode closure index loc
-                int k = 0;
-                while (plane_start(T.M, k + 1) <= loc) k++;
-                long long o = loc - plane_start(T.M, k);
-                int s = T.M - k, j = 0;
-                while (j + 1 < s && row_start(s, j + 1) <= o) j++;
-                int i = (int)(o - row_start(s, j));
-                for (int a = 0; a < 3; a++) X[a] = T.m * tp.V0[t][a] + k;
-                X[tp.perm[t][0]] += i + j;
-                X[tp.perm[t][1]] += j;
-            }
-            cpos[3 * q] = X[0];
-            cpos[3 * q + 1] = X[1];
-            cpos[3 * q + 2] = X[2];
-        }
-    }
+    for (int q = 0; q < cs.n; q++)
+        for (int a = 0; a < 3; a++) cpos[3 * q + a] = cs.pos[q][a];
     c->cval_host = cs.val;
     rc = rc ? rc : upload(*c, c->cslot, cs.slot.data(), cs.slot.size() * sizeof(long long));
     rc = rc ? rc : upload(*c, c->ccol, cs.col.data(), cs.col.size() * sizeof(int));
@@ -1072,7 +950,7 @@ int hhgr_inject_fault(hhgr_ctx *c, int tet) {
     if (!c) return fail(HHGR_EINVAL, "null context");
     if (tet < 0 || tet >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
     LevelDev &D = c->lev[c->L];
-    launch_fill<double>(c->stream, D.u + (long long)tet * D.C_pad, D.C, 0.0);
+    launch_fill<double>(c->stream, D.u + (long long)tet * D.C_pad, D.C_pad, 0.0);
     CHKLAUNCH();
     return HHGR_OK;
 }
@@ -1083,6 +961,7 @@ int hhgr_recover_local(hhgr_ctx *c, int tet, int n_cycles, double *local_rel) {
     if (tet < 0 || tet >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
     if (n_cycles < 0) return fail(HHGR_EINVAL, "negative cycle count");
     if (c->d.max_faults < 1) return fail(HHGR_ESTATE, "context created with max_faults = 0");
+    if (c->Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
     set_loc(*c, {tet});
     restore_tet(*c, tet, c->stream);
     HView<double> V = local_view(*c, 0);
@@ -1104,6 +983,7 @@ int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
     if (rc) return rc;
     if (!tets || n_tets < 1 || n_tets > c->d.max_faults) return fail(HHGR_EINVAL, "need 1..max_faults tets");
     if (n_intact < 0 || n_local < 0) return fail(HHGR_EINVAL, "negative cycle count");
+    if (c->Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
     std::vector<int> ft(tets, tets + n_tets);
     std::vector<char> isf(c->n_tets, 0);
     for (int t : ft) {
@@ -1247,23 +1127,31 @@ int hhgr_set_graph(hhgr_ctx *c, int use_graph) {
     return HHGR_OK;
 }
 
-int hhgr_tuning_info(const hhgr_ctx *c, int level, int *block_size, int *xcd_order, int *fused) {
+int hhgr_tuning_info(const hhgr_ctx *c, int level, int *block_size, int *xcd_order, int *nodes_per_thread) {
     if (!c) return fail(HHGR_EINVAL, "null context");
     if (level <= c->Lc || level > c->L) return fail(HHGR_EINVAL, "level outside coarse_level+1..level");
     const LevelDev &D = c->lev[level];
-    // block size, with the nodes per thread in the thousands digit
-    if (block_size) *block_size = kBS[D.bs_sel] + 1000 * D.cpb;
+    if (block_size) *block_size = kBS[D.bs_sel];
     if (xcd_order) *xcd_order = D.remap;
-    if (fused) *fused = D.fused ? 1 : 0;
+    if (nodes_per_thread) *nodes_per_thread = D.cpb;
     return HHGR_OK;
 }
 
-int hhgr_set_smoother(hhgr_ctx *c, int mode) {
+int hhgr_set_tuning(hhgr_ctx *c, int level, int block_size, int xcd_order, int nodes_per_thread) {
     if (!c) return fail(HHGR_EINVAL, "null context");
-    if (mode < 0 || mode > 2) return fail(HHGR_EINVAL, "smoother mode must be 0, 1 or 2");
-    for (int l = c->Lc; l <= c->L; l++) {
+    if (level != 0 && (level <= c->Lc || level > c->L)) return fail(HHGR_EINVAL, "level outside coarse_level+1..level");
+    int q = -1;
+    for (int k = 0; k < 3; k++)
+        if (kBS[k] == block_size) q = k;
+    if (q < 0) return fail(HHGR_EINVAL, "block_size must be 128, 256 or 512");
+    if (xcd_order != 0 && xcd_order != 1) return fail(HHGR_EINVAL, "xcd_order must be 0 or 1");
+    if (nodes_per_thread != 1 && nodes_per_thread != 4) return fail(HHGR_EINVAL, "nodes_per_thread must be 1 or 4");
+    for (int l = c->Lc + 1; l <= c->L; l++) {
+        if (level != 0 && l != level) continue;
         LevelDev &D = c->lev[l];
-        D.fused = mode == 2 ? D.ntiles > 0 : mode == 1 ? false : D.m >= 32;
+        D.bs_sel = q;
+        D.remap = xcd_order;
+        D.cpb = nodes_per_thread;
     }
     invalidate_graph(*c);
     return HHGR_OK;
@@ -1291,11 +1179,10 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
     }
     if (launches) *launches = n;
     if (mean_ms) *mean_ms = n ? tot / n : 0.0;
-    // fused sweep over the finest volumes: read u and b, write u (3 words per
-    // unknown); a colour pass reads the other colour's u and its own b and old u
-    // and writes its own u (4 words per updated node, 2 per unknown)
+    // a colour pass reads the other colour's u and its own b and old u and
+    // writes its own u: 4 words per updated node, 2 words per unknown
     const double w = c->mixed ? 4.0 : 8.0;
-    if (alg_bytes) *alg_bytes = (c->lev[c->L].fused ? 3.0 : 2.0) * w * (double)c->n_dofs;
+    if (alg_bytes) *alg_bytes = 2.0 * w * (double)c->n_dofs;
     return HHGR_OK;
 }
 
@@ -1322,12 +1209,10 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         std::ostringstream ks;
         ks << devname << ":n" << c->d.n_sub << ":l" << l << ":" << (c->mixed ? "f32" : "f64") << ":vk" << c->vk;
         auto it = cache.find(ks.str());
-        auto itf = cache.find(ks.str() + ":fused");
         auto itr = cache.find(ks.str() + ":remap");
         auto itc = cache.find(ks.str() + ":cpb");
-        if (it != cache.end() && itf != cache.end() && itr != cache.end() && itc != cache.end()) {
+        if (it != cache.end() && itr != cache.end() && itc != cache.end()) {
             D.bs_sel = it->second;
-            D.fused = itf->second != 0;
             D.remap = itr->second;
             D.cpb = itc->second;
             continue;
@@ -1342,11 +1227,11 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
             const IfcGeom ig = igeom(D, 0, D.n_ifc_red, nullptr, false);
             auto run = [&]() {
                 if (c->mixed)
-                    launch_colour<float>(c->stream, vg, ig, D.r32, D.r32, D.b32, weights<float>(D), c->vk, D.h,
-                                         c->d.omega, 0, false, false);
+                    launch_colour<float>(c->stream, vg, ig, D.r32, D.b32, weights<float>(D), c->vk, D.h, c->d.omega,
+                                         false, false);
                 else
-                    launch_colour<double>(c->stream, vg, ig, D.r, D.r, D.b, weights<double>(D), c->vk, D.h,
-                                          c->d.omega, 0, false, false);
+                    launch_colour<double>(c->stream, vg, ig, D.r, D.b, weights<double>(D), c->vk, D.h, c->d.omega,
+                                          false, false);
             };
             run();
             HIPCHK(hipEventRecord(e0, c->stream));
@@ -1369,38 +1254,6 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         cache[ks.str()] = bq;
         cache[ks.str() + ":remap"] = br;
         cache[ks.str() + ":cpb"] = bc;
-        // fused sweep against two plain colour passes, on scratch buffers
-        if (D.m >= 16) {
-            auto time_it = [&](bool fused) -> float {
-                auto once = [&]() {
-                    if (c->mixed) {
-                        HView<float> V = global_view<float>(*c, false, 0);
-                        V.lv[l].u = D.r32;
-                        if (fused) fused_sweep(*c, V, l, false, D.r32, D.u2_32, c->stream);
-                        else sweep(*c, V, l, false, c->stream);
-                    } else {
-                        HView<double> V = global_view<double>(*c, false, 0);
-                        V.lv[l].u = D.r;
-                        if (fused) fused_sweep(*c, V, l, false, D.r, D.u2, c->stream);
-                        else sweep(*c, V, l, false, c->stream);
-                    }
-                };
-                once();
-                hipEventRecord(e0, c->stream);
-                const int reps = l >= 6 ? 5 : 20;
-                for (int r = 0; r < reps; r++) once();
-                hipEventRecord(e1, c->stream);
-                hipEventSynchronize(e1);
-                float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
-                return ms;
-            };
-            const float tp = time_it(false), tf = time_it(true);
-            D.fused = tf < tp;
-        } else {
-            D.fused = false;
-        }
-        cache[ks.str() + ":fused"] = D.fused ? 1 : 0;
         // scratch vector used for timing goes back to zero
         launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
         if (c->mixed) launch_fill<float>(c->stream, D.r32, D.n_slots, 0.0f);
@@ -1452,15 +1305,15 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
         for (int colour = 0; colour < 2; colour++) {
             if (!((op == 3) || (op == 1 && colour == 0) || (op == 2 && colour == 1))) continue;
             const IfcGeom ig = igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc, nullptr, true);
-            launch_colour<double>(s, vgeom(D, D.vd_all, c->n_tets, false, -1, colour), ig, D.u, D.u, D.b, w, c->vk, D.h,
-                                  c->d.omega, colour, false, false);
+            launch_colour<double>(s, vgeom(D, D.vd_all, c->n_tets, false, -1, colour), ig, D.u, D.b, w, c->vk, D.h,
+                                  c->d.omega, false, false);
         }
         to_user(D.u, out, D);
         break;
     case 4: {
         LevelDev &Dc = c->lev[l - 1];
         to_slots(in0, D.r, D);
-        launch_restrict<double>(s, vgeom(Dc, Dc.vd_all, c->n_tets, false), D.vd_all, D.rowA, D.rowB,
+        launch_restrict<double>(s, vgeom(Dc, Dc.vd_all, c->n_tets, false), D.vd_all, D.rowC,
                                 igeom(Dc, 0, Dc.n_ifc, nullptr, false), Dc.rst, D.r, Dc.b);
         to_user(Dc.b, out, Dc);
         break;
@@ -1469,7 +1322,7 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
         LevelDev &Dc = c->lev[l - 1];
         to_slots(in0, Dc.u, Dc);
         to_slots(in1, D.u, D);
-        launch_prolong<double>(s, vint, Dc.vd_all, Dc.rowA, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true), D.prl, Dc.u, D.u,
+        launch_prolong<double>(s, vint, Dc.vd_all, Dc.rowC, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true), D.prl, Dc.u,
                                D.u);
         to_user(D.u, out, D);
         break;

@@ -1,13 +1,16 @@
 // HIP kernels (gfx950) of the HHG multigrid engine.
 //
-// Volume containers are processed as structured arrays: a workgroup takes a
-// chunk of consecutive slots of one plane of one tetrahedron, decodes (i,j,k)
-// arithmetically and reads its stencil neighbours at closed-form offsets, so
-// the loads of a wavefront are consecutive addresses.  Interface (face, edge,
-// vertex) nodes are few and are handled through precomputed slot tables by
-// the first workgroups of the same launch.  Block ids of the volume part are
-// remapped so that each of the 8 XCDs walks a contiguous run of chunks, which
-// keeps the neighbouring planes of a chunk in that XCD's L2.
+// Volume containers are processed as structured arrays.  A closure stores its
+// red nodes first and its black nodes after them (colour-split layout, plane
+// by plane, row by row), so the nodes of one colour are contiguous: a colour
+// pass streams whole cache lines of its own colour of u and b and of the
+// other colour of u.  A launch walks a packed (i,j,k) node list that is the
+// same for every tetrahedron; per-row tables give the slot of a node and of
+// its neighbours, so consecutive threads touch consecutive slots.  Interface
+// (face, edge, vertex) nodes are few and are handled through precomputed slot
+// tables by the first workgroups of the same launch.  Block ids of the volume
+// part are remapped so that each of the 8 XCDs walks a contiguous run of
+// volumes, which keeps the neighbouring planes of a block in that XCD's L2.
 //
 // Operator (Sec. 2.1, eq. (2)): P1 stiffness on the Kuhn meshes couples each
 // node to its 6 grid-axis neighbours only.  k = 1: diagonal 6h, off-diagonal
@@ -24,20 +27,12 @@ namespace hhgr {
 
 namespace {
 
-__device__ __forceinline__ int tetnum_d(int x) { return x * (x + 1) * (x + 2) / 6; }
-__device__ __forceinline__ int pstart_d(int M, int k) { return tetnum_d(M) - tetnum_d(M - k); }
-__device__ __forceinline__ int rstart_d(int s, int j) { return j * s - ((j * (j - 1)) >> 1); }
-__device__ __forceinline__ int cidx_d(int M, int i, int j, int k) { return pstart_d(M, k) + rstart_d(M - k, j) + i; }
+__device__ __forceinline__ int row_of(int M, int j, int k) { return k * M - ((k * (k - 1)) >> 1) + j; }
 
-// row j of a triangular plane with row-0 length s that holds plane offset o
-__device__ __forceinline__ int decode_row(int s, int o) {
-    const float b = 2.0f * (float)s + 1.0f;
-    const float disc = fmaxf(b * b - 8.0f * (float)o, 0.0f);
-    int j = (int)((b - sqrtf(disc)) * 0.5f);
-    j = max(0, min(j, s - 1));
-    while (j + 1 <= s - 1 && rstart_d(s, j + 1) <= o) ++j;
-    while (j > 0 && rstart_d(s, j) > o) --j;
-    return j;
+// slot (within its closure) of node (i,j,k) from the row table of its level
+__device__ __forceinline__ int lslot(const int2 *__restrict__ rowC, int M, int i, int j, int k) {
+    const int2 r = rowC[row_of(M, j, k)];
+    return (((i + k) & 1) ? r.y : r.x) + (i >> 1);
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin; map so that each XCD
@@ -50,54 +45,9 @@ __device__ __forceinline__ unsigned block_order(unsigned f, unsigned total, int 
     return remap ? xcd_remap(f, total) : f;
 }
 
-// chunks (of one workgroup's width) that every workgroup of the structured
-// volume kernels processes: each thread owns kCPB slots, all loads issued
-// before the first store
-constexpr int kCPB = 4;
-
-struct VNode {
-    int v, i, j, k, s, o, ps;
-};
-
-__device__ __forceinline__ bool vol_node(const VolGeom &g, unsigned lg, VNode &n) {
-    n.v = (int)(lg / (unsigned)g.nchunks);
-    const int c = (int)(lg % (unsigned)g.nchunks);
-    const int2 ch = g.chunks[c];
-    n.k = ch.x;
-    n.s = g.M - n.k;
-    n.o = ch.y + (int)threadIdx.x;
-    if (n.o >= n.s * (n.s + 1) / 2) return false;
-    n.j = decode_row(n.s, n.o);
-    n.i = n.o - rstart_d(n.s, n.j);
-    n.ps = pstart_d(g.M, n.k);
-    return true;
-}
-
-__device__ __forceinline__ bool is_interior(const VNode &n, int M) {
-    return n.i >= 1 && n.j >= 1 && n.k >= 1 && n.i + n.j + n.k <= M - 2;
-}
-
-// closure offsets of the 6 axis neighbours (local directions a, b, c)
-struct Nb6 {
-    int ap, am, bp, bm, cp, cm;
-};
-__device__ __forceinline__ Nb6 nb6(const VNode &n) {
-    const int c0 = n.ps + n.o;
-    const int rj = n.s - n.j;
-    Nb6 r;
-    r.ap = c0 + 1;
-    r.am = c0 - 1;
-    r.bp = c0 + rj - 1;                                                            // (i-1, j+1, k)
-    r.bm = c0 - rj;                                                                // (i+1, j-1, k)
-    r.cp = n.ps + n.s * (n.s + 1) / 2 + rstart_d(n.s - 1, n.j - 1) + n.i;          // (i, j-1, k+1)
-    r.cm = n.ps - (n.s + 1) * (n.s + 2) / 2 + rstart_d(n.s + 1, n.j + 1) + n.i;    // (i, j+1, k-1)
-    return r;
-}
-
-// list mode: thread -> node of the volume container; all index arithmetic
-// comes from the level's row table
+// thread -> node of a volume container
 struct LNode {
-    int v, i, j, k, c0, rj, dcp, dcm;
+    int v, i, j, k, r;
 };
 
 template <int CPB>
@@ -115,23 +65,29 @@ __device__ __forceinline__ bool list_node(const VolGeom &g, unsigned blk, unsign
     n.i = (int)(w & 1023u);
     n.j = (int)((w >> 10) & 1023u);
     n.k = (int)(w >> 20);
-    const int4 ra = g.rowA[n.k * g.M - ((n.k * (n.k - 1)) >> 1) + n.j];
-    n.c0 = ra.x + n.i;
-    n.rj = ra.y;
-    n.dcp = ra.z;
-    n.dcm = ra.w;
+    n.r = row_of(g.M, n.j, n.k);
     return true;
 }
 
-__device__ __forceinline__ Nb6 nb6l(const LNode &n) {
-    Nb6 r;
-    r.ap = n.c0 + 1;
-    r.am = n.c0 - 1;
-    r.bp = n.c0 + n.rj - 1;
-    r.bm = n.c0 - n.rj;
-    r.cp = n.c0 + n.dcp;
-    r.cm = n.c0 + n.dcm;
-    return r;
+// closure slots of an interior node and of its 6 axis neighbours
+// (local directions a, b, c; see topology.hpp for the index offsets)
+struct Nb7 {
+    int c0, ap, am, bp, bm, cp, cm;
+};
+__device__ __forceinline__ Nb7 nb7(const VolGeom &g, const LNode &n) {
+    const int c = (n.i + n.k) & 1;
+    const int4 *e = g.rowN + 2 * ((long long)c * g.nrows + n.r);
+    const int4 A = e[0], B = e[1];
+    const int t = n.i >> 1;
+    Nb7 s;
+    s.c0 = A.x + t;
+    s.ap = A.y + t;
+    s.am = A.y + t - 1;
+    s.bp = A.z + t;
+    s.bm = A.w + t;
+    s.cp = B.x + t;
+    s.cm = B.y + t;
+    return s;
 }
 
 template <typename T>
@@ -183,8 +139,7 @@ inline int ifc_blocks(const IfcGeom &ig, int bs) {
 // ---------------------------------------------------------------------------
 template <typename T, bool VK, bool OWN0, bool NB0, int CPB>
 __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib, T *__restrict__ u,
-                                                const T *__restrict__ uvol, const T *__restrict__ b, Weights<T> w,
-                                                T h, T omega, T om_d) {
+                                                const T *__restrict__ b, Weights<T> w, T h, T omega, T om_d) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
@@ -199,19 +154,13 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
             for (int e = 0; e < 6; e++) {
                 const T we = w.wi[(long long)e * ig.stride + t];
                 diag += we;
-                if (!NB0) {
-                    const int nb = ig.nbr[(long long)e * ig.stride + t];
-                    acc += we * (nb < ig.base ? uvol[nb] : u[nb]);
-                }
+                if (!NB0) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
             }
         } else {
             diag = T(6) * h;
             if (!NB0) {
 #pragma unroll
-                for (int e = 0; e < 6; e++) {
-                    const int nb = ig.nbr[(long long)e * ig.stride + t];
-                    acc += nb < ig.base ? uvol[nb] : u[nb];
-                }
+                for (int e = 0; e < 6; e++) acc += u[ig.nbr[(long long)e * ig.stride + t]];
                 acc *= h;
             }
         }
@@ -237,8 +186,8 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
         if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
         const VolDesc d = vg.vd[n.v];
         const T *uv = u + d.vec;
-        const int c0 = n.c0;
-        const Nb6 nb = nb6l(n);
+        const Nb7 nb = nb7(vg, n);
+        const int c0 = nb.c0;
         const T uo = OWN0 ? T(0) : uv[c0];
         T res;
         if (VK) {
@@ -312,8 +261,8 @@ __global__ void __launch_bounds__(512) k_residual(VolGeom vg, IfcGeom ig, int ni
             if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
             const VolDesc d = vg.vd[n.v];
             const T *uv = u + d.vec;
-            const int c0 = n.c0;
-            const Nb6 nb = nb6l(n);
+            const Nb7 nb = nb7(vg, n);
+            const int c0 = nb.c0;
             const T uo = uv[c0];
             T diag, acc;
             if (VK) {
@@ -347,13 +296,9 @@ __global__ void __launch_bounds__(512) k_residual(VolGeom vg, IfcGeom ig, int ni
 // restriction b_c = P^T r (weights 1 at the coinciding node, 1/2 at the 14
 // Freudenthal neighbours, which are the midpoints of the coarse edges)
 // ---------------------------------------------------------------------------
-__device__ __constant__ int kD14[14][3] = {{1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0}, {0, -1, 1},
-                                           {0, 1, -1}, {0, 1, 0},  {0, -1, 0}, {-1, 0, 1}, {1, 0, -1},
-                                           {1, -1, 1}, {-1, 1, -1}, {0, 0, 1}, {0, 0, -1}};
-
 template <typename T, int CPB>
-__global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__restrict__ vdf, const int4 *__restrict__ fA,
-                                                  const int4 *__restrict__ fB, IfcGeom ig, int nib,
+__global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__restrict__ vdf,
+                                                  const int2 *__restrict__ fC, IfcGeom ig, int nib,
                                                   const int *__restrict__ rst, const T *__restrict__ rf,
                                                   T *__restrict__ bc) {
     const unsigned f = blockIdx.x;
@@ -381,17 +326,27 @@ __global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__r
         LNode n;
         if (!list_node<CPB>(vc, blk, per_vol, q, n)) continue;
         const T *rv = rf + vdf[n.v].vec;
-        // fine node (2i, 2j, 2k) and its 14 Freudenthal neighbours
-        const int J = 2 * n.j, K = 2 * n.k;
-        const int rid = K * Mf - ((K * (K - 1)) >> 1) + J;
-        const int4 ra = fA[rid], rb = fB[rid];
-        const int F = ra.x + 2 * n.i, rj = ra.y;
-        const T s1 = ((rv[F + 1] + rv[F - 1]) + (rv[F + rj - 1] + rv[F - rj])) + (rv[F + ra.z] + rv[F + ra.w]);
-        const T s2 = ((rv[F + rj] + rv[F - rj - 1]) + (rv[F + rb.x - 1] + rv[F + rb.y + 1])) +
-                     (rv[F + ra.z + 1] + rv[F + ra.w - 1]);
-        const T s3 = rv[F + rb.x] + rv[F + rb.y];
-        nv[q] = rv[F] + T(0.5) * ((s1 + s2) + s3);
-        dst[q] = vc.vd[n.v].vec + n.c0;
+        // fine node (I,J,K) = (2i,2j,2k) (red) and its 14 Freudenthal neighbours,
+        // grouped by fine row; a fine node (I',J',K') has colour (I'+K')&1
+        const int I = 2 * n.i, J = 2 * n.j, K = 2 * n.k;
+        const int t0 = I >> 1;  // half index of I (and of I+1)
+        const int2 r0 = fC[row_of(Mf, J, K)];          // (I,J,K) red, (I+-1,J,K) black
+        const int2 rjp = fC[row_of(Mf, J + 1, K)];     // (I-1,J+1,K) black, (I,J+1,K) red
+        const int2 rjm = fC[row_of(Mf, J - 1, K)];     // (I+1,J-1,K) black, (I,J-1,K) red
+        const int2 rcp = fC[row_of(Mf, J - 1, K + 1)]; // (I,J-1,K+1) black, (I+1,J-1,K+1) red
+        const int2 rcm = fC[row_of(Mf, J + 1, K - 1)]; // (I,J+1,K-1) black, (I-1,J+1,K-1) red
+        const int2 rkp = fC[row_of(Mf, J, K + 1)];     // (I-1,J,K+1) red, (I,J,K+1) black
+        const int2 rkm = fC[row_of(Mf, J, K - 1)];     // (I+1,J,K-1) red, (I,J,K-1) black
+        // axis neighbours
+        const T s1 = ((rv[r0.y + t0] + rv[r0.y + t0 - 1]) + (rv[rjp.y + t0 - 1] + rv[rjm.y + t0])) +
+                     (rv[rcp.y + t0] + rv[rcm.y + t0]);
+        // face diagonals (0,+-1,0), (-+1,0,+-1), (+-1,-+1,+-1)
+        const T s2 = ((rv[rjp.x + t0] + rv[rjm.x + t0]) + (rv[rkp.x + t0 - 1] + rv[rkm.x + t0])) +
+                     (rv[rcp.x + t0] + rv[rcm.x + t0 - 1]);
+        // body diagonal (0,0,+-1)
+        const T s3 = rv[rkp.y + t0] + rv[rkm.y + t0];
+        nv[q] = rv[r0.x + t0] + T(0.5) * ((s1 + s2) + s3);
+        dst[q] = vc.vd[n.v].vec + lslot(vc.rowC, vc.M, n.i, n.j, n.k);
         ok[q] = true;
     }
 #pragma unroll
@@ -408,9 +363,9 @@ __device__ __constant__ int kParDir[8][3] = {{0, 0, 0},  {1, 0, 0}, {0, 1, 0},  
                                              {0, 0, 1},  {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
 
 template <typename T, int CPB>
-__global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__restrict__ vdc, const int4 *__restrict__ cA,
+__global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__restrict__ vdc, const int2 *__restrict__ cC,
                                                  int Mc, IfcGeom ig, int nib, const int *__restrict__ prl,
-                                                 const T *__restrict__ ec, T *uf, T *uo) {
+                                                 const T *__restrict__ ec, T *__restrict__ uf) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
@@ -436,179 +391,19 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
         LNode n;
         if (!list_node<CPB>(vf, blk, per_vol, q, n)) continue;
         const T *ev = ec + vdc[n.v].vec;
-        const long long base = vf.vd[n.v].vec;
+        const long long sl = vf.vd[n.v].vec + lslot(vf.rowC, vf.M, n.i, n.j, n.k);
         const int code = (n.i & 1) | ((n.j & 1) << 1) | ((n.k & 1) << 2);
         const int di = kParDir[code][0], dj = kParDir[code][1], dk = kParDir[code][2];
         // coarse end points of the bisected edge (the same node twice for code 0)
-        const int i1 = (n.i - di) >> 1, j1 = (n.j - dj) >> 1, k1 = (n.k - dk) >> 1;
-        const int i2 = (n.i + di) >> 1, j2 = (n.j + dj) >> 1, k2 = (n.k + dk) >> 1;
-        const T e1 = ev[cA[k1 * Mc - ((k1 * (k1 - 1)) >> 1) + j1].x + i1];
-        const T e2 = ev[cA[k2 * Mc - ((k2 * (k2 - 1)) >> 1) + j2].x + i2];
-        nv[q] = uf[base + n.c0] + (code == 0 ? e1 : T(0.5) * (e1 + e2));
-        dst[q] = base + n.c0;
+        const T e1 = ev[lslot(cC, Mc, (n.i - di) >> 1, (n.j - dj) >> 1, (n.k - dk) >> 1)];
+        const T e2 = ev[lslot(cC, Mc, (n.i + di) >> 1, (n.j + dj) >> 1, (n.k + dk) >> 1)];
+        nv[q] = uf[sl] + (code == 0 ? e1 : T(0.5) * (e1 + e2));
+        dst[q] = sl;
         ok[q] = true;
     }
 #pragma unroll
     for (int q = 0; q < CPB; q++)
-        if (ok[q]) uo[dst[q]] = nv[q];
-}
-
-
-// ---------------------------------------------------------------------------
-// fused red-black SOR sweep of the volume interiors
-//
-// A workgroup owns the rows (j,k), j in [j0, j0+8), k in [k0, k0+8), of one
-// tetrahedron and the nodes i0 .. i0+61 of those rows.  Phase 1 computes the
-// new red values of the 10x10 rows [j0-1, j0+8] x [k0-1, k0+8] (the rows a
-// black node of the tile touches) for i0-1 .. i0+62 into LDS, red nodes only
-// (the red node of row lane l is stored at l >> 1).  Phase 2 computes the new
-// black values of the tile rows from them and writes whole rows of uout.
-// Interior values are read from uin, boundary (ghost) values from ughost,
-// whose red copies the interface kernel has already updated.
-// ---------------------------------------------------------------------------
-constexpr int kFE = kFusedTile + 2;
-
-// sum of the 6 neighbour terms of interior node (i,j,k) at slot c0 of a
-// closure; neighbours on the closure's faces are read from the ghost array
-template <typename T, bool VK>
-__device__ __forceinline__ void stencil_sums(int i, int j, int k, int c0, int4 ra, const T *__restrict__ uv,
-                                             const T *__restrict__ gv, const T *__restrict__ w0,
-                                             const T *__restrict__ w1, const T *__restrict__ w2, int m, T &diag,
-                                             T &acc, bool nb0) {
-    const int rj = ra.y;
-    const int ap = c0 + 1, am = c0 - 1, bp = c0 + rj - 1, bm = c0 - rj, cp = c0 + ra.z, cm = c0 + ra.w;
-    T vap = T(0), vam = T(0), vbp = T(0), vbm = T(0), vcp = T(0), vcm = T(0);
-    if (!nb0) {
-        vap = (i + 1 + j + k == m) ? gv[ap] : uv[ap];
-        vam = (i == 1) ? gv[am] : uv[am];
-        vbp = (i == 1) ? gv[bp] : uv[bp];
-        vbm = (j == 1) ? gv[bm] : uv[bm];
-        vcp = (j == 1) ? gv[cp] : uv[cp];
-        vcm = (k == 1) ? gv[cm] : uv[cm];
-    }
-    if (VK) {
-        const T wap = w0[c0], wam = w0[am], wbp = w1[c0], wbm = w1[bm], wcp = w2[c0], wcm = w2[cm];
-        diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
-        acc = wap * vap + wam * vam + wbp * vbp + wbm * vbm + wcp * vcp + wcm * vcm;
-    } else {
-        diag = T(0);
-        acc = ((vap + vam) + (vbp + vbm)) + (vcp + vcm);
-    }
-}
-
-// SOR update of one node from its neighbour sum (k = 1: diag 6h, offdiag -h)
-template <typename T, bool VK>
-__device__ __forceinline__ T sor_update(T uo, T bval, T diag, T acc, T h, T omega, T om_d) {
-    if (VK) return uo + omega * (bval - (diag * uo - acc)) / diag;
-    return uo + om_d * (bval - h * (T(6) * uo - acc));
-}
-
-template <typename T, bool VK, bool ZERO>
-__global__ void __launch_bounds__(256) k_fused_sweep(FusedGeom fg, const T *__restrict__ uin, T *__restrict__ uout,
-                                                     const T *__restrict__ ughost, const T *__restrict__ b,
-                                                     Weights<T> w, T h, T omega, T om_d) {
-    __shared__ T red[kFE * kFE][33];
-    const unsigned lg = block_order(blockIdx.x, gridDim.x, fg.remap);
-    const int v = (int)(lg / (unsigned)fg.ntiles);
-    const int4 tile = fg.tiles[lg % (unsigned)fg.ntiles];
-    const int j0 = tile.x, k0 = tile.y, i0 = tile.z;
-    const int M = fg.M, m = M - 1;
-    const VolDesc d = fg.vd[v];
-    const T *uv = uin + d.vec;
-    const T *gv = ughost + d.vec;
-    const T *bv = b + d.vec;
-    const T *w0 = VK ? w.w0 + d.w : nullptr, *w1 = VK ? w.w1 + d.w : nullptr, *w2 = VK ? w.w2 + d.w : nullptr;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int half = lane >> 5, t = lane & 31;
-
-    // phase 1: red values of the 10x10 row box, two rows per wave step and
-    // four steps in flight
-    constexpr int kPairs = (kFE * kFE + 1) / 2;  // 50 row pairs
-    for (int base = wave; base < kPairs; base += 16) {
-        T val[4];
-        int row[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            row[q] = -1;
-            val[q] = T(0);
-            const int pr = base + 4 * q;
-            const int er = 2 * pr + half;
-            if (pr >= kPairs || er >= kFE * kFE) continue;
-            const int j = j0 - 1 + er % kFE, k = k0 - 1 + er / kFE;
-            const int prow = (k + i0 - 1) & 1;  // red lanes of this row have lane parity prow
-            const int l = 2 * t + prow;
-            const int i = i0 - 1 + l;
-            if (j < 0 || k < 0 || i < 0 || i + j + k > m) continue;
-            const int4 ra = fg.rowA[k * M - ((k * (k - 1)) >> 1) + j];
-            const int c0 = ra.x + i;
-            if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1) {
-                T diag, acc;
-                stencil_sums<T, VK>(i, j, k, c0, ra, uv, gv, w0, w1, w2, m, diag, acc, ZERO);
-                val[q] = sor_update<T, VK>(ZERO ? T(0) : uv[c0], bv[c0], diag, acc, h, omega, om_d);
-            } else {
-                val[q] = gv[c0];  // ghost: already the new red value
-            }
-            row[q] = er;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (row[q] >= 0) red[row[q]][t] = val[q];
-    }
-    __syncthreads();
-
-    // phase 2: black values of the tile rows; each thread writes lanes 2t, 2t+1
-    // of one row, two rows per wave step and two steps in flight
-    constexpr int kTPairs = kFusedTile * kFusedTile / 2;  // 32 row pairs
-    for (int base = wave; base < kTPairs; base += 8) {
-        T val[2][2];
-        int dst[2][2];
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int tr = 2 * (base + 4 * q2) + half;
-            const int jj = tr % kFusedTile, kk = tr / kFusedTile;
-            const int j = j0 + jj, k = k0 + kk;
-            const int er = (jj + 1) + kFE * (kk + 1);
-            const int prow = (k + i0 - 1) & 1;
-            const bool row_ok = base + 4 * q2 < kTPairs && j + k <= m - 2;
-            const int4 ra = row_ok ? fg.rowA[k * M - ((k * (k - 1)) >> 1) + j] : make_int4(0, 0, 0, 0);
-#pragma unroll
-            for (int q = 0; q < 2; q++) {
-                dst[q2][q] = -1;
-                val[q2][q] = T(0);
-                const int l = 2 * t + q;
-                const int i = i0 - 1 + l;
-                if (!row_ok || l < 1 || l > kFusedSeg || i + j + k > m - 1) continue;
-                const int c0 = ra.x + i;
-                if (((l + prow) & 1) == 0) {
-                    val[q2][q] = red[er][l >> 1];
-                } else {
-                    // neighbours: same row l-1, l+1; (j+1,k) at l-1; (j-1,k) at l+1;
-                    // (j-1,k+1) at l; (j+1,k-1) at l
-                    const T vap = red[er][(l + 1) >> 1], vam = red[er][(l - 1) >> 1];
-                    const T vbp = red[er + 1][(l - 1) >> 1], vbm = red[er - 1][(l + 1) >> 1];
-                    const T vcp = red[er - 1 + kFE][l >> 1], vcm = red[er + 1 - kFE][l >> 1];
-                    T diag, acc;
-                    if (VK) {
-                        const int am = c0 - 1, bm = c0 - ra.y, cm = c0 + ra.w;
-                        const T wap = w0[c0], wam = w0[am], wbp = w1[c0], wbm = w1[bm], wcp = w2[c0], wcm = w2[cm];
-                        diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
-                        acc = wap * vap + wam * vam + wbp * vbp + wbm * vbm + wcp * vcp + wcm * vcm;
-                    } else {
-                        diag = T(0);
-                        acc = ((vap + vam) + (vbp + vbm)) + (vcp + vcm);
-                    }
-                    val[q2][q] = sor_update<T, VK>(ZERO ? T(0) : uv[c0], bv[c0], diag, acc, h, omega, om_d);
-                }
-                dst[q2][q] = c0;
-            }
-        }
-        T *ov = uout + d.vec;
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++)
-#pragma unroll
-            for (int q = 0; q < 2; q++)
-                if (dst[q2][q] >= 0) ov[dst[q2][q]] = val[q2][q];
-    }
+        if (ok[q]) uf[dst[q]] = nv[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -717,25 +512,17 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
 }
 
 template <typename T, bool VK>
-__global__ void k_local_coarse(const VolDesc *__restrict__ vd, int nvol, int M, const T *__restrict__ b,
+__global__ void k_local_coarse(const VolDesc *__restrict__ vd, int nvol, int4 sl, const T *__restrict__ b,
                                T *__restrict__ u, Weights<T> w, T h) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvol) return;
     const VolDesc d = vd[v];
     // the single interior node (1,1,1) of a tetrahedron with 4 segments per edge
-    VNode n;
-    n.i = 1;
-    n.j = 1;
-    n.k = 1;
-    n.s = M - 1;
-    n.ps = pstart_d(M, 1);
-    n.o = rstart_d(n.s, 1) + 1;
-    const int c0 = n.ps + n.o;
+    const int c0 = sl.x;
     T diag;
     if (VK) {
-        const Nb6 q = nb6(n);
         const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
-        diag = ((w0[c0] + w0[q.am]) + (w1[c0] + w1[q.bm])) + (w2[c0] + w2[q.cm]);
+        diag = ((w0[c0] + w0[sl.y]) + (w1[c0] + w1[sl.z])) + (w2[c0] + w2[sl.w]);
     } else {
         diag = T(6) * h;
     }
@@ -789,14 +576,15 @@ __global__ void __launch_bounds__(512) k_user_to_slots(VolGeom vg, const int *__
         vec[ig.base + t] = (T)user[ifc_dof[t]];
         return;
     }
-    VNode n;
-    if (!vol_node(vg, block_order(f - nib, gridDim.x - nib, vg.remap), n)) return;
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    LNode n;
+    if (!list_node<1>(vg, block_order(f - nib, gridDim.x - nib, vg.remap), per_vol, 0, n)) return;
     const VolDesc d = vg.vd[n.v];
     int X[3];
     grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
     const bool in = X[0] > 0 && X[1] > 0 && X[2] > 0 && X[0] < N && X[1] < N && X[2] < N;
     const long long dof = (long long)(X[0] - 1) + (long long)(N - 1) * ((X[1] - 1) + (long long)(N - 1) * (X[2] - 1));
-    (vec + d.vec)[n.ps + n.o] = in ? (T)user[dof] : T(0);
+    (vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)] = in ? (T)user[dof] : T(0);
 }
 
 template <typename T, int CPB>
@@ -821,7 +609,7 @@ __global__ void __launch_bounds__(512) k_slots_to_user(VolGeom vg, const int *__
         grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
         const long long dof =
             (long long)(X[0] - 1) + (long long)(N - 1) * ((X[1] - 1) + (long long)(N - 1) * (X[2] - 1));
-        user[dof] = (double)(vec + d.vec)[n.c0];
+        user[dof] = (double)(vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)];
     }
 }
 
@@ -845,26 +633,27 @@ __global__ void __launch_bounds__(512) k_mass(VolGeom vg, IfcGeom ig, int nib, c
     }
     const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
     const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+    const int M = vg.M;
 #pragma unroll
     for (int q = 0; q < CPB; q++) {
         LNode n;
         if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
         const VolDesc d = vg.vd[n.v];
         const double *xv = x + d.vec;
-        const int rid = n.k * vg.M - ((n.k * (n.k - 1)) >> 1) + n.j;
-        const int4 rb = vg.rowB[rid];
-        const int F = n.c0, rj = n.rj;
+        const int i = n.i, j = n.j, k = n.k;
+        auto X = [&](int di, int dj, int dk) { return xv[lslot(vg.rowC, M, i + di, j + dj, k + dk)]; };
         // axis (a, b, c), face diagonals (a+b, b+c, a+c), body diagonal (a+b+c)
-        const double ax = ((xv[F + 1] + xv[F - 1]) + (xv[F + rj - 1] + xv[F - rj])) + (xv[F + n.dcp] + xv[F + n.dcm]);
-        const double fd = ((xv[F + rj] + xv[F - rj - 1]) + (xv[F + rb.x - 1] + xv[F + rb.y + 1])) +
-                          (xv[F + n.dcp + 1] + xv[F + n.dcm - 1]);
-        const double bd = xv[F + rb.x] + xv[F + rb.y];
-        (y + d.vec)[F] = wc * xv[F] + wax * ax + wfd * fd + wbd * bd;
+        const double ax =
+            ((X(1, 0, 0) + X(-1, 0, 0)) + (X(-1, 1, 0) + X(1, -1, 0))) + (X(0, -1, 1) + X(0, 1, -1));
+        const double fd =
+            ((X(0, 1, 0) + X(0, -1, 0)) + (X(-1, 0, 1) + X(1, 0, -1))) + (X(1, -1, 1) + X(-1, 1, -1));
+        const double bd = X(0, 0, 1) + X(0, 0, -1);
+        (y + d.vec)[lslot(vg.rowC, M, i, j, k)] = wc * X(0, 0, 0) + wax * ax + wfd * fd + wbd * bd;
     }
 }
 
-__global__ void __launch_bounds__(512) k_update_add(VolGeom vg, IfcGeom ig, int nib, double *__restrict__ u,
-                                                    const float *__restrict__ e) {
+__global__ void __launch_bounds__(256) k_update_add(const VolDesc *__restrict__ vd, long long span, IfcGeom ig,
+                                                    int nib, double *__restrict__ u, const float *__restrict__ e) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
@@ -873,10 +662,16 @@ __global__ void __launch_bounds__(512) k_update_add(VolGeom vg, IfcGeom ig, int 
         u[sl] += (double)e[sl];
         return;
     }
-    VNode n;
-    if (!vol_node(vg, block_order(f - nib, gridDim.x - nib, vg.remap), n)) return;
-    const long long sl = vg.vd[n.v].vec + n.ps + n.o;
-    u[sl] += (double)e[sl];
+    // span slots per volume, 4 per thread
+    const long long per_vol = (span + 1023) / 1024;
+    const long long g = f - nib;
+    const long long v = g / per_vol, o0 = (g % per_vol) * 1024 + threadIdx.x;
+    const long long base = vd[v].vec;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const long long o = o0 + 256 * q;
+        if (o < span) u[base + o] += (double)e[base + o];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -946,13 +741,13 @@ __device__ double edge_w(const double *__restrict__ k, int N, double h, int x, i
 __global__ void __launch_bounds__(512) k_vol_weights(VolGeom vg, const int *__restrict__ tetinfo, int m, int N,
                                                      double h, const double *__restrict__ k, double *__restrict__ w0,
                                                      double *__restrict__ w1, double *__restrict__ w2) {
-    VNode n;
-    if (!vol_node(vg, block_order(blockIdx.x, gridDim.x, vg.remap), n)) return;
+    LNode n;
+    if (!list_node<1>(vg, block_order(blockIdx.x, gridDim.x, vg.remap), list_blocks_per_vol<1>(vg), 0, n)) return;
     const VolDesc d = vg.vd[n.v];
     int X[3];
     grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
     const int *ti = tetinfo + 6 * d.tet;
-    const long long sl = d.w + n.ps + n.o;
+    const long long sl = d.w + lslot(vg.rowC, vg.M, n.i, n.j, n.k);
     // local direction s goes along grid axis p_s; skip edges that leave the cube
     double v[3];
     for (int s = 0; s < 3; s++) {
@@ -1023,10 +818,11 @@ __global__ void k_grad_k(const double *__restrict__ u, const double *__restrict_
 }
 
 // workgroups of a list-mode launch
-inline long long list_blocks(const VolGeom &g) {
-    const long long per = ((long long)g.nlist + (long long)g.bs * g.cpb - 1) / ((long long)g.bs * g.cpb);
+inline long long list_blocks(const VolGeom &g, int cpb) {
+    const long long per = ((long long)g.nlist + (long long)g.bs * cpb - 1) / ((long long)g.bs * cpb);
     return per * g.nvol;
 }
+inline long long list_blocks(const VolGeom &g) { return list_blocks(g, g.cpb); }
 
 inline unsigned grid1d(long long n, int bs) {
     long long g = (n + bs - 1) / bs;
@@ -1040,22 +836,21 @@ inline unsigned grid1d(long long n, int bs) {
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *uvol, const T *b,
-                   const Weights<T> &w, bool vk, double h, double omega, int colour, bool own0, bool nb0) {
+void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w, bool vk,
+                   double h, double omega, bool own0, bool nb0) {
     const int nib = ifc_blocks(ig, vg.bs);
     const long long nvb = list_blocks(vg);
     const long long grid = nib + nvb;
     if (grid == 0) return;
     const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
-    (void)colour;
 #define HHGR_COLOUR(VK, O0, N0)                                                                                 \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
             hipLaunchKernelGGL((k_colour<T, VK, O0, N0, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, \
-                               uvol, b, w, th, to, tod);                                                      \
+                               b, w, th, to, tod);                                                            \
         else                                                                                                   \
             hipLaunchKernelGGL((k_colour<T, VK, O0, N0, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, \
-                               uvol, b, w, th, to, tod);                                                      \
+                               b, w, th, to, tod);                                                            \
     } while (0)
     if (vk) {
         if (own0 && nb0) HHGR_COLOUR(true, true, true);
@@ -1101,49 +896,29 @@ int launch_residual(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const T
 }
 
 template <typename T>
-void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, const int4 *fA, const int4 *fB,
-                     const IfcGeom &igc, const int *rst, const T *rf, T *bc) {
+void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, const int2 *fC, const IfcGeom &igc,
+                     const int *rst, const T *rf, T *bc) {
     const int nib = ifc_blocks(igc, vc.bs);
     const long long grid = nib + list_blocks(vc);
     if (grid == 0) return;
     if (vc.cpb == 1)
-        hipLaunchKernelGGL((k_restrict<T, 1>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, fA, fB, igc, nib, rst, rf,
-                           bc);
+        hipLaunchKernelGGL((k_restrict<T, 1>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, fC, igc, nib, rst, rf, bc);
     else
-        hipLaunchKernelGGL((k_restrict<T, 4>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, fA, fB, igc, nib, rst, rf,
-                           bc);
+        hipLaunchKernelGGL((k_restrict<T, 4>), dim3((unsigned)grid), dim3(vc.bs), 0, s, vc, vdf, fC, igc, nib, rst, rf, bc);
 }
 
 template <typename T>
-void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int4 *cA, int Mc, const IfcGeom &igf,
-                    const int *prl, const T *ec, T *uf, T *uo) {
+void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int2 *cC, int Mc, const IfcGeom &igf,
+                    const int *prl, const T *ec, T *uf) {
     const int nib = ifc_blocks(igf, vf.bs);
     const long long grid = nib + list_blocks(vf);
     if (grid == 0) return;
     if (vf.cpb == 1)
-        hipLaunchKernelGGL((k_prolong<T, 1>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, cA, Mc, igf, nib, prl, ec,
-                           uf, uo);
+        hipLaunchKernelGGL((k_prolong<T, 1>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, cC, Mc, igf, nib, prl, ec,
+                           uf);
     else
-        hipLaunchKernelGGL((k_prolong<T, 4>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, cA, Mc, igf, nib, prl, ec,
-                           uf, uo);
-}
-
-template <typename T>
-void launch_fused_sweep(hipStream_t s, const FusedGeom &fg, const T *uin, T *uout, const T *ughost, const T *b,
-                        const Weights<T> &w, bool vk, double h, double omega, bool zero) {
-    const long long grid = (long long)fg.ntiles * fg.nvol;
-    if (grid == 0) return;
-    const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
-#define HHGR_FUSED(VK, Z) \
-    hipLaunchKernelGGL((k_fused_sweep<T, VK, Z>), dim3((unsigned)grid), dim3(256), 0, s, fg, uin, uout, ughost, b, w, th, to, tod)
-    if (vk) {
-        if (zero) HHGR_FUSED(true, true);
-        else HHGR_FUSED(true, false);
-    } else {
-        if (zero) HHGR_FUSED(false, true);
-        else HHGR_FUSED(false, false);
-    }
-#undef HHGR_FUSED
+        hipLaunchKernelGGL((k_prolong<T, 4>), dim3((unsigned)grid), dim3(vf.bs), 0, s, vf, vdc, cC, Mc, igf, nib, prl, ec,
+                           uf);
 }
 
 template <typename T>
@@ -1162,14 +937,14 @@ void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *c
 }
 
 template <typename T>
-void launch_local_coarse(hipStream_t s, const VolDesc *vd, int nvol, int M, const T *b, T *u, const Weights<T> &w,
+void launch_local_coarse(hipStream_t s, const VolDesc *vd, int nvol, int4 sl, const T *b, T *u, const Weights<T> &w,
                          bool vk, double h) {
     if (nvol <= 0) return;
     const unsigned g = (unsigned)((nvol + 63) / 64);
     if (vk)
-        hipLaunchKernelGGL((k_local_coarse<T, true>), dim3(g), dim3(64), 0, s, vd, nvol, M, b, u, w, (T)h);
+        hipLaunchKernelGGL((k_local_coarse<T, true>), dim3(g), dim3(64), 0, s, vd, nvol, sl, b, u, w, (T)h);
     else
-        hipLaunchKernelGGL((k_local_coarse<T, false>), dim3(g), dim3(64), 0, s, vd, nvol, M, b, u, w, (T)h);
+        hipLaunchKernelGGL((k_local_coarse<T, false>), dim3(g), dim3(64), 0, s, vd, nvol, sl, b, u, w, (T)h);
 }
 
 void launch_reduce(hipStream_t s, const double *partial, int n, double *out) {
@@ -1186,7 +961,7 @@ template <typename T>
 void launch_user_to_slots(hipStream_t s, const VolGeom &vfull, const int *tetinfo, int m, int N, const IfcGeom &ig,
                           const int *ifc_dof, const double *user, T *vec) {
     const int nib = ifc_blocks(ig, vfull.bs);
-    const long long grid = nib + (long long)vfull.nchunks * vfull.nvol;
+    const long long grid = nib + list_blocks(vfull, 1);
     if (grid == 0) return;
     hipLaunchKernelGGL((k_user_to_slots<T>), dim3((unsigned)grid), dim3(vfull.bs), 0, s, vfull, tetinfo, m, N, ig, nib,
                        ifc_dof, user, vec);
@@ -1217,11 +992,12 @@ void launch_mass(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const in
         hipLaunchKernelGGL(k_mass<4>, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, nib, nb15, x, y, h * h * h);
 }
 
-void launch_update_add(hipStream_t s, const VolGeom &vfull, const IfcGeom &ig, double *u, const float *e) {
-    const int nib = ifc_blocks(ig, vfull.bs);
-    const long long grid = nib + (long long)vfull.nchunks * vfull.nvol;
+void launch_update_add(hipStream_t s, const VolDesc *vd, int nvol, long long span, const IfcGeom &ig, double *u,
+                       const float *e) {
+    const int nib = ifc_blocks(ig, 256);
+    const long long grid = nib + (long long)nvol * ((span + 1023) / 1024);
     if (grid == 0) return;
-    hipLaunchKernelGGL(k_update_add, dim3((unsigned)grid), dim3(vfull.bs), 0, s, vfull, ig, nib, u, e);
+    hipLaunchKernelGGL(k_update_add, dim3((unsigned)grid), dim3(256), 0, s, vd, span, ig, nib, u, e);
 }
 
 template <typename T>
@@ -1243,7 +1019,7 @@ void launch_coarsen_k(hipStream_t s, const double *kf, int Nf, double *kc, int N
 
 void launch_vol_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo, int m, int N, double h,
                         const double *k, double *w0, double *w1, double *w2) {
-    const long long grid = (long long)vfull.nchunks * vfull.nvol;
+    const long long grid = list_blocks(vfull, 1);
     if (grid == 0) return;
     hipLaunchKernelGGL(k_vol_weights, dim3((unsigned)grid), dim3(vfull.bs), 0, s, vfull, tetinfo, m, N, h, k, w0, w1,
                        w2);
@@ -1267,36 +1043,32 @@ void launch_grad_k(hipStream_t s, const double *u, const double *lam, int N, dou
 
 // explicit instantiations
 template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
-                                    const double *, const Weights<double> &, bool, double, double, int, bool, bool);
-template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *, const float *,
-                                   const Weights<float> &, bool, double, double, int, bool, bool);
-template void launch_fused_sweep<double>(hipStream_t, const FusedGeom &, const double *, double *, const double *,
-                                         const double *, const Weights<double> &, bool, double, double, bool);
-template void launch_fused_sweep<float>(hipStream_t, const FusedGeom &, const float *, float *, const float *,
-                                        const float *, const Weights<float> &, bool, double, double, bool);
+                                    const Weights<double> &, bool, double, double, bool, bool);
+template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                   const Weights<float> &, bool, double, double, bool, bool);
 template int launch_residual<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                              const double *, const Weights<double> &, bool, double, double *, double *);
 template int launch_residual<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                             const double *, const Weights<double> &, bool, double, float *, double *);
 template int launch_residual<float, float>(hipStream_t, const VolGeom &, const IfcGeom &, const float *, const float *,
                                            const Weights<float> &, bool, double, float *, double *);
-template void launch_restrict<double>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, const int4 *,
-                                      const IfcGeom &, const int *, const double *, double *);
-template void launch_restrict<float>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, const int4 *,
-                                     const IfcGeom &, const int *, const float *, float *);
-template void launch_prolong<double>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, int, const IfcGeom &,
-                                     const int *, const double *, double *, double *);
-template void launch_prolong<float>(hipStream_t, const VolGeom &, const VolDesc *, const int4 *, int, const IfcGeom &,
-                                    const int *, const float *, float *, float *);
+template void launch_restrict<double>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, const IfcGeom &,
+                                      const int *, const double *, double *);
+template void launch_restrict<float>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, const IfcGeom &,
+                                     const int *, const float *, float *);
+template void launch_prolong<double>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, int, const IfcGeom &,
+                                     const int *, const double *, double *);
+template void launch_prolong<float>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, int, const IfcGeom &,
+                                    const int *, const float *, float *);
 template void launch_coarse_pcg<double>(hipStream_t, int, const long long *, const int *, const double *,
                                         const unsigned char *, const double *, double *, const int *, const int *,
                                         double, int, int *);
 template void launch_coarse_pcg<float>(hipStream_t, int, const long long *, const int *, const double *,
                                        const unsigned char *, const float *, float *, const int *, const int *, double,
                                        int, int *);
-template void launch_local_coarse<double>(hipStream_t, const VolDesc *, int, int, const double *, double *,
+template void launch_local_coarse<double>(hipStream_t, const VolDesc *, int, int4, const double *, double *,
                                           const Weights<double> &, bool, double);
-template void launch_local_coarse<float>(hipStream_t, const VolDesc *, int, int, const float *, float *,
+template void launch_local_coarse<float>(hipStream_t, const VolDesc *, int, int4, const float *, float *,
                                          const Weights<float> &, bool, double);
 template void launch_fill<double>(hipStream_t, double *, long long, double);
 template void launch_fill<float>(hipStream_t, float *, long long, float);

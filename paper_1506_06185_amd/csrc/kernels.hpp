@@ -14,22 +14,21 @@ struct VolDesc {
     int pad;
 };
 
-// structured part of a launch: every listed volume x either a list of nodes
-// (list mode: packed (i,j,k), the same for every volume, with the row offset
-// tables of the level) or every chunk of its closure (chunk mode)
+// structured part of a launch: every listed volume x a list of nodes of its
+// closure (packed (i,j,k), the same for every volume), with the row tables of
+// the level's colour-split closure layout
 struct VolGeom {
     const VolDesc *vd = nullptr;
     int nvol = 0;
-    const unsigned *list = nullptr;  // list mode
+    const unsigned *list = nullptr;
     int nlist = 0;
-    const int4 *rowA = nullptr;      // per row (j,k): (slot of (0,j,k), length, to (j-1,k+1), to (j+1,k-1))
-    const int4 *rowB = nullptr;      // per row: (to (j,k+1), to (j,k-1), 0, 0)
-    const int2 *chunks = nullptr;    // chunk mode: (plane k, first offset) per chunk of bs slots
-    int nchunks = 0;
-    int M = 0;   // nodes per macro edge at this level (2^l + 1)
+    const int2 *rowC = nullptr;  // per row: first slot of its red nodes, of its black nodes
+    const int4 *rowN = nullptr;  // per (colour, row): two int4 of neighbour bases (see topology.hpp)
+    int nrows = 0;
+    int M = 0;        // nodes per macro edge at this level (2^l + 1)
     int bs = 256;
-    int remap = 1;  // 1: contiguous block ranges per XCD, 0: hardware order
-    int cpb = 4;    // list mode: nodes per thread (1 or 4), all loads issued before the stores
+    int remap = 1;    // 1: contiguous block ranges per XCD, 0: hardware order
+    int cpb = 1;      // nodes per thread (1 or 4), all loads issued before the stores
 };
 
 // table-driven part of a launch: interface nodes [i0, i1)
@@ -49,35 +48,12 @@ struct Weights {
     const T *wi = nullptr;                                // [6][n_ifc] interface edge weights
 };
 
-// colour pass of red-black SOR (colour 0 = red = even x+y+z).  own0: the
-// nodes of this colour start from zero; nb0: all neighbours are zero.
-// uvol: where interface nodes read their volume-interior neighbours (the
-// volume interiors may live in a second buffer during fused sweeps); u holds
-// the interface masters and the ghost copies.
+// colour pass of red-black SOR: the volume nodes in vg's list and the
+// interface nodes of ig (all of one colour).  own0: the nodes of this colour
+// start from zero; nb0: all neighbours are zero.
 template <typename T>
-void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *uvol, const T *b,
-                   const Weights<T> &w, bool vk, double h, double omega, int colour, bool own0, bool nb0);
-
-// tiles of the fused sweep: (j0, k0, i0) of an 8x8 block of rows and a
-// 62-node segment along i
-constexpr int kFusedTile = 8;
-constexpr int kFusedSeg = 62;
-struct FusedGeom {
-    const VolDesc *vd = nullptr;
-    const int4 *tiles = nullptr;
-    const int4 *rowA = nullptr;
-    int ntiles = 0;
-    int nvol = 0;
-    int M = 0;
-    int remap = 1;
-};
-
-// one red-black SOR sweep of the volume interiors: reads uin (interiors) and
-// ughost (ghost copies, red ones already updated), writes uout (interiors).
-// zero: uin is logically zero (first sweep of a correction).
-template <typename T>
-void launch_fused_sweep(hipStream_t s, const FusedGeom &fg, const T *uin, T *uout, const T *ughost, const T *b,
-                        const Weights<T> &w, bool vk, double h, double omega, bool zero);
+void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w, bool vk,
+                   double h, double omega, bool own0, bool nb0);
 
 // r = b - A u on volume interiors and interface nodes; r (of type TO) may be
 // nullptr; partial (one double per block) receives block sums of r^2 if not
@@ -87,20 +63,19 @@ int launch_residual(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const T
                     bool vk, double h, TO *r, double *partial);
 
 // b_c = P^T r_f.  vc: coarse volumes (interior list of the coarse level),
-// vdf: matching fine volumes, fA/fB: row tables of the fine level;
+// vdf: matching fine volumes, fC: row table of the fine level;
 // rst: [15][n_ifc_c] fine slots per coarse interface node.
 template <typename T>
-void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, const int4 *fA, const int4 *fB,
-                     const IfcGeom &igc, const int *rst, const T *rf, T *bc);
+void launch_restrict(hipStream_t s, const VolGeom &vc, const VolDesc *vdf, const int2 *fC, const IfcGeom &igc,
+                     const int *rst, const T *rf, T *bc);
 
-// u_f += P e_c.  vf: fine volumes (interior list), vdc: matching coarse
-// volumes, cA: row table and Mc node count per edge of the coarse level;
-// prl: [2][n_ifc_f] coarse slots per fine interface node.  The volume part
-// writes uo = uf + P e_c (uo may differ from uf); the interface part updates
-// uf in place and its ghost copies.
+// u_f += P e_c in place.  vf: fine volumes (interior list), vdc: matching
+// coarse volumes, cC and Mc: row table and nodes per edge of the coarse
+// level; prl: [2][n_ifc_f] coarse slots per fine interface node (the
+// interface part also updates the ghost copies).
 template <typename T>
-void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int4 *cA, int Mc, const IfcGeom &igf,
-                    const int *prl, const T *ec, T *uf, T *uo);
+void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int2 *cC, int Mc, const IfcGeom &igf,
+                    const int *prl, const T *ec, T *uf);
 
 // Jacobi-PCG on the coarsest level in one workgroup
 template <typename T>
@@ -108,9 +83,10 @@ void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *c
                        const unsigned char *frozen, const T *b, T *u, const int *cptr, const int *cidx, double rtol,
                        int maxit, int *iters);
 
-// one-unknown coarsest level of local (single tetrahedron) hierarchies
+// one-unknown coarsest level of local (single tetrahedron) hierarchies;
+// sl = closure slots of the node (1,1,1) and of its -a, -b, -c neighbours
 template <typename T>
-void launch_local_coarse(hipStream_t s, const VolDesc *vd, int nvol, int M, const T *b, T *u, const Weights<T> &w,
+void launch_local_coarse(hipStream_t s, const VolDesc *vd, int nvol, int4 sl, const T *b, T *u, const Weights<T> &w,
                          bool vk, double h);
 
 void launch_reduce(hipStream_t s, const double *partial, int n, double *out);
@@ -118,7 +94,8 @@ void launch_reduce(hipStream_t s, const double *partial, int n, double *out);
 template <typename T>
 void launch_fill(hipStream_t s, T *p, long long n, T v);
 
-// user vector (global lexicographic interior order) <-> slot space
+// user vector (global lexicographic interior order) <-> slot space; vfull
+// lists every closure node (ghosts receive the user value or the Dirichlet zero)
 template <typename T>
 void launch_user_to_slots(hipStream_t s, const VolGeom &vfull, const int *tetinfo, int m, int N, const IfcGeom &ig,
                           const int *ifc_dof, const double *user, T *vec);
@@ -130,8 +107,10 @@ void launch_slots_to_user(hipStream_t s, const VolGeom &vint, const int *tetinfo
 void launch_mass(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const int *nb15, const double *x, double *y,
                  double h);
 
-// u64 += e32 over the closures of the listed volumes and all interface slots
-void launch_update_add(hipStream_t s, const VolGeom &vfull, const IfcGeom &ig, double *u, const float *e);
+// u64 += e32 over the closure slots [0, span) of the listed volumes and the
+// interface slots
+void launch_update_add(hipStream_t s, const VolDesc *vd, int nvol, long long span, const IfcGeom &ig, double *u,
+                       const float *e);
 
 // u[dst[q]] = u[src[q]]
 template <typename T>

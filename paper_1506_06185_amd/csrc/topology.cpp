@@ -70,18 +70,19 @@ long long Topology::slot_of(int l, int x, int y, int z) const {
     if (f >= 0) return Lv.ifc_base + f;
     int t, i, j, k;
     if (!locate_interior(l, x, y, z, &t, &i, &j, &k)) return -1;
-    return (long long)t * Lv.C_pad + closure_index(Lv.M, i, j, k);
+    return (long long)t * Lv.C_pad + Lv.lay.index(i, j, k);
 }
 
-void Topology::build_level(int l, int chunk) {
+void Topology::build_level(int l) {
     TopoLevel &Lv = lev[l];
     Lv.l = l;
     Lv.m = 1 << l;
     Lv.M = Lv.m + 1;
     Lv.N = n_sub * Lv.m;
     Lv.h = 1.0 / Lv.N;
-    Lv.C = tetnum(Lv.M);
-    Lv.C_pad = round_up(Lv.C, 64);
+    Lv.lay.build(Lv.M);
+    Lv.C = Lv.lay.C;
+    Lv.C_pad = Lv.lay.span;
     Lv.ifc_base = (long long)n_tets * Lv.C_pad;
     const int m = Lv.m, M = Lv.M, N = Lv.N;
 
@@ -174,7 +175,7 @@ void Topology::build_level(int l, int chunk) {
                     if (!bnd) continue;
                     int X[3];
                     grid_pos(t, i, j, k, X);
-                    long long dst = (long long)t * Lv.C_pad + closure_index(M, i, j, k);
+                    long long dst = (long long)t * Lv.C_pad + Lv.lay.index(i, j, k);
                     long long src = slot_of(l, X[0], X[1], X[2]);
                     Lv.tg_dst.push_back((int)dst);
                     Lv.tg_src.push_back((int)src);
@@ -199,44 +200,34 @@ void Topology::build_level(int l, int chunk) {
             Lv.nb15[(size_t)e * Lv.n_ifc + f] = (int)slot_of(l, X[0] + kF15[e][0], X[1] + kF15[e][1], X[2] + kF15[e][2]);
         }
 
-    // interior node lists and row offset tables (shared by all tetrahedra)
-    Lv.ilist.clear();
+    // node lists and row tables (shared by all tetrahedra), in slot order
     Lv.rlist.clear();
     Lv.blist.clear();
-    for (int k = 1; k <= m; k++)
-        for (int j = 1; j <= m - k; j++)
-            for (int i = 1; i + j + k <= m - 1; i++) {
-                const unsigned w = pack_ijk(i, j, k);
-                Lv.ilist.push_back(w);
-                (((i + k) & 1) == 0 ? Lv.rlist : Lv.blist).push_back(w);
-            }
+    Lv.flist.clear();
+    for (int c = 0; c < 2; c++)
+        for (int k = 0; k <= m; k++)
+            for (int j = 0; j <= m - k; j++)
+                for (int i = (c + k) & 1; i <= m - k - j; i += 2) {
+                    const unsigned w = pack_ijk(i, j, k);
+                    Lv.flist.push_back(w);
+                    if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1) (c == 0 ? Lv.rlist : Lv.blist).push_back(w);
+                }
+    Lv.ilist = Lv.rlist;
+    Lv.ilist.insert(Lv.ilist.end(), Lv.blist.begin(), Lv.blist.end());
     const int nrows = M * (M + 1) / 2;
-    Lv.rowA.assign(nrows, {0, 0, 0, 0});
-    Lv.rowB.assign(nrows, {0, 0, 0, 0});
-    for (int k = 0; k <= m; k++)
-        for (int j = 0; j <= m - k; j++) {
-            const int s = M - k;
-            const long long c = closure_index(M, 0, j, k);
-            auto rel = [&](int jj, int kk) -> int {
-                if (jj < 0 || kk < 0 || kk > m || jj > m - kk) return 0;  // row does not exist
-                return (int)(closure_index(M, 0, jj, kk) - c);
-            };
-            Lv.rowA[row_id(M, j, k)] = {(int)c, s - j, rel(j - 1, k + 1), rel(j + 1, k - 1)};
-            Lv.rowB[row_id(M, j, k)] = {rel(j, k + 1), rel(j, k - 1), 0, 0};
-        }
-
-    // chunks
-    Lv.chunks_int.clear();
-    Lv.chunks_full.clear();
-    for (int k = 0; k <= m; k++) {
-        int s = M - k;
-        long long P = (long long)s * (s + 1) / 2;
-        for (long long o = 0; o < P; o += chunk) Lv.chunks_full.push_back({k, (int)o});
-        if (k >= 1 && k <= m - 3) {
-            long long lo = s, hi = row_start(s, m - 1 - k);  // rows 1 .. m-2-k
-            for (long long o = lo; o < hi; o += chunk) Lv.chunks_int.push_back({k, (int)o});
-        }
-    }
+    Lv.rowC.assign(nrows, {0, 0});
+    for (int r = 0; r < nrows; r++) Lv.rowC[r] = {Lv.lay.row0[2 * (size_t)r], Lv.lay.row0[2 * (size_t)r + 1]};
+    Lv.rowN.assign(2 * (size_t)nrows, {0, 0, 0, 0, 0, 0, 0, 0});
+    for (int c = 0; c < 2; c++)
+        for (int k = 1; k <= m - 3; k++)
+            for (int j = 1; j + k <= m - 2; j++) {
+                const int o = 1 - c, odd = (c + k) & 1;
+                auto start = [&](int jj, int kk, int cc) { return Lv.lay.row0[2 * (size_t)row_id(M, jj, kk) + cc]; };
+                Lv.rowN[(size_t)c * nrows + row_id(M, j, k)] = {start(j, k, c),          start(j, k, o) + odd,
+                                                                start(j + 1, k, o) + odd - 1,
+                                                                start(j - 1, k, o) + odd, start(j - 1, k + 1, o),
+                                                                start(j + 1, k - 1, o),   0, 0};
+            }
 }
 
 void Topology::build_transfer(int l) {
@@ -277,7 +268,7 @@ void Topology::build_coarse() {
                     if (i + j + k > Lv.m - 1) continue;
                     int X[3];
                     grid_pos(t, i, j, k, X);
-                    cs.slot.push_back((long long)t * Lv.C_pad + closure_index(Lv.M, i, j, k));
+                    cs.slot.push_back((long long)t * Lv.C_pad + Lv.lay.index(i, j, k));
                     pos.push_back({X[0], X[1], X[2]});
                     cs.is_vol.push_back(1);
                     cs.tet.push_back(t);
@@ -291,6 +282,7 @@ void Topology::build_coarse() {
         cs.ifc.push_back(f);
     }
     cs.n = (int)cs.slot.size();
+    cs.pos = pos;
     std::vector<std::pair<long long, int>> by_slot(cs.n);
     for (int q = 0; q < cs.n; q++) by_slot[q] = {cs.slot[q], q};
     std::sort(by_slot.begin(), by_slot.end());
@@ -325,7 +317,7 @@ void Topology::build_coarse() {
     }
 }
 
-std::string Topology::build(int n, int L_, int Lc_, int chunk) {
+std::string Topology::build(int n, int L_, int Lc_) {
     if (n < 1 || n > 8) return "n_sub must be in 1..8";
     if (Lc_ < 2 || L_ <= Lc_ || L_ > 9) return "need 2 <= coarse_level < level <= 9";
     n_sub = n;
@@ -345,7 +337,7 @@ std::string Topology::build(int n, int L_, int Lc_, int chunk) {
     lev.assign(L + 1, TopoLevel());
     ifc_key_.assign(L + 1, {});
     ifc_key_idx_.assign(L + 1, {});
-    for (int l = Lc; l <= L; l++) build_level(l, chunk);
+    for (int l = Lc; l <= L; l++) build_level(l);
     for (int l = Lc; l <= L; l++) {
         // every slot lookup must have succeeded
         const TopoLevel &Lv = lev[l];

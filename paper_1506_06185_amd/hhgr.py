@@ -75,8 +75,8 @@ def lib():
         "hhgr_batch_run": (C.c_int, [_vp, C.c_double, C.c_int, C.POINTER(Report)]),
         "hhgr_batch_destroy": (None, [_vp]),
         "hhgr_set_graph": (C.c_int, [_vp, C.c_int]),
-        "hhgr_set_smoother": (C.c_int, [_vp, C.c_int]),
         "hhgr_tuning_info": (C.c_int, [_vp, C.c_int, _ip, _ip, _ip]),
+        "hhgr_set_tuning": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
         "hhgr_autotune": (C.c_int, [_vp, C.c_char_p]),
         "hhgr_kernel_timing": (C.c_int, [_vp, C.c_int]),
         "hhgr_kernel_stats": (C.c_int, [_vp, C.POINTER(C.c_longlong), _dp, _dp]),
@@ -95,7 +95,7 @@ EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_de
             "hhgr_set_rhs", "hhgr_set_coeff", "hhgr_set_solution", "hhgr_get_solution", "hhgr_vcycle",
             "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_adjoint_grad",
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_set_graph",
-            "hhgr_set_smoother", "hhgr_tuning_info",
+            "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_last_error")
 
 
@@ -226,15 +226,16 @@ class Context:
     def set_graph(self, on: bool = True):
         _check(lib().hhgr_set_graph(self._h, int(bool(on))))
 
-    def set_smoother(self, mode: str = "auto"):
-        _check(lib().hhgr_set_smoother(self._h, {"auto": 0, "plain": 1, "fused": 2}[mode]))
+    def set_tuning(self, block_size: int = 256, xcd_order: int = 1, nodes_per_thread: int = 1, level: int = 0):
+        """Fix the volume-kernel launch shape (level 0 = every level above the coarsest)."""
+        _check(lib().hhgr_set_tuning(self._h, level, block_size, xcd_order, nodes_per_thread))
 
     def autotune(self, cache_path: str | None = None):
         _check(lib().hhgr_autotune(self._h, cache_path.encode() if cache_path else None))
 
     def tuning_info(self):
-        """{level: (block size + 1000 x nodes per thread, XCD-contiguous order, fused)} for every
-        level above the coarsest."""
+        """{level: (workgroup size, XCD-contiguous order, nodes per thread)} for every level above
+        the coarsest."""
         out = {}
         for l in range(self.desc.coarse_level + 1, self.desc.level + 1):
             bs, xo, fu = C.c_int(), C.c_int(), C.c_int()

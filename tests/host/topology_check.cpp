@@ -24,18 +24,34 @@ static int fails = 0;
     } while (0)
 
 // --- replicas of the device index helpers (kernels.hip) ---
-static int tetnum_d(int x) { return x * (x + 1) * (x + 2) / 6; }
-static int pstart_d(int M, int k) { return tetnum_d(M) - tetnum_d(M - k); }
-static int rstart_d(int s, int j) { return j * s - ((j * (j - 1)) >> 1); }
-static int cidx_d(int M, int i, int j, int k) { return pstart_d(M, k) + rstart_d(M - k, j) + i; }
-static int decode_row(int s, int o) {
-    const float b = 2.0f * (float)s + 1.0f;
-    const float disc = std::fmax(b * b - 8.0f * (float)o, 0.0f);
-    int j = (int)((b - std::sqrt(disc)) * 0.5f);
-    j = std::max(0, std::min(j, s - 1));
-    while (j + 1 <= s - 1 && rstart_d(s, j + 1) <= o) ++j;
-    while (j > 0 && rstart_d(s, j) > o) --j;
-    return j;
+static int row_of(int M, int j, int k) { return k * M - ((k * (k - 1)) >> 1) + j; }
+static int lslot(const TopoLevel &T, int i, int j, int k) {
+    const auto &r = T.rowC[row_of(T.M, j, k)];
+    return (((i + k) & 1) ? r[1] : r[0]) + (i >> 1);
+}
+// nb7: own slot and the 6 axis neighbours (ap, am, bp, bm, cp, cm) from rowN
+static void nb7(const TopoLevel &T, int i, int j, int k, int out[7]) {
+    const int nrows = (int)T.rowC.size(), c = (i + k) & 1, t = i >> 1;
+    const auto &e = T.rowN[(size_t)c * nrows + row_of(T.M, j, k)];
+    out[0] = e[0] + t;
+    out[1] = e[1] + t;
+    out[2] = e[1] + t - 1;
+    out[3] = e[2] + t;
+    out[4] = e[3] + t;
+    out[5] = e[4] + t;
+    out[6] = e[5] + t;
+}
+// the 15 fine slots read by k_restrict for coarse node (i,j,k), in the order
+// centre, then kD14
+static void restrict_reads(const TopoLevel &F, int i, int j, int k, int out[15]) {
+    const int Mf = F.M, I = 2 * i, J = 2 * j, K = 2 * k, t0 = I >> 1;
+    auto R = [&](int jj, int kk) { return F.rowC[row_of(Mf, jj, kk)]; };
+    const auto r0 = R(J, K), rjp = R(J + 1, K), rjm = R(J - 1, K), rcp = R(J - 1, K + 1), rcm = R(J + 1, K - 1),
+               rkp = R(J, K + 1), rkm = R(J, K - 1);
+    const int v[15] = {r0[0] + t0,      r0[1] + t0,      r0[1] + t0 - 1,  rjp[1] + t0 - 1, rjm[1] + t0,
+                       rcp[1] + t0,     rcm[1] + t0,     rjp[0] + t0,     rjm[0] + t0,     rkp[0] + t0 - 1,
+                       rkm[0] + t0,     rcp[0] + t0,     rcm[0] + t0 - 1, rkp[1] + t0,     rkm[1] + t0};
+    for (int q = 0; q < 15; q++) out[q] = v[q];
 }
 static const int kD14[14][3] = {{1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0}, {0, -1, 1},  {0, 1, -1}, {0, 1, 0},
                                 {0, -1, 0}, {-1, 0, 1}, {1, 0, -1}, {1, -1, 1}, {-1, 1, -1}, {0, 0, 1}, {0, 0, -1}};
@@ -47,70 +63,46 @@ static void grid_pos(const Topology &tp, int t, int m, int i, int j, int k, int 
     X[tp.perm[t][1]] += j;
 }
 
-// replica of k_fused_sweep's index logic: every interior node written once,
-// every LDS read backed by a phase-1 store of an existing node
-static void check_fused(int m) {
-    const int M = m + 1, FE = kTileRows + 2;
-    std::vector<int> written((size_t)tetnum_d(M), 0);
-    for (const auto &tl : fused_tile_list(m)) {
-        const int j0 = tl[0], k0 = tl[1], i0 = tl[2];
-        std::vector<char> have(FE * FE * 33, 0);
-        for (int er = 0; er < FE * FE; er++)
-            for (int t = 0; t < 32; t++) {
-                const int j = j0 - 1 + er % FE, k = k0 - 1 + er / FE;
-                const int prow = (k + i0 - 1) & 1, l = 2 * t + prow, i = i0 - 1 + l;
-                if (l > 63 || j < 0 || k < 0 || i < 0 || i + j + k > m) continue;
-                CHECK(((i + k) & 1) == 0, "phase-1 node is red");
-                CHECK(cidx_d(M, i, j, k) >= 0 && cidx_d(M, i, j, k) < tetnum_d(M), "phase-1 index");
-                have[er * 33 + t] = 1;
-            }
-        for (int tr = 0; tr < kTileRows * kTileRows; tr++) {
-            const int jj = tr % kTileRows, kk = tr / kTileRows, j = j0 + jj, k = k0 + kk;
-            if (j + k > m - 2) continue;
-            const int er = (jj + 1) + FE * (kk + 1), prow = (k + i0 - 1) & 1;
-            for (int l = 1; l <= kTileSeg; l++) {
-                const int i = i0 - 1 + l;
-                if (i + j + k > m - 1) continue;
-                CHECK(i >= 1 && j >= 1 && k >= 1, "phase-2 node interior");
-                written[cidx_d(M, i, j, k)]++;
-                if (((l + prow) & 1) == 0) {
-                    CHECK(have[er * 33 + (l >> 1)], "red value present");
-                } else {
-                    const int reads[6][2] = {{er, (l + 1) >> 1}, {er, (l - 1) >> 1}, {er + 1, (l - 1) >> 1},
-                                             {er - 1, (l + 1) >> 1}, {er - 1 + FE, l >> 1}, {er + 1 - FE, l >> 1}};
-                    for (auto &rd : reads) {
-                        CHECK(rd[0] >= 0 && rd[0] < FE * FE && rd[1] >= 0 && rd[1] < 32, "LDS index in range");
-                        CHECK(have[rd[0] * 33 + rd[1]], "black neighbour read a stored red value m=%d", m);
-                    }
-                }
-            }
-        }
-    }
+// the colour-split layout is a bijection of the closure nodes onto slots
+// [0, span) that puts every red node before every black one, keeps plane/row/i
+// order within a colour, and makes the nodes of one colour in a row consecutive
+static void check_layout(int m) {
+    const int M = m + 1;
+    ClosureLayout ly;
+    ly.build(M);
+    CHECK(ly.C == tetnum(M), "node count m=%d", m);
+    CHECK(ly.span % 64 == 0 && ly.black0 % 32 == 0 && ly.black0 >= ly.n_red, "padding m=%d", m);
+    std::vector<int> hit((size_t)ly.span, 0);
+    long long prev[2] = {-1, ly.black0 - 1};
     for (int k = 0; k <= m; k++)
         for (int j = 0; j <= m - k; j++)
             for (int i = 0; i <= m - k - j; i++) {
-                bool interior = i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1;
-                CHECK(written[cidx_d(M, i, j, k)] == (interior ? 1 : 0), "fused coverage m=%d (%d,%d,%d)", m, i, j, k);
+                const long long s = ly.index(i, j, k);
+                const int c = (i + k) & 1;
+                CHECK(s >= 0 && s < ly.span, "slot range m=%d", m);
+                if (s < 0 || s >= ly.span) continue;
+                hit[s]++;
+                CHECK(c == 0 ? s < ly.n_red : (s >= ly.black0 && s < ly.black0 + ly.n_black), "colour part m=%d", m);
+                CHECK(s == prev[c] + 1, "consecutive within a colour m=%d (%d,%d,%d)", m, i, j, k);
+                prev[c] = s;
             }
+    for (long long s = 0; s < ly.span; s++) {
+        const bool used = s < ly.n_red || (s >= ly.black0 && s < ly.black0 + ly.n_black);
+        CHECK(hit[s] == (used ? 1 : 0), "bijection m=%d slot %lld", m, s);
+    }
 }
 
 int main(int argc, char **argv) {
-    for (int lv = 2; lv <= 9; lv++) check_fused(1 << lv);
+    for (int lv = 2; lv <= 8; lv++) check_layout(1 << lv);
     int n_sub = argc > 1 ? std::atoi(argv[1]) : 2;
     int L = argc > 2 ? std::atoi(argv[2]) : 5;
-    // decode of every plane offset for the largest supported plane size
-    for (int s = 1; s <= 513; s++)
-        for (int o = 0; o < s * (s + 1) / 2; o++) {
-            int j = decode_row(s, o);
-            CHECK(rstart_d(s, j) <= o && o < rstart_d(s, j + 1), "decode s=%d o=%d", s, o);
-        }
     Topology tp;
-    std::string e = tp.build(n_sub, L, 2, 256);
+    std::string e = tp.build(n_sub, L, 2);
     CHECK(e.empty(), "build: %s", e.c_str());
     if (!e.empty()) return 1;
     for (int l = tp.Lc; l <= L; l++) {
         const TopoLevel &T = tp.lev[l];
-        const int m = T.m, M = T.M;
+        const int m = T.m;
         // interface node count (closed forms for the n^3 x 6 Kuhn cube)
         if (n_sub == 2) {
             long long expect = 72LL * (m - 1) * (m - 2) / 2 + 26LL * (m - 1) + 1;
@@ -139,100 +131,99 @@ int main(int argc, char **argv) {
             const TopoLevel &Fl = tp.lev[l + 1];
             for (int v : T.rst) CHECK(v >= 0 && v < Fl.n_slots, "rst range");
         }
-        // chunk tables cover exactly the interior nodes / the whole closure
-        long long covered = 0;
-        for (auto &ch : T.chunks_full) {
-            int s = M - ch.k;
-            CHECK(ch.k >= 0 && ch.k <= m && ch.o0 < s * (s + 1) / 2, "full chunk");
-            covered += std::min(256, s * (s + 1) / 2 - ch.o0);
-        }
-        CHECK(covered == T.C, "full chunks cover the closure");
-        long long nint = 0;
-        for (auto &ch : T.chunks_int)
-            for (int q = 0; q < 256; q++) {
-                int s = M - ch.k, o = ch.o0 + q;
-                if (o >= s * (s + 1) / 2) break;
-                int j = decode_row(s, o), i = o - rstart_d(s, j), k = ch.k;
-                if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= M - 2) nint++;
-            }
-        CHECK(nint == (long long)(m - 1) * (m - 2) * (m - 3) / 6, "interior chunks cover the interior l=%d", l);
-        // node lists and row tables used by the list-mode kernels
+        // node lists: slot order, colours, coverage
+        const long long nint = (long long)(m - 1) * (m - 2) * (m - 3) / 6;
         CHECK(T.ilist.size() == T.rlist.size() + T.blist.size(), "colour lists partition the interior");
-        CHECK((long long)T.ilist.size() == (long long)(m - 1) * (m - 2) * (m - 3) / 6, "interior list size");
-        for (unsigned wv : T.ilist) {
-            const int i = wv & 1023, j = (wv >> 10) & 1023, k = (int)(wv >> 20);
-            const auto &ra = T.rowA[row_id(M, j, k)];
-            const auto &rb = T.rowB[row_id(M, j, k)];
-            const int c0 = ra[0] + i, rj = ra[1];
-            CHECK(c0 == closure_index(M, i, j, k), "rowA slot");
-            const int offs[14] = {c0 + 1, c0 - 1, c0 + rj - 1, c0 - rj, c0 + ra[2], c0 + ra[3], c0 + rj,
-                                  c0 - (rj + 1), c0 + rb[0] - 1, c0 + rb[1] + 1, c0 + ra[2] + 1, c0 + ra[3] - 1,
-                                  c0 + rb[0], c0 + rb[1]};
-            for (int e2 = 0; e2 < 14; e2++)
-                CHECK(offs[e2] == cidx_d(M, i + kD14[e2][0], j + kD14[e2][1], k + kD14[e2][2]), "row offsets dir %d", e2);
+        CHECK((long long)T.ilist.size() == nint, "interior list size");
+        CHECK((long long)T.flist.size() == T.C, "full list size");
+        for (size_t q = 0; q < T.ilist.size(); q++)
+            CHECK(T.ilist[q] == (q < T.rlist.size() ? T.rlist[q] : T.blist[q - T.rlist.size()]), "ilist = red, black");
+        auto unpack = [](unsigned wv, int &i, int &j, int &k) {
+            i = wv & 1023;
+            j = (wv >> 10) & 1023;
+            k = (int)(wv >> 20);
+        };
+        long long last = -1;
+        for (unsigned wv : T.flist) {
+            int i, j, k;
+            unpack(wv, i, j, k);
+            const int sl = lslot(T, i, j, k);
+            CHECK(sl == T.lay.index(i, j, k), "lslot = layout index");
+            CHECK(sl > last, "full list in slot order");
+            last = sl;
         }
         for (unsigned wv : T.rlist) CHECK((((wv & 1023) + (wv >> 20)) & 1) == 0, "red list colour");
         for (unsigned wv : T.blist) CHECK((((wv & 1023) + (wv >> 20)) & 1) == 1, "black list colour");
-        // volume neighbour arithmetic vs topology lookup, every tet, every interior node
+        // every interior node of every tet: kernel slot arithmetic vs the
+        // topology's independent grid lookup
         for (int t = 0; t < tp.n_tets; t++) {
             const long long base = (long long)t * T.C_pad;
-            for (int k = 1; k <= m; k++)
-                for (int j = 1; j <= m - k; j++)
-                    for (int i = 1; i <= m - k - j; i++) {
-                        if (i + j + k > m - 1) continue;
-                        const int s = M - k, o = rstart_d(s, j) + i, ps = pstart_d(M, k), c0 = ps + o;
-                        CHECK(c0 == closure_index(M, i, j, k), "closure index");
-                        const int rj = s - j;
-                        const int nb[6] = {c0 + 1, c0 - 1, c0 + rj - 1, c0 - rj,
-                                           ps + s * (s + 1) / 2 + rstart_d(s - 1, j - 1) + i,
-                                           ps - (s + 1) * (s + 2) / 2 + rstart_d(s + 1, j + 1) + i};
-                        const int d[6][3] = {{1, 0, 0}, {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0}, {0, -1, 1}, {0, 1, -1}};
-                        int X[3];
-                        grid_pos(tp, t, m, i, j, k, X);
-                        CHECK(tp.slot_of(l, X[0], X[1], X[2]) == base + c0, "interior slot t=%d", t);
-                        for (int e2 = 0; e2 < 6; e2++) {
-                            CHECK(nb[e2] >= 0 && nb[e2] < T.C, "nb in closure");
-                            CHECK(nb[e2] == cidx_d(M, i + d[e2][0], j + d[e2][1], k + d[e2][2]), "nb formula");
-                            int Y[3];
-                            grid_pos(tp, t, m, i + d[e2][0], j + d[e2][1], k + d[e2][2], Y);
-                            int dist = std::abs(Y[0] - X[0]) + std::abs(Y[1] - X[1]) + std::abs(Y[2] - X[2]);
-                            CHECK(dist == 1, "axis neighbour is one grid step");
-                        }
-                        // mass: 14 Freudenthal neighbours stay in the closure
-                        for (int e2 = 0; e2 < 14; e2++) {
-                            int a = i + kD14[e2][0], b = j + kD14[e2][1], c = k + kD14[e2][2];
-                            CHECK(a >= 0 && b >= 0 && c >= 0 && a + b + c <= m, "d14 in closure");
-                        }
-                        // prolongation parents
-                        if (l > tp.Lc) {
-                            const TopoLevel &Cl = tp.lev[l - 1];
-                            int code = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
-                            int p1[3] = {i - kParDir[code][0], j - kParDir[code][1], k - kParDir[code][2]};
-                            int p2[3] = {i + kParDir[code][0], j + kParDir[code][1], k + kParDir[code][2]};
-                            for (int a = 0; a < 3; a++) CHECK((p1[a] % 2) == 0 && (p2[a] % 2) == 0 && p1[a] >= 0, "parity");
-                            int c1 = cidx_d(Cl.M, p1[0] / 2, p1[1] / 2, p1[2] / 2), c2 = cidx_d(Cl.M, p2[0] / 2, p2[1] / 2, p2[2] / 2);
-                            CHECK(c1 >= 0 && c1 < Cl.C && c2 >= 0 && c2 < Cl.C, "parent in coarse closure");
-                            int Y1[3], Y2[3];
-                            grid_pos(tp, t, Cl.m, p1[0] / 2, p1[1] / 2, p1[2] / 2, Y1);
-                            grid_pos(tp, t, Cl.m, p2[0] / 2, p2[1] / 2, p2[2] / 2, Y2);
-                            for (int a = 0; a < 3; a++) CHECK(Y1[a] + Y2[a] == X[a], "fine node is the midpoint");
-                        }
-                        // restriction from the next finer level
-                        if (l < L) {
-                            const TopoLevel &Fl = tp.lev[l + 1];
-                            for (int e2 = -1; e2 < 14; e2++) {
-                                int a = 2 * i + (e2 >= 0 ? kD14[e2][0] : 0), b = 2 * j + (e2 >= 0 ? kD14[e2][1] : 0),
-                                    c = 2 * k + (e2 >= 0 ? kD14[e2][2] : 0);
-                                CHECK(a >= 1 && b >= 1 && c >= 1 && a + b + c <= Fl.m - 1, "restriction source interior");
-                                int Y[3];
-                                grid_pos(tp, t, Fl.m, a, b, c, Y);
-                                int dist = 0;
-                                for (int q = 0; q < 3; q++) dist += std::abs(Y[q] - 2 * X[q]);
-                                CHECK(dist <= 3, "restriction source adjacent");
-                            }
-                        }
+            for (unsigned wv : T.ilist) {
+                int i, j, k;
+                unpack(wv, i, j, k);
+                int X[3];
+                grid_pos(tp, t, m, i, j, k, X);
+                int nb[7];
+                nb7(T, i, j, k, nb);
+                CHECK(tp.slot_of(l, X[0], X[1], X[2]) == base + nb[0], "interior slot t=%d", t);
+                CHECK(nb[0] == lslot(T, i, j, k), "nb7 own slot");
+                const int d[6][3] = {{1, 0, 0}, {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0}, {0, -1, 1}, {0, 1, -1}};
+                for (int e2 = 0; e2 < 6; e2++) {
+                    const int a = i + d[e2][0], b = j + d[e2][1], c = k + d[e2][2];
+                    CHECK(nb[1 + e2] == T.lay.index(a, b, c), "nb7 dir %d (%d,%d,%d) l=%d", e2, i, j, k, l);
+                    int Y[3];
+                    grid_pos(tp, t, m, a, b, c, Y);
+                    const int dist = std::abs(Y[0] - X[0]) + std::abs(Y[1] - X[1]) + std::abs(Y[2] - X[2]);
+                    CHECK(dist == 1, "axis neighbour is one grid step");
+                    // ghosts and interiors: the grid lookup names the same value
+                    const long long g = tp.slot_of(l, Y[0], Y[1], Y[2]);
+                    const bool interior = a >= 1 && b >= 1 && c >= 1 && a + b + c <= m - 1;
+                    if (interior) CHECK(g == base + nb[1 + e2], "interior neighbour slot");
+                }
+                // mass: 14 Freudenthal neighbours stay in the closure
+                for (int e2 = 0; e2 < 14; e2++) {
+                    int a = i + kD14[e2][0], b = j + kD14[e2][1], c = k + kD14[e2][2];
+                    CHECK(a >= 0 && b >= 0 && c >= 0 && a + b + c <= m, "d14 in closure");
+                }
+                // prolongation parents
+                if (l > tp.Lc) {
+                    const TopoLevel &Cl = tp.lev[l - 1];
+                    int code = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+                    int p1[3] = {i - kParDir[code][0], j - kParDir[code][1], k - kParDir[code][2]};
+                    int p2[3] = {i + kParDir[code][0], j + kParDir[code][1], k + kParDir[code][2]};
+                    for (int a = 0; a < 3; a++) CHECK((p1[a] % 2) == 0 && (p2[a] % 2) == 0 && p1[a] >= 0, "parity");
+                    const int c1 = lslot(Cl, p1[0] >> 1, p1[1] >> 1, p1[2] >> 1),
+                              c2 = lslot(Cl, p2[0] >> 1, p2[1] >> 1, p2[2] >> 1);
+                    CHECK(c1 == Cl.lay.index(p1[0] / 2, p1[1] / 2, p1[2] / 2), "parent 1 slot");
+                    CHECK(c2 == Cl.lay.index(p2[0] / 2, p2[1] / 2, p2[2] / 2), "parent 2 slot");
+                    int Y1[3], Y2[3];
+                    grid_pos(tp, t, Cl.m, p1[0] / 2, p1[1] / 2, p1[2] / 2, Y1);
+                    grid_pos(tp, t, Cl.m, p2[0] / 2, p2[1] / 2, p2[2] / 2, Y2);
+                    for (int a = 0; a < 3; a++) CHECK(Y1[a] + Y2[a] == X[a], "fine node is the midpoint");
+                }
+                // restriction from the next finer level: kernel's grouped row reads
+                if (l < L) {
+                    const TopoLevel &Fl = tp.lev[l + 1];
+                    int rd[15];
+                    restrict_reads(Fl, i, j, k, rd);
+                    for (int e2 = -1; e2 < 14; e2++) {
+                        int a = 2 * i + (e2 >= 0 ? kD14[e2][0] : 0), b = 2 * j + (e2 >= 0 ? kD14[e2][1] : 0),
+                            c = 2 * k + (e2 >= 0 ? kD14[e2][2] : 0);
+                        CHECK(a >= 1 && b >= 1 && c >= 1 && a + b + c <= Fl.m - 1, "restriction source interior");
+                        CHECK(rd[e2 + 1] == Fl.lay.index(a, b, c), "restriction read %d", e2);
+                        int Y[3];
+                        grid_pos(tp, t, Fl.m, a, b, c, Y);
+                        int dist = 0;
+                        for (int q = 0; q < 3; q++) dist += std::abs(Y[q] - 2 * X[q]);
+                        CHECK(dist <= 3, "restriction source adjacent");
+                        CHECK(tp.slot_of(l + 1, Y[0], Y[1], Y[2]) == (long long)t * Fl.C_pad + rd[e2 + 1],
+                              "restriction source slot");
                     }
+                }
+            }
         }
+        // local coarsest level: the node (1,1,1) and its -a,-b,-c neighbours
+        if (l == tp.Lc) CHECK(nint == 1, "one interior node per tet on the coarsest level");
         // interface neighbour tables agree with grid lookups
         for (int f = 0; f < T.n_ifc; f += 7) {
             const auto &X = T.ifc_X[f];

@@ -75,12 +75,16 @@ def test_operator_parity(dev, hh, oracle_problem, n_sub, level):
     ctx.close()
 
 
-@pytest.mark.parametrize("smoother", ["plain", "fused"])
+# launch shapes: (workgroup size, XCD-contiguous block order, nodes per thread)
+SHAPES = {"bs256-xcd-1npt": (256, 1, 1), "bs128-hw-4npt": (128, 0, 4), "bs512-xcd-4npt": (512, 1, 4)}
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
 @pytest.mark.parametrize("n_sub,level", [(1, 4), (2, 4), (2, 5), (3, 3), (1, 6)])
-def test_vcycle_iterates(dev, hh, oracle_problem, n_sub, level, smoother):
-    print(f"\n[vcycle parity] n_sub={n_sub} level={level} smoother={smoother}", flush=True)
+def test_vcycle_iterates(dev, hh, oracle_problem, n_sub, level, shape):
+    print(f"\n[vcycle parity] n_sub={n_sub} level={level} shape={shape}", flush=True)
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
-    ctx.set_smoother(smoother)
+    ctx.set_tuning(*SHAPES[shape])
     p = oracle_problem(n_sub, level)
     g = np.random.default_rng(7)
     b = g.standard_normal(p.ndof)
@@ -151,12 +155,12 @@ def test_fault_and_local_recovery(dev, hh, oracle_problem):
     ctx.close()
 
 
-@pytest.mark.parametrize("smoother", ["plain", "fused"])
-def test_dirichlet_dirichlet_recovery(dev, hh, oracle_problem, smoother):
+@pytest.mark.parametrize("shape", ["bs256-xcd-1npt", "bs128-hw-4npt"])
+def test_dirichlet_dirichlet_recovery(dev, hh, oracle_problem, shape):
     n_sub, level = 2, 5
-    print(f"\n[recover_dd] smoother={smoother}", flush=True)
+    print(f"\n[recover_dd] shape={shape}", flush=True)
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
-    ctx.set_smoother(smoother)
+    ctx.set_tuning(*SHAPES[shape])
     p = oracle_problem(n_sub, level)
     b = inputs.uniform_load(n_sub, level, seed=1)
     ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
@@ -177,14 +181,14 @@ def test_dirichlet_dirichlet_recovery(dev, hh, oracle_problem, smoother):
     ctx.close()
 
 
-@pytest.mark.parametrize("smoother", ["plain", "fused"])
-def test_mixed_precision(dev, hh, oracle_problem, smoother):
+@pytest.mark.parametrize("shape", ["bs256-xcd-1npt", "bs512-xcd-4npt"])
+def test_mixed_precision(dev, hh, oracle_problem, shape):
     n_sub, level = 2, 5
-    print(f"\n[mixed] smoother={smoother}", flush=True)
+    print(f"\n[mixed] shape={shape}", flush=True)
     p = oracle_problem(n_sub, level)
     b = inputs.uniform_load(n_sub, level, seed=0)
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level, precision="mixed")
-    ctx.set_smoother(smoother)
+    ctx.set_tuning(*SHAPES[shape])
     ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
     # first refinement step equals the oracle's FP32 step to FP32 rounding
     ctx.vcycle(1)
@@ -212,7 +216,7 @@ def test_variable_coefficient_parity(dev, hh):
     assert rel(N(hh.debug_op(ctx, 6, 2, T(bc, dev))), p.coarse_solve(bc)[0]) < 1e-12
     ctx.close()
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
-    ctx.set_smoother("fused")
+    ctx.set_tuning(*SHAPES["bs128-hw-4npt"])
     ctx.set_coeff(T(k, dev))
     ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
     ctx.vcycle(2)
