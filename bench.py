@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "colour_pass_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "colour_pass_fp64_l7_48tets_traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -36,10 +36,13 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(launch_dofs: int):
-    """HBM bytes per launch of the colour pass from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
-    None when there is no summary for the current kernel source."""
+def measured_traffic(n_sub: int, level: int):
+    """HBM bytes per launch of the finest-level colour pass from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
+    by what the counter reads for copy kernels of known size), or None when the
+    summary is not for this workload or not for the current kernel source."""
+    if (n_sub, level) != (2, 7):
+        return None
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -47,8 +50,8 @@ def measured_traffic(launch_dofs: int):
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    kib = (t["fetch_kib_per_dispatch"] + t["write_kib_per_dispatch"]) * t.get("copy_scale", 1.0)
-    return kib * 1024.0
+    kib = t["fetch_kib_per_dispatch"] * t["fetch_scale"] + t["write_kib_per_dispatch"] * t["write_scale"]
+    return round(kib * 1024.0)
 
 
 def run_job(hh, torch, ctx, f_dev, fault_tet, k_f=5, n_rec=3, rtol=1e-8, max_cycles=60):
@@ -100,7 +103,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay captured graphs (disables kernel timing)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run one device copy of 1 GiB first (reference for HBM byte counters)")
+                    help="run two 1 GiB device copies first (runtime memcpy and an elementwise kernel): "
+                         "references of known size for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -117,7 +121,8 @@ def main():
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        dst.copy_(src)                      # runtime copy kernel: reads 1 GiB, writes 1 GiB
+        torch.mul(src, 2.0, out=dst)        # elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
     f_dev = torch.from_numpy(inputs.sine_source(n_sub, level)).to(dev)
@@ -165,7 +170,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(ctx.n_dofs),
+            "traffic": measured_traffic(n_sub, level),
             "launches": launches,
             "mean_launch_ms": round(mean_ms, 5),
             "algorithmic_bytes_per_launch": alg_bytes,
