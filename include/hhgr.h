@@ -166,9 +166,21 @@ int hhgr_mass_apply(hhgr_ctx *ctx, const double *dev_x, double *dev_y);
 
 /* Batched solves: independent contexts (each with its own workspace and
  * right-hand side) run their V-cycles as concurrent branches of captured HIP
- * graphs on hip_stream; every member stops at its own tolerance.  The batch
- * borrows the contexts.  reps: one report per member (may be NULL). */
+ * graphs on hip_stream, one graph launch per step of all members; every
+ * member stops at its own tolerance.  The batch borrows the contexts (each at
+ * most once).  reps: one report per member (may be NULL).
+ *
+ * hhgr_batch_arm_dd arms a Dirichlet-Dirichlet recovery (Sec. 4.2, Alg. 1)
+ * of the listed faulty tetrahedra of one member (after hhgr_inject_fault on
+ * them) for the next hhgr_batch_run: its first max(n_intact, 1) steps are
+ * intact-side cycles with the faulty closures frozen as Dirichlet data, and
+ * its n_local local cycles run on a stream of their own beside the first
+ * step's graph launch, concurrently with every other member's work; the
+ * member then goes on with global cycles.  Intact-side cycles count as cycles and their history
+ * entries are the intact part's residual; with n_intact = 0 the first step
+ * (local cycles only) is not counted.  Same argument rules as hhgr_recover_dd. */
 int hhgr_batch_create(hhgr_ctx **ctxs, int n, void *hip_stream, hhgr_batch **out);
+int hhgr_batch_arm_dd(hhgr_batch *batch, int member, const int *tets, int n_tets, int n_intact, int n_local);
 int hhgr_batch_run(hhgr_batch *batch, double rel_tol, int max_cycles, hhgr_report *reps);
 void hhgr_batch_destroy(hhgr_batch *batch);
 

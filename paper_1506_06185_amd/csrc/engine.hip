@@ -9,7 +9,10 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <sstream>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -115,7 +118,8 @@ using namespace hhgr;
 
 struct hhgr_ctx {
     hhgr_desc d{};
-    Topology topo;
+    std::shared_ptr<const Topology> topo_hold;  // shared by contexts of the same mesh and levels
+    const Topology *topo = nullptr;
     std::vector<LevelDev> lev;
     int L = 0, Lc = 0, n_tets = 0;
     long long n_dofs = 0, n_elems = 0;
@@ -152,15 +156,25 @@ struct hhgr_ctx {
     size_t ws_bytes = 0;
 };
 
+// a Dirichlet-Dirichlet recovery armed on a batch member
+struct BatchDD {
+    bool armed = false;
+    std::vector<int> tets;
+    int n_intact = 0, n_local = 0;
+    int step = 0;  // steps of the recovery done
+};
+
 struct hhgr_batch {
     std::vector<hhgr_ctx *> ctx;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
-    std::vector<hipStream_t> branch;
-    std::vector<hipEvent_t> ev;
+    std::vector<hipStream_t> branch, branch2;  // per member: main branch, local-recovery branch
+    std::vector<hipEvent_t> ev;                // [0] fork, [1 + q] member join
+    std::vector<hipEvent_t> evl;               // [2q] local fork, [2q + 1] local join
+    std::vector<BatchDD> dd;
     hipGraphExec_t gexec = nullptr;
-    std::vector<int> active_in_graph;
-    double *hnorm = nullptr;  // pinned, one per member
+    std::vector<int> sig_in_graph;  // (member, mode) pairs the graph was captured for
+    double *hnorm = nullptr;        // pinned, one per member
 };
 
 namespace hhgr {
@@ -170,7 +184,7 @@ namespace {
 // layout of the workspace (sizing and carving share this code)
 // ----------------------------------------------------------------------------
 void carve(hhgr_ctx &c, Carver &cv) {
-    const Topology &tp = c.topo;
+    const Topology &tp = *c.topo;
     const int nf = std::max(c.d.max_faults, 1);
     c.lev.assign(c.L + 1, LevelDev());
     int max_blocks = 0;
@@ -271,6 +285,31 @@ void carve(hhgr_ctx &c, Carver &cv) {
         c.user_u = cv.take<double>(c.n_dofs);
         c.user_l = cv.take<double>(c.n_dofs);
     }
+}
+
+// host topologies are immutable after construction and shared by every
+// context of the same (n_sub, level, coarse_level); the cache keeps the most
+// recent few
+std::string get_topology(int n_sub, int L, int Lc, std::shared_ptr<const Topology> &out) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::tuple<int, int, int>, std::shared_ptr<const Topology>>> cache;
+    const auto key = std::make_tuple(n_sub, L, Lc);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto &e : cache)
+            if (e.first == key) {
+                out = e.second;
+                return "";
+            }
+    }
+    auto t = std::make_shared<Topology>();
+    std::string err = t->build(n_sub, L, Lc);
+    if (!err.empty()) return err;
+    std::lock_guard<std::mutex> g(mu);
+    cache.push_back({key, t});
+    if (cache.size() > 6) cache.erase(cache.begin());
+    out = t;
+    return "";
 }
 
 std::string check_desc(const hhgr_desc *d) {
@@ -602,6 +641,103 @@ int upload(hhgr_ctx &c, void *dst, const void *src, size_t bytes) {
     return HHGR_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Dirichlet-Dirichlet recovery (Sec. 4.2, Alg. 1 b)): the intact part cycles
+// with the closures of the faulty tetrahedra frozen as Dirichlet data while
+// the faulty tetrahedra run local cycles; the two share no unknowns
+// ----------------------------------------------------------------------------
+int dd_check(const hhgr_ctx &c, const int *tets, int n_tets, int n_intact, int n_local, std::vector<int> &ft) {
+    if (!tets || n_tets < 1 || n_tets > c.d.max_faults) return fail(HHGR_EINVAL, "need 1..max_faults tets");
+    if (n_intact < 0 || n_local < 0) return fail(HHGR_EINVAL, "negative cycle count");
+    if (c.Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
+    ft.assign(tets, tets + n_tets);
+    std::vector<char> isf(c.n_tets, 0);
+    for (int t : ft) {
+        if (t < 0 || t >= c.n_tets) return fail(HHGR_EINVAL, "tet id out of range");
+        if (isf[t]) return fail(HHGR_EINVAL, "duplicate tet id");
+        isf[t] = 1;
+    }
+    return HHGR_OK;
+}
+
+// masks of the intact volumes and of the frozen interface nodes on every
+// level, the local hierarchy of the faulty tetrahedra, their ghost copies
+// restored and interiors zeroed, coarse corrections zeroed; synchronises
+int dd_setup(hhgr_ctx &c, const std::vector<int> &ft) {
+    std::vector<char> isf(c.n_tets, 0);
+    for (int t : ft) isf[t] = 1;
+    std::vector<std::vector<VolDesc>> vds(c.L + 1);
+    std::vector<std::vector<unsigned char>> frz(c.L + 1);
+    int rc = HHGR_OK;
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        const TopoLevel &T = c.topo->lev[l];
+        for (int t = 0; t < c.n_tets; t++)
+            if (!isf[t]) vds[l].push_back(VolDesc{(long long)t * D.C_pad, (long long)t * D.C_pad, t, 0});
+        frz[l].assign(D.n_ifc, 0);
+        for (int t : ft)
+            for (int q = T.tg_ptr[t]; q < T.tg_ptr[t + 1]; q++) {
+                long long s = T.tg_src[q];
+                if (s >= T.ifc_base && s < T.ifc_base + T.n_ifc) frz[l][s - T.ifc_base] = 1;
+            }
+        D.n_masked = (int)vds[l].size();
+        rc = rc ? rc : upload(c, D.vd_masked, vds[l].data(), vds[l].size() * sizeof(VolDesc));
+        rc = rc ? rc : upload(c, D.frozen, frz[l].data(), frz[l].size());
+    }
+    const CoarseSystem &cs = c.topo->coarse;
+    std::vector<unsigned char> cf(cs.n, 0);
+    for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? (unsigned char)isf[cs.tet[q]] : frz[c.Lc][cs.ifc[q]];
+    rc = rc ? rc : upload(c, c.cfrozen, cf.data(), cf.size());
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c.stream));
+    set_loc(c, ft);
+    for (int t : ft) restore_tet(c, t, c.stream);
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        if (l < c.L) launch_fill<double>(c.stream, D.u, D.n_slots, 0.0);
+        if (c.mixed) launch_fill<float>(c.stream, D.u32, D.n_slots, 0.0f);
+    }
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return HHGR_OK;
+}
+
+// one intact-side step on the masked hierarchy (an FP64 cycle, or a mixed
+// refinement step); with norm (or in mixed mode) the squared norm of the
+// intact residual goes to dnorm[slot]
+void dd_intact_step(hhgr_ctx &c, hipStream_t s, bool first, bool norm, int slot) {
+    HView<double> V64 = global_view<double>(c, true, 0);
+    if (c.mixed) {
+        HView<float> V32 = global_view<float>(c, true, 0);
+        if (first) finest_residual<float>(c, V64, c.lev[c.L].b32, s, c.dnorm + slot);
+        step_mixed(c, V64, V32, s, slot);
+    } else {
+        vcycle<double>(c, V64, c.L, false, s);
+        if (norm) finest_residual<double>(c, V64, (double *)nullptr, s, c.dnorm + slot);
+    }
+}
+
+void dd_local(hhgr_ctx &c, int n_local, hipStream_t s) {
+    HView<double> VL = local_view(c, 1);
+    for (int q = 0; q < n_local; q++) vcycle<double>(c, VL, c.L, false, s);
+}
+
+// residual of the whole problem once a recovery is complete (and, in mixed
+// mode, the FP32 right-hand side of the next refinement step) into dnorm[0]
+void dd_final_norm(hhgr_ctx &c, hipStream_t s) {
+    if (c.mixed) {
+        prime_mixed(c, s);
+    } else {
+        HView<double> V = global_view<double>(c, false, 0);
+        finest_residual<double>(c, V, (double *)nullptr, s, c.dnorm);
+    }
+}
+
+// masks inactive again; later global cycles use the whole hierarchy
+void dd_end(hhgr_ctx &c) {
+    for (int l = c.Lc; l <= c.L; l++) c.lev[l].n_masked = 0;
+}
+
 }  // namespace
 }  // namespace hhgr
 
@@ -638,8 +774,9 @@ int hhgr_workspace_bytes(const hhgr_desc *desc, size_t *bytes) {
     c.n_dofs = (N - 1) * (N - 1) * (N - 1);
     c.vk = desc->variable_coeff != 0;
     c.mixed = desc->precision == HHGR_MIXED;
-    std::string te = c.topo.build(desc->n_sub, c.L, c.Lc);
+    std::string te = get_topology(desc->n_sub, c.L, c.Lc, c.topo_hold);
     if (!te.empty()) return fail(HHGR_EINVAL, te);
+    c.topo = c.topo_hold.get();
     Carver cv;
     carve(c, cv);
     *bytes = cv.off + 256;
@@ -664,11 +801,12 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     c->vk = desc->variable_coeff != 0;
     c->mixed = desc->precision == HHGR_MIXED;
     c->stream = (hipStream_t)hip_stream;
-    std::string te = c->topo.build(desc->n_sub, c->L, c->Lc);
+    std::string te = get_topology(desc->n_sub, c->L, c->Lc, c->topo_hold);
     if (!te.empty()) {
         delete c;
         return fail(HHGR_EINVAL, te);
     }
+    c->topo = c->topo_hold.get();
     Carver sz;
     carve(*c, sz);
     if (sz.off + 256 > ws_bytes) {
@@ -693,7 +831,7 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     if (hipHostMalloc((void **)&c->hnorm, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return bail(fail(HHGR_EHIP, "pinned host allocation"));
 
-    const Topology &tp = c->topo;
+    const Topology &tp = *c->topo;
     // host-side staging of all tables; kept alive until the final synchronise
     std::vector<std::vector<VolDesc>> vd_store;
     std::vector<std::vector<int4>> rown_store;
@@ -981,72 +1119,22 @@ int hhgr_recover_local(hhgr_ctx *c, int tet, int n_cycles, double *local_rel) {
 int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int n_local) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (!tets || n_tets < 1 || n_tets > c->d.max_faults) return fail(HHGR_EINVAL, "need 1..max_faults tets");
-    if (n_intact < 0 || n_local < 0) return fail(HHGR_EINVAL, "negative cycle count");
-    if (c->Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
-    std::vector<int> ft(tets, tets + n_tets);
-    std::vector<char> isf(c->n_tets, 0);
-    for (int t : ft) {
-        if (t < 0 || t >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
-        if (isf[t]) return fail(HHGR_EINVAL, "duplicate tet id");
-        isf[t] = 1;
-    }
-    invalidate_graph(*c);
-    // masks: intact volumes, frozen interface nodes (closures of faulty tets)
-    std::vector<std::vector<VolDesc>> vds(c->L + 1);
-    std::vector<std::vector<unsigned char>> frz(c->L + 1);
-    for (int l = c->Lc; l <= c->L; l++) {
-        LevelDev &D = c->lev[l];
-        const TopoLevel &T = c->topo.lev[l];
-        for (int t = 0; t < c->n_tets; t++)
-            if (!isf[t]) vds[l].push_back(VolDesc{(long long)t * D.C_pad, (long long)t * D.C_pad, t, 0});
-        frz[l].assign(D.n_ifc, 0);
-        for (int t : ft)
-            for (int q = T.tg_ptr[t]; q < T.tg_ptr[t + 1]; q++) {
-                long long s = T.tg_src[q];
-                if (s >= T.ifc_base && s < T.ifc_base + T.n_ifc) frz[l][s - T.ifc_base] = 1;
-            }
-        D.n_masked = (int)vds[l].size();
-        rc = upload(*c, D.vd_masked, vds[l].data(), vds[l].size() * sizeof(VolDesc));
-        if (rc) return rc;
-        rc = upload(*c, D.frozen, frz[l].data(), frz[l].size());
-        if (rc) return rc;
-    }
-    const CoarseSystem &cs = c->topo.coarse;
-    std::vector<unsigned char> cf(cs.n, 0);
-    for (int q = 0; q < cs.n; q++)
-        cf[q] = cs.is_vol[q] ? (unsigned char)isf[cs.tet[q]] : frz[c->Lc][cs.ifc[q]];
-    rc = upload(*c, c->cfrozen, cf.data(), cf.size());
+    std::vector<int> ft;
+    rc = dd_check(*c, tets, n_tets, n_intact, n_local, ft);
     if (rc) return rc;
-    HIPCHK(hipStreamSynchronize(c->stream));
-    set_loc(*c, ft);
-    for (int t : ft) restore_tet(*c, t, c->stream);
-    // corrections of the masked cycles start from zero everywhere below the finest level
-    for (int l = c->Lc; l <= c->L; l++) {
-        LevelDev &D = c->lev[l];
-        if (l < c->L) launch_fill<double>(c->stream, D.u, D.n_slots, 0.0);
-        if (c->mixed) launch_fill<float>(c->stream, D.u32, D.n_slots, 0.0f);
-    }
+    invalidate_graph(*c);
+    rc = dd_setup(*c, ft);
+    if (rc) return rc;
     HIPCHK(hipEventRecord(c->ev_fork, c->stream));
     HIPCHK(hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
-    // intact side on the main stream
-    HView<double> V64 = global_view<double>(*c, true, 0);
-    if (c->mixed) {
-        HView<float> V32 = global_view<float>(*c, true, 0);
-        finest_residual<float>(*c, V64, c->lev[c->L].b32, c->stream, c->dnorm + 4);
-        for (int q = 0; q < n_intact; q++) step_mixed(*c, V64, V32, c->stream, 4);
-    } else {
-        for (int q = 0; q < n_intact; q++) vcycle<double>(*c, V64, c->L, false, c->stream);
-    }
-    // faulty side on the second stream
-    HView<double> VL = local_view(*c, 1);
-    for (int q = 0; q < n_local; q++) vcycle<double>(*c, VL, c->L, false, c->stream2);
+    // intact side on the main stream, faulty side on the second stream
+    for (int q = 0; q < n_intact; q++) dd_intact_step(*c, c->stream, q == 0, false, 4);
+    dd_local(*c, n_local, c->stream2);
     HIPCHK(hipEventRecord(c->ev_join, c->stream2));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
     CHKLAUNCH();
     HIPCHK(hipStreamSynchronize(c->stream));
-    // leave the masks inactive and the coarse corrections consistent for global cycles
-    for (int l = c->Lc; l <= c->L; l++) c->lev[l].n_masked = 0;
+    dd_end(*c);
     return HHGR_OK;
 }
 
@@ -1346,32 +1434,33 @@ int hhgr_batch_create(hhgr_ctx **ctxs, int n, void *hip_stream, hhgr_batch **out
     if (!out) return fail(HHGR_EINVAL, "null output");
     *out = nullptr;
     if (!ctxs || n < 1) return fail(HHGR_EINVAL, "need at least one member");
-    for (int q = 0; q < n; q++)
+    for (int q = 0; q < n; q++) {
         if (!ctxs[q]) return fail(HHGR_EINVAL, "null member");
+        for (int p = 0; p < q; p++)
+            if (ctxs[p] == ctxs[q]) return fail(HHGR_EINVAL, "a context appears twice in the batch");
+    }
     hhgr_batch *b = new hhgr_batch();
     b->ctx.assign(ctxs, ctxs + n);
     b->stream = (hipStream_t)hip_stream;
     b->branch.resize(n);
-    b->ev.resize(2 * n + 1);
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    b->branch2.resize(n);
+    b->ev.resize(n + 1);
+    b->evl.resize(2 * n);
+    b->dd.resize(n);
+    auto bail = [&](const char *what) {
         hhgr_batch_destroy(b);
-        return fail(HHGR_EHIP, "stream create");
-    }
-    for (int q = 0; q < n; q++) {
-        if (hipStreamCreateWithFlags(&b->branch[q], hipStreamNonBlocking) != hipSuccess) {
-            hhgr_batch_destroy(b);
-            return fail(HHGR_EHIP, "stream create");
-        }
-    }
-    for (auto &e : b->ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            hhgr_batch_destroy(b);
-            return fail(HHGR_EHIP, "event create");
-        }
-    if (hipHostMalloc((void **)&b->hnorm, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
-        hhgr_batch_destroy(b);
-        return fail(HHGR_EHIP, "pinned host allocation");
-    }
+        return fail(HHGR_EHIP, what);
+    };
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return bail("stream create");
+    for (int q = 0; q < n; q++)
+        if (hipStreamCreateWithFlags(&b->branch[q], hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&b->branch2[q], hipStreamNonBlocking) != hipSuccess)
+            return bail("stream create");
+    for (auto *evs : {&b->ev, &b->evl})
+        for (auto &e : *evs)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail("event create");
+    if (hipHostMalloc((void **)&b->hnorm, sizeof(double) * n, hipHostMallocDefault) != hipSuccess)
+        return bail("pinned host allocation");
     *out = b;
     return HHGR_OK;
 }
@@ -1380,25 +1469,55 @@ void hhgr_batch_destroy(hhgr_batch *b) {
     if (!b) return;
     if (b->stream) hipStreamSynchronize(b->stream);
     if (b->gexec) hipGraphExecDestroy(b->gexec);
-    for (auto s : b->branch)
-        if (s) hipStreamDestroy(s);
+    for (auto *ss : {&b->branch, &b->branch2})
+        for (auto s : *ss)
+            if (s) hipStreamDestroy(s);
     if (b->cap) hipStreamDestroy(b->cap);
-    for (auto e : b->ev)
-        if (e) hipEventDestroy(e);
+    for (auto *evs : {&b->ev, &b->evl})
+        for (auto e : *evs)
+            if (e) hipEventDestroy(e);
     if (b->hnorm) hipHostFree(b->hnorm);
     delete b;
 }
+
+int hhgr_batch_arm_dd(hhgr_batch *b, int member, const int *tets, int n_tets, int n_intact, int n_local) {
+    if (!b) return fail(HHGR_EINVAL, "null batch");
+    if (member < 0 || member >= (int)b->ctx.size()) return fail(HHGR_EINVAL, "member index out of range");
+    std::vector<int> ft;
+    int rc = dd_check(*b->ctx[member], tets, n_tets, n_intact, n_local, ft);
+    if (rc) return rc;
+    BatchDD &d = b->dd[member];
+    d.armed = true;
+    d.tets = ft;
+    d.n_intact = n_intact;
+    d.n_local = n_local;
+    d.step = 0;
+    return HHGR_OK;
+}
+
+// mode bits of a member in one batch step
+enum { kModeMasked = 1, kModeLocal = 2, kModeFinal = 4 };
 
 int hhgr_batch_run(hhgr_batch *b, double rel_tol, int max_cycles, hhgr_report *reps) {
     if (!b) return fail(HHGR_EINVAL, "null batch");
     const int n = (int)b->ctx.size();
     std::vector<double> rel(n, 0.0);
     std::vector<int> cyc(n, 0), active;
+    for (int q = 0; q < n; q++) {
+        int rc = check_ready(b->ctx[q]);
+        if (rc) return rc;
+    }
+    // armed recoveries: masks, local hierarchies, restored ghosts (eager, synchronous)
+    for (int q = 0; q < n; q++)
+        if (b->dd[q].armed) {
+            invalidate_graph(*b->ctx[q]);
+            int rc = dd_setup(*b->ctx[q], b->dd[q].tets);
+            if (rc) return rc;
+            b->dd[q].step = 0;
+        }
     // initial residuals (and FP32 right-hand sides of mixed members)
     for (int q = 0; q < n; q++) {
         hhgr_ctx *c = b->ctx[q];
-        int rc = check_ready(c);
-        if (rc) return rc;
         HView<double> V = global_view<double>(*c, false, 0);
         if (c->mixed)
             prime_mixed(*c, b->stream);
@@ -1408,29 +1527,53 @@ int hhgr_batch_run(hhgr_batch *b, double rel_tol, int max_cycles, hhgr_report *r
     }
     CHKLAUNCH();
     HIPCHK(hipStreamSynchronize(b->stream));
+    auto in_dd = [&](int q) { return b->dd[q].armed && b->dd[q].step < std::max(b->dd[q].n_intact, 1); };
     for (int q = 0; q < n; q++) {
         rel[q] = b->ctx[q]->bnorm > 0 ? std::sqrt(std::max(b->hnorm[q], 0.0)) / b->ctx[q]->bnorm : 0.0;
         if (reps && reps[q].history && reps[q].history_cap > 0) reps[q].history[0] = rel[q];
-        if (rel[q] > rel_tol && max_cycles > 0) active.push_back(q);
+        if ((rel[q] > rel_tol || in_dd(q)) && max_cycles > 0) active.push_back(q);
     }
     while (!active.empty()) {
-        if (active != b->active_in_graph || !b->gexec) {
+        // (member, mode) signature of this step; the graph is re-captured when it changes
+        std::vector<int> sig;
+        for (int q : active) {
+            int mode = 0;
+            if (in_dd(q)) {
+                const BatchDD &d = b->dd[q];
+                if (d.step < d.n_intact) mode |= kModeMasked;
+                if (d.step == 0) mode |= kModeLocal;
+                if (d.step == std::max(d.n_intact, 1) - 1) mode |= kModeFinal;
+            }
+            sig.push_back(q);
+            sig.push_back(mode);
+        }
+        // the step graph holds every member's cycle (and a recovering member's
+        // intact-side cycle); local recovery cycles run beside the graph launch
+        // on the member's second stream, forked and joined by events
+        auto in_graph = [](int mode) { return mode == 0 || (mode & kModeMasked) || !(mode & kModeLocal); };
+        if (sig != b->sig_in_graph || !b->gexec) {
             if (b->gexec) hipGraphExecDestroy(b->gexec);
             b->gexec = nullptr;
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
             HIPCHK(hipEventRecord(b->ev[0], b->cap));
             for (size_t a = 0; a < active.size(); a++) {
-                const int q = active[a];
+                const int q = sig[2 * a], mode = sig[2 * a + 1];
+                if (!in_graph(mode)) continue;
                 hhgr_ctx *c = b->ctx[q];
                 hipStream_t s = b->branch[q];
                 hipStreamWaitEvent(s, b->ev[0], 0);
-                HView<double> V64 = global_view<double>(*c, false, 0);
-                if (c->mixed) {
-                    HView<float> V32 = global_view<float>(*c, false, 0);
-                    step_mixed(*c, V64, V32, s, 0);
+                if (mode == 0) {
+                    HView<double> V64 = global_view<double>(*c, false, 0);
+                    if (c->mixed) {
+                        HView<float> V32 = global_view<float>(*c, false, 0);
+                        step_mixed(*c, V64, V32, s, 0);
+                    } else {
+                        step_fp64(*c, V64, s, 0);
+                    }
                 } else {
-                    step_fp64(*c, V64, s, 0);
+                    if (mode & kModeMasked) dd_intact_step(*c, s, b->dd[q].step == 0, true, 0);
+                    if ((mode & kModeFinal) && !(mode & kModeLocal)) dd_final_norm(*c, s);
                 }
                 hipMemcpyAsync(b->hnorm + q, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, s);
                 hipEventRecord(b->ev[1 + q], s);
@@ -1441,19 +1584,58 @@ int hhgr_batch_run(hhgr_batch *b, double rel_tol, int max_cycles, hhgr_report *r
             ce = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
             hipGraphDestroy(g);
             if (ce != hipSuccess) return fail(HHGR_EHIP, std::string("batch instantiate: ") + hipGetErrorString(ce));
-            b->active_in_graph = active;
+            b->sig_in_graph = sig;
+        }
+        // local cycles of recoveries starting now, concurrent with the graph
+        for (size_t a = 0; a < active.size(); a++) {
+            const int q = sig[2 * a], mode = sig[2 * a + 1];
+            if (!(mode & kModeLocal)) continue;
+            HIPCHK(hipEventRecord(b->evl[2 * q], b->stream));
+            HIPCHK(hipStreamWaitEvent(b->branch2[q], b->evl[2 * q], 0));
+            dd_local(*b->ctx[q], b->dd[q].n_local, b->branch2[q]);
+            HIPCHK(hipEventRecord(b->evl[2 * q + 1], b->branch2[q]));
         }
         HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        for (size_t a = 0; a < active.size(); a++) {
+            const int q = sig[2 * a], mode = sig[2 * a + 1];
+            if (!(mode & kModeLocal)) continue;
+            HIPCHK(hipStreamWaitEvent(b->stream, b->evl[2 * q + 1], 0));
+            if (mode & kModeFinal) {
+                hhgr_ctx *c = b->ctx[q];
+                dd_final_norm(*c, b->stream);
+                HIPCHK(hipMemcpyAsync(b->hnorm + q, c->dnorm, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+            }
+        }
+        CHKLAUNCH();
         HIPCHK(hipStreamSynchronize(b->stream));
         std::vector<int> next;
-        for (int q : active) {
-            cyc[q]++;
+        for (size_t a = 0; a < active.size(); a++) {
+            const int q = sig[2 * a], mode = sig[2 * a + 1];
+            // during a recovery the norm is that of the intact part's residual;
+            // a step without an intact cycle (local recovery only) is not a cycle
             rel[q] = b->ctx[q]->bnorm > 0 ? std::sqrt(std::max(b->hnorm[q], 0.0)) / b->ctx[q]->bnorm : 0.0;
-            if (reps && reps[q].history && cyc[q] < reps[q].history_cap) reps[q].history[cyc[q]] = rel[q];
-            if (rel[q] > rel_tol && cyc[q] < max_cycles && std::isfinite(rel[q])) next.push_back(q);
+            if (mode == 0 || (mode & kModeMasked)) {
+                cyc[q]++;
+                if (reps && reps[q].history && cyc[q] < reps[q].history_cap) reps[q].history[cyc[q]] = rel[q];
+            }
+            if (mode != 0) {
+                b->dd[q].step++;
+                if (mode & kModeFinal) {
+                    dd_end(*b->ctx[q]);
+                    b->dd[q].armed = false;
+                }
+            }
+            const bool more = in_dd(q) || (rel[q] > rel_tol && std::isfinite(rel[q]));
+            if (more && (cyc[q] < max_cycles || in_dd(q))) next.push_back(q);
         }
         active.swap(next);
     }
+    // a recovery cut short by max_cycles: masks off, the member stays as it is
+    for (int q = 0; q < n; q++)
+        if (b->dd[q].armed) {
+            dd_end(*b->ctx[q]);
+            b->dd[q].armed = false;
+        }
     bool all = true;
     for (int q = 0; q < n; q++) {
         if (reps) {

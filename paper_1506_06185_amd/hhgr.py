@@ -73,6 +73,7 @@ def lib():
         "hhgr_mass_apply": (C.c_int, [_vp, _vp, _vp]),
         "hhgr_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int, _vp, C.POINTER(_vp)]),
         "hhgr_batch_run": (C.c_int, [_vp, C.c_double, C.c_int, C.POINTER(Report)]),
+        "hhgr_batch_arm_dd": (C.c_int, [_vp, C.c_int, _ip, C.c_int, C.c_int, C.c_int]),
         "hhgr_batch_destroy": (None, [_vp]),
         "hhgr_set_graph": (C.c_int, [_vp, C.c_int]),
         "hhgr_tuning_info": (C.c_int, [_vp, C.c_int, _ip, _ip, _ip]),
@@ -94,7 +95,7 @@ def lib():
 EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_destroy", "hhgr_sizes",
             "hhgr_set_rhs", "hhgr_set_coeff", "hhgr_set_solution", "hhgr_get_solution", "hhgr_vcycle",
             "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_adjoint_grad",
-            "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_set_graph",
+            "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_last_error")
 
@@ -272,6 +273,12 @@ class Batch:
         h = _vp()
         _check(lib().hhgr_batch_create(arr, len(self.contexts), self.stream.cuda_stream, C.byref(h)))
         self._h = h
+
+    def arm_dd(self, member: int, tets, n_intact: int, n_local: int):
+        """Arm a Dirichlet-Dirichlet recovery of faulty tets of one member for the next run."""
+        tets = [int(t) for t in tets]
+        arr = (C.c_int * len(tets))(*tets)
+        _check(lib().hhgr_batch_arm_dd(self._h, int(member), arr, len(tets), int(n_intact), int(n_local)))
 
     def run(self, rel_tol: float = 1e-8, max_cycles: int = 100, raise_on_noconv: bool = True):
         import numpy as np

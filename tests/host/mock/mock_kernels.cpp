@@ -1,0 +1,121 @@
+// Host stand-ins for the kernel launchers of kernels.hpp (test use only): the
+// engine's host logic runs on the CPU while the numerical kernels are skipped.
+// Fills, casts, ghost refreshes and reductions are done for real (cheaply) so
+// that the engine sees consistent scalars; residual kernels report the
+// squared norm g_mock_res2 (spread over their blocks).
+#include <cstring>
+
+#include "../../../paper_1506_06185_amd/csrc/kernels.hpp"
+
+double g_mock_res2 = 0.0;
+
+namespace hhgr {
+
+static long long list_blocks_of(const VolGeom &g, int cpb) {
+    const long long per = ((long long)g.nlist + (long long)g.bs * cpb - 1) / ((long long)g.bs * cpb);
+    return per * g.nvol;
+}
+static int ifc_blocks_of(const IfcGeom &ig, int bs) {
+    const int n = ig.i1 - ig.i0;
+    if (n <= 0) return 0;
+    return (((n + bs - 1) / bs) + 7) & ~7;
+}
+
+template <typename T>
+void launch_colour(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
+                   double, bool, bool) {}
+template <typename T, typename TO>
+int launch_residual(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const T *, const T *, const Weights<T> &, bool,
+                    double, TO *, double *partial) {
+    const long long nb = ifc_blocks_of(ig, vg.bs) + list_blocks_of(vg, vg.cpb);
+    if (partial)
+        for (long long q = 0; q < nb; q++) partial[q] = q == 0 ? g_mock_res2 : 0.0;
+    return (int)nb;
+}
+template <typename T>
+void launch_restrict(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, const IfcGeom &, const int *, const T *,
+                     T *) {}
+template <typename T>
+void launch_prolong(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, int, const IfcGeom &, const int *,
+                    const T *, T *) {}
+template <typename T>
+void launch_coarse_pcg(hipStream_t, int, const long long *, const int *, const double *, const unsigned char *, const T *,
+                       T *, const int *, const int *, double, int, int *iters) {
+    if (iters) *iters = 0;
+}
+template <typename T>
+void launch_local_coarse(hipStream_t, const VolDesc *, int, int4, const T *, T *, const Weights<T> &, bool, double) {}
+void launch_reduce(hipStream_t, const double *partial, int n, double *out) {
+    double s = 0.0;
+    for (int q = 0; q < n; q++) s += partial[q];
+    out[0] = s;
+}
+template <typename T>
+void launch_fill(hipStream_t, T *p, long long n, T v) {
+    for (long long q = 0; q < n; q++) p[q] = v;
+}
+template <typename T>
+void launch_user_to_slots(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &, const int *,
+                          const double *, T *) {}
+template <typename T>
+void launch_slots_to_user(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &, const int *, const T *,
+                          double *) {}
+void launch_mass(hipStream_t, const VolGeom &, const IfcGeom &, const int *, const double *, double *, double) {}
+void launch_update_add(hipStream_t, const VolDesc *, int, long long, const IfcGeom &, double *, const float *) {}
+template <typename T>
+void launch_ghost_refresh(hipStream_t, const int *dst, const int *src, int n, T *u) {
+    for (int q = 0; q < n; q++) u[dst[q]] = u[src[q]];
+}
+template <typename TI, typename TO>
+void launch_cast(hipStream_t, const TI *in, TO *out, long long n) {
+    for (long long q = 0; q < n; q++) out[q] = (TO)in[q];
+}
+void launch_coarsen_k(hipStream_t, const double *, int, double *, int) {}
+void launch_vol_weights(hipStream_t, const VolGeom &, const int *, int, int, double, const double *, double *, double *,
+                        double *) {}
+void launch_ifc_weights(hipStream_t, int, const int *, int, double, const double *, double *) {}
+void launch_coarse_vals(hipStream_t, int, const int *, const int *, int, double, const double *, double *) {}
+void launch_grad_k(hipStream_t, const double *, const double *, int, double, double *) {}
+
+template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
+                                    const Weights<double> &, bool, double, double, bool, bool);
+template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                   const Weights<float> &, bool, double, double, bool, bool);
+template int launch_residual<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
+                                             const double *, const Weights<double> &, bool, double, double *, double *);
+template int launch_residual<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
+                                            const double *, const Weights<double> &, bool, double, float *, double *);
+template int launch_residual<float, float>(hipStream_t, const VolGeom &, const IfcGeom &, const float *, const float *,
+                                           const Weights<float> &, bool, double, float *, double *);
+template void launch_restrict<double>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, const IfcGeom &,
+                                      const int *, const double *, double *);
+template void launch_restrict<float>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, const IfcGeom &,
+                                     const int *, const float *, float *);
+template void launch_prolong<double>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, int, const IfcGeom &,
+                                     const int *, const double *, double *);
+template void launch_prolong<float>(hipStream_t, const VolGeom &, const VolDesc *, const int2 *, int, const IfcGeom &,
+                                    const int *, const float *, float *);
+template void launch_coarse_pcg<double>(hipStream_t, int, const long long *, const int *, const double *,
+                                        const unsigned char *, const double *, double *, const int *, const int *,
+                                        double, int, int *);
+template void launch_coarse_pcg<float>(hipStream_t, int, const long long *, const int *, const double *,
+                                       const unsigned char *, const float *, float *, const int *, const int *, double,
+                                       int, int *);
+template void launch_local_coarse<double>(hipStream_t, const VolDesc *, int, int4, const double *, double *,
+                                          const Weights<double> &, bool, double);
+template void launch_local_coarse<float>(hipStream_t, const VolDesc *, int, int4, const float *, float *,
+                                         const Weights<float> &, bool, double);
+template void launch_fill<double>(hipStream_t, double *, long long, double);
+template void launch_fill<float>(hipStream_t, float *, long long, float);
+template void launch_fill<unsigned char>(hipStream_t, unsigned char *, long long, unsigned char);
+template void launch_fill<unsigned int>(hipStream_t, unsigned int *, long long, unsigned int);
+template void launch_user_to_slots<double>(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &,
+                                           const int *, const double *, double *);
+template void launch_slots_to_user<double>(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &,
+                                           const int *, const double *, double *);
+template void launch_ghost_refresh<double>(hipStream_t, const int *, const int *, int, double *);
+template void launch_ghost_refresh<float>(hipStream_t, const int *, const int *, int, float *);
+template void launch_cast<double, float>(hipStream_t, const double *, float *, long long);
+template void launch_cast<float, double>(hipStream_t, const float *, double *, long long);
+
+}  // namespace hhgr

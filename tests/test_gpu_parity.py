@@ -284,3 +284,49 @@ def test_graph_replay_matches_eager(dev, hh):
         res.append(N(ctx.get_solution()))
         ctx.close()
     assert rel(res[1], res[0]) < 1e-14
+
+
+def test_batch_with_dd_recovery(dev, hh, oracle_problem):
+    """Faulty members recover by Dirichlet-Dirichlet inside the batch graphs,
+    concurrently with the other members; iterates equal the sequential oracle
+    (intact cycles, then the local cycles, then global cycles)."""
+    print("\n[batch + dd]", flush=True)
+    cases = [(2, 5), (2, 4), (1, 5)]
+    pre = [4, 0, 3]
+    faults = {0: ([int(t) for t in inputs.batch_faults(2, 2, seed=3)], 2, 4), 2: ([int(inputs.fault_tet(1, seed=5))], 0, 3)}
+    ctxs, bs = [], []
+    for q, (n_sub, level) in enumerate(cases):
+        c = hh.Context(device=dev, n_sub=n_sub, level=level)
+        b = inputs.uniform_load(n_sub, level, seed=10 + q)
+        c.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+        if pre[q]:
+            c.vcycle(pre[q])
+        for t in faults.get(q, ([], 0, 0))[0]:
+            c.inject_fault(t)
+        ctxs.append(c)
+        bs.append(b)
+    batch = hh.Batch(ctxs)
+    for q, (tets, n_i, n_f) in faults.items():
+        batch.arm_dd(q, tets, n_i, n_f)
+    out = batch.run(1e-10, 60)
+    for q, ((n_sub, level), c, b) in enumerate(zip(cases, ctxs, bs)):
+        p = oracle_problem(n_sub, level)
+        bn = float(np.linalg.norm(b))
+        u, _, _ = p.solve(b, rtol=0.0, max_cycles=pre[q]) if pre[q] else (np.zeros_like(b), 0, None)
+        done = 0
+        if q in faults:
+            tets, n_i, n_f = faults[q]
+            for t in tets:
+                u = p.inject_fault(t, u)
+            if n_i:
+                u = p.dd_intact(tets, u, b, n_i)
+            u, _ = p.recover_local(tets, u, b, n_cycles=n_f)
+            done = n_i
+        u, co, _ = p.solve(b, u0=u, rtol=1e-10, max_cycles=60 - done, r0=bn)
+        cyc, rr, hist = out[q]
+        print(f"  member {q}: cycles {cyc} (oracle {done} + {co}), rel {rr:.3e}", flush=True)
+        assert cyc == done + co
+        assert rel(N(c.get_solution()), u) < 1e-12
+    batch.close()
+    for c in ctxs:
+        c.close()
