@@ -1,18 +1,29 @@
 """Benchmark: the fault-tolerant multigrid job on one MI355X.
 
-Workload (one step): Poisson -Laplace(u) = f on the unit cube, 2x2x2 subcubes x 6
-= 48 macro tetrahedra refined 7 times (257^3 grid, 16,581,375 unknowns), P1,
-f from u = sin(pi x) sin(pi y) sin(pi z), V(2,1) red-black SOR (omega 1.25),
-FP64.  From u = 0: 5 V-cycles, a fault zeroes the interior of one seeded macro
-tetrahedron, 3 local Dirichlet V-cycles recover it from the stored
-faces/edges/vertex, then global V-cycles continue to ||r|| <= 1e-8 ||b||.
+Headline workload (one step): Poisson -Laplace(u) = f on the unit cube, 2x2x2
+subcubes x 6 = 48 macro tetrahedra refined 7 times (257^3 grid, 16,581,375
+unknowns), P1, f from u = sin(pi x) sin(pi y) sin(pi z), V(2,1) red-black SOR
+(omega 1.25), FP64.  From u = 0: 5 V-cycles, a fault zeroes the interior of
+one seeded macro tetrahedron, 3 local Dirichlet V-cycles recover it from the
+stored faces/edges/vertex, then global V-cycles continue to ||r|| <= 1e-8 ||b||.
 
 value = unknowns x global V-cycles / step wall time (MDoF/s), so the fault
-and the recovery count against it; ms_per_step is the time to 1e-8.  The same
-job in mixed precision (FP32 cycle inside FP64 refinement) is reported under
-"mixed".  roofline: the finest-level FP64 volume colour-pass kernel, timed
-with HIP events on the stream it runs on during the timed steps.
-cpu_baseline: the CPU oracle's V-cycle rate on the same problem.
+and the recovery count against it; ms_per_step is the time to 1e-8.
+roofline: the finest-level FP64 colour pass, timed with HIP events on the
+stream it runs on during the timed steps.  cpu_baseline: the CPU oracle's
+V-cycle rate on the same problem.
+
+Further legs, each in its own object of the JSON line:
+  mixed     the same job in mixed precision (FP32 cycle inside FP64 refinement);
+  mixed_l8  level 8 (133,432,831 unknowns), load b ~ U[-1,1]: mixed refinement
+            against the FP64 solve of the same problem;
+  gradients level 7 with per-element log-normal k: forward solve, adjoint
+            gradients dJ/df and dJ/dk of J = 1/2 ||u - u_obs||^2, with an exact
+            identity and finite-difference checks;
+  batched   the level-7 problem with 2 faulty tetrahedra recovered by
+            Dirichlet-Dirichlet, beside 32 independent mixed-precision solves of
+            levels 5-7 (6 of them with a faulty tetrahedron recovered locally),
+            all as concurrent branches of captured HIP graphs.
 """
 from __future__ import annotations
 
@@ -21,6 +32,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +41,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "colour_pass_fp64_l7_48tets_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -66,13 +82,13 @@ def run_job(hh, torch, ctx, f_dev, fault_tet, k_f=5, n_rec=3, rtol=1e-8, max_cyc
 
 
 def cpu_baseline(n_sub, level, cycles=3):
+    import numpy as np
+
     import oracle
     from paper_1506_06185_amd import inputs
 
     p = oracle.Problem(n_sub, level)
     b = p.apply_M(inputs.sine_source(n_sub, level))
-    import numpy as np
-
     u = np.zeros_like(b)
     u, _ = p.vcycle(u, b)  # first touch of the work vectors
     t0 = time.perf_counter()
@@ -92,6 +108,179 @@ def cpu_baseline(n_sub, level, cycles=3):
     return res
 
 
+def leg_mixed_job(hh, torch, dev, n_sub, level, f_dev, t_fault, steps, warmup, graph, tune_cache):
+    cm = hh.Context(device=dev, n_sub=n_sub, level=level, precision="mixed")
+    cm.autotune(tune_cache)
+    if graph:
+        cm.set_graph(True)
+    for _ in range(warmup):
+        run_job(hh, torch, cm, f_dev, t_fault)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot, relm = 0, None
+    for _ in range(steps):
+        cyc, relm = run_job(hh, torch, cm, f_dev, t_fault)
+        tot += cyc
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    um = cm.get_solution()
+    cm.close()
+    # error against the FP64 solution of the same problem solved to its
+    # rounding floor (about 1e-12 relative residual at this size)
+    c64 = hh.Context(device=dev, n_sub=n_sub, level=level)
+    c64.set_rhs(f_dev, hh.HHGR_RHS_NODAL_F)
+    c64.solve(1e-12, 40, raise_on_noconv=False)
+    u64 = c64.get_solution()
+    c64.close()
+    err = float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64))
+    return {
+        "value": round(um.numel() * tot / dtm / 1e6, 1),
+        "unit": "MDoF/s",
+        "ms_per_step": round(1e3 * dtm / steps, 3),
+        "refinement_steps_per_job": tot // steps,
+        "rel_error_vs_fp64_solution": err,
+        "rel_res": relm,
+    }
+
+
+def leg_mixed_l8(hh, torch, dev, tune_cache, n_sub=2, level=8):
+    """Mixed-precision refinement on 133 M unknowns against the FP64 solve."""
+    from paper_1506_06185_amd import inputs
+
+    b = torch.from_numpy(inputs.uniform_load(n_sub, level, seed=0)).to(dev)
+    out = {"workload": f"n_sub={n_sub} level={level}, load b ~ U[-1,1] (seed 0)", "unknowns": int(b.numel())}
+    sols = {}
+    for prec in ("mixed", "fp64"):
+        c = hh.Context(device=dev, n_sub=n_sub, level=level, precision=prec)
+        c.autotune(tune_cache)
+        c.set_rhs(b, hh.HHGR_RHS_LOAD)
+        c.vcycle(1)  # warm-up step
+        c.set_solution(torch.zeros_like(b))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc, _, _ = c.solve(1e-8, 60)
+        torch.cuda.synchronize()
+        dt8 = time.perf_counter() - t0
+        more, rel2, _ = c.solve(1e-12 if prec == "fp64" else 1e-11, 60, raise_on_noconv=False)
+        out[prec] = {"time_to_1e8_s": round(dt8, 4), "cycles_to_1e8": cyc,
+                     "value": round(b.numel() * cyc / dt8 / 1e6, 1), "unit": "MDoF/s",
+                     "final_rel_res": rel2, "cycles_total": cyc + more}
+        sols[prec] = c.get_solution()
+        c.close()
+        log(f"mixed_l8 {prec}: {cyc} cycles to 1e-8 in {dt8:.3f} s")
+    um, u64 = sols["mixed"], sols["fp64"]
+    out["rel_error_mixed_vs_fp64"] = float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64))
+    return out
+
+
+def leg_gradients(hh, torch, dev, n_sub=2, level=7, n_dirs=2):
+    """Forward + adjoint on 100.7 M elements with per-element log-normal k."""
+    from paper_1506_06185_amd import inputs
+
+    k = torch.from_numpy(inputs.lognormal_k(n_sub, level, seed=0)).to(dev)
+    f = torch.from_numpy(inputs.sine_source(n_sub, level)).to(dev)
+    uobs = torch.from_numpy(inputs.gaussian_obs(n_sub, level, seed=0)).to(dev)
+    c = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
+    c.set_coeff(k)
+    c.autotune(None)
+
+    # this variable-coefficient problem reaches a rounding floor near 1.3e-12
+    tol = 1e-11
+
+    def forward(ff, kk):
+        c.set_coeff(kk)
+        c.set_rhs(ff, hh.HHGR_RHS_NODAL_F)
+        c.set_solution(torch.zeros_like(ff))
+        cyc, rr, _ = c.solve(tol, 100, raise_on_noconv=False)
+        return c.get_solution(), (cyc, rr)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, (cyc_f, rr_f) = forward(f, k)
+    dJdf, dJdk = c.adjoint_grad(u - uobs, rel_tol=tol, max_cycles=100)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # exact identity (A is linear in k): sum_T k_T dJ/dk_T = -lambda^T b = -f . dJ/df
+    lhs = float((k * dJdk).sum())
+    rhs = -float((f * dJdf).sum())
+    fd = []
+    df_dirs = inputs.fd_directions(f.numel(), n_dirs, seed=0)
+    dk_dirs = inputs.fd_directions(k.numel(), n_dirs, seed=0, offset=20)
+    # central differences with steps relative to the parameter's norm: J is
+    # quadratic in f (exact for any step), the k step's truncation error is ~1e-6
+    for name, dirs, fd_h in (("f", df_dirs, 1e-2), ("k", dk_dirs, 1e-3)):
+        step = fd_h * float(torch.linalg.norm(f if name == "f" else k))
+        for d in dirs:
+            dT = torch.from_numpy(d).to(dev)
+            if name == "f":
+                up, _ = forward(f + step * dT, k)
+                um, _ = forward(f - step * dT, k)
+                g = float((dJdf * dT).sum())
+            else:
+                up, _ = forward(f, k + step * dT)
+                um, _ = forward(f, k - step * dT)
+                g = float((dJdk * dT).sum())
+            # J(+) - J(-) = <u+ - u-, (u+ + u-)/2 - u_obs>, formed without cancellation in J
+            fdv = float(((up - um) * (0.5 * (up + um) - uobs)).sum()) / (2 * step)
+            fd.append({"param": name, "step_relative": fd_h, "adjoint": g, "finite_difference": fdv,
+                       "rel_diff": abs(fdv - g) / max(abs(g), 1e-300)})
+    c.close()
+    return {"workload": f"n_sub={n_sub} level={level}, {6 * (n_sub << level) ** 3} elements, k = exp(0.5 Z)",
+            "forward_cycles": cyc_f, "forward_rel_res": rr_f, "solve_tol": tol,
+            "forward_plus_adjoint_s": round(dt, 4),
+            "identity": {"sum_k_dJdk": lhs, "minus_f_dot_dJdf": rhs,
+                         "rel_err": abs(lhs - rhs) / max(abs(rhs), 1e-300)},
+            "fd_checks": fd}
+
+
+def leg_batched(hh, torch, dev, tune_cache, n_members=32, k_f=5):
+    """Global level-7 problem with a Dirichlet-Dirichlet recovery of 2 faulty
+    tets beside 32 independent solves (levels 5-7, 6 of them with a local
+    recovery), all mixed precision, as concurrent branches of graphs."""
+    from paper_1506_06185_amd import inputs
+
+    levels = [7] + [int(x) for x in inputs.batch_levels(n_members, seed=0)]
+    ctxs, rhs = [], []
+    for q, L in enumerate(levels):
+        c = hh.Context(device=dev, n_sub=2, level=L, precision="mixed")
+        c.autotune(tune_cache)
+        b = torch.from_numpy(inputs.sine_source(2, L) if q == 0 else inputs.uniform_load(2, L, seed=100 + q)).to(dev)
+        c.set_rhs(b, hh.HHGR_RHS_NODAL_F if q == 0 else hh.HHGR_RHS_LOAD)
+        ctxs.append(c)
+        rhs.append(b)
+    g_tets = [int(t) for t in inputs.batch_faults(2, 2, seed=0)]
+    m_faults = [(m + 1, t) for m, t in inputs.batch_member_faults(n_members, 6, 2, seed=0)]
+    batch = hh.Batch(ctxs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pre = batch.run(0.0, k_f, raise_on_noconv=False)  # k_f cycles of every member
+    for t in g_tets:
+        ctxs[0].inject_fault(t)
+    for m, t in m_faults:
+        ctxs[m].inject_fault(t)
+    batch.arm_dd(0, g_tets, 2, 4)
+    for m, t in m_faults:
+        batch.arm_dd(m, [t], 0, 3)
+    out = batch.run(1e-8, 60)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dof_cycles = sum(c.n_dofs * (p[0] + o[0]) for c, p, o in zip(ctxs, pre, out))
+    res = {
+        "members": len(ctxs),
+        "levels": {str(L): levels.count(L) for L in sorted(set(levels))},
+        "unknowns_total": sum(c.n_dofs for c in ctxs),
+        "global_faulty_tets": g_tets, "member_faults": m_faults,
+        "wall_s": round(dt, 4),
+        "value": round(dof_cycles / dt / 1e6, 1), "unit": "MDoF/s (all members, refinement steps)",
+        "global_cycles": pre[0][0] + out[0][0], "all_converged": all(o[1] <= 1e-8 for o in out),
+        "max_rel_res": max(o[1] for o in out),
+    }
+    batch.close()
+    for c in ctxs:
+        c.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +290,7 @@ def main():
     ap.add_argument("--level", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the level-8, gradient and batched legs")
     ap.add_argument("--graph", action="store_true", help="replay captured graphs (disables kernel timing)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run two 1 GiB device copies first (runtime memcpy and an elementwise kernel): "
@@ -118,6 +308,7 @@ def main():
 
     dev = torch.device("cuda:0")
     n_sub, level = args.n_sub, args.level
+    tune_cache = os.path.join(tempfile.gettempdir(), f"hhgr_tune_{os.getpid()}.txt")
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -128,11 +319,11 @@ def main():
     f_dev = torch.from_numpy(inputs.sine_source(n_sub, level)).to(dev)
     t_fault = inputs.fault_tet(n_sub, seed=0)
 
-    print(f"[bench] setup n_sub={n_sub} level={level}", file=sys.stderr, flush=True)
+    log(f"setup n_sub={n_sub} level={level}")
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
-    ctx.autotune(None)
+    ctx.autotune(tune_cache)
     tuning = ctx.tuning_info()
-    print(f"[bench] tuning (level: block size, xcd order, nodes per thread) {tuning}", file=sys.stderr, flush=True)
+    log(f"tuning (level: block size, xcd order, nodes per thread) {tuning}")
     if args.graph:
         ctx.set_graph(True)
     # fault-free cycle count for the cycle advantage, eq. (3)
@@ -141,7 +332,7 @@ def main():
 
     for w in range(args.warmup):
         run_job(hh, torch, ctx, f_dev, t_fault)
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        log(f"warmup {w + 1}/{args.warmup} done")
     if not args.graph:
         ctx.kernel_timing(True)
     torch.cuda.synchronize()
@@ -153,7 +344,7 @@ def main():
         total_cycles += cyc
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    log(f"timed {args.steps} steps in {dt:.3f} s")
     launches, mean_ms, alg_bytes = ctx.kernel_stats() if not args.graph else (0, 0.0, 0.0)
     ctx.kernel_timing(False)
     k_faulty = total_cycles // args.steps
@@ -179,44 +370,28 @@ def main():
 
     mixed = None
     if not args.no_mixed:
-        print("[bench] mixed precision leg", file=sys.stderr, flush=True)
-        cm = hh.Context(device=dev, n_sub=n_sub, level=level, precision="mixed")
-        cm.autotune(None)
-        if args.graph:
-            cm.set_graph(True)
-        for w in range(args.warmup):
-            run_job(hh, torch, cm, f_dev, t_fault)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tot = 0
-        for s in range(args.steps):
-            cyc, relm = run_job(hh, torch, cm, f_dev, t_fault)
-            tot += cyc
-        torch.cuda.synchronize()
-        dtm = time.perf_counter() - t0
-        um = cm.get_solution()
-        cm.close()
-        # error against the FP64 solution of the same problem solved to its
-        # rounding floor (about 1e-12 relative residual at this size)
-        c64 = hh.Context(device=dev, n_sub=n_sub, level=level)
-        c64.set_rhs(f_dev, hh.HHGR_RHS_NODAL_F)
-        c64.solve(1e-12, 40, raise_on_noconv=False)
-        u64 = c64.get_solution()
-        c64.close()
-        err = float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64))
-        mixed = {
-            "value": round(um.numel() * tot / dtm / 1e6, 1),
-            "unit": "MDoF/s",
-            "ms_per_step": round(1e3 * dtm / args.steps, 3),
-            "refinement_steps_per_job": tot // args.steps,
-            "rel_error_vs_fp64_solution": err,
-            "rel_res": relm,
-        }
+        log("mixed precision leg")
+        mixed = leg_mixed_job(hh, torch, dev, n_sub, level, f_dev, t_fault, args.steps, args.warmup, args.graph,
+                              tune_cache)
+    extra = {}
+    if not args.no_extra:
+        for name, fn in (("mixed_l8", lambda: leg_mixed_l8(hh, torch, dev, tune_cache)),
+                         ("gradients", lambda: leg_gradients(hh, torch, dev)),
+                         ("batched", lambda: leg_batched(hh, torch, dev, tune_cache))):
+            log(f"{name} leg")
+            t1 = time.perf_counter()
+            extra[name] = fn()
+            torch.cuda.empty_cache()
+            log(f"{name} leg done in {time.perf_counter() - t1:.1f} s")
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle)")
         cpu = cpu_baseline(n_sub, level)
+    try:
+        os.remove(tune_cache)
+    except OSError:
+        pass
 
     line = {
         "metric": "V-cycle MDoF/s + time-to-1e-8 residual (incl. fault recovery), FP64 vs mixed",
@@ -248,6 +423,7 @@ def main():
         "final_rel_res": rel,
         "roofline": roofline,
         "mixed": mixed,
+        **extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -106,6 +106,26 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+def residual_unit_k(u, b, n_sub: int, level: int) -> np.ndarray:
+    """r = b - A u for k = 1 without assembling A, for problems too large for
+    the CSR oracle (used as a property check at level 8).
+
+    Eq. (2) with k = 1 on the Kuhn meshes has A = h * (7-point Laplacian):
+    diagonal 6h, grid-axis neighbours -h, zero on the cube's boundary.  That
+    closed form is checked against this oracle's element-by-element assembly
+    by the operator tests, and this routine against the assembled residual.
+    """
+    N = int(n_sub) << int(level)
+    h = 1.0 / N
+    n = N - 1
+    U = np.zeros((n + 2, n + 2, n + 2))
+    U[1:-1, 1:-1, 1:-1] = _f64(u).reshape(n, n, n)  # axis order z, y, x
+    c = U[1:-1, 1:-1, 1:-1]
+    nb = (U[2:, 1:-1, 1:-1] + U[:-2, 1:-1, 1:-1]) + (U[1:-1, 2:, 1:-1] + U[1:-1, :-2, 1:-1]) + \
+         (U[1:-1, 1:-1, 2:] + U[1:-1, 1:-1, :-2])
+    return _f64(b) - h * (6.0 * c - nb).reshape(-1)
+
+
 class Problem:
     """Poisson / variable-coefficient problem on the n^3 x 6 Kuhn macro mesh.
 

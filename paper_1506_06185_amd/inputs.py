@@ -115,3 +115,14 @@ def batch_faults(n_faults: int, n_sub: int, seed: int = 0) -> np.ndarray:
     """Distinct faulty macro-tets for the concurrent-recovery workload."""
     g = rng(seed, STREAM_BATCH_FAULTS)
     return np.sort(g.choice(n_macro_tets(n_sub), size=n_faults, replace=False))
+
+
+def batch_member_faults(n_members: int, n_faulty: int, n_sub: int, seed: int = 0):
+    """(member, tet) pairs of the faulty batch members: distinct members, one
+    faulty macro-tet each (drawn after the global problem's faulty tets of
+    ``batch_faults`` in the same stream, so the two plans are independent)."""
+    g = rng(seed, STREAM_BATCH_FAULTS)
+    g.integers(1 << 30, size=16)
+    members = np.sort(g.choice(n_members, size=n_faulty, replace=False))
+    tets = g.integers(n_macro_tets(n_sub), size=n_faulty)
+    return [(int(m), int(t)) for m, t in zip(members, tets)]

@@ -1,0 +1,215 @@
+"""GPU checks at the full sizes of the benchmark workloads.
+
+* fault job, 48 tets at level 7 (16.6 M unknowns): V-cycle iterates, the fault
+  and the local recovery element by element against the CPU oracle, to the
+  FP64 bar of 1e-10 relative (the small-size tests hold 1e-12; here both sides
+  sum 16.6 M-term reductions and stop their coarsest-level PCG at 1e-14 in
+  different orders, and the observed difference is printed);
+* mixed precision at level 8 (133 M unknowns): the oracle's matrix-free
+  residual of the mixed and of the FP64 solutions, and their difference (1e-9);
+* gradients at level 7 with log-normal k (100.7 M elements): adjoint gradients
+  against the oracle's, the exact identity sum_T k_T dJ/dk_T = -f . dJ/df and
+  central finite differences on 20 directions for f and for k;
+* the concurrent workload: a level-7 problem with a Dirichlet-Dirichlet
+  recovery beside 32 members of levels 5-7 (6 with a local recovery) in one
+  batch; every member equals the same operations run one member at a time.
+
+Each test prints its case before running; launch shapes are the autotuner's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_06185_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_1506_06185_amd import hhgr
+
+    hhgr.lib()
+    return hhgr
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_fault_job_level7_against_oracle(dev, hh):
+    n_sub, level = 2, 7
+    print(f"\n[fault job] n_sub={n_sub} level={level}", flush=True)
+    p = oracle.Problem(n_sub, level)
+    f = inputs.sine_source(n_sub, level)
+    b = p.apply_M(f)
+    t = inputs.fault_tet(n_sub, seed=0)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    ctx.autotune(None)
+    ctx.set_rhs(T(f, dev), hh.HHGR_RHS_NODAL_F)
+    u = np.zeros_like(b)
+    tol = 1e-10
+
+    def check(what):
+        d = rel(N(ctx.get_solution()), u)
+        print(f"  {what}: rel diff {d:.3e}", flush=True)
+        assert d < tol, what
+
+    for it in range(2):
+        ctx.vcycle(1)
+        u, _ = p.vcycle(u, b)
+        check(f"cycle {it + 1}")
+    ctx.inject_fault(t)
+    u = p.inject_fault(t, u)
+    check("fault")
+    ctx.recover_local(t, 3)
+    u, _ = p.recover_local([t], u, b, n_cycles=3)
+    check("local recovery")
+    ctx.vcycle(1)
+    u, _ = p.vcycle(u, b)
+    check("cycle after recovery")
+    ctx.close()
+    p.close()
+
+
+def test_mixed_precision_level8(dev, hh):
+    n_sub, level = 2, 8
+    print(f"\n[mixed] n_sub={n_sub} level={level}", flush=True)
+    b = inputs.uniform_load(n_sub, level, seed=0)
+    bT = T(b, dev)
+    sol = {}
+    for prec, tol in (("mixed", 1e-11), ("fp64", 1e-12)):
+        c = hh.Context(device=dev, n_sub=n_sub, level=level, precision=prec)
+        c.set_rhs(bT, hh.HHGR_RHS_LOAD)
+        cyc, rr, _ = c.solve(tol, 60)
+        sol[prec] = N(c.get_solution())
+        c.close()
+        r = oracle.residual_unit_k(sol[prec], b, n_sub, level)
+        rr_o = np.linalg.norm(r) / np.linalg.norm(b)
+        print(f"  {prec}: {cyc} steps, rel res {rr:.3e} (oracle {rr_o:.3e})", flush=True)
+        assert rr_o <= 1.05 * tol
+        assert rr_o == pytest.approx(rr, rel=1e-3)
+    err = np.linalg.norm(sol["mixed"] - sol["fp64"]) / np.linalg.norm(sol["fp64"])
+    print(f"  mixed vs fp64 rel err {err:.3e}", flush=True)
+    assert err < 1e-9
+
+
+def test_gradients_level7(dev, hh):
+    n_sub, level = 2, 7
+    print(f"\n[gradients] n_sub={n_sub} level={level}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=0)
+    f = inputs.sine_source(n_sub, level)
+    uobs = inputs.gaussian_obs(n_sub, level, seed=0)
+    tol = 1e-11
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
+    fT, kT, oT = T(f, dev), T(k, dev), T(uobs, dev)
+    uT = hh.HHGSolve.apply(ctx, fT.requires_grad_(True), kT.requires_grad_(True), tol, 100)
+    J = 0.5 * ((uT - oT) ** 2).sum()
+    J.backward()
+    gf, gk = fT.grad.detach(), kT.grad.detach()
+    # exact identity of the bilinear form
+    lhs, rhs = float((kT.detach() * gk).sum()), -float((fT.detach() * gf).sum())
+    print(f"  identity {lhs:.12e} vs {rhs:.12e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+    # against the oracle's adjoint gradient
+    p = oracle.Problem(n_sub, level, k=k)
+    b = p.apply_M(f)
+    u, cu, _ = p.solve(b, rtol=tol, max_cycles=100)
+    lam, cl, _ = p.solve(u - uobs, rtol=tol, max_cycles=100)
+    print(f"  oracle cycles: forward {cu}, adjoint {cl}", flush=True)
+    assert rel(N(uT.detach()), u) < 1e-8
+    assert rel(N(gf), p.apply_M(lam)) < 1e-7
+    assert rel(N(gk), p.grad_k(u, lam)) < 1e-7
+    print("  oracle gradients ok", flush=True)
+    p.close()
+    # central finite differences with steps relative to the parameter's norm:
+    # J is quadratic in f, so its central difference is exact for any step (a
+    # large one keeps the solver's rounding out); in k the truncation error of
+    # a 1e-3 step is about 1e-6 relative
+    for name, base, grad, dirs, fd_h in (
+            ("f", fT.detach(), gf, inputs.fd_directions(f.size, 20, seed=0), 1e-2),
+            ("k", kT.detach(), gk, inputs.fd_directions(k.size, 20, seed=0, offset=20), 1e-3)):
+        step = fd_h * float(torch.linalg.norm(base))
+        worst = 0.0
+        for d in dirs:
+            dT = T(d, dev)
+            outs = []
+            for sgn in (1.0, -1.0):
+                ff, kk = (base + sgn * step * dT, kT.detach()) if name == "f" else (fT.detach(), base + sgn * step * dT)
+                outs.append(hh.HHGSolve.apply(ctx, ff, kk, tol, 100).detach())
+            up, um = outs
+            fdv = float(((up - um) * (0.5 * (up + um) - oT)).sum()) / (2 * step)
+            g = float((grad * dT).sum())
+            worst = max(worst, abs(fdv - g) / abs(g))
+        print(f"  FD {name}: worst rel diff {worst:.3e}", flush=True)
+        assert worst < 1e-4
+    ctx.close()
+
+
+def test_concurrent_batch_equals_member_by_member(dev, hh):
+    n_members, k_f = 32, 5
+    print(f"\n[concurrent batch] 1 + {n_members} members", flush=True)
+    levels = [7] + [int(x) for x in inputs.batch_levels(n_members, seed=0)]
+    g_tets = [int(t) for t in inputs.batch_faults(2, 2, seed=0)]
+    m_faults = dict((m + 1, t) for m, t in inputs.batch_member_faults(n_members, 6, 2, seed=0))
+
+    def rhs(q, L):
+        return T(inputs.sine_source(2, L) if q == 0 else inputs.uniform_load(2, L, seed=100 + q), dev)
+
+    def kind(q):
+        return hh.HHGR_RHS_NODAL_F if q == 0 else hh.HHGR_RHS_LOAD
+
+    ctxs = []
+    for q, L in enumerate(levels):
+        c = hh.Context(device=dev, n_sub=2, level=L, precision="mixed")
+        c.set_rhs(rhs(q, L), kind(q))
+        ctxs.append(c)
+    batch = hh.Batch(ctxs)
+    batch.run(0.0, k_f, raise_on_noconv=False)
+    for t in g_tets:
+        ctxs[0].inject_fault(t)
+    for m, t in m_faults.items():
+        ctxs[m].inject_fault(t)
+    batch.arm_dd(0, g_tets, 2, 4)
+    for m, t in m_faults.items():
+        batch.arm_dd(m, [t], 0, 3)
+    out = batch.run(1e-8, 60)
+    batch.close()
+    assert all(o[1] <= 1e-8 for o in out)
+    print("  batch converged; member by member:", flush=True)
+    for q, L in enumerate(levels):
+        got = N(ctxs[q].get_solution())
+        ctxs[q].close()
+        c = hh.Context(device=dev, n_sub=2, level=L, precision="mixed")
+        c.set_rhs(rhs(q, L), kind(q))
+        c.vcycle(k_f)
+        if q == 0:
+            for t in g_tets:
+                c.inject_fault(t)
+            c.recover_dd(g_tets, 2, 4)
+        elif q in m_faults:
+            c.inject_fault(m_faults[q])
+            c.recover_local(m_faults[q], 3)
+        cyc, _, _ = c.solve(1e-8, 60)
+        ref = N(c.get_solution())
+        c.close()
+        n_rec = 2 if q == 0 else 0
+        assert out[q][0] == cyc + n_rec, (q, out[q][0], cyc)
+        assert rel(got, ref) < 1e-14, q
+    print("  all members equal", flush=True)

@@ -152,3 +152,16 @@ def test_apply_matches_exported_matrices():
     assert np.allclose(r, 1 - p.matrix(3, "A") @ u, atol=1e-13)
     bc = p.restrict(u)
     assert np.allclose(bc, p.matrix(3, "P").T @ u, atol=1e-14)
+
+
+def test_closed_form_residual_matches_assembled(oracle_problem):
+    """The matrix-free k = 1 residual used at level 8 equals the assembled one."""
+    import oracle
+
+    for n_sub, level in ((1, 4), (2, 3)):
+        p = oracle_problem(n_sub, level)
+        g = np.random.default_rng(3)
+        u, b = g.standard_normal(p.ndof), g.standard_normal(p.ndof)
+        r = oracle.residual_unit_k(u, b, n_sub, level)
+        ref = p.residual(u, b)
+        assert np.abs(r - ref).max() <= 1e-13 * np.abs(ref).max()
