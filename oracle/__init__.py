@@ -83,6 +83,9 @@ def lib():
         "ohhg_recover_local": (None, [_vp, _ip, C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int,
                                       C.c_int, _dp]),
         "ohhg_dd_intact": (None, [_vp, _ip, C.c_int, _dp, _dp, C.c_int, C.c_double, C.c_int, C.c_int]),
+        "ohhg_dn_recover": (None, [_vp, _ip, C.c_int, _dp, _dp, C.c_int, C.c_int, C.c_double, C.c_int,
+                                   C.c_int]),
+        "ohhg_side_matrix": (_vp, [_vp, C.c_int, _ip, C.c_int, C.c_int]),
         "ohhg_grad_k": (None, [_vp, _dp, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
@@ -199,12 +202,10 @@ class Problem:
         return c
 
     # -- matrices -----------------------------------------------------------
-    def matrix(self, level: int, which: str = "A", full: bool = False):
-        """scipy CSR of A (stiffness), M (mass) or P (level-1 -> level)."""
+    @staticmethod
+    def _fetch_matrix(h):
         import scipy.sparse as sp
 
-        code = {"A": 0, "M": 1, "P": 2}[which] + (3 if full else 0)
-        h = lib().ohhg_matrix(self._h, level, code)
         try:
             n = int(lib().ohhg_matrix_rows(h))
             m = int(lib().ohhg_matrix_cols(h))
@@ -216,6 +217,19 @@ class Problem:
         finally:
             lib().ohhg_matrix_free(h)
         return sp.csr_matrix((val, col, ptr), shape=(n, m))
+
+    def matrix(self, level: int, which: str = "A", full: bool = False):
+        """scipy CSR of A (stiffness), M (mass) or P (level-1 -> level)."""
+        code = {"A": 0, "M": 1, "P": 2}[which] + (3 if full else 0)
+        return self._fetch_matrix(lib().ohhg_matrix(self._h, level, code))
+
+    def side_matrix(self, level: int, tets, side: str = "intact"):
+        """Stiffness matrix (interior dofs) assembled over the elements of the
+        intact (or faulty) macro tetrahedra only: the sub-stencils of eq. (5)."""
+        tets = np.ascontiguousarray(np.atleast_1d(tets), dtype=np.int32)
+        h = lib().ohhg_side_matrix(self._h, level, tets.ctypes.data_as(_ip), len(tets),
+                                   {"intact": 0, "faulty": 1}[side])
+        return self._fetch_matrix(h)
 
     # -- operators ----------------------------------------------------------
     def apply_A(self, u, level: int | None = None) -> np.ndarray:
@@ -309,6 +323,18 @@ class Problem:
         lib().ohhg_recover_local(self._h, tets.ctypes.data_as(_ip), len(tets), _d(u), _d(b),
                                  int(n_cycles), float(omega), int(nu1), int(nu2), _d(res))
         return u, res[:n_cycles].copy()
+
+    def dn_recover(self, tets, u, b, n_intact: int, eta: int = 1, omega: float = 1.25, nu1: int = 2,
+                   nu2: int = 1):
+        """Dirichlet-Neumann recovery (Alg. 2) of the faulty tets: n_intact rounds of
+        eta local cycles (interface data of the round's start) and one intact
+        Neumann cycle."""
+        tets = np.ascontiguousarray(np.atleast_1d(tets), dtype=np.int32)
+        u = _f64(u).copy()
+        b = _f64(b)
+        lib().ohhg_dn_recover(self._h, tets.ctypes.data_as(_ip), len(tets), _d(u), _d(b), int(n_intact),
+                              int(eta), float(omega), int(nu1), int(nu2))
+        return u
 
     def dd_intact(self, tets, u, b, n_cycles: int, omega: float = 1.25, nu1: int = 2, nu2: int = 1):
         tets = np.ascontiguousarray(np.atleast_1d(tets), dtype=np.int32)

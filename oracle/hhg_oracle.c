@@ -1243,6 +1243,167 @@ void ohhg_dd_intact(void *vp, const int *tets, int nt, double *u, const double *
 }
 
 /* ------------------------------------------------------------------------- */
+/* Dirichlet-Neumann recovery (Sec. 4.3, Alg. 2, eq. (5))                      */
+/* ------------------------------------------------------------------------- */
+/* Element coefficient restricted to one side of the fault: k of the element
+ * (1 without variable k) where its macro tetrahedron is intact (side 0) or
+ * faulty (side 1), else 0.  Element e of level l descends from macro element
+ * e >> 3l (Bey children of e are 8e..8e+7). */
+static double *side_coeff(const oproblem *p, int l, const unsigned char *faulty, int side) {
+    const olevel *Lv = &p->lev[l];
+    double *k = xmalloc((size_t)Lv->ne * sizeof(double));
+    for (i64 e = 0; e < Lv->ne; e++) {
+        const int f = faulty[e >> (3 * l)];
+        const double ke = p->var_k ? Lv->k[Lv->ecl[e]] : 1.0;
+        k[Lv->ecl[e]] = (side == 0 ? !f : f) ? ke : 0.0;
+    }
+    return k;
+}
+
+/* Stiffness matrix of level l assembled over the elements of one side only:
+ * the sub-stencils of eq. (5) (A_II, A_{I Gamma_I}, A_{Gamma_I Gamma_I} for
+ * side 0).  A^intact + A^faulty = A. */
+static csr side_matrix(const oproblem *p, int l, const int *tets, int nt, int side) {
+    unsigned char *faulty = xcalloc((size_t)p->lev[0].ne, 1);
+    for (int q = 0; q < nt; q++) faulty[tets[q]] = 1;
+    double *k = side_coeff(p, l, faulty, side);
+    csr A = assemble(&p->lev[l], k, 0, 1);
+    free(k);
+    free(faulty);
+    return A;
+}
+
+/* Multigrid hierarchy of given operators ops[l], restricted to keep[l]; the
+ * transfers are the restrictions of the global ones */
+static void hier_ops(oproblem *p, csr *ops, unsigned char **keep, mghier *H, i64 **map_out) {
+    memset(H, 0, sizeof(*H));
+    H->Lc = p->Lc;
+    H->L = p->L;
+    i64 *map[MAXLEV] = {0};
+    for (int l = p->Lc; l <= p->L; l++) {
+        olevel *Lv = &p->lev[l];
+        map[l] = xmalloc((size_t)Lv->ndof * sizeof(i64));
+        i64 c = 0;
+        for (i64 i = 0; i < Lv->ndof; i++) map[l][i] = keep[l][i] ? c++ : -1;
+        mglev *m = &H->lv[l];
+        m->n = c;
+        m->owned = 1;
+        m->A = csr_sub(&ops[l], map[l], c, map[l], c);
+        m->diag = xcalloc((size_t)(c ? c : 1), sizeof(double));
+        m->red = xmalloc((size_t)(c ? c : 1) * sizeof(i64));
+        m->black = xmalloc((size_t)(c ? c : 1) * sizeof(i64));
+        for (i64 i = 0; i < c; i++)
+            for (i64 q = m->A.ptr[i]; q < m->A.ptr[i + 1]; q++)
+                if (m->A.col[q] == i) m->diag[i] = m->A.val[q];
+        for (i64 q = 0; q < Lv->nred; q++)
+            if (map[l][Lv->red[q]] >= 0) m->red[m->nred++] = map[l][Lv->red[q]];
+        for (i64 q = 0; q < Lv->nblack; q++)
+            if (map[l][Lv->black[q]] >= 0) m->black[m->nblack++] = map[l][Lv->black[q]];
+        if (l > p->Lc) {
+            m->P = csr_sub(&Lv->P, map[l], c, map[l - 1], H->lv[l - 1].n);
+            m->R = csr_transpose(&m->P);
+        }
+    }
+    for (int l = 0; l < MAXLEV; l++) {
+        if (map_out)
+            map_out[l] = map[l];
+        else
+            free(map[l]);
+    }
+}
+
+/* Alg. 2.  Intact side: V-cycles for the Neumann problem (lines 1+2 of
+ * eq. (5)) on the nodes the intact operator couples (intact interiors and the
+ * interface Gamma), right-hand side b off Gamma and, on Gamma, the intact-side
+ * action A^I u of the data at the time of the fault (lambda of Alg. 2 taken
+ * with static data).  Faulty side: u_F starts at zero; the local Dirichlet
+ * problems (line 6) get their boundary values from Gamma (line 5).
+ * n_intact rounds: in round i the faulty side runs eta local cycles with the
+ * interface values of the start of the round, continuing from its current
+ * u_F, and the intact side runs one V-cycle; the two sides share no unknown
+ * within a round, so their order inside it does not matter. */
+void ohhg_dn_recover(void *vp, const int *tets, int nt, double *u, const double *b, int n_intact, int eta,
+                     double omega, int nu1, int nu2) {
+    oproblem *p = vp;
+    const int L = p->L;
+    const olevel *F = &p->lev[L];
+    mgopt o = {omega, nu1, nu2};
+    /* intact side */
+    csr ops[MAXLEV];
+    memset(ops, 0, sizeof(ops));
+    unsigned char *keep[MAXLEV] = {0};
+    for (int l = p->Lc; l <= L; l++) {
+        ops[l] = side_matrix(p, l, tets, nt, 0);
+        keep[l] = xcalloc((size_t)p->lev[l].ndof, 1);
+        for (i64 i = 0; i < p->lev[l].ndof; i++)
+            for (i64 q = ops[l].ptr[i]; q < ops[l].ptr[i + 1]; q++)
+                if (ops[l].col[q] == i && ops[l].val[q] > 0.0) keep[l][i] = 1;
+    }
+    i64 *mapI[MAXLEV] = {0};
+    mghier HI;
+    hier_ops(p, ops, keep, &HI, mapI);
+    unsigned char *onF = xcalloc((size_t)F->ndof, 1), *m = xmalloc((size_t)F->ndof);
+    for (int q = 0; q < nt; q++) {
+        ohhg_tet_mask(p, L, tets[q], 1, m);
+        for (i64 i = 0; i < F->ndof; i++) onF[i] |= m[i];
+    }
+    const i64 nI = HI.lv[L].n;
+    double *Au = xmalloc((size_t)F->ndof * sizeof(double));
+    spmv(&ops[L], u, Au);
+    double *bI = xmalloc((size_t)(nI ? nI : 1) * sizeof(double));
+    double *xI = xmalloc((size_t)(nI ? nI : 1) * sizeof(double));
+    for (i64 i = 0; i < F->ndof; i++) {
+        const i64 j = mapI[L][i];
+        if (j < 0) continue;
+        bI[j] = onF[i] ? Au[i] : b[i]; /* Gamma: static Neumann data */
+        xI[j] = u[i];
+    }
+    /* faulty side */
+    unsigned char *keepF[MAXLEV] = {0};
+    i64 *mapF[MAXLEV] = {0};
+    build_masks(p, tets, nt, 0, 0, keepF);
+    mghier HF;
+    hier_sub(p, keepF, &HF, mapF);
+    const i64 nF = HF.lv[L].n;
+    double *bF = xmalloc((size_t)(nF ? nF : 1) * sizeof(double));
+    double *xF = xcalloc((size_t)(nF ? nF : 1), sizeof(double));
+    for (i64 i = 0; i < F->ndof; i++)
+        if (mapF[L][i] >= 0) u[i] = 0.0;
+    for (int r = 0; r < n_intact; r++) {
+        sub_rhs(&F->A, mapF[L], nF, u, b, bF); /* interface values of the start of the round */
+        for (int c = 0; c < eta; c++) vcycle64(&HF, L, xF, bF, &o);
+        vcycle64(&HI, L, xI, bI, &o);
+        for (i64 i = 0; i < F->ndof; i++) {
+            if (mapF[L][i] >= 0) u[i] = xF[mapF[L][i]];
+            if (mapI[L][i] >= 0) u[i] = xI[mapI[L][i]];
+        }
+    }
+    free(Au);
+    free(bI);
+    free(xI);
+    free(bF);
+    free(xF);
+    free(onF);
+    free(m);
+    hier_free(&HI);
+    hier_free(&HF);
+    for (int l = 0; l < MAXLEV; l++) {
+        csr_free(&ops[l]);
+        free(keep[l]);
+        free(keepF[l]);
+        free(mapI[l]);
+        free(mapF[l]);
+    }
+}
+
+/* The side matrices for tests: side 0 = intact, 1 = faulty (matrix handle) */
+void *ohhg_side_matrix(void *vp, int l, const int *tets, int nt, int side) {
+    csr *A = xmalloc(sizeof(csr));
+    *A = side_matrix(vp, l, tets, nt, side);
+    return A;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Mixed precision: FP32 V-cycle inside an FP64 residual-correction loop      */
 /* ------------------------------------------------------------------------- */
 static void ensure_fp32(mghier *H) {

@@ -136,3 +136,85 @@ def test_dd_recovery_beats_do_nothing(oracle_problem):
     u, _ = p.recover_local(t, u, b, n_cycles=n_F)
     k_dd = kF + n_I + _cycles_to(p, b, u, r0)  # Sec. 4.4: n_I counts towards k_faulty
     assert kappa(k_dd, k_free, kF) < kappa(k_dn, k_free, kF)
+
+
+def test_side_matrices_split_the_operator(oracle_problem):
+    """Sub-stencils of eq. (5): the matrices assembled over the intact and over
+    the faulty macro tetrahedra add up to A; the intact one couples no node
+    strictly inside a faulty tet, is symmetric and is SPD on the nodes it
+    couples; rows of nodes away from the faulty closures equal A's."""
+    n_sub, L = 2, 3
+    p = oracle_problem(n_sub, L)
+    tets = [5, 30]
+    A = p.matrix(L, "A").tocsr()
+    AI = p.side_matrix(L, tets, "intact").tocsr()
+    AF = p.side_matrix(L, tets, "faulty").tocsr()
+    assert abs(AI + AF - A).max() <= 1e-15 * abs(A).max()
+    assert abs(AI - AI.T).max() <= 1e-15 * abs(A).max()
+    inside = np.zeros(p.ndof, bool)
+    closed = np.zeros(p.ndof, bool)
+    for t in tets:
+        inside |= p.tet_mask(t)
+        closed |= p.tet_mask(t, closure=True)
+    assert abs(AI[inside]).max() == 0.0 and abs(AI[:, inside]).max() == 0.0
+    assert abs(AF[~closed]).max() == 0.0
+    away = ~closed
+    assert abs(AI[away] - A[away]).max() == 0.0
+    free = AI.diagonal() > 0
+    assert np.array_equal(free, ~inside & (AI.diagonal() > 0))
+    np.linalg.cholesky(AI[free][:, free].toarray())
+
+
+def test_dn_recovery_keeps_the_exact_solution(oracle_problem):
+    """At the converged solution the static Neumann data make the intact side
+    stationary, and the local Dirichlet cycles restore the faulty interiors."""
+    n_sub, L = 2, 4
+    p = oracle_problem(n_sub, L)
+    b = p.apply_M(inputs.sine_source(n_sub, L))
+    u, _, _ = p.solve(b, rtol=1e-14, max_cycles=80)
+    tets = [int(t) for t in inputs.batch_faults(2, n_sub, seed=2)]
+    uf = u.copy()
+    for t in tets:
+        uf = p.inject_fault(t, uf)
+    ud = p.dn_recover(tets, uf, b, n_intact=3, eta=4)
+    inside = np.zeros(p.ndof, bool)
+    for t in tets:
+        inside |= p.tet_mask(t)
+    scale = np.abs(u).max()
+    assert np.abs(ud[~inside] - u[~inside]).max() < 1e-12 * scale
+    assert np.abs(ud[inside] - u[inside]).max() < 1e-8 * scale
+
+
+def test_dn_intact_side_is_one_directional(oracle_problem):
+    """The intact side never reads u_F: its result does not depend on the
+    faulty interiors; the faulty side reads only the interface values of the
+    start of each round, so a round with eta = 0 leaves u_F at zero."""
+    n_sub, L = 2, 4
+    p = oracle_problem(n_sub, L)
+    b = inputs.uniform_load(n_sub, L, seed=4)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=4)
+    t = inputs.fault_tet(n_sub, seed=0)
+    uf = p.inject_fault(t, u)
+    inside = p.tet_mask(t)
+    a = p.dn_recover([t], uf, b, n_intact=2, eta=0)
+    assert np.all(a[inside] == 0.0)
+    c = p.dn_recover([t], uf, b, n_intact=2, eta=3)
+    # equal up to the oracle's own run-to-run rounding (OpenMP reduction order)
+    assert np.abs(a[~inside] - c[~inside]).max() <= 1e-13 * np.abs(a).max()
+    assert np.abs(c[inside]).max() > 0.0
+
+
+def test_dn_recovery_beats_do_nothing(oracle_problem):
+    n_sub, L, kF = 2, 5, 5
+    p = oracle_problem(n_sub, L)
+    b = p.apply_M(inputs.sine_source(n_sub, L))
+    r0 = np.linalg.norm(b)
+    _, k_free, _ = p.solve(b, rtol=1e-8)
+    u5, _, _ = p.solve(b, rtol=0.0, max_cycles=kF)
+    t = inputs.fault_tet(n_sub, seed=0)
+    uf = p.inject_fault(t, u5)
+    k_nothing = kF + _cycles_to(p, b, uf, r0)
+    n_I, eta = 2, 2
+    u = p.dn_recover([t], uf, b, n_intact=n_I, eta=eta)
+    k_dn = kF + n_I + _cycles_to(p, b, u, r0)  # Sec. 4.4: n_I counts towards k_faulty
+    assert kappa(k_dn, k_free, kF) < kappa(k_nothing, k_free, kF)
