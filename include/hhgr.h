@@ -151,6 +151,20 @@ int hhgr_recover_local(hhgr_ctx *ctx, int tet, int n_cycles, double *local_rel_r
  * coarse_level != 2. */
 int hhgr_recover_dd(hhgr_ctx *ctx, const int *tets, int n_tets, int n_intact, int n_local);
 
+/* Dirichlet-Neumann recovery (Sec. 4.3, Alg. 2, eq. (5)) of the listed faulty
+ * tetrahedra (after hhgr_inject_fault on them).  The intact side cycles on a
+ * Neumann problem: the stiffness assembled over the elements of intact
+ * macro tetrahedra only (the sub-stencils of eq. (5)), with the interface
+ * nodes free and, on the interface, the static Neumann data A^I u of the
+ * data at call time (lambda of Alg. 2).  The faulty side starts from zero and
+ * runs local Dirichlet cycles with boundary values from the interface.
+ * n_intact rounds: eta local cycles with the interface values of the start
+ * of the round, concurrently (second stream) with one intact cycle.  Faces,
+ * edges and vertices inside the faulty region stay as stored.  Returns after
+ * both sides finish; later cycles use the whole problem again.  Same
+ * argument rules as hhgr_recover_dd (eta in place of n_local). */
+int hhgr_recover_dn(hhgr_ctx *ctx, const int *tets, int n_tets, int n_intact, int eta);
+
 /* Adjoint gradients for J = 1/2 ||u - u_obs||^2 with A(k) u = M f: given
  * dev_g = u - u_obs (device, vector order), solves A lambda = g with the same
  * multigrid (A is symmetric) to rel_tol and returns dJ/df = M lambda (vector

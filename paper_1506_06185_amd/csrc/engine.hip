@@ -88,6 +88,11 @@ struct LevelDev {
     int n_masked = 0, n_loc = 0;
     unsigned char *frozen = nullptr;
     double *lu = nullptr, *lb = nullptr, *lr = nullptr;  // local hierarchy (levels < L)
+    // Dirichlet-Neumann recovery: intact-side interface weights, ghost copies
+    // outside the faulty closures, interface nodes with static Neumann data
+    double *wi_dn = nullptr;
+    int *gptr_dn = nullptr, *gidx_dn = nullptr;
+    unsigned char *gamma = nullptr;
 };
 
 template <typename T>
@@ -98,6 +103,7 @@ struct LevView {
     int nvol = 0;
     bool ifc = false;
     const unsigned char *frozen = nullptr;
+    const int *gptr = nullptr, *gidx = nullptr;  // ghost copies to update (nullptr: all of the level's)
 };
 
 template <typename T>
@@ -106,6 +112,7 @@ struct HView {
     int L = 0, Lc = 0;
     bool local = false;
     const unsigned char *cfrozen = nullptr;
+    const double *cval = nullptr;  // coarsest-level operator (nullptr: the context's)
     double *partial = nullptr;
     unsigned int *counter = nullptr;
     bool timed = false;
@@ -135,8 +142,8 @@ struct hhgr_ctx {
     // coarsest level
     long long *cslot = nullptr;
     int *ccol = nullptr, *cptr = nullptr, *cidx = nullptr, *cpos = nullptr, *citers = nullptr;
-    double *cval = nullptr;
-    unsigned char *cfrozen = nullptr;
+    double *cval = nullptr, *cval_dn = nullptr;
+    unsigned char *cfrozen = nullptr, *dn_faulty = nullptr;
     int cn = 0;
     std::vector<double> cval_host;
     // adjoint temporaries
@@ -262,6 +269,10 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.lb = cv.take<double>((size_t)nf * T.C_pad);
             D.lr = cv.take<double>((size_t)nf * T.C_pad);
         }
+        D.wi_dn = cv.take<double>(6 * (size_t)T.n_ifc);
+        D.gptr_dn = cv.take<int>(T.n_ifc + 1);
+        D.gidx_dn = cv.take<int>(T.gidx.size());
+        if (l == c.L) D.gamma = cv.take<unsigned char>(T.n_ifc);
     }
     c.partial_cap = max_blocks;
     c.partial[0] = cv.take<double>(max_blocks);
@@ -277,6 +288,8 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.cidx = cv.take<int>(tp.coarse.cidx.size());
     c.cpos = cv.take<int>(3 * (size_t)c.cn);
     c.cfrozen = cv.take<unsigned char>(c.cn);
+    c.cval_dn = cv.take<double>(7 * (size_t)c.cn);
+    c.dn_faulty = cv.take<unsigned char>(c.n_tets);
     c.citers = cv.take<int>(4);
     const TopoLevel &TL = tp.lev[c.L];
     c.aux_u = cv.take<double>(TL.n_slots);
@@ -367,6 +380,17 @@ IfcGeom igeom(const LevelDev &D, int i0, int i1, const unsigned char *frozen, bo
 
 IfcGeom ig_none() { return IfcGeom(); }
 
+// interface part of a launch on a view's level (its frozen nodes and ghost lists)
+template <typename T>
+IfcGeom igeom_v(const LevelDev &D, const LevView<T> &v, int i0, int i1, bool scatter) {
+    IfcGeom g = igeom(D, i0, i1, v.frozen, scatter);
+    if (scatter && v.gptr) {
+        g.gptr = v.gptr;
+        g.gidx = v.gidx;
+    }
+    return g;
+}
+
 template <typename T>
 Weights<T> weights(const LevelDev &D);
 template <>
@@ -426,7 +450,7 @@ HView<T> global_view(hhgr_ctx &c, bool masked, int stream_idx) {
 }
 
 // local hierarchy of the faulty tetrahedra currently in vd_loc (FP64)
-HView<double> local_view(hhgr_ctx &c, int stream_idx) {
+HView<double> local_view(hhgr_ctx &c, int stream_idx, double *finest_r = nullptr) {
     HView<double> V;
     V.L = c.L;
     V.Lc = c.Lc;
@@ -439,7 +463,7 @@ HView<double> local_view(hhgr_ctx &c, int stream_idx) {
         if (l == c.L) {
             v.u = D.u;
             v.b = D.b;
-            v.r = D.r;
+            v.r = finest_r ? finest_r : D.r;
         } else {
             v.u = D.lu;
             v.b = D.lb;
@@ -479,8 +503,8 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const LevView<T> &v = V.lv[l];
     for (int colour = 0; colour < 2; colour++) {
         const VolGeom vg = vgeom(D, v.vd, v.nvol, false, -1, colour);
-        const IfcGeom ig = v.ifc ? igeom(D, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc,
-                                         v.frozen, true)
+        const IfcGeom ig = v.ifc ? igeom_v(D, v, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc,
+                                           true)
                                  : ig_none();
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
@@ -501,8 +525,8 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     if (V.local) {
         launch_local_coarse<T>(s, v.vd, v.nvol, D.lc_sl, v.b, v.u, v.w, c.vk, D.h);
     } else {
-        launch_coarse_pcg<T>(s, c.cn, c.cslot, c.ccol, c.cval, V.cfrozen, v.b, v.u, c.cptr, c.cidx, kCoarseRtol,
-                             kCoarseMaxit, c.citers);
+        launch_coarse_pcg<T>(s, c.cn, c.cslot, c.ccol, V.cval ? V.cval : c.cval, V.cfrozen, v.b, v.u, c.cptr, c.cidx,
+                             kCoarseRtol, kCoarseMaxit, c.citers);
     }
 }
 
@@ -525,7 +549,7 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
     launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
-    const IfcGeom igp = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, true) : ig_none();
+    const IfcGeom igp = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
     launch_prolong<T>(s, vg, vc.vd, Dc.rowC, Dc.M, igp, D.prl, vc.u, v.u);
     smooth(c, V, l, c.d.nu_post, false, s);
 }
@@ -730,6 +754,114 @@ void dd_final_norm(hhgr_ctx &c, hipStream_t s) {
     } else {
         HView<double> V = global_view<double>(c, false, 0);
         finest_residual<double>(c, V, (double *)nullptr, s, c.dnorm);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Dirichlet-Neumann recovery (Sec. 4.3, Alg. 2, eq. (5)): the intact side
+// cycles on a Neumann problem (stiffness over the elements of intact macro
+// tetrahedra only, interface nodes free, static Neumann data on the
+// interface); the faulty side runs local Dirichlet cycles whose boundary
+// values are refreshed from the interface at the start of every round
+// ----------------------------------------------------------------------------
+int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
+    std::vector<unsigned char> isf(c.n_tets, 0);
+    for (int t : ft) isf[t] = 1;
+    int rc = HHGR_OK;
+    std::vector<std::vector<VolDesc>> vds(c.L + 1);
+    std::vector<std::vector<unsigned char>> frz(c.L + 1), gam(c.L + 1);
+    std::vector<std::vector<int>> gp(c.L + 1), gi(c.L + 1);
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        const TopoLevel &T = c.topo->lev[l];
+        for (int t = 0; t < c.n_tets; t++)
+            if (!isf[t]) vds[l].push_back(VolDesc{(long long)t * D.C_pad, (long long)t * D.C_pad, t, 0});
+        // an interface node lies in the closures of the tetrahedra holding its
+        // ghost copies: frozen if all of them are faulty, on the interface
+        // Gamma if some are; ghost copies in faulty closures are skipped
+        frz[l].assign(D.n_ifc, 0);
+        gam[l].assign(D.n_ifc, 0);
+        gp[l].assign(D.n_ifc + 1, 0);
+        for (int f = 0; f < D.n_ifc; f++) {
+            int nf = 0, ni = 0;
+            for (int g = T.gptr[f]; g < T.gptr[f + 1]; g++) {
+                const int tet = (int)(T.gidx[g] / T.C_pad);
+                if (isf[tet]) {
+                    nf++;
+                } else {
+                    ni++;
+                    gi[l].push_back(T.gidx[g]);
+                }
+            }
+            frz[l][f] = ni == 0 ? 1 : 0;
+            gam[l][f] = (nf > 0 && ni > 0) ? 1 : 0;
+            gp[l][f + 1] = (int)gi[l].size();
+        }
+        D.n_masked = (int)vds[l].size();
+        rc = rc ? rc : upload(c, D.vd_masked, vds[l].data(), vds[l].size() * sizeof(VolDesc));
+        rc = rc ? rc : upload(c, D.frozen, frz[l].data(), frz[l].size());
+        rc = rc ? rc : upload(c, D.gptr_dn, gp[l].data(), gp[l].size() * sizeof(int));
+        rc = rc ? rc : upload(c, D.gidx_dn, gi[l].data(), gi[l].size() * sizeof(int));
+        if (D.gamma) rc = rc ? rc : upload(c, D.gamma, gam[l].data(), gam[l].size());
+    }
+    const CoarseSystem &cs = c.topo->coarse;
+    std::vector<unsigned char> cf(cs.n, 0);
+    for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? isf[cs.tet[q]] : frz[c.Lc][cs.ifc[q]];
+    rc = rc ? rc : upload(c, c.cfrozen, cf.data(), cf.size());
+    rc = rc ? rc : upload(c, c.dn_faulty, isf.data(), isf.size());
+    if (rc) return rc;
+    // intact-side operators on every level
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        launch_ifc_weights_intact(c.stream, D.n_ifc, D.ifc_xyz, D.N, D.m, c.d.n_sub, D.h, c.vk ? D.kc : nullptr,
+                                  c.dn_faulty, D.wi_dn);
+    }
+    const LevelDev &Dc = c.lev[c.Lc];
+    launch_coarse_vals_intact(c.stream, c.cn, c.cpos, c.ccol, Dc.N, Dc.m, c.d.n_sub, Dc.h, c.vk ? Dc.kc : nullptr,
+                              c.dn_faulty, c.cval_dn);
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c.stream));
+    set_loc(c, ft);
+    LevelDev &F = c.lev[c.L];
+    // static Neumann data from the data at the time of the fault (u_F plays
+    // no part: its edges have zero intact-side weight)
+    HIPCHK(hipMemcpyAsync(c.aux_b, F.b, F.n_slots * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+    launch_neumann_rhs(c.stream, F.n_ifc, F.ifc_base, F.nbr, F.wi_dn, F.gamma, F.u, c.aux_b);
+    for (int t : ft) restore_tet(c, t, c.stream);
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        if (l < c.L) launch_fill<double>(c.stream, D.u, D.n_slots, 0.0);
+        // the intact side never writes residuals inside faulty closures; its
+        // restriction reads them there as zero
+        launch_fill<double>(c.stream, D.r, D.n_slots, 0.0);
+    }
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return HHGR_OK;
+}
+
+// the intact side's Neumann hierarchy (FP64)
+HView<double> dn_view(hhgr_ctx &c) {
+    HView<double> V = global_view<double>(c, true, 0);
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        LevView<double> &v = V.lv[l];
+        v.w.wi = D.wi_dn;
+        v.gptr = D.gptr_dn;
+        v.gidx = D.gidx_dn;
+    }
+    V.lv[c.L].b = c.aux_b;
+    V.cval = c.cval_dn;
+    return V;
+}
+
+// ghost copies of the faulty tetrahedra from the interface masters (their
+// interiors are kept)
+void refresh_faulty_ghosts(hhgr_ctx &c, const std::vector<int> &ft, hipStream_t s) {
+    LevelDev &D = c.lev[c.L];
+    for (int t : ft) {
+        const int a = D.tg_ptr[t], b = D.tg_ptr[t + 1];
+        launch_ghost_refresh<double>(s, D.tg_dst + a, D.tg_src + a, b - a, D.u);
     }
 }
 
@@ -1132,6 +1264,34 @@ int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
     dd_local(*c, n_local, c->stream2);
     HIPCHK(hipEventRecord(c->ev_join, c->stream2));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dd_end(*c);
+    return HHGR_OK;
+}
+
+int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int eta) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    std::vector<int> ft;
+    rc = dd_check(*c, tets, n_tets, n_intact, eta, ft);
+    if (rc) return rc;
+    invalidate_graph(*c);
+    rc = dn_setup(*c, ft);
+    if (rc) return rc;
+    HView<double> VI = dn_view(*c);
+    HView<double> VL = local_view(*c, 1, c->aux_u);
+    for (int q = 0; q < n_intact; q++) {
+        // the faulty side reads the interface values of the start of the round
+        refresh_faulty_ghosts(*c, ft, c->stream);
+        HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+        for (int e = 0; e < eta; e++) vcycle<double>(*c, VL, c->L, false, c->stream2);
+        vcycle<double>(*c, VI, c->L, false, c->stream);
+        HIPCHK(hipEventRecord(c->ev_join, c->stream2));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    }
+    refresh_faulty_ghosts(*c, ft, c->stream);
     CHKLAUNCH();
     HIPCHK(hipStreamSynchronize(c->stream));
     dd_end(*c);

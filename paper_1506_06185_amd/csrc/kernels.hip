@@ -148,13 +148,16 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
         const long long sl = ig.base + t;
         const T uo = OWN0 ? T(0) : u[sl];
         T acc = T(0), diag;
-        if (VK) {
+        // interface weights: variable k, or the intact-side stencils of a
+        // Dirichlet-Neumann recovery (given also when k = 1)
+        if (VK || w.wi) {
             diag = T(0);
 #pragma unroll
             for (int e = 0; e < 6; e++) {
                 const T we = w.wi[(long long)e * ig.stride + t];
                 diag += we;
-                if (!NB0) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
+                // edges of weight zero (outside an intact side) are not read
+                if (!NB0 && we != T(0)) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
             }
         } else {
             diag = T(6) * h;
@@ -228,13 +231,13 @@ __global__ void __launch_bounds__(512) k_residual(VolGeom vg, IfcGeom ig, int ni
             const long long sl = ig.base + t;
             const T uo = u[sl];
             T acc = T(0), diag;
-            if (VK) {
+            if (VK || w.wi) {
                 diag = T(0);
 #pragma unroll
                 for (int e = 0; e < 6; e++) {
                     const T we = w.wi[(long long)e * ig.stride + t];
                     diag += we;
-                    acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
+                    if (we != T(0)) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
                 }
             } else {
                 diag = T(6) * h;
@@ -791,6 +794,97 @@ __global__ void k_coarse_vals(int n, const int *__restrict__ pos, const int *__r
     val[7 * q] = diag;
 }
 
+// Dirichlet-Neumann recovery (Sec. 4.3, eq. (5)): the intact side's
+// sub-stencils are the stiffness assembled over the elements of intact macro
+// tetrahedra only.  Fine element (cell c, permutation q) at a level with m
+// segments per macro edge lies in the macro tetrahedron of macro cell c / m
+// whose axis order sorts the element's centroid offsets in that macro cell.
+__device__ int macro_tet_of(int cx, int cy, int cz, int q, int m, int n_sub) {
+    const int C[3] = {cx / m, cy / m, cz / m};
+    // centroid offsets in quarter units: 3, 2, 1 along the element's axes p0, p1, p2
+    int D[3] = {4 * (cx - m * C[0]), 4 * (cy - m * C[1]), 4 * (cz - m * C[2])};
+    D[kPermD[q][0]] += 3;
+    D[kPermD[q][1]] += 2;
+    D[kPermD[q][2]] += 1;
+    const int a0 = D[0] > D[1] ? (D[0] > D[2] ? 0 : 2) : (D[1] > D[2] ? 1 : 2);
+    const int a2 = D[0] < D[1] ? (D[0] < D[2] ? 0 : 2) : (D[1] < D[2] ? 1 : 2);
+    const int a1 = 3 - a0 - a2;
+    return 6 * (C[0] + n_sub * (C[1] + n_sub * C[2])) + perm_id(a0, a1);
+}
+
+// edge weight over intact elements: k (or 1 with k == nullptr) of each
+// tetrahedron having the edge on its axis path, unless its macro
+// tetrahedron is faulty
+__device__ double edge_w_intact(const double *__restrict__ k, int N, double h, int x, int y, int z, int a, int m,
+                                int n_sub, const unsigned char *__restrict__ faulty) {
+    double sum = 0.0;
+    const int P[3] = {x, y, z};
+    for (int dd = 0; dd < 8; dd++) {
+        const int dl[3] = {dd & 1, (dd >> 1) & 1, (dd >> 2) & 1};
+        if (dl[a]) continue;
+        const int c[3] = {P[0] - dl[0], P[1] - dl[1], P[2] - dl[2]};
+        if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= N || c[1] >= N || c[2] >= N) continue;
+        const int ns = dl[0] + dl[1] + dl[2];
+        for (int q = 0; q < 6; q++) {
+            bool ok = kPermD[q][ns] == a;
+            for (int s = 0; s < ns; s++) ok = ok && dl[kPermD[q][s]];
+            if (!ok || faulty[macro_tet_of(c[0], c[1], c[2], q, m, n_sub)]) continue;
+            sum += k ? k[6LL * (c[0] + (long long)N * (c[1] + (long long)N * c[2])) + q] : 1.0;
+        }
+    }
+    return sum * h / 6.0;
+}
+
+__global__ void k_ifc_weights_intact(int n_ifc, const int *__restrict__ xyz, int N, int m, int n_sub, double h,
+                                     const double *__restrict__ k, const unsigned char *__restrict__ faulty,
+                                     double *__restrict__ wi) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ifc) return;
+    const int x = xyz[3 * t], y = xyz[3 * t + 1], z = xyz[3 * t + 2];
+    const int X[3] = {x, y, z};
+    for (int a = 0; a < 3; a++) {
+        int Xm[3] = {x, y, z};
+        Xm[a] -= 1;
+        wi[(long long)(2 * a) * n_ifc + t] = X[a] < N ? edge_w_intact(k, N, h, x, y, z, a, m, n_sub, faulty) : 0.0;
+        wi[(long long)(2 * a + 1) * n_ifc + t] =
+            X[a] > 0 ? edge_w_intact(k, N, h, Xm[0], Xm[1], Xm[2], a, m, n_sub, faulty) : 0.0;
+    }
+}
+
+__global__ void k_coarse_vals_intact(int n, const int *__restrict__ pos, const int *__restrict__ col, int N, int m,
+                                     int n_sub, double h, const double *__restrict__ k,
+                                     const unsigned char *__restrict__ faulty, double *__restrict__ val) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int x = pos[3 * q], y = pos[3 * q + 1], z = pos[3 * q + 2];
+    double diag = 0.0;
+    for (int a = 0; a < 3; a++) {
+        int Xm[3] = {x, y, z};
+        Xm[a] -= 1;
+        const double wp = edge_w_intact(k, N, h, x, y, z, a, m, n_sub, faulty);
+        const double wm = edge_w_intact(k, N, h, Xm[0], Xm[1], Xm[2], a, m, n_sub, faulty);
+        diag += wp + wm;
+        val[7 * q + 1 + 2 * a] = col[7 * q + 1 + 2 * a] >= 0 ? -wp : 0.0;
+        val[7 * q + 2 + 2 * a] = col[7 * q + 2 + 2 * a] >= 0 ? -wm : 0.0;
+    }
+    val[7 * q] = diag;
+}
+
+// static Neumann data of the intact side on the interface (Alg. 2): at the
+// nodes flagged in gamma, b_out = (A^I u) from the intact-side weights wi
+__global__ void k_neumann_rhs(int n_ifc, long long base, const int *__restrict__ nbr, const double *__restrict__ wi,
+                              const unsigned char *__restrict__ gamma, const double *__restrict__ u,
+                              double *__restrict__ b_out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ifc || !gamma[t]) return;
+    const long long sl = base + t;
+    const double uo = u[sl];
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 6; e++) s += wi[(long long)e * n_ifc + t] * (uo - u[nbr[(long long)e * n_ifc + t]]);
+    b_out[sl] = s;
+}
+
 // dJ/dk_T = -(h/6) sum over the 3 path edges (a,b) of T of (lam_a - lam_b)(u_a - u_b)
 __global__ void k_grad_k(const double *__restrict__ u, const double *__restrict__ lam, int N, double h,
                          double *__restrict__ out) {
@@ -1034,6 +1128,27 @@ void launch_coarse_vals(hipStream_t s, int n, const int *pos, const int *col, in
                         double *val) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_coarse_vals, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, col, N, h, k, val);
+}
+
+void launch_ifc_weights_intact(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, int m, int n_sub, double h,
+                               const double *k, const unsigned char *faulty, double *wi) {
+    if (n_ifc <= 0) return;
+    hipLaunchKernelGGL(k_ifc_weights_intact, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, ifc_xyz, N, m, n_sub, h,
+                       k, faulty, wi);
+}
+
+void launch_coarse_vals_intact(hipStream_t s, int n, const int *pos, const int *col, int N, int m, int n_sub, double h,
+                               const double *k, const unsigned char *faulty, double *val) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_coarse_vals_intact, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, col, N, m, n_sub, h, k,
+                       faulty, val);
+}
+
+void launch_neumann_rhs(hipStream_t s, int n_ifc, long long base, const int *nbr, const double *wi,
+                        const unsigned char *gamma, const double *u, double *b_out) {
+    if (n_ifc <= 0) return;
+    hipLaunchKernelGGL(k_neumann_rhs, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, base, nbr, wi, gamma, u,
+                       b_out);
 }
 
 void launch_grad_k(hipStream_t s, const double *u, const double *lam, int N, double h, double *out) {

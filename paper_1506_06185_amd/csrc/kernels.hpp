@@ -127,6 +127,17 @@ void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, dou
 void launch_coarse_vals(hipStream_t s, int n, const int *pos, const int *col, int N, double h, const double *k,
                         double *val);
 
+// Dirichlet-Neumann recovery: interface and coarsest-level operators over the
+// elements of intact macro tetrahedra only (k == nullptr: k = 1; faulty[t] for
+// each macro tetrahedron), and the static Neumann data b_out = A^I u at the
+// interface nodes flagged in gamma
+void launch_ifc_weights_intact(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, int m, int n_sub, double h,
+                               const double *k, const unsigned char *faulty, double *wi);
+void launch_coarse_vals_intact(hipStream_t s, int n, const int *pos, const int *col, int N, int m, int n_sub, double h,
+                               const double *k, const unsigned char *faulty, double *val);
+void launch_neumann_rhs(hipStream_t s, int n_ifc, long long base, const int *nbr, const double *wi,
+                        const unsigned char *gamma, const double *u, double *b_out);
+
 // dJ/dk per element from user-order u and lambda
 void launch_grad_k(hipStream_t s, const double *u, const double *lam, int N, double h, double *out);
 

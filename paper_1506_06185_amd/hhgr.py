@@ -68,6 +68,7 @@ def lib():
         "hhgr_solve": (C.c_int, [_vp, C.c_double, C.c_int, C.POINTER(Report)]),
         "hhgr_inject_fault": (C.c_int, [_vp, C.c_int]),
         "hhgr_recover_local": (C.c_int, [_vp, C.c_int, C.c_int, _dp]),
+        "hhgr_recover_dn": (C.c_int, [_vp, _ip, C.c_int, C.c_int, C.c_int]),
         "hhgr_recover_dd": (C.c_int, [_vp, _ip, C.c_int, C.c_int, C.c_int]),
         "hhgr_adjoint_grad": (C.c_int, [_vp, _vp, C.c_double, C.c_int, _vp, _vp]),
         "hhgr_mass_apply": (C.c_int, [_vp, _vp, _vp]),
@@ -94,7 +95,7 @@ def lib():
 
 EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_destroy", "hhgr_sizes",
             "hhgr_set_rhs", "hhgr_set_coeff", "hhgr_set_solution", "hhgr_get_solution", "hhgr_vcycle",
-            "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_adjoint_grad",
+            "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_recover_dn", "hhgr_adjoint_grad",
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_last_error")
@@ -210,6 +211,12 @@ class Context:
     def recover_dd(self, tets, n_intact: int, n_local: int):
         arr = (C.c_int * len(tets))(*[int(t) for t in tets])
         _check(lib().hhgr_recover_dd(self._h, arr, len(tets), int(n_intact), int(n_local)))
+
+    def recover_dn(self, tets, n_intact: int, eta: int = 1):
+        """Dirichlet-Neumann recovery (Alg. 2) of faulty tets: n_intact rounds of eta local
+        cycles beside one intact Neumann cycle."""
+        arr = (C.c_int * len(tets))(*[int(t) for t in tets])
+        _check(lib().hhgr_recover_dn(self._h, arr, len(tets), int(n_intact), int(eta)))
 
     def adjoint_grad(self, g: torch.Tensor, rel_tol: float = 1e-13, max_cycles: int = 100, want_k: bool = True):
         dJdf = self._vec()

@@ -60,6 +60,10 @@ int main() {
     CHECK(hhgr_recover_dd(cs[0].h, t2, 2, 2, 3) == HHGR_OK, "recover_dd: %s", hhgr_last_error());
     CHECK(hhgr_recover_local(cs[1].h, 5, 2, &rr) == HHGR_OK, "recover_local");
     for (int t : t2) hhgr_inject_fault(cs[0].h, t);
+    CHECK(hhgr_recover_dn(cs[0].h, t2, 2, 3, 2) == HHGR_OK, "recover_dn: %s", hhgr_last_error());
+    CHECK(hhgr_recover_dn(cs[0].h, t2, 2, -1, 2) == HHGR_EINVAL, "recover_dn bad count");
+    CHECK(hhgr_vcycle(cs[0].h, 1, &rr) == HHGR_OK, "vcycle after dn");
+    for (int t : t2) hhgr_inject_fault(cs[0].h, t);
     int t1 = 4;
     hhgr_inject_fault(cs[2].h, t1);
     std::vector<hhgr_ctx *> hs;

@@ -76,6 +76,12 @@ void launch_vol_weights(hipStream_t, const VolGeom &, const int *, int, int, dou
 void launch_ifc_weights(hipStream_t, int, const int *, int, double, const double *, double *) {}
 void launch_coarse_vals(hipStream_t, int, const int *, const int *, int, double, const double *, double *) {}
 void launch_grad_k(hipStream_t, const double *, const double *, int, double, double *) {}
+void launch_ifc_weights_intact(hipStream_t, int, const int *, int, int, int, double, const double *,
+                               const unsigned char *, double *) {}
+void launch_coarse_vals_intact(hipStream_t, int, const int *, const int *, int, int, int, double, const double *,
+                               const unsigned char *, double *) {}
+void launch_neumann_rhs(hipStream_t, int, long long, const int *, const double *, const unsigned char *,
+                        const double *, double *) {}
 
 template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
                                     const Weights<double> &, bool, double, double, bool, bool);

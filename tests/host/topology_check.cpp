@@ -2,6 +2,7 @@
 // arithmetic that the volume kernels use (replicated here in plain C++):
 // every table entry is in range, every neighbour/transfer offset computed in
 // a kernel names the same slot as the topology's independent grid lookup.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -92,6 +93,43 @@ static void check_layout(int m) {
     }
 }
 
+// replica of the device mapping fine element (cell, permutation q) -> macro
+// tetrahedron used by the Dirichlet-Neumann operators
+static const int kPermH[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+static int perm_id_h(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : a == 1 ? (b == 0 ? 2 : 3) : (b == 0 ? 4 : 5); }
+static int macro_tet_of(int cx, int cy, int cz, int q, int m, int n_sub) {
+    const int C[3] = {cx / m, cy / m, cz / m};
+    int D[3] = {4 * (cx - m * C[0]), 4 * (cy - m * C[1]), 4 * (cz - m * C[2])};
+    D[kPermH[q][0]] += 3;
+    D[kPermH[q][1]] += 2;
+    D[kPermH[q][2]] += 1;
+    const int a0 = D[0] > D[1] ? (D[0] > D[2] ? 0 : 2) : (D[1] > D[2] ? 1 : 2);
+    const int a2 = D[0] < D[1] ? (D[0] < D[2] ? 0 : 2) : (D[1] < D[2] ? 1 : 2);
+    return 6 * (C[0] + n_sub * (C[1] + n_sub * C[2])) + perm_id_h(a0, 3 - a0 - a2);
+}
+
+// every vertex of every fine element lies in the closed macro tetrahedron the
+// mapping names (grid position X of the vertex: X - m V0 sorted along the
+// macro tet's axis order is a non-increasing sequence in [0, m])
+static void check_element_macro(const Topology &tp, int l) {
+    const int m = 1 << l, N = tp.n_sub * m;
+    for (int cz = 0; cz < N; cz++)
+        for (int cy = 0; cy < N; cy++)
+            for (int cx = 0; cx < N; cx++)
+                for (int q = 0; q < 6; q++) {
+                    const int t = macro_tet_of(cx, cy, cz, q, m, tp.n_sub);
+                    CHECK(t >= 0 && t < tp.n_tets, "macro tet range");
+                    int X[3] = {cx, cy, cz};
+                    for (int v = 0; v < 4; v++) {
+                        if (v > 0) X[kPermH[q][v - 1]] += 1;
+                        int D[3];
+                        for (int a = 0; a < 3; a++) D[a] = X[a] - m * tp.V0[t][a];
+                        const int d0 = D[tp.perm[t][0]], d1 = D[tp.perm[t][1]], d2 = D[tp.perm[t][2]];
+                        CHECK(m >= d0 && d0 >= d1 && d1 >= d2 && d2 >= 0, "element vertex in macro tet l=%d", l);
+                    }
+                }
+}
+
 int main(int argc, char **argv) {
     for (int lv = 2; lv <= 8; lv++) check_layout(1 << lv);
     int n_sub = argc > 1 ? std::atoi(argv[1]) : 2;
@@ -100,6 +138,7 @@ int main(int argc, char **argv) {
     std::string e = tp.build(n_sub, L, 2);
     CHECK(e.empty(), "build: %s", e.c_str());
     if (!e.empty()) return 1;
+    for (int l = 0; l <= std::min(L, 4); l++) check_element_macro(tp, l);
     for (int l = tp.Lc; l <= L; l++) {
         const TopoLevel &T = tp.lev[l];
         const int m = T.m;

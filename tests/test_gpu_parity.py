@@ -330,3 +330,38 @@ def test_batch_with_dd_recovery(dev, hh, oracle_problem):
     batch.close()
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("case", ["k1", "variable-k", "mixed-context"])
+def test_dirichlet_neumann_recovery(dev, hh, case):
+    """Alg. 2 on the GPU (intact Neumann cycles beside local Dirichlet cycles,
+    interface refreshed per round) equals the oracle's rounds, then global cycles."""
+    n_sub, level = 2, (4 if case == "variable-k" else 5)
+    print(f"\n[recover_dn] {case} n_sub={n_sub} level={level}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=1) if case == "variable-k" else None
+    p = oracle.Problem(n_sub, level, k=k)
+    b = inputs.uniform_load(n_sub, level, seed=7)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=k is not None,
+                     precision="mixed" if case == "mixed-context" else "fp64")
+    if k is not None:
+        ctx.set_coeff(T(k, dev))
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    u = np.zeros_like(b)
+    if case != "mixed-context":
+        ctx.vcycle(4)
+        u, _, _ = p.solve(b, rtol=0.0, max_cycles=4)
+    else:
+        ctx.set_solution(T(u, dev))
+    tets = [int(t) for t in inputs.batch_faults(2, n_sub, seed=5)]
+    for t in tets:
+        ctx.inject_fault(t)
+        u = p.inject_fault(t, u)
+    ctx.recover_dn(tets, 3, 2)
+    u = p.dn_recover(tets, u, b, n_intact=3, eta=2)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    if case != "mixed-context":
+        ctx.vcycle(2)
+        u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=2)
+        assert rel(N(ctx.get_solution()), u) < 1e-12
+    ctx.close()
+    p.close()
