@@ -231,6 +231,21 @@ class Problem:
                                    {"intact": 0, "faulty": 1}[side])
         return self._fetch_matrix(h)
 
+    def dirichlet_load(self, g, level: int | None = None) -> np.ndarray:
+        """Right-hand side of eq. (2) for Laplace's equation with Dirichlet data,
+        eq. (1) (Sec. 2.1): the stiffness matrix assembled over all grid
+        vertices, applied to g restricted to the boundary vertices, negated,
+        on the interior rows.  g holds the (N+1)^3 vertex values, x fastest;
+        its interior entries are ignored."""
+        level = self.level if level is None else level
+        N = self.n_sub << level
+        g = _f64(g).reshape(N + 1, N + 1, N + 1)  # [z, y, x]
+        gb = g.copy()
+        gb[1:-1, 1:-1, 1:-1] = 0.0
+        A = self.matrix(level, "A", full=True)
+        full = -(A @ gb.ravel())
+        return np.ascontiguousarray(full.reshape(N + 1, N + 1, N + 1)[1:-1, 1:-1, 1:-1].ravel())
+
     # -- operators ----------------------------------------------------------
     def apply_A(self, u, level: int | None = None) -> np.ndarray:
         level = self.level if level is None else level
