@@ -55,7 +55,7 @@ enum {
 };
 
 enum { HHGR_FP64 = 0, HHGR_MIXED = 1 };
-enum { HHGR_RHS_LOAD = 0, HHGR_RHS_NODAL_F = 1 };
+enum { HHGR_RHS_LOAD = 0, HHGR_RHS_NODAL_F = 1, HHGR_RHS_DIRICHLET = 2 };
 
 /* Solver description.  hhgr_desc_default fills the defaults shown. */
 typedef struct {
@@ -100,8 +100,17 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
 /* Right-hand side of eq. (2) from a device vector in the vector order above.
  * kind = HHGR_RHS_LOAD: the vector is the load vector b itself;
  * kind = HHGR_RHS_NODAL_F: the vector holds nodal values of f (zero on the
- * boundary) and b = M f with the consistent P1 mass matrix.  Also records
- * ||b|| as the reference for relative residuals. */
+ * boundary) and b = M f with the consistent P1 mass matrix;
+ * kind = HHGR_RHS_DIRICHLET: Laplace's equation with inhomogeneous Dirichlet
+ * data, eq. (1) (f = 0, u = g on the boundary).  The vector holds the values
+ * of the (N+1)^3 grid nodes, node (x,y,z), 0 <= x,y,z <= N, at index
+ * x + (N+1)*(y + (N+1)*z); only the boundary entries (g) are read.  The known
+ * boundary values are moved to the right-hand side as in eq. (2):
+ * b_i = sum over the axis neighbours j of node i on the boundary of
+ * w_ij g_j, w_ij = h for k = 1, else the edge weight of the coefficient set
+ * by hhgr_set_coeff (ESTATE if none was set; a later hhgr_set_coeff does not
+ * update b).  The solution holds the interior values; g is not stored.
+ * Every kind records ||b|| as the reference for relative residuals. */
 int hhgr_set_rhs(hhgr_ctx *ctx, const double *dev_vec, int kind);
 
 /* Per-element diffusion coefficient (device, element order, length 6 N^3,

@@ -1076,13 +1076,21 @@ int hhgr_sizes(const hhgr_ctx *c, long long *n_dofs, int *n_tets, long long *n_e
 
 int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     if (!c || !dev_vec) return fail(HHGR_EINVAL, "null argument");
-    if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F) return fail(HHGR_EINVAL, "bad rhs kind");
+    if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F && kind != HHGR_RHS_DIRICHLET)
+        return fail(HHGR_EINVAL, "bad rhs kind");
+    if (kind == HHGR_RHS_DIRICHLET && c->vk && !c->coeff_set)
+        return fail(HHGR_ESTATE, "Dirichlet data with variable_coeff = 1 needs hhgr_set_coeff first");
     LevelDev &D = c->lev[c->L];
     const VolGeom vfull = vgeom(D, D.vd_all, c->n_tets, true);
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     if (kind == HHGR_RHS_LOAD) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.b);
+    } else if (kind == HHGR_RHS_DIRICHLET) {
+        // the load in vector order goes through aux_u (n_slots >= (N-1)^3 entries)
+        if (D.n_slots < (long long)(D.N - 1) * (D.N - 1) * (D.N - 1)) return fail(HHGR_EINVAL, "aux buffer too small");
+        launch_dirichlet_load(c->stream, D.N, D.h, c->vk ? D.kc : nullptr, dev_vec, c->aux_u);
+        launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
     } else {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.r);
         launch_mass(c->stream, vint, ig, D.nb15, D.r, D.b, D.h);

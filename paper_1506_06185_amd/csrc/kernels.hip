@@ -794,6 +794,32 @@ __global__ void k_coarse_vals(int n, const int *__restrict__ pos, const int *__r
     val[7 * q] = diag;
 }
 
+// Inhomogeneous Dirichlet data of eq. (1) moved to the right-hand side: an
+// interior node couples only to its six axis neighbours (the other edges of a
+// Kuhn simplex carry zero stiffness), so b_i = sum of w_ij g_j over those axis
+// neighbours j that lie on the cube's boundary, w_ij = h for k = 1 (k null)
+// and the edge weight of the coefficient otherwise.  Output in vector order.
+__global__ void k_dirichlet_load(int N, double h, const double *__restrict__ k, const double *__restrict__ g,
+                                 double *__restrict__ b) {
+    const long long n1 = N - 1;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n1 * n1 * n1) return;
+    const int P[3] = {(int)(t % n1) + 1, (int)((t / n1) % n1) + 1, (int)(t / (n1 * n1)) + 1};
+    const long long M = N + 1;
+    double s = 0.0;
+    for (int a = 0; a < 3; a++) {
+        for (int side = -1; side <= 1; side += 2) {
+            int X[3] = {P[0], P[1], P[2]};
+            X[a] += side;
+            if (X[a] != 0 && X[a] != N) continue;
+            const int *lo = side < 0 ? X : P;
+            const double w = k ? edge_w(k, N, h, lo[0], lo[1], lo[2], a) : h;
+            s += w * g[X[0] + M * (X[1] + M * (long long)X[2])];
+        }
+    }
+    b[t] = s;
+}
+
 // Dirichlet-Neumann recovery (Sec. 4.3, eq. (5)): the intact side's
 // sub-stencils are the stiffness assembled over the elements of intact macro
 // tetrahedra only.  Fine element (cell c, permutation q) at a level with m
@@ -1122,6 +1148,12 @@ void launch_vol_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo,
 void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, double h, const double *k, double *wi) {
     if (n_ifc <= 0) return;
     hipLaunchKernelGGL(k_ifc_weights, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, ifc_xyz, N, h, k, wi);
+}
+
+void launch_dirichlet_load(hipStream_t s, int N, double h, const double *k, const double *g, double *b) {
+    const long long n = (long long)(N - 1) * (N - 1) * (N - 1);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_dirichlet_load, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, h, k, g, b);
 }
 
 void launch_coarse_vals(hipStream_t s, int n, const int *pos, const int *col, int N, double h, const double *k,

@@ -124,6 +124,8 @@ void launch_coarsen_k(hipStream_t s, const double *kf, int Nf, double *kc, int N
 void launch_vol_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo, int m, int N, double h,
                         const double *k, double *w0, double *w1, double *w2);
 void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, double h, const double *k, double *wi);
+// b = eliminated Dirichlet data g (full (N+1)^3 grid, x fastest), vector order
+void launch_dirichlet_load(hipStream_t s, int N, double h, const double *k, const double *g, double *b);
 void launch_coarse_vals(hipStream_t s, int n, const int *pos, const int *col, int N, double h, const double *k,
                         double *val);
 

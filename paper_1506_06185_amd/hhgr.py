@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhhgr.so")
 
 HHGR_OK, HHGR_EINVAL, HHGR_ENOMEM, HHGR_EHIP, HHGR_ESTATE, HHGR_ENOCONV = 0, -1, -2, -3, -4, -5
 HHGR_FP64, HHGR_MIXED = 0, 1
-HHGR_RHS_LOAD, HHGR_RHS_NODAL_F = 0, 1
+HHGR_RHS_LOAD, HHGR_RHS_NODAL_F, HHGR_RHS_DIRICHLET = 0, 1, 2
 _CODES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENOCONV"}
 
 
@@ -149,6 +149,7 @@ class Context:
         nd, nt, ne = C.c_longlong(), C.c_int(), C.c_longlong()
         _check(lib().hhgr_sizes(self._h, C.byref(nd), C.byref(nt), C.byref(ne)))
         self.n_dofs, self.n_tets, self.n_elems = int(nd.value), int(nt.value), int(ne.value)
+        self.N = self.desc.n_sub << self.desc.level
         self.workspace_nbytes = nbytes
 
     @property
@@ -170,6 +171,9 @@ class Context:
         return torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
 
     def set_rhs(self, vec: torch.Tensor, kind: int = HHGR_RHS_LOAD):
+        want = (self.N + 1) ** 3 if kind == HHGR_RHS_DIRICHLET else self.n_dofs
+        if vec.numel() != want:
+            raise HHGRError(HHGR_EINVAL, f"right-hand side has {vec.numel()} entries, expected {want}")
         _check(lib().hhgr_set_rhs(self._h, _ptr(vec), int(kind)))
         self._keep_rhs = vec
 

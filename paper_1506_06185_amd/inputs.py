@@ -1,8 +1,9 @@
 """Seeded synthetic inputs for the unit-cube workloads.
 
 This module is shared by the GPU path's callers (tests, benchmark) and by the
-oracle-side tests.  It holds no multigrid arithmetic: only random draws and
-point evaluations of the source function, returned in the user-facing orders
+oracle-side tests.  It holds no multigrid arithmetic: only random draws,
+point evaluations of the source and boundary functions and the macro-mesh
+geometry that places a fault, returned in the user-facing orders
 
 * interior nodes: global lexicographic, index = (x-1) + (N-1)*((y-1) + (N-1)*(z-1)),
   x fastest, with N = n_sub * 2**level cells per axis and h = 1/N;
@@ -126,3 +127,74 @@ def batch_member_faults(n_members: int, n_faulty: int, n_sub: int, seed: int = 0
     members = np.sort(g.choice(n_members, size=n_faulty, replace=False))
     tets = g.integers(n_macro_tets(n_sub), size=n_faulty)
     return [(int(m), int(t)) for m, t in zip(members, tets)]
+
+
+def harmonic_boundary(n_sub: int, level: int) -> np.ndarray:
+    """Dirichlet data g = 1 + x^2 + 2 y^2 - 3 z^2 + x y at all (N+1)^3 grid
+    vertices, index x + (N+1)*(y + (N+1)*z) with x fastest (the solver reads
+    only the boundary entries).  g is harmonic, so it is also the exact
+    solution of Laplace's equation with these boundary values."""
+    N = cells_per_axis(n_sub, level)
+    t = np.arange(N + 1, dtype=np.float64) / N
+    z, y, x = t[:, None, None], t[None, :, None], t[None, None, :]
+    g = 1.0 + x * x + 2.0 * y * y - 3.0 * z * z + x * y
+    return np.ascontiguousarray(g.reshape(-1))
+
+
+_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def macro_tet_vertices(n_sub: int, tet: int):
+    """The 4 vertices of a macro tetrahedron in subcube units: its subcube's
+    lowest corner, then one unit step along each axis of its permutation."""
+    cube, perm = divmod(int(tet), 6)
+    v = [cube % n_sub, (cube // n_sub) % n_sub, cube // (n_sub * n_sub)]
+    out = [tuple(v)]
+    for a in _PERMS[perm]:
+        v[a] += 1
+        out.append(tuple(v))
+    return out
+
+
+def boundary_contact(n_sub: int, tet: int):
+    """(faces, edges, vertices) of a macro tetrahedron that lie on the cube's
+    boundary: a simplex of vertices lies there when they share a coordinate
+    equal to 0 or n_sub."""
+    from itertools import combinations
+
+    vs = macro_tet_vertices(n_sub, tet)
+
+    def on_boundary(pts):
+        return any(all(p[a] == side for p in pts) for a in range(3) for side in (0, n_sub))
+
+    return tuple(sum(on_boundary(c) for c in combinations(vs, k)) for k in (3, 2, 1))
+
+
+# fault scenarios of the recovery-strategy comparison: mesh size and the
+# geometric position of the faulty macro tetrahedron
+SCENARIOS = {
+    "I": dict(n_sub=1, about="two faces on the boundary"),
+    "II": dict(n_sub=2, about="one edge on the boundary, no face"),
+    "III": dict(n_sub=3, about="no vertex on the boundary (floating)"),
+}
+
+
+def scenario_fault_tet(name: str) -> int:
+    """Lowest-numbered macro tetrahedron matching the scenario's description."""
+    n = SCENARIOS[name]["n_sub"]
+    want = {"I": lambda f, e, v: f == 2, "II": lambda f, e, v: f == 0 and e == 1,
+            "III": lambda f, e, v: v == 0}[name]
+    for t in range(n_macro_tets(n)):
+        if want(*boundary_contact(n, t)):
+            return t
+    raise ValueError(f"no macro tetrahedron fits scenario {name}")
+
+
+def second_fault_tet(n_sub: int, first: int) -> int:
+    """Lowest-numbered macro tetrahedron with no face on the boundary that shares
+    no vertex with ``first`` (the later fault of a two-fault sequence)."""
+    vs = set(macro_tet_vertices(n_sub, first))
+    for t in range(n_macro_tets(n_sub)):
+        if boundary_contact(n_sub, t)[0] == 0 and not vs & set(macro_tet_vertices(n_sub, t)):
+            return t
+    raise ValueError("no separated macro tetrahedron")

@@ -1,0 +1,255 @@
+"""Recovery-strategy comparison on one GPU through the C ABI (Sec. 4.4,
+Tables 1 and 2; the fault sequences of Sec. 5, Tables 3 and 4, counted in
+iterations and in this GPU's seconds).
+
+A job solves Laplace's equation with Dirichlet data g, eq. (1), from u = 0
+until ||b - A u|| <= tol ||b||.  Fault events strike after a given iteration;
+the iteration counter counts global V-cycles and, for every recovery, its n_I
+steps, so that k_faulty is the number of global cycles plus n_I (Sec. 4.4).
+Strategies of an event:
+
+* ``none``: do-nothing, the lost values stay zero (Sec. 2.2);
+* ``LR``:   local recovery, n_F local V-cycles on the faulty tetrahedra while
+            the intact part waits n_I steps (Sec. 4.4);
+* ``DD``:   Dirichlet-Dirichlet, n_I intact cycles with the faulty closures
+            frozen and n_F local cycles at the same time (Alg. 1);
+* ``DN``:   Dirichlet-Neumann, n_I rounds of eta local cycles and one intact
+            Neumann cycle (Alg. 2, eq. (5)).
+
+A superman of speed-up eta does n_F = ceil(eta n_I) local cycles in the time
+of n_I global ones; the cycle advantage is kappa = (k_faulty - k_free) / k_F,
+eq. (3).  Every numerical step runs in the library; this module only
+sequences calls.
+
+Run ``python -m paper_1506_06185_amd.study --help`` for the command line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass
+
+import torch
+
+from . import hhgr, inputs
+
+STRATEGIES = ("LR", "DD", "DN")
+
+
+@dataclass(frozen=True)
+class Fault:
+    after: int          # iteration count at which the fault strikes
+    tets: tuple         # faulty macro tetrahedra
+    strategy: str = "none"
+    n_I: int = 0
+    eta: float = 1.0
+
+    @property
+    def n_F(self) -> int:
+        return math.ceil(self.n_I * self.eta - 1e-12)
+
+    @property
+    def steps(self) -> int:
+        """Iterations the recovery adds to the count."""
+        return 0 if self.strategy == "none" else self.n_I
+
+
+class Runner:
+    """Runs jobs on one context; the state after the first k cycles of the
+    fault-free job is kept, so jobs that share a fault-free prefix restart from
+    it (the same state the prefix would produce again)."""
+
+    def __init__(self, ctx: hhgr.Context, tol: float, max_cycles: int = 100):
+        self.ctx, self.tol, self.max_cycles = ctx, float(tol), int(max_cycles)
+        self._prefix = {}
+
+    def _sync(self):
+        self.ctx.stream.synchronize()
+
+    def prefix(self, k: int) -> torch.Tensor:
+        if k not in self._prefix:
+            self.ctx.set_solution(torch.zeros(self.ctx.n_dofs, dtype=torch.float64, device=self.ctx.device))
+            if k:
+                self.ctx.vcycle(k)
+            self._prefix[k] = self.ctx.get_solution()
+        return self._prefix[k]
+
+    def free(self):
+        """Fault-free job: (k_free, history, seconds)."""
+        self.ctx.set_solution(self.prefix(0))
+        self._sync()
+        t0 = time.perf_counter()
+        cyc, rr, hist = self.ctx.solve(self.tol, self.max_cycles)
+        self._sync()
+        return cyc, list(hist), time.perf_counter() - t0
+
+    def faulty(self, faults):
+        """Job with the fault events ``faults``: (k_faulty, final residual
+        history, seconds from the first fault to the end)."""
+        faults = sorted(faults, key=lambda f: f.after)
+        it = faults[0].after
+        self.ctx.set_solution(self.prefix(it))
+        self._sync()
+        t0 = time.perf_counter()
+        for i, f in enumerate(faults):
+            if f.after < it:
+                raise ValueError("fault events overlap a recovery")
+            if f.after > it:
+                self.ctx.vcycle(f.after - it)
+                it = f.after
+            for t in f.tets:
+                self.ctx.inject_fault(int(t))
+            if f.steps:
+                if f.strategy == "LR":
+                    for t in f.tets:
+                        self.ctx.recover_local(int(t), f.n_F)
+                elif f.strategy == "DD":
+                    self.ctx.recover_dd(list(f.tets), f.n_I, f.n_F)
+                elif f.strategy == "DN":
+                    if f.eta != int(f.eta):
+                        raise ValueError("Dirichlet-Neumann rounds need an integer eta")
+                    self.ctx.recover_dn(list(f.tets), f.n_I, int(f.eta))
+                else:
+                    raise ValueError(f"unknown strategy {f.strategy}")
+            it += f.steps
+        cyc, rr, hist = self.ctx.solve(self.tol, self.max_cycles - it, raise_on_noconv=False)
+        self._sync()
+        if rr > self.tol:
+            raise RuntimeError(f"job did not reach {self.tol} in {self.max_cycles} iterations")
+        return it + cyc, list(hist), time.perf_counter() - t0
+
+
+def kappa(k_faulty: int, k_free: int, k_F: int) -> float:
+    """Relative cycle advantage, eq. (3)."""
+    return (k_faulty - k_free) / k_F
+
+
+def make_context(n_sub: int, level: int, device=None, tune: bool = True, tune_cache: str | None = None):
+    """FP64 context with the Dirichlet data of ``inputs.harmonic_boundary``."""
+    dev = torch.device("cuda:0") if device is None else torch.device(device)
+    ctx = hhgr.Context(device=dev, n_sub=n_sub, level=level)
+    if tune:
+        ctx.autotune(tune_cache)
+    g = torch.from_numpy(inputs.harmonic_boundary(n_sub, level)).to(dev)
+    ctx.set_rhs(g, hhgr.HHGR_RHS_DIRICHLET)
+    return ctx
+
+
+def kappa_table(runner: Runner, tet: int, k_F: int, etas, n_Is, strategies=STRATEGIES):
+    """k_faulty and kappa for every (eta, n_I, strategy); n_I = 0 is the
+    do-nothing job.  Returns {"k_free", "rows": [{eta, n_I, strategy, k, kappa}]}."""
+    k_free, _, _ = runner.free()
+    k_none, _, _ = runner.faulty([Fault(k_F, (tet,))])
+    rows = []
+    for eta in etas:
+        for n_I in n_Is:
+            for s in strategies:
+                k = runner.faulty([Fault(k_F, (tet,), s, n_I, eta)])[0] if n_I else k_none
+                rows.append(dict(eta=eta, n_I=n_I, strategy=s, k=k, kappa=kappa(k, k_free, k_F)))
+    return dict(k_free=k_free, k_F=k_F, rows=rows)
+
+
+def sequence_table(runner: Runner, events, etas, n_Is, strategies=("DD", "DN"), repeats: int = 2, log=None):
+    """Extra iterations and extra seconds on this GPU, relative to the
+    fault-free job, of jobs whose faults strike at ``events`` = [(after, tet),
+    ...], all recovered with the same strategy, n_I and eta (n_I = 0: none).
+    Seconds are the best of ``repeats`` runs of the part from the first fault
+    on, against the same part of the fault-free job."""
+    k_free, _, _ = runner.free()
+    first = events[0][0]
+
+    def best(fn):
+        out = None
+        for _ in range(repeats):
+            r = fn()
+            out = r if out is None or r[-1] < out[-1] else out
+        return out
+
+    def free_tail():
+        runner.ctx.set_solution(runner.prefix(first))
+        runner._sync()
+        t0 = time.perf_counter()
+        cyc, _, _ = runner.ctx.solve(runner.tol, runner.max_cycles)
+        runner._sync()
+        return cyc, time.perf_counter() - t0
+
+    _, t_free = best(free_tail)
+    rows = []
+    for eta in etas:
+        for n_I in n_Is:
+            for s in strategies:
+                fs = [Fault(a, (t,), s if n_I else "none", n_I, eta) for a, t in events]
+                k, _, sec = best(lambda: runner.faulty(fs))
+                rows.append(dict(eta=eta, n_I=n_I, strategy=s, k=k, extra_k=k - k_free, extra_s=sec - t_free))
+                if log:
+                    log(f"  {s} eta={eta:g} n_I={n_I}: +{k - k_free} iterations, {(sec - t_free) * 1e3:+.1f} ms")
+    return dict(k_free=k_free, events=[list(e) for e in events], free_tail_s=t_free, rows=rows)
+
+
+def format_kappa(table) -> str:
+    """Rows n_I, columns LR DD DN, one block per eta (the layout of Tables 1-2)."""
+    out = []
+    etas = sorted({r["eta"] for r in table["rows"]})
+    strategies = [s for s in STRATEGIES if any(r["strategy"] == s for r in table["rows"])]
+    for eta in etas:
+        out.append(f"  eta={eta:g}  (k_free={table['k_free']}, k_F={table['k_F']})   n_I: " + " ".join(f"{s:>5}" for s in strategies))
+        for n_I in sorted({r["n_I"] for r in table["rows"]}):
+            vals = {r["strategy"]: r["kappa"] for r in table["rows"] if r["eta"] == eta and r["n_I"] == n_I}
+            out.append(f"  {'':>44}{n_I:>3}: " + " ".join(f"{vals[s]:5.2f}" for s in strategies))
+    return "\n".join(out)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--level", type=int, default=7, help="refinement level of every scenario")
+    ap.add_argument("--tol", type=float, default=1e-13, help="relative residual of the stopping rule")
+    ap.add_argument("--scenarios", default="I,II,III")
+    ap.add_argument("--sequence-level", type=int, default=8,
+                    help="level of the two-fault sequence on the 162-tet mesh (0 = skip)")
+    ap.add_argument("--out", default=None, help="JSON file for the results")
+    a = ap.parse_args(argv)
+    res = dict(level=a.level, tol=a.tol, scenarios={})
+    for sc in a.scenarios.split(","):
+        n, tet = inputs.SCENARIOS[sc]["n_sub"], inputs.scenario_fault_tet(sc)
+        ctx = make_context(n, a.level)
+        run = Runner(ctx, a.tol)
+        entry = dict(n_sub=n, tet=tet, n_dofs=ctx.n_dofs, tables=[])
+        # the fault-free residual history down to the rounding floor
+        ctx.set_solution(run.prefix(0))
+        _, _, hist = ctx.solve(0.0, 24, raise_on_noconv=False)
+        entry["floor_history"] = list(hist)
+        print(f"Scenario {sc}: fault-free history " + " ".join(f"{x:.1e}" for x in hist), flush=True)
+        for k_F, n_max in ((5, 4), (11, 6)):
+            t = kappa_table(run, tet, k_F, (2, 5), range(n_max + 1))
+            entry["tables"].append(t)
+            print(f"Scenario {sc}: {ctx.n_dofs} unknowns, fault in tet {tet}\n" + format_kappa(t), flush=True)
+        res["scenarios"][sc] = entry
+        ctx.close()
+    if a.sequence_level:
+        n = 3
+        t1 = inputs.scenario_fault_tet("III")
+        t2 = inputs.second_fault_tet(n, t1)
+        ctx = make_context(n, a.sequence_level)
+        run = Runner(ctx, a.tol)
+        def log(msg):
+            print(msg, flush=True)
+
+        print(f"one fault after 7 iterations in tet {t1}, {ctx.n_dofs} unknowns", flush=True)
+        single = sequence_table(run, [(7, t1)], (1, 2, 4, 8), range(5), log=log)
+        print(f"faults after 5 and 9 iterations in tets {t1} and {t2}", flush=True)
+        double = sequence_table(run, [(5, t1), (9, t2)], (4,), range(5), strategies=("DN",), log=log)
+        res["sequences"] = dict(n_sub=n, level=a.sequence_level, n_dofs=ctx.n_dofs, single=single, double=double)
+        for name, t in (("one fault", single), ("two faults", double)):
+            print(f"{name}: k_free={t['k_free']}, fault-free tail {t['free_tail_s'] * 1e3:.1f} ms", flush=True)
+        ctx.close()
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(res, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
