@@ -91,7 +91,7 @@ struct LevelDev {
     // Dirichlet-Neumann recovery: intact-side interface weights, ghost copies
     // outside the faulty closures, interface nodes with static Neumann data
     double *wi_dn = nullptr;
-    int *gptr_dn = nullptr, *gidx_dn = nullptr;
+    int *gidx_dn = nullptr;  // same layout as gidx (gptr)
     unsigned char *gamma = nullptr;
 };
 
@@ -270,7 +270,6 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.lr = cv.take<double>((size_t)nf * T.C_pad);
         }
         D.wi_dn = cv.take<double>(6 * (size_t)T.n_ifc);
-        D.gptr_dn = cv.take<int>(T.n_ifc + 1);
         D.gidx_dn = cv.take<int>(T.gidx.size());
         if (l == c.L) D.gamma = cv.take<unsigned char>(T.n_ifc);
     }
@@ -767,48 +766,36 @@ void dd_final_norm(hhgr_ctx &c, hipStream_t s) {
 int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     std::vector<unsigned char> isf(c.n_tets, 0);
     for (int t : ft) isf[t] = 1;
-    int rc = HHGR_OK;
+    int rc = upload(c, c.dn_faulty, isf.data(), isf.size());
     std::vector<std::vector<VolDesc>> vds(c.L + 1);
-    std::vector<std::vector<unsigned char>> frz(c.L + 1), gam(c.L + 1);
-    std::vector<std::vector<int>> gp(c.L + 1), gi(c.L + 1);
     for (int l = c.Lc; l <= c.L; l++) {
         LevelDev &D = c.lev[l];
-        const TopoLevel &T = c.topo->lev[l];
         for (int t = 0; t < c.n_tets; t++)
             if (!isf[t]) vds[l].push_back(VolDesc{(long long)t * D.C_pad, (long long)t * D.C_pad, t, 0});
-        // an interface node lies in the closures of the tetrahedra holding its
-        // ghost copies: frozen if all of them are faulty, on the interface
-        // Gamma if some are; ghost copies in faulty closures are skipped
-        frz[l].assign(D.n_ifc, 0);
-        gam[l].assign(D.n_ifc, 0);
-        gp[l].assign(D.n_ifc + 1, 0);
-        for (int f = 0; f < D.n_ifc; f++) {
-            int nf = 0, ni = 0;
-            for (int g = T.gptr[f]; g < T.gptr[f + 1]; g++) {
-                const int tet = (int)(T.gidx[g] / T.C_pad);
-                if (isf[tet]) {
-                    nf++;
-                } else {
-                    ni++;
-                    gi[l].push_back(T.gidx[g]);
-                }
-            }
-            frz[l][f] = ni == 0 ? 1 : 0;
-            gam[l][f] = (nf > 0 && ni > 0) ? 1 : 0;
-            gp[l][f + 1] = (int)gi[l].size();
-        }
         D.n_masked = (int)vds[l].size();
         rc = rc ? rc : upload(c, D.vd_masked, vds[l].data(), vds[l].size() * sizeof(VolDesc));
-        rc = rc ? rc : upload(c, D.frozen, frz[l].data(), frz[l].size());
-        rc = rc ? rc : upload(c, D.gptr_dn, gp[l].data(), gp[l].size() * sizeof(int));
-        rc = rc ? rc : upload(c, D.gidx_dn, gi[l].data(), gi[l].size() * sizeof(int));
-        if (D.gamma) rc = rc ? rc : upload(c, D.gamma, gam[l].data(), gam[l].size());
+    }
+    if (rc) return rc;
+    // an interface node lies in the closures of the tetrahedra holding its
+    // ghost copies: frozen if all of them are faulty, on the interface Gamma
+    // if some are; ghost copies in faulty closures are not written
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        launch_dn_masks(c.stream, D.n_ifc, D.ifc_base, D.C_pad, D.gptr, D.gidx, c.dn_faulty, D.frozen, D.gamma,
+                        D.gidx_dn);
+    }
+    // frozen flags of the coarsest level's unknowns (a small host loop)
+    const TopoLevel &Tc = c.topo->lev[c.Lc];
+    std::vector<unsigned char> frc(Tc.n_ifc, 0);
+    for (int f = 0; f < Tc.n_ifc; f++) {
+        int ni = 0;
+        for (int g = Tc.gptr[f]; g < Tc.gptr[f + 1]; g++) ni += !isf[(int)(Tc.gidx[g] / Tc.C_pad)];
+        frc[f] = ni == 0;
     }
     const CoarseSystem &cs = c.topo->coarse;
     std::vector<unsigned char> cf(cs.n, 0);
-    for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? isf[cs.tet[q]] : frz[c.Lc][cs.ifc[q]];
-    rc = rc ? rc : upload(c, c.cfrozen, cf.data(), cf.size());
-    rc = rc ? rc : upload(c, c.dn_faulty, isf.data(), isf.size());
+    for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? isf[cs.tet[q]] : frc[cs.ifc[q]];
+    rc = upload(c, c.cfrozen, cf.data(), cf.size());
     if (rc) return rc;
     // intact-side operators on every level
     for (int l = c.Lc; l <= c.L; l++) {
@@ -847,7 +834,7 @@ HView<double> dn_view(hhgr_ctx &c) {
         LevelDev &D = c.lev[l];
         LevView<double> &v = V.lv[l];
         v.w.wi = D.wi_dn;
-        v.gptr = D.gptr_dn;
+        v.gptr = D.gptr;
         v.gidx = D.gidx_dn;
     }
     V.lv[c.L].b = c.aux_b;

@@ -911,6 +911,32 @@ __global__ void k_neumann_rhs(int n_ifc, long long base, const int *__restrict__
     b_out[sl] = s;
 }
 
+// Interface masks of a Dirichlet-Neumann recovery: a node whose ghost copies
+// all lie in faulty closures is frozen, one with copies on both sides is on
+// Gamma (gamma may be null).  The intact side's ghost list keeps the layout of
+// the full list; a copy in a faulty closure is replaced by the master's own
+// slot, so the scatter rewrites the master with the value it just stored.
+__global__ void k_dn_masks(int n_ifc, long long base, long long C_pad, const int *__restrict__ gptr,
+                           const int *__restrict__ gidx, const unsigned char *__restrict__ faulty,
+                           unsigned char *__restrict__ frozen, unsigned char *__restrict__ gamma,
+                           int *__restrict__ gidx_dn) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ifc) return;
+    int nf = 0, ni = 0;
+    for (int g = gptr[t]; g < gptr[t + 1]; g++) {
+        const int sl = gidx[g];
+        if (faulty[sl / C_pad]) {
+            nf++;
+            gidx_dn[g] = (int)(base + t);
+        } else {
+            ni++;
+            gidx_dn[g] = sl;
+        }
+    }
+    frozen[t] = ni == 0;
+    if (gamma) gamma[t] = nf > 0 && ni > 0;
+}
+
 // dJ/dk_T = -(h/6) sum over the 3 path edges (a,b) of T of (lam_a - lam_b)(u_a - u_b)
 __global__ void k_grad_k(const double *__restrict__ u, const double *__restrict__ lam, int N, double h,
                          double *__restrict__ out) {
@@ -1181,6 +1207,13 @@ void launch_neumann_rhs(hipStream_t s, int n_ifc, long long base, const int *nbr
     if (n_ifc <= 0) return;
     hipLaunchKernelGGL(k_neumann_rhs, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, base, nbr, wi, gamma, u,
                        b_out);
+}
+
+void launch_dn_masks(hipStream_t s, int n_ifc, long long base, long long C_pad, const int *gptr, const int *gidx,
+                     const unsigned char *faulty, unsigned char *frozen, unsigned char *gamma, int *gidx_dn) {
+    if (n_ifc <= 0) return;
+    hipLaunchKernelGGL(k_dn_masks, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, base, C_pad, gptr, gidx, faulty,
+                       frozen, gamma, gidx_dn);
 }
 
 void launch_grad_k(hipStream_t s, const double *u, const double *lam, int N, double h, double *out) {

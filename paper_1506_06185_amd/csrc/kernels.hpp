@@ -140,6 +140,10 @@ void launch_coarse_vals_intact(hipStream_t s, int n, const int *pos, const int *
 void launch_neumann_rhs(hipStream_t s, int n_ifc, long long base, const int *nbr, const double *wi,
                         const unsigned char *gamma, const double *u, double *b_out);
 
+// frozen / Gamma flags and the intact-side ghost list of a Dirichlet-Neumann recovery
+void launch_dn_masks(hipStream_t s, int n_ifc, long long base, long long C_pad, const int *gptr, const int *gidx,
+                     const unsigned char *faulty, unsigned char *frozen, unsigned char *gamma, int *gidx_dn);
+
 // dJ/dk per element from user-order u and lambda
 void launch_grad_k(hipStream_t s, const double *u, const double *lam, int N, double h, double *out);
 

@@ -212,7 +212,7 @@ def main(argv=None):
     ap.add_argument("--out", default=None, help="JSON file for the results")
     a = ap.parse_args(argv)
     res = dict(level=a.level, tol=a.tol, scenarios={})
-    for sc in a.scenarios.split(","):
+    for sc in filter(None, a.scenarios.split(",")):
         n, tet = inputs.SCENARIOS[sc]["n_sub"], inputs.scenario_fault_tet(sc)
         ctx = make_context(n, a.level)
         run = Runner(ctx, a.tol)

@@ -76,6 +76,8 @@ void launch_vol_weights(hipStream_t, const VolGeom &, const int *, int, int, dou
 void launch_ifc_weights(hipStream_t, int, const int *, int, double, const double *, double *) {}
 void launch_coarse_vals(hipStream_t, int, const int *, const int *, int, double, const double *, double *) {}
 void launch_dirichlet_load(hipStream_t, int, double, const double *, const double *, double *) {}
+void launch_dn_masks(hipStream_t, int, long long, long long, const int *, const int *, const unsigned char *,
+                     unsigned char *, unsigned char *, int *) {}
 void launch_grad_k(hipStream_t, const double *, const double *, int, double, double *) {}
 void launch_ifc_weights_intact(hipStream_t, int, const int *, int, int, int, double, const double *,
                                const unsigned char *, double *) {}
