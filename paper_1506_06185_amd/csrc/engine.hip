@@ -69,6 +69,8 @@ struct LevelDev {
     int bs_sel = 1;  // colour pass
     int remap = 1;   // XCD-contiguous block order (autotuned)
     int cpb = 1;     // nodes per thread of the list-mode kernels (autotuned)
+    int cpb_res = 1; // ... of the residual and of the prolongation (autotuned separately)
+    int cpb_prl = 1;
     int *nbr = nullptr, *gptr = nullptr, *gidx = nullptr, *rst = nullptr, *prl = nullptr, *nb15 = nullptr;
     int *ifc_dof = nullptr, *ifc_xyz = nullptr, *tg_dst = nullptr, *tg_src = nullptr;
     std::vector<int> tg_ptr;
@@ -541,14 +543,16 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const LevView<T> &vc = V.lv[l - 1];
     smooth(c, V, l, c.d.nu_pre, zero, s);
     if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, V.local && l < c.L ? (long long)c.d.max_faults * D.C_pad : D.n_slots, T(0));
-    const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+    VolGeom vg = vgeom(D, v.vd, v.nvol, false);
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
-    launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
+    vg.cpb = D.cpb_res;
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
+    launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
     const IfcGeom igp = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
+    vg.cpb = D.cpb_prl;
     launch_prolong<T>(s, vg, vc.vd, Dc.rowC, Dc.M, igp, D.prl, vc.u, v.u);
     smooth(c, V, l, c.d.nu_post, false, s);
 }
@@ -558,7 +562,8 @@ template <typename TO>
 void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t s, double *dst) {
     const LevelDev &D = c.lev[c.L];
     const LevView<double> &v = V.lv[c.L];
-    const VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+    VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+    vg.cpb = D.cpb_res;
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
     const int nb = launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
     if (nb > 0)
@@ -1395,6 +1400,8 @@ int hhgr_set_tuning(hhgr_ctx *c, int level, int block_size, int xcd_order, int n
         D.bs_sel = q;
         D.remap = xcd_order;
         D.cpb = nodes_per_thread;
+        D.cpb_res = nodes_per_thread;
+        D.cpb_prl = nodes_per_thread;
     }
     invalidate_graph(*c);
     return HHGR_OK;
@@ -1454,12 +1461,25 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         auto it = cache.find(ks.str());
         auto itr = cache.find(ks.str() + ":remap");
         auto itc = cache.find(ks.str() + ":cpb");
-        if (it != cache.end() && itr != cache.end() && itc != cache.end()) {
+        auto itcr = cache.find(ks.str() + ":cpb_res");
+        auto itcp = cache.find(ks.str() + ":cpb_prl");
+        if (it != cache.end() && itr != cache.end() && itc != cache.end() && itcr != cache.end() &&
+            itcp != cache.end()) {
             D.bs_sel = it->second;
             D.remap = itr->second;
             D.cpb = itc->second;
+            D.cpb_res = itcr->second;
+            D.cpb_prl = itcp->second;
             continue;
         }
+        auto time_it = [&](auto run, int reps) -> float {
+            run();
+            if (hipEventRecord(e0, c->stream) != hipSuccess) return 1e30f;
+            for (int r = 0; r < reps; r++) run();
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30f;
+            float ms = 0;
+            return hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? ms : 1e30f;
+        };
         double best = 1e30;
         int bq = 1, br = 1, bc = 1;
         for (int rq = 0; rq < 12; rq++) {
@@ -1497,6 +1517,37 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         cache[ks.str()] = bq;
         cache[ks.str() + ":remap"] = br;
         cache[ks.str() + ":cpb"] = bc;
+        // nodes per thread of the residual (norm form) and of the
+        // prolongation at that workgroup size and block order; the scratch
+        // vectors r of this level and of the next coarser one stand in for
+        // u and the coarse correction
+        const int reps = l >= 6 ? 5 : 20;
+        float tr[2], tp[2];
+        const LevelDev &Dc = c->lev[l - 1];
+        for (int qc = 0; qc < 2; qc++) {
+            VolGeom vg = vgeom(D, D.vd_all, c->n_tets, false);
+            vg.cpb = qc ? 4 : 1;
+            tr[qc] = time_it([&]() {
+                if (c->mixed)
+                    launch_residual<float, float>(c->stream, vg, igeom(D, 0, D.n_ifc, nullptr, false), D.r32, D.b32,
+                                                  weights<float>(D), c->vk, D.h, (float *)nullptr, c->partial[0]);
+                else
+                    launch_residual<double, double>(c->stream, vg, igeom(D, 0, D.n_ifc, nullptr, false), D.r, D.b,
+                                                    weights<double>(D), c->vk, D.h, (double *)nullptr, c->partial[0]);
+            }, reps);
+            tp[qc] = time_it([&]() {
+                if (c->mixed)
+                    launch_prolong<float>(c->stream, vg, Dc.vd_all, Dc.rowC, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true),
+                                          D.prl, Dc.r32, D.r32);
+                else
+                    launch_prolong<double>(c->stream, vg, Dc.vd_all, Dc.rowC, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true),
+                                           D.prl, Dc.r, D.r);
+            }, reps);
+        }
+        D.cpb_res = tr[1] < tr[0] ? 4 : 1;
+        D.cpb_prl = tp[1] < tp[0] ? 4 : 1;
+        cache[ks.str() + ":cpb_res"] = D.cpb_res;
+        cache[ks.str() + ":cpb_prl"] = D.cpb_prl;
         // scratch vector used for timing goes back to zero
         launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
         if (c->mixed) launch_fill<float>(c->stream, D.r32, D.n_slots, 0.0f);

@@ -97,6 +97,31 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// sum over a wavefront with DPP moves instead of LDS permutes: prefix sums
+// within each 16-lane row (shifts 1, 2, 4, 8), then the row totals carried
+// into rows 1 and 3 (lane 15 broadcast) and rows 2 and 3 (lane 31
+// broadcast); lane 63 ends with the total, which is returned to every lane.
+// Out-of-row sources and masked rows contribute +0.  Fixed order.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // sum over the block, result valid in every thread (fixed order)
 __device__ __forceinline__ double block_sum_all(double v, double *sh) {
     v = wave_sum(v);
@@ -507,6 +532,107 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
 #pragma unroll
     for (int s = 0; s < NPT; s++) {
         const int q = tid + s * nt;
+        if (!act[s]) continue;
+        const T xv = (T)x[s];
+        for (int c = cptr[q]; c < cptr[q + 1]; c++) u[cidx[c]] = xv;
+    }
+    if (tid == 0 && iters) *iters = it;
+}
+
+// the same Jacobi-PCG in a single wavefront (n <= 64 NPT): reductions are
+// wave shuffles and the only barrier is the one that publishes p in LDS
+template <typename T, int NPT>
+__global__ void __launch_bounds__(64) k_coarse_pcg_wave(int n, const long long *__restrict__ slot,
+                                                        const int *__restrict__ col, const double *__restrict__ val,
+                                                        const unsigned char *__restrict__ frozen,
+                                                        const T *__restrict__ b, T *__restrict__ u,
+                                                        const int *__restrict__ cptr, const int *__restrict__ cidx,
+                                                        double rtol, int maxit, int *__restrict__ iters) {
+    __shared__ double p_sh[64 * NPT];
+    const int tid = threadIdx.x;
+    double x[NPT], r[NPT], p[NPT], dinv[NPT], dg[NPT], av[NPT][6];
+    int ac[NPT][6];
+    bool act[NPT];
+#pragma unroll
+    for (int s = 0; s < NPT; s++) {
+        const int q = tid + 64 * s;
+        act[s] = q < n && !(frozen && frozen[q]);
+        x[s] = 0.0;
+        r[s] = 0.0;
+        p[s] = 0.0;
+        dinv[s] = 0.0;
+        dg[s] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            ac[s][e] = 0;
+            av[s][e] = 0.0;
+        }
+        if (act[s]) {
+            dg[s] = val[7 * q];
+            dinv[s] = 1.0 / dg[s];
+            r[s] = (double)b[slot[q]];
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                const int c = col[7 * q + 1 + e];
+                ac[s][e] = c >= 0 ? c : 0;
+                av[s][e] = c >= 0 ? val[7 * q + 1 + e] : 0.0;
+            }
+        }
+        p[s] = r[s] * dinv[s];
+        p_sh[q] = p[s];
+    }
+    double rz = 0.0, rr0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NPT; s++) {
+        rz += r[s] * p[s];
+        rr0 += r[s] * r[s];
+    }
+    rz = wave_sum_dpp(rz);
+    rr0 = wave_sum_dpp(rr0);
+    int it = 0;
+    if (rr0 > 0.0) {
+        const double stop = rtol * rtol * rr0;
+        for (it = 1; it <= maxit; it++) {
+            __syncthreads();
+            double qv[NPT];
+            double pq = 0.0;
+#pragma unroll
+            for (int s = 0; s < NPT; s++) {
+                double a = 0.0;
+                if (act[s]) {
+                    a = dg[s] * p[s];
+#pragma unroll
+                    for (int e = 0; e < 6; e++) a += av[s][e] * p_sh[ac[s][e]];
+                }
+                qv[s] = a;
+                pq += p[s] * a;
+            }
+            pq = wave_sum_dpp(pq);
+            const double alpha = rz / pq;
+            double rr = 0.0, rz1 = 0.0;
+#pragma unroll
+            for (int s = 0; s < NPT; s++) {
+                x[s] += alpha * p[s];
+                r[s] -= alpha * qv[s];
+                rr += r[s] * r[s];
+                rz1 += r[s] * r[s] * dinv[s];
+            }
+            rr = wave_sum_dpp(rr);
+            rz1 = wave_sum_dpp(rz1);
+            if (rr <= stop) break;
+            const double beta = rz1 / rz;
+            rz = rz1;
+            __syncthreads();  // every lane has finished reading p_sh
+#pragma unroll
+            for (int s = 0; s < NPT; s++) {
+                p[s] = r[s] * dinv[s] + beta * p[s];
+                p_sh[tid + 64 * s] = p[s];
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NPT; s++) {
+        const int q = tid + 64 * s;
         if (!act[s]) continue;
         const T xv = (T)x[s];
         for (int c = cptr[q]; c < cptr[q + 1]; c++) u[cidx[c]] = xv;
@@ -1071,8 +1197,21 @@ template <typename T>
 void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
                        const unsigned char *frozen, const T *b, T *u, const int *cptr, const int *cidx, double rtol,
                        int maxit, int *iters) {
-    // one unknown per thread in as few waves as possible (cheaper barriers)
-    if (n <= 1024) {
+    // up to 512 unknowns in a single wavefront; otherwise one unknown per
+    // thread in as few waves as possible (cheaper barriers)
+    if (n <= 64) {
+        hipLaunchKernelGGL((k_coarse_pcg_wave<T, 1>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
+    } else if (n <= 128) {
+        hipLaunchKernelGGL((k_coarse_pcg_wave<T, 2>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
+    } else if (n <= 256) {
+        hipLaunchKernelGGL((k_coarse_pcg_wave<T, 4>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
+    } else if (n <= 512) {
+        hipLaunchKernelGGL((k_coarse_pcg_wave<T, 8>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
+    } else if (n <= 1024) {
         const int bs = n <= 64 ? 64 : n <= 128 ? 128 : n <= 256 ? 256 : n <= 512 ? 512 : 1024;
         hipLaunchKernelGGL((k_coarse_pcg<T, 1>), dim3(1), dim3(bs), 0, s, n, slot, col, val, frozen, b, u, cptr, cidx,
                            rtol, maxit, iters);

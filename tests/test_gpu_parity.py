@@ -365,3 +365,54 @@ def test_dirichlet_neumann_recovery(dev, hh, case):
         assert rel(N(ctx.get_solution()), u) < 1e-12
     ctx.close()
     p.close()
+
+
+@pytest.mark.parametrize("case", ["k1-dd", "vk-dn", "k1-local", "mixed"])
+def test_recoveries_level6(dev, hh, case):
+    """Faults and recoveries one level above the other small cases (6 tets at
+    level 6, 250 k unknowns): iterates equal the oracle's."""
+    n_sub, level = 1, 6
+    print(f"\n[level 6] {case} n_sub={n_sub} level={level}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=2) if case == "vk-dn" else None
+    p = oracle.Problem(n_sub, level, k=k)
+    b = inputs.uniform_load(n_sub, level, seed=11)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=k is not None,
+                     precision="mixed" if case == "mixed" else "fp64")
+    if k is not None:
+        ctx.set_coeff(T(k, dev))
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    if case == "mixed":
+        cyc, rr, _ = ctx.solve(1e-12, 60)
+        u64, _, _ = p.solve(b, rtol=1e-13, max_cycles=60)
+        err = np.linalg.norm(N(ctx.get_solution()) - u64) / np.linalg.norm(u64)
+        print(f"  mixed: {cyc} steps, error vs FP64 oracle {err:.2e}", flush=True)
+        assert err < 1e-9
+        ctx.close()
+        p.close()
+        return
+    ctx.vcycle(3)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    tets = [1, 4]
+    for t in tets:
+        ctx.inject_fault(t)
+        u = p.inject_fault(t, u)
+    if case == "k1-dd":
+        ctx.recover_dd(tets, 2, 3)
+        u = p.dd_intact(tets, u, b, 2)
+        u, _ = p.recover_local(tets, u, b, n_cycles=3)
+    elif case == "vk-dn":
+        ctx.recover_dn(tets, 2, 2)
+        u = p.dn_recover(tets, u, b, n_intact=2, eta=2)
+    else:
+        for t in tets:
+            ctx.recover_local(t, 3)
+        u, _ = p.recover_local(tets, u, b, n_cycles=3)
+    d = rel(N(ctx.get_solution()), u)
+    print(f"  after recovery: rel diff {d:.2e}", flush=True)
+    assert d < 1e-12
+    ctx.vcycle(2)
+    u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=2)
+    assert rel(N(ctx.get_solution()), u) < 1e-12
+    ctx.close()
+    p.close()
