@@ -49,6 +49,7 @@ def lib():
     L = C.CDLL(_LIB)
     sig = {
         "ohhg_create": (_vp, [C.c_int, C.c_int, C.c_int, _dp]),
+        "ohhg_create_geom": (_vp, [C.c_int, C.c_int, C.c_int, _dp, _dp]),
         "ohhg_destroy": (None, [_vp]),
         "ohhg_threads": (C.c_int, []),
         "ohhg_setup_seconds": (C.c_double, [_vp]),
@@ -56,6 +57,7 @@ def lib():
         "ohhg_nelem": (C.c_longlong, [_vp, C.c_int]),
         "ohhg_cells": (C.c_int, [_vp, C.c_int]),
         "ohhg_elements": (None, [_vp, C.c_int, _ip, _lp]),
+        "ohhg_positions": (None, [_vp, C.c_int, _dp]),
         "ohhg_coeff": (None, [_vp, C.c_int, _dp]),
         "ohhg_volume_sum": (C.c_double, [_vp, C.c_int]),
         "ohhg_check_freudenthal": (C.c_int, [_vp, C.c_int]),
@@ -138,11 +140,23 @@ class Problem:
     coefficient on the finest level (None: k = 1).
     """
 
-    def __init__(self, n_sub: int, level: int, coarse_level: int = 2, k=None):
+    def __init__(self, n_sub: int, level: int, coarse_level: int = 2, k=None, vertices=None):
+        """``vertices`` (optional): positions of the (n+1)^3 macro vertices, shape
+        ((n+1)^3, 3), x fastest -- a general macro mesh with the same
+        connectivity; refinement bisects edges, and the smoother then sweeps the
+        4 classes of (x+y+z) mod 4 (grid units), which the 15-point stencils of
+        a general mesh leave uncoupled."""
         self.n_sub, self.level, self.coarse_level = int(n_sub), int(level), int(coarse_level)
         self._k = None if k is None else _f64(k)
         kp = None if self._k is None else _d(self._k)
-        self._h = lib().ohhg_create(self.n_sub, self.level, self.coarse_level, kp)
+        self.general = vertices is not None
+        if self.general:
+            self._xyz = _f64(vertices).reshape(-1)
+            if self._xyz.size != 3 * (self.n_sub + 1) ** 3:
+                raise ValueError("vertices must hold 3 coordinates for each of the (n+1)^3 macro vertices")
+            self._h = lib().ohhg_create_geom(self.n_sub, self.level, self.coarse_level, kp, _d(self._xyz))
+        else:
+            self._h = lib().ohhg_create(self.n_sub, self.level, self.coarse_level, kp)
         if not self._h:
             raise ValueError("invalid oracle problem parameters")
         self.N = self.n_sub << self.level
@@ -177,6 +191,14 @@ class Problem:
         ecl = np.empty(ne, dtype=np.int64)
         lib().ohhg_elements(self._h, level, ev.ctypes.data_as(_ip), ecl.ctypes.data_as(_lp))
         return ev, ecl
+
+    def positions(self, level: int | None = None) -> np.ndarray:
+        """Vertex positions ((N+1)^3, 3) of a level, x fastest."""
+        level = self.level if level is None else level
+        N = self.n_sub << level
+        out = np.empty(3 * (N + 1) ** 3)
+        lib().ohhg_positions(self._h, level, _d(out))
+        return out.reshape(-1, 3)
 
     def coeff(self, level: int) -> np.ndarray:
         k = np.empty(self.nelem_at(level))
@@ -269,7 +291,9 @@ class Problem:
         return r
 
     def smooth(self, u, b, omega: float = 1.25, colours: int = 3, level: int | None = None) -> np.ndarray:
-        """Returns u after a red (1), black (2) or red+black (3) SOR pass."""
+        """Returns u after a red (1), black (2) or red+black (3) SOR pass; for a
+        general geometry, bits 1, 2, 4, 8 select the classes 0..3 of (x+y+z)
+        mod 4 (15 = one sweep)."""
         level = self.level if level is None else level
         u = _f64(u).copy()
         b = _f64(b)

@@ -209,12 +209,17 @@ typedef struct {
     double *diag;
     i64 nred, nblack;
     i64 *red, *black;
+    /* general geometry: colours (x+y+z) mod 4; red = classes 0 then 2 (the
+     * first nred0 entries are class 0), black = classes 1 then 3 */
+    i64 nred0, nblack1;
+    double *xyz; /* vertex positions (3 per vertex) when the geometry is given */
     float *A32, *diag32;
 } olevel;
 
 typedef struct {
     int n_sub, L, Lc;
     int var_k;
+    int geom; /* 1: vertex positions given, 4-colour smoother */
     olevel lev[MAXLEV];
     double setup_s;
 } oproblem;
@@ -364,6 +369,41 @@ static void elem_mats(int N, const int *ev, double K[4][4], double Mm[4][4]) {
         }
 }
 
+/* The same element matrices from physical vertex positions (general macro
+ * meshes): no scaling afterwards. */
+static void elem_mats_xyz(const double *xyz, const int *ev, double K[4][4], double Mm[4][4]) {
+    double J[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) J[r][c] = xyz[3 * (i64)ev[c + 1] + r] - xyz[3 * (i64)ev[0] + r];
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (det == 0.0) die("degenerate element");
+    double inv[3][3];
+    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    double g[4][3];
+    for (int c = 0; c < 3; c++) {
+        g[1][c] = inv[0][c];
+        g[2][c] = inv[1][c];
+        g[3][c] = inv[2][c];
+        g[0][c] = -(inv[0][c] + inv[1][c] + inv[2][c]);
+    }
+    double vol = fabs(det) / 6.0;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) {
+            K[a][b] = vol * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
+            Mm[a][b] = vol * (a == b ? 2.0 : 1.0) / 20.0;
+        }
+}
+
 static double elem_volume_grid(int N, const int *ev) {
     int x[4][3];
     for (int a = 0; a < 4; a++) vxyz(N, ev[a], &x[a][0], &x[a][1], &x[a][2]);
@@ -408,7 +448,7 @@ static csr assemble(const olevel *Lv, const double *kcoef, int which, int interi
     csr A;
     A.nrow = A.ncol = nrow;
     A.ptr = xcalloc((size_t)nrow + 1, sizeof(i64));
-    const double scale = which == 0 ? Lv->h : Lv->h * Lv->h * Lv->h;
+    const double scale = Lv->xyz ? 1.0 : which == 0 ? Lv->h : Lv->h * Lv->h * Lv->h;
     for (int pass = 0; pass < 2; pass++) {
         if (pass == 1) {
             for (i64 i = 0; i < nrow; i++) A.ptr[i + 1] += A.ptr[i];
@@ -440,7 +480,10 @@ static csr assemble(const olevel *Lv, const double *kcoef, int which, int interi
                 double K[4][4], Mm[4][4];
                 double ke = 1.0;
                 if (pass == 1) {
-                    elem_mats(N, ev, K, Mm);
+                    if (Lv->xyz)
+                        elem_mats_xyz(Lv->xyz, ev, K, Mm);
+                    else
+                        elem_mats(N, ev, K, Mm);
                     if (which == 0 && kcoef) ke = kcoef[Lv->ecl[e]];
                 }
                 for (int b = 0; b < 4; b++) {
@@ -554,21 +597,32 @@ static void build_level_operators(oproblem *p, int l) {
         for (i64 q = Lv->A.ptr[i]; q < Lv->A.ptr[i + 1]; q++)
             if (Lv->A.col[q] == i) Lv->diag[i] = Lv->A.val[q];
     }
-    /* red = even x+y+z, black = odd (grid units of this level) */
+    /* red = even x+y+z, black = odd (grid units of this level).  With a
+     * general geometry every edge of the mesh couples (x+y+z) classes that
+     * differ by 1, 2 or 3, so the classes mod 4 are the colours: red holds
+     * class 0 then class 2, black class 1 then class 3. */
     const int N = Lv->N;
     Lv->nred = Lv->nblack = 0;
     Lv->red = xmalloc((size_t)Lv->ndof * sizeof(i64));
     Lv->black = xmalloc((size_t)Lv->ndof * sizeof(i64));
-    for (i64 i = 0; i < Lv->ndof; i++) {
-        i64 t = i;
-        int x = (int)(t % (N - 1)) + 1;
-        t /= (N - 1);
-        int y = (int)(t % (N - 1)) + 1;
-        int z = (int)(t / (N - 1)) + 1;
-        if (((x + y + z) & 1) == 0)
-            Lv->red[Lv->nred++] = i;
-        else
-            Lv->black[Lv->nblack++] = i;
+    for (int pass = 0; pass < (p->geom ? 2 : 1); pass++) {
+        for (i64 i = 0; i < Lv->ndof; i++) {
+            i64 t = i;
+            int x = (int)(t % (N - 1)) + 1;
+            t /= (N - 1);
+            int y = (int)(t % (N - 1)) + 1;
+            int z = (int)(t / (N - 1)) + 1;
+            const int c4 = (x + y + z) & 3;
+            if (p->geom && (c4 >> 1) != pass) continue;
+            if (((x + y + z) & 1) == 0)
+                Lv->red[Lv->nred++] = i;
+            else
+                Lv->black[Lv->nblack++] = i;
+        }
+        if (pass == 0) {
+            Lv->nred0 = Lv->nred;
+            Lv->nblack1 = Lv->nblack;
+        }
     }
     if (l > p->Lc) {
         Lv->P = prolongation(&p->lev[l - 1], Lv, 1);
@@ -582,7 +636,10 @@ static void build_level_operators(oproblem *p, int l) {
 /* ------------------------------------------------------------------------- */
 void ohhg_destroy(void *vp);
 
-void *ohhg_create(int n_sub, int L, int Lc, const double *k_fine) {
+/* xyz_macro (optional): positions of the (n+1)^3 macro vertices, x fastest;
+ * a refined vertex sits at the midpoint of the coarse edge it bisects (Bey's
+ * refinement), so every macro tetrahedron is refined affinely. */
+void *ohhg_create_geom(int n_sub, int L, int Lc, const double *k_fine, const double *xyz_macro) {
     if (n_sub < 1 || L < 1 || L >= MAXLEV || Lc < 1 || Lc > L) return NULL;
     double t0 = now_s();
     oproblem *p = xcalloc(1, sizeof(oproblem));
@@ -590,8 +647,22 @@ void *ohhg_create(int n_sub, int L, int Lc, const double *k_fine) {
     p->L = L;
     p->Lc = Lc;
     p->var_k = k_fine != NULL;
+    p->geom = xyz_macro != NULL;
     macro_mesh(&p->lev[0], n_sub);
     for (int l = 1; l <= L; l++) refine(&p->lev[l - 1], &p->lev[l]);
+    if (p->geom) {
+        const i64 nv0 = (i64)(n_sub + 1) * (n_sub + 1) * (n_sub + 1);
+        p->lev[0].xyz = xmalloc((size_t)nv0 * 3 * sizeof(double));
+        memcpy(p->lev[0].xyz, xyz_macro, (size_t)nv0 * 3 * sizeof(double));
+        for (int l = 1; l <= L; l++) {
+            olevel *C = &p->lev[l - 1], *F = &p->lev[l];
+            const i64 nv = (i64)(F->N + 1) * (F->N + 1) * (F->N + 1);
+            F->xyz = xmalloc((size_t)nv * 3 * sizeof(double));
+            for (i64 v = 0; v < nv; v++)
+                for (int a = 0; a < 3; a++)
+                    F->xyz[3 * v + a] = 0.5 * (C->xyz[3 * (i64)F->par[2 * v] + a] + C->xyz[3 * (i64)F->par[2 * v + 1] + a]);
+        }
+    }
     for (int l = 0; l <= L; l++) {
         olevel *Lv = &p->lev[l];
         if (!classify_elements(Lv)) die("refined element is not a Kuhn tetrahedron");
@@ -616,6 +687,8 @@ void *ohhg_create(int n_sub, int L, int Lc, const double *k_fine) {
     return p;
 }
 
+void *ohhg_create(int n_sub, int L, int Lc, const double *k_fine) { return ohhg_create_geom(n_sub, L, Lc, k_fine, NULL); }
+
 void ohhg_destroy(void *vp) {
     oproblem *p = vp;
     if (!p) return;
@@ -632,6 +705,7 @@ void ohhg_destroy(void *vp) {
         free(Lv->diag);
         free(Lv->red);
         free(Lv->black);
+        free(Lv->xyz);
         free(Lv->A32);
         free(Lv->diag32);
     }
@@ -650,6 +724,20 @@ double ohhg_setup_seconds(void *vp) { return ((oproblem *)vp)->setup_s; }
 long long ohhg_ndof(void *vp, int l) { return ((oproblem *)vp)->lev[l].ndof; }
 long long ohhg_nelem(void *vp, int l) { return ((oproblem *)vp)->lev[l].ne; }
 int ohhg_cells(void *vp, int l) { return ((oproblem *)vp)->lev[l].N; }
+
+/* vertex positions of level l ((N+1)^3 x 3, x fastest); the grid points
+ * (x/N, y/N, z/N) when no geometry was given */
+void ohhg_positions(void *vp, int l, double *out) {
+    olevel *Lv = &((oproblem *)vp)->lev[l];
+    const int N = Lv->N;
+    const i64 nv = (i64)(N + 1) * (N + 1) * (N + 1);
+    for (i64 v = 0; v < nv; v++) {
+        int x, y, z;
+        vxyz(N, v, &x, &y, &z);
+        const double g[3] = {(double)x / N, (double)y / N, (double)z / N};
+        for (int a = 0; a < 3; a++) out[3 * v + a] = Lv->xyz ? Lv->xyz[3 * v + a] : g[a];
+    }
+}
 
 /* element export: vertex ids (grid (N+1)^3 numbering) and cell-lex index */
 void ohhg_elements(void *vp, int l, int *ev, long long *ecl) {
@@ -845,6 +933,8 @@ typedef struct {
     double *diag;
     i64 nred, nblack;
     i64 *red, *black;
+    int four;            /* 4-colour sweep: red[0..nred0), black[0..nblack1), then the rest of each */
+    i64 nred0, nblack1;
     float *A32, *diag32;
     int owned;
 } mglev;
@@ -875,6 +965,9 @@ static void hier_global(oproblem *p, mghier *H) {
         m->nblack = Lv->nblack;
         m->red = Lv->red;
         m->black = Lv->black;
+        m->four = p->geom;
+        m->nred0 = Lv->nred0;
+        m->nblack1 = Lv->nblack1;
         m->owned = 0;
     }
 }
@@ -900,10 +993,17 @@ static void hier_sub(oproblem *p, unsigned char **keep, mghier *H, i64 **map_out
         m->black = xmalloc((size_t)(c ? c : 1) * sizeof(i64));
         for (i64 i = 0; i < Lv->ndof; i++)
             if (map[l][i] >= 0) m->diag[map[l][i]] = Lv->diag[i];
-        for (i64 q = 0; q < Lv->nred; q++)
+        for (i64 q = 0; q < Lv->nred; q++) {
+            if (q == Lv->nred0) m->nred0 = m->nred;
             if (map[l][Lv->red[q]] >= 0) m->red[m->nred++] = map[l][Lv->red[q]];
-        for (i64 q = 0; q < Lv->nblack; q++)
+        }
+        if (Lv->nred0 >= Lv->nred) m->nred0 = m->nred;
+        for (i64 q = 0; q < Lv->nblack; q++) {
+            if (q == Lv->nblack1) m->nblack1 = m->nblack;
             if (map[l][Lv->black[q]] >= 0) m->black[m->nblack++] = map[l][Lv->black[q]];
+        }
+        if (Lv->nblack1 >= Lv->nblack) m->nblack1 = m->nblack;
+        m->four = p->geom;
         if (l > p->Lc) {
             m->P = csr_sub(&Lv->P, map[l], c, map[l - 1], H->lv[l - 1].n);
             m->R = csr_transpose(&m->P);
@@ -953,6 +1053,14 @@ static void colour_pass64(const mglev *m, const i64 *list, i64 cnt, double *u, c
 /* smoother (Sec. 2.1 names a Gauss-Seidel variant): red-black SOR sweep, red
  * (even x+y+z) first */
 static void sweep64(const mglev *m, double *u, const double *b, double omega) {
+    if (m->four) {
+        /* classes 0, 1, 2, 3 of (x+y+z) mod 4 */
+        colour_pass64(m, m->red, m->nred0, u, b, omega);
+        colour_pass64(m, m->black, m->nblack1, u, b, omega);
+        colour_pass64(m, m->red + m->nred0, m->nred - m->nred0, u, b, omega);
+        colour_pass64(m, m->black + m->nblack1, m->nblack - m->nblack1, u, b, omega);
+        return;
+    }
     colour_pass64(m, m->red, m->nred, u, b, omega);
     colour_pass64(m, m->black, m->nblack, u, b, omega);
 }
@@ -1065,12 +1173,21 @@ void ohhg_residual(void *vp, int l, const double *u, const double *b, double *r)
     residual(&p->lev[l].A, u, b, r);
 }
 
-/* colours: 1 red pass, 2 black pass, 3 full sweep (red then black) */
+/* colours: 1 red pass, 2 black pass, 3 full sweep (red then black); with a
+ * general geometry bits 1, 2, 4, 8 select the classes 0..3 of (x+y+z) mod 4
+ * (15 = full sweep) */
 void ohhg_smooth(void *vp, int l, double *u, const double *b, double omega, int colours) {
     oproblem *p = vp;
     mghier H;
     hier_global(p, &H);
     const mglev *m = &H.lv[l];
+    if (m->four) {
+        if (colours & 1) colour_pass64(m, m->red, m->nred0, u, b, omega);
+        if (colours & 2) colour_pass64(m, m->black, m->nblack1, u, b, omega);
+        if (colours & 4) colour_pass64(m, m->red + m->nred0, m->nred - m->nred0, u, b, omega);
+        if (colours & 8) colour_pass64(m, m->black + m->nblack1, m->nblack - m->nblack1, u, b, omega);
+        return;
+    }
     if (colours & 1) colour_pass64(m, m->red, m->nred, u, b, omega);
     if (colours & 2) colour_pass64(m, m->black, m->nblack, u, b, omega);
 }
@@ -1295,10 +1412,17 @@ static void hier_ops(oproblem *p, csr *ops, unsigned char **keep, mghier *H, i64
         for (i64 i = 0; i < c; i++)
             for (i64 q = m->A.ptr[i]; q < m->A.ptr[i + 1]; q++)
                 if (m->A.col[q] == i) m->diag[i] = m->A.val[q];
-        for (i64 q = 0; q < Lv->nred; q++)
+        for (i64 q = 0; q < Lv->nred; q++) {
+            if (q == Lv->nred0) m->nred0 = m->nred;
             if (map[l][Lv->red[q]] >= 0) m->red[m->nred++] = map[l][Lv->red[q]];
-        for (i64 q = 0; q < Lv->nblack; q++)
+        }
+        if (Lv->nred0 >= Lv->nred) m->nred0 = m->nred;
+        for (i64 q = 0; q < Lv->nblack; q++) {
+            if (q == Lv->nblack1) m->nblack1 = m->nblack;
             if (map[l][Lv->black[q]] >= 0) m->black[m->nblack++] = map[l][Lv->black[q]];
+        }
+        if (Lv->nblack1 >= Lv->nblack) m->nblack1 = m->nblack;
+        m->four = p->geom;
         if (l > p->Lc) {
             m->P = csr_sub(&Lv->P, map[l], c, map[l - 1], H->lv[l - 1].n);
             m->R = csr_transpose(&m->P);
@@ -1500,6 +1624,7 @@ static void vcycle32(const mghier *H, int l, float *u, const float *b, const mgo
  * hist[c] = ||r_c|| / r0.  Returns the step count or -1. */
 int ohhg_solve_mixed(void *vp, double *u, const double *b, double omega, int nu1, int nu2, double rtol,
                      int max_steps, double r0_ref, double *hist) {
+    if (((oproblem *)vp)->geom) die("mixed precision is not defined for a general geometry");
     oproblem *p = vp;
     mghier H;
     hier_global(p, &H);
@@ -1542,6 +1667,7 @@ int ohhg_solve_mixed(void *vp, double *u, const double *b, double omega, int nu1
  * where A lambda = dJ/du.  A_T is the unit-coefficient element stiffness;
  * Dirichlet nodes carry u = lambda = 0.  out is in cell-lex element order. */
 void ohhg_grad_k(void *vp, const double *u, const double *lam, double *out) {
+    if (((oproblem *)vp)->geom) die("the gradient formula assumes the Kuhn geometry");
     oproblem *p = vp;
     olevel *Lv = &p->lev[p->L];
     const int N = Lv->N;

@@ -26,6 +26,7 @@ STREAM_U_OBS = 4
 STREAM_FD_DIRS = 5
 STREAM_BATCH_SIZES = 6
 STREAM_BATCH_FAULTS = 7
+STREAM_VERTICES = 8
 
 
 def rng(seed: int, stream: int) -> np.random.Generator:
@@ -198,3 +199,24 @@ def second_fault_tet(n_sub: int, first: int) -> int:
         if boundary_contact(n_sub, t)[0] == 0 and not vs & set(macro_tet_vertices(n_sub, t)):
             return t
     raise ValueError("no separated macro tetrahedron")
+
+
+def perturbed_vertices(n_sub: int, seed: int = 0, amplitude: float = 0.15) -> np.ndarray:
+    """Positions ((n+1)^3, 3), x fastest, of the macro vertices of a general
+    macro mesh: the grid points (x, y, z) / n, each moved by amplitude / n
+    times a U[-1, 1]^3 draw.  Boundary vertices move too, so the domain is a
+    perturbed cube.  The connectivity is the Kuhn split's."""
+    n = int(n_sub)
+    t = np.arange(n + 1, dtype=np.float64) / n
+    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+    base = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    d = rng(seed, STREAM_VERTICES).uniform(-1.0, 1.0, base.shape)
+    return np.ascontiguousarray(base + (amplitude / n) * d)
+
+
+def macro_tet_corners(vertices: np.ndarray, n_sub: int, tet: int) -> np.ndarray:
+    """The 4 corner positions (4, 3) of a macro tetrahedron of a general macro
+    mesh, in the order of macro_tet_vertices."""
+    n = int(n_sub)
+    idx = [v[0] + (n + 1) * (v[1] + (n + 1) * v[2]) for v in macro_tet_vertices(n, tet)]
+    return np.asarray(vertices)[idx]
