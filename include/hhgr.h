@@ -68,6 +68,9 @@ typedef struct {
     int precision;      /* HHGR_FP64 or HHGR_MIXED (FP32 cycle, FP64 refinement)        */
     int variable_coeff; /* 0: k = 1; 1: per-element k from hhgr_set_coeff               */
     int max_faults;     /* faulty tetrahedra recoverable at once, 0..8, default 8       */
+    int general_geometry; /* 0: the unit cube; 1: moved macro vertices from
+                             hhgr_set_geometry (needs precision = HHGR_FP64 and
+                             variable_coeff = 0), default 0                      */
 } hhgr_desc;
 
 /* Convergence report.  history (optional, caller-owned, history_cap entries)
@@ -96,6 +99,26 @@ void hhgr_destroy(hhgr_ctx *ctx);
 
 /* Sizes: interior unknowns (N-1)^3, macro tetrahedra 6 n^3, elements 6 N^3. */
 int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n_elems);
+
+/* General macro meshes (Sec. 3.1: unstructured macro mesh, each macro
+ * element refined regularly): needs general_geometry = 1.  host_xyz (host
+ * memory, read during the call) holds the positions of the (n+1)^3 macro
+ * vertices, vertex (x,y,z) at 3*(x + (n+1)*(y + (n+1)*z)) + {0,1,2}; the
+ * connectivity stays the Kuhn split of the cube described above, every
+ * macro tetrahedron is refined regularly and mapped affinely (so a refined
+ * node is the midpoint of its parent edge) and the operator of level l is the
+ * P1 stiffness matrix (k = 1) assembled in physical coordinates, with u = 0 on
+ * the boundary of the deformed cube.  Since an affine element has a constant
+ * stencil, every node of one primitive (tetrahedron interior, face, edge,
+ * vertex) shares one 15-point stencil; these are computed on the host and
+ * uploaded.  The smoother colours the nodes in the 4 classes (x+y+z) mod 4,
+ * which no 15-point stencil couples to themselves; a sweep visits classes
+ * 0, 1, 2, 3.  Vectors keep the grid-node order above.  EINVAL for an inverted
+ * or degenerate macro tetrahedron; may be called again to move the vertices.
+ * Not available with such contexts: mixed precision, variable coefficients,
+ * right-hand-side kinds other than HHGR_RHS_LOAD, Dirichlet-Neumann recovery,
+ * hhgr_mass_apply, hhgr_adjoint_grad and hhgr_autotune (ESTATE). */
+int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Right-hand side of eq. (2) from a device vector in the vector order above.
  * kind = HHGR_RHS_LOAD: the vector is the load vector b itself;
@@ -247,6 +270,9 @@ int hhgr_kernel_stats(hhgr_ctx *ctx, long long *launches, double *mean_ms, doubl
  *   op 4: out (level-1) = P^T in0               (restriction)
  *   op 5: out = in1 + P in0, in0 on level-1     (interpolation and correction)
  *   op 6: out = coarsest-level PCG solution for right-hand side in0 (level = coarse_level)
+ * With general_geometry = 1, ops 1 and 2 are EINVAL, op 3 is one 4-class
+ * sweep and op 8 + mask (mask 1..15) runs the passes of the classes whose
+ * bits are set in mask, lowest class first.
  * EINVAL for a bad op/level combination. */
 int hhgr_debug_op(hhgr_ctx *ctx, int op, int level, const double *in0, const double *in1, double *out);
 

@@ -14,9 +14,11 @@
 #include <sstream>
 #include <tuple>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hhgr.h"
+#include "geometry.hpp"
 #include "kernels.hpp"
 #include "topology.hpp"
 
@@ -95,6 +97,18 @@ struct LevelDev {
     double *wi_dn = nullptr;
     int *gidx_dn = nullptr;  // same layout as gidx (gptr)
     unsigned char *gamma = nullptr;
+    // general macro meshes: interior nodes and interface masters of each of
+    // the 4 classes, 15-point row bases, the volume stencil of every
+    // tetrahedron, and per master the index of its stencil in a table of the
+    // level's distinct stencils (one per primitive)
+    unsigned *qlist[4] = {};
+    int nqlist[4] = {};
+    int *ifcq[4] = {};
+    int nifcq[4] = {};
+    int *rowN15 = nullptr;
+    double *w15 = nullptr, *wtab = nullptr;
+    int *sid = nullptr;
+    int wtab_cap = 0;
 };
 
 template <typename T>
@@ -147,6 +161,10 @@ struct hhgr_ctx {
     double *cval = nullptr, *cval_dn = nullptr;
     unsigned char *cfrozen = nullptr, *dn_faulty = nullptr;
     int cn = 0;
+    // general macro meshes: 15-point coarsest-level operator
+    bool gen = false, geom_set = false;
+    int *ccol15 = nullptr;
+    double *cval15 = nullptr;
     std::vector<double> cval_host;
     // adjoint temporaries
     double *aux_u = nullptr, *aux_b = nullptr, *user_u = nullptr, *user_l = nullptr;
@@ -223,7 +241,22 @@ void carve(hhgr_ctx &c, Carver &cv) {
         D.gidx = cv.take<int>(T.gidx.size());
         if (l > c.Lc) D.prl = cv.take<int>(2 * (size_t)T.n_ifc);
         if (l < c.L) D.rst = cv.take<int>(15 * (size_t)T.n_ifc);
-        if (l == c.L) D.nb15 = cv.take<int>(15 * (size_t)T.n_ifc);
+        if (l == c.L || c.gen) D.nb15 = cv.take<int>(15 * (size_t)T.n_ifc);
+        if (c.gen) {
+            for (int q = 0; q < 4; q++) {
+                D.nqlist[q] = (int)T.qlist[q].size();
+                D.nifcq[q] = (int)T.ifcq[q].size();
+                D.qlist[q] = cv.take<unsigned>(D.nqlist[q]);
+                D.ifcq[q] = cv.take<int>(D.nifcq[q]);
+            }
+            D.rowN15 = cv.take<int>(16 * T.rowN15.size());
+            D.w15 = cv.take<double>(15 * (size_t)c.n_tets);
+            // distinct master stencils: at most one per primitive (4 faces,
+            // 6 edges, 4 vertices per tetrahedron), one zero stencil first
+            D.wtab_cap = 1 + 14 * c.n_tets;
+            D.wtab = cv.take<double>(15 * (size_t)D.wtab_cap);
+            D.sid = cv.take<int>(T.n_ifc);
+        }
         D.ifc_dof = cv.take<int>(T.n_ifc);
         D.ifc_xyz = cv.take<int>(3 * (size_t)T.n_ifc);
         D.tg_dst = cv.take<int>(T.tg_dst.size());
@@ -292,6 +325,10 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.cval_dn = cv.take<double>(7 * (size_t)c.cn);
     c.dn_faulty = cv.take<unsigned char>(c.n_tets);
     c.citers = cv.take<int>(4);
+    if (c.gen) {
+        c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
+        c.cval15 = cv.take<double>(15 * (size_t)c.cn);
+    }
     const TopoLevel &TL = tp.lev[c.L];
     c.aux_u = cv.take<double>(TL.n_slots);
     c.aux_b = cv.take<double>(TL.n_slots);
@@ -336,6 +373,9 @@ std::string check_desc(const hhgr_desc *d) {
     if (d->precision != HHGR_FP64 && d->precision != HHGR_MIXED) return "bad precision";
     if (d->variable_coeff != 0 && d->variable_coeff != 1) return "variable_coeff must be 0 or 1";
     if (d->max_faults < 0 || d->max_faults > 8) return "max_faults must be in 0..8";
+    if (d->general_geometry != 0 && d->general_geometry != 1) return "general_geometry must be 0 or 1";
+    if (d->general_geometry && d->precision != HHGR_FP64) return "general_geometry needs precision = HHGR_FP64";
+    if (d->general_geometry && d->variable_coeff) return "general_geometry needs variable_coeff = 0";
     return "";
 }
 
@@ -389,6 +429,20 @@ IfcGeom igeom_v(const LevelDev &D, const LevView<T> &v, int i0, int i1, bool sca
         g.gptr = v.gptr;
         g.gidx = v.gidx;
     }
+    return g;
+}
+
+// 15-point data of a level; q >= 0 selects the interface masters of class q
+// (none unless ifc)
+Gen15 gen15(const LevelDev &D, int q, bool ifc) {
+    Gen15 g;
+    g.rowN15 = D.rowN15;
+    g.w15 = D.w15;
+    g.sid = D.sid;
+    g.wtab = D.wtab;
+    g.nb15 = D.nb15;
+    g.ifcq = q >= 0 ? D.ifcq[q] : nullptr;
+    g.nq = q >= 0 && ifc ? D.nifcq[q] : 0;
     return g;
 }
 
@@ -497,9 +551,41 @@ void timed_end(hhgr_ctx &c, hipStream_t s) {
     }
 }
 
+// vector length of a view's level (a local hierarchy below the finest
+// level holds max_faults closures)
+template <typename T>
+long long view_len(const hhgr_ctx &c, const HView<T> &V, int l) {
+    const LevelDev &D = c.lev[l];
+    return V.local && l < c.L ? (long long)std::max(c.d.max_faults, 1) * D.C_pad : D.n_slots;
+}
+
+// general macro meshes: one 4-colour sweep, classes 0, 1, 2, 3 (a start
+// from zero clears the level's vector first)
+void sweep15(hhgr_ctx &c, const HView<double> &V, int l, bool zero, hipStream_t s) {
+    const LevelDev &D = c.lev[l];
+    const LevView<double> &v = V.lv[l];
+    if (zero) launch_fill<double>(s, v.u, view_len(c, V, l), 0.0);
+    for (int q = 0; q < 4; q++) {
+        VolGeom vg = vgeom(D, v.vd, v.nvol, false);
+        vg.list = D.qlist[q];
+        vg.nlist = D.nqlist[q];
+        const IfcGeom ig = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
+        const bool timed = c.timing && V.timed && l == c.L;
+        if (timed) timed_begin(c, s);
+        launch_colour15(s, vg, ig, gen15(D, q, v.ifc), v.u, v.b, c.d.omega);
+        if (timed) timed_end(c, s);
+    }
+}
+
 // one red-black sweep in place: two colour passes
 template <typename T>
 void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.gen) {
+            sweep15(c, V, l, zero, s);
+            return;
+        }
+    }
     const LevelDev &D = c.lev[l];
     const LevView<T> &v = V.lv[l];
     for (int colour = 0; colour < 2; colour++) {
@@ -523,6 +609,16 @@ template <typename T>
 void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     const LevelDev &D = c.lev[c.Lc];
     const LevView<T> &v = V.lv[c.Lc];
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.gen) {
+            if (V.local)
+                launch_local_coarse15(s, v.vd, v.nvol, D.lc_sl.x, D.w15, v.b, v.u);
+            else
+                launch_coarse_pcg15(s, c.cn, c.cslot, c.ccol15, c.cval15, V.cfrozen, v.b, v.u, c.cptr, c.cidx,
+                                    kCoarseRtol, kCoarseMaxit, c.citers);
+            return;
+        }
+    }
     if (V.local) {
         launch_local_coarse<T>(s, v.vd, v.nvol, D.lc_sl, v.b, v.u, v.w, c.vk, D.h);
     } else {
@@ -542,13 +638,20 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const LevView<T> &v = V.lv[l];
     const LevView<T> &vc = V.lv[l - 1];
     smooth(c, V, l, c.d.nu_pre, zero, s);
-    if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, V.local && l < c.L ? (long long)c.d.max_faults * D.C_pad : D.n_slots, T(0));
+    if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, view_len(c, V, l), T(0));
     VolGeom vg = vgeom(D, v.vd, v.nvol, false);
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
     vg.cpb = D.cpb_res;
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
-    launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
+    bool done = false;
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.gen) {
+            launch_residual15(s, vg, ig, gen15(D, -1, false), v.u, v.b, v.r, nullptr);
+            done = true;
+        }
+    }
+    if (!done) launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
     const IfcGeom igp = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
@@ -565,7 +668,11 @@ void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t 
     VolGeom vg = vgeom(D, v.vd, v.nvol, false);
     vg.cpb = D.cpb_res;
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
-    const int nb = launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
+    int nb = -1;
+    if constexpr (std::is_same<TO, double>::value) {
+        if (c.gen) nb = launch_residual15(s, vg, ig, gen15(D, -1, false), v.u, v.b, rout, V.partial);
+    }
+    if (nb < 0) nb = launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
     if (nb > 0)
         launch_reduce(s, V.partial, nb, dst);
     else
@@ -881,6 +988,7 @@ void hhgr_desc_default(hhgr_desc *d) {
     d->precision = HHGR_FP64;
     d->variable_coeff = 0;
     d->max_faults = 8;
+    d->general_geometry = 0;
 }
 
 const char *hhgr_last_error(void) { return g_err.c_str(); }
@@ -898,6 +1006,7 @@ int hhgr_workspace_bytes(const hhgr_desc *desc, size_t *bytes) {
     c.n_dofs = (N - 1) * (N - 1) * (N - 1);
     c.vk = desc->variable_coeff != 0;
     c.mixed = desc->precision == HHGR_MIXED;
+    c.gen = desc->general_geometry != 0;
     std::string te = get_topology(desc->n_sub, c.L, c.Lc, c.topo_hold);
     if (!te.empty()) return fail(HHGR_EINVAL, te);
     c.topo = c.topo_hold.get();
@@ -924,6 +1033,7 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     c->n_elems = 6 * N * N * N;
     c->vk = desc->variable_coeff != 0;
     c->mixed = desc->precision == HHGR_MIXED;
+    c->gen = desc->general_geometry != 0;
     c->stream = (hipStream_t)hip_stream;
     std::string te = get_topology(desc->n_sub, c->L, c->Lc, c->topo_hold);
     if (!te.empty()) {
@@ -992,6 +1102,17 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
             rown_store.push_back(std::move(rn));
             rc = rc ? rc : upload(*c, D.rowN, rown_store.back().data(), rown_store.back().size() * sizeof(int4));
         }
+        if (c->gen) {
+            for (int q = 0; q < 4; q++) {
+                rc = rc ? rc : upload(*c, D.qlist[q], T.qlist[q].data(), T.qlist[q].size() * sizeof(unsigned));
+                rc = rc ? rc : upload(*c, D.ifcq[q], T.ifcq[q].data(), T.ifcq[q].size() * sizeof(int));
+            }
+            rc = rc ? rc : upload(*c, D.rowN15, T.rowN15.data(), T.rowN15.size() * 16 * sizeof(int));
+            // no operator until hhgr_set_geometry
+            launch_fill<double>(c->stream, D.w15, 15LL * c->n_tets, 0.0);
+            launch_fill<double>(c->stream, D.wtab, 15LL * D.wtab_cap, 0.0);
+            launch_fill<unsigned int>(c->stream, reinterpret_cast<unsigned int *>(D.sid), T.n_ifc, 0u);
+        }
         // zero every vector (also the Dirichlet ghosts and the zero slot)
         launch_fill<double>(c->stream, D.u, T.n_slots, 0.0);
         launch_fill<double>(c->stream, D.b, T.n_slots, 0.0);
@@ -1032,6 +1153,10 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     rc = rc ? rc : upload(*c, c->cptr, cs.cptr.data(), cs.cptr.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cidx, cs.cidx.data(), cs.cidx.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cpos, cpos.data(), cpos.size() * sizeof(int));
+    if (c->gen) {
+        rc = rc ? rc : upload(*c, c->ccol15, cs.col15.data(), cs.col15.size() * sizeof(int));
+        launch_fill<double>(c->stream, c->cval15, 15LL * cs.n, 0.0);
+    }
     launch_fill<unsigned char>(c->stream, c->cfrozen, cs.n, 0);
     launch_fill<double>(c->stream, c->dnorm, 8, 0.0);
     launch_fill<unsigned int>(c->stream, c->counter, 64, 0u);
@@ -1070,6 +1195,8 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     if (!c || !dev_vec) return fail(HHGR_EINVAL, "null argument");
     if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F && kind != HHGR_RHS_DIRICHLET)
         return fail(HHGR_EINVAL, "bad rhs kind");
+    if (c->gen && kind != HHGR_RHS_LOAD)
+        return fail(HHGR_ESTATE, "general_geometry contexts take HHGR_RHS_LOAD only");
     if (kind == HHGR_RHS_DIRICHLET && c->vk && !c->coeff_set)
         return fail(HHGR_ESTATE, "Dirichlet data with variable_coeff = 1 needs hhgr_set_coeff first");
     LevelDev &D = c->lev[c->L];
@@ -1127,6 +1254,35 @@ int hhgr_set_coeff(hhgr_ctx *c, const double *dev_k) {
     return HHGR_OK;
 }
 
+int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
+    if (!c || !host_xyz) return fail(HHGR_EINVAL, "null argument");
+    if (!c->gen) return fail(HHGR_ESTATE, "context created with general_geometry = 0");
+    const Topology &tp = *c->topo;
+    std::string e = check_macro_mesh(tp, host_xyz);
+    if (!e.empty()) return fail(HHGR_EINVAL, e);
+    std::vector<LevelStencils> G(c->L + 1);
+    for (int l = c->Lc; l <= c->L; l++) {
+        e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
+        if (!e.empty()) return fail(HHGR_EINVAL, e);
+    }
+    std::vector<double> cval;
+    coarse_stencils(tp, host_xyz, cval);
+    invalidate_graph(*c);
+    int rc = HHGR_OK;
+    for (int l = c->Lc; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        rc = rc ? rc : upload(*c, D.w15, G[l].w15.data(), G[l].w15.size() * sizeof(double));
+        rc = rc ? rc : upload(*c, D.wtab, G[l].wtab.data(), G[l].wtab.size() * sizeof(double));
+        rc = rc ? rc : upload(*c, D.sid, G[l].sid.data(), G[l].sid.size() * sizeof(int));
+    }
+    rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
+    // the host staging vectors must outlive the copies
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (rc) return rc;
+    c->geom_set = true;
+    return HHGR_OK;
+}
+
 int hhgr_set_solution(hhgr_ctx *c, const double *dev_u) {
     if (!c || !dev_u) return fail(HHGR_EINVAL, "null argument");
     LevelDev &D = c->lev[c->L];
@@ -1150,6 +1306,7 @@ static int check_ready(hhgr_ctx *c) {
     if (!c) return fail(HHGR_EINVAL, "null context");
     if (!c->rhs_set) return fail(HHGR_ESTATE, "no right-hand side set");
     if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
+    if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     return HHGR_OK;
 }
 
@@ -1273,6 +1430,7 @@ int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int eta) {
     int rc = check_ready(c);
     if (rc) return rc;
+    if (c->gen) return fail(HHGR_ESTATE, "Dirichlet-Neumann recovery needs general_geometry = 0");
     std::vector<int> ft;
     rc = dd_check(*c, tets, n_tets, n_intact, eta, ft);
     if (rc) return rc;
@@ -1300,6 +1458,7 @@ int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 
 int hhgr_mass_apply(hhgr_ctx *c, const double *dev_x, double *dev_y) {
     if (!c || !dev_x || !dev_y) return fail(HHGR_EINVAL, "null argument");
+    if (c->gen) return fail(HHGR_ESTATE, "mass matrix needs general_geometry = 0");
     LevelDev &D = c->lev[c->L];
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
@@ -1316,6 +1475,7 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
     int rc = check_ready(c);
     if (rc) return rc;
     if (!dev_g) return fail(HHGR_EINVAL, "null g");
+    if (c->gen) return fail(HHGR_ESTATE, "adjoint needs general_geometry = 0");
     if (dev_dJdk && !c->vk) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
     LevelDev &D = c->lev[c->L];
     const long long ns = D.n_slots;
@@ -1430,14 +1590,17 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
     if (launches) *launches = n;
     if (mean_ms) *mean_ms = n ? tot / n : 0.0;
     // a colour pass reads the other colour's u and its own b and old u and
-    // writes its own u: 4 words per updated node, 2 words per unknown
+    // writes its own u: 4 words per updated node, 2 words per unknown; a
+    // class pass of the 4-colour sweep reads the other 3 classes' u
+    // (3/4 word per unknown) and 3 words per node of its class (1/4)
     const double w = c->mixed ? 4.0 : 8.0;
-    if (alg_bytes) *alg_bytes = 2.0 * w * (double)c->n_dofs;
+    if (alg_bytes) *alg_bytes = (c->gen ? 1.5 : 2.0) * w * (double)c->n_dofs;
     return HHGR_OK;
 }
 
 int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
     if (!c) return fail(HHGR_EINVAL, "null context");
+    if (c->gen) return fail(HHGR_ESTATE, "the autotuner covers general_geometry = 0");
     hipDeviceProp_t prop;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -1565,11 +1728,14 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
 
 int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *in1, double *out) {
     if (!c || !in0 || !out) return fail(HHGR_EINVAL, "null argument");
-    if (l < c->Lc || l > c->L || op < 0 || op > 6) return fail(HHGR_EINVAL, "bad op or level");
+    const bool class_op = c->gen && op >= 9 && op <= 23;
+    if (l < c->Lc || l > c->L || op < 0 || (op > 6 && !class_op)) return fail(HHGR_EINVAL, "bad op or level");
+    if (c->gen && (op == 1 || op == 2)) return fail(HHGR_EINVAL, "general_geometry: class passes are op 8 + class mask");
     if ((op == 4 || op == 5) && l <= c->Lc) return fail(HHGR_EINVAL, "transfer needs level > coarse_level");
     if (op == 6 && l != c->Lc) return fail(HHGR_EINVAL, "coarse solve needs level = coarse_level");
-    if ((op <= 3 || op == 5) && !in1) return fail(HHGR_EINVAL, "null second input");
+    if ((op <= 3 || op == 5 || class_op) && !in1) return fail(HHGR_EINVAL, "null second input");
     if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
+    if (c->gen && !c->geom_set && op != 4 && op != 5) return fail(HHGR_ESTATE, "no geometry set");
     invalidate_graph(*c);
     hipStream_t s = c->stream;
     auto to_slots = [&](const double *user, double *vec, LevelDev &D) {
@@ -1583,6 +1749,33 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
     LevelDev &D = c->lev[l];
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const Weights<double> w = weights<double>(D);
+    if (c->gen && (op == 0 || op == 3 || op == 6 || class_op)) {
+        if (op == 0) {
+            to_slots(in0, D.u, D);
+            to_slots(in1, D.b, D);
+            launch_residual15(s, vint, igeom(D, 0, D.n_ifc, nullptr, false), gen15(D, -1, false), D.u, D.b, D.r,
+                              nullptr);
+            to_user(D.r, out, D);
+        } else if (op == 6) {
+            to_slots(in0, D.b, D);
+            launch_coarse_pcg15(s, c->cn, c->cslot, c->ccol15, c->cval15, nullptr, D.b, D.u, c->cptr, c->cidx,
+                                kCoarseRtol, kCoarseMaxit, c->citers);
+            to_user(D.u, out, D);
+        } else {
+            const int mask = op == 3 ? 15 : op - 8;
+            to_slots(in0, D.u, D);
+            to_slots(in1, D.b, D);
+            for (int q = 0; q < 4; q++) {
+                if (!((mask >> q) & 1)) continue;
+                VolGeom vg = vint;
+                vg.list = D.qlist[q];
+                vg.nlist = D.nqlist[q];
+                launch_colour15(s, vg, igeom(D, 0, D.n_ifc, nullptr, true), gen15(D, q, true), D.u, D.b, c->d.omega);
+            }
+            to_user(D.u, out, D);
+        }
+        op = -1;  // done
+    }
     switch (op) {
     case 0:
         to_slots(in0, D.u, D);

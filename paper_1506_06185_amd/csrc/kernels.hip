@@ -435,10 +435,113 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
 }
 
 // ---------------------------------------------------------------------------
+// general macro meshes: 15-point stencils (see Gen15)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double master_Au(const IfcGeom &ig, const Gen15 &g, const double *__restrict__ u, int t,
+                                            double uo, double &diag) {
+    const double *w = g.wtab + 15LL * g.sid[t];
+    diag = w[0];
+    double acc = 0.0;
+#pragma unroll
+    for (int n = 1; n < 15; n++) acc += w[n] * u[g.nb15[(long long)n * ig.stride + t]];
+    return diag * uo + acc;
+}
+
+__device__ __forceinline__ double volume_Au(const VolGeom &vg, const Gen15 &g, const VolDesc &d, const LNode &nd,
+                                            const double *__restrict__ uv, int &c0, double &uo, double &diag) {
+    const int4 *e4 = (const int4 *)(g.rowN15 + 16 * ((long long)((nd.i + nd.k) & 1) * vg.nrows + nd.r));
+    const int4 E0 = e4[0], E1 = e4[1], E2 = e4[2], E3 = e4[3];
+    const int t = nd.i >> 1;
+    const double *w = g.w15 + 15LL * d.tet;
+    const int sl[15] = {E0.x, E0.y, E0.z, E0.w, E1.x, E1.y, E1.z, E1.w, E2.x, E2.y, E2.z, E2.w, E3.x, E3.y, E3.z};
+    c0 = sl[0] + t;
+    uo = uv[c0];
+    diag = w[0];
+    double acc = 0.0;
+#pragma unroll
+    for (int n = 1; n < 15; n++) acc += w[n] * uv[sl[n] + t];
+    return diag * uo + acc;
+}
+
+__global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, double *__restrict__ u,
+                                                  const double *__restrict__ b, double omega) {
+    const unsigned f = blockIdx.x;
+    if (f < (unsigned)nib) {
+        const int q = (int)(f * blockDim.x + threadIdx.x);
+        if (q >= g.nq) return;
+        const int t = g.ifcq[q];
+        if (ig.frozen && ig.frozen[t]) return;
+        const long long sl = ig.base + t;
+        const double uo = u[sl];
+        double diag;
+        const double Au = master_Au(ig, g, u, t, uo, diag);
+        const double un = uo + omega * (b[sl] - Au) / diag;
+        u[sl] = un;
+        if (ig.gptr)
+            for (int gq = ig.gptr[t]; gq < ig.gptr[t + 1]; gq++) u[ig.gidx[gq]] = un;
+        return;
+    }
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+    LNode nd;
+    if (!list_node<1>(vg, blk, per_vol, 0, nd)) return;
+    const VolDesc d = vg.vd[nd.v];
+    double *uv = u + d.vec;
+    int c0;
+    double uo, diag;
+    const double Au = volume_Au(vg, g, d, nd, uv, c0, uo, diag);
+    uv[c0] = uo + omega * ((b + d.vec)[c0] - Au) / diag;
+}
+
+template <bool WRITE, bool NORM>
+__global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen15 g, int nib,
+                                                    const double *__restrict__ u, const double *__restrict__ b,
+                                                    double *__restrict__ r, double *__restrict__ partial) {
+    __shared__ double sh[64];
+    const unsigned f = blockIdx.x;
+    double acc2 = 0.0;
+    if (f < (unsigned)nib) {
+        const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
+        if (t < ig.i1 && !(ig.frozen && ig.frozen[t])) {
+            const long long sl = ig.base + t;
+            double diag;
+            const double res = b[sl] - master_Au(ig, g, u, t, u[sl], diag);
+            if (WRITE) r[sl] = res;
+            acc2 = res * res;
+        }
+    } else {
+        const unsigned per_vol = list_blocks_per_vol<1>(vg);
+        const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+        LNode nd;
+        if (list_node<1>(vg, blk, per_vol, 0, nd)) {
+            const VolDesc d = vg.vd[nd.v];
+            int c0;
+            double uo, diag;
+            const double Au = volume_Au(vg, g, d, nd, u + d.vec, c0, uo, diag);
+            const double res = (b + d.vec)[c0] - Au;
+            if (WRITE) r[d.vec + c0] = res;
+            acc2 = res * res;
+        }
+    }
+    if (NORM) {
+        const double s = block_sum_all(acc2, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_local_coarse15(const VolDesc *__restrict__ vd, int nvol, int slot, const double *__restrict__ w15,
+                                 const double *__restrict__ b, double *__restrict__ u) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvol) return;
+    const VolDesc d = vd[v];
+    (u + d.vec)[slot] = (b + d.vec)[slot] / w15[15LL * d.tet];
+}
+
+// ---------------------------------------------------------------------------
 // coarsest level: Jacobi-PCG in one workgroup, unknowns owned by threads,
 // search direction shared through LDS
 // ---------------------------------------------------------------------------
-template <typename T, int NPT>
+template <typename T, int NPT, int NB = 6>
 __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__restrict__ slot,
                                                      const int *__restrict__ col, const double *__restrict__ val,
                                                      const unsigned char *__restrict__ frozen, const T *__restrict__ b,
@@ -449,8 +552,8 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
     __shared__ double red[64];
     const int tid = threadIdx.x, nt = blockDim.x;
     // every thread owns NPT unknowns; their matrix rows stay in registers
-    double x[NPT], r[NPT], p[NPT], dinv[NPT], dg[NPT], av[NPT][6];
-    int ac[NPT][6];
+    double x[NPT], r[NPT], p[NPT], dinv[NPT], dg[NPT], av[NPT][NB];
+    int ac[NPT][NB];
     bool act[NPT];
 #pragma unroll
     for (int s = 0; s < NPT; s++) {
@@ -462,20 +565,20 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
         dinv[s] = 0.0;
         dg[s] = 0.0;
 #pragma unroll
-        for (int e = 0; e < 6; e++) {
+        for (int e = 0; e < NB; e++) {
             ac[s][e] = 0;
             av[s][e] = 0.0;
         }
         if (q < n) {
             if (act[s]) {
-                dg[s] = val[7 * q];
+                dg[s] = val[(NB + 1) * q];
                 dinv[s] = 1.0 / dg[s];
                 r[s] = (double)b[slot[q]];
 #pragma unroll
-                for (int e = 0; e < 6; e++) {
-                    const int c = col[7 * q + 1 + e];
+                for (int e = 0; e < NB; e++) {
+                    const int c = col[(NB + 1) * q + 1 + e];
                     ac[s][e] = c >= 0 ? c : 0;
-                    av[s][e] = c >= 0 ? val[7 * q + 1 + e] : 0.0;
+                    av[s][e] = c >= 0 ? val[(NB + 1) * q + 1 + e] : 0.0;
                 }
             }
             p[s] = r[s] * dinv[s];
@@ -502,7 +605,7 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
                 if (act[s]) {
                     a = dg[s] * p[s];
 #pragma unroll
-                    for (int e = 0; e < 6; e++) a += av[s][e] * p_sh[ac[s][e]];
+                    for (int e = 0; e < NB; e++) a += av[s][e] * p_sh[ac[s][e]];
                 }
                 qv[s] = a;
                 pq += p[s] * a;
@@ -541,7 +644,7 @@ __global__ void __launch_bounds__(1024) k_coarse_pcg(int n, const long long *__r
 
 // the same Jacobi-PCG in a single wavefront (n <= 64 NPT): reductions are
 // wave shuffles and the only barrier is the one that publishes p in LDS
-template <typename T, int NPT>
+template <typename T, int NPT, int NB = 6>
 __global__ void __launch_bounds__(64) k_coarse_pcg_wave(int n, const long long *__restrict__ slot,
                                                         const int *__restrict__ col, const double *__restrict__ val,
                                                         const unsigned char *__restrict__ frozen,
@@ -550,8 +653,8 @@ __global__ void __launch_bounds__(64) k_coarse_pcg_wave(int n, const long long *
                                                         double rtol, int maxit, int *__restrict__ iters) {
     __shared__ double p_sh[64 * NPT];
     const int tid = threadIdx.x;
-    double x[NPT], r[NPT], p[NPT], dinv[NPT], dg[NPT], av[NPT][6];
-    int ac[NPT][6];
+    double x[NPT], r[NPT], p[NPT], dinv[NPT], dg[NPT], av[NPT][NB];
+    int ac[NPT][NB];
     bool act[NPT];
 #pragma unroll
     for (int s = 0; s < NPT; s++) {
@@ -563,19 +666,19 @@ __global__ void __launch_bounds__(64) k_coarse_pcg_wave(int n, const long long *
         dinv[s] = 0.0;
         dg[s] = 0.0;
 #pragma unroll
-        for (int e = 0; e < 6; e++) {
+        for (int e = 0; e < NB; e++) {
             ac[s][e] = 0;
             av[s][e] = 0.0;
         }
         if (act[s]) {
-            dg[s] = val[7 * q];
+            dg[s] = val[(NB + 1) * q];
             dinv[s] = 1.0 / dg[s];
             r[s] = (double)b[slot[q]];
 #pragma unroll
-            for (int e = 0; e < 6; e++) {
-                const int c = col[7 * q + 1 + e];
+            for (int e = 0; e < NB; e++) {
+                const int c = col[(NB + 1) * q + 1 + e];
                 ac[s][e] = c >= 0 ? c : 0;
-                av[s][e] = c >= 0 ? val[7 * q + 1 + e] : 0.0;
+                av[s][e] = c >= 0 ? val[(NB + 1) * q + 1 + e] : 0.0;
             }
         }
         p[s] = r[s] * dinv[s];
@@ -602,7 +705,7 @@ __global__ void __launch_bounds__(64) k_coarse_pcg_wave(int n, const long long *
                 if (act[s]) {
                     a = dg[s] * p[s];
 #pragma unroll
-                    for (int e = 0; e < 6; e++) a += av[s][e] * p_sh[ac[s][e]];
+                    for (int e = 0; e < NB; e++) a += av[s][e] * p_sh[ac[s][e]];
                 }
                 qv[s] = a;
                 pq += p[s] * a;
@@ -1313,6 +1416,58 @@ void launch_vol_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo,
 void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, double h, const double *k, double *wi) {
     if (n_ifc <= 0) return;
     hipLaunchKernelGGL(k_ifc_weights, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, ifc_xyz, N, h, k, wi);
+}
+
+void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, double *u, const double *b,
+                     double omega) {
+    const int nib = g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0;
+    const long long grid = nib + list_blocks(vg, 1);
+    if (grid == 0) return;
+    hipLaunchKernelGGL(k_colour15, dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b, omega);
+}
+
+int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const double *u,
+                      const double *b, double *r, double *partial) {
+    const int nib = ifc_blocks(ig, vg.bs);
+    const long long grid = nib + list_blocks(vg, 1);
+    if (grid == 0) return 0;
+    const dim3 gd((unsigned)grid), bd(vg.bs);
+    if (r && partial)
+        hipLaunchKernelGGL((k_residual15<true, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+    else if (r)
+        hipLaunchKernelGGL((k_residual15<true, false>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+    else
+        hipLaunchKernelGGL((k_residual15<false, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+    return (int)grid;
+}
+
+void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
+                         const unsigned char *frozen, const double *b, double *u, const int *cptr, const int *cidx,
+                         double rtol, int maxit, int *iters) {
+    if (n <= 64)
+        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 1, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
+                           cptr, cidx, rtol, maxit, iters);
+    else if (n <= 128)
+        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 2, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
+                           cptr, cidx, rtol, maxit, iters);
+    else if (n <= 256)
+        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 4, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
+                           cptr, cidx, rtol, maxit, iters);
+    else if (n <= 512)
+        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 8, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
+                           cptr, cidx, rtol, maxit, iters);
+    else if (n <= 1024)
+        hipLaunchKernelGGL((k_coarse_pcg<double, 1, 14>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
+    else
+        hipLaunchKernelGGL((k_coarse_pcg<double, 2, 14>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
+}
+
+void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const double *w15, const double *b,
+                           double *u) {
+    if (nvol <= 0) return;
+    hipLaunchKernelGGL(k_local_coarse15, dim3((unsigned)((nvol + 63) / 64)), dim3(64), 0, s, vd, nvol, slot, w15, b, u);
 }
 
 void launch_dirichlet_load(hipStream_t s, int N, double h, const double *k, const double *g, double *b) {

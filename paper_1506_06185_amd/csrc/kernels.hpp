@@ -42,6 +42,22 @@ struct IfcGeom {
     const unsigned char *frozen = nullptr;  // Dirichlet-frozen nodes or nullptr
 };
 
+// General macro meshes (moved macro vertices): 15-point stencils.  A volume
+// node of tetrahedron t uses w15[15 t + n], n in the index-offset order of
+// kIdx15 (entry 0 the diagonal), with slots rowN15[16 (c rows + r) + n] +
+// (i >> 1) (c = parity colour, r = row); an interface master f uses the
+// stencil wtab[15 sid[f] + n] at the slots nb15[n stride + f] (grid-offset
+// order of kGrid15).  A class pass walks the masters listed in ifcq[0 .. nq).
+struct Gen15 {
+    const int *rowN15 = nullptr;
+    const double *w15 = nullptr;
+    const int *sid = nullptr;
+    const double *wtab = nullptr;
+    const int *nb15 = nullptr;
+    const int *ifcq = nullptr;
+    int nq = 0;
+};
+
 template <typename T>
 struct Weights {
     const T *w0 = nullptr, *w1 = nullptr, *w2 = nullptr;  // volume edge weights per slot, local dirs a,b,c
@@ -124,6 +140,21 @@ void launch_coarsen_k(hipStream_t s, const double *kf, int Nf, double *kc, int N
 void launch_vol_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo, int m, int N, double h,
                         const double *k, double *w0, double *w1, double *w2);
 void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, double h, const double *k, double *wi);
+// general macro meshes: one SOR pass over one of the 4 classes (vg lists its
+// interior nodes, g.ifcq its masters; ig gives base, stride, ghosts, frozen)
+void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, double *u, const double *b,
+                     double omega);
+// general macro meshes: r = b - A u over the interior list of vg and every
+// master of ig (r and/or partial sums of r^2 per block, as launch_residual)
+int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const double *u,
+                      const double *b, double *r, double *partial);
+// coarsest level of a general macro mesh: Jacobi-PCG with 15 entries per row
+void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
+                         const unsigned char *frozen, const double *b, double *u, const int *cptr, const int *cidx,
+                         double rtol, int maxit, int *iters);
+// local coarsest level of a general macro mesh: u = b / w15[15 tet] at the single interior node
+void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const double *w15, const double *b,
+                           double *u);
 // b = eliminated Dirichlet data g (full (N+1)^3 grid, x fastest), vector order
 void launch_dirichlet_load(hipStream_t s, int N, double h, const double *k, const double *g, double *b);
 void launch_coarse_vals(hipStream_t s, int n, const int *pos, const int *col, int N, double h, const double *k,

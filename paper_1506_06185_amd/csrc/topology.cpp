@@ -23,10 +23,6 @@ inline bool on_boundary(int N, int x, int y, int z) {
     return x == 0 || y == 0 || z == 0 || x == N || y == N || z == N;
 }
 
-// the 14 Freudenthal neighbour directions (grid units), centre first
-constexpr int kF15[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
-                             {0, 0, 1},  {0, 0, -1}, {1, 1, 0},   {-1, -1, 0}, {0, 1, 1},
-                             {0, -1, -1}, {1, 0, 1}, {-1, 0, -1}, {1, 1, 1},  {-1, -1, -1}};
 constexpr int kAxis6[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 
 }  // namespace
@@ -197,7 +193,7 @@ void Topology::build_level(int l) {
     for (int f = 0; f < Lv.n_ifc; f++)
         for (int e = 0; e < 15; e++) {
             const auto &X = Lv.ifc_X[f];
-            Lv.nb15[(size_t)e * Lv.n_ifc + f] = (int)slot_of(l, X[0] + kF15[e][0], X[1] + kF15[e][1], X[2] + kF15[e][2]);
+            Lv.nb15[(size_t)e * Lv.n_ifc + f] = (int)slot_of(l, X[0] + kGrid15[e][0], X[1] + kGrid15[e][1], X[2] + kGrid15[e][2]);
         }
 
     // node lists and row tables (shared by all tetrahedra), in slot order
@@ -214,6 +210,17 @@ void Topology::build_level(int l) {
                 }
     Lv.ilist = Lv.rlist;
     Lv.ilist.insert(Lv.ilist.end(), Lv.blist.begin(), Lv.blist.end());
+    for (int q = 0; q < 4; q++) Lv.qlist[q].clear();
+    for (int c = 0; c < 2; c++)
+        for (unsigned w : (c ? Lv.blist : Lv.rlist)) {
+            const int i = (int)(w & 1023u), j = (int)((w >> 10) & 1023u), k = (int)(w >> 20);
+            Lv.qlist[(i + 2 * j + 3 * k) & 3].push_back(w);
+        }
+    for (int q = 0; q < 4; q++) Lv.ifcq[q].clear();
+    for (int f = 0; f < Lv.n_ifc; f++) {
+        const auto &X = Lv.ifc_X[f];
+        Lv.ifcq[(X[0] + X[1] + X[2]) & 3].push_back(f);
+    }
     const int nrows = M * (M + 1) / 2;
     Lv.rowC.assign(nrows, {0, 0});
     for (int r = 0; r < nrows; r++) Lv.rowC[r] = {Lv.lay.row0[2 * (size_t)r], Lv.lay.row0[2 * (size_t)r + 1]};
@@ -227,6 +234,22 @@ void Topology::build_level(int l) {
                                                                 start(j + 1, k, o) + odd - 1,
                                                                 start(j - 1, k, o) + odd, start(j - 1, k + 1, o),
                                                                 start(j + 1, k - 1, o),   0, 0};
+            }
+    // 15-point bases: node i = 2t + p (p = (c + k) & 1) of row (j, k); its
+    // neighbour at index offset (di, dj, dk) has parity colour (c + di + dk) & 1
+    // and storage index (i + di) >> 1 = t + ((p + di) >> 1)
+    Lv.rowN15.assign(2 * (size_t)nrows, {});
+    for (int c = 0; c < 2; c++)
+        for (int k = 1; k <= m - 3; k++)
+            for (int j = 1; j + k <= m - 2; j++) {
+                const int p = (c + k) & 1;
+                auto &e = Lv.rowN15[(size_t)c * nrows + row_id(M, j, k)];
+                for (int n = 0; n < 15; n++) {
+                    const int di = kIdx15[n][0], dj = kIdx15[n][1], dk = kIdx15[n][2];
+                    const int cc = (c + di + dk) & 1;
+                    e[n] = Lv.lay.row0[2 * (size_t)row_id(M, j + dj, k + dk) + cc] + ((p + di) >> 1);
+                }
+                e[15] = 0;
             }
 }
 
@@ -247,7 +270,7 @@ void Topology::build_transfer(int l) {
         const auto &X = Cl.ifc_X[f];
         for (int e = 0; e < 15; e++)
             Cl.rst[(size_t)e * Cl.n_ifc + f] =
-                (int)slot_of(l, 2 * X[0] + kF15[e][0], 2 * X[1] + kF15[e][1], 2 * X[2] + kF15[e][2]);
+                (int)slot_of(l, 2 * X[0] + kGrid15[e][0], 2 * X[1] + kGrid15[e][1], 2 * X[2] + kGrid15[e][2]);
     }
 }
 
@@ -305,6 +328,12 @@ void Topology::build_coarse() {
             cs.grid_dir[7 * q + 1 + e] = 1 + e;
         }
     }
+    cs.col15.assign(15 * (size_t)cs.n, -1);
+    for (int q = 0; q < cs.n; q++)
+        for (int e = 0; e < 15; e++) {
+            long long s = slot_of(Lc, pos[q][0] + kGrid15[e][0], pos[q][1] + kGrid15[e][1], pos[q][2] + kGrid15[e][2]);
+            cs.col15[15 * (size_t)q + e] = s == Lv.zero_slot ? -1 : unknown_of_slot(s);
+        }
     cs.cptr.assign(cs.n + 1, 0);
     cs.cidx.clear();
     for (int q = 0; q < cs.n; q++) {

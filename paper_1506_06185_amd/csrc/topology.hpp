@@ -104,7 +104,26 @@ struct TopoLevel {
     // (i-1,j,k) is the (i+1,j,k) base minus one.  Zero for rows without
     // interior nodes.
     std::vector<std::array<int, 8>> rowN;
+    // general macro meshes (15-point stencils, 4-colour smoother): interior
+    // nodes of each class (i + 2j + 3k) mod 4 = (x + y + z) mod 4, in slot order;
+    // per parity colour c and row r at [c * rows + r], the 15 bases of the
+    // node and of its neighbours at the index offsets kIdx15 (node at base +
+    // (i >> 1)); interface masters of each class
+    std::array<std::vector<unsigned>, 4> qlist;
+    std::vector<std::array<int, 16>> rowN15;
+    std::array<std::vector<int>, 4> ifcq;
 };
+
+// index-space offsets of the 15-point stencil (centre first); offset n
+// of a tetrahedron with axis order (a, b, c) is the grid step
+// di e_a + dj (e_a + e_b) + dk (e_a + e_b + e_c)
+constexpr int kIdx15[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0},
+                               {0, -1, 1}, {0, 1, -1}, {0, 1, 0},  {0, -1, 0}, {-1, 0, 1},
+                               {1, 0, -1}, {1, -1, 1}, {-1, 1, -1}, {0, 0, 1}, {0, 0, -1}};
+// grid offsets of the 15-point stencil (centre first), the order of nb15
+constexpr int kGrid15[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {0, 1, 1},
+                                {0, -1, -1}, {1, 0, 1}, {-1, 0, -1}, {1, 1, 1}, {-1, -1, -1}};
 
 // coarsest-level direct data (Jacobi-PCG in one workgroup)
 struct CoarseSystem {
@@ -115,6 +134,7 @@ struct CoarseSystem {
     std::vector<std::array<int, 3>> pos;  // grid position of every unknown
     std::vector<int> cptr, cidx;     // unknown -> all slots holding it (master + ghosts)
     std::vector<int> grid_dir;       // [n][7] grid direction code of each column (0 self, 1..6 +x,-x,+y,-y,+z,-z)
+    std::vector<int> col15;          // [n][15] unknowns at the kGrid15 offsets, -1 = none
     std::vector<int> is_vol;         // 1 if volume-interior unknown
     std::vector<int> tet;            // tet of a volume unknown, -1 for interface
     std::vector<int> ifc;            // interface index, -1 for volume

@@ -33,7 +33,7 @@ class HHGRError(RuntimeError):
 class Desc(C.Structure):
     _fields_ = [("n_sub", C.c_int), ("level", C.c_int), ("coarse_level", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("omega", C.c_double), ("precision", C.c_int),
-                ("variable_coeff", C.c_int), ("max_faults", C.c_int)]
+                ("variable_coeff", C.c_int), ("max_faults", C.c_int), ("general_geometry", C.c_int)]
 
 
 class Report(C.Structure):
@@ -62,6 +62,7 @@ def lib():
         "hhgr_sizes": (C.c_int, [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
         "hhgr_set_rhs": (C.c_int, [_vp, _vp, C.c_int]),
         "hhgr_set_coeff": (C.c_int, [_vp, _vp]),
+        "hhgr_set_geometry": (C.c_int, [_vp, _dp]),
         "hhgr_set_solution": (C.c_int, [_vp, _vp]),
         "hhgr_get_solution": (C.c_int, [_vp, _vp]),
         "hhgr_vcycle": (C.c_int, [_vp, C.c_int, _dp]),
@@ -94,7 +95,7 @@ def lib():
 
 
 EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_destroy", "hhgr_sizes",
-            "hhgr_set_rhs", "hhgr_set_coeff", "hhgr_set_solution", "hhgr_get_solution", "hhgr_vcycle",
+            "hhgr_set_rhs", "hhgr_set_coeff", "hhgr_set_geometry", "hhgr_set_solution", "hhgr_get_solution", "hhgr_vcycle",
             "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_recover_dn", "hhgr_adjoint_grad",
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
@@ -109,7 +110,7 @@ def _check(rc: int, allow=()):
 
 
 def make_desc(n_sub=2, level=7, coarse_level=2, nu_pre=2, nu_post=1, omega=1.25, precision="fp64",
-              variable_coeff=False, max_faults=8) -> Desc:
+              variable_coeff=False, max_faults=8, general_geometry=False) -> Desc:
     d = Desc()
     lib().hhgr_desc_default(C.byref(d))
     d.n_sub, d.level, d.coarse_level = int(n_sub), int(level), int(coarse_level)
@@ -117,6 +118,7 @@ def make_desc(n_sub=2, level=7, coarse_level=2, nu_pre=2, nu_post=1, omega=1.25,
     d.precision = {"fp64": HHGR_FP64, "mixed": HHGR_MIXED}[precision]
     d.variable_coeff = int(bool(variable_coeff))
     d.max_faults = int(max_faults)
+    d.general_geometry = int(bool(general_geometry))
     return d
 
 
@@ -179,6 +181,15 @@ class Context:
 
     def set_coeff(self, k: torch.Tensor):
         _check(lib().hhgr_set_coeff(self._h, _ptr(k)))
+
+    def set_geometry(self, vertices):
+        """Macro vertex positions ((n+1)^3, 3), x fastest (host array)."""
+        import numpy as np
+
+        xyz = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1)
+        if xyz.size != 3 * (self.desc.n_sub + 1) ** 3:
+            raise HHGRError(HHGR_EINVAL, f"expected {(self.desc.n_sub + 1) ** 3} vertices, got {xyz.size / 3:g}")
+        _check(lib().hhgr_set_geometry(self._h, xyz.ctypes.data_as(_dp)))
 
     def set_solution(self, u: torch.Tensor):
         _check(lib().hhgr_set_solution(self._h, _ptr(u)))

@@ -2,6 +2,7 @@
 // armed Dirichlet-Dirichlet recoveries, graph bookkeeping) against the mock
 // HIP runtime, under AddressSanitizer: the numerical kernels are skipped, so
 // this checks control flow, table sizes and host memory use only.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -96,6 +97,66 @@ int main() {
     CHECK(hhgr_set_tuning(cs[1].h, 0, 512, 0, 4) == HHGR_OK, "tuning");
     CHECK(hhgr_set_tuning(cs[1].h, 0, 100, 0, 4) == HHGR_EINVAL, "bad tuning");
     CHECK(hhgr_autotune(cs[1].h, nullptr) == HHGR_OK, "autotune");
+    {
+        // general macro mesh: stencils from moved vertices, cycles and recoveries
+        g_mock_res2 = 1.0;
+        hhgr_desc d;
+        hhgr_desc_default(&d);
+        d.n_sub = 2;
+        d.level = 5;
+        d.general_geometry = 1;
+        hhgr_desc bad = d;
+        bad.precision = HHGR_MIXED;
+        size_t bytes = 0;
+        CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_EINVAL, "general + mixed rejected");
+        bad = d;
+        bad.variable_coeff = 1;
+        CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_EINVAL, "general + variable k rejected");
+        CHECK(hhgr_workspace_bytes(&d, &bytes) == HHGR_OK, "general workspace");
+        void *ws = std::aligned_alloc(256, (bytes + 255) / 256 * 256);
+        hhgr_ctx *g = nullptr;
+        CHECK(hhgr_create(&d, ws, bytes, nullptr, &g) == HHGR_OK, "general create: %s", hhgr_last_error());
+        long long nd = 0;
+        hhgr_sizes(g, &nd, nullptr, nullptr);
+        std::vector<double> v(nd, 1.0), w(nd, 0.0);
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "general rhs");
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_ESTATE, "general nodal f rejected");
+        CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_ESTATE, "no geometry yet");
+        std::vector<double> xyz;
+        for (int z = 0; z <= 2; z++)
+            for (int y = 0; y <= 2; y++)
+                for (int x = 0; x <= 2; x++) {
+                    const double j = 0.03 * std::sin(1.0 + x + 3.0 * y + 7.0 * z);
+                    xyz.push_back(x / 2.0 + j);
+                    xyz.push_back(y / 2.0 - j);
+                    xyz.push_back(z / 2.0 + 0.5 * j);
+                }
+        CHECK(hhgr_set_geometry(cs[1].h, xyz.data()) == HHGR_ESTATE, "geometry needs a general context");
+        CHECK(hhgr_set_geometry(g, xyz.data()) == HHGR_OK, "set geometry: %s", hhgr_last_error());
+        CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "general vcycle");
+        CHECK(hhgr_set_graph(g, 1) == HHGR_OK, "general graph on");
+        CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "general graph vcycle");
+        CHECK(hhgr_recover_local(g, 5, 2, &rr) == HHGR_OK, "general recover_local: %s", hhgr_last_error());
+        CHECK(hhgr_recover_dd(g, t2, 2, 2, 3) == HHGR_OK, "general recover_dd: %s", hhgr_last_error());
+        CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_ESTATE, "general dn rejected");
+        CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_ESTATE, "general mass rejected");
+        CHECK(hhgr_autotune(g, nullptr) == HHGR_ESTATE, "general autotune rejected");
+        CHECK(hhgr_debug_op(g, 0, 5, v.data(), v.data(), w.data()) == HHGR_OK, "general residual op");
+        CHECK(hhgr_debug_op(g, 1, 5, v.data(), v.data(), w.data()) == HHGR_EINVAL, "general op 1 rejected");
+        CHECK(hhgr_debug_op(g, 8 + 5, 5, v.data(), v.data(), w.data()) == HHGR_OK, "general class op");
+        CHECK(hhgr_debug_op(g, 24, 5, v.data(), v.data(), w.data()) == HHGR_EINVAL, "op 24 rejected");
+        CHECK(hhgr_debug_op(g, 6, 2, v.data(), v.data(), w.data()) == HHGR_OK, "general coarse op");
+        xyz[3 * 13] = 5.0;  // centre vertex pulled far outside: inverted tetrahedra
+        CHECK(hhgr_set_geometry(g, xyz.data()) == HHGR_EINVAL, "inverted mesh rejected");
+        hhgr_ctx *pair[2] = {g, cs[1].h};
+        hhgr_batch *gb = nullptr;
+        CHECK(hhgr_batch_create(pair, 2, nullptr, &gb) == HHGR_OK, "general batch");
+        rc = hhgr_batch_run(gb, 1e-10, 3, nullptr);
+        CHECK(rc == HHGR_ENOCONV, "general batch run: %d %s", rc, hhgr_last_error());
+        hhgr_batch_destroy(gb);
+        hhgr_destroy(g);
+        std::free(ws);
+    }
     for (auto &c : cs) {
         hhgr_destroy(c.h);
         std::free(c.ws);

@@ -76,6 +76,19 @@ void launch_vol_weights(hipStream_t, const VolGeom &, const int *, int, int, dou
 void launch_ifc_weights(hipStream_t, int, const int *, int, double, const double *, double *) {}
 void launch_coarse_vals(hipStream_t, int, const int *, const int *, int, double, const double *, double *) {}
 void launch_dirichlet_load(hipStream_t, int, double, const double *, const double *, double *) {}
+void launch_colour15(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, double *, const double *, double) {}
+int launch_residual15(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const Gen15 &, const double *, const double *,
+                      double *, double *partial) {
+    const long long nb = ifc_blocks_of(ig, vg.bs) + list_blocks_of(vg, 1);
+    if (partial)
+        for (long long q = 0; q < nb; q++) partial[q] = q == 0 ? g_mock_res2 : 0.0;
+    return (int)nb;
+}
+void launch_coarse_pcg15(hipStream_t, int, const long long *, const int *, const double *, const unsigned char *,
+                         const double *, double *, const int *, const int *, double, int, int *iters) {
+    if (iters) *iters = 0;
+}
+void launch_local_coarse15(hipStream_t, const VolDesc *, int, int, const double *, const double *, double *) {}
 void launch_dn_masks(hipStream_t, int, long long, long long, const int *, const int *, const unsigned char *,
                      unsigned char *, unsigned char *, int *) {}
 void launch_grad_k(hipStream_t, const double *, const double *, int, double, double *) {}

@@ -193,6 +193,49 @@ int main(int argc, char **argv) {
         }
         for (unsigned wv : T.rlist) CHECK((((wv & 1023) + (wv >> 20)) & 1) == 0, "red list colour");
         for (unsigned wv : T.blist) CHECK((((wv & 1023) + (wv >> 20)) & 1) == 1, "black list colour");
+        // 15-point tables of general macro meshes: class lists partition the
+        // interior (and the masters), neighbours of a node are in other
+        // classes, and the row bases give every neighbour's slot
+        {
+            size_t nq = 0, nf = 0;
+            for (int q = 0; q < 4; q++) {
+                nq += T.qlist[q].size();
+                nf += T.ifcq[q].size();
+                long long lastq = -1;
+                for (unsigned wv : T.qlist[q]) {
+                    const int i = wv & 1023, j = (wv >> 10) & 1023, k = (int)(wv >> 20);
+                    CHECK(((i + 2 * j + 3 * k) & 3) == q, "class list membership");
+                    const long long sl = T.lay.index(i, j, k);
+                    const bool same_part = lastq < 0 || ((sl < T.lay.black0) == (lastq < T.lay.black0));
+                    CHECK(!same_part || sl > lastq, "class list in slot order");
+                    lastq = sl;
+                    const auto &e = T.rowN15[(size_t)((i + k) & 1) * T.rowC.size() + row_of(T.M, j, k)];
+                    for (int n = 0; n < 15; n++) {
+                        const int a = i + kIdx15[n][0], b = j + kIdx15[n][1], c = k + kIdx15[n][2];
+                        CHECK(a >= 0 && b >= 0 && c >= 0 && a + b + c <= m, "15-point neighbour in closure");
+                        CHECK(e[n] + (i >> 1) == T.lay.index(a, b, c), "rowN15 slot n=%d", n);
+                        if (n > 0) CHECK(((a + 2 * b + 3 * c) & 3) != q, "neighbour in another class");
+                    }
+                }
+                for (int f : T.ifcq[q]) {
+                    const auto &X = T.ifc_X[f];
+                    CHECK(((X[0] + X[1] + X[2]) & 3) == q, "interface class");
+                }
+            }
+            CHECK(nq == T.ilist.size() && nf == (size_t)T.n_ifc, "class lists partition");
+            for (int t = 0; t < tp.n_tets; t++)
+                for (int n = 1; n < 15; n++) {
+                    int d[3] = {0, 0, 0};
+                    const auto &P = tp.perm[t];
+                    d[P[0]] += kIdx15[n][0] + kIdx15[n][1] + kIdx15[n][2];
+                    d[P[1]] += kIdx15[n][1] + kIdx15[n][2];
+                    d[P[2]] += kIdx15[n][2];
+                    int hit = 0;
+                    for (int e2 = 1; e2 < 15; e2++)
+                        hit += d[0] == kGrid15[e2][0] && d[1] == kGrid15[e2][1] && d[2] == kGrid15[e2][2];
+                    CHECK(hit == 1, "index offset %d of tet %d is one grid stencil offset", n, t);
+                }
+        }
         // every interior node of every tet: kernel slot arithmetic vs the
         // topology's independent grid lookup
         for (int t = 0; t < tp.n_tets; t++) {

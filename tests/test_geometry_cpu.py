@@ -1,0 +1,159 @@
+"""Host-side 15-point stencils of general macro meshes (moved macro vertices,
+each macro tetrahedron refined regularly and mapped affinely; Sec. 3.1)
+against the oracle's stiffness matrices assembled element by element in
+physical coordinates (CPU only, no GPU calls).
+
+The library keeps one stencil per tetrahedron for volume nodes and one per
+primitive for interface masters; every such stencil is compared here with
+the oracle's matrix row of EVERY node that uses it, so a wrong element-to-
+tetrahedron assignment, a wrong offset order or a node whose row differs from
+its primitive's shows up as a mismatch."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_06185_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# grid offsets of the 15-point stencil (centre first): the order of the
+# interface tables, and index-space offsets of the volume stencils (entry n
+# of a tetrahedron with axis order (a, b, c) is the grid step
+# di e_a + dj (e_a + e_b) + dk (e_a + e_b + e_c))
+GRID15 = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1), (1, 1, 0),
+                   (-1, -1, 0), (0, 1, 1), (0, -1, -1), (1, 0, 1), (-1, 0, -1), (1, 1, 1), (-1, -1, -1)])
+IDX15 = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (-1, 1, 0), (1, -1, 0), (0, -1, 1), (0, 1, -1), (0, 1, 0),
+                  (0, -1, 0), (-1, 0, 1), (1, 0, -1), (1, -1, 1), (-1, 1, -1), (0, 0, 1), (0, 0, -1)])
+
+
+@pytest.fixture(scope="module")
+def dump_exe(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("geom") / "geometry_dump")
+    csrc = os.path.join(ROOT, "paper_1506_06185_amd", "csrc")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-o", exe,
+                    os.path.join(ROOT, "tests", "host", "geometry_dump.cpp"),
+                    os.path.join(csrc, "topology.cpp"), os.path.join(csrc, "geometry.cpp")], check=True)
+    return exe
+
+
+def dump(exe, out, n_sub, level, vertices):
+    vf = str(out / "v.f64")
+    np.ascontiguousarray(vertices, dtype=np.float64).tofile(vf)
+    r = subprocess.run([exe, str(n_sub), str(level), "2", vf, str(out)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    return r.stdout
+
+
+def entries(A, rows, cols):
+    if len(rows) == 0:
+        return np.zeros(0)
+    return np.asarray(A[rows, cols]).ravel()
+
+
+def vidx(X, N):
+    return (X[:, 0] - 1) + (N - 1) * ((X[:, 1] - 1) + (N - 1) * (X[:, 2] - 1))
+
+
+def interior(Y, N):
+    return np.all((Y >= 1) & (Y <= N - 1), axis=1)
+
+
+@pytest.mark.parametrize("n_sub,level,seed", [(1, 4, 3), (2, 3, 5), (2, 4, 11), (3, 3, 2)])
+def test_host_stencils_match_oracle_rows(dump_exe, tmp_path, n_sub, level, seed):
+    V = inputs.perturbed_vertices(n_sub, seed)
+    dump(dump_exe, tmp_path, n_sub, level, V)
+    p = oracle.Problem(n_sub, level, vertices=V)
+    tets = np.fromfile(tmp_path / "tets.i32", dtype=np.int32).reshape(2, -1, 3)
+    for l in range(2, level + 1):
+        A = p.matrix(l).tocsr()
+        N, m = n_sub << l, 1 << l
+        scale = np.abs(A.diagonal()).max()
+        X = np.fromfile(tmp_path / f"l{l}_X.i32", dtype=np.int32).reshape(-1, 3)
+        sid = np.fromfile(tmp_path / f"l{l}_sid.i32", dtype=np.int32)
+        wtab = np.fromfile(tmp_path / f"l{l}_wtab.f64").reshape(-1, 15)
+        w15 = np.fromfile(tmp_path / f"l{l}_w15.f64").reshape(-1, 15)
+        assert len(X) == len(sid) and sid.min() >= 0 and sid.max() < len(wtab)
+        # distinct stencils: at most one per macro face, edge and vertex
+        assert len(wtab) <= 14 * 6 * n_sub ** 3
+        # interface masters: every entry of every row
+        rows = vidx(X, N)
+        covered = np.zeros(len(X))
+        for e in range(15):
+            Y = X + GRID15[e]
+            ok = interior(Y, N)
+            got = wtab[sid[ok], e]
+            want = entries(A, rows[ok], vidx(Y[ok], N))
+            np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * scale, err_msg=f"level {l} offset {e}")
+            covered[ok] += np.abs(want)
+        # nothing of the oracle's rows lies outside the 15 offsets
+        np.testing.assert_allclose(covered, np.asarray(abs(A)[rows].sum(axis=1)).ravel(), rtol=1e-12)
+        # volume nodes: every interior node of every tetrahedron
+        for t in range(len(w15)):
+            a, b, c = tets[1, t]
+            ijk = np.array([(i, j, k) for k in range(1, m) for j in range(1, m) for i in range(1, m)
+                            if i + j + k <= m - 1])
+            Xt = np.tile(m * tets[0, t], (len(ijk), 1))
+            Xt[:, a] += ijk.sum(axis=1)
+            Xt[:, b] += ijk[:, 1] + ijk[:, 2]
+            Xt[:, c] += ijk[:, 2]
+            for n in range(15):
+                g = np.zeros(3, dtype=np.int64)
+                g[a] += IDX15[n].sum()
+                g[b] += IDX15[n][1] + IDX15[n][2]
+                g[c] += IDX15[n][2]
+                Y = Xt + g
+                ok = interior(Y, N)
+                want = entries(A, vidx(Xt[ok], N), vidx(Y[ok], N))
+                np.testing.assert_allclose(np.full(ok.sum(), w15[t, n]), want, rtol=0, atol=1e-12 * scale,
+                                           err_msg=f"level {l} tet {t} offset {n}")
+    # coarsest level: matrix rows over the unknowns
+    A = p.matrix(2).tocsr()
+    N = n_sub << 2
+    pos = np.fromfile(tmp_path / "c_pos.i32", dtype=np.int32).reshape(-1, 3)
+    col = np.fromfile(tmp_path / "c_col15.i32", dtype=np.int32).reshape(-1, 15)
+    val = np.fromfile(tmp_path / "c_val15.f64").reshape(-1, 15)
+    for e in range(15):
+        Y = pos + GRID15[e]
+        ok = col[:, e] >= 0
+        assert np.array_equal(ok, interior(Y, N))
+        assert np.array_equal(pos[col[ok, e]], Y[ok])
+        np.testing.assert_allclose(val[ok, e], entries(A, vidx(pos[ok], N), vidx(Y[ok], N)), rtol=0,
+                                   atol=1e-12 * np.abs(A.diagonal()).max())
+        assert np.all(val[~ok, e] == 0.0)
+
+
+def test_undeformed_geometry_gives_kuhn_stencils(dump_exe, tmp_path):
+    """Unmoved vertices: volume stencils are h times the 7-point stencil (6 on
+    the diagonal, -1 on the 6 axis neighbours, 0 on the diagonals)."""
+    n_sub, level = 2, 3
+    t = np.arange(n_sub + 1) / n_sub
+    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+    V = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    dump(dump_exe, tmp_path, n_sub, level, V)
+    for l in range(2, level + 1):
+        h = 1.0 / (n_sub << l)
+        wtab = np.fromfile(tmp_path / f"l{l}_wtab.f64").reshape(-1, 15)
+        kuhn = np.zeros(15)
+        kuhn[0], kuhn[1:7] = 6 * h, -h
+        np.testing.assert_allclose(wtab, np.tile(kuhn, (len(wtab), 1)), atol=1e-14)
+        w15 = np.fromfile(tmp_path / f"l{l}_w15.f64").reshape(-1, 15)
+        # the axis neighbours in index space: (+-1,0,0), (-+1,+-1,0), (0,-+1,+-1)
+        want = np.zeros(15)
+        want[0] = 6 * h
+        want[[1, 2, 3, 4, 5, 6]] = -h
+        np.testing.assert_allclose(w15, np.tile(want, (len(w15), 1)), atol=1e-14)
+
+
+def test_inverted_macro_tetrahedron_is_rejected(dump_exe, tmp_path):
+    n_sub = 1
+    t = np.arange(n_sub + 1) / n_sub
+    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+    V = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    V[7] = [-0.5, -0.5, -0.5]  # the (1,1,1) corner pulled through the opposite one
+    vf = str(tmp_path / "v.f64")
+    V.tofile(vf)
+    r = subprocess.run([dump_exe, "1", "3", "2", vf, str(tmp_path)], capture_output=True, text=True)
+    assert r.returncode == 1 and "inverted or degenerate" in r.stdout
