@@ -1158,6 +1158,9 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
         launch_fill<double>(c->stream, c->cval15, 15LL * cs.n, 0.0);
     }
     launch_fill<unsigned char>(c->stream, c->cfrozen, cs.n, 0);
+    // the scratch vectors' zero slot and Dirichlet ghosts must read zero
+    launch_fill<double>(c->stream, c->aux_u, tp.lev[c->L].n_slots, 0.0);
+    launch_fill<double>(c->stream, c->aux_b, tp.lev[c->L].n_slots, 0.0);
     launch_fill<double>(c->stream, c->dnorm, 8, 0.0);
     launch_fill<unsigned int>(c->stream, c->counter, 64, 0u);
     if (rc != HHGR_OK) return bail(rc);
