@@ -69,8 +69,8 @@ typedef struct {
     int variable_coeff; /* 0: k = 1; 1: per-element k from hhgr_set_coeff               */
     int max_faults;     /* faulty tetrahedra recoverable at once, 0..8, default 8       */
     int general_geometry; /* 0: the unit cube; 1: moved macro vertices from
-                             hhgr_set_geometry (needs precision = HHGR_FP64 and
-                             variable_coeff = 0), default 0                      */
+                             hhgr_set_geometry (needs precision = HHGR_FP64),
+                             default 0                                          */
 } hhgr_desc;
 
 /* Convergence report.  history (optional, caller-owned, history_cap entries)
@@ -107,17 +107,24 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * connectivity stays the Kuhn split of the cube described above, every
  * macro tetrahedron is refined regularly and mapped affinely (so a refined
  * node is the midpoint of its parent edge) and the operator of level l is the
- * P1 stiffness matrix (k = 1) assembled in physical coordinates, with u = 0 on
- * the boundary of the deformed cube.  Since an affine element has a constant
- * stencil, every node of one primitive (tetrahedron interior, face, edge,
- * vertex) shares one 15-point stencil; these are computed on the host and
- * uploaded.  The smoother colours the nodes in the 4 classes (x+y+z) mod 4,
- * which no 15-point stencil couples to themselves; a sweep visits classes
- * 0, 1, 2, 3.  Vectors keep the grid-node order above.  EINVAL for an inverted
- * or degenerate macro tetrahedron; may be called again to move the vertices.
- * Not available with such contexts: mixed precision, variable coefficients,
- * right-hand-side kinds other than HHGR_RHS_LOAD, Dirichlet-Neumann recovery,
- * hhgr_mass_apply, hhgr_adjoint_grad and hhgr_autotune (ESTATE). */
+ * P1 stiffness matrix assembled in physical coordinates.  With k = 1 an
+ * affine element has a constant stencil, so every node of one primitive
+ * (tetrahedron interior, face, edge, vertex) shares one 15-point stencil;
+ * these are computed on the host and uploaded.  With variable_coeff = 1 the
+ * element coefficients of hhgr_set_coeff (element order above; coarse levels
+ * take the mean of the 8 children) weight the element matrices, and the GPU
+ * computes per-node stencils on every level and the coarsest-level matrix
+ * (after both calls, in either order).  The smoother colours the nodes in the
+ * 4 classes (x+y+z) mod 4, which no 15-point stencil couples to themselves; a
+ * sweep visits classes 0, 1, 2, 3.  Vectors keep the grid-node order above;
+ * HHGR_RHS_DIRICHLET takes the boundary values g at the moved boundary nodes
+ * and sets b_i = -sum of A_ij g_j over the boundary neighbours j (after this
+ * call, and after hhgr_set_coeff with variable_coeff = 1; ESTATE otherwise).
+ * EINVAL for an inverted or degenerate macro tetrahedron; may be called again
+ * to move the vertices (a right-hand side from Dirichlet data is not
+ * recomputed).  Not available with such contexts: mixed precision,
+ * HHGR_RHS_NODAL_F, Dirichlet-Neumann recovery, hhgr_mass_apply,
+ * hhgr_adjoint_grad and hhgr_autotune (ESTATE). */
 int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Right-hand side of eq. (2) from a device vector in the vector order above.

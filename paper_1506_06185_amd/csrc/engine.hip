@@ -109,6 +109,9 @@ struct LevelDev {
     double *w15 = nullptr, *wtab = nullptr;
     int *sid = nullptr;
     int wtab_cap = 0;
+    // ... with a per-element coefficient: 7 forward edge weights and the
+    // diagonal per closure slot ([e n_slots + slot]), 15 entries per master
+    double *wv = nullptr, *wi15 = nullptr;
 };
 
 template <typename T>
@@ -165,6 +168,7 @@ struct hhgr_ctx {
     bool gen = false, geom_set = false;
     int *ccol15 = nullptr;
     double *cval15 = nullptr;
+    double *kel = nullptr;  // unit-size element matrices per macro tet and axis order (variable k)
     std::vector<double> cval_host;
     // adjoint temporaries
     double *aux_u = nullptr, *aux_b = nullptr, *user_u = nullptr, *user_l = nullptr;
@@ -286,7 +290,11 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.lc_sl = make_int4((int)ly.index(1, 1, 1), (int)ly.index(0, 1, 1), (int)ly.index(2, 0, 1),
                                 (int)ly.index(1, 2, 0));
         }
-        if (c.vk) {
+        if (c.vk && c.gen) {
+            D.wv = cv.take<double>(8 * (size_t)T.n_slots);
+            D.wi15 = cv.take<double>(15 * (size_t)T.n_ifc);
+            D.kc = cv.take<double>(6 * (size_t)T.N * T.N * T.N);
+        } else if (c.vk) {
             for (int s = 0; s < 3; s++) D.w[s] = cv.take<double>(T.n_slots);
             D.wi = cv.take<double>(6 * (size_t)T.n_ifc);
             if (c.mixed) {
@@ -328,6 +336,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
+        if (c.vk) c.kel = cv.take<double>(96 * (size_t)c.n_tets);
     }
     const TopoLevel &TL = tp.lev[c.L];
     c.aux_u = cv.take<double>(TL.n_slots);
@@ -375,7 +384,6 @@ std::string check_desc(const hhgr_desc *d) {
     if (d->max_faults < 0 || d->max_faults > 8) return "max_faults must be in 0..8";
     if (d->general_geometry != 0 && d->general_geometry != 1) return "general_geometry must be 0 or 1";
     if (d->general_geometry && d->precision != HHGR_FP64) return "general_geometry needs precision = HHGR_FP64";
-    if (d->general_geometry && d->variable_coeff) return "general_geometry needs variable_coeff = 0";
     return "";
 }
 
@@ -443,6 +451,9 @@ Gen15 gen15(const LevelDev &D, int q, bool ifc) {
     g.nb15 = D.nb15;
     g.ifcq = q >= 0 ? D.ifcq[q] : nullptr;
     g.nq = q >= 0 && ifc ? D.nifcq[q] : 0;
+    g.wv = D.wv;
+    g.ws = D.n_slots;
+    g.wi15 = D.wi15;
     return g;
 }
 
@@ -612,7 +623,7 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     if constexpr (std::is_same<T, double>::value) {
         if (c.gen) {
             if (V.local)
-                launch_local_coarse15(s, v.vd, v.nvol, D.lc_sl.x, D.w15, v.b, v.u);
+                launch_local_coarse15(s, v.vd, v.nvol, D.lc_sl.x, gen15(D, -1, false), v.b, v.u);
             else
                 launch_coarse_pcg15(s, c.cn, c.cslot, c.ccol15, c.cval15, V.cfrozen, v.b, v.u, c.cptr, c.cidx,
                                     kCoarseRtol, kCoarseMaxit, c.citers);
@@ -969,6 +980,27 @@ void dd_end(hhgr_ctx &c) {
     for (int l = c.Lc; l <= c.L; l++) c.lev[l].n_masked = 0;
 }
 
+// general macro mesh with a per-element coefficient: the per-node stencils
+// of every level and the coarsest-level rows from the level's k and the
+// element matrices; synchronises
+int gen_weights(hhgr_ctx &c) {
+    GenK G;
+    G.kel = c.kel;
+    G.n_sub = c.d.n_sub;
+    for (int l = c.Lc; l <= c.L; l++) {
+        LevelDev &D = c.lev[l];
+        G.k = D.kc;
+        G.N = D.N;
+        G.m = D.m;
+        launch_gen_weights(c.stream, vgeom(D, D.vd_all, c.n_tets, true), c.tetinfo, G, D.wv, D.n_slots);
+        launch_gen_ifc_weights(c.stream, D.n_ifc, D.ifc_xyz, G, D.wi15);
+        if (l == c.Lc) launch_gen_coarse_vals(c.stream, c.cn, c.cpos, c.ccol15, G, c.cval15);
+    }
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return HHGR_OK;
+}
+
 }  // namespace
 }  // namespace hhgr
 
@@ -1129,7 +1161,10 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
             launch_fill<double>(c->stream, D.lr, n, 0.0);
         }
         launch_fill<unsigned char>(c->stream, D.frozen, T.n_ifc, 0);
-        if (c->vk) {
+        if (c->vk && c->gen) {
+            launch_fill<double>(c->stream, D.wv, 8 * T.n_slots, 0.0);
+            launch_fill<double>(c->stream, D.wi15, 15LL * T.n_ifc, 0.0);
+        } else if (c->vk) {
             for (int s = 0; s < 3; s++) launch_fill<double>(c->stream, D.w[s], T.n_slots, 0.0);
             if (c->mixed)
                 for (int s = 0; s < 3; s++) launch_fill<float>(c->stream, D.w32[s], T.n_slots, 0.0f);
@@ -1198,8 +1233,10 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     if (!c || !dev_vec) return fail(HHGR_EINVAL, "null argument");
     if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F && kind != HHGR_RHS_DIRICHLET)
         return fail(HHGR_EINVAL, "bad rhs kind");
-    if (c->gen && kind != HHGR_RHS_LOAD)
-        return fail(HHGR_ESTATE, "general_geometry contexts take HHGR_RHS_LOAD only");
+    if (c->gen && kind == HHGR_RHS_NODAL_F)
+        return fail(HHGR_ESTATE, "general_geometry contexts take HHGR_RHS_LOAD or HHGR_RHS_DIRICHLET");
+    if (c->gen && kind == HHGR_RHS_DIRICHLET && !c->geom_set)
+        return fail(HHGR_ESTATE, "Dirichlet data on a general macro mesh needs hhgr_set_geometry first");
     if (kind == HHGR_RHS_DIRICHLET && c->vk && !c->coeff_set)
         return fail(HHGR_ESTATE, "Dirichlet data with variable_coeff = 1 needs hhgr_set_coeff first");
     LevelDev &D = c->lev[c->L];
@@ -1208,6 +1245,8 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     if (kind == HHGR_RHS_LOAD) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.b);
+    } else if (kind == HHGR_RHS_DIRICHLET && c->gen) {
+        launch_gen_dirichlet(c->stream, vint, ig, gen15(D, -1, false), c->tetinfo, D.ifc_xyz, D.N, dev_vec, D.b);
     } else if (kind == HHGR_RHS_DIRICHLET) {
         // the load in vector order goes through aux_u (n_slots >= (N-1)^3 entries)
         if (D.n_slots < (long long)(D.N - 1) * (D.N - 1) * (D.N - 1)) return fail(HHGR_EINVAL, "aux buffer too small");
@@ -1239,6 +1278,12 @@ int hhgr_set_coeff(hhgr_ctx *c, const double *dev_k) {
     HIPCHK(hipMemcpyAsync(F.kc, dev_k, sizeof(double) * 6 * (size_t)F.N * F.N * F.N, hipMemcpyDeviceToDevice,
                           c->stream));
     for (int l = c->L - 1; l >= c->Lc; l--) launch_coarsen_k(c->stream, c->lev[l + 1].kc, c->lev[l + 1].N, c->lev[l].kc, c->lev[l].N);
+    if (c->gen) {
+        CHKLAUNCH();
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->coeff_set = true;
+        return c->geom_set ? gen_weights(*c) : HHGR_OK;
+    }
     for (int l = c->Lc; l <= c->L; l++) {
         LevelDev &D = c->lev[l];
         launch_vol_weights(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N, D.h, D.kc, D.w[0],
@@ -1263,26 +1308,33 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
     const Topology &tp = *c->topo;
     std::string e = check_macro_mesh(tp, host_xyz);
     if (!e.empty()) return fail(HHGR_EINVAL, e);
-    std::vector<LevelStencils> G(c->L + 1);
-    for (int l = c->Lc; l <= c->L; l++) {
-        e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
-        if (!e.empty()) return fail(HHGR_EINVAL, e);
-    }
-    std::vector<double> cval;
-    coarse_stencils(tp, host_xyz, cval);
     invalidate_graph(*c);
     int rc = HHGR_OK;
-    for (int l = c->Lc; l <= c->L; l++) {
-        LevelDev &D = c->lev[l];
-        rc = rc ? rc : upload(*c, D.w15, G[l].w15.data(), G[l].w15.size() * sizeof(double));
-        rc = rc ? rc : upload(*c, D.wtab, G[l].wtab.data(), G[l].wtab.size() * sizeof(double));
-        rc = rc ? rc : upload(*c, D.sid, G[l].sid.data(), G[l].sid.size() * sizeof(int));
+    // host staging vectors must outlive the copies (synchronised below)
+    std::vector<LevelStencils> G(c->L + 1);
+    std::vector<double> cval, kel;
+    if (c->vk) {
+        // per-node stencils from k and the element matrices (on the GPU)
+        element_matrices(tp, host_xyz, kel);
+        rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
+    } else {
+        for (int l = c->Lc; l <= c->L; l++) {
+            e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
+            if (!e.empty()) return fail(HHGR_EINVAL, e);
+        }
+        coarse_stencils(tp, host_xyz, cval);
+        for (int l = c->Lc; l <= c->L; l++) {
+            LevelDev &D = c->lev[l];
+            rc = rc ? rc : upload(*c, D.w15, G[l].w15.data(), G[l].w15.size() * sizeof(double));
+            rc = rc ? rc : upload(*c, D.wtab, G[l].wtab.data(), G[l].wtab.size() * sizeof(double));
+            rc = rc ? rc : upload(*c, D.sid, G[l].sid.data(), G[l].sid.size() * sizeof(int));
+        }
+        rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
     }
-    rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
-    // the host staging vectors must outlive the copies
     HIPCHK(hipStreamSynchronize(c->stream));
     if (rc) return rc;
     c->geom_set = true;
+    if (c->vk && c->coeff_set) return gen_weights(*c);
     return HHGR_OK;
 }
 

@@ -244,6 +244,31 @@ void coarse_stencils(const Topology &tp, const double *xyz, std::vector<double> 
     }
 }
 
+void element_matrices(const Topology &tp, const double *xyz, std::vector<double> &kel) {
+    kel.assign(96 * (size_t)tp.n_tets, 0.0);
+    for (int t = 0; t < tp.n_tets; t++) {
+        double P[4][3], E[3][3];
+        corners(tp, xyz, t, P);
+        for (int s = 0; s < 3; s++)
+            for (int d = 0; d < 3; d++) E[s][d] = P[s + 1][d] - P[0][d];
+        const int a = tp.perm[t][0], b = tp.perm[t][1], c = tp.perm[t][2];
+        for (int q = 0; q < 6; q++) {
+            int o[4][3] = {};
+            for (int v = 1; v < 4; v++)
+                for (int w = 0; w < v; w++) o[v][kPerm[q][w]] = 1;
+            double ev[3][3];
+            for (int v = 1; v < 4; v++) {
+                const double di = o[v][a] - o[v][b], dj = o[v][b] - o[v][c], dk = o[v][c];
+                for (int x = 0; x < 3; x++) ev[v - 1][x] = di * E[0][x] + dj * E[1][x] + dk * E[2][x];
+            }
+            double K[4][4];
+            p1_stiffness(ev[0], ev[1], ev[2], K);
+            for (int r = 0; r < 4; r++)
+                for (int r2 = 0; r2 < 4; r2++) kel[(6 * (size_t)t + q) * 16 + 4 * r + r2] = K[r][r2];
+        }
+    }
+}
+
 std::string check_macro_mesh(const Topology &tp, const double *xyz) {
     const long long nv = (long long)(tp.n_sub + 1) * (tp.n_sub + 1) * (tp.n_sub + 1);
     for (long long q = 0; q < 3 * nv; q++)

@@ -61,6 +61,12 @@ std::string level_stencils(const Topology &tp, const double *xyz, int l, int cap
 // ([15 q + e], zero where the column is a boundary node).
 void coarse_stencils(const Topology &tp, const double *xyz, std::vector<double> &val);
 
+// Unit-size element matrices of every macro tetrahedron: kel[(6 t + q) 16 +
+// 4 r + r'] is the P1 stiffness entry of vertices r, r' of a fine element with
+// axis order q (vertices at the cube corner offsets 0, e_q0, e_q0 + e_q1,
+// (1,1,1)) inside macro tetrahedron t at m = 1; level m divides it by m.
+void element_matrices(const Topology &tp, const double *xyz, std::vector<double> &kel);
+
 // Orientation check of the macro mesh: every macro tetrahedron must keep the
 // sign of its undeformed volume, and 6 |volume| must exceed 1e-8 times the
 // cube of its longest edge.  Returns an empty string or the error.

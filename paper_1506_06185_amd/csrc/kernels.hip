@@ -437,32 +437,58 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
 // ---------------------------------------------------------------------------
 // general macro meshes: 15-point stencils (see Gen15)
 // ---------------------------------------------------------------------------
+// A u at interface master t (diag: its diagonal entry); VK: the master's own
+// 15 entries, else its primitive's stencil
+template <bool VK>
 __device__ __forceinline__ double master_Au(const IfcGeom &ig, const Gen15 &g, const double *__restrict__ u, int t,
                                             double uo, double &diag) {
-    const double *w = g.wtab + 15LL * g.sid[t];
-    diag = w[0];
     double acc = 0.0;
+    if (VK) {
+        diag = g.wi15[t];
 #pragma unroll
-    for (int n = 1; n < 15; n++) acc += w[n] * u[g.nb15[(long long)n * ig.stride + t]];
+        for (int n = 1; n < 15; n++)
+            acc += g.wi15[(long long)n * ig.stride + t] * u[g.nb15[(long long)n * ig.stride + t]];
+    } else {
+        const double *w = g.wtab + 15LL * g.sid[t];
+        diag = w[0];
+#pragma unroll
+        for (int n = 1; n < 15; n++) acc += w[n] * u[g.nb15[(long long)n * ig.stride + t]];
+    }
     return diag * uo + acc;
 }
 
+// A u at a volume node of tetrahedron d.tet (c0: its slot in the closure);
+// VK: forward edge n = 2e + 1 is weight e at the node's own slot, backward
+// edge n = 2e + 2 is weight e at the neighbour's slot
+template <bool VK>
 __device__ __forceinline__ double volume_Au(const VolGeom &vg, const Gen15 &g, const VolDesc &d, const LNode &nd,
                                             const double *__restrict__ uv, int &c0, double &uo, double &diag) {
     const int4 *e4 = (const int4 *)(g.rowN15 + 16 * ((long long)((nd.i + nd.k) & 1) * vg.nrows + nd.r));
     const int4 E0 = e4[0], E1 = e4[1], E2 = e4[2], E3 = e4[3];
     const int t = nd.i >> 1;
-    const double *w = g.w15 + 15LL * d.tet;
     const int sl[15] = {E0.x, E0.y, E0.z, E0.w, E1.x, E1.y, E1.z, E1.w, E2.x, E2.y, E2.z, E2.w, E3.x, E3.y, E3.z};
     c0 = sl[0] + t;
     uo = uv[c0];
-    diag = w[0];
     double acc = 0.0;
+    if (VK) {
+        const double *W = g.wv + d.w;
+        diag = W[7 * g.ws + c0];
 #pragma unroll
-    for (int n = 1; n < 15; n++) acc += w[n] * uv[sl[n] + t];
+        for (int n = 1; n < 15; n++) {
+            const int sn = sl[n] + t;
+            const double w = (n & 1) ? W[((n - 1) >> 1) * g.ws + c0] : W[((n - 2) >> 1) * g.ws + sn];
+            acc += w * uv[sn];
+        }
+    } else {
+        const double *w = g.w15 + 15LL * d.tet;
+        diag = w[0];
+#pragma unroll
+        for (int n = 1; n < 15; n++) acc += w[n] * uv[sl[n] + t];
+    }
     return diag * uo + acc;
 }
 
+template <bool VK>
 __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, double *__restrict__ u,
                                                   const double *__restrict__ b, double omega) {
     const unsigned f = blockIdx.x;
@@ -474,7 +500,7 @@ __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 
         const long long sl = ig.base + t;
         const double uo = u[sl];
         double diag;
-        const double Au = master_Au(ig, g, u, t, uo, diag);
+        const double Au = master_Au<VK>(ig, g, u, t, uo, diag);
         const double un = uo + omega * (b[sl] - Au) / diag;
         u[sl] = un;
         if (ig.gptr)
@@ -489,11 +515,11 @@ __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 
     double *uv = u + d.vec;
     int c0;
     double uo, diag;
-    const double Au = volume_Au(vg, g, d, nd, uv, c0, uo, diag);
+    const double Au = volume_Au<VK>(vg, g, d, nd, uv, c0, uo, diag);
     uv[c0] = uo + omega * ((b + d.vec)[c0] - Au) / diag;
 }
 
-template <bool WRITE, bool NORM>
+template <bool WRITE, bool NORM, bool VK>
 __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen15 g, int nib,
                                                     const double *__restrict__ u, const double *__restrict__ b,
                                                     double *__restrict__ r, double *__restrict__ partial) {
@@ -505,7 +531,7 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
         if (t < ig.i1 && !(ig.frozen && ig.frozen[t])) {
             const long long sl = ig.base + t;
             double diag;
-            const double res = b[sl] - master_Au(ig, g, u, t, u[sl], diag);
+            const double res = b[sl] - master_Au<VK>(ig, g, u, t, u[sl], diag);
             if (WRITE) r[sl] = res;
             acc2 = res * res;
         }
@@ -517,7 +543,7 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
             const VolDesc d = vg.vd[nd.v];
             int c0;
             double uo, diag;
-            const double Au = volume_Au(vg, g, d, nd, u + d.vec, c0, uo, diag);
+            const double Au = volume_Au<VK>(vg, g, d, nd, u + d.vec, c0, uo, diag);
             const double res = (b + d.vec)[c0] - Au;
             if (WRITE) r[d.vec + c0] = res;
             acc2 = res * res;
@@ -529,12 +555,14 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
     }
 }
 
-__global__ void k_local_coarse15(const VolDesc *__restrict__ vd, int nvol, int slot, const double *__restrict__ w15,
+// local coarsest level: u = b / diag at the single interior node (slot)
+__global__ void k_local_coarse15(const VolDesc *__restrict__ vd, int nvol, int slot, Gen15 g,
                                  const double *__restrict__ b, double *__restrict__ u) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvol) return;
     const VolDesc d = vd[v];
-    (u + d.vec)[slot] = (b + d.vec)[slot] / w15[15LL * d.tet];
+    const double diag = g.wv ? g.wv[7 * g.ws + d.w + slot] : g.w15[15LL * d.tet];
+    (u + d.vec)[slot] = (b + d.vec)[slot] / diag;
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,6 +1153,166 @@ __global__ void k_coarse_vals_intact(int n, const int *__restrict__ pos, const i
     val[7 * q] = diag;
 }
 
+// ---------------------------------------------------------------------------
+// general macro meshes with a per-element coefficient (see GenK): the
+// stiffness entry of grid nodes X and X + delta sums k_e K_e[r][r'] over the
+// fine elements e holding both, K_e the matrix of e's macro tetrahedron and
+// axis order at unit size, divided by m; the diagonal (delta = 0) sums over
+// every element at X.  Elements outside the grid are skipped.
+// ---------------------------------------------------------------------------
+__device__ __constant__ int kIdx15D[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0},
+                                              {0, -1, 1}, {0, 1, -1}, {0, 1, 0},  {0, -1, 0}, {-1, 0, 1},
+                                              {1, 0, -1}, {1, -1, 1}, {-1, 1, -1}, {0, 0, 1}, {0, 0, -1}};
+__device__ __constant__ int kGrid15D[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                               {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {0, 1, 1},
+                                               {0, -1, -1}, {1, 0, 1}, {-1, 0, -1}, {1, 1, 1}, {-1, -1, -1}};
+
+// offset of vertex v of an element with axis order q from its cube corner:
+// 0, e_q0, e_q0 + e_q1, (1,1,1)
+__device__ __forceinline__ void elem_vertex(int q, int v, int o[3]) {
+    o[0] = o[1] = o[2] = 0;
+    if (v >= 1) o[kPermD[q][0]] = 1;
+    if (v >= 2) o[kPermD[q][1]] = 1;
+    if (v >= 3) o[kPermD[q][2]] = 1;
+}
+
+__device__ double gen_entry(const GenK &G, const int X[3], int dx, int dy, int dz) {
+    double s = 0.0;
+    for (int q = 0; q < 6; q++)
+        for (int r = 0; r < 4; r++) {
+            int o[3];
+            elem_vertex(q, r, o);
+            const int c[3] = {X[0] - o[0], X[1] - o[1], X[2] - o[2]};
+            if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= G.N || c[1] >= G.N || c[2] >= G.N) continue;
+            int rr = -1;
+            for (int v = 0; v < 4; v++) {
+                int p[3];
+                elem_vertex(q, v, p);
+                if (p[0] - o[0] == dx && p[1] - o[1] == dy && p[2] - o[2] == dz) rr = v;
+            }
+            if (rr < 0) continue;
+            const long long e = 6 * (c[0] + (long long)G.N * (c[1] + (long long)G.N * c[2])) + q;
+            const int t = macro_tet_of(c[0], c[1], c[2], q, G.m, G.n_sub);
+            s += G.k[e] * G.kel[(6LL * t + q) * 16 + 4 * r + rr];
+        }
+    return s / G.m;
+}
+
+// grid position of node (i,j,k) of tetrahedron t and the grid step of its
+// index offset n
+__device__ __forceinline__ void tet_grid(const int *__restrict__ tetinfo, int t, int m, int i, int j, int k, int X[3]) {
+    for (int a = 0; a < 3; a++) X[a] = m * tetinfo[6 * t + a];
+    X[tetinfo[6 * t + 3]] += i + j + k;
+    X[tetinfo[6 * t + 4]] += j + k;
+    X[tetinfo[6 * t + 5]] += k;
+}
+__device__ __forceinline__ void tet_step(const int *__restrict__ tetinfo, int t, int n, int g[3]) {
+    g[0] = g[1] = g[2] = 0;
+    g[tetinfo[6 * t + 3]] += kIdx15D[n][0] + kIdx15D[n][1] + kIdx15D[n][2];
+    g[tetinfo[6 * t + 4]] += kIdx15D[n][1] + kIdx15D[n][2];
+    g[tetinfo[6 * t + 5]] += kIdx15D[n][2];
+}
+
+// every closure node (vg lists the full closure): the 7 forward edge weights
+// of the edges that stay in the closure (0 otherwise) and the diagonal
+__global__ void __launch_bounds__(256) k_gen_weights(VolGeom vg, const int *__restrict__ tetinfo, GenK G,
+                                                     double *__restrict__ wv, long long ws) {
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    LNode nd;
+    if (!list_node<1>(vg, blockIdx.x, per_vol, 0, nd)) return;
+    const VolDesc d = vg.vd[nd.v];
+    const int m = vg.M - 1;
+    int X[3];
+    tet_grid(tetinfo, d.tet, m, nd.i, nd.j, nd.k, X);
+    const long long sl = d.w + lslot(vg.rowC, vg.M, nd.i, nd.j, nd.k);
+    for (int e = 0; e < 7; e++) {
+        const int n = 2 * e + 1;
+        const int i2 = nd.i + kIdx15D[n][0], j2 = nd.j + kIdx15D[n][1], k2 = nd.k + kIdx15D[n][2];
+        double w = 0.0;
+        if (i2 >= 0 && j2 >= 0 && k2 >= 0 && i2 + j2 + k2 <= m) {
+            int g[3];
+            tet_step(tetinfo, d.tet, n, g);
+            w = gen_entry(G, X, g[0], g[1], g[2]);
+        }
+        wv[e * ws + sl] = w;
+    }
+    wv[7 * ws + sl] = gen_entry(G, X, 0, 0, 0);
+}
+
+__global__ void k_gen_ifc_weights(int n_ifc, const int *__restrict__ xyz, GenK G, double *__restrict__ wi15) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_ifc) return;
+    const int X[3] = {xyz[3 * f], xyz[3 * f + 1], xyz[3 * f + 2]};
+    for (int n = 0; n < 15; n++)
+        wi15[(long long)n * n_ifc + f] = gen_entry(G, X, kGrid15D[n][0], kGrid15D[n][1], kGrid15D[n][2]);
+}
+
+__global__ void k_gen_coarse_vals(int n, const int *__restrict__ pos, const int *__restrict__ col15, GenK G,
+                                  double *__restrict__ val) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int X[3] = {pos[3 * q], pos[3 * q + 1], pos[3 * q + 2]};
+    for (int e = 0; e < 15; e++)
+        val[15 * q + e] = e == 0 || col15[15 * q + e] >= 0
+                              ? gen_entry(G, X, kGrid15D[e][0], kGrid15D[e][1], kGrid15D[e][2])
+                              : 0.0;
+}
+
+// eliminated Dirichlet data on a general macro mesh: b = -sum over the
+// boundary neighbours j of A_ij g_j at every interior node and master
+// (g on the full (N+1)^3 grid, x fastest)
+template <bool VK>
+__global__ void __launch_bounds__(256) k_gen_dirichlet(VolGeom vg, IfcGeom ig, Gen15 g, int nib,
+                                                       const int *__restrict__ tetinfo, const int *__restrict__ ifc_xyz,
+                                                       int N, const double *__restrict__ gfull, double *__restrict__ b) {
+    const long long M1 = N + 1;
+    auto on_bnd = [&](const int *Y) {
+        return Y[0] == 0 || Y[1] == 0 || Y[2] == 0 || Y[0] == N || Y[1] == N || Y[2] == N;
+    };
+    const unsigned f = blockIdx.x;
+    if (f < (unsigned)nib) {
+        const int t = (int)(f * blockDim.x + threadIdx.x);
+        if (t >= ig.i1) return;
+        const int X[3] = {ifc_xyz[3 * t], ifc_xyz[3 * t + 1], ifc_xyz[3 * t + 2]};
+        const double *w = VK ? nullptr : g.wtab + 15LL * g.sid[t];
+        double s = 0.0;
+        for (int n = 1; n < 15; n++) {
+            const int Y[3] = {X[0] + kGrid15D[n][0], X[1] + kGrid15D[n][1], X[2] + kGrid15D[n][2]};
+            if (!on_bnd(Y)) continue;
+            const double a = VK ? g.wi15[(long long)n * ig.stride + t] : w[n];
+            s -= a * gfull[Y[0] + M1 * (Y[1] + M1 * Y[2])];
+        }
+        b[ig.base + t] = s;
+        return;
+    }
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    LNode nd;
+    if (!list_node<1>(vg, f - nib, per_vol, 0, nd)) return;
+    const VolDesc d = vg.vd[nd.v];
+    const int m = vg.M - 1;
+    int X[3];
+    tet_grid(tetinfo, d.tet, m, nd.i, nd.j, nd.k, X);
+    const long long c0 = lslot(vg.rowC, vg.M, nd.i, nd.j, nd.k);
+    double s = 0.0;
+    for (int n = 1; n < 15; n++) {
+        int gs[3];
+        tet_step(tetinfo, d.tet, n, gs);
+        const int Y[3] = {X[0] + gs[0], X[1] + gs[1], X[2] + gs[2]};
+        if (!on_bnd(Y)) continue;
+        double a;
+        if (VK) {
+            const int e = (n - 1) >> 1;
+            const long long sn =
+                lslot(vg.rowC, vg.M, nd.i + kIdx15D[n][0], nd.j + kIdx15D[n][1], nd.k + kIdx15D[n][2]);
+            a = (n & 1) ? g.wv[e * g.ws + d.w + c0] : g.wv[e * g.ws + d.w + sn];
+        } else {
+            a = g.w15[15LL * d.tet + n];
+        }
+        s -= a * gfull[Y[0] + M1 * (Y[1] + M1 * Y[2])];
+    }
+    b[d.vec + c0] = s;
+}
+
 // static Neumann data of the intact side on the interface (Alg. 2): at the
 // nodes flagged in gamma, b_out = (A^I u) from the intact-side weights wi
 __global__ void k_neumann_rhs(int n_ifc, long long base, const int *__restrict__ nbr, const double *__restrict__ wi,
@@ -1423,7 +1611,21 @@ void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const 
     const int nib = g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0;
     const long long grid = nib + list_blocks(vg, 1);
     if (grid == 0) return;
-    hipLaunchKernelGGL(k_colour15, dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b, omega);
+    if (g.wv)
+        hipLaunchKernelGGL(k_colour15<true>, dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b, omega);
+    else
+        hipLaunchKernelGGL(k_colour15<false>, dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b, omega);
+}
+
+template <bool VK>
+static void residual15(hipStream_t s, dim3 gd, dim3 bd, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, int nib,
+                       const double *u, const double *b, double *r, double *partial) {
+    if (r && partial)
+        hipLaunchKernelGGL((k_residual15<true, true, VK>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+    else if (r)
+        hipLaunchKernelGGL((k_residual15<true, false, VK>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+    else
+        hipLaunchKernelGGL((k_residual15<false, true, VK>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
 }
 
 int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const double *u,
@@ -1432,12 +1634,10 @@ int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const
     const long long grid = nib + list_blocks(vg, 1);
     if (grid == 0) return 0;
     const dim3 gd((unsigned)grid), bd(vg.bs);
-    if (r && partial)
-        hipLaunchKernelGGL((k_residual15<true, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
-    else if (r)
-        hipLaunchKernelGGL((k_residual15<true, false>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+    if (g.wv)
+        residual15<true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     else
-        hipLaunchKernelGGL((k_residual15<false, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        residual15<false>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     return (int)grid;
 }
 
@@ -1464,10 +1664,44 @@ void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int 
                            cidx, rtol, maxit, iters);
 }
 
-void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const double *w15, const double *b,
+void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const Gen15 &g, const double *b,
                            double *u) {
     if (nvol <= 0) return;
-    hipLaunchKernelGGL(k_local_coarse15, dim3((unsigned)((nvol + 63) / 64)), dim3(64), 0, s, vd, nvol, slot, w15, b, u);
+    hipLaunchKernelGGL(k_local_coarse15, dim3((unsigned)((nvol + 63) / 64)), dim3(64), 0, s, vd, nvol, slot, g, b, u);
+}
+
+void launch_gen_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo, const GenK &G, double *wv,
+                        long long ws) {
+    VolGeom v = vfull;
+    v.bs = 256;
+    const long long grid = list_blocks(v, 1);
+    if (grid == 0) return;
+    hipLaunchKernelGGL(k_gen_weights, dim3((unsigned)grid), dim3(256), 0, s, v, tetinfo, G, wv, ws);
+}
+
+void launch_gen_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, const GenK &G, double *wi15) {
+    if (n_ifc <= 0) return;
+    hipLaunchKernelGGL(k_gen_ifc_weights, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, ifc_xyz, G, wi15);
+}
+
+void launch_gen_coarse_vals(hipStream_t s, int n, const int *pos, const int *col15, const GenK &G, double *val) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gen_coarse_vals, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, col15, G, val);
+}
+
+void launch_gen_dirichlet(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const Gen15 &g, const int *tetinfo,
+                          const int *ifc_xyz, int N, const double *gfull, double *b) {
+    VolGeom v = vint;
+    v.bs = 256;
+    const int nib = ig.i1 > 0 ? (ig.i1 + 255) / 256 : 0;
+    const long long grid = nib + list_blocks(v, 1);
+    if (grid == 0) return;
+    if (g.wv)
+        hipLaunchKernelGGL(k_gen_dirichlet<true>, dim3((unsigned)grid), dim3(256), 0, s, v, ig, g, nib, tetinfo,
+                           ifc_xyz, N, gfull, b);
+    else
+        hipLaunchKernelGGL(k_gen_dirichlet<false>, dim3((unsigned)grid), dim3(256), 0, s, v, ig, g, nib, tetinfo,
+                           ifc_xyz, N, gfull, b);
 }
 
 void launch_dirichlet_load(hipStream_t s, int N, double h, const double *k, const double *g, double *b) {

@@ -48,6 +48,11 @@ struct IfcGeom {
 // (i >> 1) (c = parity colour, r = row); an interface master f uses the
 // stencil wtab[15 sid[f] + n] at the slots nb15[n stride + f] (grid-offset
 // order of kGrid15).  A class pass walks the masters listed in ifcq[0 .. nq).
+// With a per-element coefficient (wv != nullptr) the stencils vary per node:
+// a closure slot holds the weights of its 7 forward index offsets kIdx15[1],
+// [3], ..., [13] at wv[e ws + slot] (e = 0..6, zero where the edge leaves the
+// closure) and its diagonal at wv[7 ws + slot]; a master holds its 15 entries
+// at wi15[n stride + f] (kGrid15 order).
 struct Gen15 {
     const int *rowN15 = nullptr;
     const double *w15 = nullptr;
@@ -56,6 +61,19 @@ struct Gen15 {
     const int *nb15 = nullptr;
     const int *ifcq = nullptr;
     int nq = 0;
+    const double *wv = nullptr;
+    long long ws = 0;
+    const double *wi15 = nullptr;
+};
+
+// Per-element coefficient on a general macro mesh: k of the level's elements
+// (element order), the unit-size element matrices kel[((6 t + q) 16 + 4 r + r']
+// of macro tetrahedron t and axis order q, the level's cells per axis N and
+// segments per macro edge m.
+struct GenK {
+    const double *k = nullptr;
+    const double *kel = nullptr;
+    int N = 0, m = 0, n_sub = 0;
 };
 
 template <typename T>
@@ -152,9 +170,20 @@ int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const
 void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
                          const unsigned char *frozen, const double *b, double *u, const int *cptr, const int *cidx,
                          double rtol, int maxit, int *iters);
-// local coarsest level of a general macro mesh: u = b / w15[15 tet] at the single interior node
-void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const double *w15, const double *b,
+// local coarsest level of a general macro mesh: u = b / diagonal at the single interior node
+void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const Gen15 &g, const double *b,
                            double *u);
+// per-element coefficient on a general macro mesh: closure-slot weights of
+// every tetrahedron in vfull (full closure lists), interface weights, and the
+// coarsest-level rows (kGrid15 order, zero for boundary columns)
+void launch_gen_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo, const GenK &G, double *wv,
+                        long long ws);
+void launch_gen_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, const GenK &G, double *wi15);
+void launch_gen_coarse_vals(hipStream_t s, int n, const int *pos, const int *col15, const GenK &G, double *val);
+// eliminated Dirichlet data on a general macro mesh into b (slot order):
+// interior nodes of vint and masters [0, ig.i1) of ig
+void launch_gen_dirichlet(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const Gen15 &g, const int *tetinfo,
+                          const int *ifc_xyz, int N, const double *gfull, double *b);
 // b = eliminated Dirichlet data g (full (N+1)^3 grid, x fastest), vector order
 void launch_dirichlet_load(hipStream_t s, int N, double h, const double *k, const double *g, double *b);
 void launch_coarse_vals(hipStream_t s, int n, const int *pos, const int *col, int N, double h, const double *k,

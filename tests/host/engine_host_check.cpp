@@ -109,9 +109,6 @@ int main() {
         bad.precision = HHGR_MIXED;
         size_t bytes = 0;
         CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_EINVAL, "general + mixed rejected");
-        bad = d;
-        bad.variable_coeff = 1;
-        CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_EINVAL, "general + variable k rejected");
         CHECK(hhgr_workspace_bytes(&d, &bytes) == HHGR_OK, "general workspace");
         void *ws = std::aligned_alloc(256, (bytes + 255) / 256 * 256);
         hhgr_ctx *g = nullptr;
@@ -154,6 +151,26 @@ int main() {
         rc = hhgr_batch_run(gb, 1e-10, 3, nullptr);
         CHECK(rc == HHGR_ENOCONV, "general batch run: %d %s", rc, hhgr_last_error());
         hhgr_batch_destroy(gb);
+        hhgr_destroy(g);
+        std::free(ws);
+        // variable coefficient: weights once both the geometry and k are set
+        d.variable_coeff = 1;
+        CHECK(hhgr_workspace_bytes(&d, &bytes) == HHGR_OK, "general vk workspace");
+        ws = std::aligned_alloc(256, (bytes + 255) / 256 * 256);
+        CHECK(hhgr_create(&d, ws, bytes, nullptr, &g) == HHGR_OK, "general vk create: %s", hhgr_last_error());
+        long long ne = 0;
+        hhgr_sizes(g, nullptr, nullptr, &ne);
+        std::vector<double> k(ne, 1.5), gdat(33 * 33 * 33, 0.25);
+        xyz[3 * 13] = 0.5;
+        CHECK(hhgr_set_rhs(g, gdat.data(), HHGR_RHS_DIRICHLET) == HHGR_ESTATE, "vk Dirichlet needs k");
+        CHECK(hhgr_set_coeff(g, k.data()) == HHGR_OK, "general vk coeff: %s", hhgr_last_error());
+        CHECK(hhgr_set_rhs(g, gdat.data(), HHGR_RHS_DIRICHLET) == HHGR_ESTATE, "Dirichlet needs geometry");
+        CHECK(hhgr_set_geometry(g, xyz.data()) == HHGR_OK, "general vk geometry: %s", hhgr_last_error());
+        CHECK(hhgr_set_rhs(g, gdat.data(), HHGR_RHS_DIRICHLET) == HHGR_OK, "general Dirichlet: %s", hhgr_last_error());
+        CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "general vk vcycle");
+        CHECK(hhgr_recover_local(g, 7, 2, &rr) == HHGR_OK, "general vk recover_local");
+        CHECK(hhgr_recover_dd(g, t2, 2, 1, 2) == HHGR_OK, "general vk recover_dd: %s", hhgr_last_error());
+        CHECK(hhgr_set_coeff(g, k.data()) == HHGR_OK, "general vk coeff again");
         hhgr_destroy(g);
         std::free(ws);
     }

@@ -88,7 +88,12 @@ void launch_coarse_pcg15(hipStream_t, int, const long long *, const int *, const
                          const double *, double *, const int *, const int *, double, int, int *iters) {
     if (iters) *iters = 0;
 }
-void launch_local_coarse15(hipStream_t, const VolDesc *, int, int, const double *, const double *, double *) {}
+void launch_local_coarse15(hipStream_t, const VolDesc *, int, int, const Gen15 &, const double *, double *) {}
+void launch_gen_weights(hipStream_t, const VolGeom &, const int *, const GenK &, double *, long long) {}
+void launch_gen_ifc_weights(hipStream_t, int, const int *, const GenK &, double *) {}
+void launch_gen_coarse_vals(hipStream_t, int, const int *, const int *, const GenK &, double *) {}
+void launch_gen_dirichlet(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, const int *, const int *, int,
+                          const double *, double *) {}
 void launch_dn_masks(hipStream_t, int, long long, long long, const int *, const int *, const unsigned char *,
                      unsigned char *, unsigned char *, int *) {}
 void launch_grad_k(hipStream_t, const double *, const double *, int, double, double *) {}

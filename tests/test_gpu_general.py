@@ -54,14 +54,91 @@ def problem(n_sub, level, seed):
     return _PROBLEMS[key]
 
 
-def context(hh, dev, n_sub, level, seed, **kw):
-    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, general_geometry=True, **kw)
+def context(hh, dev, n_sub, level, seed, k=None, **kw):
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, general_geometry=True, variable_coeff=k is not None, **kw)
+    if k is not None:
+        ctx.set_coeff(T(k, dev))
     ctx.set_geometry(inputs.perturbed_vertices(n_sub, seed))
     return ctx
 
 
+def problem_k(n_sub, level, seed, kseed):
+    key = (n_sub, level, seed, "k", kseed)
+    if key not in _PROBLEMS:
+        _PROBLEMS[key] = oracle.Problem(n_sub, level, k=inputs.lognormal_k(n_sub, level, seed=kseed),
+                                        vertices=inputs.perturbed_vertices(n_sub, seed))
+    return _PROBLEMS[key]
+
+
 # several workgroups per class list and ragged tails; 1, 2 and 3 subcubes per axis
 CASES = [(1, 5, 3), (2, 4, 5), (3, 3, 7)]
+K_CASES = [(1, 4, 3), (2, 4, 5), (3, 3, 7)]
+
+
+@pytest.mark.parametrize("n_sub,level,seed", K_CASES)
+def test_variable_k_operators_and_solve(dev, hh, n_sub, level, seed):
+    """Per-element log-normal k on a general macro mesh: per-node stencils on
+    every level (coarse k = mean of the 8 children), class passes, the
+    coarsest-level rows, iterates and a solve."""
+    print(f"\n[general variable k] n_sub={n_sub} level={level} seed={seed}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=seed)
+    ctx = context(hh, dev, n_sub, level, seed, k=k)
+    p = problem_k(n_sub, level, seed, seed)
+    g = np.random.default_rng(500 + seed)
+    for l in range(2, level + 1):
+        nd = p.ndof_at(l)
+        u, b = g.standard_normal(nd), g.standard_normal(nd)
+        r = Nn(hh.debug_op(ctx, 0, l, T(u, dev), T(b, dev)))
+        assert rel(r, p.residual(u, b, level=l)) < 1e-12, l
+        for mask in (1, 2, 4, 8, 15):
+            us = Nn(hh.debug_op(ctx, 8 + mask, l, T(u, dev), T(b, dev)))
+            assert rel(us, p.smooth(u, b, omega=1.25, colours=mask, level=l)) < 1e-12, (l, mask)
+    bc = g.standard_normal(p.ndof_at(2))
+    uc = Nn(hh.debug_op(ctx, 6, 2, T(bc, dev)))
+    uo = p.coarse_solve(bc)
+    uo = uo[0] if isinstance(uo, tuple) else uo
+    assert rel(uc, uo) < 1e-10
+    b = g.uniform(0.0, 1.0, p.ndof) / p.ndof
+    ctx.set_rhs(T(b, dev))
+    ctx.set_solution(T(np.zeros(p.ndof), dev))  # the operator calls above left their input in u
+    ctx.vcycle(2)
+    uo, _, _ = p.solve(b, rtol=0.0, max_cycles=2)
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-12
+    cyc, rr, hist = ctx.solve(1e-10, 80)
+    uo, co, _ = p.solve(b, rtol=1e-10, max_cycles=80)
+    print(f"  {cyc + 2} cycles (oracle {co}), rate {hist[-1] / hist[-2]:.3f}", flush=True)
+    assert cyc + 2 == co
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("vk", [False, True])
+def test_dirichlet_data_and_recovery(dev, hh, vk):
+    """Eq. (1) on a general macro mesh: b from boundary values g, iterates,
+    a fault with local recovery, and the solve, against the oracle."""
+    n_sub, level, seed = 2, 4, 8
+    print(f"\n[general Dirichlet] variable_k={vk}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=2) if vk else None
+    ctx = context(hh, dev, n_sub, level, seed, k=k)
+    p = problem_k(n_sub, level, seed, 2) if vk else problem(n_sub, level, seed)
+    gb = inputs.harmonic_boundary(n_sub, level)
+    b = p.dirichlet_load(gb)
+    ctx.set_rhs(T(gb, dev), hh.HHGR_RHS_DIRICHLET)
+    rr = ctx.vcycle(3)
+    uo, _, ho = p.solve(b, rtol=0.0, max_cycles=3)
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-12
+    assert rr == pytest.approx(ho[3], rel=1e-9)
+    t = inputs.fault_tet(n_sub, seed=4)
+    ctx.inject_fault(t)
+    ctx.recover_local(t, 2)
+    uo = p.inject_fault(t, uo)
+    uo, _ = p.recover_local([t], uo, b, 2)
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-12
+    cyc, rr, _ = ctx.solve(1e-10, 60)
+    uo, co, _ = p.solve(b, u0=uo, rtol=1e-10, max_cycles=60, r0=float(np.linalg.norm(b)))
+    assert cyc == co
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-10
+    ctx.close()
 
 
 @pytest.mark.parametrize("n_sub,level,seed", CASES)
@@ -164,13 +241,14 @@ def test_geometry_level6_iterates(dev, hh):
     ctx.close()
 
 
-def grid_positions(vertices, n_sub, level):
-    """Physical positions of the interior grid nodes (vector order), each
-    node mapped affinely by the macro tetrahedron holding it (ties on faces,
-    edges and vertices give the same point)."""
+def grid_positions(vertices, n_sub, level, full=False):
+    """Physical positions of the interior grid nodes (vector order; with full,
+    of all (N+1)^3 nodes, x fastest), each node mapped affinely by the macro
+    tetrahedron holding it (ties on faces, edges and vertices give the same
+    point)."""
     m = 1 << level
     N = n_sub * m
-    ax = np.arange(1, N)
+    ax = np.arange(0, N + 1) if full else np.arange(1, N)
     z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
     X = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
     cube = np.minimum(X // m, n_sub - 1)
@@ -191,8 +269,8 @@ def grid_positions(vertices, n_sub, level):
 
 def test_full_size_linear_reproduction(dev, hh):
     """2 subcubes per axis, level 7 (the benchmark size): A u = 0 for a linear
-    u away from the boundary, and solving with that u's boundary data
-    recovers u on the whole grid."""
+    u away from the boundary, and solving with that u's values on the moved
+    boundary as Dirichlet data, eq. (1), recovers u on the whole grid."""
     n_sub, level, seed = 2, 7, 5
     print(f"\n[general full size] n_sub={n_sub} level={level}", flush=True)
     V = inputs.perturbed_vertices(n_sub, seed)
@@ -207,11 +285,40 @@ def test_full_size_linear_reproduction(dev, hh):
     scale = np.abs(u).max() / N
     assert np.abs(r[far]).max() < 1e-12 * scale
     assert np.abs(r[~far]).max() > 1e-3 * scale  # boundary data enter next to the boundary
-    # b = boundary terms of u (A u restricted to the interior rows is -r)
-    ctx.set_rhs(T(-r, dev))
+    # Dirichlet data: the linear function on the boundary nodes
+    ug = 0.3 + grid_positions(V, n_sub, level, full=True) @ np.array([1.0, -2.0, 0.5])
+    ctx.set_rhs(T(ug, dev), hh.HHGR_RHS_DIRICHLET)
     ctx.set_solution(T(np.zeros_like(u), dev))  # the operator call above left u in the solver
     cyc, rr, hist = ctx.solve(1e-12, 40)
     err = rel(Nn(ctx.get_solution()), u)
     print(f"  {cyc} cycles, rate {hist[-1] / hist[-2]:.3f}, max error {err:.2e}", flush=True)
     assert err < 1e-8
+    ctx.close()
+
+
+def test_full_size_variable_k_symmetry_and_constants(dev, hh):
+    """2 subcubes per axis, level 7, per-element log-normal k: the per-node
+    stencils give a symmetric operator (x.A y = y.A x for random x, y) whose
+    rows annihilate constants away from the boundary."""
+    n_sub, level, seed = 2, 7, 5
+    print(f"\n[general full size, variable k] n_sub={n_sub} level={level}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=1)
+    ctx = context(hh, dev, n_sub, level, seed, k=k)
+    N = n_sub << level
+    nd = (N - 1) ** 3
+    g = np.random.default_rng(600)
+    x, y = g.standard_normal(nd), g.standard_normal(nd)
+    zero = T(np.zeros(nd), dev)
+    Ax = -Nn(hh.debug_op(ctx, 0, level, T(x, dev), zero))
+    Ay = -Nn(hh.debug_op(ctx, 0, level, T(y, dev), zero))
+    xAy, yAx = float(x @ Ay), float(y @ Ax)
+    print(f"  x.Ay = {xAy:.15e}, y.Ax = {yAx:.15e}", flush=True)
+    assert abs(xAy - yAx) < 1e-11 * np.sqrt(float(x @ Ax) * float(y @ Ay))
+    assert float(x @ Ax) > 0 and float(y @ Ay) > 0
+    A1 = -Nn(hh.debug_op(ctx, 0, level, T(np.ones(nd), dev), zero))
+    ax = np.arange(1, N)
+    zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+    far = ((xx > 1) & (xx < N - 1) & (yy > 1) & (yy < N - 1) & (zz > 1) & (zz < N - 1)).ravel()
+    assert np.abs(A1[far]).max() < 1e-12 * np.abs(Ax).max()
+    assert np.abs(A1[~far]).min() > 0
     ctx.close()
