@@ -45,6 +45,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "colour_pass_fp64_l7_48tets_traffic.json")
+TRAFFIC_FILE_GENERAL = os.path.join(ROOT, "profiles", "class_pass15_fp64_l7_48tets_traffic.json")
 
 
 def log(msg):
@@ -56,7 +57,7 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(n_sub: int, level: int):
+def measured_traffic(n_sub: int, level: int, path: str = TRAFFIC_FILE):
     """HBM bytes per launch of the finest-level colour pass from the committed
     rocprofv3 counter summary, or None when the summary is not for this workload
     or not for the current kernel source.  The figure is the L2-to-memory read
@@ -67,7 +68,7 @@ def measured_traffic(n_sub: int, level: int):
     if (n_sub, level) != (2, 7):
         return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except OSError:
         return None
@@ -203,7 +204,7 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(n_sub, level, TRAFFIC_FILE_GENERAL),
             "launches": launches,
             "mean_launch_ms": round(mean_ms, 5),
             "algorithmic_bytes_per_launch": alg_bytes,
