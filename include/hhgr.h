@@ -122,9 +122,11 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * call, and after hhgr_set_coeff with variable_coeff = 1; ESTATE otherwise).
  * EINVAL for an inverted or degenerate macro tetrahedron; may be called again
  * to move the vertices (a right-hand side from Dirichlet data is not
- * recomputed).  Not available with such contexts: mixed precision,
- * HHGR_RHS_NODAL_F, Dirichlet-Neumann recovery, hhgr_mass_apply,
- * hhgr_adjoint_grad and hhgr_autotune (ESTATE). */
+ * recomputed).  The recoveries work as on the cube; the intact side of a
+ * Dirichlet-Neumann recovery takes the 15-point entries assembled over the
+ * elements of intact macro tetrahedra.  Not available with such contexts:
+ * mixed precision, HHGR_RHS_NODAL_F, hhgr_mass_apply, hhgr_adjoint_grad and
+ * hhgr_autotune (ESTATE). */
 int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Right-hand side of eq. (2) from a device vector in the vector order above.

@@ -112,6 +112,7 @@ struct LevelDev {
     // ... with a per-element coefficient: 7 forward edge weights and the
     // diagonal per closure slot ([e n_slots + slot]), 15 entries per master
     double *wv = nullptr, *wi15 = nullptr;
+    double *wi15_dn = nullptr;  // intact-side master entries of a Dirichlet-Neumann recovery
 };
 
 template <typename T>
@@ -123,6 +124,7 @@ struct LevView {
     bool ifc = false;
     const unsigned char *frozen = nullptr;
     const int *gptr = nullptr, *gidx = nullptr;  // ghost copies to update (nullptr: all of the level's)
+    const double *wi15 = nullptr;                // general macro mesh: master entries (nullptr: the level's)
 };
 
 template <typename T>
@@ -168,7 +170,8 @@ struct hhgr_ctx {
     bool gen = false, geom_set = false;
     int *ccol15 = nullptr;
     double *cval15 = nullptr;
-    double *kel = nullptr;  // unit-size element matrices per macro tet and axis order (variable k)
+    double *kel = nullptr;  // unit-size element matrices per macro tet and axis order
+    double *cval15_dn = nullptr;  // intact-side coarsest-level rows of a Dirichlet-Neumann recovery
     std::vector<double> cval_host;
     // adjoint temporaries
     double *aux_u = nullptr, *aux_b = nullptr, *user_u = nullptr, *user_l = nullptr;
@@ -260,6 +263,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.wtab_cap = 1 + 14 * c.n_tets;
             D.wtab = cv.take<double>(15 * (size_t)D.wtab_cap);
             D.sid = cv.take<int>(T.n_ifc);
+            D.wi15_dn = cv.take<double>(15 * (size_t)T.n_ifc);
         }
         D.ifc_dof = cv.take<int>(T.n_ifc);
         D.ifc_xyz = cv.take<int>(3 * (size_t)T.n_ifc);
@@ -336,7 +340,8 @@ void carve(hhgr_ctx &c, Carver &cv) {
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
-        if (c.vk) c.kel = cv.take<double>(96 * (size_t)c.n_tets);
+        c.cval15_dn = cv.take<double>(15 * (size_t)c.cn);
+        c.kel = cv.take<double>(96 * (size_t)c.n_tets);
     }
     const TopoLevel &TL = tp.lev[c.L];
     c.aux_u = cv.take<double>(TL.n_slots);
@@ -454,6 +459,13 @@ Gen15 gen15(const LevelDev &D, int q, bool ifc) {
     g.wv = D.wv;
     g.ws = D.n_slots;
     g.wi15 = D.wi15;
+    return g;
+}
+
+// ... of a view's level (a view may bring its own master entries)
+Gen15 gen15v(const LevelDev &D, const LevView<double> &v, int q) {
+    Gen15 g = gen15(D, q, v.ifc);
+    if (v.wi15) g.wi15 = v.wi15;
     return g;
 }
 
@@ -583,7 +595,7 @@ void sweep15(hhgr_ctx &c, const HView<double> &V, int l, bool zero, hipStream_t 
         const IfcGeom ig = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
-        launch_colour15(s, vg, ig, gen15(D, q, v.ifc), v.u, v.b, c.d.omega);
+        launch_colour15(s, vg, ig, gen15v(D, v, q), v.u, v.b, c.d.omega);
         if (timed) timed_end(c, s);
     }
 }
@@ -625,8 +637,8 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
             if (V.local)
                 launch_local_coarse15(s, v.vd, v.nvol, D.lc_sl.x, gen15(D, -1, false), v.b, v.u);
             else
-                launch_coarse_pcg15(s, c.cn, c.cslot, c.ccol15, c.cval15, V.cfrozen, v.b, v.u, c.cptr, c.cidx,
-                                    kCoarseRtol, kCoarseMaxit, c.citers);
+                launch_coarse_pcg15(s, c.cn, c.cslot, c.ccol15, V.cval ? V.cval : c.cval15, V.cfrozen, v.b, v.u,
+                                    c.cptr, c.cidx, kCoarseRtol, kCoarseMaxit, c.citers);
             return;
         }
     }
@@ -658,7 +670,7 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     bool done = false;
     if constexpr (std::is_same<T, double>::value) {
         if (c.gen) {
-            launch_residual15(s, vg, ig, gen15(D, -1, false), v.u, v.b, v.r, nullptr);
+            launch_residual15(s, vg, ig, gen15v(D, v, -1), v.u, v.b, v.r, nullptr);
             done = true;
         }
     }
@@ -681,7 +693,7 @@ void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t 
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
     int nb = -1;
     if constexpr (std::is_same<TO, double>::value) {
-        if (c.gen) nb = launch_residual15(s, vg, ig, gen15(D, -1, false), v.u, v.b, rout, V.partial);
+        if (c.gen) nb = launch_residual15(s, vg, ig, gen15v(D, v, -1), v.u, v.b, rout, V.partial);
     }
     if (nb < 0) nb = launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
     if (nb > 0)
@@ -921,14 +933,29 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     rc = upload(c, c.cfrozen, cf.data(), cf.size());
     if (rc) return rc;
     // intact-side operators on every level
-    for (int l = c.Lc; l <= c.L; l++) {
-        LevelDev &D = c.lev[l];
-        launch_ifc_weights_intact(c.stream, D.n_ifc, D.ifc_xyz, D.N, D.m, c.d.n_sub, D.h, c.vk ? D.kc : nullptr,
-                                  c.dn_faulty, D.wi_dn);
+    if (c.gen) {
+        GenK G;
+        G.kel = c.kel;
+        G.faulty = c.dn_faulty;
+        G.n_sub = c.d.n_sub;
+        for (int l = c.Lc; l <= c.L; l++) {
+            LevelDev &D = c.lev[l];
+            G.k = c.vk ? D.kc : nullptr;
+            G.N = D.N;
+            G.m = D.m;
+            launch_gen_ifc_weights(c.stream, D.n_ifc, D.ifc_xyz, G, D.wi15_dn);
+            if (l == c.Lc) launch_gen_coarse_vals(c.stream, c.cn, c.cpos, c.ccol15, G, c.cval15_dn);
+        }
+    } else {
+        for (int l = c.Lc; l <= c.L; l++) {
+            LevelDev &D = c.lev[l];
+            launch_ifc_weights_intact(c.stream, D.n_ifc, D.ifc_xyz, D.N, D.m, c.d.n_sub, D.h, c.vk ? D.kc : nullptr,
+                                      c.dn_faulty, D.wi_dn);
+        }
+        const LevelDev &Dc = c.lev[c.Lc];
+        launch_coarse_vals_intact(c.stream, c.cn, c.cpos, c.ccol, Dc.N, Dc.m, c.d.n_sub, Dc.h, c.vk ? Dc.kc : nullptr,
+                                  c.dn_faulty, c.cval_dn);
     }
-    const LevelDev &Dc = c.lev[c.Lc];
-    launch_coarse_vals_intact(c.stream, c.cn, c.cpos, c.ccol, Dc.N, Dc.m, c.d.n_sub, Dc.h, c.vk ? Dc.kc : nullptr,
-                              c.dn_faulty, c.cval_dn);
     CHKLAUNCH();
     HIPCHK(hipStreamSynchronize(c.stream));
     set_loc(c, ft);
@@ -936,7 +963,10 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     // static Neumann data from the data at the time of the fault (u_F plays
     // no part: its edges have zero intact-side weight)
     HIPCHK(hipMemcpyAsync(c.aux_b, F.b, F.n_slots * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-    launch_neumann_rhs(c.stream, F.n_ifc, F.ifc_base, F.nbr, F.wi_dn, F.gamma, F.u, c.aux_b);
+    if (c.gen)
+        launch_neumann_rhs15(c.stream, F.n_ifc, F.ifc_base, F.nb15, F.wi15_dn, F.gamma, F.u, c.aux_b);
+    else
+        launch_neumann_rhs(c.stream, F.n_ifc, F.ifc_base, F.nbr, F.wi_dn, F.gamma, F.u, c.aux_b);
     for (int t : ft) restore_tet(c, t, c.stream);
     for (int l = c.Lc; l <= c.L; l++) {
         LevelDev &D = c.lev[l];
@@ -957,11 +987,12 @@ HView<double> dn_view(hhgr_ctx &c) {
         LevelDev &D = c.lev[l];
         LevView<double> &v = V.lv[l];
         v.w.wi = D.wi_dn;
+        v.wi15 = D.wi15_dn;
         v.gptr = D.gptr;
         v.gidx = D.gidx_dn;
     }
     V.lv[c.L].b = c.aux_b;
-    V.cval = c.cval_dn;
+    V.cval = c.gen ? c.cval15_dn : c.cval_dn;
     return V;
 }
 
@@ -1313,11 +1344,11 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
     // host staging vectors must outlive the copies (synchronised below)
     std::vector<LevelStencils> G(c->L + 1);
     std::vector<double> cval, kel;
-    if (c->vk) {
-        // per-node stencils from k and the element matrices (on the GPU)
-        element_matrices(tp, host_xyz, kel);
-        rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
-    } else {
+    // element matrices: per-node stencils of a variable k and the intact side
+    // of a Dirichlet-Neumann recovery are computed from them on the GPU
+    element_matrices(tp, host_xyz, kel);
+    rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
+    if (!c->vk) {
         for (int l = c->Lc; l <= c->L; l++) {
             e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
             if (!e.empty()) return fail(HHGR_EINVAL, e);
@@ -1485,7 +1516,6 @@ int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int eta) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (c->gen) return fail(HHGR_ESTATE, "Dirichlet-Neumann recovery needs general_geometry = 0");
     std::vector<int> ft;
     rc = dd_check(*c, tets, n_tets, n_intact, eta, ft);
     if (rc) return rc;

@@ -438,7 +438,8 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
 // general macro meshes: 15-point stencils (see Gen15)
 // ---------------------------------------------------------------------------
 // A u at interface master t (diag: its diagonal entry); VK: the master's own
-// 15 entries, else its primitive's stencil
+// 15 entries (per-element k, or the intact side of a Dirichlet-Neumann
+// recovery), else its primitive's stencil
 template <bool VK>
 __device__ __forceinline__ double master_Au(const IfcGeom &ig, const Gen15 &g, const double *__restrict__ u, int t,
                                             double uo, double &diag) {
@@ -488,7 +489,8 @@ __device__ __forceinline__ double volume_Au(const VolGeom &vg, const Gen15 &g, c
     return diag * uo + acc;
 }
 
-template <bool VK>
+// VKV: per-node volume weights (wv), VKI: per-master entries (wi15)
+template <bool VKV, bool VKI>
 __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, double *__restrict__ u,
                                                   const double *__restrict__ b, double omega) {
     const unsigned f = blockIdx.x;
@@ -500,7 +502,7 @@ __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 
         const long long sl = ig.base + t;
         const double uo = u[sl];
         double diag;
-        const double Au = master_Au<VK>(ig, g, u, t, uo, diag);
+        const double Au = master_Au<VKI>(ig, g, u, t, uo, diag);
         const double un = uo + omega * (b[sl] - Au) / diag;
         u[sl] = un;
         if (ig.gptr)
@@ -515,11 +517,11 @@ __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 
     double *uv = u + d.vec;
     int c0;
     double uo, diag;
-    const double Au = volume_Au<VK>(vg, g, d, nd, uv, c0, uo, diag);
+    const double Au = volume_Au<VKV>(vg, g, d, nd, uv, c0, uo, diag);
     uv[c0] = uo + omega * ((b + d.vec)[c0] - Au) / diag;
 }
 
-template <bool WRITE, bool NORM, bool VK>
+template <bool WRITE, bool NORM, bool VKV, bool VKI>
 __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen15 g, int nib,
                                                     const double *__restrict__ u, const double *__restrict__ b,
                                                     double *__restrict__ r, double *__restrict__ partial) {
@@ -531,7 +533,7 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
         if (t < ig.i1 && !(ig.frozen && ig.frozen[t])) {
             const long long sl = ig.base + t;
             double diag;
-            const double res = b[sl] - master_Au<VK>(ig, g, u, t, u[sl], diag);
+            const double res = b[sl] - master_Au<VKI>(ig, g, u, t, u[sl], diag);
             if (WRITE) r[sl] = res;
             acc2 = res * res;
         }
@@ -543,7 +545,7 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
             const VolDesc d = vg.vd[nd.v];
             int c0;
             double uo, diag;
-            const double Au = volume_Au<VK>(vg, g, d, nd, u + d.vec, c0, uo, diag);
+            const double Au = volume_Au<VKV>(vg, g, d, nd, u + d.vec, c0, uo, diag);
             const double res = (b + d.vec)[c0] - Au;
             if (WRITE) r[d.vec + c0] = res;
             acc2 = res * res;
@@ -1193,7 +1195,8 @@ __device__ double gen_entry(const GenK &G, const int X[3], int dx, int dy, int d
             if (rr < 0) continue;
             const long long e = 6 * (c[0] + (long long)G.N * (c[1] + (long long)G.N * c[2])) + q;
             const int t = macro_tet_of(c[0], c[1], c[2], q, G.m, G.n_sub);
-            s += G.k[e] * G.kel[(6LL * t + q) * 16 + 4 * r + rr];
+            if (G.faulty && G.faulty[t]) continue;
+            s += (G.k ? G.k[e] : 1.0) * G.kel[(6LL * t + q) * 16 + 4 * r + rr];
         }
     return s / G.m;
 }
@@ -1274,12 +1277,12 @@ __global__ void __launch_bounds__(256) k_gen_dirichlet(VolGeom vg, IfcGeom ig, G
         const int t = (int)(f * blockDim.x + threadIdx.x);
         if (t >= ig.i1) return;
         const int X[3] = {ifc_xyz[3 * t], ifc_xyz[3 * t + 1], ifc_xyz[3 * t + 2]};
-        const double *w = VK ? nullptr : g.wtab + 15LL * g.sid[t];
+        const double *w = g.wi15 ? nullptr : g.wtab + 15LL * g.sid[t];
         double s = 0.0;
         for (int n = 1; n < 15; n++) {
             const int Y[3] = {X[0] + kGrid15D[n][0], X[1] + kGrid15D[n][1], X[2] + kGrid15D[n][2]};
             if (!on_bnd(Y)) continue;
-            const double a = VK ? g.wi15[(long long)n * ig.stride + t] : w[n];
+            const double a = g.wi15 ? g.wi15[(long long)n * ig.stride + t] : w[n];
             s -= a * gfull[Y[0] + M1 * (Y[1] + M1 * Y[2])];
         }
         b[ig.base + t] = s;
@@ -1326,6 +1329,20 @@ __global__ void k_neumann_rhs(int n_ifc, long long base, const int *__restrict__
 #pragma unroll
     for (int e = 0; e < 6; e++) s += wi[(long long)e * n_ifc + t] * (uo - u[nbr[(long long)e * n_ifc + t]]);
     b_out[sl] = s;
+}
+
+// the same on a general macro mesh: b_out = (A^I u) at the nodes of gamma
+// with the intact side's 15 entries per master (kGrid15 order, entry 0 the
+// diagonal at the master's own slot)
+__global__ void k_neumann_rhs15(int n_ifc, long long base, const int *__restrict__ nb15,
+                                const double *__restrict__ wi15, const unsigned char *__restrict__ gamma,
+                                const double *__restrict__ u, double *__restrict__ b_out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ifc || !gamma[t]) return;
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 15; e++) s += wi15[(long long)e * n_ifc + t] * u[nb15[(long long)e * n_ifc + t]];
+    b_out[base + t] = s;
 }
 
 // Interface masks of a Dirichlet-Neumann recovery: a node whose ghost copies
@@ -1612,20 +1629,25 @@ void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const 
     const long long grid = nib + list_blocks(vg, 1);
     if (grid == 0) return;
     if (g.wv)
-        hipLaunchKernelGGL(k_colour15<true>, dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b, omega);
+        hipLaunchKernelGGL((k_colour15<true, true>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b,
+                           omega);
+    else if (g.wi15)
+        hipLaunchKernelGGL((k_colour15<false, true>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b,
+                           omega);
     else
-        hipLaunchKernelGGL(k_colour15<false>, dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b, omega);
+        hipLaunchKernelGGL((k_colour15<false, false>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b,
+                           omega);
 }
 
-template <bool VK>
+template <bool VKV, bool VKI>
 static void residual15(hipStream_t s, dim3 gd, dim3 bd, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, int nib,
                        const double *u, const double *b, double *r, double *partial) {
     if (r && partial)
-        hipLaunchKernelGGL((k_residual15<true, true, VK>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        hipLaunchKernelGGL((k_residual15<true, true, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
     else if (r)
-        hipLaunchKernelGGL((k_residual15<true, false, VK>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        hipLaunchKernelGGL((k_residual15<true, false, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
     else
-        hipLaunchKernelGGL((k_residual15<false, true, VK>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        hipLaunchKernelGGL((k_residual15<false, true, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
 }
 
 int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const double *u,
@@ -1635,9 +1657,11 @@ int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const
     if (grid == 0) return 0;
     const dim3 gd((unsigned)grid), bd(vg.bs);
     if (g.wv)
-        residual15<true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
+        residual15<true, true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
+    else if (g.wi15)
+        residual15<false, true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     else
-        residual15<false>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
+        residual15<false, false>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     return (int)grid;
 }
 
@@ -1687,6 +1711,13 @@ void launch_gen_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, const 
 void launch_gen_coarse_vals(hipStream_t s, int n, const int *pos, const int *col15, const GenK &G, double *val) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gen_coarse_vals, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, col15, G, val);
+}
+
+void launch_neumann_rhs15(hipStream_t s, int n_ifc, long long base, const int *nb15, const double *wi15,
+                          const unsigned char *gamma, const double *u, double *b_out) {
+    if (n_ifc <= 0) return;
+    hipLaunchKernelGGL(k_neumann_rhs15, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, base, nb15, wi15, gamma, u,
+                       b_out);
 }
 
 void launch_gen_dirichlet(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const Gen15 &g, const int *tetinfo,

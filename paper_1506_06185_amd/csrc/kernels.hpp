@@ -51,8 +51,9 @@ struct IfcGeom {
 // With a per-element coefficient (wv != nullptr) the stencils vary per node:
 // a closure slot holds the weights of its 7 forward index offsets kIdx15[1],
 // [3], ..., [13] at wv[e ws + slot] (e = 0..6, zero where the edge leaves the
-// closure) and its diagonal at wv[7 ws + slot]; a master holds its 15 entries
-// at wi15[n stride + f] (kGrid15 order).
+// closure) and its diagonal at wv[7 ws + slot].  With wi15 != nullptr (per-
+// element k, or the intact side of a Dirichlet-Neumann recovery) a master
+// holds its own 15 entries at wi15[n stride + f] (kGrid15 order).
 struct Gen15 {
     const int *rowN15 = nullptr;
     const double *w15 = nullptr;
@@ -71,8 +72,9 @@ struct Gen15 {
 // of macro tetrahedron t and axis order q, the level's cells per axis N and
 // segments per macro edge m.
 struct GenK {
-    const double *k = nullptr;
+    const double *k = nullptr;             // nullptr: k = 1
     const double *kel = nullptr;
+    const unsigned char *faulty = nullptr;  // macro tetrahedra whose elements are left out, or nullptr
     int N = 0, m = 0, n_sub = 0;
 };
 
@@ -180,6 +182,9 @@ void launch_gen_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo,
                         long long ws);
 void launch_gen_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, const GenK &G, double *wi15);
 void launch_gen_coarse_vals(hipStream_t s, int n, const int *pos, const int *col15, const GenK &G, double *val);
+// Dirichlet-Neumann Neumann data on a general macro mesh (see launch_neumann_rhs)
+void launch_neumann_rhs15(hipStream_t s, int n_ifc, long long base, const int *nb15, const double *wi15,
+                          const unsigned char *gamma, const double *u, double *b_out);
 // eliminated Dirichlet data on a general macro mesh into b (slot order):
 // interior nodes of vint and masters [0, ig.i1) of ig
 void launch_gen_dirichlet(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const Gen15 &g, const int *tetinfo,

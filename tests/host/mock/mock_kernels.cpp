@@ -92,6 +92,8 @@ void launch_local_coarse15(hipStream_t, const VolDesc *, int, int, const Gen15 &
 void launch_gen_weights(hipStream_t, const VolGeom &, const int *, const GenK &, double *, long long) {}
 void launch_gen_ifc_weights(hipStream_t, int, const int *, const GenK &, double *) {}
 void launch_gen_coarse_vals(hipStream_t, int, const int *, const int *, const GenK &, double *) {}
+void launch_neumann_rhs15(hipStream_t, int, long long, const int *, const double *, const unsigned char *,
+                          const double *, double *) {}
 void launch_gen_dirichlet(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, const int *, const int *, int,
                           const double *, double *) {}
 void launch_dn_masks(hipStream_t, int, long long, long long, const int *, const int *, const unsigned char *,

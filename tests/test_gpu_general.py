@@ -191,8 +191,8 @@ def test_vcycle_iterates_and_solve(dev, hh, n_sub, level, seed):
     ctx.close()
 
 
-@pytest.mark.parametrize("strategy", ["local", "dd"])
-def test_recovery_parity(dev, hh, strategy):
+@pytest.mark.parametrize("strategy,vk", [("local", False), ("dd", False), ("dn", False), ("dn", True)])
+def test_recovery_parity(dev, hh, strategy, vk):
     if strategy == "local":
         n_sub, level, seed = 2, 4, 5
         tets = [inputs.fault_tet(n_sub, seed=3)]
@@ -200,9 +200,10 @@ def test_recovery_parity(dev, hh, strategy):
         n_sub, level, seed = 3, 4, 6
         tets = [inputs.scenario_fault_tet("III")]
         tets.append(inputs.second_fault_tet(n_sub, tets[0]))
-    print(f"\n[general recovery] {strategy} tets={tets}", flush=True)
-    ctx = context(hh, dev, n_sub, level, seed)
-    p = problem(n_sub, level, seed)
+    print(f"\n[general recovery] {strategy} variable_k={vk} tets={tets}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=4) if vk else None
+    ctx = context(hh, dev, n_sub, level, seed, k=k)
+    p = problem_k(n_sub, level, seed, 4) if vk else problem(n_sub, level, seed)
     b = np.random.default_rng(300).uniform(0.0, 1.0, p.ndof) / p.ndof
     ctx.set_rhs(T(b, dev))
     ctx.vcycle(3)
@@ -214,16 +215,18 @@ def test_recovery_parity(dev, hh, strategy):
     if strategy == "local":
         ctx.recover_local(tets[0], 3)
         uo, _ = p.recover_local(tets, uo, b, 3)
-    else:
+    elif strategy == "dd":
         ctx.recover_dd(tets, 2, 4)
         uo = p.dd_intact(tets, uo, b, 2)
         uo, _ = p.recover_local(tets, uo, b, 4)
+    else:
+        # intact side on the sub-stencils of the intact macro tetrahedra, eq. (5)
+        ctx.recover_dn(tets, 3, 2)
+        uo = p.dn_recover(tets, uo, b, 3, 2)
     assert rel(Nn(ctx.get_solution()), uo) < 1e-12
     ctx.vcycle(2)
     uo, _, _ = p.solve(b, u0=uo, rtol=0.0, max_cycles=2)
     assert rel(Nn(ctx.get_solution()), uo) < 1e-12
-    with pytest.raises(hh.HHGRError):
-        ctx.recover_dn(tets, 1, 1)
     ctx.close()
 
 
