@@ -127,11 +127,16 @@ def kappa(k_faulty: int, k_free: int, k_F: int) -> float:
     return (k_faulty - k_free) / k_F
 
 
-def make_context(n_sub: int, level: int, device=None, tune: bool = True, tune_cache: str | None = None):
-    """FP64 context with the Dirichlet data of ``inputs.harmonic_boundary``."""
+def make_context(n_sub: int, level: int, device=None, tune: bool = True, tune_cache: str | None = None,
+                 vertices=None):
+    """FP64 context with the Dirichlet data of ``inputs.harmonic_boundary``;
+    with ``vertices`` (macro vertex positions) a general macro mesh, whose
+    boundary nodes take the same data at their grid indices."""
     dev = torch.device("cuda:0") if device is None else torch.device(device)
-    ctx = hhgr.Context(device=dev, n_sub=n_sub, level=level)
-    if tune:
+    ctx = hhgr.Context(device=dev, n_sub=n_sub, level=level, general_geometry=vertices is not None)
+    if vertices is not None:
+        ctx.set_geometry(vertices)
+    elif tune:
         ctx.autotune(tune_cache)
     g = torch.from_numpy(inputs.harmonic_boundary(n_sub, level)).to(dev)
     ctx.set_rhs(g, hhgr.HHGR_RHS_DIRICHLET)
@@ -210,11 +215,18 @@ def main(argv=None):
     ap.add_argument("--sequence-level", type=int, default=8,
                     help="level of the two-fault sequence on the 162-tet mesh (0 = skip)")
     ap.add_argument("--out", default=None, help="JSON file for the results")
+    ap.add_argument("--general-seed", type=int, default=None,
+                    help="run the scenarios on general macro meshes: macro vertices moved by "
+                         "inputs.perturbed_vertices with this seed")
     a = ap.parse_args(argv)
-    res = dict(level=a.level, tol=a.tol, scenarios={})
+    res = dict(level=a.level, tol=a.tol, general_seed=a.general_seed, scenarios={})
+
+    def verts(n):
+        return None if a.general_seed is None else inputs.perturbed_vertices(n, a.general_seed)
+
     for sc in filter(None, a.scenarios.split(",")):
         n, tet = inputs.SCENARIOS[sc]["n_sub"], inputs.scenario_fault_tet(sc)
-        ctx = make_context(n, a.level)
+        ctx = make_context(n, a.level, vertices=verts(n))
         run = Runner(ctx, a.tol)
         entry = dict(n_sub=n, tet=tet, n_dofs=ctx.n_dofs, tables=[])
         # the fault-free residual history down to the rounding floor
@@ -232,7 +244,7 @@ def main(argv=None):
         n = 3
         t1 = inputs.scenario_fault_tet("III")
         t2 = inputs.second_fault_tet(n, t1)
-        ctx = make_context(n, a.sequence_level)
+        ctx = make_context(n, a.sequence_level, vertices=verts(n))
         run = Runner(ctx, a.tol)
         def log(msg):
             print(msg, flush=True)

@@ -134,16 +134,17 @@ class OracleJobs:
 SCENARIO_LEVELS = {"I": 5, "II": 4, "III": 4}
 
 
-@pytest.mark.parametrize("scenario", list(SCENARIO_LEVELS))
-def test_kappa_tables_match_oracle(dev, hh, scenario):
+@pytest.mark.parametrize("scenario,general", [(s, False) for s in SCENARIO_LEVELS] + [("II", True)])
+def test_kappa_tables_match_oracle(dev, hh, scenario, general):
     from paper_1506_06185_amd import study
 
     n_sub, level = inputs.SCENARIOS[scenario]["n_sub"], SCENARIO_LEVELS[scenario]
     tet = inputs.scenario_fault_tet(scenario)
-    print(f"\n[kappa tables] scenario {scenario}: n_sub={n_sub} level={level} tet={tet}", flush=True)
-    ctx = study.make_context(n_sub, level, device=dev, tune=False)
+    V = inputs.perturbed_vertices(n_sub, 0) if general else None
+    print(f"\n[kappa tables] scenario {scenario}: n_sub={n_sub} level={level} tet={tet} general={general}", flush=True)
+    ctx = study.make_context(n_sub, level, device=dev, tune=False, vertices=V)
     run = study.Runner(ctx, TOL)
-    p = oracle.Problem(n_sub, level)
+    p = oracle.Problem(n_sub, level, vertices=V)
     oj = OracleJobs(p, p.dirichlet_load(inputs.harmonic_boundary(n_sub, level)))
     k_free = oj.free()
     for k_F, n_max in ((5, 4), (11, 6)):
