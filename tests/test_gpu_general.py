@@ -325,3 +325,80 @@ def test_full_size_variable_k_symmetry_and_constants(dev, hh):
     assert np.abs(A1[far]).max() < 1e-12 * np.abs(Ax).max()
     assert np.abs(A1[~far]).min() > 0
     ctx.close()
+
+
+def test_graphs_and_batches_on_general_meshes(dev, hh):
+    """Captured cycles replay the eager ones bitwise, and a batch of a general
+    member (with an armed Dirichlet-Dirichlet recovery), a variable-k general
+    member and a cube member equals the oracle run member by member."""
+    print("\n[general graphs + batch]", flush=True)
+    n_sub, level, seed = 2, 4, 5
+    b = np.random.default_rng(700).uniform(-1.0, 1.0, (n_sub * 2 ** level - 1) ** 3)
+    res = []
+    for graph in (False, True):
+        ctx = context(hh, dev, n_sub, level, seed)
+        ctx.set_graph(graph)
+        ctx.set_rhs(T(b, dev))
+        for _ in range(4):  # several replays with host reads in between
+            ctx.vcycle(1)
+        res.append(Nn(ctx.get_solution()))
+        ctx.close()
+    assert rel(res[1], res[0]) < 1e-14
+
+    k = inputs.lognormal_k(2, 4, seed=6)
+    members = [
+        dict(ctx=context(hh, dev, 3, 4, 6), p=problem(3, 4, 6), pre=3,
+             dd=([inputs.scenario_fault_tet("III"), inputs.second_fault_tet(3, inputs.scenario_fault_tet("III"))], 2, 3)),
+        dict(ctx=context(hh, dev, 2, 4, 6, k=k), p=problem_k(2, 4, 6, 6), pre=0, dd=None),
+        dict(ctx=hh.Context(device=dev, n_sub=1, level=5), p=oracle.Problem(1, 5), pre=0, dd=None),
+    ]
+    for q, m in enumerate(members):
+        m["b"] = np.random.default_rng(710 + q).uniform(0.0, 1.0, m["p"].ndof) / m["p"].ndof
+        m["ctx"].set_rhs(T(m["b"], dev))
+        if m["pre"]:
+            m["ctx"].vcycle(m["pre"])
+        if m["dd"]:
+            for t in m["dd"][0]:
+                m["ctx"].inject_fault(t)
+    batch = hh.Batch([m["ctx"] for m in members])
+    for q, m in enumerate(members):
+        if m["dd"]:
+            batch.arm_dd(q, *m["dd"])
+    out = batch.run(1e-10, 80)
+    for q, m in enumerate(members):
+        p, bb = m["p"], m["b"]
+        bn = float(np.linalg.norm(bb))
+        u = p.solve(bb, rtol=0.0, max_cycles=m["pre"])[0] if m["pre"] else np.zeros_like(bb)
+        done = 0
+        if m["dd"]:
+            tets, n_i, n_f = m["dd"]
+            for t in tets:
+                u = p.inject_fault(t, u)
+            u = p.dd_intact(tets, u, bb, n_i)
+            u, _ = p.recover_local(tets, u, bb, n_f)
+            done = n_i
+        u, co, _ = p.solve(bb, u0=u, rtol=1e-10, max_cycles=80 - done, r0=bn)
+        cyc = out[q][0]
+        print(f"  member {q}: cycles {cyc} (oracle {done} + {co})", flush=True)
+        assert cyc == done + co
+        assert rel(Nn(m["ctx"].get_solution()), u) < 1e-12
+    batch.close()
+    for m in members:
+        m["ctx"].close()
+
+
+def test_coarse_level_3(dev, hh):
+    """A coarser hierarchy ending at level 3 (the 15-point PCG on 343 unknowns)."""
+    n_sub, level, seed = 1, 5, 3
+    print("\n[general coarse level 3]", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, coarse_level=3, general_geometry=True)
+    ctx.set_geometry(inputs.perturbed_vertices(n_sub, seed))
+    p = oracle.Problem(n_sub, level, coarse_level=3, vertices=inputs.perturbed_vertices(n_sub, seed))
+    b = np.random.default_rng(720).uniform(0.0, 1.0, p.ndof) / p.ndof
+    ctx.set_rhs(T(b, dev))
+    ctx.vcycle(3)
+    uo, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-11
+    with pytest.raises(hh.HHGRError):
+        ctx.recover_local(0, 1)  # local recovery needs coarse level 2
+    ctx.close()
