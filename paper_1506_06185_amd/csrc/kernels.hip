@@ -1668,22 +1668,19 @@ int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const
 void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
                          const unsigned char *frozen, const double *b, double *u, const int *cptr, const int *cidx,
                          double rtol, int maxit, int *iters) {
+    // 14 off-diagonal entries per row stay in registers: at most 2 rows per
+    // lane (more spill to scratch), so above 128 unknowns one row per thread
     if (n <= 64)
         hipLaunchKernelGGL((k_coarse_pcg_wave<double, 1, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
                            cptr, cidx, rtol, maxit, iters);
     else if (n <= 128)
         hipLaunchKernelGGL((k_coarse_pcg_wave<double, 2, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
                            cptr, cidx, rtol, maxit, iters);
-    else if (n <= 256)
-        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 4, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
-                           cptr, cidx, rtol, maxit, iters);
-    else if (n <= 512)
-        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 8, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
-                           cptr, cidx, rtol, maxit, iters);
-    else if (n <= 1024)
-        hipLaunchKernelGGL((k_coarse_pcg<double, 1, 14>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr,
+    else if (n <= 1024) {
+        const int bs = n <= 256 ? 256 : n <= 512 ? 512 : 1024;
+        hipLaunchKernelGGL((k_coarse_pcg<double, 1, 14>), dim3(1), dim3(bs), 0, s, n, slot, col, val, frozen, b, u, cptr,
                            cidx, rtol, maxit, iters);
-    else
+    } else
         hipLaunchKernelGGL((k_coarse_pcg<double, 2, 14>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr,
                            cidx, rtol, maxit, iters);
 }
