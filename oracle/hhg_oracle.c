@@ -1436,12 +1436,13 @@ static void hier_ops(oproblem *p, csr *ops, unsigned char **keep, mghier *H, i64
     }
 }
 
-/* Alg. 2.  Intact side: V-cycles for the Neumann problem (lines 1+2 of
- * eq. (5)) on the nodes the intact operator couples (intact interiors and the
- * interface Gamma), right-hand side b off Gamma and, on Gamma, the intact-side
- * action A^I u of the data at the time of the fault (lambda of Alg. 2 taken
- * with static data).  Faulty side: u_F starts at zero; the local Dirichlet
- * problems (line 6) get their boundary values from Gamma (line 5).
+/* Alg. 2.  Intact side: V-cycles for the Neumann problem (the first two
+ * block rows of eq. (5)) on the nodes the intact operator couples (intact
+ * interiors and the interface Gamma), right-hand side b off Gamma and, on
+ * Gamma, the intact-side action A^I u of the data at the time of the fault
+ * (lambda of Alg. 2 taken with static data).  Faulty side: u_F starts at
+ * zero; its local Dirichlet problems take their boundary values from the
+ * interface values on Gamma.
  * n_intact rounds: in round i the faulty side runs eta local cycles with the
  * interface values of the start of the round, continuing from its current
  * u_F, and the intact side runs one V-cycle; the two sides share no unknown
