@@ -1665,17 +1665,21 @@ int ohhg_solve_mixed(void *vp, double *u, const double *b, double omega, int nu1
 /* Adjoint gradient with respect to the element coefficients                  */
 /* ------------------------------------------------------------------------- */
 /* J(u) with A(k) u = b and A(k) = sum_T k_T A_T: dJ/dk_T = -lambda^T A_T u,
- * where A lambda = dJ/du.  A_T is the unit-coefficient element stiffness;
- * Dirichlet nodes carry u = lambda = 0.  out is in cell-lex element order. */
+ * where A lambda = dJ/du.  A_T is the unit-coefficient element stiffness (in
+ * physical coordinates when the geometry is given, the same matrices the
+ * assembly uses); Dirichlet nodes carry u = lambda = 0.  out is in cell-lex
+ * element order. */
 void ohhg_grad_k(void *vp, const double *u, const double *lam, double *out) {
-    if (((oproblem *)vp)->geom) die("the gradient formula assumes the Kuhn geometry");
     oproblem *p = vp;
     olevel *Lv = &p->lev[p->L];
     const int N = Lv->N;
 #pragma omp parallel for schedule(static)
     for (i64 e = 0; e < Lv->ne; e++) {
         double K[4][4], Mm[4][4], ul[4], ll[4];
-        elem_mats(N, &Lv->ev[4 * e], K, Mm);
+        if (Lv->xyz)
+            elem_mats_xyz(Lv->xyz, &Lv->ev[4 * e], K, Mm);
+        else
+            elem_mats(N, &Lv->ev[4 * e], K, Mm);
         for (int a = 0; a < 4; a++) {
             i64 d = dof_vid(N, Lv->ev[4 * e + a]);
             ul[a] = d >= 0 ? u[d] : 0.0;
@@ -1684,6 +1688,7 @@ void ohhg_grad_k(void *vp, const double *u, const double *lam, double *out) {
         double g = 0.0;
         for (int a = 0; a < 4; a++)
             for (int b = 0; b < 4; b++) g += ll[a] * K[a][b] * ul[b];
-        out[Lv->ecl[e]] = -Lv->h * g;
+        /* the reference matrices of elem_mats are scaled by h in the assembly */
+        out[Lv->ecl[e]] = -(Lv->xyz ? 1.0 : Lv->h) * g;
     }
 }
