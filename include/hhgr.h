@@ -124,9 +124,10 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * to move the vertices (a right-hand side from Dirichlet data is not
  * recomputed).  The recoveries work as on the cube; the intact side of a
  * Dirichlet-Neumann recovery takes the 15-point entries assembled over the
- * elements of intact macro tetrahedra.  Not available with such contexts:
- * mixed precision, HHGR_RHS_NODAL_F, hhgr_mass_apply, hhgr_adjoint_grad and
- * hhgr_autotune (ESTATE). */
+ * elements of intact macro tetrahedra.  HHGR_RHS_NODAL_F, hhgr_mass_apply and
+ * hhgr_adjoint_grad use the consistent P1 mass matrix and the element
+ * matrices of the moved elements (after this call).  Not available with such
+ * contexts: mixed precision and hhgr_autotune (ESTATE). */
 int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Right-hand side of eq. (2) from a device vector in the vector order above.

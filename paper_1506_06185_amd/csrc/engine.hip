@@ -113,6 +113,7 @@ struct LevelDev {
     // diagonal per closure slot ([e n_slots + slot]), 15 entries per master
     double *wv = nullptr, *wi15 = nullptr;
     double *wi15_dn = nullptr;  // intact-side master entries of a Dirichlet-Neumann recovery
+    double *mw15 = nullptr, *mwtab = nullptr;  // finest level: mass stencils (indexed like w15, wtab)
 };
 
 template <typename T>
@@ -264,6 +265,10 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.wtab = cv.take<double>(15 * (size_t)D.wtab_cap);
             D.sid = cv.take<int>(T.n_ifc);
             D.wi15_dn = cv.take<double>(15 * (size_t)T.n_ifc);
+            if (l == c.L) {
+                D.mw15 = cv.take<double>(15 * (size_t)c.n_tets);
+                D.mwtab = cv.take<double>(15 * (size_t)D.wtab_cap);
+            }
         }
         D.ifc_dof = cv.take<int>(T.n_ifc);
         D.ifc_xyz = cv.take<int>(3 * (size_t)T.n_ifc);
@@ -459,6 +464,17 @@ Gen15 gen15(const LevelDev &D, int q, bool ifc) {
     g.wv = D.wv;
     g.ws = D.n_slots;
     g.wi15 = D.wi15;
+    return g;
+}
+
+// the finest level's mass matrix of a general macro mesh
+Gen15 gen15mass(const LevelDev &D) {
+    Gen15 g;
+    g.rowN15 = D.rowN15;
+    g.w15 = D.mw15;
+    g.sid = D.sid;
+    g.wtab = D.mwtab;
+    g.nb15 = D.nb15;
     return g;
 }
 
@@ -1175,6 +1191,10 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
             launch_fill<double>(c->stream, D.w15, 15LL * c->n_tets, 0.0);
             launch_fill<double>(c->stream, D.wtab, 15LL * D.wtab_cap, 0.0);
             launch_fill<unsigned int>(c->stream, reinterpret_cast<unsigned int *>(D.sid), T.n_ifc, 0u);
+            if (D.mw15) {
+                launch_fill<double>(c->stream, D.mw15, 15LL * c->n_tets, 0.0);
+                launch_fill<double>(c->stream, D.mwtab, 15LL * D.wtab_cap, 0.0);
+            }
         }
         // zero every vector (also the Dirichlet ghosts and the zero slot)
         launch_fill<double>(c->stream, D.u, T.n_slots, 0.0);
@@ -1264,10 +1284,8 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     if (!c || !dev_vec) return fail(HHGR_EINVAL, "null argument");
     if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F && kind != HHGR_RHS_DIRICHLET)
         return fail(HHGR_EINVAL, "bad rhs kind");
-    if (c->gen && kind == HHGR_RHS_NODAL_F)
-        return fail(HHGR_ESTATE, "general_geometry contexts take HHGR_RHS_LOAD or HHGR_RHS_DIRICHLET");
-    if (c->gen && kind == HHGR_RHS_DIRICHLET && !c->geom_set)
-        return fail(HHGR_ESTATE, "Dirichlet data on a general macro mesh needs hhgr_set_geometry first");
+    if (c->gen && kind != HHGR_RHS_LOAD && !c->geom_set)
+        return fail(HHGR_ESTATE, "this right-hand side on a general macro mesh needs hhgr_set_geometry first");
     if (kind == HHGR_RHS_DIRICHLET && c->vk && !c->coeff_set)
         return fail(HHGR_ESTATE, "Dirichlet data with variable_coeff = 1 needs hhgr_set_coeff first");
     LevelDev &D = c->lev[c->L];
@@ -1285,7 +1303,10 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
     } else {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.r);
-        launch_mass(c->stream, vint, ig, D.nb15, D.r, D.b, D.h);
+        if (c->gen)
+            launch_apply15(c->stream, vint, ig, gen15mass(D), D.r, D.b);
+        else
+            launch_mass(c->stream, vint, ig, D.nb15, D.r, D.b, D.h);
     }
     // ||b||: residual of the zero vector
     launch_fill<double>(c->stream, c->aux_u, D.n_slots, 0.0);
@@ -1348,18 +1369,22 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
     // of a Dirichlet-Neumann recovery are computed from them on the GPU
     element_matrices(tp, host_xyz, kel);
     rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
+    // k = 1: the stiffness stencils of every level; the finest level's mass
+    // stencils (and master ids) in either case
+    for (int l = c->vk ? c->L : c->Lc; l <= c->L; l++) {
+        e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
+        if (!e.empty()) return fail(HHGR_EINVAL, e);
+        LevelDev &D = c->lev[l];
+        rc = rc ? rc : upload(*c, D.w15, G[l].w15.data(), G[l].w15.size() * sizeof(double));
+        rc = rc ? rc : upload(*c, D.wtab, G[l].wtab.data(), G[l].wtab.size() * sizeof(double));
+        rc = rc ? rc : upload(*c, D.sid, G[l].sid.data(), G[l].sid.size() * sizeof(int));
+        if (l == c->L) {
+            rc = rc ? rc : upload(*c, D.mw15, G[l].mw15.data(), G[l].mw15.size() * sizeof(double));
+            rc = rc ? rc : upload(*c, D.mwtab, G[l].mwtab.data(), G[l].mwtab.size() * sizeof(double));
+        }
+    }
     if (!c->vk) {
-        for (int l = c->Lc; l <= c->L; l++) {
-            e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
-            if (!e.empty()) return fail(HHGR_EINVAL, e);
-        }
         coarse_stencils(tp, host_xyz, cval);
-        for (int l = c->Lc; l <= c->L; l++) {
-            LevelDev &D = c->lev[l];
-            rc = rc ? rc : upload(*c, D.w15, G[l].w15.data(), G[l].w15.size() * sizeof(double));
-            rc = rc ? rc : upload(*c, D.wtab, G[l].wtab.data(), G[l].wtab.size() * sizeof(double));
-            rc = rc ? rc : upload(*c, D.sid, G[l].sid.data(), G[l].sid.size() * sizeof(int));
-        }
         rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1543,12 +1568,15 @@ int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 
 int hhgr_mass_apply(hhgr_ctx *c, const double *dev_x, double *dev_y) {
     if (!c || !dev_x || !dev_y) return fail(HHGR_EINVAL, "null argument");
-    if (c->gen) return fail(HHGR_ESTATE, "mass matrix needs general_geometry = 0");
+    if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     LevelDev &D = c->lev[c->L];
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
                                  dev_x, c->aux_b);
-    launch_mass(c->stream, vgeom(D, D.vd_all, c->n_tets, false), ig, D.nb15, c->aux_b, c->aux_u, D.h);
+    if (c->gen)
+        launch_apply15(c->stream, vgeom(D, D.vd_all, c->n_tets, false), ig, gen15mass(D), c->aux_b, c->aux_u);
+    else
+        launch_mass(c->stream, vgeom(D, D.vd_all, c->n_tets, false), ig, D.nb15, c->aux_b, c->aux_u, D.h);
     launch_slots_to_user<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
                                  c->aux_u, dev_y);
     CHKLAUNCH();
@@ -1560,7 +1588,6 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
     int rc = check_ready(c);
     if (rc) return rc;
     if (!dev_g) return fail(HHGR_EINVAL, "null g");
-    if (c->gen) return fail(HHGR_ESTATE, "adjoint needs general_geometry = 0");
     if (dev_dJdk && !c->vk) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
     LevelDev &D = c->lev[c->L];
     const long long ns = D.n_slots;
@@ -1593,12 +1620,18 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
         hhgr_report rep{0, 0.0, nullptr, 0};
         result = gn > 0 ? hhgr_solve(c, rel_tol, max_cycles, &rep) : HHGR_OK;
         if (dev_dJdf) {
-            launch_mass(c->stream, vint, ig, D.nb15, D.u, D.r, D.h);
+            if (c->gen)
+                launch_apply15(c->stream, vint, ig, gen15mass(D), D.u, D.r);
+            else
+                launch_mass(c->stream, vint, ig, D.nb15, D.u, D.r, D.h);
             launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.r, dev_dJdf);
         }
         if (dev_dJdk) {
             launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_l);
-            launch_grad_k(c->stream, c->user_u, c->user_l, D.N, D.h, dev_dJdk);
+            if (c->gen)
+                launch_grad_k15(c->stream, D.N, D.m, c->d.n_sub, c->kel, c->user_u, c->user_l, dev_dJdk);
+            else
+                launch_grad_k(c->stream, c->user_u, c->user_l, D.N, D.h, dev_dJdk);
         }
     }
     // restore the forward state

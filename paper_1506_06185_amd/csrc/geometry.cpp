@@ -65,6 +65,15 @@ void p1_stiffness(const double *e1, const double *e2, const double *e3, double K
         for (int b = 0; b < 4; b++) K[a][b] = vol * dot(g[a], g[b]);
 }
 
+// consistent P1 mass matrix of the same tetrahedron: |T| / 20 (1 + delta_ab)
+void p1_mass(const double *e1, const double *e2, const double *e3, double Mm[4][4]) {
+    double c[3];
+    cross(e2, e3, c);
+    const double vol = std::fabs(dot(e1, c)) / 6.0;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) Mm[a][b] = vol / 20.0 * (a == b ? 2.0 : 1.0);
+}
+
 void corners(const Topology &tp, const double *xyz, int t, double P[4][3]) {
     const int n1 = tp.n_sub + 1;
     int v[3] = {tp.V0[t][0], tp.V0[t][1], tp.V0[t][2]};
@@ -126,7 +135,7 @@ void StencilBuilder::key(const int X[3], NodeKey &k) const {
 
 // sum of the element stiffness entries of the node (vertex r of each
 // element) with itself and with the element's other vertices
-void StencilBuilder::stencil(const NodeKey &k, double S[15]) const {
+void StencilBuilder::stencil(const NodeKey &k, double S[15], bool mass) const {
     const auto &A = around();
     for (int e = 0; e < 15; e++) S[e] = 0.0;
     for (int q = 0; q < 24; q++) {
@@ -140,7 +149,10 @@ void StencilBuilder::stencil(const NodeKey &k, double S[15]) const {
             for (int x = 0; x < 3; x++) ev[v - 1][x] = di * E_[t][x] + dj * E_[t][3 + x] + dk * E_[t][6 + x];
         }
         double K[4][4];
-        p1_stiffness(ev[0], ev[1], ev[2], K);
+        if (mass)
+            p1_mass(ev[0], ev[1], ev[2], K);
+        else
+            p1_stiffness(ev[0], ev[1], ev[2], K);
         const int r = e.r;
         S[0] += K[r][r];
         for (int v = 0; v < 4; v++) {
@@ -150,26 +162,27 @@ void StencilBuilder::stencil(const NodeKey &k, double S[15]) const {
     }
 }
 
-void StencilBuilder::grid_stencil(const int X[3], double S[15]) {
+void StencilBuilder::grid_stencil(const int X[3], double S[15], bool mass) {
     NodeKey k;
     key(X, k);
-    auto it = memo_.find(k);
-    if (it == memo_.end()) {
+    auto &memo = mass ? memo_mass_ : memo_;
+    auto it = memo.find(k);
+    if (it == memo.end()) {
         std::array<double, 15> st;
-        stencil(k, st.data());
-        it = memo_.emplace(k, st).first;
+        stencil(k, st.data(), mass);
+        it = memo.emplace(k, st).first;
     }
     for (int e = 0; e < 15; e++) S[e] = it->second[e];
 }
 
-void StencilBuilder::volume_stencil(int t, double S[15]) {
+void StencilBuilder::volume_stencil(int t, double S[15], bool mass) {
     const int a = tp_.perm[t][0], b = tp_.perm[t][1], c = tp_.perm[t][2];
     int X[3] = {m_ * tp_.V0[t][0], m_ * tp_.V0[t][1], m_ * tp_.V0[t][2]};
     X[a] += 3;
     X[b] += 2;
     X[c] += 1;
     double G[15];
-    grid_stencil(X, G);
+    grid_stencil(X, G, mass);
     for (int n = 0; n < 15; n++) {
         int g[3] = {0, 0, 0};
         g[a] += kIdx15[n][0] + kIdx15[n][1] + kIdx15[n][2];
@@ -185,7 +198,11 @@ std::string level_stencils(const Topology &tp, const double *xyz, int l, int cap
     const TopoLevel &T = tp.lev[l];
     StencilBuilder sb(tp, xyz, l);
     G.w15.assign(15 * (size_t)tp.n_tets, 0.0);
-    for (int t = 0; t < tp.n_tets; t++) sb.volume_stencil(t, &G.w15[15 * (size_t)t]);
+    G.mw15.assign(15 * (size_t)tp.n_tets, 0.0);
+    for (int t = 0; t < tp.n_tets; t++) {
+        sb.volume_stencil(t, &G.w15[15 * (size_t)t], false);
+        sb.volume_stencil(t, &G.mw15[15 * (size_t)t], true);
+    }
     const int n = T.n_ifc;
     const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
     const int chunk = (n + nth - 1) / nth;
@@ -229,7 +246,11 @@ std::string level_stencils(const Topology &tp, const double *xyz, int l, int cap
     for (int w = 0; w < nth; w++)
         for (int f = w * chunk; f < std::min(n, (w + 1) * chunk); f++) G.sid[f] = renum[w][G.sid[f]];
     G.wtab.assign(15 * all.size(), 0.0);
-    for (size_t q = 0; q < all.size(); q++) sb.stencil(all[q], &G.wtab[15 * q]);
+    G.mwtab.assign(15 * all.size(), 0.0);
+    for (size_t q = 0; q < all.size(); q++) {
+        sb.stencil(all[q], &G.wtab[15 * q], false);
+        sb.stencil(all[q], &G.mwtab[15 * q], true);
+    }
     return "";
 }
 

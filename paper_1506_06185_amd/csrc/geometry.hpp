@@ -32,27 +32,29 @@ class StencilBuilder {
     StencilBuilder(const Topology &tp, const double *xyz, int l);
     // key of the interior grid node X
     void key(const int X[3], NodeKey &k) const;
-    // stencil in kGrid15 order (entry 0 the diagonal) of a node with key k
-    void stencil(const NodeKey &k, double S[15]) const;
+    // stencil in kGrid15 order (entry 0 the diagonal) of a node with key k:
+    // stiffness, or with mass the consistent P1 mass matrix
+    void stencil(const NodeKey &k, double S[15], bool mass = false) const;
     // stencil of the interior grid node X in kGrid15 order (memoised by key)
-    void grid_stencil(const int X[3], double S[15]);
+    void grid_stencil(const int X[3], double S[15], bool mass = false);
     // volume stencil of tetrahedron t in kIdx15 order
-    void volume_stencil(int t, double S[15]);
+    void volume_stencil(int t, double S[15], bool mass = false);
 
   private:
     const Topology &tp_;
     int m_;
     std::vector<std::array<double, 9>> E_;  // per macro tet: (P1-P0)/m, (P2-P0)/m, (P3-P0)/m
-    std::map<NodeKey, std::array<double, 15>> memo_;
+    std::map<NodeKey, std::array<double, 15>> memo_, memo_mass_;
     int macro_tet(const int c[3], int pi) const;
 };
 
 // Stencils of one level: the volume stencil of every tetrahedron (kIdx15
 // order, [15 t + n]) and, per interface master, the index of its stencil in
-// the table of the level's distinct stencils (kGrid15 order, [15 id + n]).
-// cap bounds the table; returns an empty string or the error.
+// the table of the level's distinct stencils (kGrid15 order, [15 id + n]);
+// the same for the mass matrix (mw15, mwtab, same indices).  cap bounds the
+// table; returns an empty string or the error.
 struct LevelStencils {
-    std::vector<double> w15, wtab;
+    std::vector<double> w15, wtab, mw15, mwtab;
     std::vector<int> sid;
 };
 std::string level_stencils(const Topology &tp, const double *xyz, int l, int cap, LevelStencils &G);

@@ -557,6 +557,29 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
     }
 }
 
+// y = S x at every interior node of vg and every master of ig with the
+// stencils of g (one per tetrahedron and one per primitive; the mass matrix)
+__global__ void __launch_bounds__(512) k_apply15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+    const unsigned f = blockIdx.x;
+    if (f < (unsigned)nib) {
+        const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
+        if (t >= ig.i1) return;
+        double diag;
+        y[ig.base + t] = master_Au<false>(ig, g, x, t, x[ig.base + t], diag);
+        return;
+    }
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+    LNode nd;
+    if (!list_node<1>(vg, blk, per_vol, 0, nd)) return;
+    const VolDesc d = vg.vd[nd.v];
+    int c0;
+    double xo, diag;
+    const double Sx = volume_Au<false>(vg, g, d, nd, x + d.vec, c0, xo, diag);
+    y[d.vec + c0] = Sx;
+}
+
 // local coarsest level: u = b / diag at the single interior node (slot)
 __global__ void k_local_coarse15(const VolDesc *__restrict__ vd, int nvol, int slot, Gen15 g,
                                  const double *__restrict__ b, double *__restrict__ u) {
@@ -1216,6 +1239,35 @@ __device__ __forceinline__ void tet_step(const int *__restrict__ tetinfo, int t,
     g[tetinfo[6 * t + 5]] += kIdx15D[n][2];
 }
 
+// dJ/dk_e = -lambda_e^T K_e u_e for every element e of the level (element
+// order), K_e its unit-coefficient matrix (kel / m); u and lambda in vector
+// order, zero on the boundary
+__global__ void k_grad_k15(int N, int m, int n_sub, const double *__restrict__ kel, const double *__restrict__ u,
+                           const double *__restrict__ lam, double *__restrict__ out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long ne = 6LL * N * N * N;
+    if (e >= ne) return;
+    const int q = (int)(e % 6);
+    const long long cell = e / 6;
+    const int c[3] = {(int)(cell % N), (int)((cell / N) % N), (int)(cell / ((long long)N * N))};
+    const long long n1 = N - 1;
+    double ul[4], ll[4];
+    for (int v = 0; v < 4; v++) {
+        int o[3];
+        elem_vertex(q, v, o);
+        const int X[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
+        const bool in = X[0] > 0 && X[1] > 0 && X[2] > 0 && X[0] < N && X[1] < N && X[2] < N;
+        const long long d = (X[0] - 1) + n1 * ((X[1] - 1) + n1 * (X[2] - 1));
+        ul[v] = in ? u[d] : 0.0;
+        ll[v] = in ? lam[d] : 0.0;
+    }
+    const double *K = kel + (6LL * macro_tet_of(c[0], c[1], c[2], q, m, n_sub) + q) * 16;
+    double g = 0.0;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) g += ll[a] * K[4 * a + b] * ul[b];
+    out[e] = -g / m;
+}
+
 // every closure node (vg lists the full closure): the 7 forward edge weights
 // of the edges that stay in the closure (0 otherwise) and the diagonal
 __global__ void __launch_bounds__(256) k_gen_weights(VolGeom vg, const int *__restrict__ tetinfo, GenK G,
@@ -1708,6 +1760,19 @@ void launch_gen_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, const 
 void launch_gen_coarse_vals(hipStream_t s, int n, const int *pos, const int *col15, const GenK &G, double *val) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gen_coarse_vals, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, col15, G, val);
+}
+
+void launch_apply15(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const Gen15 &g, const double *x, double *y) {
+    const int nib = ifc_blocks(ig, vint.bs);
+    const long long grid = nib + list_blocks(vint, 1);
+    if (grid == 0) return;
+    hipLaunchKernelGGL(k_apply15, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, g, nib, x, y);
+}
+
+void launch_grad_k15(hipStream_t s, int N, int m, int n_sub, const double *kel, const double *u, const double *lam,
+                     double *out) {
+    const long long ne = 6LL * N * N * N;
+    hipLaunchKernelGGL(k_grad_k15, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, N, m, n_sub, kel, u, lam, out);
 }
 
 void launch_neumann_rhs15(hipStream_t s, int n_ifc, long long base, const int *nb15, const double *wi15,

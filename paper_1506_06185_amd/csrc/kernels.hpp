@@ -182,6 +182,12 @@ void launch_gen_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo,
                         long long ws);
 void launch_gen_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, const GenK &G, double *wi15);
 void launch_gen_coarse_vals(hipStream_t s, int n, const int *pos, const int *col15, const GenK &G, double *val);
+// y = S x on a general macro mesh (interior nodes of vint, masters of ig)
+// with the stencils of g, e.g. the mass matrix
+void launch_apply15(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const Gen15 &g, const double *x, double *y);
+// dJ/dk per element of a general macro mesh (u, lam in vector order)
+void launch_grad_k15(hipStream_t s, int N, int m, int n_sub, const double *kel, const double *u, const double *lam,
+                     double *out);
 // Dirichlet-Neumann Neumann data on a general macro mesh (see launch_neumann_rhs)
 void launch_neumann_rhs15(hipStream_t s, int n_ifc, long long base, const int *nb15, const double *wi15,
                           const unsigned char *gamma, const double *u, double *b_out);

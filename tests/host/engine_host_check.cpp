@@ -12,6 +12,11 @@
 extern int g_mock_captures, g_mock_launches;
 extern double g_mock_res2;
 static int fails = 0;
+static long long nd_vk(hhgr_ctx *c) {
+    long long n = 0;
+    hhgr_sizes(c, &n, nullptr, nullptr);
+    return n;
+}
 #define CHECK(c, ...)                          \
     do {                                       \
         if (!(c)) {                            \
@@ -117,7 +122,7 @@ int main() {
         hhgr_sizes(g, &nd, nullptr, nullptr);
         std::vector<double> v(nd, 1.0), w(nd, 0.0);
         CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "general rhs");
-        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_ESTATE, "general nodal f rejected");
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_ESTATE, "general nodal f needs geometry");
         CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_ESTATE, "no geometry yet");
         std::vector<double> xyz;
         for (int z = 0; z <= 2; z++)
@@ -136,7 +141,8 @@ int main() {
         CHECK(hhgr_recover_local(g, 5, 2, &rr) == HHGR_OK, "general recover_local: %s", hhgr_last_error());
         CHECK(hhgr_recover_dd(g, t2, 2, 2, 3) == HHGR_OK, "general recover_dd: %s", hhgr_last_error());
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_OK, "general dn: %s", hhgr_last_error());
-        CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_ESTATE, "general mass rejected");
+        CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_OK, "general mass: %s", hhgr_last_error());
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_OK, "general nodal f: %s", hhgr_last_error());
         CHECK(hhgr_autotune(g, nullptr) == HHGR_ESTATE, "general autotune rejected");
         CHECK(hhgr_debug_op(g, 0, 5, v.data(), v.data(), w.data()) == HHGR_OK, "general residual op");
         CHECK(hhgr_debug_op(g, 1, 5, v.data(), v.data(), w.data()) == HHGR_EINVAL, "general op 1 rejected");
@@ -171,6 +177,11 @@ int main() {
         CHECK(hhgr_recover_local(g, 7, 2, &rr) == HHGR_OK, "general vk recover_local");
         CHECK(hhgr_recover_dd(g, t2, 2, 1, 2) == HHGR_OK, "general vk recover_dd: %s", hhgr_last_error());
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 2) == HHGR_OK, "general vk recover_dn: %s", hhgr_last_error());
+        {
+            std::vector<double> gg(nd_vk(g), 0.5), dfv(nd_vk(g)), dkv(ne);
+            CHECK(hhgr_adjoint_grad(g, gg.data(), 1e-10, 5, dfv.data(), dkv.data()) == HHGR_ENOCONV,
+                  "general adjoint runs (mock residuals never converge): %s", hhgr_last_error());
+        }
         CHECK(hhgr_set_coeff(g, k.data()) == HHGR_OK, "general vk coeff again");
         hhgr_destroy(g);
         std::free(ws);

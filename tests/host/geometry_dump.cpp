@@ -3,7 +3,8 @@
 //   geometry_dump n_sub level coarse_level vertices.f64 out_dir
 // vertices.f64: (n+1)^3 x 3 doubles, x fastest.  Per level l:
 //   l<l>_X.i32 (interface grid positions), l<l>_sid.i32, l<l>_wtab.f64,
-//   l<l>_w15.f64; coarse: c_pos.i32, c_col15.i32, c_val15.f64;
+//   l<l>_w15.f64, and the mass stencils l<l>_mwtab.f64, l<l>_mw15.f64;
+//   coarse: c_pos.i32, c_col15.i32, c_val15.f64;
 //   tets.i32 (V0 and axis order per macro tetrahedron).
 #include <cstdio>
 #include <cstdlib>
@@ -64,6 +65,8 @@ int main(int argc, char **argv) {
         ok = ok && put(p + "sid.i32", G.sid.data(), G.sid.size());
         ok = ok && put(p + "wtab.f64", G.wtab.data(), G.wtab.size());
         ok = ok && put(p + "w15.f64", G.w15.data(), G.w15.size());
+        ok = ok && put(p + "mwtab.f64", G.mwtab.data(), G.mwtab.size());
+        ok = ok && put(p + "mw15.f64", G.mw15.data(), G.mw15.size());
         std::printf("level %d: %d interface masters, %zu distinct stencils\n", l, T.n_ifc, G.wtab.size() / 15);
     }
     std::vector<double> cval;

@@ -94,6 +94,8 @@ void launch_gen_ifc_weights(hipStream_t, int, const int *, const GenK &, double 
 void launch_gen_coarse_vals(hipStream_t, int, const int *, const int *, const GenK &, double *) {}
 void launch_neumann_rhs15(hipStream_t, int, long long, const int *, const double *, const unsigned char *,
                           const double *, double *) {}
+void launch_apply15(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, const double *, double *) {}
+void launch_grad_k15(hipStream_t, int, int, int, const double *, const double *, const double *, double *) {}
 void launch_gen_dirichlet(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, const int *, const int *, int,
                           const double *, double *) {}
 void launch_dn_masks(hipStream_t, int, long long, long long, const int *, const int *, const unsigned char *,

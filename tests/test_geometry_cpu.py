@@ -1,7 +1,7 @@
 """Host-side 15-point stencils of general macro meshes (moved macro vertices,
 each macro tetrahedron refined regularly and mapped affinely; Sec. 3.1)
-against the oracle's stiffness matrices assembled element by element in
-physical coordinates (CPU only, no GPU calls).
+against the oracle's stiffness and mass matrices assembled element by
+element in physical coordinates (CPU only, no GPU calls).
 
 The library keeps one stencil per tetrahedron for volume nodes and one per
 primitive for interface masters; every such stencil is compared here with
@@ -67,14 +67,15 @@ def test_host_stencils_match_oracle_rows(dump_exe, tmp_path, n_sub, level, seed)
     dump(dump_exe, tmp_path, n_sub, level, V)
     p = oracle.Problem(n_sub, level, vertices=V)
     tets = np.fromfile(tmp_path / "tets.i32", dtype=np.int32).reshape(2, -1, 3)
-    for l in range(2, level + 1):
-        A = p.matrix(l).tocsr()
+    for l, which in [(l, w) for l in range(2, level + 1) for w in ("A", "M")]:
+        A = p.matrix(l, which).tocsr()
         N, m = n_sub << l, 1 << l
         scale = np.abs(A.diagonal()).max()
+        pre = "" if which == "A" else "m"
         X = np.fromfile(tmp_path / f"l{l}_X.i32", dtype=np.int32).reshape(-1, 3)
         sid = np.fromfile(tmp_path / f"l{l}_sid.i32", dtype=np.int32)
-        wtab = np.fromfile(tmp_path / f"l{l}_wtab.f64").reshape(-1, 15)
-        w15 = np.fromfile(tmp_path / f"l{l}_w15.f64").reshape(-1, 15)
+        wtab = np.fromfile(tmp_path / f"l{l}_{pre}wtab.f64").reshape(-1, 15)
+        w15 = np.fromfile(tmp_path / f"l{l}_{pre}w15.f64").reshape(-1, 15)
         assert len(X) == len(sid) and sid.min() >= 0 and sid.max() < len(wtab)
         # distinct stencils: at most one per macro face, edge and vertex
         assert len(wtab) <= 14 * 6 * n_sub ** 3
@@ -86,7 +87,7 @@ def test_host_stencils_match_oracle_rows(dump_exe, tmp_path, n_sub, level, seed)
             ok = interior(Y, N)
             got = wtab[sid[ok], e]
             want = entries(A, rows[ok], vidx(Y[ok], N))
-            np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * scale, err_msg=f"level {l} offset {e}")
+            np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * scale, err_msg=f"{which} level {l} offset {e}")
             covered[ok] += np.abs(want)
         # nothing of the oracle's rows lies outside the 15 offsets
         np.testing.assert_allclose(covered, np.asarray(abs(A)[rows].sum(axis=1)).ravel(), rtol=1e-12)
@@ -108,7 +109,7 @@ def test_host_stencils_match_oracle_rows(dump_exe, tmp_path, n_sub, level, seed)
                 ok = interior(Y, N)
                 want = entries(A, vidx(Xt[ok], N), vidx(Y[ok], N))
                 np.testing.assert_allclose(np.full(ok.sum(), w15[t, n]), want, rtol=0, atol=1e-12 * scale,
-                                           err_msg=f"level {l} tet {t} offset {n}")
+                                           err_msg=f"{which} level {l} tet {t} offset {n}")
     # coarsest level: matrix rows over the unknowns
     A = p.matrix(2).tocsr()
     N = n_sub << 2

@@ -402,3 +402,31 @@ def test_coarse_level_3(dev, hh):
     with pytest.raises(hh.HHGRError):
         ctx.recover_local(0, 1)  # local recovery needs coarse level 2
     ctx.close()
+
+
+def test_mass_source_and_adjoint_gradients(dev, hh):
+    """The consistent mass matrix of the moved elements (mass_apply and
+    b = M f), and the adjoint gradients dJ/df = M lambda and
+    dJ/dk_T = -lambda^T A_T u through the autograd Function, against the
+    oracle on the same mesh."""
+    n_sub, level, seed = 2, 4, 8
+    print("\n[general mass + adjoint]", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=3)
+    f = inputs.sine_source(n_sub, level)
+    uobs = inputs.gaussian_obs(n_sub, level, seed=3)
+    p = problem_k(n_sub, level, seed, 3)
+    ctx = context(hh, dev, n_sub, level, seed, k=k)
+    x = np.random.default_rng(800).standard_normal(p.ndof)
+    assert rel(Nn(ctx.mass_apply(T(x, dev))), p.apply_M(x)) < 1e-13
+    b = p.apply_M(f)
+    u, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+    lam, _, _ = p.solve(u - uobs, rtol=1e-13, max_cycles=80)
+    fT = T(f, dev).requires_grad_(True)
+    kT = T(k, dev).requires_grad_(True)
+    uT = hh.HHGSolve.apply(ctx, fT, kT, 1e-13, 80)
+    assert rel(Nn(uT), u) < 1e-10
+    J = 0.5 * ((uT - T(uobs, dev)) ** 2).sum()
+    J.backward()
+    assert rel(Nn(fT.grad), p.apply_M(lam)) < 1e-9
+    assert rel(Nn(kT.grad), p.grad_k(u, lam)) < 1e-9
+    ctx.close()
