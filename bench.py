@@ -153,7 +153,7 @@ def leg_mixed_job(hh, torch, dev, n_sub, level, f_dev, t_fault, steps, warmup, g
     }
 
 
-def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph):
+def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph, tune_cache):
     """The headline job (5 cycles, fault, 3 local recovery cycles, solve to
     1e-8) on a general macro mesh; value = unknowns x cycles / time."""
     from paper_1506_06185_amd import inputs
@@ -162,6 +162,7 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph):
     t0 = time.perf_counter()
     ctx.set_geometry(inputs.perturbed_vertices(n_sub, seed=0))
     t_geom = time.perf_counter() - t0
+    ctx.autotune(tune_cache)
     if graph:
         ctx.set_graph(True)
     b = torch.from_numpy(inputs.uniform_load(n_sub, level, seed=0)).to(dev)
@@ -463,7 +464,7 @@ def main():
     general = None
     if not args.no_general:
         log("general macro mesh leg")
-        general = leg_general(hh, torch, dev, n_sub, level, args.steps, args.warmup, args.graph)
+        general = leg_general(hh, torch, dev, n_sub, level, args.steps, args.warmup, args.graph, tune_cache)
     extra = {}
     if not args.no_extra:
         for name, fn in (("mixed_l8", lambda: leg_mixed_l8(hh, torch, dev, tune_cache)),

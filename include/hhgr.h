@@ -126,8 +126,9 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * Dirichlet-Neumann recovery takes the 15-point entries assembled over the
  * elements of intact macro tetrahedra.  HHGR_RHS_NODAL_F, hhgr_mass_apply and
  * hhgr_adjoint_grad use the consistent P1 mass matrix and the element
- * matrices of the moved elements (after this call).  Not available with such
- * contexts: mixed precision and hhgr_autotune (ESTATE). */
+ * matrices of the moved elements (after this call); hhgr_autotune times the
+ * class pass (after this call).  Not available with such contexts: mixed
+ * precision (EINVAL at creation). */
 int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Right-hand side of eq. (2) from a device vector in the vector order above.

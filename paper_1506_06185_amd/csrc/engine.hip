@@ -1718,7 +1718,7 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
 
 int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
     if (!c) return fail(HHGR_EINVAL, "null context");
-    if (c->gen) return fail(HHGR_ESTATE, "the autotuner covers general_geometry = 0");
+    if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     hipDeviceProp_t prop;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -1738,7 +1738,8 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
     for (int l = c->Lc + 1; l <= c->L; l++) {
         LevelDev &D = c->lev[l];
         std::ostringstream ks;
-        ks << devname << ":n" << c->d.n_sub << ":l" << l << ":" << (c->mixed ? "f32" : "f64") << ":vk" << c->vk;
+        ks << devname << ":n" << c->d.n_sub << ":l" << l << ":" << (c->mixed ? "f32" : "f64") << ":vk" << c->vk
+           << (c->gen ? ":g15" : "");
         auto it = cache.find(ks.str());
         auto itr = cache.find(ks.str() + ":remap");
         auto itc = cache.find(ks.str() + ":cpb");
@@ -1763,6 +1764,36 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         };
         double best = 1e30;
         int bq = 1, br = 1, bc = 1;
+        if (c->gen) {
+            // general macro mesh: workgroup size and block order of the class
+            // pass (one node per thread); the residual takes the same shape
+            for (int rq = 0; rq < 6; rq++) {
+                const int q = rq % 3;
+                D.remap = rq < 3 ? 1 : 0;
+                VolGeom vg = vgeom(D, D.vd_all, c->n_tets, false, q);
+                vg.list = D.qlist[0];
+                vg.nlist = D.nqlist[0];
+                const float ms = time_it([&]() {
+                    launch_colour15(c->stream, vg, igeom(D, 0, D.n_ifc, nullptr, true), gen15(D, 0, true), D.r, D.b,
+                                    c->d.omega);
+                }, l >= 6 ? 5 : 20);
+                if (ms < best) {
+                    best = ms;
+                    bq = q;
+                    br = D.remap;
+                }
+            }
+            D.bs_sel = bq;
+            D.remap = br;
+            D.cpb = D.cpb_res = D.cpb_prl = 1;
+            cache[ks.str()] = bq;
+            cache[ks.str() + ":remap"] = br;
+            cache[ks.str() + ":cpb"] = 1;
+            cache[ks.str() + ":cpb_res"] = 1;
+            cache[ks.str() + ":cpb_prl"] = 1;
+            launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
+            continue;
+        }
         for (int rq = 0; rq < 12; rq++) {
             const int q = rq % 3;
             D.remap = (rq / 3) % 2 == 0 ? 1 : 0;

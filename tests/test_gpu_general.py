@@ -430,3 +430,20 @@ def test_mass_source_and_adjoint_gradients(dev, hh):
     assert rel(Nn(fT.grad), p.apply_M(lam)) < 1e-9
     assert rel(Nn(kT.grad), p.grad_k(u, lam)) < 1e-9
     ctx.close()
+
+
+def test_autotuned_shapes_give_the_same_iterates(dev, hh):
+    """The autotuner's class-pass shape (workgroup size, block order) per
+    level leaves the iterates unchanged."""
+    n_sub, level, seed = 2, 5, 5
+    print("\n[general autotune]", flush=True)
+    ctx = context(hh, dev, n_sub, level, seed)
+    ctx.autotune()
+    print(f"  tuning {ctx.tuning_info()}", flush=True)
+    p = problem(n_sub, level, seed)
+    b = np.random.default_rng(900).uniform(0.0, 1.0, p.ndof) / p.ndof
+    ctx.set_rhs(T(b, dev))
+    ctx.vcycle(3)
+    uo, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-12
+    ctx.close()
