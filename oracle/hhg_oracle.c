@@ -1566,6 +1566,19 @@ static void residual32(const mglev *m, const float *u, const float *b, float *r)
     }
 }
 
+/* one FP32 sweep in the order of sweep64 */
+static void sweep32(const mglev *m, float *u, const float *b, float omega) {
+    if (m->four) {
+        colour_pass32(m, m->red, m->nred0, u, b, omega);
+        colour_pass32(m, m->black, m->nblack1, u, b, omega);
+        colour_pass32(m, m->red + m->nred0, m->nred - m->nred0, u, b, omega);
+        colour_pass32(m, m->black + m->nblack1, m->nblack - m->nblack1, u, b, omega);
+        return;
+    }
+    colour_pass32(m, m->red, m->nred, u, b, omega);
+    colour_pass32(m, m->black, m->nblack, u, b, omega);
+}
+
 static void spmv32(const csr *A, const float *x, float *y) {
 #pragma omp parallel for schedule(static)
     for (i64 i = 0; i < A->nrow; i++) {
@@ -1599,10 +1612,7 @@ static void vcycle32(const mghier *H, int l, float *u, const float *b, const mgo
         return;
     }
     float om = (float)o->omega;
-    for (int s = 0; s < o->nu1; s++) {
-        colour_pass32(m, m->red, m->nred, u, b, om);
-        colour_pass32(m, m->black, m->nblack, u, b, om);
-    }
+    for (int s = 0; s < o->nu1; s++) sweep32(m, u, b, om);
     float *r = xmalloc((size_t)(n ? n : 1) * sizeof(float));
     residual32(m, u, b, r);
     const mglev *mc = &H->lv[l - 1];
@@ -1612,10 +1622,7 @@ static void vcycle32(const mghier *H, int l, float *u, const float *b, const mgo
     vcycle32(H, l - 1, ec, bc, o);
     spmv32(&m->P, ec, r);
     for (i64 i = 0; i < n; i++) u[i] += r[i];
-    for (int s = 0; s < o->nu2; s++) {
-        colour_pass32(m, m->red, m->nred, u, b, om);
-        colour_pass32(m, m->black, m->nblack, u, b, om);
-    }
+    for (int s = 0; s < o->nu2; s++) sweep32(m, u, b, om);
     free(bc);
     free(ec);
     free(r);
@@ -1625,7 +1632,6 @@ static void vcycle32(const mghier *H, int l, float *u, const float *b, const mgo
  * hist[c] = ||r_c|| / r0.  Returns the step count or -1. */
 int ohhg_solve_mixed(void *vp, double *u, const double *b, double omega, int nu1, int nu2, double rtol,
                      int max_steps, double r0_ref, double *hist) {
-    if (((oproblem *)vp)->geom) die("mixed precision is not defined for a general geometry");
     oproblem *p = vp;
     mghier H;
     hier_global(p, &H);

@@ -8,8 +8,10 @@ import oracle
 from paper_1506_06185_amd import inputs
 
 
-def test_mixed_precision_reaches_fp64_accuracy(oracle_problem):
-    p = oracle_problem(2, 5)
+@pytest.mark.parametrize("general", [False, True])
+def test_mixed_precision_reaches_fp64_accuracy(oracle_problem, general):
+    """With general, on a moved mesh (the FP32 cycle takes the 4-class sweep)."""
+    p = oracle.Problem(2, 5, vertices=inputs.perturbed_vertices(2, 7)) if general else oracle_problem(2, 5)
     b = inputs.uniform_load(2, 5, seed=0)
     u64, c64, h64 = p.solve(b, rtol=1e-13, max_cycles=60)
     um, cm, hm = p.solve_mixed(b, rtol=1e-12, max_steps=60)
