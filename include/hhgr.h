@@ -69,8 +69,7 @@ typedef struct {
     int variable_coeff; /* 0: k = 1; 1: per-element k from hhgr_set_coeff               */
     int max_faults;     /* faulty tetrahedra recoverable at once, 0..8, default 8       */
     int general_geometry; /* 0: the unit cube; 1: moved macro vertices from
-                             hhgr_set_geometry (needs precision = HHGR_FP64),
-                             default 0                                          */
+                             hhgr_set_geometry, default 0                        */
 } hhgr_desc;
 
 /* Convergence report.  history (optional, caller-owned, history_cap entries)
@@ -127,8 +126,8 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * elements of intact macro tetrahedra.  HHGR_RHS_NODAL_F, hhgr_mass_apply and
  * hhgr_adjoint_grad use the consistent P1 mass matrix and the element
  * matrices of the moved elements (after this call); hhgr_autotune times the
- * class pass (after this call).  Not available with such contexts: mixed
- * precision (EINVAL at creation). */
+ * class pass (after this call); mixed precision keeps FP32 copies of the
+ * stencil tables for its FP32 cycle. */
 int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Right-hand side of eq. (2) from a device vector in the vector order above.

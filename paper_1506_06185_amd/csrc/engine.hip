@@ -114,6 +114,7 @@ struct LevelDev {
     double *wv = nullptr, *wi15 = nullptr;
     double *wi15_dn = nullptr;  // intact-side master entries of a Dirichlet-Neumann recovery
     double *mw15 = nullptr, *mwtab = nullptr;  // finest level: mass stencils (indexed like w15, wtab)
+    float *w15f = nullptr, *wtabf = nullptr, *wvf = nullptr, *wi15f = nullptr;  // FP32 copies (mixed precision)
 };
 
 template <typename T>
@@ -269,6 +270,13 @@ void carve(hhgr_ctx &c, Carver &cv) {
                 D.mw15 = cv.take<double>(15 * (size_t)c.n_tets);
                 D.mwtab = cv.take<double>(15 * (size_t)D.wtab_cap);
             }
+            if (c.mixed && c.vk) {
+                D.wvf = cv.take<float>(8 * (size_t)T.n_slots);
+                D.wi15f = cv.take<float>(15 * (size_t)T.n_ifc);
+            } else if (c.mixed) {
+                D.w15f = cv.take<float>(15 * (size_t)c.n_tets);
+                D.wtabf = cv.take<float>(15 * (size_t)D.wtab_cap);
+            }
         }
         D.ifc_dof = cv.take<int>(T.n_ifc);
         D.ifc_xyz = cv.take<int>(3 * (size_t)T.n_ifc);
@@ -393,7 +401,6 @@ std::string check_desc(const hhgr_desc *d) {
     if (d->variable_coeff != 0 && d->variable_coeff != 1) return "variable_coeff must be 0 or 1";
     if (d->max_faults < 0 || d->max_faults > 8) return "max_faults must be in 0..8";
     if (d->general_geometry != 0 && d->general_geometry != 1) return "general_geometry must be 0 or 1";
-    if (d->general_geometry && d->precision != HHGR_FP64) return "general_geometry needs precision = HHGR_FP64";
     return "";
 }
 
@@ -464,6 +471,10 @@ Gen15 gen15(const LevelDev &D, int q, bool ifc) {
     g.wv = D.wv;
     g.ws = D.n_slots;
     g.wi15 = D.wi15;
+    g.w15f = D.w15f;
+    g.wtabf = D.wtabf;
+    g.wvf = D.wvf;
+    g.wi15f = D.wi15f;
     return g;
 }
 
@@ -479,7 +490,8 @@ Gen15 gen15mass(const LevelDev &D) {
 }
 
 // ... of a view's level (a view may bring its own master entries)
-Gen15 gen15v(const LevelDev &D, const LevView<double> &v, int q) {
+template <typename T>
+Gen15 gen15v(const LevelDev &D, const LevView<T> &v, int q) {
     Gen15 g = gen15(D, q, v.ifc);
     if (v.wi15) g.wi15 = v.wi15;
     return g;
@@ -600,10 +612,11 @@ long long view_len(const hhgr_ctx &c, const HView<T> &V, int l) {
 
 // general macro meshes: one 4-colour sweep, classes 0, 1, 2, 3 (a start
 // from zero clears the level's vector first)
-void sweep15(hhgr_ctx &c, const HView<double> &V, int l, bool zero, hipStream_t s) {
+template <typename T>
+void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     const LevelDev &D = c.lev[l];
-    const LevView<double> &v = V.lv[l];
-    if (zero) launch_fill<double>(s, v.u, view_len(c, V, l), 0.0);
+    const LevView<T> &v = V.lv[l];
+    if (zero) launch_fill<T>(s, v.u, view_len(c, V, l), T(0));
     for (int q = 0; q < 4; q++) {
         VolGeom vg = vgeom(D, v.vd, v.nvol, false);
         vg.list = D.qlist[q];
@@ -611,7 +624,7 @@ void sweep15(hhgr_ctx &c, const HView<double> &V, int l, bool zero, hipStream_t 
         const IfcGeom ig = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
-        launch_colour15(s, vg, ig, gen15v(D, v, q), v.u, v.b, c.d.omega);
+        launch_colour15<T>(s, vg, ig, gen15v(D, v, q), v.u, v.b, c.d.omega);
         if (timed) timed_end(c, s);
     }
 }
@@ -619,11 +632,9 @@ void sweep15(hhgr_ctx &c, const HView<double> &V, int l, bool zero, hipStream_t 
 // one red-black sweep in place: two colour passes
 template <typename T>
 void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
-    if constexpr (std::is_same<T, double>::value) {
-        if (c.gen) {
-            sweep15(c, V, l, zero, s);
-            return;
-        }
+    if (c.gen) {
+        sweep15<T>(c, V, l, zero, s);
+        return;
     }
     const LevelDev &D = c.lev[l];
     const LevView<T> &v = V.lv[l];
@@ -648,15 +659,16 @@ template <typename T>
 void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     const LevelDev &D = c.lev[c.Lc];
     const LevView<T> &v = V.lv[c.Lc];
-    if constexpr (std::is_same<T, double>::value) {
-        if (c.gen) {
-            if (V.local)
+    if (c.gen) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (V.local) {
                 launch_local_coarse15(s, v.vd, v.nvol, D.lc_sl.x, gen15(D, -1, false), v.b, v.u);
-            else
-                launch_coarse_pcg15(s, c.cn, c.cslot, c.ccol15, V.cval ? V.cval : c.cval15, V.cfrozen, v.b, v.u,
-                                    c.cptr, c.cidx, kCoarseRtol, kCoarseMaxit, c.citers);
-            return;
+                return;
+            }
         }
+        launch_coarse_pcg15<T>(s, c.cn, c.cslot, c.ccol15, V.cval ? V.cval : c.cval15, V.cfrozen, v.b, v.u, c.cptr,
+                               c.cidx, kCoarseRtol, kCoarseMaxit, c.citers);
+        return;
     }
     if (V.local) {
         launch_local_coarse<T>(s, v.vd, v.nvol, D.lc_sl, v.b, v.u, v.w, c.vk, D.h);
@@ -683,14 +695,10 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     vg.cpb = D.cpb_res;
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
-    bool done = false;
-    if constexpr (std::is_same<T, double>::value) {
-        if (c.gen) {
-            launch_residual15(s, vg, ig, gen15v(D, v, -1), v.u, v.b, v.r, nullptr);
-            done = true;
-        }
-    }
-    if (!done) launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
+    if (c.gen)
+        launch_residual15<T, T>(s, vg, ig, gen15v(D, v, -1), v.u, v.b, v.r, nullptr);
+    else
+        launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
     const IfcGeom igp = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
@@ -707,11 +715,8 @@ void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t 
     VolGeom vg = vgeom(D, v.vd, v.nvol, false);
     vg.cpb = D.cpb_res;
     const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
-    int nb = -1;
-    if constexpr (std::is_same<TO, double>::value) {
-        if (c.gen) nb = launch_residual15(s, vg, ig, gen15v(D, v, -1), v.u, v.b, rout, V.partial);
-    }
-    if (nb < 0) nb = launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
+    const int nb = c.gen ? launch_residual15<double, TO>(s, vg, ig, gen15v(D, v, -1), v.u, v.b, rout, V.partial)
+                         : launch_residual<double, TO>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, rout, V.partial);
     if (nb > 0)
         launch_reduce(s, V.partial, nb, dst);
     else
@@ -1041,6 +1046,10 @@ int gen_weights(hhgr_ctx &c) {
         G.m = D.m;
         launch_gen_weights(c.stream, vgeom(D, D.vd_all, c.n_tets, true), c.tetinfo, G, D.wv, D.n_slots);
         launch_gen_ifc_weights(c.stream, D.n_ifc, D.ifc_xyz, G, D.wi15);
+        if (c.mixed) {
+            launch_cast<double, float>(c.stream, D.wv, D.wvf, 8 * D.n_slots);
+            launch_cast<double, float>(c.stream, D.wi15, D.wi15f, 15LL * D.n_ifc);
+        }
         if (l == c.Lc) launch_gen_coarse_vals(c.stream, c.cn, c.cpos, c.ccol15, G, c.cval15);
     }
     CHKLAUNCH();
@@ -1386,6 +1395,12 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
     if (!c->vk) {
         coarse_stencils(tp, host_xyz, cval);
         rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
+        if (c->mixed)
+            for (int l = c->Lc; l <= c->L; l++) {
+                LevelDev &D = c->lev[l];
+                launch_cast<double, float>(c->stream, D.w15, D.w15f, 15LL * c->n_tets);
+                launch_cast<double, float>(c->stream, D.wtab, D.wtabf, 15LL * D.wtab_cap);
+            }
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     if (rc) return rc;

@@ -437,20 +437,33 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
 // ---------------------------------------------------------------------------
 // general macro meshes: 15-point stencils (see Gen15)
 // ---------------------------------------------------------------------------
+// stencil tables in the value type of the pass
+template <typename T>
+__device__ __forceinline__ const T *gsel(const double *d, const float *f);
+template <>
+__device__ __forceinline__ const double *gsel<double>(const double *d, const float *) {
+    return d;
+}
+template <>
+__device__ __forceinline__ const float *gsel<float>(const double *, const float *f) {
+    return f;
+}
+
 // A u at interface master t (diag: its diagonal entry); VK: the master's own
 // 15 entries (per-element k, or the intact side of a Dirichlet-Neumann
 // recovery), else its primitive's stencil
-template <bool VK>
-__device__ __forceinline__ double master_Au(const IfcGeom &ig, const Gen15 &g, const double *__restrict__ u, int t,
-                                            double uo, double &diag) {
-    double acc = 0.0;
+template <typename T, bool VK>
+__device__ __forceinline__ T master_Au(const IfcGeom &ig, const Gen15 &g, const T *__restrict__ u, int t, T uo,
+                                       T &diag) {
+    T acc = T(0);
     if (VK) {
-        diag = g.wi15[t];
+        const T *wi = gsel<T>(g.wi15, g.wi15f);
+        diag = wi[t];
 #pragma unroll
         for (int n = 1; n < 15; n++)
-            acc += g.wi15[(long long)n * ig.stride + t] * u[g.nb15[(long long)n * ig.stride + t]];
+            acc += wi[(long long)n * ig.stride + t] * u[g.nb15[(long long)n * ig.stride + t]];
     } else {
-        const double *w = g.wtab + 15LL * g.sid[t];
+        const T *w = gsel<T>(g.wtab, g.wtabf) + 15LL * g.sid[t];
         diag = w[0];
 #pragma unroll
         for (int n = 1; n < 15; n++) acc += w[n] * u[g.nb15[(long long)n * ig.stride + t]];
@@ -461,27 +474,27 @@ __device__ __forceinline__ double master_Au(const IfcGeom &ig, const Gen15 &g, c
 // A u at a volume node of tetrahedron d.tet (c0: its slot in the closure);
 // VK: forward edge n = 2e + 1 is weight e at the node's own slot, backward
 // edge n = 2e + 2 is weight e at the neighbour's slot
-template <bool VK>
-__device__ __forceinline__ double volume_Au(const VolGeom &vg, const Gen15 &g, const VolDesc &d, const LNode &nd,
-                                            const double *__restrict__ uv, int &c0, double &uo, double &diag) {
+template <typename T, bool VK>
+__device__ __forceinline__ T volume_Au(const VolGeom &vg, const Gen15 &g, const VolDesc &d, const LNode &nd,
+                                       const T *__restrict__ uv, int &c0, T &uo, T &diag) {
     const int4 *e4 = (const int4 *)(g.rowN15 + 16 * ((long long)((nd.i + nd.k) & 1) * vg.nrows + nd.r));
     const int4 E0 = e4[0], E1 = e4[1], E2 = e4[2], E3 = e4[3];
     const int t = nd.i >> 1;
     const int sl[15] = {E0.x, E0.y, E0.z, E0.w, E1.x, E1.y, E1.z, E1.w, E2.x, E2.y, E2.z, E2.w, E3.x, E3.y, E3.z};
     c0 = sl[0] + t;
     uo = uv[c0];
-    double acc = 0.0;
+    T acc = T(0);
     if (VK) {
-        const double *W = g.wv + d.w;
+        const T *W = gsel<T>(g.wv, g.wvf) + d.w;
         diag = W[7 * g.ws + c0];
 #pragma unroll
         for (int n = 1; n < 15; n++) {
             const int sn = sl[n] + t;
-            const double w = (n & 1) ? W[((n - 1) >> 1) * g.ws + c0] : W[((n - 2) >> 1) * g.ws + sn];
+            const T w = (n & 1) ? W[((n - 1) >> 1) * g.ws + c0] : W[((n - 2) >> 1) * g.ws + sn];
             acc += w * uv[sn];
         }
     } else {
-        const double *w = g.w15 + 15LL * d.tet;
+        const T *w = gsel<T>(g.w15, g.w15f) + 15LL * d.tet;
         diag = w[0];
 #pragma unroll
         for (int n = 1; n < 15; n++) acc += w[n] * uv[sl[n] + t];
@@ -490,9 +503,9 @@ __device__ __forceinline__ double volume_Au(const VolGeom &vg, const Gen15 &g, c
 }
 
 // VKV: per-node volume weights (wv), VKI: per-master entries (wi15)
-template <bool VKV, bool VKI>
-__global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, double *__restrict__ u,
-                                                  const double *__restrict__ b, double omega) {
+template <typename T, bool VKV, bool VKI>
+__global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, T *__restrict__ u,
+                                                  const T *__restrict__ b, T omega) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int q = (int)(f * blockDim.x + threadIdx.x);
@@ -500,10 +513,10 @@ __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 
         const int t = g.ifcq[q];
         if (ig.frozen && ig.frozen[t]) return;
         const long long sl = ig.base + t;
-        const double uo = u[sl];
-        double diag;
-        const double Au = master_Au<VKI>(ig, g, u, t, uo, diag);
-        const double un = uo + omega * (b[sl] - Au) / diag;
+        const T uo = u[sl];
+        T diag;
+        const T Au = master_Au<T, VKI>(ig, g, u, t, uo, diag);
+        const T un = uo + omega * (b[sl] - Au) / diag;
         u[sl] = un;
         if (ig.gptr)
             for (int gq = ig.gptr[t]; gq < ig.gptr[t + 1]; gq++) u[ig.gidx[gq]] = un;
@@ -514,17 +527,18 @@ __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 
     LNode nd;
     if (!list_node<1>(vg, blk, per_vol, 0, nd)) return;
     const VolDesc d = vg.vd[nd.v];
-    double *uv = u + d.vec;
+    T *uv = u + d.vec;
     int c0;
-    double uo, diag;
-    const double Au = volume_Au<VKV>(vg, g, d, nd, uv, c0, uo, diag);
+    T uo, diag;
+    const T Au = volume_Au<T, VKV>(vg, g, d, nd, uv, c0, uo, diag);
     uv[c0] = uo + omega * ((b + d.vec)[c0] - Au) / diag;
 }
 
-template <bool WRITE, bool NORM, bool VKV, bool VKI>
-__global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen15 g, int nib,
-                                                    const double *__restrict__ u, const double *__restrict__ b,
-                                                    double *__restrict__ r, double *__restrict__ partial) {
+// r = b - A u in the value type T, written as TO
+template <typename T, typename TO, bool WRITE, bool NORM, bool VKV, bool VKI>
+__global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, const T *__restrict__ u,
+                                                    const T *__restrict__ b, TO *__restrict__ r,
+                                                    double *__restrict__ partial) {
     __shared__ double sh[64];
     const unsigned f = blockIdx.x;
     double acc2 = 0.0;
@@ -532,10 +546,10 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
         if (t < ig.i1 && !(ig.frozen && ig.frozen[t])) {
             const long long sl = ig.base + t;
-            double diag;
-            const double res = b[sl] - master_Au<VKI>(ig, g, u, t, u[sl], diag);
-            if (WRITE) r[sl] = res;
-            acc2 = res * res;
+            T diag;
+            const T res = b[sl] - master_Au<T, VKI>(ig, g, u, t, u[sl], diag);
+            if (WRITE) r[sl] = (TO)res;
+            acc2 = (double)res * (double)res;
         }
     } else {
         const unsigned per_vol = list_blocks_per_vol<1>(vg);
@@ -544,11 +558,11 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
         if (list_node<1>(vg, blk, per_vol, 0, nd)) {
             const VolDesc d = vg.vd[nd.v];
             int c0;
-            double uo, diag;
-            const double Au = volume_Au<VKV>(vg, g, d, nd, u + d.vec, c0, uo, diag);
-            const double res = (b + d.vec)[c0] - Au;
-            if (WRITE) r[d.vec + c0] = res;
-            acc2 = res * res;
+            T uo, diag;
+            const T Au = volume_Au<T, VKV>(vg, g, d, nd, u + d.vec, c0, uo, diag);
+            const T res = (b + d.vec)[c0] - Au;
+            if (WRITE) r[d.vec + c0] = (TO)res;
+            acc2 = (double)res * (double)res;
         }
     }
     if (NORM) {
@@ -566,7 +580,7 @@ __global__ void __launch_bounds__(512) k_apply15(VolGeom vg, IfcGeom ig, Gen15 g
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
         if (t >= ig.i1) return;
         double diag;
-        y[ig.base + t] = master_Au<false>(ig, g, x, t, x[ig.base + t], diag);
+        y[ig.base + t] = master_Au<double, false>(ig, g, x, t, x[ig.base + t], diag);
         return;
     }
     const unsigned per_vol = list_blocks_per_vol<1>(vg);
@@ -576,7 +590,7 @@ __global__ void __launch_bounds__(512) k_apply15(VolGeom vg, IfcGeom ig, Gen15 g
     const VolDesc d = vg.vd[nd.v];
     int c0;
     double xo, diag;
-    const double Sx = volume_Au<false>(vg, g, d, nd, x + d.vec, c0, xo, diag);
+    const double Sx = volume_Au<double, false>(vg, g, d, nd, x + d.vec, c0, xo, diag);
     y[d.vec + c0] = Sx;
 }
 
@@ -1675,67 +1689,86 @@ void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, dou
     hipLaunchKernelGGL(k_ifc_weights, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, ifc_xyz, N, h, k, wi);
 }
 
-void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, double *u, const double *b,
+template <typename T>
+void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
                      double omega) {
     const int nib = g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0;
     const long long grid = nib + list_blocks(vg, 1);
     if (grid == 0) return;
+    const dim3 gd((unsigned)grid), bd(vg.bs);
     if (g.wv)
-        hipLaunchKernelGGL((k_colour15<true, true>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b,
-                           omega);
+        hipLaunchKernelGGL((k_colour15<T, true, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega);
     else if (g.wi15)
-        hipLaunchKernelGGL((k_colour15<false, true>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b,
-                           omega);
+        hipLaunchKernelGGL((k_colour15<T, false, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega);
     else
-        hipLaunchKernelGGL((k_colour15<false, false>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, g, nib, u, b,
-                           omega);
+        hipLaunchKernelGGL((k_colour15<T, false, false>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega);
 }
 
-template <bool VKV, bool VKI>
+template <typename T, typename TO, bool VKV, bool VKI>
 static void residual15(hipStream_t s, dim3 gd, dim3 bd, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, int nib,
-                       const double *u, const double *b, double *r, double *partial) {
+                       const T *u, const T *b, TO *r, double *partial) {
     if (r && partial)
-        hipLaunchKernelGGL((k_residual15<true, true, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        hipLaunchKernelGGL((k_residual15<T, TO, true, true, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
     else if (r)
-        hipLaunchKernelGGL((k_residual15<true, false, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        hipLaunchKernelGGL((k_residual15<T, TO, true, false, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
     else
-        hipLaunchKernelGGL((k_residual15<false, true, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
+        hipLaunchKernelGGL((k_residual15<T, TO, false, true, VKV, VKI>), gd, bd, 0, s, vg, ig, g, nib, u, b, r, partial);
 }
 
-int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const double *u,
-                      const double *b, double *r, double *partial) {
+template <typename T, typename TO>
+int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const T *u, const T *b,
+                      TO *r, double *partial) {
     const int nib = ifc_blocks(ig, vg.bs);
     const long long grid = nib + list_blocks(vg, 1);
     if (grid == 0) return 0;
     const dim3 gd((unsigned)grid), bd(vg.bs);
     if (g.wv)
-        residual15<true, true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
+        residual15<T, TO, true, true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     else if (g.wi15)
-        residual15<false, true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
+        residual15<T, TO, false, true>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     else
-        residual15<false, false>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
+        residual15<T, TO, false, false>(s, gd, bd, vg, ig, g, nib, u, b, r, partial);
     return (int)grid;
 }
 
+template void launch_colour15<double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, double *,
+                                      const double *, double);
+template void launch_colour15<float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, float *,
+                                     const float *, double);
+template int launch_residual15<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
+                                               const double *, const double *, double *, double *);
+template int launch_residual15<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
+                                              const double *, const double *, float *, double *);
+template int launch_residual15<float, float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
+                                             const float *, const float *, float *, double *);
+
+template <typename T>
 void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
-                         const unsigned char *frozen, const double *b, double *u, const int *cptr, const int *cidx,
+                         const unsigned char *frozen, const T *b, T *u, const int *cptr, const int *cidx,
                          double rtol, int maxit, int *iters) {
     // 14 off-diagonal entries per row stay in registers: at most 2 rows per
     // lane (more spill to scratch), so above 128 unknowns one row per thread
     if (n <= 64)
-        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 1, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
-                           cptr, cidx, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_coarse_pcg_wave<T, 1, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
     else if (n <= 128)
-        hipLaunchKernelGGL((k_coarse_pcg_wave<double, 2, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u,
-                           cptr, cidx, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_coarse_pcg_wave<T, 2, 14>), dim3(1), dim3(64), 0, s, n, slot, col, val, frozen, b, u, cptr,
+                           cidx, rtol, maxit, iters);
     else if (n <= 1024) {
         const int bs = n <= 256 ? 256 : n <= 512 ? 512 : 1024;
-        hipLaunchKernelGGL((k_coarse_pcg<double, 1, 14>), dim3(1), dim3(bs), 0, s, n, slot, col, val, frozen, b, u, cptr,
-                           cidx, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_coarse_pcg<T, 1, 14>), dim3(1), dim3(bs), 0, s, n, slot, col, val, frozen, b, u, cptr, cidx,
+                           rtol, maxit, iters);
     } else
-        hipLaunchKernelGGL((k_coarse_pcg<double, 2, 14>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr,
+        hipLaunchKernelGGL((k_coarse_pcg<T, 2, 14>), dim3(1), dim3(1024), 0, s, n, slot, col, val, frozen, b, u, cptr,
                            cidx, rtol, maxit, iters);
 }
+
+template void launch_coarse_pcg15<double>(hipStream_t, int, const long long *, const int *, const double *,
+                                          const unsigned char *, const double *, double *, const int *, const int *,
+                                          double, int, int *);
+template void launch_coarse_pcg15<float>(hipStream_t, int, const long long *, const int *, const double *,
+                                         const unsigned char *, const float *, float *, const int *, const int *,
+                                         double, int, int *);
 
 void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const Gen15 &g, const double *b,
                            double *u) {

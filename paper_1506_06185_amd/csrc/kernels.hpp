@@ -65,6 +65,8 @@ struct Gen15 {
     const double *wv = nullptr;
     long long ws = 0;
     const double *wi15 = nullptr;
+    // FP32 copies of w15, wtab, wv, wi15 (mixed precision; nullptr otherwise)
+    const float *w15f = nullptr, *wtabf = nullptr, *wvf = nullptr, *wi15f = nullptr;
 };
 
 // Per-element coefficient on a general macro mesh: k of the level's elements
@@ -162,15 +164,18 @@ void launch_vol_weights(hipStream_t s, const VolGeom &vfull, const int *tetinfo,
 void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, double h, const double *k, double *wi);
 // general macro meshes: one SOR pass over one of the 4 classes (vg lists its
 // interior nodes, g.ifcq its masters; ig gives base, stride, ghosts, frozen)
-void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, double *u, const double *b,
+template <typename T>
+void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
                      double omega);
 // general macro meshes: r = b - A u over the interior list of vg and every
 // master of ig (r and/or partial sums of r^2 per block, as launch_residual)
-int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const double *u,
-                      const double *b, double *r, double *partial);
+template <typename T, typename TO>
+int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const T *u, const T *b,
+                      TO *r, double *partial);
 // coarsest level of a general macro mesh: Jacobi-PCG with 15 entries per row
+template <typename T>
 void launch_coarse_pcg15(hipStream_t s, int n, const long long *slot, const int *col, const double *val,
-                         const unsigned char *frozen, const double *b, double *u, const int *cptr, const int *cidx,
+                         const unsigned char *frozen, const T *b, T *u, const int *cptr, const int *cidx,
                          double rtol, int maxit, int *iters);
 // local coarsest level of a general macro mesh: u = b / diagonal at the single interior node
 void launch_local_coarse15(hipStream_t s, const VolDesc *vd, int nvol, int slot, const Gen15 &g, const double *b,

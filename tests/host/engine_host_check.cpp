@@ -111,9 +111,12 @@ int main() {
         d.level = 5;
         d.general_geometry = 1;
         hhgr_desc bad = d;
-        bad.precision = HHGR_MIXED;
+        bad.general_geometry = 2;
         size_t bytes = 0;
-        CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_EINVAL, "general + mixed rejected");
+        CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_EINVAL, "general_geometry 2 rejected");
+        bad = d;
+        bad.precision = HHGR_MIXED;
+        CHECK(hhgr_workspace_bytes(&bad, &bytes) == HHGR_OK, "general + mixed sized");
         CHECK(hhgr_workspace_bytes(&d, &bytes) == HHGR_OK, "general workspace");
         void *ws = std::aligned_alloc(256, (bytes + 255) / 256 * 256);
         hhgr_ctx *g = nullptr;
@@ -159,6 +162,23 @@ int main() {
         hhgr_batch_destroy(gb);
         hhgr_destroy(g);
         std::free(ws);
+        {
+            // mixed precision: FP32 copies of the stencil tables
+            xyz[3 * 13] = 0.5;  // the centre vertex back inside
+            hhgr_desc dm = d;
+            dm.precision = HHGR_MIXED;
+            size_t bm = 0;
+            CHECK(hhgr_workspace_bytes(&dm, &bm) == HHGR_OK, "general mixed workspace");
+            void *wm = std::aligned_alloc(256, (bm + 255) / 256 * 256);
+            hhgr_ctx *gm = nullptr;
+            CHECK(hhgr_create(&dm, wm, bm, nullptr, &gm) == HHGR_OK, "general mixed create: %s", hhgr_last_error());
+            CHECK(hhgr_set_geometry(gm, xyz.data()) == HHGR_OK, "general mixed geometry");
+            CHECK(hhgr_set_rhs(gm, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "general mixed rhs");
+            CHECK(hhgr_vcycle(gm, 2, &rr) == HHGR_OK, "general mixed vcycle: %s", hhgr_last_error());
+            CHECK(hhgr_recover_dd(gm, t2, 2, 1, 2) == HHGR_OK, "general mixed dd: %s", hhgr_last_error());
+            hhgr_destroy(gm);
+            std::free(wm);
+        }
         // variable coefficient: weights once both the geometry and k are set
         d.variable_coeff = 1;
         CHECK(hhgr_workspace_bytes(&d, &bytes) == HHGR_OK, "general vk workspace");

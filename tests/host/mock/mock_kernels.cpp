@@ -76,18 +76,37 @@ void launch_vol_weights(hipStream_t, const VolGeom &, const int *, int, int, dou
 void launch_ifc_weights(hipStream_t, int, const int *, int, double, const double *, double *) {}
 void launch_coarse_vals(hipStream_t, int, const int *, const int *, int, double, const double *, double *) {}
 void launch_dirichlet_load(hipStream_t, int, double, const double *, const double *, double *) {}
-void launch_colour15(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, double *, const double *, double) {}
-int launch_residual15(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const Gen15 &, const double *, const double *,
-                      double *, double *partial) {
+template <typename T>
+void launch_colour15(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, T *, const T *, double) {}
+template <typename T, typename TO>
+int launch_residual15(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const Gen15 &, const T *, const T *, TO *,
+                      double *partial) {
     const long long nb = ifc_blocks_of(ig, vg.bs) + list_blocks_of(vg, 1);
     if (partial)
         for (long long q = 0; q < nb; q++) partial[q] = q == 0 ? g_mock_res2 : 0.0;
     return (int)nb;
 }
+template <typename T>
 void launch_coarse_pcg15(hipStream_t, int, const long long *, const int *, const double *, const unsigned char *,
-                         const double *, double *, const int *, const int *, double, int, int *iters) {
+                         const T *, T *, const int *, const int *, double, int, int *iters) {
     if (iters) *iters = 0;
 }
+template void launch_colour15<double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, double *,
+                                      const double *, double);
+template void launch_colour15<float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, float *,
+                                     const float *, double);
+template int launch_residual15<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
+                                               const double *, const double *, double *, double *);
+template int launch_residual15<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
+                                              const double *, const double *, float *, double *);
+template int launch_residual15<float, float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
+                                             const float *, const float *, float *, double *);
+template void launch_coarse_pcg15<double>(hipStream_t, int, const long long *, const int *, const double *,
+                                          const unsigned char *, const double *, double *, const int *, const int *,
+                                          double, int, int *);
+template void launch_coarse_pcg15<float>(hipStream_t, int, const long long *, const int *, const double *,
+                                         const unsigned char *, const float *, float *, const int *, const int *,
+                                         double, int, int *);
 void launch_local_coarse15(hipStream_t, const VolDesc *, int, int, const Gen15 &, const double *, double *) {}
 void launch_gen_weights(hipStream_t, const VolGeom &, const int *, const GenK &, double *, long long) {}
 void launch_gen_ifc_weights(hipStream_t, int, const int *, const GenK &, double *) {}

@@ -447,3 +447,35 @@ def test_autotuned_shapes_give_the_same_iterates(dev, hh):
     uo, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
     assert rel(Nn(ctx.get_solution()), uo) < 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("vk", [False, True])
+def test_mixed_precision(dev, hh, vk):
+    """FP32 cycles inside FP64 refinement on a general macro mesh: the first
+    step equals the oracle's FP32 step to FP32 rounding, the refined solution
+    reaches the FP64 oracle solution to 1e-9, and a fault recovered by
+    Dirichlet-Dirichlet recovery (intact side in mixed steps) as well."""
+    n_sub, level, seed = 2, 5, 5
+    print(f"\n[general mixed] variable_k={vk}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=9) if vk else None
+    p = problem_k(n_sub, level, seed, 9) if vk else problem(n_sub, level, seed)
+    b = inputs.uniform_load(n_sub, level, seed=0)
+    ctx = context(hh, dev, n_sub, level, seed, k=k, precision="mixed")
+    ctx.set_rhs(T(b, dev))
+    ctx.vcycle(1)
+    u1, _, _ = p.solve_mixed(b, rtol=0.0, max_steps=1)
+    assert rel(Nn(ctx.get_solution()), u1) < 1e-5
+    cyc, rr, hist = ctx.solve(1e-12, 80)
+    u64, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+    err = np.linalg.norm(Nn(ctx.get_solution()) - u64) / np.linalg.norm(u64)
+    print(f"  {cyc + 1} steps, error vs FP64 oracle {err:.2e}", flush=True)
+    assert err < 1e-9, err
+    tets = [inputs.fault_tet(n_sub, seed=2)]
+    ctx.set_solution(T(np.zeros_like(b), dev))
+    ctx.vcycle(3)
+    ctx.inject_fault(tets[0])
+    ctx.recover_dd(tets, 2, 3)
+    cyc, rr, hist = ctx.solve(1e-12, 80)
+    err = np.linalg.norm(Nn(ctx.get_solution()) - u64) / np.linalg.norm(u64)
+    assert err < 1e-9, err
+    ctx.close()
