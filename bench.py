@@ -26,8 +26,8 @@ Further legs, each in its own object of the JSON line:
             all as concurrent branches of captured HIP graphs;
   general_mesh  the headline job on a general macro mesh: the 27 macro
             vertices moved (inputs.perturbed_vertices, seed 0), 15-point
-            stencils, 4-colour SOR, load b ~ U[-1,1]; its roofline is the
-            finest-level FP64 class pass.
+            stencils, 4-colour SOR, load b ~ U[-1,1], in FP64 and in mixed
+            precision; its roofline is the finest-level FP64 class pass.
 """
 from __future__ import annotations
 
@@ -194,7 +194,35 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph, tune_cache):
     dt = time.perf_counter() - t0
     launches, mean_ms, alg_bytes = ctx.kernel_stats() if not graph else (0, 0.0, 0.0)
     ctx.kernel_timing(False)
+    u64 = ctx.get_solution()
     ctx.close()
+    # the same job in mixed precision (FP32 class passes inside FP64 refinement)
+    cm = hh.Context(device=dev, n_sub=n_sub, level=level, general_geometry=True, precision="mixed")
+    cm.set_geometry(inputs.perturbed_vertices(n_sub, seed=0))
+    cm.autotune(tune_cache)
+    if graph:
+        cm.set_graph(True)
+    ctx = cm
+    for _ in range(warmup):
+        job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    totm, relm = 0, None
+    for _ in range(steps):
+        cyc, relm = job()
+        totm += cyc
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    um = cm.get_solution()
+    cm.close()
+    mixed = {
+        "value": round(b.numel() * totm / dtm / 1e6, 1),
+        "unit": "MDoF/s",
+        "ms_per_step": round(1e3 * dtm / steps, 3),
+        "refinement_steps_per_job": totm // steps,
+        "rel_diff_vs_fp64_job": float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64)),
+        "rel_res": relm,
+    }
     roofline = None
     if launches > 0:
         achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
@@ -223,6 +251,7 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph, tune_cache):
         "final_rel_res": rel,
         "set_geometry_s": round(t_geom, 3),
         "roofline": roofline,
+        "mixed": mixed,
     }
 
 
