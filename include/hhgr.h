@@ -119,9 +119,10 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * HHGR_RHS_DIRICHLET takes the boundary values g at the moved boundary nodes
  * and sets b_i = -sum of A_ij g_j over the boundary neighbours j (after this
  * call, and after hhgr_set_coeff with variable_coeff = 1; ESTATE otherwise).
- * EINVAL for an inverted or degenerate macro tetrahedron; may be called again
- * to move the vertices (a right-hand side from Dirichlet data is not
- * recomputed).  The recoveries work as on the cube; the intact side of a
+ * Cycles, solves and recoveries return ESTATE until this call.  EINVAL for
+ * an inverted or degenerate macro tetrahedron (the context keeps its previous
+ * geometry); may be called again to move the vertices (a right-hand side set
+ * from Dirichlet data or nodal values before is not recomputed).  The recoveries work as on the cube; the intact side of a
  * Dirichlet-Neumann recovery takes the 15-point entries assembled over the
  * elements of intact macro tetrahedra.  HHGR_RHS_NODAL_F, hhgr_mass_apply and
  * hhgr_adjoint_grad use the consistent P1 mass matrix and the element
