@@ -1377,12 +1377,17 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
     // element matrices: per-node stencils of a variable k and the intact side
     // of a Dirichlet-Neumann recovery are computed from them on the GPU
     element_matrices(tp, host_xyz, kel);
-    rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
     // k = 1: the stiffness stencils of every level; the finest level's mass
-    // stencils (and master ids) in either case
-    for (int l = c->vk ? c->L : c->Lc; l <= c->L; l++) {
+    // stencils (and master ids) in either case.  Everything is computed
+    // before the first copy, so a failure leaves the context as it was.
+    const int l0 = c->vk ? c->L : c->Lc;
+    for (int l = l0; l <= c->L; l++) {
         e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
         if (!e.empty()) return fail(HHGR_EINVAL, e);
+    }
+    if (!c->vk) coarse_stencils(tp, host_xyz, cval);
+    rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
+    for (int l = l0; l <= c->L; l++) {
         LevelDev &D = c->lev[l];
         rc = rc ? rc : upload(*c, D.w15, G[l].w15.data(), G[l].w15.size() * sizeof(double));
         rc = rc ? rc : upload(*c, D.wtab, G[l].wtab.data(), G[l].wtab.size() * sizeof(double));
@@ -1393,7 +1398,6 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
         }
     }
     if (!c->vk) {
-        coarse_stencils(tp, host_xyz, cval);
         rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
         if (c->mixed)
             for (int l = c->Lc; l <= c->L; l++) {
