@@ -867,8 +867,9 @@ int dd_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     std::vector<unsigned char> cf(cs.n, 0);
     for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? (unsigned char)isf[cs.tet[q]] : frz[c.Lc][cs.ifc[q]];
     rc = rc ? rc : upload(c, c.cfrozen, cf.data(), cf.size());
-    if (rc) return rc;
+    // copies already queued read the host vectors above: wait before any return
     HIPCHK(hipStreamSynchronize(c.stream));
+    if (rc) return rc;
     set_loc(c, ft);
     for (int t : ft) restore_tet(c, t, c.stream);
     for (int l = c.Lc; l <= c.L; l++) {
@@ -931,7 +932,10 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
         D.n_masked = (int)vds[l].size();
         rc = rc ? rc : upload(c, D.vd_masked, vds[l].data(), vds[l].size() * sizeof(VolDesc));
     }
-    if (rc) return rc;
+    if (rc) {
+        hipStreamSynchronize(c.stream);  // queued copies read vds
+        return rc;
+    }
     // an interface node lies in the closures of the tetrahedra holding its
     // ghost copies: frozen if all of them are faulty, on the interface Gamma
     // if some are; ghost copies in faulty closures are not written
@@ -952,7 +956,10 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     std::vector<unsigned char> cf(cs.n, 0);
     for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? isf[cs.tet[q]] : frc[cs.ifc[q]];
     rc = upload(c, c.cfrozen, cf.data(), cf.size());
-    if (rc) return rc;
+    if (rc) {
+        hipStreamSynchronize(c.stream);  // queued copies read vds and cf
+        return rc;
+    }
     // intact-side operators on every level
     if (c.gen) {
         GenK G;
@@ -1267,7 +1274,7 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
 
 void hhgr_destroy(hhgr_ctx *c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    hipStreamSynchronize(c->stream);  // also the legacy default stream (nullptr)
     if (c->stream2) {
         hipStreamSynchronize(c->stream2);
         hipStreamDestroy(c->stream2);
