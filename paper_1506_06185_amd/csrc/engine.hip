@@ -629,9 +629,10 @@ void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     }
 }
 
-// one red-black sweep in place: two colour passes
+// one red-black sweep in place: two colour passes.  pr: the red pass first
+// adds the coarse-grid correction to its nodes (the black nodes hold theirs)
 template <typename T>
-void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
+void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, const Prol<T> *pr = nullptr) {
     if (c.gen) {
         sweep15<T>(c, V, l, zero, s);
         return;
@@ -643,6 +644,10 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
         const IfcGeom ig = v.ifc ? igeom_v(D, v, colour == 0 ? 0 : D.n_ifc_red, colour == 0 ? D.n_ifc_red : D.n_ifc,
                                            true)
                                  : ig_none();
+        if (pr && colour == 0) {
+            launch_colour_prol<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, *pr);
+            continue;
+        }
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
         launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero, zero && colour == 0);
@@ -651,8 +656,9 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
 }
 
 template <typename T>
-void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s) {
-    for (int k = 0; k < nsweeps; k++) sweep(c, V, l, zero && k == 0, s);
+void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s,
+            const Prol<T> *pr = nullptr) {
+    for (int k = 0; k < nsweeps; k++) sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr);
 }
 
 template <typename T>
@@ -701,10 +707,26 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
         launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
-    const IfcGeom igp = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
-    vg.cpb = D.cpb_prl;
-    launch_prolong<T>(s, vg, vc.vd, Dc.rowC, Dc.M, igp, D.prl, vc.u, v.u);
-    smooth(c, V, l, c.d.nu_post, false, s);
+    // u += P e_c.  With a red-black post-smoother only the black nodes are
+    // corrected here; the first red pass corrects its own nodes as it reads
+    // them (it reads nothing else of its colour), so no red value is written
+    // twice.
+    const bool fuse = !c.gen && c.d.nu_post > 0;
+    const IfcGeom igp = v.ifc ? igeom_v(D, v, fuse ? D.n_ifc_red : 0, D.n_ifc, true) : ig_none();
+    VolGeom vgp = vgeom(D, v.vd, v.nvol, false, -1, fuse ? 1 : -1);
+    vgp.cpb = D.cpb_prl;
+    launch_prolong<T>(s, vgp, vc.vd, Dc.rowC, Dc.M, igp, D.prl, vc.u, v.u);
+    if (fuse) {
+        Prol<T> pr;
+        pr.vdc = vc.vd;
+        pr.cC = Dc.rowC;
+        pr.Mc = Dc.M;
+        pr.prl = D.prl;
+        pr.ec = vc.u;
+        smooth(c, V, l, c.d.nu_post, false, s, &pr);
+    } else {
+        smooth(c, V, l, c.d.nu_post, false, s);
+    }
 }
 
 // ||b - A u||^2 (or with TO output: r = b - A u written as TO) on level L of a view

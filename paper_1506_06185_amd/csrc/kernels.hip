@@ -160,18 +160,49 @@ inline int ifc_blocks(const IfcGeom &ig, int bs) {
 }
 
 // ---------------------------------------------------------------------------
+// linear interpolation of the coarse-grid correction (P e_c)
+// ---------------------------------------------------------------------------
+// index direction of the coarse edge bisected by a fine node with parity code
+// (i&1) | (j&1)<<1 | (k&1)<<2
+__device__ __constant__ int kParDir[8][3] = {{0, 0, 0},  {1, 0, 0}, {0, 1, 0},  {-1, 1, 0},
+                                             {0, 0, 1},  {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
+
+// (P e_c) at fine interior node n of a closure whose coarse closure holds ev:
+// the coarse value where the node coincides with a coarse node, else the mean
+// of the end points of the coarse edge it bisects
+template <typename T>
+__device__ __forceinline__ T coarse_corr(const T *__restrict__ ev, const int2 *__restrict__ cC, int Mc, const LNode &n) {
+    const int code = (n.i & 1) | ((n.j & 1) << 1) | ((n.k & 1) << 2);
+    const int di = kParDir[code][0], dj = kParDir[code][1], dk = kParDir[code][2];
+    // coarse end points of the bisected edge (the same node twice for code 0)
+    const T e1 = ev[lslot(cC, Mc, (n.i - di) >> 1, (n.j - dj) >> 1, (n.k - dk) >> 1)];
+    const T e2 = ev[lslot(cC, Mc, (n.i + di) >> 1, (n.j + dj) >> 1, (n.k + dk) >> 1)];
+    return code == 0 ? e1 : T(0.5) * (e1 + e2);
+}
+
+// (P e_c) at interface master t from its two coarse slots (equal where the
+// master coincides with a coarse node)
+template <typename T>
+__device__ __forceinline__ T coarse_corr_ifc(const T *__restrict__ ec, const int *__restrict__ prl, int stride, int t) {
+    return T(0.5) * (ec[prl[t]] + ec[prl[(long long)stride + t]]);
+}
+
+// ---------------------------------------------------------------------------
 // red-black SOR colour pass
 // ---------------------------------------------------------------------------
-template <typename T, bool VK, bool OWN0, bool NB0, int CPB>
+// PR: each node first receives its coarse-grid correction (the pass then
+// runs on u + P e_c at its own colour; the other colour already holds it)
+template <typename T, bool VK, bool OWN0, bool NB0, bool PR, int CPB>
 __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib, T *__restrict__ u,
-                                                const T *__restrict__ b, Weights<T> w, T h, T omega, T om_d) {
+                                                const T *__restrict__ b, Weights<T> w, T h, T omega, T om_d,
+                                                Prol<T> p) {
     const unsigned f = blockIdx.x;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
         if (t >= ig.i1) return;
         if (ig.frozen && ig.frozen[t]) return;
         const long long sl = ig.base + t;
-        const T uo = OWN0 ? T(0) : u[sl];
+        const T uo = OWN0 ? T(0) : PR ? u[sl] + coarse_corr_ifc(p.ec, p.prl, ig.stride, t) : u[sl];
         T acc = T(0), diag;
         // interface weights: variable k, or the intact-side stencils of a
         // Dirichlet-Neumann recovery (given also when k = 1)
@@ -216,7 +247,7 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
         const T *uv = u + d.vec;
         const Nb7 nb = nb7(vg, n);
         const int c0 = nb.c0;
-        const T uo = OWN0 ? T(0) : uv[c0];
+        const T uo = OWN0 ? T(0) : PR ? uv[c0] + coarse_corr(p.ec + p.vdc[n.v].vec, p.cC, p.Mc, n) : uv[c0];
         T res;
         if (VK) {
             const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
@@ -385,11 +416,6 @@ __global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__r
 // ---------------------------------------------------------------------------
 // prolongation u_f += P e_c (linear interpolation)
 // ---------------------------------------------------------------------------
-// index direction of the coarse edge bisected by a fine node with parity code
-// (i&1) | (j&1)<<1 | (k&1)<<2
-__device__ __constant__ int kParDir[8][3] = {{0, 0, 0},  {1, 0, 0}, {0, 1, 0},  {-1, 1, 0},
-                                             {0, 0, 1},  {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
-
 template <typename T, int CPB>
 __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__restrict__ vdc, const int2 *__restrict__ cC,
                                                  int Mc, IfcGeom ig, int nib, const int *__restrict__ prl,
@@ -400,7 +426,7 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
         if (t >= ig.i1) return;
         if (ig.frozen && ig.frozen[t]) return;
         const long long sl = ig.base + t;
-        const T v = uf[sl] + T(0.5) * (ec[prl[t]] + ec[prl[(long long)ig.stride + t]]);
+        const T v = uf[sl] + coarse_corr_ifc(ec, prl, ig.stride, t);
         uf[sl] = v;
         if (ig.gptr)
             for (int g = ig.gptr[t]; g < ig.gptr[t + 1]; g++) uf[ig.gidx[g]] = v;
@@ -418,14 +444,8 @@ __global__ void __launch_bounds__(512) k_prolong(VolGeom vf, const VolDesc *__re
         dst[q] = 0;
         LNode n;
         if (!list_node<CPB>(vf, blk, per_vol, q, n)) continue;
-        const T *ev = ec + vdc[n.v].vec;
         const long long sl = vf.vd[n.v].vec + lslot(vf.rowC, vf.M, n.i, n.j, n.k);
-        const int code = (n.i & 1) | ((n.j & 1) << 1) | ((n.k & 1) << 2);
-        const int di = kParDir[code][0], dj = kParDir[code][1], dk = kParDir[code][2];
-        // coarse end points of the bisected edge (the same node twice for code 0)
-        const T e1 = ev[lslot(cC, Mc, (n.i - di) >> 1, (n.j - dj) >> 1, (n.k - dk) >> 1)];
-        const T e2 = ev[lslot(cC, Mc, (n.i + di) >> 1, (n.j + dj) >> 1, (n.k + dk) >> 1)];
-        nv[q] = uf[sl] + (code == 0 ? e1 : T(0.5) * (e1 + e2));
+        nv[q] = uf[sl] + coarse_corr(ec + vdc[n.v].vec, cC, Mc, n);
         dst[q] = sl;
         ok[q] = true;
     }
@@ -1489,14 +1509,15 @@ void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, co
     const long long grid = nib + nvb;
     if (grid == 0) return;
     const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
+    const Prol<T> p;
 #define HHGR_COLOUR(VK, O0, N0)                                                                                 \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
-            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, \
-                               b, w, th, to, tod);                                                            \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, \
+                               nib, u, b, w, th, to, tod, p);                                                 \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, nib, u, \
-                               b, w, th, to, tod);                                                            \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, \
+                               nib, u, b, w, th, to, tod, p);                                                 \
     } while (0)
     if (vk) {
         if (own0 && nb0) HHGR_COLOUR(true, true, true);
@@ -1508,6 +1529,30 @@ void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, co
         else HHGR_COLOUR(false, false, false);
     }
 #undef HHGR_COLOUR
+}
+
+template <typename T>
+void launch_colour_prol(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w,
+                        bool vk, double h, double omega, const Prol<T> &p) {
+    const int nib = ifc_blocks(ig, vg.bs);
+    const long long nvb = list_blocks(vg);
+    const long long grid = nib + nvb;
+    if (grid == 0) return;
+    const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
+#define HHGR_COLOUR_PR(VK)                                                                                      \
+    do {                                                                                                       \
+        if (vg.cpb == 1)                                                                                       \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
+                               ig, nib, u, b, w, th, to, tod, p);                                             \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
+                               ig, nib, u, b, w, th, to, tod, p);                                             \
+    } while (0)
+    if (vk)
+        HHGR_COLOUR_PR(true);
+    else
+        HHGR_COLOUR_PR(false);
+#undef HHGR_COLOUR_PR
 }
 
 template <typename T, typename TO>
@@ -1880,6 +1925,10 @@ template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom 
                                     const Weights<double> &, bool, double, double, bool, bool);
 template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
                                    const Weights<float> &, bool, double, double, bool, bool);
+template void launch_colour_prol<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
+                                         const Weights<double> &, bool, double, double, const Prol<double> &);
+template void launch_colour_prol<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                        const Weights<float> &, bool, double, double, const Prol<float> &);
 template int launch_residual<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                              const double *, const Weights<double> &, bool, double, double *, double *);
 template int launch_residual<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,

@@ -93,6 +93,27 @@ template <typename T>
 void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w, bool vk,
                    double h, double omega, bool own0, bool nb0);
 
+// coarse-grid correction u += P e_c of the nodes of one colour, in the form
+// launch_prolong takes it (coarse volume descriptors in the fine view's
+// order, coarse row table and closure edge length, [2][n_ifc] coarse slots
+// per interface master, the coarse correction)
+template <typename T>
+struct Prol {
+    const VolDesc *vdc = nullptr;
+    const int2 *cC = nullptr;
+    int Mc = 0;
+    const int *prl = nullptr;
+    const T *ec = nullptr;
+};
+
+// colour pass that first adds the coarse-grid correction to each of its own
+// nodes (bitwise the value launch_prolong would have stored) and then
+// updates it.  Its neighbours are of the other colour and must already hold
+// their corrected values.
+template <typename T>
+void launch_colour_prol(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w,
+                        bool vk, double h, double omega, const Prol<T> &p);
+
 // r = b - A u on volume interiors and interface nodes; r (of type TO) may be
 // nullptr; partial (one double per block) receives block sums of r^2 if not
 // nullptr.  Returns the number of blocks launched.

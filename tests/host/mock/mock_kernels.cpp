@@ -24,6 +24,9 @@ static int ifc_blocks_of(const IfcGeom &ig, int bs) {
 template <typename T>
 void launch_colour(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
                    double, bool, bool) {}
+template <typename T>
+void launch_colour_prol(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
+                        double, const Prol<T> &) {}
 template <typename T, typename TO>
 int launch_residual(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const T *, const T *, const Weights<T> &, bool,
                     double, TO *, double *partial) {
@@ -131,6 +134,10 @@ template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom 
                                     const Weights<double> &, bool, double, double, bool, bool);
 template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
                                    const Weights<float> &, bool, double, double, bool, bool);
+template void launch_colour_prol<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
+                                         const Weights<double> &, bool, double, double, const Prol<double> &);
+template void launch_colour_prol<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                        const Weights<float> &, bool, double, double, const Prol<float> &);
 template int launch_residual<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                              const double *, const Weights<double> &, bool, double, double *, double *);
 template int launch_residual<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
