@@ -532,7 +532,7 @@ def main():
             "workload": f"poisson-kuhn-cube n_sub={n_sub} ({6 * n_sub ** 3} macro tets) level={level}: "
                         f"fault after 5 V(2,1) cycles, 3 local recovery cycles, solve to 1e-8",
             "unknowns": int(f_dev.numel()),
-            "smoother": "red-black SOR omega=1.25, V(2,1), coarse level 2 Jacobi-PCG",
+            "smoother": "red-black SOR omega=1.25, V(2,1), coarse level 2 solved with its dense inverse",
             "fault_tet": t_fault,
             "graph": bool(args.graph),
             "tuning": {str(k): {"block": v[0], "xcd_order": v[1], "nodes_per_thread": v[2]}

@@ -157,8 +157,11 @@ int hhgr_set_solution(hhgr_ctx *ctx, const double *dev_u);
 int hhgr_get_solution(const hhgr_ctx *ctx, double *dev_u);
 
 /* n multigrid V-cycles of the correction scheme (Sec. 2.1): red-black SOR
- * smoothing, restriction by the transpose of linear interpolation,
- * Jacobi-PCG on the coarsest level, linear interpolation of the correction.
+ * smoothing, restriction by the transpose of linear interpolation, the
+ * coarsest level solved to round-off (Jacobi-PCG to a relative residual of
+ * 1e-14; with k = 1 on the cube and at most 512 coarsest unknowns, a dense
+ * inverse factorised on the host at hhgr_create), linear interpolation of
+ * the correction.
  * With precision = HHGR_MIXED one cycle is one refinement step
  * u += V32(b - A u) with the residual and update in FP64.  rel_res_out
  * (optional) receives ||b - A u|| / ||b||.  ESTATE without a right-hand side. */
@@ -281,6 +284,7 @@ int hhgr_kernel_stats(hhgr_ctx *ctx, long long *launches, double *mean_ms, doubl
  *   op 4: out (level-1) = P^T in0               (restriction)
  *   op 5: out = in1 + P in0, in0 on level-1     (interpolation and correction)
  *   op 6: out = coarsest-level PCG solution for right-hand side in0 (level = coarse_level)
+ *   op 7: the same through the dense inverse (EINVAL where the context has none)
  * With general_geometry = 1, ops 1 and 2 are EINVAL, op 3 is one 4-class
  * sweep and op 8 + mask (mask 1..15) runs the passes of the classes whose
  * bits are set in mask, lowest class first.

@@ -48,6 +48,9 @@ int fail(int code, const std::string &msg) {
 constexpr int kBS[3] = {128, 256, 512};
 constexpr double kCoarseRtol = 1e-14;
 constexpr int kCoarseMaxit = 2000;
+// largest coarsest level (unknowns) solved with a precomputed dense inverse
+// (k = 1 on the cube; 512^2 FP64 = 2 MiB of workspace)
+constexpr int kDenseCoarseMax = 512;
 constexpr int kMaxLevels = 10;
 
 // bump allocator over the caller's workspace; with base == nullptr it only sizes
@@ -168,6 +171,10 @@ struct hhgr_ctx {
     double *cval = nullptr, *cval_dn = nullptr;
     unsigned char *cfrozen = nullptr, *dn_faulty = nullptr;
     int cn = 0;
+    // dense inverse of the unmasked coarsest-level operator (k = 1 on the
+    // cube, at most kDenseCoarseMax unknowns); the other operators use PCG
+    bool dense_coarse = false;
+    double *cinv = nullptr;
     // general macro meshes: 15-point coarsest-level operator
     bool gen = false, geom_set = false;
     int *ccol15 = nullptr;
@@ -350,6 +357,8 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.cval_dn = cv.take<double>(7 * (size_t)c.cn);
     c.dn_faulty = cv.take<unsigned char>(c.n_tets);
     c.citers = cv.take<int>(4);
+    c.dense_coarse = !c.gen && !c.vk && c.cn <= kDenseCoarseMax;
+    if (c.dense_coarse) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
@@ -678,6 +687,8 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     }
     if (V.local) {
         launch_local_coarse<T>(s, v.vd, v.nvol, D.lc_sl, v.b, v.u, v.w, c.vk, D.h);
+    } else if (c.dense_coarse && !V.cfrozen && !V.cval) {
+        launch_coarse_dense<T>(s, c.cn, c.cslot, c.cinv, v.b, v.u, c.cptr, c.cidx);
     } else {
         launch_coarse_pcg<T>(s, c.cn, c.cslot, c.ccol, V.cval ? V.cval : c.cval, V.cfrozen, v.b, v.u, c.cptr, c.cidx,
                              kCoarseRtol, kCoarseMaxit, c.citers);
@@ -1274,6 +1285,13 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     rc = rc ? rc : upload(*c, c->cslot, cs.slot.data(), cs.slot.size() * sizeof(long long));
     rc = rc ? rc : upload(*c, c->ccol, cs.col.data(), cs.col.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cval, c->cval_host.data(), c->cval_host.size() * sizeof(double));
+    if (c->dense_coarse) {
+        std::vector<double> inv;
+        if (coarse_inverse(cs.n, cs.col, cs.val, inv))
+            rc = rc ? rc : upload(*c, c->cinv, inv.data(), inv.size() * sizeof(double));
+        else
+            c->dense_coarse = false;
+    }
     rc = rc ? rc : upload(*c, c->cptr, cs.cptr.data(), cs.cptr.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cidx, cs.cidx.data(), cs.cidx.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cpos, cpos.data(), cpos.size() * sizeof(int));
@@ -1926,10 +1944,11 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
 int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *in1, double *out) {
     if (!c || !in0 || !out) return fail(HHGR_EINVAL, "null argument");
     const bool class_op = c->gen && op >= 9 && op <= 23;
-    if (l < c->Lc || l > c->L || op < 0 || (op > 6 && !class_op)) return fail(HHGR_EINVAL, "bad op or level");
+    if (l < c->Lc || l > c->L || op < 0 || (op > 7 && !class_op)) return fail(HHGR_EINVAL, "bad op or level");
     if (c->gen && (op == 1 || op == 2)) return fail(HHGR_EINVAL, "general_geometry: class passes are op 8 + class mask");
     if ((op == 4 || op == 5) && l <= c->Lc) return fail(HHGR_EINVAL, "transfer needs level > coarse_level");
-    if (op == 6 && l != c->Lc) return fail(HHGR_EINVAL, "coarse solve needs level = coarse_level");
+    if ((op == 6 || op == 7) && l != c->Lc) return fail(HHGR_EINVAL, "coarse solve needs level = coarse_level");
+    if (op == 7 && !c->dense_coarse) return fail(HHGR_EINVAL, "no dense coarsest-level inverse in this context");
     if ((op <= 3 || op == 5 || class_op) && !in1) return fail(HHGR_EINVAL, "null second input");
     if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
     if (c->gen && !c->geom_set && op != 4 && op != 5) return fail(HHGR_ESTATE, "no geometry set");
@@ -2015,6 +2034,11 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
         to_slots(in0, D.b, D);
         launch_coarse_pcg<double>(s, c->cn, c->cslot, c->ccol, c->cval, nullptr, D.b, D.u, c->cptr, c->cidx,
                                   kCoarseRtol, kCoarseMaxit, c->citers);
+        to_user(D.u, out, D);
+        break;
+    case 7:
+        to_slots(in0, D.b, D);
+        launch_coarse_dense<double>(s, c->cn, c->cslot, c->cinv, D.b, D.u, c->cptr, c->cidx);
         to_user(D.u, out, D);
         break;
     }

@@ -830,6 +830,24 @@ __global__ void __launch_bounds__(64) k_coarse_pcg_wave(int n, const long long *
     if (tid == 0 && iters) *iters = it;
 }
 
+// coarsest level with a precomputed dense inverse (row-major n x n): one
+// wavefront per unknown q computes x_q = sum_j inv[q][j] b_j in a fixed order
+// (the reduction leaves lane 63's total in every lane, so the master and its
+// ghost copies receive the same value)
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_dense(int n, const long long *__restrict__ slot,
+                                                      const double *__restrict__ inv, const T *__restrict__ b,
+                                                      T *__restrict__ u, const int *__restrict__ cptr,
+                                                      const int *__restrict__ cidx) {
+    const int q = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    if (q >= n) return;  // uniform over the wavefront
+    const double *a = inv + (long long)q * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc += a[j] * (double)b[slot[j]];
+    const T xv = (T)wave_sum_dpp(acc);
+    for (int c = cptr[q] + lane; c < cptr[q + 1]; c += 64) u[cidx[c]] = xv;
+}
+
 template <typename T, bool VK>
 __global__ void k_local_coarse(const VolDesc *__restrict__ vd, int nvol, int4 sl, const T *__restrict__ b,
                                T *__restrict__ u, Weights<T> w, T h) {
@@ -1641,6 +1659,14 @@ void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *c
 }
 
 template <typename T>
+void launch_coarse_dense(hipStream_t s, int n, const long long *slot, const double *inv, const T *b, T *u,
+                         const int *cptr, const int *cidx) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_coarse_dense<T>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, slot, inv, b, u, cptr,
+                       cidx);
+}
+
+template <typename T>
 void launch_local_coarse(hipStream_t s, const VolDesc *vd, int nvol, int4 sl, const T *b, T *u, const Weights<T> &w,
                          bool vk, double h) {
     if (nvol <= 0) return;
@@ -1949,6 +1975,10 @@ template void launch_coarse_pcg<double>(hipStream_t, int, const long long *, con
 template void launch_coarse_pcg<float>(hipStream_t, int, const long long *, const int *, const double *,
                                        const unsigned char *, const float *, float *, const int *, const int *, double,
                                        int, int *);
+template void launch_coarse_dense<double>(hipStream_t, int, const long long *, const double *, const double *,
+                                          double *, const int *, const int *);
+template void launch_coarse_dense<float>(hipStream_t, int, const long long *, const double *, const float *, float *,
+                                         const int *, const int *);
 template void launch_local_coarse<double>(hipStream_t, const VolDesc *, int, int4, const double *, double *,
                                           const Weights<double> &, bool, double);
 template void launch_local_coarse<float>(hipStream_t, const VolDesc *, int, int4, const float *, float *,

@@ -136,6 +136,13 @@ template <typename T>
 void launch_prolong(hipStream_t s, const VolGeom &vf, const VolDesc *vdc, const int2 *cC, int Mc, const IfcGeom &igf,
                     const int *prl, const T *ec, T *uf);
 
+// coarsest level solved with a precomputed dense inverse inv (row-major
+// n x n, FP64): x = inv b over the master slots, written to every slot that
+// holds each unknown (cptr/cidx), in the value type of b and u
+template <typename T>
+void launch_coarse_dense(hipStream_t s, int n, const long long *slot, const double *inv, const T *b, T *u,
+                         const int *cptr, const int *cidx);
+
 // Jacobi-PCG on the coarsest level in one workgroup
 template <typename T>
 void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *col, const double *val,

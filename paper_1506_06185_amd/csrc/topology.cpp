@@ -2,6 +2,7 @@
 #include "topology.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <tuple>
 
@@ -388,6 +389,56 @@ std::string Topology::build(int n, int L_, int Lc_) {
     build_coarse();
     if (coarse.n > 2048) return "coarsest level has more than 2048 unknowns";
     return "";
+}
+
+bool coarse_inverse(int n, const std::vector<int> &col, const std::vector<double> &val, std::vector<double> &inv) {
+    const size_t nn = (size_t)n;
+    // lower triangle of A, overwritten by L
+    std::vector<double> L(nn * nn, 0.0);
+    for (int q = 0; q < n; q++)
+        for (int e = 0; e < 7; e++) {
+            const int c = col[7 * (size_t)q + e];
+            if (c >= 0 && c <= q) L[q * nn + c] += val[7 * (size_t)q + e];
+        }
+    for (int j = 0; j < n; j++) {
+        double *Lj = &L[j * nn];
+        double s = Lj[j];
+        for (int k = 0; k < j; k++) s -= Lj[k] * Lj[k];
+        if (!(s > 0.0)) return false;
+        const double d = std::sqrt(s);
+        Lj[j] = d;
+        for (int i = j + 1; i < n; i++) {
+            double *Li = &L[i * nn];
+            double t = Li[j];
+            for (int k = 0; k < j; k++) t -= Li[k] * Lj[k];
+            Li[j] = t / d;
+        }
+    }
+    // U = L^T, row-major, for the backward substitution
+    std::vector<double> U(nn * nn, 0.0);
+    for (int i = 0; i < n; i++)
+        for (int k = 0; k <= i; k++) U[k * nn + i] = L[i * nn + k];
+    inv.assign(nn * nn, 0.0);
+    std::vector<double> y(nn), x(nn);
+    for (int j = 0; j < n; j++) {
+        // L y = e_j (y_i = 0 for i < j)
+        for (int i = 0; i < j; i++) y[i] = 0.0;
+        for (int i = j; i < n; i++) {
+            const double *Li = &L[i * nn];
+            double t = i == j ? 1.0 : 0.0;
+            for (int k = j; k < i; k++) t -= Li[k] * y[k];
+            y[i] = t / Li[i];
+        }
+        // L^T x = y
+        for (int i = n - 1; i >= 0; i--) {
+            const double *Ui = &U[i * nn];
+            double t = y[i];
+            for (int k = i + 1; k < n; k++) t -= Ui[k] * x[k];
+            x[i] = t / Ui[i];
+        }
+        for (int i = 0; i < n; i++) inv[i * nn + j] = x[i];
+    }
+    return true;
 }
 
 }  // namespace hhgr

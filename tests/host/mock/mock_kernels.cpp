@@ -25,6 +25,9 @@ template <typename T>
 void launch_colour(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
                    double, bool, bool) {}
 template <typename T>
+void launch_coarse_dense(hipStream_t, int, const long long *, const double *, const T *, T *, const int *,
+                         const int *) {}
+template <typename T>
 void launch_colour_prol(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
                         double, const Prol<T> &) {}
 template <typename T, typename TO>
@@ -138,6 +141,10 @@ template void launch_colour_prol<double>(hipStream_t, const VolGeom &, const Ifc
                                          const Weights<double> &, bool, double, double, const Prol<double> &);
 template void launch_colour_prol<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
                                         const Weights<float> &, bool, double, double, const Prol<float> &);
+template void launch_coarse_dense<double>(hipStream_t, int, const long long *, const double *, const double *,
+                                          double *, const int *, const int *);
+template void launch_coarse_dense<float>(hipStream_t, int, const long long *, const double *, const float *, float *,
+                                         const int *, const int *);
 template int launch_residual<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,
                                              const double *, const Weights<double> &, bool, double, double *, double *);
 template int launch_residual<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const double *,

@@ -67,11 +67,19 @@ def test_operator_parity(dev, hh, oracle_problem, n_sub, level):
         ec, uf = g.standard_normal(nc), g.standard_normal(nf)
         up = N(hh.debug_op(ctx, 5, l, T(ec, dev), T(uf, dev)))
         assert rel(up, p.prolong_add(ec, uf, level=l)) < 1e-15
-    # coarsest-level PCG
+    # coarsest level: PCG, and the dense inverse the cycles use with k = 1
+    # (up to 512 unknowns; n_sub = 3 has 1331 and keeps the PCG)
     bc = g.standard_normal(p.ndof_at(2))
     x = N(hh.debug_op(ctx, 6, 2, T(bc, dev)))
     xo, _ = p.coarse_solve(bc)
     assert rel(x, xo) < 1e-12
+    if n_sub <= 2:
+        xd = N(hh.debug_op(ctx, 7, 2, T(bc, dev)))
+        assert rel(xd, xo) < 1e-12
+    else:
+        with pytest.raises(hh.HHGRError) as e:
+            hh.debug_op(ctx, 7, 2, T(bc, dev))
+        assert e.value.code == hh.HHGR_EINVAL
     ctx.close()
 
 
@@ -214,6 +222,9 @@ def test_variable_coefficient_parity(dev, hh):
     assert rel(N(hh.debug_op(ctx, 3, level, T(u, dev), T(b, dev))), p.smooth(u, b, 1.25, 3)) < 1e-13
     bc = g.standard_normal(p.ndof_at(2))
     assert rel(N(hh.debug_op(ctx, 6, 2, T(bc, dev))), p.coarse_solve(bc)[0]) < 1e-12
+    with pytest.raises(hh.HHGRError) as e:  # per-element k: the coarsest level uses the PCG only
+        hh.debug_op(ctx, 7, 2, T(bc, dev))
+    assert e.value.code == hh.HHGR_EINVAL
     ctx.close()
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
     ctx.set_tuning(*SHAPES["bs128-hw-4npt"])
