@@ -49,7 +49,7 @@ constexpr int kBS[3] = {128, 256, 512};
 constexpr double kCoarseRtol = 1e-14;
 constexpr int kCoarseMaxit = 2000;
 // largest coarsest level (unknowns) solved with a precomputed dense inverse
-// (k = 1 on the cube; 512^2 FP64 = 2 MiB of workspace)
+// (k = 1; 512^2 FP64 = 2 MiB of workspace)
 constexpr int kDenseCoarseMax = 512;
 constexpr int kMaxLevels = 10;
 
@@ -171,8 +171,10 @@ struct hhgr_ctx {
     double *cval = nullptr, *cval_dn = nullptr;
     unsigned char *cfrozen = nullptr, *dn_faulty = nullptr;
     int cn = 0;
-    // dense inverse of the unmasked coarsest-level operator (k = 1 on the
-    // cube, at most kDenseCoarseMax unknowns); the other operators use PCG
+    // dense inverse of the unmasked coarsest-level operator (k = 1, at most
+    // kDenseCoarseMax unknowns): workspace room in cinv, valid once
+    // dense_coarse is set (at create on the cube, by hhgr_set_geometry on a
+    // general mesh); the other operators use PCG
     bool dense_coarse = false;
     double *cinv = nullptr;
     // general macro meshes: 15-point coarsest-level operator
@@ -357,8 +359,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.cval_dn = cv.take<double>(7 * (size_t)c.cn);
     c.dn_faulty = cv.take<unsigned char>(c.n_tets);
     c.citers = cv.take<int>(4);
-    c.dense_coarse = !c.gen && !c.vk && c.cn <= kDenseCoarseMax;
-    if (c.dense_coarse) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
+    if (!c.vk && c.cn <= kDenseCoarseMax) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
@@ -680,6 +681,10 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
                 launch_local_coarse15(s, v.vd, v.nvol, D.lc_sl.x, gen15(D, -1, false), v.b, v.u);
                 return;
             }
+        }
+        if (c.dense_coarse && !V.cfrozen && !V.cval) {
+            launch_coarse_dense<T>(s, c.cn, c.cslot, c.cinv, v.b, v.u, c.cptr, c.cidx);
+            return;
         }
         launch_coarse_pcg15<T>(s, c.cn, c.cslot, c.ccol15, V.cval ? V.cval : c.cval15, V.cfrozen, v.b, v.u, c.cptr,
                                c.cidx, kCoarseRtol, kCoarseMaxit, c.citers);
@@ -1285,12 +1290,10 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     rc = rc ? rc : upload(*c, c->cslot, cs.slot.data(), cs.slot.size() * sizeof(long long));
     rc = rc ? rc : upload(*c, c->ccol, cs.col.data(), cs.col.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cval, c->cval_host.data(), c->cval_host.size() * sizeof(double));
-    if (c->dense_coarse) {
-        std::vector<double> inv;
-        if (coarse_inverse(cs.n, cs.col, cs.val, inv))
-            rc = rc ? rc : upload(*c, c->cinv, inv.data(), inv.size() * sizeof(double));
-        else
-            c->dense_coarse = false;
+    std::vector<double> cinv_host;
+    if (!c->gen && c->cinv && coarse_inverse(cs.n, 7, cs.col, cs.val, cinv_host)) {
+        rc = rc ? rc : upload(*c, c->cinv, cinv_host.data(), cinv_host.size() * sizeof(double));
+        c->dense_coarse = true;
     }
     rc = rc ? rc : upload(*c, c->cptr, cs.cptr.data(), cs.cptr.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cidx, cs.cidx.data(), cs.cidx.size() * sizeof(int));
@@ -1432,7 +1435,12 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
         e = level_stencils(tp, host_xyz, l, c->lev[l].wtab_cap, G[l]);
         if (!e.empty()) return fail(HHGR_EINVAL, e);
     }
-    if (!c->vk) coarse_stencils(tp, host_xyz, cval);
+    std::vector<double> cinv_host;
+    bool dense = false;
+    if (!c->vk) {
+        coarse_stencils(tp, host_xyz, cval);
+        dense = c->cinv && coarse_inverse(tp.coarse.n, 15, tp.coarse.col15, cval, cinv_host);
+    }
     rc = upload(*c, c->kel, kel.data(), kel.size() * sizeof(double));
     for (int l = l0; l <= c->L; l++) {
         LevelDev &D = c->lev[l];
@@ -1443,6 +1451,11 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
             rc = rc ? rc : upload(*c, D.mw15, G[l].mw15.data(), G[l].mw15.size() * sizeof(double));
             rc = rc ? rc : upload(*c, D.mwtab, G[l].mwtab.data(), G[l].mwtab.size() * sizeof(double));
         }
+    }
+    c->dense_coarse = false;
+    if (dense) {
+        rc = rc ? rc : upload(*c, c->cinv, cinv_host.data(), cinv_host.size() * sizeof(double));
+        c->dense_coarse = true;
     }
     if (!c->vk) {
         rc = rc ? rc : upload(*c, c->cval15, cval.data(), cval.size() * sizeof(double));
@@ -1948,10 +1961,10 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
     if (c->gen && (op == 1 || op == 2)) return fail(HHGR_EINVAL, "general_geometry: class passes are op 8 + class mask");
     if ((op == 4 || op == 5) && l <= c->Lc) return fail(HHGR_EINVAL, "transfer needs level > coarse_level");
     if ((op == 6 || op == 7) && l != c->Lc) return fail(HHGR_EINVAL, "coarse solve needs level = coarse_level");
-    if (op == 7 && !c->dense_coarse) return fail(HHGR_EINVAL, "no dense coarsest-level inverse in this context");
     if ((op <= 3 || op == 5 || class_op) && !in1) return fail(HHGR_EINVAL, "null second input");
     if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
     if (c->gen && !c->geom_set && op != 4 && op != 5) return fail(HHGR_ESTATE, "no geometry set");
+    if (op == 7 && !c->dense_coarse) return fail(HHGR_EINVAL, "no dense coarsest-level inverse in this context");
     invalidate_graph(*c);
     hipStream_t s = c->stream;
     auto to_slots = [&](const double *user, double *vec, LevelDev &D) {
@@ -1965,7 +1978,7 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
     LevelDev &D = c->lev[l];
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const Weights<double> w = weights<double>(D);
-    if (c->gen && (op == 0 || op == 3 || op == 6 || class_op)) {
+    if (c->gen && (op == 0 || op == 3 || op == 6 || op == 7 || class_op)) {
         if (op == 0) {
             to_slots(in0, D.u, D);
             to_slots(in1, D.b, D);
@@ -1976,6 +1989,10 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
             to_slots(in0, D.b, D);
             launch_coarse_pcg15(s, c->cn, c->cslot, c->ccol15, c->cval15, nullptr, D.b, D.u, c->cptr, c->cidx,
                                 kCoarseRtol, kCoarseMaxit, c->citers);
+            to_user(D.u, out, D);
+        } else if (op == 7) {
+            to_slots(in0, D.b, D);
+            launch_coarse_dense<double>(s, c->cn, c->cslot, c->cinv, D.b, D.u, c->cptr, c->cidx);
             to_user(D.u, out, D);
         } else {
             const int mask = op == 3 ? 15 : op - 8;

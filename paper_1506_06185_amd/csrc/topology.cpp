@@ -391,14 +391,15 @@ std::string Topology::build(int n, int L_, int Lc_) {
     return "";
 }
 
-bool coarse_inverse(int n, const std::vector<int> &col, const std::vector<double> &val, std::vector<double> &inv) {
+bool coarse_inverse(int n, int nb, const std::vector<int> &col, const std::vector<double> &val,
+                    std::vector<double> &inv) {
     const size_t nn = (size_t)n;
     // lower triangle of A, overwritten by L
     std::vector<double> L(nn * nn, 0.0);
     for (int q = 0; q < n; q++)
-        for (int e = 0; e < 7; e++) {
-            const int c = col[7 * (size_t)q + e];
-            if (c >= 0 && c <= q) L[q * nn + c] += val[7 * (size_t)q + e];
+        for (int e = 0; e < nb; e++) {
+            const int c = col[(size_t)nb * q + e];
+            if (c >= 0 && c <= q) L[q * nn + c] += val[(size_t)nb * q + e];
         }
     for (int j = 0; j < n; j++) {
         double *Lj = &L[j * nn];

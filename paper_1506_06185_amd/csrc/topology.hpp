@@ -164,11 +164,11 @@ struct Topology {
     void build_coarse();
 };
 
-// Dense inverse (row-major n x n) of a coarsest-level operator given as
-// [n][7] columns and values (column 0 the diagonal, -1 none): Cholesky
-// factorisation A = L L^T, then A^{-1} e_j by a forward and a backward
-// substitution for every j.  Returns false if A is not numerically positive
-// definite.
-bool coarse_inverse(int n, const std::vector<int> &col, const std::vector<double> &val, std::vector<double> &inv);
+// Dense inverse (row-major n x n) of a symmetric coarsest-level operator
+// given as [n][nb] columns and values (-1: no entry): Cholesky factorisation
+// A = L L^T, then A^{-1} e_j by a forward and a backward substitution for
+// every j.  Returns false if A is not numerically positive definite.
+bool coarse_inverse(int n, int nb, const std::vector<int> &col, const std::vector<double> &val,
+                    std::vector<double> &inv);
 
 }  // namespace hhgr

@@ -98,6 +98,9 @@ def test_variable_k_operators_and_solve(dev, hh, n_sub, level, seed):
     uo = p.coarse_solve(bc)
     uo = uo[0] if isinstance(uo, tuple) else uo
     assert rel(uc, uo) < 1e-10
+    with pytest.raises(hh.HHGRError) as e:  # per-element k: the coarsest level uses the PCG only
+        hh.debug_op(ctx, 7, 2, T(bc, dev))
+    assert e.value.code == hh.HHGR_EINVAL
     b = g.uniform(0.0, 1.0, p.ndof) / p.ndof
     ctx.set_rhs(T(b, dev))
     ctx.set_solution(T(np.zeros(p.ndof), dev))  # the operator calls above left their input in u
@@ -166,6 +169,8 @@ def test_operator_and_class_passes(dev, hh, n_sub, level, seed):
     uo = p.coarse_solve(bc)
     uo = uo[0] if isinstance(uo, tuple) else uo
     assert rel(uc, uo) < 1e-10
+    if n_sub <= 2:  # k = 1 with at most 512 coarsest unknowns: the dense inverse the cycles use
+        assert rel(Nn(hh.debug_op(ctx, 7, 2, T(bc, dev))), uo) < 1e-10
     with pytest.raises(hh.HHGRError):
         hh.debug_op(ctx, 1, level, T(u, dev), T(b, dev))
     ctx.close()
