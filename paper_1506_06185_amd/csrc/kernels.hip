@@ -162,22 +162,25 @@ inline int ifc_blocks(const IfcGeom &ig, int bs) {
 // ---------------------------------------------------------------------------
 // linear interpolation of the coarse-grid correction (P e_c)
 // ---------------------------------------------------------------------------
-// index direction of the coarse edge bisected by a fine node with parity code
-// (i&1) | (j&1)<<1 | (k&1)<<2
-__device__ __constant__ int kParDir[8][3] = {{0, 0, 0},  {1, 0, 0}, {0, 1, 0},  {-1, 1, 0},
-                                             {0, 0, 1},  {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
-
 // (P e_c) at fine interior node n of a closure whose coarse closure holds ev:
 // the coarse value where the node coincides with a coarse node, else the mean
 // of the end points of the coarse edge it bisects
 template <typename T>
 __device__ __forceinline__ T coarse_corr(const T *__restrict__ ev, const int2 *__restrict__ cC, int Mc, const LNode &n) {
-    const int code = (n.i & 1) | ((n.j & 1) << 1) | ((n.k & 1) << 2);
-    const int di = kParDir[code][0], dj = kParDir[code][1], dk = kParDir[code][2];
-    // coarse end points of the bisected edge (the same node twice for code 0)
+    // index direction (di, dj, dk) of that edge from the parity bits of
+    // (i, j, k), one of the 7 edge directions of the index space:
+    //   (i,j,k) mod 2: 000 001 010 011 100 101 110 111  (k j i)
+    //   (di,dj,dk):    0    (1,0,0) (0,1,0) (-1,1,0) (0,0,1) (-1,0,1) (0,-1,1) (1,-1,1)
+    // computed, not looked up, so the coarse loads depend on the node list
+    // entry only
+    const int pi = n.i & 1, pj = n.j & 1, pk = n.k & 1;
+    const int dk = pk;
+    const int dj = pk ? -pj : pj;
+    const int di = (pj ^ pk) ? -pi : pi;
+    // coarse end points of the bisected edge (the same node twice at even (i, j, k))
     const T e1 = ev[lslot(cC, Mc, (n.i - di) >> 1, (n.j - dj) >> 1, (n.k - dk) >> 1)];
     const T e2 = ev[lslot(cC, Mc, (n.i + di) >> 1, (n.j + dj) >> 1, (n.k + dk) >> 1)];
-    return code == 0 ? e1 : T(0.5) * (e1 + e2);
+    return (pi | pj | pk) == 0 ? e1 : T(0.5) * (e1 + e2);
 }
 
 // (P e_c) at interface master t from its two coarse slots (equal where the
