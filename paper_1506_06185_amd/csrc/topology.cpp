@@ -209,8 +209,14 @@ void Topology::build_level(int l) {
                     Lv.flist.push_back(w);
                     if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1) (c == 0 ? Lv.rlist : Lv.blist).push_back(w);
                 }
-    Lv.ilist = Lv.rlist;
-    Lv.ilist.insert(Lv.ilist.end(), Lv.blist.begin(), Lv.blist.end());
+    // all interior nodes row by row (plane k, row j; a row's red nodes, then
+    // its black ones): a launch over both colours then reads each row's u and
+    // b once while they are in cache, instead of once per colour half
+    Lv.ilist.clear();
+    for (int k = 1; k <= m - 3; k++)
+        for (int j = 1; j <= m - 2 - k; j++)
+            for (int c = 0; c < 2; c++)
+                for (int i = 1 + ((1 + c + k) & 1); i <= m - 1 - k - j; i += 2) Lv.ilist.push_back(pack_ijk(i, j, k));
     for (int q = 0; q < 4; q++) Lv.qlist[q].clear();
     for (int c = 0; c < 2; c++)
         for (unsigned w : (c ? Lv.blist : Lv.rlist)) {

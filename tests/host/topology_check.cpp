@@ -175,8 +175,23 @@ int main(int argc, char **argv) {
         CHECK(T.ilist.size() == T.rlist.size() + T.blist.size(), "colour lists partition the interior");
         CHECK((long long)T.ilist.size() == nint, "interior list size");
         CHECK((long long)T.flist.size() == T.C, "full list size");
-        for (size_t q = 0; q < T.ilist.size(); q++)
-            CHECK(T.ilist[q] == (q < T.rlist.size() ? T.rlist[q] : T.blist[q - T.rlist.size()]), "ilist = red, black");
+        {
+            // ilist: the red and the black list merged row by row (a row's red
+            // nodes, then its black ones, rows in slot order)
+            std::vector<unsigned> want;
+            size_t pr = 0, pb = 0;
+            auto row = [](unsigned wv) { return wv >> 10; };  // (j, k)
+            while (pr < T.rlist.size() || pb < T.blist.size()) {
+                const unsigned r = pr < T.rlist.size() ? row(T.rlist[pr]) : ~0u;
+                const unsigned b = pb < T.blist.size() ? row(T.blist[pb]) : ~0u;
+                const unsigned k_r = r >> 10, k_b = b >> 10, j_r = r & 1023, j_b = b & 1023;
+                const bool red_first = k_r < k_b || (k_r == k_b && j_r <= j_b);
+                const unsigned cur = red_first ? r : b;
+                while (pr < T.rlist.size() && row(T.rlist[pr]) == cur) want.push_back(T.rlist[pr++]);
+                while (pb < T.blist.size() && row(T.blist[pb]) == cur) want.push_back(T.blist[pb++]);
+            }
+            CHECK(want == T.ilist, "ilist = rows of red then black nodes");
+        }
         auto unpack = [](unsigned wv, int &i, int &j, int &k) {
             i = wv & 1023;
             j = (wv >> 10) & 1023;
