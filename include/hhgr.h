@@ -109,7 +109,9 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * P1 stiffness matrix assembled in physical coordinates.  With k = 1 an
  * affine element has a constant stencil, so every node of one primitive
  * (tetrahedron interior, face, edge, vertex) shares one 15-point stencil;
- * these are computed on the host and uploaded.  With variable_coeff = 1 the
+ * these are computed on the host and uploaded (with k = 1 and at most 512
+ * coarsest unknowns, also the dense inverse of the coarsest-level matrix,
+ * which the cycles then apply as on the cube).  With variable_coeff = 1 the
  * element coefficients of hhgr_set_coeff (element order above; coarse levels
  * take the mean of the 8 children) weight the element matrices, and the GPU
  * computes per-node stencils on every level and the coarsest-level matrix
