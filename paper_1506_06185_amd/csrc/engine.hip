@@ -74,8 +74,9 @@ struct LevelDev {
     int bs_sel = 1;  // colour pass
     int remap = 1;   // XCD-contiguous block order (autotuned)
     int cpb = 1;     // nodes per thread of the list-mode kernels (autotuned)
-    int cpb_res = 1; // ... of the residual and of the prolongation (autotuned separately)
-    int cpb_prl = 1;
+    int cpb_res = 1; // ... of the residual, of the prolongation and of the red
+    int cpb_prl = 1; // post-smoothing pass that adds the correction (autotuned
+    int cpb_fus = 1; // separately)
     int *nbr = nullptr, *gptr = nullptr, *gidx = nullptr, *rst = nullptr, *prl = nullptr, *nb15 = nullptr;
     int *ifc_dof = nullptr, *ifc_xyz = nullptr, *tg_dst = nullptr, *tg_src = nullptr;
     std::vector<int> tg_ptr;
@@ -655,7 +656,9 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, cons
                                            true)
                                  : ig_none();
         if (pr && colour == 0) {
-            launch_colour_prol<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, *pr);
+            VolGeom vgf = vg;
+            vgf.cpb = D.cpb_fus;
+            launch_colour_prol<T>(s, vgf, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, *pr);
             continue;
         }
         const bool timed = c.timing && V.timed && l == c.L;
@@ -1759,6 +1762,7 @@ int hhgr_set_tuning(hhgr_ctx *c, int level, int block_size, int xcd_order, int n
         D.cpb = nodes_per_thread;
         D.cpb_res = nodes_per_thread;
         D.cpb_prl = nodes_per_thread;
+        D.cpb_fus = nodes_per_thread;
     }
     invalidate_graph(*c);
     return HHGR_OK;
@@ -1824,13 +1828,15 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         auto itc = cache.find(ks.str() + ":cpb");
         auto itcr = cache.find(ks.str() + ":cpb_res");
         auto itcp = cache.find(ks.str() + ":cpb_prl");
+        auto itcf = cache.find(ks.str() + ":cpb_fus");
         if (it != cache.end() && itr != cache.end() && itc != cache.end() && itcr != cache.end() &&
-            itcp != cache.end()) {
+            itcp != cache.end() && itcf != cache.end()) {
             D.bs_sel = it->second;
             D.remap = itr->second;
             D.cpb = itc->second;
             D.cpb_res = itcr->second;
             D.cpb_prl = itcp->second;
+            D.cpb_fus = itcf->second;
             continue;
         }
         auto time_it = [&](auto run, int reps) -> float {
@@ -1864,12 +1870,13 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
             }
             D.bs_sel = bq;
             D.remap = br;
-            D.cpb = D.cpb_res = D.cpb_prl = 1;
+            D.cpb = D.cpb_res = D.cpb_prl = D.cpb_fus = 1;
             cache[ks.str()] = bq;
             cache[ks.str() + ":remap"] = br;
             cache[ks.str() + ":cpb"] = 1;
             cache[ks.str() + ":cpb_res"] = 1;
             cache[ks.str() + ":cpb_prl"] = 1;
+            cache[ks.str() + ":cpb_fus"] = 1;
             launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
             continue;
         }
@@ -1908,16 +1915,21 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         cache[ks.str()] = bq;
         cache[ks.str() + ":remap"] = br;
         cache[ks.str() + ":cpb"] = bc;
-        // nodes per thread of the residual (norm form) and of the
-        // prolongation at that workgroup size and block order; the scratch
+        // nodes per thread of the residual (norm form), of the prolongation
+        // (black nodes, as in the cycle) and of the red pass that adds the
+        // correction, at that workgroup size and block order; the scratch
         // vectors r of this level and of the next coarser one stand in for
         // u and the coarse correction
         const int reps = l >= 6 ? 5 : 20;
-        float tr[2], tp[2];
+        float tr[2], tp[2], tf[2];
         const LevelDev &Dc = c->lev[l - 1];
         for (int qc = 0; qc < 2; qc++) {
             VolGeom vg = vgeom(D, D.vd_all, c->n_tets, false);
             vg.cpb = qc ? 4 : 1;
+            VolGeom vgb = vgeom(D, D.vd_all, c->n_tets, false, -1, 1);
+            vgb.cpb = vg.cpb;
+            VolGeom vgr = vgeom(D, D.vd_all, c->n_tets, false, -1, 0);
+            vgr.cpb = vg.cpb;
             tr[qc] = time_it([&]() {
                 if (c->mixed)
                     launch_residual<float, float>(c->stream, vg, igeom(D, 0, D.n_ifc, nullptr, false), D.r32, D.b32,
@@ -1927,18 +1939,41 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
                                                     weights<double>(D), c->vk, D.h, (double *)nullptr, c->partial[0]);
             }, reps);
             tp[qc] = time_it([&]() {
+                const IfcGeom igb = igeom(D, D.n_ifc_red, D.n_ifc, nullptr, true);
                 if (c->mixed)
-                    launch_prolong<float>(c->stream, vg, Dc.vd_all, Dc.rowC, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true),
-                                          D.prl, Dc.r32, D.r32);
+                    launch_prolong<float>(c->stream, vgb, Dc.vd_all, Dc.rowC, Dc.M, igb, D.prl, Dc.r32, D.r32);
                 else
-                    launch_prolong<double>(c->stream, vg, Dc.vd_all, Dc.rowC, Dc.M, igeom(D, 0, D.n_ifc, nullptr, true),
-                                           D.prl, Dc.r, D.r);
+                    launch_prolong<double>(c->stream, vgb, Dc.vd_all, Dc.rowC, Dc.M, igb, D.prl, Dc.r, D.r);
+            }, reps);
+            tf[qc] = time_it([&]() {
+                const IfcGeom igr = igeom(D, 0, D.n_ifc_red, nullptr, true);
+                if (c->mixed) {
+                    Prol<float> pr;
+                    pr.vdc = Dc.vd_all;
+                    pr.cC = Dc.rowC;
+                    pr.Mc = Dc.M;
+                    pr.prl = D.prl;
+                    pr.ec = Dc.r32;
+                    launch_colour_prol<float>(c->stream, vgr, igr, D.r32, D.b32, weights<float>(D), c->vk, D.h,
+                                              c->d.omega, pr);
+                } else {
+                    Prol<double> pr;
+                    pr.vdc = Dc.vd_all;
+                    pr.cC = Dc.rowC;
+                    pr.Mc = Dc.M;
+                    pr.prl = D.prl;
+                    pr.ec = Dc.r;
+                    launch_colour_prol<double>(c->stream, vgr, igr, D.r, D.b, weights<double>(D), c->vk, D.h,
+                                               c->d.omega, pr);
+                }
             }, reps);
         }
         D.cpb_res = tr[1] < tr[0] ? 4 : 1;
         D.cpb_prl = tp[1] < tp[0] ? 4 : 1;
+        D.cpb_fus = tf[1] < tf[0] ? 4 : 1;
         cache[ks.str() + ":cpb_res"] = D.cpb_res;
         cache[ks.str() + ":cpb_prl"] = D.cpb_prl;
+        cache[ks.str() + ":cpb_fus"] = D.cpb_fus;
         // scratch vector used for timing goes back to zero
         launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
         if (c->mixed) launch_fill<float>(c->stream, D.r32, D.n_slots, 0.0f);
