@@ -252,8 +252,12 @@ int hhgr_set_graph(hhgr_ctx *ctx, int use_graph);
 
 /* Autotuner: times the candidate workgroup sizes, nodes per thread and block
  * orders of the volume colour pass on every level and keeps the fastest per
- * (level, precision, coefficient mode) for all volume kernels of that level.  cache_path (optional) is a text file read before and written
- * after tuning, keyed by device name.  Enqueues work and synchronises. */
+ * (level, precision, coefficient mode) for all volume kernels of that level;
+ * at that shape it then picks 1 or 4 nodes per thread separately for the
+ * residual, the prolongation and the red post-smoothing pass that adds the
+ * coarse-grid correction.  cache_path (optional) is a text file read before
+ * and written after tuning, keyed by device name.  Enqueues work and
+ * synchronises. */
 int hhgr_autotune(hhgr_ctx *ctx, const char *cache_path);
 
 /* The tuning choices in use on `level` (any output may be NULL): workgroup
