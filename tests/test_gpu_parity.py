@@ -107,6 +107,38 @@ def test_vcycle_iterates(dev, hh, oracle_problem, n_sub, level, shape):
     ctx.close()
 
 
+# smoothing sweep counts and SOR factor: no post-smoothing (the prolongation
+# corrects every node), no pre-smoothing with two post sweeps (the red pass
+# adds the correction in the first sweep only), the paper's 3 + 3 sweeps,
+# and plain Gauss-Seidel
+SWEEPS = [(1, 0, 1.25), (0, 2, 1.25), (3, 3, 1.25), (2, 1, 1.0)]
+
+
+@pytest.mark.parametrize("vk", [False, True])
+@pytest.mark.parametrize("nu_pre,nu_post,omega", SWEEPS)
+def test_vcycle_sweep_counts(dev, hh, nu_pre, nu_post, omega, vk):
+    n_sub, level = 2, 4
+    print(f"\n[vcycle sweeps] nu=({nu_pre},{nu_post}) omega={omega} vk={vk}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=1) if vk else None
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, nu_pre=nu_pre, nu_post=nu_post, omega=omega,
+                     variable_coeff=vk)
+    if vk:
+        ctx.set_coeff(T(k, dev))
+    p = oracle.Problem(n_sub, level, k=k)
+    g = np.random.default_rng(11)
+    b = g.standard_normal(p.ndof)
+    u = g.standard_normal(p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(T(u, dev))
+    for it in range(3):
+        relres = ctx.vcycle(1)
+        u, rn = p.vcycle(u, b, omega=omega, nu1=nu_pre, nu2=nu_post)
+        assert rel(N(ctx.get_solution()), u) < 1e-12, it
+        assert relres == pytest.approx(rn / np.linalg.norm(b), rel=1e-10)
+    ctx.close()
+    p.close()
+
+
 def test_solve_c1(dev, hh, oracle_problem):
     # 6 macro tets, level 4, sine source, V(2,1) to 1e-8
     n_sub, level = 1, 4
