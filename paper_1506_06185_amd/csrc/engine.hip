@@ -1363,18 +1363,26 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
         if (D.n_slots < (long long)(D.N - 1) * (D.N - 1) * (D.N - 1)) return fail(HHGR_EINVAL, "aux buffer too small");
         launch_dirichlet_load(c->stream, D.N, D.h, c->vk ? D.kc : nullptr, dev_vec, c->aux_u);
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
-    } else {
+    } else if (c->gen) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.r);
-        if (c->gen)
-            launch_apply15(c->stream, vint, ig, gen15mass(D), D.r, D.b);
-        else
-            launch_mass(c->stream, vint, ig, D.nb15, D.r, D.b, D.h);
+        launch_apply15(c->stream, vint, ig, gen15mass(D), D.r, D.b);
+    } else {
+        // b = M f on the grid in vector order (through aux_u), then into the slots
+        if (D.n_slots < (long long)(D.N - 1) * (D.N - 1) * (D.N - 1)) return fail(HHGR_EINVAL, "aux buffer too small");
+        launch_mass_grid(c->stream, D.N, D.h, dev_vec, c->aux_u);
+        launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
     }
-    // ||b||: residual of the zero vector
+    // aux_u (a scratch vector whose zero slot and boundary ghosts must read
+    // zero) may have held the load in vector order
     launch_fill<double>(c->stream, c->aux_u, D.n_slots, 0.0);
-    HView<double> V = global_view<double>(*c, false, 0);
-    V.lv[c->L].u = c->aux_u;
-    finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm + 1);
+    // ||b|| over every interior node once
+    VolGeom vn = vint;
+    vn.cpb = 1;
+    const int nb = launch_norm2(c->stream, vn, ig, D.b, c->partial[0]);
+    if (nb > 0)
+        launch_reduce(c->stream, c->partial[0], nb, c->dnorm + 1);
+    else
+        launch_fill<double>(c->stream, c->dnorm + 1, 1, 0.0);
     CHKLAUNCH();
     double bn;
     int rc = read_norm(*c, 1, &bn);

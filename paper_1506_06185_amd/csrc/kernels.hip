@@ -924,7 +924,8 @@ __global__ void __launch_bounds__(512) k_user_to_slots(VolGeom vg, const int *__
     grid_pos(tetinfo, d.tet, m, n.i, n.j, n.k, X);
     const bool in = X[0] > 0 && X[1] > 0 && X[2] > 0 && X[0] < N && X[1] < N && X[2] < N;
     const long long dof = (long long)(X[0] - 1) + (long long)(N - 1) * ((X[1] - 1) + (long long)(N - 1) * (X[2] - 1));
-    (vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)] = in ? (T)user[dof] : T(0);
+    const double uv = user[in ? dof : 0];  // boundary nodes read a valid address and store zero
+    (vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)] = in ? (T)uv : T(0);
 }
 
 template <typename T, int CPB>
@@ -990,6 +991,66 @@ __global__ void __launch_bounds__(512) k_mass(VolGeom vg, IfcGeom ig, int nib, c
         const double bd = X(0, 0, 1) + X(0, 0, -1);
         (y + d.vec)[lslot(vg.rowC, M, i, j, k)] = wc * X(0, 0, 0) + wax * ax + wfd * fd + wbd * bd;
     }
+}
+
+// b = M f on the unit cube's Kuhn mesh in vector order (interior node
+// (x, y, z) at (x-1) + (N-1)((y-1) + (N-1)(z-1)); f = 0 on the boundary).
+// The consistent P1 mass matrix does not depend on k: 0.4 h^3 on the
+// diagonal, h^3/20 to the 6 axis neighbours (6 elements share such an edge),
+// h^3/30 to the face diagonals (1,1,0), (0,1,1), (1,0,1) (4 elements) and
+// h^3/20 to the body diagonal (1,1,1) (6 elements), each in both signs.
+__global__ void __launch_bounds__(256) k_mass_grid(int N, double h3, const double *__restrict__ f,
+                                                   double *__restrict__ b) {
+    const int n = N - 1;
+    const long long sz = (long long)n * n;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= sz * n) return;
+    const int x = (int)(q % n), y = (int)((q / n) % n), z = (int)(q / sz);
+    // a neighbour outside the interior reads the node itself (a valid
+    // address) and contributes zero
+    auto F = [&](int dx, int dy, int dz) -> double {
+        const bool in = (unsigned)(x + dx) < (unsigned)n && (unsigned)(y + dy) < (unsigned)n &&
+                        (unsigned)(z + dz) < (unsigned)n;
+        const double v = f[in ? q + dx + (long long)dy * n + (long long)dz * sz : q];
+        return in ? v : 0.0;
+    };
+    const double wc = 0.4 * h3, wax = h3 / 20.0, wfd = h3 / 30.0, wbd = h3 / 20.0;
+    const double ax = ((F(1, 0, 0) + F(-1, 0, 0)) + (F(0, 1, 0) + F(0, -1, 0))) + (F(0, 0, 1) + F(0, 0, -1));
+    const double fd = ((F(1, 1, 0) + F(-1, -1, 0)) + (F(0, 1, 1) + F(0, -1, -1))) + (F(1, 0, 1) + F(-1, 0, -1));
+    const double bd = F(1, 1, 1) + F(-1, -1, -1);
+    b[q] = wc * F(0, 0, 0) + wax * ax + wfd * fd + wbd * bd;
+}
+
+// per-block partial sums of v^2 over the volume nodes of vg's list and the
+// interface masters of ig (every interior node once); CPB volume nodes per
+// thread, whose load chains (list entry, row table, value) are independent
+template <int CPB>
+__global__ void __launch_bounds__(512) k_norm2(VolGeom vg, IfcGeom ig, int nib, const double *__restrict__ v,
+                                               double *__restrict__ partial) {
+    __shared__ double sh[64];
+    const unsigned f = blockIdx.x;
+    double acc = 0.0;
+    if (f < (unsigned)nib) {
+        const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
+        if (t < ig.i1) {
+            const double x = v[ig.base + t];
+            acc = x * x;
+        }
+    } else {
+        const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
+        const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+        double x[CPB];
+#pragma unroll
+        for (int q = 0; q < CPB; q++) {
+            x[q] = 0.0;
+            LNode n;
+            if (list_node<CPB>(vg, blk, per_vol, q, n)) x[q] = (v + vg.vd[n.v].vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)];
+        }
+#pragma unroll
+        for (int q = 0; q < CPB; q++) acc += x[q] * x[q];
+    }
+    const double s = block_sum_all(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(256) k_update_add(const VolDesc *__restrict__ vd, long long span, IfcGeom ig,
@@ -1723,6 +1784,22 @@ void launch_mass(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const in
         hipLaunchKernelGGL(k_mass<1>, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, nib, nb15, x, y, h * h * h);
     else
         hipLaunchKernelGGL(k_mass<4>, dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, ig, nib, nb15, x, y, h * h * h);
+}
+
+void launch_mass_grid(hipStream_t s, int N, double h, const double *f, double *b) {
+    const long long n = (long long)(N - 1) * (N - 1) * (N - 1);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mass_grid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, h * h * h, f, b);
+}
+
+int launch_norm2(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const double *v, double *partial) {
+    VolGeom g = vg;
+    g.cpb = 4;
+    const int nib = ifc_blocks(ig, g.bs);
+    const long long grid = nib + list_blocks(g);
+    if (grid == 0) return 0;
+    hipLaunchKernelGGL(k_norm2<4>, dim3((unsigned)grid), dim3(g.bs), 0, s, g, ig, nib, v, partial);
+    return (int)grid;
 }
 
 void launch_update_add(hipStream_t s, const VolDesc *vd, int nvol, long long span, const IfcGeom &ig, double *u,

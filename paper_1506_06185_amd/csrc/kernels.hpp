@@ -143,6 +143,16 @@ template <typename T>
 void launch_coarse_dense(hipStream_t s, int n, const long long *slot, const double *inv, const T *b, T *u,
                          const int *cptr, const int *cidx);
 
+// b = M f with the unit cube's k-independent P1 mass matrix, both in vector
+// order ((N-1)^3 interior nodes, x fastest)
+void launch_mass_grid(hipStream_t s, int N, double h, const double *f, double *b);
+
+// per-block partial sums of v^2 over every interior node once (the volume
+// nodes of vg's list, four per thread, and the masters of ig); returns the
+// number of blocks (at most the block count of a one-node-per-thread list
+// launch)
+int launch_norm2(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const double *v, double *partial);
+
 // Jacobi-PCG on the coarsest level in one workgroup
 template <typename T>
 void launch_coarse_pcg(hipStream_t s, int n, const long long *slot, const int *col, const double *val,

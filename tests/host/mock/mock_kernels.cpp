@@ -24,6 +24,12 @@ static int ifc_blocks_of(const IfcGeom &ig, int bs) {
 template <typename T>
 void launch_colour(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
                    double, bool, bool) {}
+void launch_mass_grid(hipStream_t, int, double, const double *, double *) {}
+int launch_norm2(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const double *, double *partial) {
+    const long long nb = ifc_blocks_of(ig, vg.bs) + list_blocks_of(vg, 4);
+    for (long long q = 0; q < nb; q++) partial[q] = q == 0 ? g_mock_res2 : 0.0;
+    return (int)nb;
+}
 template <typename T>
 void launch_coarse_dense(hipStream_t, int, const long long *, const double *, const T *, T *, const int *,
                          const int *) {}
