@@ -83,7 +83,7 @@ def measured_traffic(n_sub: int, level: int, path: str = TRAFFIC_FILE):
 def run_job(hh, torch, ctx, f_dev, fault_tet, k_f=5, n_rec=3, rtol=1e-8, max_cycles=60):
     """One step: solve from zero with a fault after k_f cycles and local recovery."""
     ctx.set_rhs(f_dev, hh.HHGR_RHS_NODAL_F)
-    ctx.set_solution(torch.zeros_like(f_dev))
+    ctx.set_solution(None)  # u = 0
     ctx.vcycle(k_f)
     ctx.inject_fault(fault_tet)
     ctx.recover_local(fault_tet, n_rec)
@@ -267,7 +267,7 @@ def leg_mixed_l8(hh, torch, dev, tune_cache, n_sub=2, level=8):
         c.autotune(tune_cache)
         c.set_rhs(b, hh.HHGR_RHS_LOAD)
         c.vcycle(1)  # warm-up step
-        c.set_solution(torch.zeros_like(b))
+        c.set_solution(None)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cyc, _, _ = c.solve(1e-8, 60)
@@ -302,7 +302,7 @@ def leg_gradients(hh, torch, dev, n_sub=2, level=7, n_dirs=2):
     def forward(ff, kk):
         c.set_coeff(kk)
         c.set_rhs(ff, hh.HHGR_RHS_NODAL_F)
-        c.set_solution(torch.zeros_like(ff))
+        c.set_solution(None)
         cyc, rr, _ = c.solve(tol, 100, raise_on_noconv=False)
         return c.get_solution(), (cyc, rr)
 

@@ -154,7 +154,8 @@ int hhgr_set_rhs(hhgr_ctx *ctx, const double *dev_vec, int kind);
  * 8 children of each coarse element (the Galerkin-consistent choice). */
 int hhgr_set_coeff(hhgr_ctx *ctx, const double *dev_k);
 
-/* Copy a device vector into / out of the solver's containers (vector order). */
+/* Copy a device vector into / out of the solver's containers (vector order).
+ * hhgr_set_solution with dev_u = NULL sets u = 0 (a fill, no copy). */
 int hhgr_set_solution(hhgr_ctx *ctx, const double *dev_u);
 int hhgr_get_solution(const hhgr_ctx *ctx, double *dev_u);
 

@@ -1485,8 +1485,14 @@ int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
 }
 
 int hhgr_set_solution(hhgr_ctx *c, const double *dev_u) {
-    if (!c || !dev_u) return fail(HHGR_EINVAL, "null argument");
+    if (!c) return fail(HHGR_EINVAL, "null context");
     LevelDev &D = c->lev[c->L];
+    if (!dev_u) {
+        // u = 0 in every slot (ghost copies and the zero slot included)
+        launch_fill<double>(c->stream, D.u, D.n_slots, 0.0);
+        CHKLAUNCH();
+        return HHGR_OK;
+    }
     launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N,
                                  igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, dev_u, D.u);
     CHKLAUNCH();

@@ -191,8 +191,9 @@ class Context:
             raise HHGRError(HHGR_EINVAL, f"expected {(self.desc.n_sub + 1) ** 3} vertices, got {xyz.size / 3:g}")
         _check(lib().hhgr_set_geometry(self._h, xyz.ctypes.data_as(_dp)))
 
-    def set_solution(self, u: torch.Tensor):
-        _check(lib().hhgr_set_solution(self._h, _ptr(u)))
+    def set_solution(self, u: torch.Tensor | None):
+        """Initial guess from a device vector in vector order; None sets u = 0."""
+        _check(lib().hhgr_set_solution(self._h, _ptr(u) if u is not None else None))
         self.stream.synchronize()
 
     def get_solution(self, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -341,7 +342,7 @@ class HHGSolve(torch.autograd.Function):
                 max_cycles: int = 100):
         ctx_obj.set_coeff(k.contiguous())
         ctx_obj.set_rhs(f.contiguous(), HHGR_RHS_NODAL_F)
-        ctx_obj.set_solution(torch.zeros_like(f))
+        ctx_obj.set_solution(None)
         ctx_obj.solve(rel_tol, max_cycles)
         u = ctx_obj.get_solution()
         fctx.ctx_obj = ctx_obj

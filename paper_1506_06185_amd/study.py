@@ -71,7 +71,7 @@ class Runner:
 
     def prefix(self, k: int) -> torch.Tensor:
         if k not in self._prefix:
-            self.ctx.set_solution(torch.zeros(self.ctx.n_dofs, dtype=torch.float64, device=self.ctx.device))
+            self.ctx.set_solution(None)
             if k:
                 self.ctx.vcycle(k)
             self._prefix[k] = self.ctx.get_solution()

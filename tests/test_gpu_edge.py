@@ -102,6 +102,27 @@ def test_smallest_hierarchy_and_unfaulted_recovery(dev, hh, general):
     ctx.close()
 
 
+@pytest.mark.parametrize("general", [False, True])
+def test_zero_initial_guess_fill(dev, hh, general):
+    """set_solution(None) sets u = 0 by a fill; cycles from it equal cycles
+    from a zero vector copied in, bit for bit."""
+    n_sub, level = 2, 4
+    print(f"\n[zero initial guess] general={general}", flush=True)
+    ctx, p = make(hh, dev, n_sub, level, general)
+    b = inputs.uniform_load(n_sub, level, seed=4)
+    ctx.set_rhs(T(b, dev))
+    ctx.set_solution(T(np.ones(p.ndof), dev))
+    ctx.set_solution(None)
+    assert np.count_nonzero(Nn(ctx.get_solution())) == 0
+    r1 = ctx.vcycle(3)
+    u1 = Nn(ctx.get_solution())
+    ctx.set_solution(T(np.zeros(p.ndof), dev))
+    r2 = ctx.vcycle(3)
+    assert r1 == r2
+    assert np.array_equal(Nn(ctx.get_solution()), u1)
+    ctx.close()
+
+
 def test_zero_cycles_and_rejected_arguments(dev, hh):
     n_sub, level = 1, 4
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level, max_faults=2)
