@@ -1354,6 +1354,7 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     const VolGeom vfull = vgeom(D, D.vd_all, c->n_tets, true);
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
+    bool aux_used = false;  // aux_u held the load in vector order
     if (kind == HHGR_RHS_LOAD) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.b);
     } else if (kind == HHGR_RHS_DIRICHLET && c->gen) {
@@ -1363,6 +1364,7 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
         if (D.n_slots < (long long)(D.N - 1) * (D.N - 1) * (D.N - 1)) return fail(HHGR_EINVAL, "aux buffer too small");
         launch_dirichlet_load(c->stream, D.N, D.h, c->vk ? D.kc : nullptr, dev_vec, c->aux_u);
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
+        aux_used = true;
     } else if (c->gen) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.r);
         launch_apply15(c->stream, vint, ig, gen15mass(D), D.r, D.b);
@@ -1371,14 +1373,12 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
         if (D.n_slots < (long long)(D.N - 1) * (D.N - 1) * (D.N - 1)) return fail(HHGR_EINVAL, "aux buffer too small");
         launch_mass_grid(c->stream, D.N, D.h, dev_vec, c->aux_u);
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
+        aux_used = true;
     }
-    // aux_u (a scratch vector whose zero slot and boundary ghosts must read
-    // zero) may have held the load in vector order
-    launch_fill<double>(c->stream, c->aux_u, D.n_slots, 0.0);
+    // aux_u is a scratch slot vector again (zero slot and boundary ghosts zero)
+    if (aux_used) launch_fill<double>(c->stream, c->aux_u, D.n_slots, 0.0);
     // ||b|| over every interior node once
-    VolGeom vn = vint;
-    vn.cpb = 1;
-    const int nb = launch_norm2(c->stream, vn, ig, D.b, c->partial[0]);
+    const int nb = launch_norm2(c->stream, vint, ig, D.b, c->partial[0]);
     if (nb > 0)
         launch_reduce(c->stream, c->partial[0], nb, c->dnorm + 1);
     else
