@@ -640,10 +640,19 @@ void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     }
 }
 
+// per-workgroup sums of the squared residual that the last black pass of a
+// cycle leaves (FP64 cube cycles; see launch_colour_norm)
+struct NormOut {
+    double *partial = nullptr;
+    int blocks = 0;
+};
+
 // one red-black sweep in place: two colour passes.  pr: the red pass first
-// adds the coarse-grid correction to its nodes (the black nodes hold theirs)
+// adds the coarse-grid correction to its nodes (the black nodes hold theirs).
+// nout: the black pass also sums the squared residual of its nodes.
 template <typename T>
-void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, const Prol<T> *pr = nullptr) {
+void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, const Prol<T> *pr = nullptr,
+           NormOut *nout = nullptr) {
     if (c.gen) {
         sweep15<T>(c, V, l, zero, s);
         return;
@@ -661,6 +670,12 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, cons
             launch_colour_prol<T>(s, vgf, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, *pr);
             continue;
         }
+        if constexpr (std::is_same<T, double>::value) {
+            if (nout && colour == 1) {
+                nout->blocks = launch_colour_norm(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, nout->partial);
+                continue;
+            }
+        }
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
         launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero, zero && colour == 0);
@@ -670,8 +685,9 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, cons
 
 template <typename T>
 void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s,
-            const Prol<T> *pr = nullptr) {
-    for (int k = 0; k < nsweeps; k++) sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr);
+            const Prol<T> *pr = nullptr, NormOut *nout = nullptr) {
+    for (int k = 0; k < nsweeps; k++)
+        sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr, k == nsweeps - 1 ? nout : nullptr);
 }
 
 template <typename T>
@@ -703,8 +719,10 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
     }
 }
 
+// nout (top level, at least one post-smoothing sweep): the last black pass
+// leaves the squared residual of the black nodes (launch_colour_norm)
 template <typename T>
-void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
+void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, NormOut *nout = nullptr) {
     if (l == V.Lc) {
         coarse_solve(c, V, s);
         return;
@@ -742,9 +760,9 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
         pr.Mc = Dc.M;
         pr.prl = D.prl;
         pr.ec = vc.u;
-        smooth(c, V, l, c.d.nu_post, false, s, &pr);
+        smooth(c, V, l, c.d.nu_post, false, s, &pr, nout);
     } else {
-        smooth(c, V, l, c.d.nu_post, false, s);
+        smooth(c, V, l, c.d.nu_post, false, s, (const Prol<T> *)nullptr, nout);
     }
 }
 
@@ -766,6 +784,32 @@ void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t 
 
 // one FP64 cycle + residual norm into dnorm[slot]
 void step_fp64(hhgr_ctx &c, const HView<double> &V, hipStream_t s, int slot) {
+    // On the cube the cycle ends with a black pass, which leaves the squared
+    // residual of the black nodes: ((1 - omega) r)^2 with r its residual
+    // before the update.  The red nodes' residual then comes from a
+    // red-only residual launch, so the norm of b - A u costs one pass over
+    // the red nodes instead of one over all.
+    if (!c.gen && c.d.nu_post > 0) {
+        const LevelDev &D = c.lev[c.L];
+        const LevView<double> &v = V.lv[c.L];
+        const VolGeom vb = vgeom(D, v.vd, v.nvol, false, -1, 1);
+        const IfcGeom igb = v.ifc ? igeom_v(D, v, D.n_ifc_red, D.n_ifc, true) : ig_none();
+        VolGeom vr = vgeom(D, v.vd, v.nvol, false, -1, 0);
+        vr.cpb = D.cpb_res;
+        const IfcGeom igr = v.ifc ? igeom(D, 0, D.n_ifc_red, v.frozen, false) : ig_none();
+        if ((long long)colour_blocks(vb, igb) + colour_blocks(vr, igr) <= c.partial_cap) {
+            NormOut no;
+            no.partial = V.partial;
+            vcycle<double>(c, V, c.L, false, s, &no);
+            const int nr = launch_residual<double, double>(s, vr, igr, v.u, v.b, v.w, c.vk, D.h, (double *)nullptr,
+                                                           V.partial + no.blocks);
+            if (no.blocks + nr > 0)
+                launch_reduce(s, V.partial, no.blocks + nr, c.dnorm + slot);
+            else
+                launch_fill<double>(s, c.dnorm + slot, 1, 0.0);
+            return;
+        }
+    }
     vcycle<double>(c, V, c.L, false, s);
     finest_residual<double>(c, V, (double *)nullptr, s, c.dnorm + slot);
 }

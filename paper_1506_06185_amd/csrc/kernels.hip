@@ -194,84 +194,104 @@ __device__ __forceinline__ T coarse_corr_ifc(const T *__restrict__ ec, const int
 // red-black SOR colour pass
 // ---------------------------------------------------------------------------
 // PR: each node first receives its coarse-grid correction (the pass then
-// runs on u + P e_c at its own colour; the other colour already holds it)
-template <typename T, bool VK, bool OWN0, bool NB0, bool PR, int CPB>
+// runs on u + P e_c at its own colour; the other colour already holds it).
+// NRM: per-block partial sums of ((1 - omega) r)^2 over the updated nodes,
+// r = b - A u before the update; that is the node's residual after it (its
+// neighbours, all of the other colour, do not change in the pass).
+template <typename T, bool VK, bool OWN0, bool NB0, bool PR, bool NRM, int CPB>
 __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib, T *__restrict__ u,
                                                 const T *__restrict__ b, Weights<T> w, T h, T omega, T om_d,
-                                                Prol<T> p) {
+                                                Prol<T> p, double *__restrict__ partial) {
+    __shared__ double sh[64];
     const unsigned f = blockIdx.x;
+    double r2 = 0.0;
     if (f < (unsigned)nib) {
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
-        if (t >= ig.i1) return;
-        if (ig.frozen && ig.frozen[t]) return;
-        const long long sl = ig.base + t;
-        const T uo = OWN0 ? T(0) : PR ? u[sl] + coarse_corr_ifc(p.ec, p.prl, ig.stride, t) : u[sl];
-        T acc = T(0), diag;
-        // interface weights: variable k, or the intact-side stencils of a
-        // Dirichlet-Neumann recovery (given also when k = 1)
-        if (VK || w.wi) {
-            diag = T(0);
+        if (t < ig.i1 && !(ig.frozen && ig.frozen[t])) {
+            const long long sl = ig.base + t;
+            const T uo = OWN0 ? T(0) : PR ? u[sl] + coarse_corr_ifc(p.ec, p.prl, ig.stride, t) : u[sl];
+            T acc = T(0), diag;
+            // interface weights: variable k, or the intact-side stencils of a
+            // Dirichlet-Neumann recovery (given also when k = 1)
+            if (VK || w.wi) {
+                diag = T(0);
 #pragma unroll
-            for (int e = 0; e < 6; e++) {
-                const T we = w.wi[(long long)e * ig.stride + t];
-                diag += we;
-                // edges of weight zero (outside an intact side) are not read
-                if (!NB0 && we != T(0)) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
+                for (int e = 0; e < 6; e++) {
+                    const T we = w.wi[(long long)e * ig.stride + t];
+                    diag += we;
+                    // edges of weight zero (outside an intact side) are not read
+                    if (!NB0 && we != T(0)) acc += we * u[ig.nbr[(long long)e * ig.stride + t]];
+                }
+            } else {
+                diag = T(6) * h;
+                if (!NB0) {
+#pragma unroll
+                    for (int e = 0; e < 6; e++) acc += u[ig.nbr[(long long)e * ig.stride + t]];
+                    acc *= h;
+                }
             }
-        } else {
-            diag = T(6) * h;
-            if (!NB0) {
-#pragma unroll
-                for (int e = 0; e < 6; e++) acc += u[ig.nbr[(long long)e * ig.stride + t]];
-                acc *= h;
+            const T rr = b[sl] - (diag * uo - acc);
+            const T un = uo + omega * rr / diag;
+            u[sl] = un;
+            if (ig.gptr)
+                for (int g = ig.gptr[t]; g < ig.gptr[t + 1]; g++) u[ig.gidx[g]] = un;
+            if (NRM) {
+                const double e = (1.0 - (double)omega) * (double)rr;
+                r2 = e * e;
             }
         }
-        const T Au = diag * uo - acc;
-        const T un = uo + omega * (b[sl] - Au) / diag;
-        u[sl] = un;
-        if (ig.gptr)
-            for (int g = ig.gptr[t]; g < ig.gptr[t + 1]; g++) u[ig.gidx[g]] = un;
-        return;
-    }
-    // list holds only nodes of this colour
-    const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
-    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
-    T nv[CPB];
-    long long dst[CPB];
-    bool ok[CPB];
+    } else {
+        // list holds only nodes of this colour
+        const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
+        const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+        T nv[CPB];
+        long long dst[CPB];
+        bool ok[CPB];
 #pragma unroll
-    for (int q = 0; q < CPB; q++) {
-        ok[q] = false;
-        nv[q] = T(0);
-        dst[q] = 0;
-        LNode n;
-        if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
-        const VolDesc d = vg.vd[n.v];
-        const T *uv = u + d.vec;
-        const Nb7 nb = nb7(vg, n);
-        const int c0 = nb.c0;
-        const T uo = OWN0 ? T(0) : PR ? uv[c0] + coarse_corr(p.ec + p.vdc[n.v].vec, p.cC, p.Mc, n) : uv[c0];
-        T res;
-        if (VK) {
-            const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
-            const T wap = w0[c0], wam = w0[nb.am], wbp = w1[c0], wbm = w1[nb.bm], wcp = w2[c0], wcm = w2[nb.cm];
-            const T diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
-            const T acc = NB0 ? T(0)
-                              : wap * uv[nb.ap] + wam * uv[nb.am] + wbp * uv[nb.bp] + wbm * uv[nb.bm] +
-                                    wcp * uv[nb.cp] + wcm * uv[nb.cm];
-            res = omega * ((b + d.vec)[c0] - (diag * uo - acc)) / diag;
-        } else {
-            const T acc = NB0 ? T(0) : (((uv[nb.ap] + uv[nb.am]) + (uv[nb.bp] + uv[nb.bm])) + (uv[nb.cp] + uv[nb.cm]));
-            // diag = 6h, off-diagonal -h; om_d = omega / (6h)
-            res = om_d * ((b + d.vec)[c0] - h * (T(6) * uo - acc));
+        for (int q = 0; q < CPB; q++) {
+            ok[q] = false;
+            nv[q] = T(0);
+            dst[q] = 0;
+            LNode n;
+            if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
+            const VolDesc d = vg.vd[n.v];
+            const T *uv = u + d.vec;
+            const Nb7 nb = nb7(vg, n);
+            const int c0 = nb.c0;
+            const T uo = OWN0 ? T(0) : PR ? uv[c0] + coarse_corr(p.ec + p.vdc[n.v].vec, p.cC, p.Mc, n) : uv[c0];
+            T rr, res;
+            if (VK) {
+                const T *w0 = w.w0 + d.w, *w1 = w.w1 + d.w, *w2 = w.w2 + d.w;
+                const T wap = w0[c0], wam = w0[nb.am], wbp = w1[c0], wbm = w1[nb.bm], wcp = w2[c0], wcm = w2[nb.cm];
+                const T diag = ((wap + wam) + (wbp + wbm)) + (wcp + wcm);
+                const T acc = NB0 ? T(0)
+                                  : wap * uv[nb.ap] + wam * uv[nb.am] + wbp * uv[nb.bp] + wbm * uv[nb.bm] +
+                                        wcp * uv[nb.cp] + wcm * uv[nb.cm];
+                rr = (b + d.vec)[c0] - (diag * uo - acc);
+                res = omega * rr / diag;
+            } else {
+                const T acc =
+                    NB0 ? T(0) : (((uv[nb.ap] + uv[nb.am]) + (uv[nb.bp] + uv[nb.bm])) + (uv[nb.cp] + uv[nb.cm]));
+                // diag = 6h, off-diagonal -h; om_d = omega / (6h)
+                rr = (b + d.vec)[c0] - h * (T(6) * uo - acc);
+                res = om_d * rr;
+            }
+            if (NRM) {
+                const double e = (1.0 - (double)omega) * (double)rr;
+                r2 += e * e;
+            }
+            nv[q] = uo + res;
+            dst[q] = d.vec + c0;
+            ok[q] = true;
         }
-        nv[q] = uo + res;
-        dst[q] = d.vec + c0;
-        ok[q] = true;
-    }
 #pragma unroll
-    for (int q = 0; q < CPB; q++)
-        if (ok[q]) u[dst[q]] = nv[q];
+        for (int q = 0; q < CPB; q++)
+            if (ok[q]) u[dst[q]] = nv[q];
+    }
+    if (NRM) {
+        const double sum = block_sum_all(r2, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1592,14 +1612,15 @@ void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, co
     if (grid == 0) return;
     const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
     const Prol<T> p;
+    double *const np = nullptr;
 #define HHGR_COLOUR(VK, O0, N0)                                                                                 \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
-            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, \
-                               nib, u, b, w, th, to, tod, p);                                                 \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, false, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
+                               ig, nib, u, b, w, th, to, tod, p, np);                                         \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, ig, \
-                               nib, u, b, w, th, to, tod, p);                                                 \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, false, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
+                               ig, nib, u, b, w, th, to, tod, p, np);                                         \
     } while (0)
     if (vk) {
         if (own0 && nb0) HHGR_COLOUR(true, true, true);
@@ -1621,20 +1642,48 @@ void launch_colour_prol(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *
     const long long grid = nib + nvb;
     if (grid == 0) return;
     const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
+    double *const np = nullptr;
 #define HHGR_COLOUR_PR(VK)                                                                                      \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
-            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
-                               ig, nib, u, b, w, th, to, tod, p);                                             \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, false, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, \
+                               vg, ig, nib, u, b, w, th, to, tod, p, np);                                     \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
-                               ig, nib, u, b, w, th, to, tod, p);                                             \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, false, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, \
+                               vg, ig, nib, u, b, w, th, to, tod, p, np);                                     \
     } while (0)
     if (vk)
         HHGR_COLOUR_PR(true);
     else
         HHGR_COLOUR_PR(false);
 #undef HHGR_COLOUR_PR
+}
+
+int colour_blocks(const VolGeom &vg, const IfcGeom &ig) { return ifc_blocks(ig, vg.bs) + (int)list_blocks(vg); }
+
+int launch_colour_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, double *u, const double *b,
+                       const Weights<double> &w, bool vk, double h, double omega, double *partial) {
+    const int nib = ifc_blocks(ig, vg.bs);
+    const long long nvb = list_blocks(vg);
+    const long long grid = nib + nvb;
+    if (grid == 0) return 0;
+    const Prol<double> p;
+    const double tod = omega / (6.0 * h);
+#define HHGR_COLOUR_NRM(VK)                                                                                     \
+    do {                                                                                                       \
+        if (vg.cpb == 1)                                                                                       \
+            hipLaunchKernelGGL((k_colour<double, VK, false, false, false, true, 1>), dim3((unsigned)grid), dim3(vg.bs), \
+                               0, s, vg, ig, nib, u, b, w, h, omega, tod, p, partial);                        \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_colour<double, VK, false, false, false, true, 4>), dim3((unsigned)grid), dim3(vg.bs), \
+                               0, s, vg, ig, nib, u, b, w, h, omega, tod, p, partial);                        \
+    } while (0)
+    if (vk)
+        HHGR_COLOUR_NRM(true);
+    else
+        HHGR_COLOUR_NRM(false);
+#undef HHGR_COLOUR_NRM
+    return (int)grid;
 }
 
 template <typename T, typename TO>

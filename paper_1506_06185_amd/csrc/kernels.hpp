@@ -114,6 +114,17 @@ template <typename T>
 void launch_colour_prol(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w,
                         bool vk, double h, double omega, const Prol<T> &p);
 
+// number of workgroups of a colour pass (volume list and interface part)
+int colour_blocks(const VolGeom &vg, const IfcGeom &ig);
+
+// FP64 colour pass that also leaves, per workgroup, the sum of
+// ((1 - omega) r)^2 over its nodes in partial (r = b - A u before each
+// update: after the pass, the residual of each updated node is (1 - omega) r,
+// since its neighbours are of the other colour).  Returns the number of
+// workgroups, colour_blocks(vg, ig).
+int launch_colour_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, double *u, const double *b,
+                       const Weights<double> &w, bool vk, double h, double omega, double *partial);
+
 // r = b - A u on volume interiors and interface nodes; r (of type TO) may be
 // nullptr; partial (one double per block) receives block sums of r^2 if not
 // nullptr.  Returns the number of blocks launched.

@@ -24,6 +24,15 @@ static int ifc_blocks_of(const IfcGeom &ig, int bs) {
 template <typename T>
 void launch_colour(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
                    double, bool, bool) {}
+int colour_blocks(const VolGeom &vg, const IfcGeom &ig) {
+    return ifc_blocks_of(ig, vg.bs) + (int)list_blocks_of(vg, vg.cpb);
+}
+int launch_colour_norm(hipStream_t, const VolGeom &vg, const IfcGeom &ig, double *, const double *,
+                       const Weights<double> &, bool, double, double, double *partial) {
+    const int nb = colour_blocks(vg, ig);
+    for (int q = 0; q < nb; q++) partial[q] = 0.0;  // the residual launch that follows carries g_mock_res2
+    return nb;
+}
 void launch_mass_grid(hipStream_t, int, double, const double *, double *) {}
 int launch_norm2(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const double *, double *partial) {
     const long long nb = ifc_blocks_of(ig, vg.bs) + list_blocks_of(vg, 4);
