@@ -649,10 +649,11 @@ struct NormOut {
 
 // one red-black sweep in place: two colour passes.  pr: the red pass first
 // adds the coarse-grid correction to its nodes (the black nodes hold theirs).
-// nout: the black pass also sums the squared residual of its nodes.
+// nout: the black pass also sums the squared residual of its nodes; rout:
+// the black pass also writes the residual of its nodes there.
 template <typename T>
 void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, const Prol<T> *pr = nullptr,
-           NormOut *nout = nullptr) {
+           NormOut *nout = nullptr, T *rout = nullptr) {
     if (c.gen) {
         sweep15<T>(c, V, l, zero, s);
         return;
@@ -676,6 +677,10 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, cons
                 continue;
             }
         }
+        if (rout && colour == 1 && !zero) {
+            launch_colour_res<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, rout);
+            continue;
+        }
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
         launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero, zero && colour == 0);
@@ -685,9 +690,10 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, cons
 
 template <typename T>
 void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s,
-            const Prol<T> *pr = nullptr, NormOut *nout = nullptr) {
+            const Prol<T> *pr = nullptr, NormOut *nout = nullptr, T *rout = nullptr) {
     for (int k = 0; k < nsweeps; k++)
-        sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr, k == nsweeps - 1 ? nout : nullptr);
+        sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr, k == nsweeps - 1 ? nout : nullptr,
+              k == nsweeps - 1 ? rout : nullptr);
 }
 
 template <typename T>
@@ -731,10 +737,14 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, Nor
     LevelDev &Dc = c.lev[l - 1];
     const LevView<T> &v = V.lv[l];
     const LevView<T> &vc = V.lv[l - 1];
-    smooth(c, V, l, c.d.nu_pre, zero, s);
+    // On the cube the last pre-smoothing pass (black, not the first pass from
+    // zero) writes the residual of the black nodes, and the residual launch
+    // covers the red nodes only
+    const bool split_res = !c.gen && (c.d.nu_pre >= 2 || (c.d.nu_pre == 1 && !zero));
+    smooth(c, V, l, c.d.nu_pre, zero, s, (const Prol<T> *)nullptr, (NormOut *)nullptr, split_res ? v.r : nullptr);
     if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, view_len(c, V, l), T(0));
-    VolGeom vg = vgeom(D, v.vd, v.nvol, false);
-    const IfcGeom ig = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
+    VolGeom vg = vgeom(D, v.vd, v.nvol, false, -1, split_res ? 0 : -1);
+    const IfcGeom ig = v.ifc ? igeom(D, 0, split_res ? D.n_ifc_red : D.n_ifc, v.frozen, false) : ig_none();
     vg.cpb = D.cpb_res;
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();

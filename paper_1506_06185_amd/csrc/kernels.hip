@@ -195,13 +195,15 @@ __device__ __forceinline__ T coarse_corr_ifc(const T *__restrict__ ec, const int
 // ---------------------------------------------------------------------------
 // PR: each node first receives its coarse-grid correction (the pass then
 // runs on u + P e_c at its own colour; the other colour already holds it).
-// NRM: per-block partial sums of ((1 - omega) r)^2 over the updated nodes,
-// r = b - A u before the update; that is the node's residual after it (its
-// neighbours, all of the other colour, do not change in the pass).
-template <typename T, bool VK, bool OWN0, bool NB0, bool PR, bool NRM, int CPB>
+// TAIL: with r = b - A u of a node before its update, (1 - omega) r is the
+// node's residual after the pass (its neighbours, all of the other colour,
+// do not change in it).  kTailNorm: per-block partial sums of its square;
+// kTailRes: it is written to rout at the node's slot.
+constexpr int kTailNone = 0, kTailNorm = 1, kTailRes = 2;
+template <typename T, bool VK, bool OWN0, bool NB0, bool PR, int TAIL, int CPB>
 __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib, T *__restrict__ u,
                                                 const T *__restrict__ b, Weights<T> w, T h, T omega, T om_d,
-                                                Prol<T> p, double *__restrict__ partial) {
+                                                Prol<T> p, double *__restrict__ partial, T *__restrict__ rout) {
     __shared__ double sh[64];
     const unsigned f = blockIdx.x;
     double r2 = 0.0;
@@ -235,22 +237,24 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
             u[sl] = un;
             if (ig.gptr)
                 for (int g = ig.gptr[t]; g < ig.gptr[t + 1]; g++) u[ig.gidx[g]] = un;
-            if (NRM) {
+            if (TAIL == kTailNorm) {
                 const double e = (1.0 - (double)omega) * (double)rr;
                 r2 = e * e;
             }
+            if (TAIL == kTailRes) rout[sl] = (T(1) - omega) * rr;
         }
     } else {
         // list holds only nodes of this colour
         const unsigned per_vol = list_blocks_per_vol<CPB>(vg);
         const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
-        T nv[CPB];
+        T nv[CPB], rv[CPB];
         long long dst[CPB];
         bool ok[CPB];
 #pragma unroll
         for (int q = 0; q < CPB; q++) {
             ok[q] = false;
             nv[q] = T(0);
+            rv[q] = T(0);
             dst[q] = 0;
             LNode n;
             if (!list_node<CPB>(vg, blk, per_vol, q, n)) continue;
@@ -276,19 +280,23 @@ __global__ void __launch_bounds__(512) k_colour(VolGeom vg, IfcGeom ig, int nib,
                 rr = (b + d.vec)[c0] - h * (T(6) * uo - acc);
                 res = om_d * rr;
             }
-            if (NRM) {
+            if (TAIL == kTailNorm) {
                 const double e = (1.0 - (double)omega) * (double)rr;
                 r2 += e * e;
             }
+            if (TAIL == kTailRes) rv[q] = (T(1) - omega) * rr;
             nv[q] = uo + res;
             dst[q] = d.vec + c0;
             ok[q] = true;
         }
 #pragma unroll
         for (int q = 0; q < CPB; q++)
-            if (ok[q]) u[dst[q]] = nv[q];
+            if (ok[q]) {
+                u[dst[q]] = nv[q];
+                if (TAIL == kTailRes) rout[dst[q]] = rv[q];
+            }
     }
-    if (NRM) {
+    if (TAIL == kTailNorm) {
         const double sum = block_sum_all(r2, sh);
         if (threadIdx.x == 0) partial[blockIdx.x] = sum;
     }
@@ -1613,14 +1621,15 @@ void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, co
     const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
     const Prol<T> p;
     double *const np = nullptr;
+    T *const nr = nullptr;
 #define HHGR_COLOUR(VK, O0, N0)                                                                                 \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
-            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, false, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
-                               ig, nib, u, b, w, th, to, tod, p, np);                                         \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, kTailNone, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, \
+                               vg, ig, nib, u, b, w, th, to, tod, p, np, nr);                                 \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, false, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, vg, \
-                               ig, nib, u, b, w, th, to, tod, p, np);                                         \
+            hipLaunchKernelGGL((k_colour<T, VK, O0, N0, false, kTailNone, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, \
+                               vg, ig, nib, u, b, w, th, to, tod, p, np, nr);                                 \
     } while (0)
     if (vk) {
         if (own0 && nb0) HHGR_COLOUR(true, true, true);
@@ -1643,14 +1652,15 @@ void launch_colour_prol(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *
     if (grid == 0) return;
     const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
     double *const np = nullptr;
+    T *const nr = nullptr;
 #define HHGR_COLOUR_PR(VK)                                                                                      \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
-            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, false, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, s, \
-                               vg, ig, nib, u, b, w, th, to, tod, p, np);                                     \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, kTailNone, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, \
+                               s, vg, ig, nib, u, b, w, th, to, tod, p, np, nr);                              \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, false, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, s, \
-                               vg, ig, nib, u, b, w, th, to, tod, p, np);                                     \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, true, kTailNone, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, \
+                               s, vg, ig, nib, u, b, w, th, to, tod, p, np, nr);                              \
     } while (0)
     if (vk)
         HHGR_COLOUR_PR(true);
@@ -1669,14 +1679,15 @@ int launch_colour_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, doub
     if (grid == 0) return 0;
     const Prol<double> p;
     const double tod = omega / (6.0 * h);
+    double *const nr = nullptr;
 #define HHGR_COLOUR_NRM(VK)                                                                                     \
     do {                                                                                                       \
         if (vg.cpb == 1)                                                                                       \
-            hipLaunchKernelGGL((k_colour<double, VK, false, false, false, true, 1>), dim3((unsigned)grid), dim3(vg.bs), \
-                               0, s, vg, ig, nib, u, b, w, h, omega, tod, p, partial);                        \
+            hipLaunchKernelGGL((k_colour<double, VK, false, false, false, kTailNorm, 1>), dim3((unsigned)grid),      \
+                               dim3(vg.bs), 0, s, vg, ig, nib, u, b, w, h, omega, tod, p, partial, nr);       \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_colour<double, VK, false, false, false, true, 4>), dim3((unsigned)grid), dim3(vg.bs), \
-                               0, s, vg, ig, nib, u, b, w, h, omega, tod, p, partial);                        \
+            hipLaunchKernelGGL((k_colour<double, VK, false, false, false, kTailNorm, 4>), dim3((unsigned)grid),      \
+                               dim3(vg.bs), 0, s, vg, ig, nib, u, b, w, h, omega, tod, p, partial, nr);       \
     } while (0)
     if (vk)
         HHGR_COLOUR_NRM(true);
@@ -1684,6 +1695,32 @@ int launch_colour_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, doub
         HHGR_COLOUR_NRM(false);
 #undef HHGR_COLOUR_NRM
     return (int)grid;
+}
+
+template <typename T>
+void launch_colour_res(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w,
+                       bool vk, double h, double omega, T *r) {
+    const int nib = ifc_blocks(ig, vg.bs);
+    const long long nvb = list_blocks(vg);
+    const long long grid = nib + nvb;
+    if (grid == 0) return;
+    const T th = (T)h, to = (T)omega, tod = (T)(omega / (6.0 * h));
+    const Prol<T> p;
+    double *const np = nullptr;
+#define HHGR_COLOUR_RES(VK)                                                                                     \
+    do {                                                                                                       \
+        if (vg.cpb == 1)                                                                                       \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, false, kTailRes, 1>), dim3((unsigned)grid), dim3(vg.bs), 0, \
+                               s, vg, ig, nib, u, b, w, th, to, tod, p, np, r);                               \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_colour<T, VK, false, false, false, kTailRes, 4>), dim3((unsigned)grid), dim3(vg.bs), 0, \
+                               s, vg, ig, nib, u, b, w, th, to, tod, p, np, r);                               \
+    } while (0)
+    if (vk)
+        HHGR_COLOUR_RES(true);
+    else
+        HHGR_COLOUR_RES(false);
+#undef HHGR_COLOUR_RES
 }
 
 template <typename T, typename TO>
@@ -2080,6 +2117,10 @@ template void launch_colour<double>(hipStream_t, const VolGeom &, const IfcGeom 
                                     const Weights<double> &, bool, double, double, bool, bool);
 template void launch_colour<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
                                    const Weights<float> &, bool, double, double, bool, bool);
+template void launch_colour_res<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
+                                        const Weights<double> &, bool, double, double, double *);
+template void launch_colour_res<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                       const Weights<float> &, bool, double, double, float *);
 template void launch_colour_prol<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
                                          const Weights<double> &, bool, double, double, const Prol<double> &);
 template void launch_colour_prol<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,

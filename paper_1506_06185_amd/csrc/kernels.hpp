@@ -125,6 +125,14 @@ int colour_blocks(const VolGeom &vg, const IfcGeom &ig);
 int launch_colour_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, double *u, const double *b,
                        const Weights<double> &w, bool vk, double h, double omega, double *partial);
 
+// colour pass that also writes, at each updated node, its residual after the
+// pass to r: (1 - omega) (b - A u) with A u taken before the update (the
+// node's neighbours are of the other colour and do not change).  The other
+// colour's entries of r are left as they are.
+template <typename T>
+void launch_colour_res(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w,
+                       bool vk, double h, double omega, T *r);
+
 // r = b - A u on volume interiors and interface nodes; r (of type TO) may be
 // nullptr; partial (one double per block) receives block sums of r^2 if not
 // nullptr.  Returns the number of blocks launched.

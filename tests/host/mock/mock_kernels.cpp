@@ -24,6 +24,13 @@ static int ifc_blocks_of(const IfcGeom &ig, int bs) {
 template <typename T>
 void launch_colour(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
                    double, bool, bool) {}
+template <typename T>
+void launch_colour_res(hipStream_t, const VolGeom &, const IfcGeom &, T *, const T *, const Weights<T> &, bool, double,
+                       double, T *) {}
+template void launch_colour_res<double>(hipStream_t, const VolGeom &, const IfcGeom &, double *, const double *,
+                                        const Weights<double> &, bool, double, double, double *);
+template void launch_colour_res<float>(hipStream_t, const VolGeom &, const IfcGeom &, float *, const float *,
+                                       const Weights<float> &, bool, double, double, float *);
 int colour_blocks(const VolGeom &vg, const IfcGeom &ig) {
     return ifc_blocks_of(ig, vg.bs) + (int)list_blocks_of(vg, vg.cpb);
 }
