@@ -793,12 +793,13 @@ void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t 
 }
 
 // one FP64 cycle + residual norm into dnorm[slot]
-void step_fp64(hhgr_ctx &c, const HView<double> &V, hipStream_t s, int slot) {
-    // On the cube the cycle ends with a black pass, which leaves the squared
-    // residual of the black nodes: ((1 - omega) r)^2 with r its residual
-    // before the update.  The red nodes' residual then comes from a
-    // red-only residual launch, so the norm of b - A u costs one pass over
-    // the red nodes instead of one over all.
+// one FP64 cycle on view V and ||b - A u||^2 on its finest level into *dst.
+// On the cube the cycle ends with a black pass, which leaves the squared
+// residual of the black nodes: ((1 - omega) r)^2 with r its residual before
+// the update.  The red nodes' residual then comes from a red-only residual
+// launch, so the norm costs one pass over the red nodes instead of one over
+// all (frozen masters are left out on both sides, as in the full residual).
+void cycle_and_norm(hhgr_ctx &c, const HView<double> &V, hipStream_t s, double *dst) {
     if (!c.gen && c.d.nu_post > 0) {
         const LevelDev &D = c.lev[c.L];
         const LevView<double> &v = V.lv[c.L];
@@ -814,14 +815,18 @@ void step_fp64(hhgr_ctx &c, const HView<double> &V, hipStream_t s, int slot) {
             const int nr = launch_residual<double, double>(s, vr, igr, v.u, v.b, v.w, c.vk, D.h, (double *)nullptr,
                                                            V.partial + no.blocks);
             if (no.blocks + nr > 0)
-                launch_reduce(s, V.partial, no.blocks + nr, c.dnorm + slot);
+                launch_reduce(s, V.partial, no.blocks + nr, dst);
             else
-                launch_fill<double>(s, c.dnorm + slot, 1, 0.0);
+                launch_fill<double>(s, dst, 1, 0.0);
             return;
         }
     }
     vcycle<double>(c, V, c.L, false, s);
-    finest_residual<double>(c, V, (double *)nullptr, s, c.dnorm + slot);
+    finest_residual<double>(c, V, (double *)nullptr, s, dst);
+}
+
+void step_fp64(hhgr_ctx &c, const HView<double> &V, hipStream_t s, int slot) {
+    cycle_and_norm(c, V, s, c.dnorm + slot);
 }
 
 // mixed step: e32 = V32(b32) from zero, u += e32, then b32 = round32(b - A u) and its norm
@@ -986,9 +991,10 @@ void dd_intact_step(hhgr_ctx &c, hipStream_t s, bool first, bool norm, int slot)
         HView<float> V32 = global_view<float>(c, true, 0);
         if (first) finest_residual<float>(c, V64, c.lev[c.L].b32, s, c.dnorm + slot);
         step_mixed(c, V64, V32, s, slot);
+    } else if (norm) {
+        cycle_and_norm(c, V64, s, c.dnorm + slot);
     } else {
         vcycle<double>(c, V64, c.L, false, s);
-        if (norm) finest_residual<double>(c, V64, (double *)nullptr, s, c.dnorm + slot);
     }
 }
 
