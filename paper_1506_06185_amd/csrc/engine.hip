@@ -262,11 +262,22 @@ void carve(hhgr_ctx &c, Carver &cv) {
         if (l < c.L) D.rst = cv.take<int>(15 * (size_t)T.n_ifc);
         if (l == c.L || c.gen) D.nb15 = cv.take<int>(15 * (size_t)T.n_ifc);
         if (c.gen) {
+            // the class lists (nodes, masters) back to back, so that classes
+            // 0..2 form a prefix of each
+            size_t nq_all = 0, nf_all = 0;
             for (int q = 0; q < 4; q++) {
                 D.nqlist[q] = (int)T.qlist[q].size();
                 D.nifcq[q] = (int)T.ifcq[q].size();
-                D.qlist[q] = cv.take<unsigned>(D.nqlist[q]);
-                D.ifcq[q] = cv.take<int>(D.nifcq[q]);
+                nq_all += D.nqlist[q];
+                nf_all += D.nifcq[q];
+            }
+            unsigned *qall = cv.take<unsigned>(nq_all);
+            int *fall = cv.take<int>(nf_all);
+            for (int q = 0, oq = 0, of = 0; q < 4; q++) {
+                D.qlist[q] = qall ? qall + oq : nullptr;
+                D.ifcq[q] = fall ? fall + of : nullptr;
+                oq += D.nqlist[q];
+                of += D.nifcq[q];
             }
             D.rowN15 = cv.take<int>(16 * T.rowN15.size());
             D.w15 = cv.take<double>(15 * (size_t)c.n_tets);
@@ -621,10 +632,19 @@ long long view_len(const hhgr_ctx &c, const HView<T> &V, int l) {
     return V.local && l < c.L ? (long long)std::max(c.d.max_faults, 1) * D.C_pad : D.n_slots;
 }
 
+// per-workgroup sums of the squared residual that the last black pass (or
+// class-3 pass) of an FP64 cycle leaves (see launch_colour_norm)
+struct NormOut {
+    double *partial = nullptr;
+    int blocks = 0;
+};
+
 // general macro meshes: one 4-colour sweep, classes 0, 1, 2, 3 (a start
-// from zero clears the level's vector first)
+// from zero clears the level's vector first).  The class-3 pass also sums
+// the squared residual of its nodes (nout) or writes it to rout.
 template <typename T>
-void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
+void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, NormOut *nout = nullptr,
+             T *rout = nullptr) {
     const LevelDev &D = c.lev[l];
     const LevView<T> &v = V.lv[l];
     if (zero) launch_fill<T>(s, v.u, view_len(c, V, l), T(0));
@@ -633,6 +653,16 @@ void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
         vg.list = D.qlist[q];
         vg.nlist = D.nqlist[q];
         const IfcGeom ig = v.ifc ? igeom_v(D, v, 0, D.n_ifc, true) : ig_none();
+        if constexpr (std::is_same<T, double>::value) {
+            if (nout && q == 3) {
+                nout->blocks = launch_colour15_norm(s, vg, ig, gen15v(D, v, q), v.u, v.b, c.d.omega, nout->partial);
+                continue;
+            }
+        }
+        if (rout && q == 3) {
+            launch_colour15_res<T>(s, vg, ig, gen15v(D, v, q), v.u, v.b, c.d.omega, rout);
+            continue;
+        }
         const bool timed = c.timing && V.timed && l == c.L;
         if (timed) timed_begin(c, s);
         launch_colour15<T>(s, vg, ig, gen15v(D, v, q), v.u, v.b, c.d.omega);
@@ -640,12 +670,15 @@ void sweep15(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s) {
     }
 }
 
-// per-workgroup sums of the squared residual that the last black pass of a
-// cycle leaves (FP64 cube cycles; see launch_colour_norm)
-struct NormOut {
-    double *partial = nullptr;
-    int blocks = 0;
-};
+// general macro meshes: the classes 0..2 (whose lists are stored back to
+// back) as one node list and one master list, for residuals after a sweep
+template <typename T>
+void classes012(const LevelDev &D, const LevView<T> &v, VolGeom &vg, Gen15 &g) {
+    vg.list = D.qlist[0];
+    vg.nlist = D.nqlist[0] + D.nqlist[1] + D.nqlist[2];
+    g.ifcq = v.ifc ? D.ifcq[0] : nullptr;
+    g.nq = v.ifc ? D.nifcq[0] + D.nifcq[1] + D.nifcq[2] : 0;
+}
 
 // one red-black sweep in place: two colour passes.  pr: the red pass first
 // adds the coarse-grid correction to its nodes (the black nodes hold theirs).
@@ -655,7 +688,7 @@ template <typename T>
 void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, const Prol<T> *pr = nullptr,
            NormOut *nout = nullptr, T *rout = nullptr) {
     if (c.gen) {
-        sweep15<T>(c, V, l, zero, s);
+        sweep15<T>(c, V, l, zero, s, nout, rout);
         return;
     }
     const LevelDev &D = c.lev[l];
@@ -740,17 +773,21 @@ void vcycle(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, Nor
     // On the cube the last pre-smoothing pass (black, not the first pass from
     // zero) writes the residual of the black nodes, and the residual launch
     // covers the red nodes only
-    const bool split_res = !c.gen && (c.d.nu_pre >= 2 || (c.d.nu_pre == 1 && !zero));
+    // (a general mesh's class-3 pass has no zero-start variant)
+    const bool split_res = c.gen ? c.d.nu_pre >= 1 : (c.d.nu_pre >= 2 || (c.d.nu_pre == 1 && !zero));
     smooth(c, V, l, c.d.nu_pre, zero, s, (const Prol<T> *)nullptr, (NormOut *)nullptr, split_res ? v.r : nullptr);
     if (c.d.nu_pre == 0 && zero) launch_fill<T>(s, v.u, view_len(c, V, l), T(0));
-    VolGeom vg = vgeom(D, v.vd, v.nvol, false, -1, split_res ? 0 : -1);
-    const IfcGeom ig = v.ifc ? igeom(D, 0, split_res ? D.n_ifc_red : D.n_ifc, v.frozen, false) : ig_none();
+    VolGeom vg = vgeom(D, v.vd, v.nvol, false, -1, split_res && !c.gen ? 0 : -1);
+    const IfcGeom ig =
+        v.ifc ? igeom(D, 0, split_res && !c.gen ? D.n_ifc_red : D.n_ifc, v.frozen, false) : ig_none();
     vg.cpb = D.cpb_res;
     const VolGeom vgc = vgeom(Dc, vc.vd, vc.nvol, false);
     const IfcGeom igc = vc.ifc ? igeom(Dc, 0, Dc.n_ifc, vc.frozen, false) : ig_none();
-    if (c.gen)
-        launch_residual15<T, T>(s, vg, ig, gen15v(D, v, -1), v.u, v.b, v.r, nullptr);
-    else
+    if (c.gen) {
+        Gen15 g = gen15v(D, v, -1);
+        if (split_res) classes012(D, v, vg, g);
+        launch_residual15<T, T>(s, vg, ig, g, v.u, v.b, v.r, nullptr);
+    } else
         launch_residual<T, T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, v.r, nullptr);
     launch_restrict<T>(s, vgc, v.vd, D.rowC, igc, Dc.rst, v.r, vc.b);
     vcycle(c, V, l - 1, true, s);
@@ -799,6 +836,7 @@ void finest_residual(hhgr_ctx &c, const HView<double> &V, TO *rout, hipStream_t 
 // the update.  The red nodes' residual then comes from a red-only residual
 // launch, so the norm costs one pass over the red nodes instead of one over
 // all (frozen masters are left out on both sides, as in the full residual).
+// On a general mesh the class-3 pass and classes 0..2 play those parts.
 void cycle_and_norm(hhgr_ctx &c, const HView<double> &V, hipStream_t s, double *dst) {
     if (!c.gen && c.d.nu_post > 0) {
         const LevelDev &D = c.lev[c.L];
@@ -814,6 +852,31 @@ void cycle_and_norm(hhgr_ctx &c, const HView<double> &V, hipStream_t s, double *
             vcycle<double>(c, V, c.L, false, s, &no);
             const int nr = launch_residual<double, double>(s, vr, igr, v.u, v.b, v.w, c.vk, D.h, (double *)nullptr,
                                                            V.partial + no.blocks);
+            if (no.blocks + nr > 0)
+                launch_reduce(s, V.partial, no.blocks + nr, dst);
+            else
+                launch_fill<double>(s, dst, 1, 0.0);
+            return;
+        }
+    }
+    if (c.gen && c.d.nu_post > 0) {
+        // general mesh: the last class-3 pass and a residual over classes 0..2
+        const LevelDev &D = c.lev[c.L];
+        const LevView<double> &v = V.lv[c.L];
+        VolGeom v3 = vgeom(D, v.vd, v.nvol, false);
+        v3.list = D.qlist[3];
+        v3.nlist = D.nqlist[3];
+        const Gen15 g3 = gen15v(D, v, 3);
+        VolGeom vr = vgeom(D, v.vd, v.nvol, false);
+        Gen15 gr = gen15v(D, v, -1);
+        classes012(D, v, vr, gr);
+        const IfcGeom igr = v.ifc ? igeom(D, 0, D.n_ifc, v.frozen, false) : ig_none();
+        if ((long long)colour15_blocks(v3, g3) + colour15_blocks(vr, gr) <= c.partial_cap) {
+            NormOut no;
+            no.partial = V.partial;
+            vcycle<double>(c, V, c.L, false, s, &no);
+            const int nr =
+                launch_residual15<double, double>(s, vr, igr, gr, v.u, v.b, (double *)nullptr, V.partial + no.blocks);
             if (no.blocks + nr > 0)
                 launch_reduce(s, V.partial, no.blocks + nr, dst);
             else

@@ -554,35 +554,58 @@ __device__ __forceinline__ T volume_Au(const VolGeom &vg, const Gen15 &g, const 
 }
 
 // VKV: per-node volume weights (wv), VKI: per-master entries (wi15)
-template <typename T, bool VKV, bool VKI>
+// TAIL as in k_colour: (1 - omega) r is a node's residual after its class
+// pass (no 15-point stencil couples two nodes of one class)
+template <typename T, bool VKV, bool VKI, int TAIL>
 __global__ void __launch_bounds__(512) k_colour15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, T *__restrict__ u,
-                                                  const T *__restrict__ b, T omega) {
+                                                  const T *__restrict__ b, T omega, double *__restrict__ partial,
+                                                  T *__restrict__ rout) {
+    __shared__ double sh[64];
     const unsigned f = blockIdx.x;
+    double r2 = 0.0;
     if (f < (unsigned)nib) {
         const int q = (int)(f * blockDim.x + threadIdx.x);
-        if (q >= g.nq) return;
-        const int t = g.ifcq[q];
-        if (ig.frozen && ig.frozen[t]) return;
-        const long long sl = ig.base + t;
-        const T uo = u[sl];
-        T diag;
-        const T Au = master_Au<T, VKI>(ig, g, u, t, uo, diag);
-        const T un = uo + omega * (b[sl] - Au) / diag;
-        u[sl] = un;
-        if (ig.gptr)
-            for (int gq = ig.gptr[t]; gq < ig.gptr[t + 1]; gq++) u[ig.gidx[gq]] = un;
-        return;
+        if (q < g.nq) {
+            const int t = g.ifcq[q];
+            if (!(ig.frozen && ig.frozen[t])) {
+                const long long sl = ig.base + t;
+                const T uo = u[sl];
+                T diag;
+                const T rr = b[sl] - master_Au<T, VKI>(ig, g, u, t, uo, diag);
+                const T un = uo + omega * rr / diag;
+                u[sl] = un;
+                if (ig.gptr)
+                    for (int gq = ig.gptr[t]; gq < ig.gptr[t + 1]; gq++) u[ig.gidx[gq]] = un;
+                if (TAIL == kTailNorm) {
+                    const double e = (1.0 - (double)omega) * (double)rr;
+                    r2 = e * e;
+                }
+                if (TAIL == kTailRes) rout[sl] = (T(1) - omega) * rr;
+            }
+        }
+    } else {
+        const unsigned per_vol = list_blocks_per_vol<1>(vg);
+        const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
+        LNode nd;
+        if (list_node<1>(vg, blk, per_vol, 0, nd)) {
+            const VolDesc d = vg.vd[nd.v];
+            T *uv = u + d.vec;
+            int c0;
+            T uo, diag;
+            const T Au = volume_Au<T, VKV>(vg, g, d, nd, uv, c0, uo, diag);
+            const T rr = (b + d.vec)[c0] - Au;
+            uv[c0] = uo + omega * rr / diag;
+            if (TAIL == kTailNorm) {
+                const double e = (1.0 - (double)omega) * (double)rr;
+                r2 = e * e;
+            }
+            if (TAIL == kTailRes) (rout + d.vec)[c0] = (T(1) - omega) * rr;
+        }
     }
-    const unsigned per_vol = list_blocks_per_vol<1>(vg);
-    const unsigned blk = block_order(f - nib, gridDim.x - nib, vg.remap);
-    LNode nd;
-    if (!list_node<1>(vg, blk, per_vol, 0, nd)) return;
-    const VolDesc d = vg.vd[nd.v];
-    T *uv = u + d.vec;
-    int c0;
-    T uo, diag;
-    const T Au = volume_Au<T, VKV>(vg, g, d, nd, uv, c0, uo, diag);
-    uv[c0] = uo + omega * ((b + d.vec)[c0] - Au) / diag;
+    if (TAIL == kTailNorm) {
+        const double sum = block_sum_all(r2, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+    }
 }
 
 // r = b - A u in the value type T, written as TO
@@ -594,8 +617,10 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
     const unsigned f = blockIdx.x;
     double acc2 = 0.0;
     if (f < (unsigned)nib) {
-        const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
-        if (t < ig.i1 && !(ig.frozen && ig.frozen[t])) {
+        // the masters g.ifcq[0 .. nq) if listed, else [ig.i0, ig.i1)
+        const int q = (int)(f * blockDim.x + threadIdx.x);
+        const int t = g.ifcq ? (q < g.nq ? g.ifcq[q] : -1) : (ig.i0 + q < ig.i1 ? ig.i0 + q : -1);
+        if (t >= 0 && !(ig.frozen && ig.frozen[t])) {
             const long long sl = ig.base + t;
             T diag;
             const T res = b[sl] - master_Au<T, VKI>(ig, g, u, t, u[sl], diag);
@@ -1926,19 +1951,42 @@ void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, dou
     hipLaunchKernelGGL(k_ifc_weights, dim3((n_ifc + 255) / 256), dim3(256), 0, s, n_ifc, ifc_xyz, N, h, k, wi);
 }
 
+int colour15_blocks(const VolGeom &vg, const Gen15 &g) {
+    const int nib = g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0;
+    return nib + (int)list_blocks(vg, 1);
+}
+
+template <typename T, int TAIL>
+static int colour15_tail(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
+                         double omega, double *partial, T *r) {
+    const int nib = g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0;
+    const long long grid = nib + list_blocks(vg, 1);
+    if (grid == 0) return 0;
+    const dim3 gd((unsigned)grid), bd(vg.bs);
+    if (g.wv)
+        hipLaunchKernelGGL((k_colour15<T, true, true, TAIL>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega, partial, r);
+    else if (g.wi15)
+        hipLaunchKernelGGL((k_colour15<T, false, true, TAIL>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega, partial, r);
+    else
+        hipLaunchKernelGGL((k_colour15<T, false, false, TAIL>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega, partial, r);
+    return (int)grid;
+}
+
 template <typename T>
 void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
                      double omega) {
-    const int nib = g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0;
-    const long long grid = nib + list_blocks(vg, 1);
-    if (grid == 0) return;
-    const dim3 gd((unsigned)grid), bd(vg.bs);
-    if (g.wv)
-        hipLaunchKernelGGL((k_colour15<T, true, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega);
-    else if (g.wi15)
-        hipLaunchKernelGGL((k_colour15<T, false, true>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega);
-    else
-        hipLaunchKernelGGL((k_colour15<T, false, false>), gd, bd, 0, s, vg, ig, g, nib, u, b, (T)omega);
+    colour15_tail<T, kTailNone>(s, vg, ig, g, u, b, omega, nullptr, nullptr);
+}
+
+int launch_colour15_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, double *u,
+                         const double *b, double omega, double *partial) {
+    return colour15_tail<double, kTailNorm>(s, vg, ig, g, u, b, omega, partial, nullptr);
+}
+
+template <typename T>
+void launch_colour15_res(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
+                         double omega, T *r) {
+    colour15_tail<T, kTailRes>(s, vg, ig, g, u, b, omega, nullptr, r);
 }
 
 template <typename T, typename TO, bool VKV, bool VKI>
@@ -1955,7 +2003,7 @@ static void residual15(hipStream_t s, dim3 gd, dim3 bd, const VolGeom &vg, const
 template <typename T, typename TO>
 int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const T *u, const T *b,
                       TO *r, double *partial) {
-    const int nib = ifc_blocks(ig, vg.bs);
+    const int nib = g.ifcq ? (g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0) : ifc_blocks(ig, vg.bs);
     const long long grid = nib + list_blocks(vg, 1);
     if (grid == 0) return 0;
     const dim3 gd((unsigned)grid), bd(vg.bs);
@@ -1972,6 +2020,10 @@ template void launch_colour15<double>(hipStream_t, const VolGeom &, const IfcGeo
                                       const double *, double);
 template void launch_colour15<float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, float *,
                                      const float *, double);
+template void launch_colour15_res<double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, double *,
+                                          const double *, double, double *);
+template void launch_colour15_res<float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, float *,
+                                         const float *, double, float *);
 template int launch_residual15<double, double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,
                                                const double *, const double *, double *, double *);
 template int launch_residual15<double, float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &,

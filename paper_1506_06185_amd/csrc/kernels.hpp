@@ -224,8 +224,20 @@ void launch_ifc_weights(hipStream_t s, int n_ifc, const int *ifc_xyz, int N, dou
 template <typename T>
 void launch_colour15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
                      double omega);
-// general macro meshes: r = b - A u over the interior list of vg and every
-// master of ig (r and/or partial sums of r^2 per block, as launch_residual)
+// workgroups of such a class pass
+int colour15_blocks(const VolGeom &vg, const Gen15 &g);
+// class pass that also leaves per-workgroup sums of ((1 - omega) r)^2 over
+// its nodes (FP64), or writes (1 - omega) r to r at its nodes: with r the
+// residual before the update, that is the node's residual after the pass
+// (no 15-point stencil couples two nodes of one class)
+int launch_colour15_norm(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, double *u,
+                         const double *b, double omega, double *partial);
+template <typename T>
+void launch_colour15_res(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, T *u, const T *b,
+                         double omega, T *r);
+// general macro meshes: r = b - A u over the interior list of vg and the
+// masters g.ifcq[0 .. g.nq) if g.ifcq is set, else every master of ig (r
+// and/or partial sums of r^2 per block, as launch_residual)
 template <typename T, typename TO>
 int launch_residual15(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, const Gen15 &g, const T *u, const T *b,
                       TO *r, double *partial);

@@ -106,6 +106,21 @@ void launch_coarse_vals(hipStream_t, int, const int *, const int *, int, double,
 void launch_dirichlet_load(hipStream_t, int, double, const double *, const double *, double *) {}
 template <typename T>
 void launch_colour15(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, T *, const T *, double) {}
+int colour15_blocks(const VolGeom &vg, const Gen15 &g) {
+    return (g.nq > 0 ? (((g.nq + vg.bs - 1) / vg.bs + 7) & ~7) : 0) + (int)list_blocks_of(vg, 1);
+}
+int launch_colour15_norm(hipStream_t, const VolGeom &vg, const IfcGeom &, const Gen15 &g, double *, const double *,
+                         double, double *partial) {
+    const int nb = colour15_blocks(vg, g);
+    for (int q = 0; q < nb; q++) partial[q] = 0.0;  // the residual launch that follows carries g_mock_res2
+    return nb;
+}
+template <typename T>
+void launch_colour15_res(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, T *, const T *, double, T *) {}
+template void launch_colour15_res<double>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, double *,
+                                          const double *, double, double *);
+template void launch_colour15_res<float>(hipStream_t, const VolGeom &, const IfcGeom &, const Gen15 &, float *,
+                                         const float *, double, float *);
 template <typename T, typename TO>
 int launch_residual15(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const Gen15 &, const T *, const T *, TO *,
                       double *partial) {
