@@ -414,8 +414,8 @@ def main():
                          "references of known size for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding the macro tetrahedra over GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
