@@ -139,6 +139,31 @@ def test_vcycle_sweep_counts(dev, hh, nu_pre, nu_post, omega, vk):
     p.close()
 
 
+@pytest.mark.parametrize("general", [False, True])
+def test_split_norm_equals_full_residual(dev, hh, general):
+    """The norm a cycle reports is taken from its last black (class-3) pass
+    and a residual over the other nodes; it equals ||b - A u|| of the same
+    iterate computed in full by the residual operator."""
+    n_sub, level = 2, 5
+    print(f"\n[split norm] general={general}", flush=True)
+    V = inputs.perturbed_vertices(n_sub, 2) if general else None
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, general_geometry=general)
+    if general:
+        ctx.set_geometry(V)
+    g = np.random.default_rng(13)
+    nd = (n_sub * 2 ** level - 1) ** 3
+    b = g.standard_normal(nd)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(None)
+    bn = np.linalg.norm(b)
+    for it in range(4):
+        relres = ctx.vcycle(1)
+        u = N(ctx.get_solution())
+        r = N(hh.debug_op(ctx, 0, level, T(u, dev), T(b, dev)))
+        assert relres == pytest.approx(np.linalg.norm(r) / bn, rel=1e-11), it
+    ctx.close()
+
+
 def test_solve_c1(dev, hh, oracle_problem):
     # 6 macro tets, level 4, sine source, V(2,1) to 1e-8
     n_sub, level = 1, 4
