@@ -75,6 +75,31 @@ CASES = [(1, 5, 3), (2, 4, 5), (3, 3, 7)]
 K_CASES = [(1, 4, 3), (2, 4, 5), (3, 3, 7)]
 
 
+# sweep counts: no post-smoothing, no pre-smoothing, the paper's 3 + 3.  The
+# last pre-smoothing class-3 pass writes the residual of its nodes (also in
+# a sweep that starts from zero) and the last class-3 pass of a cycle sums
+# its squares; the residual launches cover classes 0..2
+@pytest.mark.parametrize("vk", [False, True])
+@pytest.mark.parametrize("nu_pre,nu_post", [(1, 0), (0, 2), (3, 3)])
+def test_sweep_counts(dev, hh, nu_pre, nu_post, vk):
+    n_sub, level, seed = 2, 4, 5
+    print(f"\n[general sweeps] nu=({nu_pre},{nu_post}) vk={vk}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=seed) if vk else None
+    ctx = context(hh, dev, n_sub, level, seed, k=k, nu_pre=nu_pre, nu_post=nu_post)
+    p = problem_k(n_sub, level, seed, seed) if vk else problem(n_sub, level, seed)
+    g = np.random.default_rng(600 + seed)
+    b = g.standard_normal(p.ndof)
+    u = g.standard_normal(p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(T(u, dev))
+    for it in range(3):
+        relres = ctx.vcycle(1)
+        u, rn = p.vcycle(u, b, nu1=nu_pre, nu2=nu_post)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+        assert relres == pytest.approx(rn / np.linalg.norm(b), rel=1e-10)
+    ctx.close()
+
+
 @pytest.mark.parametrize("n_sub,level,seed", K_CASES)
 def test_variable_k_operators_and_solve(dev, hh, n_sub, level, seed):
     """Per-element log-normal k on a general macro mesh: per-node stencils on
