@@ -149,9 +149,13 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * Every kind records ||b|| as the reference for relative residuals. */
 int hhgr_set_rhs(hhgr_ctx *ctx, const double *dev_vec, int kind);
 
-/* Per-element diffusion coefficient (device, element order, length 6 N^3,
- * positive); needs variable_coeff = 1.  Coarse levels use the mean over the
- * 8 children of each coarse element (the Galerkin-consistent choice). */
+/* Per-element diffusion coefficient of -div(k grad u) = f, one of the
+ * "other scalar elliptic problems" the model problem generalises to (Sec. 2.1,
+ * after eq. (1)); the operator of eq. (2) becomes the P1 stiffness matrix
+ * weighted by k on every element.  dev_k: device, element order, length
+ * 6 N^3, positive; needs variable_coeff = 1 (ESTATE otherwise).  Coarse
+ * levels use the mean over the 8 children of each coarse element (the
+ * Galerkin-consistent choice).  EINVAL for a null pointer. */
 int hhgr_set_coeff(hhgr_ctx *ctx, const double *dev_k);
 
 /* Copy a device vector into / out of the solver's containers (vector order).
@@ -176,9 +180,13 @@ int hhgr_vcycle(hhgr_ctx *ctx, int n, double *rel_res_out);
 int hhgr_solve(hhgr_ctx *ctx, double rel_tol, int max_cycles, hhgr_report *report);
 
 /* Fail-stop fault of one macro tetrahedron (Sec. 2.2): the unknowns strictly
- * inside it and its ghost copies of face/edge/vertex values are lost and set to
- * zero; the face, edge and vertex containers (stored redundantly) survive.
- * Only between cycles.  EINVAL for a bad tet id. */
+ * inside it are lost and set to zero (re-initialisation).  Its ghost copies of
+ * face/edge/vertex values are lost too; the face, edge and vertex containers
+ * (stored redundantly, eq. (4)) survive, and the copies are filled again
+ * from them at once, as the ghost update of Sec. 3.1 would do before any
+ * stencil reads them.  So a cycle run right after the fault (the do-nothing
+ * strategy) sees the interface values and a zero interior.  Only between
+ * cycles.  EINVAL for a bad tet id. */
 int hhgr_inject_fault(hhgr_ctx *ctx, int tet);
 
 /* Local recovery (Sec. 4; Alg. 1 a)): restores the tetrahedron's

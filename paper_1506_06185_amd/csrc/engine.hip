@@ -1706,8 +1706,9 @@ int hhgr_solve(hhgr_ctx *c, double rel_tol, int max_cycles, hhgr_report *rep) {
 int hhgr_inject_fault(hhgr_ctx *c, int tet) {
     if (!c) return fail(HHGR_EINVAL, "null context");
     if (tet < 0 || tet >= c->n_tets) return fail(HHGR_EINVAL, "tet id out of range");
-    LevelDev &D = c->lev[c->L];
-    launch_fill<double>(c->stream, D.u + (long long)tet * D.C_pad, D.C_pad, 0.0);
+    // the closure is lost; its ghost copies come back from the surviving
+    // masters (eq. (4)) before any cycle reads them
+    restore_tet(*c, tet, c->stream);
     CHKLAUNCH();
     return HHGR_OK;
 }

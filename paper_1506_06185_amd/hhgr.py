@@ -153,6 +153,9 @@ class Context:
         self.n_dofs, self.n_tets, self.n_elems = int(nd.value), int(nt.value), int(ne.value)
         self.N = self.desc.n_sub << self.desc.level
         self.workspace_nbytes = nbytes
+        # incremented by every call that changes the solution, the operator
+        # or the right-hand side (HHGSolve checks it before its backward)
+        self.version = 0
 
     @property
     def handle(self):
@@ -173,6 +176,7 @@ class Context:
         return torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
 
     def set_rhs(self, vec: torch.Tensor, kind: int = HHGR_RHS_LOAD):
+        self.version += 1
         want = (self.N + 1) ** 3 if kind == HHGR_RHS_DIRICHLET else self.n_dofs
         if vec.numel() != want:
             raise HHGRError(HHGR_EINVAL, f"right-hand side has {vec.numel()} entries, expected {want}")
@@ -180,6 +184,7 @@ class Context:
         self._keep_rhs = vec
 
     def set_coeff(self, k: torch.Tensor):
+        self.version += 1
         _check(lib().hhgr_set_coeff(self._h, _ptr(k)))
 
     def set_geometry(self, vertices):
@@ -189,10 +194,12 @@ class Context:
         xyz = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1)
         if xyz.size != 3 * (self.desc.n_sub + 1) ** 3:
             raise HHGRError(HHGR_EINVAL, f"expected {(self.desc.n_sub + 1) ** 3} vertices, got {xyz.size / 3:g}")
+        self.version += 1
         _check(lib().hhgr_set_geometry(self._h, xyz.ctypes.data_as(_dp)))
 
     def set_solution(self, u: torch.Tensor | None):
         """Initial guess from a device vector in vector order; None sets u = 0."""
+        self.version += 1
         _check(lib().hhgr_set_solution(self._h, _ptr(u) if u is not None else None))
         self.stream.synchronize()
 
@@ -203,11 +210,13 @@ class Context:
         return out
 
     def vcycle(self, n: int = 1) -> float:
+        self.version += 1
         rel = C.c_double(0.0)
         _check(lib().hhgr_vcycle(self._h, int(n), C.byref(rel)))
         return float(rel.value)
 
     def solve(self, rel_tol: float = 1e-8, max_cycles: int = 100, raise_on_noconv: bool = True):
+        self.version += 1
         import numpy as np
 
         hist = (C.c_double * (max_cycles + 1))()
@@ -217,20 +226,24 @@ class Context:
         return int(rep.cycles), float(rep.rel_res), np.array(hist[: rep.cycles + 1])
 
     def inject_fault(self, tet: int):
+        self.version += 1
         _check(lib().hhgr_inject_fault(self._h, int(tet)))
 
     def recover_local(self, tet: int, n_cycles: int = 3) -> float:
+        self.version += 1
         rel = C.c_double(0.0)
         _check(lib().hhgr_recover_local(self._h, int(tet), int(n_cycles), C.byref(rel)))
         return float(rel.value)
 
     def recover_dd(self, tets, n_intact: int, n_local: int):
+        self.version += 1
         arr = (C.c_int * len(tets))(*[int(t) for t in tets])
         _check(lib().hhgr_recover_dd(self._h, arr, len(tets), int(n_intact), int(n_local)))
 
     def recover_dn(self, tets, n_intact: int, eta: int = 1):
         """Dirichlet-Neumann recovery (Alg. 2) of faulty tets: n_intact rounds of eta local
         cycles beside one intact Neumann cycle."""
+        self.version += 1
         arr = (C.c_int * len(tets))(*[int(t) for t in tets])
         _check(lib().hhgr_recover_dn(self._h, arr, len(tets), int(n_intact), int(eta)))
 
@@ -325,16 +338,14 @@ class Batch:
             pass
 
 
-def kappa(k_faulty: int, k_free: int, k_F: int) -> float:
-    """Relative cycle advantage, eq. (3): (k_faulty - k_free) / k_F."""
-    return (k_faulty - k_free) / k_F
-
-
 class HHGSolve(torch.autograd.Function):
     """u = A(k)^{-1} M f on a context created with variable_coeff=True.
 
     forward(ctx_obj, f, k) -> u; backward returns dJ/df = M lambda and
     dJ/dk_T = -lambda^T A_T u with A lambda = dJ/du (adjoint multigrid solve).
+    The adjoint reads the context's coefficient and solution, so forward saves
+    u and k; if the context was used in between (another forward, a finite-
+    difference probe), backward sets them back before the adjoint solve.
     """
 
     @staticmethod
@@ -347,11 +358,18 @@ class HHGSolve(torch.autograd.Function):
         u = ctx_obj.get_solution()
         fctx.ctx_obj = ctx_obj
         fctx.rel_tol, fctx.max_cycles = rel_tol, max_cycles
+        fctx.version = ctx_obj.version
+        fctx.save_for_backward(u, k)
         return u
 
     @staticmethod
     def backward(fctx, g: torch.Tensor):
         c = fctx.ctx_obj
+        u, k = fctx.saved_tensors
+        if c.version != fctx.version:
+            c.set_coeff(k.detach().contiguous())
+            c.set_solution(u.detach().contiguous())
+            fctx.version = c.version
         dJdf, dJdk = c.adjoint_grad(g.contiguous(), fctx.rel_tol, fctx.max_cycles, want_k=True)
         c.stream.synchronize()
         return None, dJdf, dJdk, None, None

@@ -260,6 +260,27 @@ def test_recovery_parity(dev, hh, strategy, vk):
     ctx.close()
 
 
+def test_fault_then_plain_cycles(dev, hh):
+    # do-nothing (Sec. 2.2) on a moved mesh: the cycle after the fault reads
+    # the faulty closure's ghost copies, which hold the surviving interface
+    n_sub, level, seed = 2, 4, 5
+    print("\n[general fault + plain cycles]", flush=True)
+    p = problem(n_sub, level, seed)
+    ctx = context(hh, dev, n_sub, level, seed)
+    b = inputs.uniform_load(n_sub, level, seed=4)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.vcycle(3)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    t = inputs.fault_tet(n_sub, seed=0)
+    ctx.inject_fault(t)
+    u = p.inject_fault(t, u)
+    for it in range(2):
+        ctx.vcycle(1)
+        u, _ = p.vcycle(u, b)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+    ctx.close()
+
+
 def test_geometry_level6_iterates(dev, hh):
     """The oracle at the largest size it runs in seconds (2 subcubes, level 6)."""
     n_sub, level, seed = 2, 6, 9

@@ -220,6 +220,34 @@ def test_fault_and_local_recovery(dev, hh, oracle_problem):
     ctx.close()
 
 
+@pytest.mark.parametrize("vk", [False, True])
+def test_fault_then_plain_cycles(dev, hh, vk):
+    # the do-nothing strategy (Sec. 2.2): cycles continue right after the
+    # fault.  The faulty closure's ghost copies must hold the surviving
+    # interface values, as the oracle's global vector does.
+    n_sub, level = 2, 4
+    print(f"\n[fault + plain cycles] vk={vk}", flush=True)
+    k = inputs.lognormal_k(n_sub, level, seed=2) if vk else None
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=vk)
+    if vk:
+        ctx.set_coeff(T(k, dev))
+    p = oracle.Problem(n_sub, level, k=k)
+    b = inputs.uniform_load(n_sub, level, seed=3)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.vcycle(3)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    for t in (inputs.fault_tet(n_sub, seed=0), 0):
+        ctx.inject_fault(t)
+        u = p.inject_fault(t, u)
+        for it in range(2):
+            relres = ctx.vcycle(1)
+            u, rn = p.vcycle(u, b)
+            assert rel(N(ctx.get_solution()), u) < 1e-12, (t, it)
+            assert relres == pytest.approx(rn / np.linalg.norm(b), rel=1e-10)
+    ctx.close()
+    p.close()
+
+
 @pytest.mark.parametrize("shape", ["bs256-xcd-1npt", "bs128-hw-4npt"])
 def test_dirichlet_dirichlet_recovery(dev, hh, oracle_problem, shape):
     n_sub, level = 2, 5
@@ -315,6 +343,34 @@ def test_adjoint_gradients(dev, hh):
     J.backward()
     assert rel(N(fT.grad), p.apply_M(lam)) < 1e-9
     assert rel(N(kT.grad), p.grad_k(u, lam)) < 1e-9
+    ctx.close()
+
+
+def test_adjoint_after_interleaved_forwards(dev, hh):
+    # two forwards on one context before the first backward: each backward
+    # must use its own forward's u and k
+    n_sub, level = 1, 4
+    print("\n[adjoint, interleaved forwards]", flush=True)
+    f = inputs.sine_source(n_sub, level)
+    uobs = inputs.gaussian_obs(n_sub, level, seed=0)
+    ks = [inputs.lognormal_k(n_sub, level, seed=s) for s in (0, 7)]
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level, variable_coeff=True)
+    fTs, kTs, Js = [], [], []
+    for k in ks:
+        fT, kT = T(f, dev).requires_grad_(True), T(k, dev).requires_grad_(True)
+        uT = hh.HHGSolve.apply(ctx, fT, kT, 1e-13, 80)
+        Js.append(0.5 * ((uT - T(uobs, dev)) ** 2).sum())
+        fTs.append(fT)
+        kTs.append(kT)
+    for q in (0, 1):
+        Js[q].backward()
+        p = oracle.Problem(n_sub, level, k=ks[q])
+        b = p.apply_M(f)
+        u, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+        lam, _, _ = p.solve(u - uobs, rtol=1e-13, max_cycles=80)
+        assert rel(N(fTs[q].grad), p.apply_M(lam)) < 1e-9, q
+        assert rel(N(kTs[q].grad), p.grad_k(u, lam)) < 1e-9, q
+        p.close()
     ctx.close()
 
 
