@@ -306,6 +306,30 @@ int hhgr_kernel_stats(hhgr_ctx *ctx, long long *launches, double *mean_ms, doubl
  * EINVAL for a bad op/level combination. */
 int hhgr_debug_op(hhgr_ctx *ctx, int op, int level, const double *in0, const double *in1, double *out);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): a
+ * variant of hhgr_create + hhgr_set_rhs + hhgr_solve + hhgr_get_solution that
+ * brings no workspace.  The workspace of the solve lives in a static device
+ * array of the library, 64 MiB per GPU (held by every GPU the library runs
+ * on until the process ends); problems whose hhgr_workspace_bytes exceed it
+ * are rejected with EINVAL and a message naming both sizes (64 MiB holds
+ * n_sub = 2 up to level 5 and n_sub = 1 up to level 6).  k = 1 on the unit
+ * cube only (variable_coeff and general_geometry must be 0, else EINVAL).
+ * dev_rhs: device vector of the given kind, as for hhgr_set_rhs; dev_u:
+ * device vector (vector order) that receives the solution, computed from
+ * u = 0 with V-cycles until ||b - A u|| <= rel_tol ||b|| or max_cycles
+ * (ENOCONV; dev_u and the report are still filled).  report (optional, as
+ * for hhgr_solve) receives the cycle count, the final relative residual and
+ * the history.  Work runs on hip_stream and the call synchronises it before
+ * returning; it allocates no device or pinned memory and creates no streams,
+ * events or graphs.  Every call on one GPU uses that GPU's one array and
+ * keeps nothing from the previous call; calls from several host threads on
+ * the same device are serialised by the library.  Work of the caller that
+ * overlaps a call on the same GPU must not touch the array (it cannot: its
+ * address is not exported). */
+int hhgr_solve_static(const hhgr_desc *desc, const double *dev_rhs, int kind, double rel_tol, int max_cycles,
+                      double *dev_u, hhgr_report *report, void *hip_stream);
+
 const char *hhgr_last_error(void);
 
 #ifdef __cplusplus

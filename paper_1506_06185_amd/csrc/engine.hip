@@ -164,7 +164,8 @@ struct hhgr_ctx {
     unsigned int *counter = nullptr;  // [2] last-block detection of the norm reductions
     int partial_cap = 0;
     double *dnorm = nullptr;
-    double *hnorm = nullptr;  // pinned
+    double *hnorm = nullptr;  // pinned, or hnorm_local in a context without HIP objects of its own
+    double hnorm_local[8] = {};
     int *tetinfo = nullptr;
     // coarsest level
     long long *cslot = nullptr;
@@ -1275,7 +1276,18 @@ int hhgr_workspace_bytes(const hhgr_desc *desc, size_t *bytes) {
     return HHGR_OK;
 }
 
-int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out) {
+}  // extern "C"
+
+namespace hhgr {
+namespace {
+
+// hhgr_create and the context of hhgr_solve_static.  own_objects: create the
+// second stream, the capture stream, the fork/join events and the pinned
+// read-back buffer; without them (a context that allocates nothing) the
+// norms are read back into pageable host memory and the context supports
+// set_rhs, solve and get_solution only (no graphs, recoveries or batches).
+int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, bool own_objects,
+               hhgr_ctx **out) {
     if (!out) return fail(HHGR_EINVAL, "null output pointer");
     *out = nullptr;
     std::string e = check_desc(desc);
@@ -1315,14 +1327,18 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
         hhgr_destroy(c);
         return code;
     };
-    if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(HHGR_EHIP, "stream create"));
-    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(HHGR_EHIP, "event create"));
-    if (hipHostMalloc((void **)&c->hnorm, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-        return bail(fail(HHGR_EHIP, "pinned host allocation"));
+    if (own_objects) {
+        if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(HHGR_EHIP, "stream create"));
+        if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(HHGR_EHIP, "event create"));
+        if (hipHostMalloc((void **)&c->hnorm, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return bail(fail(HHGR_EHIP, "pinned host allocation"));
+    } else {
+        c->hnorm = c->hnorm_local;
+    }
 
     const Topology &tp = *c->topo;
     // host-side staging of all tables; kept alive until the final synchronise
@@ -1441,6 +1457,15 @@ int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_
     return HHGR_OK;
 }
 
+}  // namespace
+}  // namespace hhgr
+
+extern "C" {
+
+int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out) {
+    return create_ctx(desc, dev_ws, ws_bytes, hip_stream, true, out);
+}
+
 void hhgr_destroy(hhgr_ctx *c) {
     if (!c) return;
     hipStreamSynchronize(c->stream);  // also the legacy default stream (nullptr)
@@ -1453,7 +1478,7 @@ void hhgr_destroy(hhgr_ctx *c) {
     if (c->ev_join) hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->tev) hipEventDestroy(e);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
-    if (c->hnorm) hipHostFree(c->hnorm);
+    if (c->hnorm && c->hnorm != c->hnorm_local) hipHostFree(c->hnorm);
     delete c;
 }
 
@@ -2455,6 +2480,84 @@ int hhgr_batch_run(hhgr_batch *b, double rel_tol, int max_cycles, hhgr_report *r
         all = all && rel[q] <= rel_tol;
     }
     return all ? HHGR_OK : fail(HHGR_ENOCONV, "some batch members did not converge");
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Solve without device allocation (hhgr_solve_static)
+// ----------------------------------------------------------------------------
+// The whole workspace of one solve lives in this file-scope device array.
+// Every GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: the device address of
+// each GPU's copy comes from hipGetSymbolAddress, once per device.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kStaticMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+struct StaticScratch {
+    std::mutex m;          // held for a whole hhgr_solve_static call on the device
+    void *ptr = nullptr;   // device address of this device's copy of scratch
+};
+StaticScratch g_static[kStaticMaxDevices];
+}  // namespace
+
+extern "C" {
+
+int hhgr_solve_static(const hhgr_desc *desc, const double *dev_rhs, int kind, double rel_tol, int max_cycles,
+                      double *dev_u, hhgr_report *report, void *hip_stream) {
+    if (!desc || !dev_rhs || !dev_u) return fail(HHGR_EINVAL, "null argument");
+    if (desc->variable_coeff || desc->general_geometry)
+        return fail(HHGR_EINVAL, "hhgr_solve_static takes k = 1 on the unit cube only");
+    if (kind != HHGR_RHS_LOAD && kind != HHGR_RHS_NODAL_F && kind != HHGR_RHS_DIRICHLET)
+        return fail(HHGR_EINVAL, "bad rhs kind");
+    if (max_cycles < 0) return fail(HHGR_EINVAL, "negative max_cycles");
+    size_t need = 0;
+    int rc = hhgr_workspace_bytes(desc, &need);
+    if (rc) return rc;
+    if (need > kStaticScratchBytes)
+        return fail(HHGR_EINVAL, "problem needs " + std::to_string(need) + " bytes of workspace; the static scratch of "
+                                     "hhgr_solve_static holds " + std::to_string(kStaticScratchBytes));
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(HHGR_EINVAL, "device ordinal out of range");
+    StaticScratch &S = g_static[dev];
+    std::lock_guard<std::mutex> lock(S.m);
+    if (!S.ptr) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255) != 0) return fail(HHGR_EHIP, "static scratch address");
+        S.ptr = p;
+    }
+    // the context carves S.ptr and clears every vector it reads (zero slot,
+    // Dirichlet ghosts, partial sums, counters), so the previous call's
+    // contents do not matter
+    hhgr_ctx *c = nullptr;
+    rc = create_ctx(desc, S.ptr, kStaticScratchBytes, hip_stream, false, &c);
+    if (rc) return rc;
+    rc = hhgr_set_rhs(c, dev_rhs, kind);
+    hhgr_report rep{0, 0.0, nullptr, 0};
+    if (report) rep = *report;
+    int src = rc ? rc : hhgr_solve(c, rel_tol, max_cycles, &rep);
+    if (report && !rc) {
+        report->cycles = rep.cycles;
+        report->rel_res = rep.rel_res;
+    }
+    if (src == HHGR_OK || src == HHGR_ENOCONV) {
+        const std::string keep = g_err;
+        rc = hhgr_get_solution(c, dev_u);
+        if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(HHGR_EHIP, "synchronise");
+        if (!rc && src == HHGR_ENOCONV) g_err = keep;
+        if (!rc) rc = src;
+    } else {
+        rc = src;
+    }
+    hhgr_destroy(c);
+    return rc;
 }
 
 }  // extern "C"

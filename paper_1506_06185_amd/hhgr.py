@@ -84,6 +84,8 @@ def lib():
         "hhgr_kernel_timing": (C.c_int, [_vp, C.c_int]),
         "hhgr_kernel_stats": (C.c_int, [_vp, C.POINTER(C.c_longlong), _dp, _dp]),
         "hhgr_debug_op": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp]),
+        "hhgr_solve_static": (C.c_int, [C.POINTER(Desc), _vp, C.c_int, C.c_double, C.c_int, _vp, C.POINTER(Report),
+                                        _vp]),
         "hhgr_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -99,7 +101,8 @@ EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_de
             "hhgr_solve", "hhgr_inject_fault", "hhgr_recover_local", "hhgr_recover_dd", "hhgr_recover_dn", "hhgr_adjoint_grad",
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
-            "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_last_error")
+            "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_solve_static",
+            "hhgr_last_error")
 
 
 def _check(rc: int, allow=()):
@@ -297,6 +300,24 @@ def debug_op(ctx: "Context", op: int, level: int, in0: torch.Tensor, in1: torch.
     _check(lib().hhgr_debug_op(ctx.handle, int(op), int(level), _ptr(in0), _ptr(in1) if in1 is not None else None,
                                _ptr(out)))
     return out
+
+
+def solve_static(rhs: torch.Tensor, kind: int = HHGR_RHS_LOAD, rel_tol: float = 1e-8, max_cycles: int = 100,
+                 out: torch.Tensor | None = None, stream=None, raise_on_noconv: bool = True, **desc_kw):
+    """hhgr_solve_static: a whole solve in the library's static device scratch
+    (no workspace).  Returns (u, cycles, rel_res, history)."""
+    import numpy as np
+
+    desc = make_desc(**desc_kw)
+    N = desc.n_sub << desc.level
+    u = torch.empty((N - 1) ** 3, dtype=torch.float64, device=rhs.device) if out is None else out
+    stream = torch.cuda.current_stream(rhs.device) if stream is None else stream
+    hist = (C.c_double * (max_cycles + 1))()
+    rep = Report(0, 0.0, C.cast(hist, _dp), max_cycles + 1)
+    rc = lib().hhgr_solve_static(C.byref(desc), _ptr(rhs), int(kind), float(rel_tol), int(max_cycles), _ptr(u),
+                                 C.byref(rep), stream.cuda_stream)
+    _check(rc, allow=() if raise_on_noconv else (HHGR_ENOCONV,))
+    return u, int(rep.cycles), float(rep.rel_res), np.array(hist[: rep.cycles + 1])
 
 
 class Batch:

@@ -206,6 +206,32 @@ int main() {
         hhgr_destroy(g);
         std::free(ws);
     }
+    {
+        // the solve in the static scratch: two calls, the second smaller,
+        // and a problem too large for the scratch
+        hhgr_desc d;
+        hhgr_desc_default(&d);
+        d.n_sub = 2;
+        d.level = 5;
+        std::vector<double> rhs(31 * 31 * 31, 1.0), u(31 * 31 * 31, 7.0), hist(11);
+        hhgr_report rep{0, 0.0, hist.data(), 11};
+        // (mock residuals never converge)
+        CHECK(hhgr_solve_static(&d, rhs.data(), HHGR_RHS_LOAD, 1e-8, 10, u.data(), &rep, nullptr) == HHGR_ENOCONV,
+              "static solve: %s", hhgr_last_error());
+        CHECK(rep.cycles == 10, "static solve report");
+        d.n_sub = 1;
+        d.level = 4;
+        CHECK(hhgr_solve_static(&d, rhs.data(), HHGR_RHS_NODAL_F, 1e-8, 10, u.data(), &rep, nullptr) == HHGR_ENOCONV,
+              "static solve, smaller: %s", hhgr_last_error());
+        d.n_sub = 2;
+        d.level = 7;
+        CHECK(hhgr_solve_static(&d, rhs.data(), HHGR_RHS_LOAD, 1e-8, 10, u.data(), &rep, nullptr) == HHGR_EINVAL,
+              "static solve too large rejected");
+        d.level = 4;
+        d.variable_coeff = 1;
+        CHECK(hhgr_solve_static(&d, rhs.data(), HHGR_RHS_LOAD, 1e-8, 10, u.data(), &rep, nullptr) == HHGR_EINVAL,
+              "static solve with variable k rejected");
+    }
     for (auto &c : cs) {
         hhgr_destroy(c.h);
         std::free(c.ws);

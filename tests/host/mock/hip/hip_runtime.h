@@ -51,3 +51,14 @@ hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, char *, 
 hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s);
 hipError_t hipGraphExecDestroy(hipGraphExec_t x);
 hipError_t hipGraphDestroy(hipGraph_t g);
+
+// device-symbol stand-ins: a __device__ array is an ordinary host array and
+// its "device address" is its host address
+#define __device__
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(X) X
+hipError_t hipGetSymbolAddress(void **p, const void *symbol);
+template <typename T>
+hipError_t hipGetSymbolAddress(void **p, const T &symbol) {
+    return hipGetSymbolAddress(p, (const void *)&symbol);
+}

@@ -73,6 +73,10 @@ hipError_t hipHostFree(void *p) {
 }
 hipError_t hipGetLastError() { return hipSuccess; }
 const char *hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "mock error"; }
+hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+    *p = const_cast<void *>(symbol);
+    return hipSuccess;
+}
 hipError_t hipGetDevice(int *d) {
     *d = 0;
     return hipSuccess;
