@@ -9,9 +9,14 @@ stored faces/edges/vertex, then global V-cycles continue to ||r|| <= 1e-8 ||b||.
 
 value = unknowns x global V-cycles / step wall time (MDoF/s), so the fault
 and the recovery count against it; ms_per_step is the time to 1e-8.
-roofline: the finest-level FP64 colour pass, timed with HIP events on the
-stream it runs on during the timed steps.  cpu_baseline: the CPU oracle's
-V-cycle rate on the same problem.
+roofline: the finest-level FP64 smoother kernel, timed with HIP events on
+the stream it runs on during the timed steps: the red-black colour pass
+(12 B per unknown: a sweep reads u and b once and writes u once, 24 B per
+unknown, in two passes; the pass's own count, 16 B, is reported beside it),
+or the fused sweep kernel where the autotuner chose it (24 B per
+volume-interior unknown).  cpu_baseline: the CPU oracle on
+the same job (time to 1e-8 on every host thread, a one-thread sample, and the
+gradient workload's forward and adjoint solves).
 
 Further legs, each in its own object of the JSON line:
   mixed     the same job in mixed precision (FP32 cycle inside FP64 refinement);
@@ -44,7 +49,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "colour_pass_fp64_l7_48tets_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_sweep_fp64_l7_48tets_traffic.json")
+TRAFFIC_FILE_COLOUR = os.path.join(ROOT, "profiles", "colour_pass_fp64_l7_48tets_traffic.json")
 TRAFFIC_FILE_GENERAL = os.path.join(ROOT, "profiles", "class_pass15_fp64_l7_48tets_traffic.json")
 
 
@@ -52,13 +58,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_1506_06185_amd", "csrc", "kernels.hip"), "rb") as f:
+def kernel_source_hash(name: str = "kernels.hip") -> str:
+    with open(os.path.join(ROOT, "paper_1506_06185_amd", "csrc", name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(n_sub: int, level: int, path: str = TRAFFIC_FILE):
-    """HBM bytes per launch of the finest-level colour pass from the committed
+def measured_traffic(n_sub: int, level: int, path: str = TRAFFIC_FILE, source: str = "fused.hip"):
+    """HBM bytes per launch of the finest-level dominant kernel from the committed
     rocprofv3 counter summary, or None when the summary is not for this workload
     or not for the current kernel source.  The figure is the L2-to-memory read
     and write requests counted in 32-byte units (TCC_EA0_RDREQ_DRAM_32B_sum,
@@ -72,7 +78,7 @@ def measured_traffic(n_sub: int, level: int, path: str = TRAFFIC_FILE):
             t = json.load(f)
     except OSError:
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(source):
         return None
     if "dram_read_bytes_per_dispatch" in t:
         return round(t["dram_read_bytes_per_dispatch"] + t["dram_write_bytes_per_dispatch"])
@@ -91,30 +97,84 @@ def run_job(hh, torch, ctx, f_dev, fault_tet, k_f=5, n_rec=3, rtol=1e-8, max_cyc
     return k_f + cyc, rel
 
 
-def cpu_baseline(n_sub, level, cycles=3):
+def host_info():
+    import platform
+    import subprocess
+
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "machine": platform.machine()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info["lscpu " + k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(n_sub, level, grad=True):
+    """The CPU oracle (C + OpenMP, CSR sparse multigrid; a correctness
+    baseline, not a tuned CPU stencil code) timed on this host's cores:
+    the headline fault job to 1e-8 on every thread, two V-cycles on one
+    thread, and the gradient workload's forward + adjoint solve."""
     import numpy as np
 
     import oracle
     from paper_1506_06185_amd import inputs
 
+    nthr = oracle.threads()
     p = oracle.Problem(n_sub, level)
     b = p.apply_M(inputs.sine_source(n_sub, level))
-    u = np.zeros_like(b)
-    u, _ = p.vcycle(u, b)  # first touch of the work vectors
+    t_fault = inputs.fault_tet(n_sub, seed=0)
+    # the fault job: 5 cycles, fault, 3 local recovery cycles, solve to 1e-8
     t0 = time.perf_counter()
-    for _ in range(cycles):
-        u, _ = p.vcycle(u, b)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=5)
+    u = p.inject_fault(t_fault, u)
+    u, _ = p.recover_local(t_fault, u, b, n_cycles=3)
+    u, cyc, _ = p.solve(b, u0=u, rtol=1e-8, max_cycles=60, r0=np.linalg.norm(b))
     dt = time.perf_counter() - t0
+    cycles = 5 + cyc
+    # one thread: two V-cycles (a bounded sample of the same job)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    for _ in range(2):
+        u, _ = p.vcycle(u, b)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(nthr)
     res = {
         "value": round(p.ndof * cycles / dt / 1e6, 3),
         "unit": "MDoF/s",
-        "cores": oracle.threads(),
+        "cores": nthr,
         "kind": "oracle",
-        "sample": f"{cycles} V(2,1) cycles of the n_sub={n_sub}, level={level} problem ({p.ndof} unknowns) "
-                  f"after one untimed cycle; CSR sparse multigrid in C/OpenMP, assembly "
-                  f"({p.setup_seconds:.1f} s) excluded",
+        "sample": f"the headline fault job (n_sub={n_sub}, level={level}, {p.ndof} unknowns): 5 V(2,1) cycles, "
+                  f"fault in tet {t_fault}, 3 local recovery cycles, cycles to 1e-8 ({cycles} global cycles); "
+                  f"CSR sparse multigrid in C/OpenMP on {nthr} threads, assembly ({p.setup_seconds:.1f} s) excluded",
+        "time_to_1e8_s": round(dt, 3),
+        "one_thread": {"value": round(p.ndof * 2 / dt1 / 1e6, 3), "unit": "MDoF/s", "cores": 1,
+                       "sample": "2 V(2,1) cycles of the same problem on one thread",
+                       "time_to_1e8_s_estimate": round(dt1 / 2 * cycles, 2)},
+        "host": host_info(),
     }
     p.close()
+    if grad:
+        # the gradient workload: forward and adjoint solves to 1e-11 with
+        # per-element log-normal k, dJ/df = M lambda, dJ/dk per element
+        k = inputs.lognormal_k(n_sub, level, seed=0)
+        uobs = inputs.gaussian_obs(n_sub, level, seed=0)
+        pk = oracle.Problem(n_sub, level, k=k)
+        bk = pk.apply_M(inputs.sine_source(n_sub, level))
+        t2 = time.perf_counter()
+        uk, cf, _ = pk.solve(bk, rtol=1e-11, max_cycles=100)
+        lam, ca, _ = pk.solve(uk - uobs, rtol=1e-11, max_cycles=100)
+        pk.apply_M(lam)
+        pk.grad_k(uk, lam)
+        dt2 = time.perf_counter() - t2
+        res["gradients"] = {"forward_plus_adjoint_s": round(dt2, 3), "forward_cycles": cf, "adjoint_cycles": ca,
+                            "cores": nthr,
+                            "sample": f"n_sub={n_sub} level={level}, k = exp(0.5 Z): forward and adjoint solves to "
+                                      f"1e-11, M lambda and dJ/dk; assembly ({pk.setup_seconds:.1f} s) excluded"}
+        pk.close()
     return res
 
 
@@ -233,7 +293,7 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph, tune_cache):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(n_sub, level, TRAFFIC_FILE_GENERAL),
+            "traffic": measured_traffic(n_sub, level, TRAFFIC_FILE_GENERAL, "kernels.hip"),
             "launches": launches,
             "mean_launch_ms": round(mean_ms, 5),
             "algorithmic_bytes_per_launch": alg_bytes,
@@ -470,18 +530,37 @@ def main():
 
     roofline = None
     if launches > 0:
-        achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
+        t = mean_ms * 1e-3
+        pass_bytes = 2.0 * 8.0 * ctx.n_dofs  # a colour pass's own count: u all, b and u of its colour
+        if abs(alg_bytes - pass_bytes) > 1.0:
+            # the autotuner chose fused sweep pairs on the finest level
+            kernel = "k_sweep_fused<double> (finest-level fused red-black SOR sweep of the volume interiors, FP64, k=1)"
+            sweep_bytes, own = alg_bytes, None
+            traffic = measured_traffic(n_sub, level)
+        else:
+            # per red-black sweep u and b are read once and u is written once
+            # (24 B per unknown in FP64), i.e. 12 B per colour pass; the pass
+            # itself reads u of both colours, so its own count is 16 B
+            kernel = "k_colour<double> (finest-level red-black SOR colour pass, FP64, k=1)"
+            sweep_bytes = 12.0 * ctx.n_dofs
+            own = {"algorithmic_bytes_per_launch": pass_bytes, "achieved": round(pass_bytes / t / 1e9, 1),
+                   "frac": round(pass_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                   "count": "16 B per unknown: u of both colours, b and u of the pass's colour"}
+            traffic = measured_traffic(n_sub, level, TRAFFIC_FILE_COLOUR, "kernels.hip")
+        achieved = sweep_bytes / t / 1e9
         roofline = {
             "bound": "hbm",
-            "kernel": "k_colour<double> (finest-level colour pass, FP64, k=1)",
+            "kernel": kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(n_sub, level),
+            "traffic": traffic,
             "launches": launches,
             "mean_launch_ms": round(mean_ms, 5),
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes_per_launch": sweep_bytes,
+            "count": "24 B per unknown per red-black sweep (u and b read once, u written once), 12 B per colour pass",
+            "pass_own_count": own,
         }
     ctx.close()
 

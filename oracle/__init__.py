@@ -52,6 +52,7 @@ def lib():
         "ohhg_create_geom": (_vp, [C.c_int, C.c_int, C.c_int, _dp, _dp]),
         "ohhg_destroy": (None, [_vp]),
         "ohhg_threads": (C.c_int, []),
+        "ohhg_set_threads": (None, [C.c_int]),
         "ohhg_setup_seconds": (C.c_double, [_vp]),
         "ohhg_ndof": (C.c_longlong, [_vp, C.c_int]),
         "ohhg_nelem": (C.c_longlong, [_vp, C.c_int]),
@@ -100,6 +101,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().ohhg_threads())
+
+
+def set_threads(n: int):
+    """OpenMP threads of the oracle's later calls (for timing on fewer cores)."""
+    lib().ohhg_set_threads(int(n))
 
 
 def _d(a: np.ndarray):

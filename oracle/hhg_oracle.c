@@ -720,6 +720,15 @@ int ohhg_threads(void) {
 #endif
 }
 
+/* number of OpenMP threads of later calls (timing of the CPU baseline) */
+void ohhg_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 double ohhg_setup_seconds(void *vp) { return ((oproblem *)vp)->setup_s; }
 long long ohhg_ndof(void *vp, int l) { return ((oproblem *)vp)->lev[l].ndof; }
 long long ohhg_nelem(void *vp, int l) { return ((oproblem *)vp)->lev[l].ne; }

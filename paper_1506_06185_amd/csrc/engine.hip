@@ -119,11 +119,24 @@ struct LevelDev {
     double *wi15_dn = nullptr;  // intact-side master entries of a Dirichlet-Neumann recovery
     double *mw15 = nullptr, *mwtab = nullptr;  // finest level: mass stencils (indexed like w15, wtab)
     float *w15f = nullptr, *wtabf = nullptr, *wvf = nullptr, *wi15f = nullptr;  // FP32 copies (mixed precision)
+    // fused red-black sweeps (cube, k = 1, unmasked cycles): a second slot
+    // vector of u in the cycle's precision (the pair of sweeps goes u -> ualt
+    // -> u), plane starts and tiles (FusedGeom)
+    double *ualt = nullptr;
+    float *u32alt = nullptr;
+    int *fz_ps = nullptr;
+    int4 *fz_tiles = nullptr;
+    std::vector<int> fz_ps_host;
+    std::vector<int4> fz_tiles_host;
+    int fz_TJ = 0, fz_TK = 0;
+    long long fz_black0 = 0;
+    bool fz_on = false;  // the cycles use fused pairs on this level (autotuner: where faster)
 };
 
 template <typename T>
 struct LevView {
     T *u = nullptr, *b = nullptr, *r = nullptr;
+    T *ualt = nullptr;  // second buffer of fused sweep pairs (unmasked cube cycles with k = 1), or nullptr
     Weights<T> w;
     const VolDesc *vd = nullptr;
     int nvol = 0;
@@ -228,6 +241,53 @@ namespace hhgr {
 namespace {
 
 // ----------------------------------------------------------------------------
+// fused sweep tables of one level: plane starts of each colour, tile shape
+// (i extent fixed by the kernel, rows TJ, planes TK) and the tiles that hold
+// interior nodes
+// ----------------------------------------------------------------------------
+// planes and rows per tile (the LDS of one FP64 workgroup is 288 (7 TJ + 22)
+// bytes with tiles of 64 i values, under 64 KiB for TJ <= 28)
+#ifndef HHGR_FUSED_TK
+#define HHGR_FUSED_TK 16
+#endif
+#ifndef HHGR_FUSED_TJ
+#define HHGR_FUSED_TJ 28
+#endif
+constexpr int kFusedTK = HHGR_FUSED_TK;
+constexpr int kFusedTJ = HHGR_FUSED_TJ;
+
+// false: the kernel cannot take this level (the level keeps two colour passes per sweep)
+bool fused_tables(const TopoLevel &T, LevelDev &D) {
+    const int m = T.m, M = T.M;
+    const ClosureLayout &ly = T.lay;
+    D.fz_black0 = ly.black0;
+    D.fz_ps_host.assign(2 * (size_t)(m + 2), 0);
+    for (int c = 0; c < 2; c++) {
+        for (int k = 0; k <= m; k++)
+            D.fz_ps_host[c * (m + 2) + k] = ly.row0[2 * (size_t)row_id(M, 0, k) + c] - (c ? (int)ly.black0 : 0);
+        D.fz_ps_host[c * (m + 2) + m + 1] = (int)(c ? ly.n_black : ly.n_red);
+    }
+    D.fz_TJ = std::min(kFusedTJ, m);
+    D.fz_TK = std::min(kFusedTK, m);
+    FusedGeom g;
+    g.m = m;
+    g.TJ = D.fz_TJ;
+    g.TK = D.fz_TK;
+    if (!fused_shape_ok(g)) {
+        D.fz_ps_host.clear();
+        D.fz_tiles_host.clear();
+        return false;
+    }
+    const int ti = fused_tile_i();
+    D.fz_tiles_host.clear();
+    for (int k0 = 1; k0 <= m - 3; k0 += D.fz_TK)
+        for (int j0 = 1; j0 <= m - 3; j0 += D.fz_TJ)
+            for (int i0 = 1; i0 <= m - 3; i0 += ti)
+                if (i0 + j0 + k0 <= m - 1) D.fz_tiles_host.push_back(make_int4(i0, j0, k0, 0));
+    return true;
+}
+
+// ----------------------------------------------------------------------------
 // layout of the workspace (sizing and carving share this code)
 // ----------------------------------------------------------------------------
 void carve(hhgr_ctx &c, Carver &cv) {
@@ -312,6 +372,14 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.u32 = cv.take<float>(T.n_slots);
             D.b32 = cv.take<float>(T.n_slots);
             D.r32 = cv.take<float>(T.n_slots);
+        }
+        if (!c.gen && !c.vk && l > c.Lc && T.m >= 8 && fused_tables(T, D)) {
+            D.fz_ps = cv.take<int>(D.fz_ps_host.size());
+            D.fz_tiles = cv.take<int4>(D.fz_tiles_host.size());
+            if (c.mixed)
+                D.u32alt = cv.take<float>(T.n_slots);
+            else
+                D.ualt = cv.take<double>(T.n_slots);
         }
         D.nilist = (int)T.ilist.size();
         D.nrlist = (int)T.rlist.size();
@@ -545,11 +613,11 @@ template <typename T>
 T *lvec(LevelDev &D, int which);
 template <>
 double *lvec<double>(LevelDev &D, int which) {
-    return which == 0 ? D.u : which == 1 ? D.b : D.r;
+    return which == 0 ? D.u : which == 1 ? D.b : which == 2 ? D.r : D.ualt;
 }
 template <>
 float *lvec<float>(LevelDev &D, int which) {
-    return which == 0 ? D.u32 : which == 1 ? D.b32 : D.r32;
+    return which == 0 ? D.u32 : which == 1 ? D.b32 : which == 2 ? D.r32 : D.u32alt;
 }
 
 // global (all tetrahedra) or masked (intact tetrahedra, frozen interface) view
@@ -569,6 +637,7 @@ HView<T> global_view(hhgr_ctx &c, bool masked, int stream_idx) {
         v.u = lvec<T>(D, 0);
         v.b = lvec<T>(D, 1);
         v.r = lvec<T>(D, 2);
+        v.ualt = masked ? nullptr : lvec<T>(D, 3);
         v.w = weights<T>(D);
         v.vd = masked ? D.vd_masked : D.vd_all;
         v.nvol = masked ? D.n_masked : c.n_tets;
@@ -639,6 +708,9 @@ struct NormOut {
     double *partial = nullptr;
     int blocks = 0;
 };
+
+template <typename T>
+bool fused_ok(const hhgr_ctx &c, const HView<T> &V, int l, bool any = false);
 
 // general macro meshes: one 4-colour sweep, classes 0, 1, 2, 3 (a start
 // from zero clears the level's vector first).  The class-3 pass also sums
@@ -715,19 +787,75 @@ void sweep(hhgr_ctx &c, const HView<T> &V, int l, bool zero, hipStream_t s, cons
             launch_colour_res<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, rout);
             continue;
         }
-        const bool timed = c.timing && V.timed && l == c.L;
+        const bool timed = c.timing && V.timed && l == c.L && !fused_ok(c, V, l);
         if (timed) timed_begin(c, s);
         launch_colour<T>(s, vg, ig, v.u, v.b, v.w, c.vk, D.h, c.d.omega, zero, zero && colour == 0);
         if (timed) timed_end(c, s);
     }
 }
 
+// the fused kernels apply: the cube with k = 1, every tetrahedron and
+// every master of the level (no frozen nodes, no intact-side stencils), a
+// second buffer for the level; and the level uses them (any = true: whether
+// or not the autotuner chose them)
+template <typename T>
+bool fused_ok(const hhgr_ctx &c, const HView<T> &V, int l, bool any) {
+    const LevelDev &D = c.lev[l];
+    const LevView<T> &v = V.lv[l];
+    return !c.gen && !c.vk && !V.local && v.ualt && v.ifc && !v.frozen && !v.w.wi && !v.gptr && D.fz_ps &&
+           v.vd == D.vd_all && v.nvol == c.n_tets && (any || D.fz_on);
+}
+
+template <typename T>
+FusedGeom fgeom(const LevelDev &D, const LevView<T> &v) {
+    FusedGeom g;
+    g.vd = v.vd;
+    g.nvol = v.nvol;
+    g.tiles = D.fz_tiles;
+    g.ntiles = (int)D.fz_tiles_host.size();
+    g.m = D.m;
+    g.TJ = D.fz_TJ;
+    g.TK = D.fz_TK;
+    g.black0 = D.fz_black0;
+    g.ps = D.fz_ps;
+    g.remap = D.remap;
+    return g;
+}
+
+// one red-black sweep from us into ud: red masters, the volume interiors
+// (fused kernel), black masters.  zero: from u = 0; rout: black residual tail.
+template <typename T>
+void fused_sweep(hhgr_ctx &c, const HView<T> &V, int l, const T *us, T *ud, bool zero, hipStream_t s, T *rout) {
+    const LevelDev &D = c.lev[l];
+    const LevView<T> &v = V.lv[l];
+    const IfcGeom red = igeom(D, 0, D.n_ifc_red, nullptr, true), black = igeom(D, D.n_ifc_red, D.n_ifc, nullptr, true);
+    launch_ifc_sor<T>(s, red, us, us, ud, v.b, D.h, c.d.omega, zero, zero, (T *)nullptr);
+    const bool timed = c.timing && V.timed && l == c.L && !zero && !rout;
+    if (timed) timed_begin(c, s);
+    launch_sweep_fused_vol<T>(s, fgeom(D, v), us, ud, v.b, D.h, c.d.omega, zero, rout);
+    if (timed) timed_end(c, s);
+    launch_ifc_sor<T>(s, black, us, ud, ud, v.b, D.h, c.d.omega, zero, false, rout);
+}
+
+// nsweeps red-black sweeps in place.  Two sweeps in a row run fused where
+// fused_ok holds, the first into the level's second buffer and the second
+// back (the first sweep may start from zero, the second may write the
+// residual tail); a sweep that adds the coarse-grid correction (pr) or sums
+// the squared residual (nout) runs as two colour passes.
 template <typename T>
 void smooth(hhgr_ctx &c, const HView<T> &V, int l, int nsweeps, bool zero, hipStream_t s,
-            const Prol<T> *pr = nullptr, NormOut *nout = nullptr, T *rout = nullptr) {
-    for (int k = 0; k < nsweeps; k++)
-        sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr, k == nsweeps - 1 ? nout : nullptr,
-              k == nsweeps - 1 ? rout : nullptr);
+            const Prol<T> *pr = nullptr, NormOut *nout = nullptr, T *rout = nullptr, bool force_fused = false) {
+    const LevView<T> &v = V.lv[l];
+    for (int k = 0; k < nsweeps; k++) {
+        const bool last = k == nsweeps - 1;
+        if (k + 1 < nsweeps && fused_ok(c, V, l, force_fused) && !(k == 0 && pr) && !(k + 1 == nsweeps - 1 && nout)) {
+            fused_sweep<T>(c, V, l, v.u, v.ualt, zero && k == 0, s, (T *)nullptr);
+            fused_sweep<T>(c, V, l, v.ualt, v.u, false, s, k + 1 == nsweeps - 1 ? rout : nullptr);
+            k++;
+            continue;
+        }
+        sweep(c, V, l, zero && k == 0, s, k == 0 ? pr : nullptr, last ? nout : nullptr, last ? rout : nullptr);
+    }
 }
 
 template <typename T>
@@ -1392,7 +1520,13 @@ int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_s
                 launch_fill<double>(c->stream, D.mwtab, 15LL * D.wtab_cap, 0.0);
             }
         }
+        if (D.fz_ps) {
+            rc = rc ? rc : upload(*c, D.fz_ps, D.fz_ps_host.data(), D.fz_ps_host.size() * sizeof(int));
+            rc = rc ? rc : upload(*c, D.fz_tiles, D.fz_tiles_host.data(), D.fz_tiles_host.size() * sizeof(int4));
+        }
         // zero every vector (also the Dirichlet ghosts and the zero slot)
+        if (D.ualt) launch_fill<double>(c->stream, D.ualt, T.n_slots, 0.0);
+        if (D.u32alt) launch_fill<float>(c->stream, D.u32alt, T.n_slots, 0.0f);
         launch_fill<double>(c->stream, D.u, T.n_slots, 0.0);
         launch_fill<double>(c->stream, D.b, T.n_slots, 0.0);
         launch_fill<double>(c->stream, D.r, T.n_slots, 0.0);
@@ -1958,7 +2092,15 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
     // class pass of the 4-colour sweep reads the other 3 classes' u
     // (3/4 word per unknown) and 3 words per node of its class (1/4)
     const double w = c->mixed ? 4.0 : 8.0;
-    if (alg_bytes) *alg_bytes = (c->gen ? 1.5 : 2.0) * w * (double)c->n_dofs;
+    const LevelDev &F = c->lev[c->L];
+    if (F.fz_on && (c->mixed ? F.u32alt != nullptr : F.ualt != nullptr)) {
+        // the fused sweep's volume kernel: u (both colours) and b read once,
+        // u written once, over the volume-interior nodes
+        const double mm = F.m;
+        if (alg_bytes) *alg_bytes = 3.0 * w * (double)c->n_tets * (mm - 1) * (mm - 2) * (mm - 3) / 6.0;
+    } else if (alg_bytes) {
+        *alg_bytes = (c->gen ? 1.5 : 2.0) * w * (double)c->n_dofs;
+    }
     return HHGR_OK;
 }
 
@@ -1992,14 +2134,16 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         auto itcr = cache.find(ks.str() + ":cpb_res");
         auto itcp = cache.find(ks.str() + ":cpb_prl");
         auto itcf = cache.find(ks.str() + ":cpb_fus");
+        auto itfz = cache.find(ks.str() + ":fused");
         if (it != cache.end() && itr != cache.end() && itc != cache.end() && itcr != cache.end() &&
-            itcp != cache.end() && itcf != cache.end()) {
+            itcp != cache.end() && itcf != cache.end() && (itfz != cache.end() || !D.fz_ps)) {
             D.bs_sel = it->second;
             D.remap = itr->second;
             D.cpb = itc->second;
             D.cpb_res = itcr->second;
             D.cpb_prl = itcp->second;
             D.cpb_fus = itcf->second;
+            D.fz_on = D.fz_ps && itfz->second != 0;
             continue;
         }
         auto time_it = [&](auto run, int reps) -> float {
@@ -2137,6 +2281,30 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         cache[ks.str() + ":cpb_res"] = D.cpb_res;
         cache[ks.str() + ":cpb_prl"] = D.cpb_prl;
         cache[ks.str() + ":cpb_fus"] = D.cpb_fus;
+        // two sweeps as a fused pair (through the level's second buffer)
+        // against two sweeps of two colour passes each, from the scratch
+        // vector r; the cycles use the pair only where it is faster
+        if (D.fz_ps && (c->mixed ? D.u32alt != nullptr : D.ualt != nullptr)) {
+            HView<double> V64 = global_view<double>(*c, false, 0);
+            HView<float> V32 = global_view<float>(*c, false, 0);
+            V64.lv[l].u = D.r;
+            V32.lv[l].u = D.r32;
+            V64.timed = V32.timed = false;
+            const float t_pair = time_it([&]() {
+                if (c->mixed)
+                    smooth<float>(*c, V32, l, 2, false, c->stream, nullptr, nullptr, nullptr, true);
+                else
+                    smooth<double>(*c, V64, l, 2, false, c->stream, nullptr, nullptr, nullptr, true);
+            }, reps);
+            const float t_plain = time_it([&]() {
+                if (c->mixed)
+                    for (int q = 0; q < 2; q++) sweep<float>(*c, V32, l, false, c->stream);
+                else
+                    for (int q = 0; q < 2; q++) sweep<double>(*c, V64, l, false, c->stream);
+            }, reps);
+            D.fz_on = t_pair < t_plain;
+            cache[ks.str() + ":fused"] = D.fz_on ? 1 : 0;
+        }
         // scratch vector used for timing goes back to zero
         launch_fill<double>(c->stream, D.r, D.n_slots, 0.0);
         if (c->mixed) launch_fill<float>(c->stream, D.r32, D.n_slots, 0.0f);
@@ -2155,11 +2323,15 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
 int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *in1, double *out) {
     if (!c || !in0 || !out) return fail(HHGR_EINVAL, "null argument");
     const bool class_op = c->gen && op >= 9 && op <= 23;
-    if (l < c->Lc || l > c->L || op < 0 || (op > 7 && !class_op)) return fail(HHGR_EINVAL, "bad op or level");
+    const bool fused_op = !c->gen && (op == 9 || op == 10);
+    if (l < c->Lc || l > c->L || op < 0 || (op > 7 && !class_op && !fused_op))
+        return fail(HHGR_EINVAL, "bad op or level");
+    if (fused_op && !fused_ok(*c, global_view<double>(*c, false, 0), l, true))
+        return fail(HHGR_EINVAL, "no fused sweeps on this level of this context");
     if (c->gen && (op == 1 || op == 2)) return fail(HHGR_EINVAL, "general_geometry: class passes are op 8 + class mask");
     if ((op == 4 || op == 5) && l <= c->Lc) return fail(HHGR_EINVAL, "transfer needs level > coarse_level");
     if ((op == 6 || op == 7) && l != c->Lc) return fail(HHGR_EINVAL, "coarse solve needs level = coarse_level");
-    if ((op <= 3 || op == 5 || class_op) && !in1) return fail(HHGR_EINVAL, "null second input");
+    if ((op <= 3 || op == 5 || class_op || fused_op) && !in1) return fail(HHGR_EINVAL, "null second input");
     if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
     if (c->gen && !c->geom_set && op != 4 && op != 5) return fail(HHGR_ESTATE, "no geometry set");
     if (op == 7 && !c->dense_coarse) return fail(HHGR_EINVAL, "no dense coarsest-level inverse in this context");
@@ -2256,6 +2428,16 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
         launch_coarse_dense<double>(s, c->cn, c->cslot, c->cinv, D.b, D.u, c->cptr, c->cidx);
         to_user(D.u, out, D);
         break;
+    case 9:
+    case 10: {
+        // two sweeps as a fused pair (op 10: the first from u = 0)
+        to_slots(in0, D.u, D);
+        to_slots(in1, D.b, D);
+        HView<double> V = global_view<double>(*c, false, 0);
+        smooth<double>(*c, V, l, 2, op == 10, s, nullptr, nullptr, nullptr, true);
+        to_user(D.u, out, D);
+        break;
+    }
     }
     CHKLAUNCH();
     HIPCHK(hipStreamSynchronize(s));

@@ -93,6 +93,42 @@ template <typename T>
 void launch_colour(hipStream_t s, const VolGeom &vg, const IfcGeom &ig, T *u, const T *b, const Weights<T> &w, bool vk,
                    double h, double omega, bool own0, bool nb0);
 
+// Fused red-black sweep on the cube with k = 1 (fused.hip): the volume
+// interiors of the listed tetrahedra, tile by tile.  A tile (i0, j0, k0, -)
+// covers i0 .. i0 + fused_tile_i() - 1, rows j0 .. j0 + TJ - 1 and planes
+// k0 .. k0 + TK - 1 of each tetrahedron's index space; m = segments per macro
+// edge; ps holds the first slot of every plane's red nodes ([0][k]) and
+// black nodes ([1][k], counted from black0), [2][m + 2].
+struct FusedGeom {
+    const VolDesc *vd = nullptr;
+    int nvol = 0;
+    const int4 *tiles = nullptr;
+    int ntiles = 0;
+    int m = 0;
+    int TJ = 0, TK = 0;
+    long long black0 = 0;
+    const int *ps = nullptr;
+    int remap = 1;
+};
+// LDS bytes of one workgroup (word = sizeof(T)), the i extent of a tile, and
+// whether a shape fits the kernel
+size_t fused_lds_bytes(const FusedGeom &g, size_t word);
+int fused_tile_i();
+bool fused_shape_ok(const FusedGeom &g);
+// one sweep of the volume interiors from us to ud (us is not written; ud's
+// red boundary copies must already hold the new red interface values);
+// zero: the sweep starts from u = 0 (us is not read); rout (optional): the
+// black nodes' residual after the sweep, (1 - omega) r
+template <typename T>
+void launch_sweep_fused_vol(hipStream_t s, const FusedGeom &g, const T *us, T *ud, const T *b, double h, double omega,
+                            bool zero, T *rout);
+// SOR update of the interface masters [ig.i0, ig.i1) of one colour with k = 1:
+// own value from us (0 if own0), neighbours from un (0 if nb0), new value to
+// ud at the master and its ghost copies; rout (optional) as above
+template <typename T>
+void launch_ifc_sor(hipStream_t s, const IfcGeom &ig, const T *us, const T *un, T *ud, const T *b, double h,
+                    double omega, bool own0, bool nb0, T *rout);
+
 // coarse-grid correction u += P e_c of the nodes of one colour, in the form
 // launch_prolong takes it (coarse volume descriptors in the fine view's
 // order, coarse row table and closure edge length, [2][n_ifc] coarse slots

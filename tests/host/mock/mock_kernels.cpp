@@ -41,6 +41,23 @@ int launch_colour_norm(hipStream_t, const VolGeom &vg, const IfcGeom &ig, double
     return nb;
 }
 void launch_mass_grid(hipStream_t, int, double, const double *, double *) {}
+size_t fused_lds_bytes(const FusedGeom &g, size_t word) {
+    return (size_t)(4 * (g.TJ + 4) + 3 * (g.TJ + 2)) * 36 * word + 2 * (size_t)(g.m + 2) * sizeof(int);
+}
+int fused_tile_i() { return 64; }
+bool fused_shape_ok(const FusedGeom &) { return true; }
+template <typename T>
+void launch_sweep_fused_vol(hipStream_t, const FusedGeom &, const T *, T *, const T *, double, double, bool, T *) {}
+template void launch_sweep_fused_vol<double>(hipStream_t, const FusedGeom &, const double *, double *, const double *,
+                                             double, double, bool, double *);
+template void launch_sweep_fused_vol<float>(hipStream_t, const FusedGeom &, const float *, float *, const float *,
+                                            double, double, bool, float *);
+template <typename T>
+void launch_ifc_sor(hipStream_t, const IfcGeom &, const T *, const T *, T *, const T *, double, double, bool, bool, T *) {}
+template void launch_ifc_sor<double>(hipStream_t, const IfcGeom &, const double *, const double *, double *,
+                                     const double *, double, double, bool, bool, double *);
+template void launch_ifc_sor<float>(hipStream_t, const IfcGeom &, const float *, const float *, float *, const float *,
+                                    double, double, bool, bool, float *);
 int launch_norm2(hipStream_t, const VolGeom &vg, const IfcGeom &ig, const double *, double *partial) {
     const long long nb = ifc_blocks_of(ig, vg.bs) + list_blocks_of(vg, 4);
     for (long long q = 0; q < nb; q++) partial[q] = q == 0 ? g_mock_res2 : 0.0;

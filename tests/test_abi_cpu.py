@@ -67,3 +67,25 @@ def test_engine_host_logic_under_asan(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, env=env)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "ok" in out.stdout
+
+
+def test_fused_sweep_kernel_in_cpu_emulation(tmp_path):
+    """The fused red-black sweep kernel source (fused.hip) built for the host
+    against a device-code emulation (a workgroup = host threads meeting at a
+    barrier) and run under AddressSanitizer/UBSan: every slot of one fused
+    sweep equals a plain two-colour sweep from the closure layout, bitwise,
+    for several meshes, levels and tile shapes (zero start with a NaN source,
+    residual tail, FP64 and FP32).  Built with tiles of 8 i values instead of
+    64, so that these small levels have several tiles along i as well (the
+    seams between tiles are where the halo logic could go wrong)."""
+    exe = str(tmp_path / "fusedcheck")
+    h = os.path.join(ROOT, "tests/host")
+    subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                    "-ffp-contract=off", "-pthread", "-DHHGR_FUSED_TI=8", "-I" + os.path.join(h, "mockdev"), "-x", "c++",
+                    os.path.join(ROOT, "paper_1506_06185_amd/csrc/fused.hip"), "-x", "none",
+                    os.path.join(h, "fused_check.cpp"), os.path.join(ROOT, "paper_1506_06185_amd/csrc/topology.cpp"),
+                    "-o", exe], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1")
+    out = subprocess.run([exe], capture_output=True, text=True, env=env)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "ok" in out.stdout

@@ -83,6 +83,32 @@ def test_operator_parity(dev, hh, oracle_problem, n_sub, level):
     ctx.close()
 
 
+# fused sweep pairs (one launch per sweep for the volume interiors): two
+# sweeps from a random iterate (op 9) and from zero (op 10), against the
+# oracle and bitwise against two plain sweeps of two colour passes each;
+# the levels give one or several tiles per tetrahedron and ragged ones
+@pytest.mark.parametrize("n_sub,level", [(1, 5), (2, 4), (3, 3), (1, 6), (2, 5)])
+def test_fused_sweep_pair(dev, hh, oracle_problem, n_sub, level):
+    print(f"\n[fused pair] n_sub={n_sub} level={level}", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    p = oracle_problem(n_sub, level)
+    g = np.random.default_rng(50 + 10 * n_sub + level)
+    for l in range(level, 2, -1):
+        nd = p.ndof_at(l)
+        u, b = g.standard_normal(nd), g.standard_normal(nd)
+        uT, bT = T(u, dev), T(b, dev)
+        two = N(hh.debug_op(ctx, 9, l, uT, bT))
+        ref = p.smooth(p.smooth(u, b, level=l), b, level=l)
+        assert rel(two, ref) < 1e-13, l
+        plain = N(hh.debug_op(ctx, 3, l, hh.debug_op(ctx, 3, l, uT, bT), bT))
+        assert np.array_equal(two, plain), l
+        z = N(hh.debug_op(ctx, 10, l, uT, bT))
+        zero = np.zeros(nd)
+        refz = p.smooth(p.smooth(zero, b, level=l), b, level=l)
+        assert rel(z, refz) < 1e-13, l
+    ctx.close()
+
+
 # launch shapes: (workgroup size, XCD-contiguous block order, nodes per thread)
 SHAPES = {"bs256-xcd-1npt": (256, 1, 1), "bs128-hw-4npt": (128, 0, 4), "bs512-xcd-4npt": (512, 1, 4)}
 
