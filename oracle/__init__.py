@@ -90,6 +90,9 @@ def lib():
                                    C.c_int]),
         "ohhg_side_matrix": (_vp, [_vp, C.c_int, _ip, C.c_int, C.c_int]),
         "ohhg_grad_k": (None, [_vp, _dp, _dp, _dp]),
+        "ohhg_create_mesh": (_vp, [C.c_int, _dp, C.c_int, _ip, C.c_int, C.c_int]),
+        "ohhg_mesh_nodes": (C.c_longlong, [_vp, C.c_int, _dp, _lp]),
+        "ohhg_mesh_keys": (None, [_vp, C.c_int, _ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -395,3 +398,66 @@ class Problem:
         out = np.empty(self.nelem_at(self.level))
         lib().ohhg_grad_k(self._h, _d(u), _d(lam), _d(out))
         return out
+
+
+class MeshProblem(Problem):
+    """Poisson problem on a general macro mesh given by vertex and tetrahedron
+    lists (Sec. 3.1), every macro tetrahedron refined regularly ``level``
+    times; Dirichlet boundary on the faces that belong to one tetrahedron.
+
+    Each tetrahedron lists its vertices by a proper 4-colouring of the macro
+    mesh (a vertex has the same position in every tetrahedron around it).
+    Vectors hold the interior nodes in the documented user order: vertices by
+    id, then edges (a < b) by the weight of b, faces (a < b < c) by the weight
+    of c then b, tetrahedron interiors by tet id and the weights of the
+    tetrahedron's vertices 3, 2, 1.
+    """
+
+    def __init__(self, vertices, tets, level: int, coarse_level: int = 2):
+        self._xyz = _f64(vertices).reshape(-1)
+        self._tets = np.ascontiguousarray(np.asarray(tets, dtype=np.int32).reshape(-1))
+        self.nv, self.n_tets = self._xyz.size // 3, self._tets.size // 4
+        if self._xyz.size != 3 * self.nv or self._tets.size != 4 * self.n_tets:
+            raise ValueError("vertices must be (nv, 3) and tets (nt, 4)")
+        self.level, self.coarse_level = int(level), int(coarse_level)
+        self.n_sub, self.general, self._k = None, True, None
+        self._h = lib().ohhg_create_mesh(self.nv, _d(self._xyz), self.n_tets, self._tets.ctypes.data_as(_ip),
+                                         self.level, self.coarse_level)
+        if not self._h:
+            raise ValueError("invalid macro mesh (colouring, ids, flat tetrahedra) or levels")
+        self.ndof = int(lib().ohhg_ndof(self._h, self.level))
+
+    def nodes(self, level: int | None = None):
+        """(positions (n, 3), user index or -1 on the boundary) of every node
+        of a level, in creation order (macro vertices first)."""
+        level = self.level if level is None else level
+        n = int(lib().ohhg_mesh_nodes(self._h, level, None, None))
+        xyz = np.empty(3 * n)
+        dof = np.empty(n, dtype=np.int64)
+        lib().ohhg_mesh_nodes(self._h, level, _d(xyz), dof.ctypes.data_as(_lp))
+        return xyz.reshape(n, 3), dof
+
+    def keys(self, level: int | None = None) -> np.ndarray:
+        """(n, 4, 2) (macro vertex, weight) pairs of every node (vertex -1:
+        unused); the weights sum to 2^level."""
+        level = self.level if level is None else level
+        n = int(lib().ohhg_mesh_nodes(self._h, level, None, None))
+        k = np.empty(8 * n, dtype=np.int32)
+        lib().ohhg_mesh_keys(self._h, level, k.ctypes.data_as(_ip))
+        return k.reshape(n, 4, 2)
+
+    def interior_positions(self, level: int | None = None) -> np.ndarray:
+        """Positions of the interior nodes in user order."""
+        xyz, dof = self.nodes(level)
+        out = np.empty((int((dof >= 0).sum()), 3))
+        out[dof[dof >= 0]] = xyz[dof >= 0]
+        return out
+
+    def positions(self, level: int | None = None):
+        raise NotImplementedError("a general macro mesh has no grid positions: use nodes()")
+
+    def dirichlet_load(self, g, level: int | None = None):
+        raise NotImplementedError("not defined on a general macro mesh")
+
+    def grad_k(self, u, lam):
+        raise NotImplementedError("not defined on a general macro mesh")

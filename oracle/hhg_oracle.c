@@ -214,6 +214,13 @@ typedef struct {
     i64 nred0, nblack1;
     double *xyz; /* vertex positions (3 per vertex) when the geometry is given */
     float *A32, *diag32;
+    /* general macro mesh (vertex and tetrahedron lists): nodes of the level in
+     * creation order; per node its user index (or -1 on the boundary) and its
+     * key: up to 4 (macro vertex, weight) pairs, vertex ascending, -1 padded,
+     * the weights its barycentric coordinates times 2^level */
+    i64 nnode;
+    i64 *dof, *node_of_dof;
+    int *key;
 } olevel;
 
 typedef struct {
@@ -222,6 +229,10 @@ typedef struct {
     int geom; /* 1: vertex positions given, 4-colour smoother */
     olevel lev[MAXLEV];
     double setup_s;
+    /* general macro mesh: macro vertices (colour = the position of the vertex
+     * in the vertex list of each of its tetrahedra) and tetrahedra */
+    int mesh, nv, nt;
+    int *tet_v, *vcol;
 } oproblem;
 
 /* Macro mesh (Sec. 2.1, base mesh): each subcube c of the n^3 split becomes 6
@@ -708,7 +719,12 @@ void ohhg_destroy(void *vp) {
         free(Lv->xyz);
         free(Lv->A32);
         free(Lv->diag32);
+        free(Lv->dof);
+        free(Lv->node_of_dof);
+        free(Lv->key);
     }
+    free(p->tet_v);
+    free(p->vcol);
     free(p);
 }
 
@@ -819,6 +835,481 @@ int ohhg_check_freudenthal(void *vp, int l) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* General macro meshes from vertex and tetrahedron lists (Sec. 3.1: an       */
+/* unstructured macro mesh, every macro element refined regularly)            */
+/* ------------------------------------------------------------------------- */
+/* Input: nv macro vertices (3 coordinates each) and nt tetrahedra (4 vertex
+ * ids each).  The vertex order of every tetrahedron is its order for Bey's
+ * refinement, and it must list the vertices by a proper 4-colouring of the
+ * macro mesh: a vertex is at the same position (its colour 0..3) in every
+ * tetrahedron it belongs to.  A refined node then has the colour class
+ * (sum over macro vertices v of colour(v) x weight(v)) mod 4, weights being
+ * its barycentric coordinates times 2^level; two nodes joined by a refined
+ * edge always differ in class (an edge is parallel to a macro edge, whose
+ * ends differ in colour, or is the octahedron diagonal x02-x13 of Bey's
+ * rule, which changes the class by 2), so the 4 classes are independent sets
+ * of the stiffness matrix and the smoother sweeps them in the order 0, 1, 2, 3.
+ *
+ * Boundary: the faces of exactly one tetrahedron; a node whose support (the
+ * macro vertices with nonzero weight) lies in a boundary face is a Dirichlet
+ * node (value 0).
+ *
+ * Order of the interior nodes (the vector order of callers): vertices by id;
+ * then edges by their vertex pair (a < b), nodes by weight of b; then faces by
+ * their vertex triple (a < b < c), nodes by weight of c, then of b; then
+ * tetrahedra by id, nodes by weight of their vertex 3, then 2, then 1 (the
+ * tetrahedron's own order). */
+
+static int mesh_in_tet(const oproblem *p, const int *key, int tet, int closure);
+
+/* (lo, hi) node pair -> midpoint node: open addressing */
+typedef struct {
+    i64 *k;
+    i64 *v;
+    i64 cap;
+} pairmap;
+
+static void pm_init(pairmap *m, i64 n) {
+    m->cap = 16;
+    while (m->cap < 2 * n) m->cap *= 2;
+    m->k = xmalloc((size_t)m->cap * sizeof(i64));
+    m->v = xmalloc((size_t)m->cap * sizeof(i64));
+    for (i64 i = 0; i < m->cap; i++) m->k[i] = -1;
+}
+static i64 pm_get(pairmap *m, i64 a, i64 b, i64 *next) {
+    const i64 lo = a < b ? a : b, hi = a < b ? b : a;
+    const i64 key = lo * 4294967296LL + hi;
+    i64 h = (i64)(((uint64_t)key * 0x9E3779B97F4A7C15ULL) >> 20) & (m->cap - 1);
+    while (m->k[h] >= 0 && m->k[h] != key) h = (h + 1) & (m->cap - 1);
+    if (m->k[h] < 0) {
+        m->k[h] = key;
+        m->v[h] = (*next)++;
+    }
+    return m->v[h];
+}
+
+/* key of the midpoint of nodes with keys ka, kb of the previous level: the
+ * union of the supports, weights added (each key sums to 2^(l-1), the result
+ * to 2^l) */
+static void key_mid(const int *ka, const int *kb, int *out) {
+    int v[8], w[8], n = 0;
+    for (int s = 0; s < 2; s++) {
+        const int *k = s ? kb : ka;
+        for (int a = 0; a < 4 && k[2 * a] >= 0; a++) {
+            int q = 0;
+            while (q < n && v[q] != k[2 * a]) q++;
+            if (q == n) {
+                v[n] = k[2 * a];
+                w[n++] = 0;
+            }
+            w[q] += k[2 * a + 1];
+        }
+    }
+    if (n > 4) die("midpoint outside every macro tetrahedron");
+    for (int a = 0; a < n; a++)
+        for (int b = a + 1; b < n; b++)
+            if (v[b] < v[a]) {
+                int t = v[a];
+                v[a] = v[b];
+                v[b] = t;
+                t = w[a];
+                w[a] = w[b];
+                w[b] = t;
+            }
+    for (int a = 0; a < 4; a++) {
+        out[2 * a] = a < n ? v[a] : -1;
+        out[2 * a + 1] = a < n ? w[a] : 0;
+    }
+}
+
+static int key_size(const int *k) {
+    int n = 0;
+    while (n < 4 && k[2 * n] >= 0) n++;
+    return n;
+}
+
+static int cmp_int3(const void *a, const void *b) {
+    const int *x = a, *y = b;
+    for (int q = 0; q < 3; q++)
+        if (x[q] != y[q]) return x[q] < y[q] ? -1 : 1;
+    return 0;
+}
+
+/* sorted unique list of the boundary faces (vertex triples, ascending) */
+static int *boundary_faces(const oproblem *p, int *nbf) {
+    const int nf = 4 * p->nt;
+    int *f = xmalloc((size_t)nf * 3 * sizeof(int));
+    for (int t = 0; t < p->nt; t++)
+        for (int o = 0; o < 4; o++) {
+            int q = 0;
+            int *fr = &f[3 * (4 * t + o)];
+            for (int r = 0; r < 4; r++)
+                if (r != o) fr[q++] = p->tet_v[4 * t + r];
+            for (int a = 0; a < 3; a++)
+                for (int b = a + 1; b < 3; b++)
+                    if (fr[b] < fr[a]) {
+                        int tt = fr[a];
+                        fr[a] = fr[b];
+                        fr[b] = tt;
+                    }
+        }
+    qsort(f, (size_t)nf, 3 * sizeof(int), cmp_int3);
+    int *out = xmalloc((size_t)nf * 3 * sizeof(int));
+    int n = 0;
+    for (int i = 0; i < nf;) {
+        int j = i;
+        while (j < nf && cmp_int3(&f[3 * i], &f[3 * j]) == 0) j++;
+        if (j - i == 1) memcpy(&out[3 * n++], &f[3 * i], 3 * sizeof(int));
+        if (j - i > 2) die("a face belongs to more than two tetrahedra");
+        i = j;
+    }
+    free(f);
+    *nbf = n;
+    return out;
+}
+
+/* is the support of key k inside some boundary face? */
+static int mesh_on_boundary(const int *bf, int nbf, const int *k) {
+    const int n = key_size(k);
+    if (n == 4) return 0;
+    for (int q = 0; q < nbf; q++) {
+        int all = 1;
+        for (int a = 0; a < n; a++) {
+            const int v = k[2 * a];
+            all &= bf[3 * q] == v || bf[3 * q + 1] == v || bf[3 * q + 2] == v;
+        }
+        if (all) return 1;
+    }
+    return 0;
+}
+
+typedef struct {
+    int dim;     /* support size - 1 */
+    int prim[4]; /* sorted support vertices, or (tet id, 0, 0, 0) for tetrahedron interiors */
+    int w[3];    /* order within the primitive, most significant first */
+    i64 node;
+} mrec;
+
+static int cmp_mrec(const void *a, const void *b) {
+    const mrec *x = a, *y = b;
+    if (x->dim != y->dim) return x->dim < y->dim ? -1 : 1;
+    for (int q = 0; q < 4; q++)
+        if (x->prim[q] != y->prim[q]) return x->prim[q] < y->prim[q] ? -1 : 1;
+    for (int q = 0; q < 3; q++)
+        if (x->w[q] != y->w[q]) return x->w[q] < y->w[q] ? -1 : 1;
+    return 0;
+}
+
+static int weight_of(const int *k, int v) {
+    for (int a = 0; a < 4; a++)
+        if (k[2 * a] == v) return k[2 * a + 1];
+    return 0;
+}
+
+/* the tetrahedron whose vertex set is the support of k (size 4) */
+static int mesh_tet_of(const oproblem *p, const int *k) {
+    for (int t = 0; t < p->nt; t++)
+        if (mesh_in_tet(p, k, t, 0)) return t;
+    die("interior node outside every tetrahedron");
+    return -1;
+}
+
+/* user order of the interior nodes of level l (see above) */
+static void mesh_order(oproblem *p, int l, const int *bf, int nbf) {
+    olevel *Lv = &p->lev[l];
+    mrec *r = xmalloc((size_t)(Lv->nnode ? Lv->nnode : 1) * sizeof(mrec));
+    i64 n = 0;
+    for (i64 v = 0; v < Lv->nnode; v++) {
+        const int *k = &Lv->key[8 * v];
+        if (mesh_on_boundary(bf, nbf, k)) continue;
+        mrec *e = &r[n++];
+        memset(e, 0, sizeof(*e));
+        e->node = v;
+        const int ns = key_size(k);
+        e->dim = ns - 1;
+        if (ns == 4) {
+            const int t = mesh_tet_of(p, k);
+            e->prim[0] = t;
+            for (int q = 0; q < 3; q++) e->w[q] = weight_of(k, p->tet_v[4 * t + 3 - q]);
+        } else {
+            for (int a = 0; a < ns; a++) e->prim[a] = k[2 * a];
+            for (int a = ns; a < 4; a++) e->prim[a] = -1;
+            /* edge (a, b): weight of b; face (a, b, c): of c, then of b */
+            if (ns == 2) e->w[0] = k[3];
+            if (ns == 3) {
+                e->w[0] = k[5];
+                e->w[1] = k[3];
+            }
+        }
+    }
+    qsort(r, (size_t)n, sizeof(mrec), cmp_mrec);
+    Lv->ndof = n;
+    Lv->dof = xmalloc((size_t)(Lv->nnode ? Lv->nnode : 1) * sizeof(i64));
+    Lv->node_of_dof = xmalloc((size_t)(n ? n : 1) * sizeof(i64));
+    for (i64 v = 0; v < Lv->nnode; v++) Lv->dof[v] = -1;
+    for (i64 q = 0; q < n; q++) {
+        Lv->dof[r[q].node] = q;
+        Lv->node_of_dof[q] = r[q].node;
+    }
+    free(r);
+}
+
+/* triplets (row, col, val) summed into a CSR matrix of nrow x ncol */
+typedef struct {
+    i64 r, c;
+    double v;
+} trip;
+static int cmp_trip(const void *a, const void *b) {
+    const trip *x = a, *y = b;
+    if (x->r != y->r) return x->r < y->r ? -1 : 1;
+    if (x->c != y->c) return x->c < y->c ? -1 : 1;
+    return 0;
+}
+static csr csr_from_trip(trip *t, i64 nt, i64 nrow, i64 ncol) {
+    qsort(t, (size_t)nt, sizeof(trip), cmp_trip);
+    csr m;
+    m.nrow = nrow;
+    m.ncol = ncol;
+    m.ptr = xcalloc((size_t)nrow + 1, sizeof(i64));
+    i64 nnz = 0;
+    for (i64 q = 0; q < nt; q++)
+        if (q == 0 || t[q].r != t[q - 1].r || t[q].c != t[q - 1].c) nnz++;
+    m.col = xmalloc((size_t)(nnz ? nnz : 1) * sizeof(int));
+    m.val = xmalloc((size_t)(nnz ? nnz : 1) * sizeof(double));
+    i64 z = -1;
+    for (i64 q = 0; q < nt; q++) {
+        if (q == 0 || t[q].r != t[q - 1].r || t[q].c != t[q - 1].c) {
+            z++;
+            m.col[z] = (int)t[q].c;
+            m.val[z] = 0.0;
+            m.ptr[t[q].r + 1]++;
+        }
+        m.val[z] += t[q].v;
+    }
+    for (i64 i = 0; i < nrow; i++) m.ptr[i + 1] += m.ptr[i];
+    return m;
+}
+
+/* element-by-element stiffness (which = 0) or mass (which = 1) matrix of a
+ * mesh level in physical coordinates, element e scaled by kcoef[e] (NULL: 1);
+ * rows and columns through map (node -> index or -1 to drop), n indices */
+static csr mesh_assemble(const olevel *Lv, const double *kcoef, int which, const i64 *map, i64 n) {
+    trip *t = xmalloc((size_t)(16 * Lv->ne + 1) * sizeof(trip));
+    i64 nt = 0;
+    for (i64 e = 0; e < Lv->ne; e++) {
+        double K[4][4], Mm[4][4];
+        elem_mats_xyz(Lv->xyz, &Lv->ev[4 * e], K, Mm);
+        const double ke = kcoef ? kcoef[e] : 1.0;
+        for (int a = 0; a < 4; a++) {
+            const i64 r = map ? map[Lv->ev[4 * e + a]] : Lv->ev[4 * e + a];
+            if (r < 0) continue;
+            for (int b = 0; b < 4; b++) {
+                const i64 c = map ? map[Lv->ev[4 * e + b]] : Lv->ev[4 * e + b];
+                if (c < 0) continue;
+                t[nt].r = r;
+                t[nt].c = c;
+                t[nt].v = which ? Mm[a][b] : ke * K[a][b];
+                nt++;
+            }
+        }
+    }
+    csr m = csr_from_trip(t, nt, n, n);
+    free(t);
+    return m;
+}
+
+/* linear interpolation from level l-1: an old node keeps its value, a new
+ * node takes the mean of the two nodes of the coarse edge it bisects; through
+ * the maps (-1: dropped) */
+static csr mesh_prolongation(const olevel *C, const olevel *F, const i64 *mapf, i64 nf, const i64 *mapc, i64 nc) {
+    trip *t = xmalloc((size_t)(2 * F->nnode + 1) * sizeof(trip));
+    i64 nt = 0;
+    for (i64 v = 0; v < F->nnode; v++) {
+        const i64 r = mapf ? mapf[v] : v;
+        if (r < 0) continue;
+        const i64 a = F->par[2 * v], b = F->par[2 * v + 1];
+        const i64 ca = mapc ? mapc[a] : a, cb = mapc ? mapc[b] : b;
+        if (a == b) {
+            if (ca >= 0) t[nt++] = (trip){r, ca, 1.0};
+        } else {
+            if (ca >= 0) t[nt++] = (trip){r, ca, 0.5};
+            if (cb >= 0) t[nt++] = (trip){r, cb, 0.5};
+        }
+    }
+    csr m = csr_from_trip(t, nt, nf, nc);
+    free(t);
+    (void)C;
+    return m;
+}
+
+static void mesh_level_operators(oproblem *p, int l) {
+    olevel *Lv = &p->lev[l];
+    Lv->A = mesh_assemble(Lv, NULL, 0, Lv->dof, Lv->ndof);
+    Lv->diag = xmalloc((size_t)(Lv->ndof ? Lv->ndof : 1) * sizeof(double));
+    for (i64 i = 0; i < Lv->ndof; i++) {
+        Lv->diag[i] = 0.0;
+        for (i64 q = Lv->A.ptr[i]; q < Lv->A.ptr[i + 1]; q++)
+            if (Lv->A.col[q] == i) Lv->diag[i] = Lv->A.val[q];
+    }
+    /* classes 0, 2 (red) and 1, 3 (black), each list in dof order */
+    Lv->red = xmalloc((size_t)(Lv->ndof ? Lv->ndof : 1) * sizeof(i64));
+    Lv->black = xmalloc((size_t)(Lv->ndof ? Lv->ndof : 1) * sizeof(i64));
+    Lv->nred = Lv->nblack = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        for (i64 i = 0; i < Lv->ndof; i++) {
+            const int *k = &Lv->key[8 * Lv->node_of_dof[i]];
+            int c = 0;
+            for (int a = 0; a < 4 && k[2 * a] >= 0; a++) c += p->vcol[k[2 * a]] * k[2 * a + 1];
+            c &= 3;
+            if ((c >> 1) != pass) continue;
+            if ((c & 1) == 0)
+                Lv->red[Lv->nred++] = i;
+            else
+                Lv->black[Lv->nblack++] = i;
+        }
+        if (pass == 0) {
+            Lv->nred0 = Lv->nred;
+            Lv->nblack1 = Lv->nblack;
+        }
+    }
+    if (l > p->Lc) {
+        const olevel *C = &p->lev[l - 1];
+        Lv->P = mesh_prolongation(C, Lv, Lv->dof, Lv->ndof, C->dof, C->ndof);
+        Lv->R = csr_transpose(&Lv->P);
+    }
+    Lv->built = 1;
+}
+
+void *ohhg_create_mesh(int nv, const double *xyz, int nt, const int *tets, int L, int Lc) {
+    if (nv < 4 || nt < 1 || !xyz || !tets || L < 1 || L >= MAXLEV || Lc < 1 || Lc > L) return NULL;
+    double t0 = now_s();
+    oproblem *p = xcalloc(1, sizeof(oproblem));
+    p->mesh = 1;
+    p->geom = 1;
+    p->L = L;
+    p->Lc = Lc;
+    p->nv = nv;
+    p->nt = nt;
+    p->tet_v = xmalloc((size_t)nt * 4 * sizeof(int));
+    memcpy(p->tet_v, tets, (size_t)nt * 4 * sizeof(int));
+    p->vcol = xmalloc((size_t)nv * sizeof(int));
+    for (int v = 0; v < nv; v++) p->vcol[v] = -1;
+    for (int t = 0; t < nt; t++)
+        for (int r = 0; r < 4; r++) {
+            const int v = tets[4 * t + r];
+            if (v < 0 || v >= nv || (p->vcol[v] >= 0 && p->vcol[v] != r)) {
+                ohhg_destroy(p);
+                return NULL;
+            }
+            p->vcol[v] = r;
+        }
+    /* level 0: the macro mesh */
+    olevel *M0 = &p->lev[0];
+    M0->nnode = nv;
+    M0->ne = nt;
+    M0->ev = xmalloc((size_t)nt * 4 * sizeof(int));
+    memcpy(M0->ev, tets, (size_t)nt * 4 * sizeof(int));
+    M0->xyz = xmalloc((size_t)nv * 3 * sizeof(double));
+    memcpy(M0->xyz, xyz, (size_t)nv * 3 * sizeof(double));
+    M0->key = xmalloc((size_t)nv * 8 * sizeof(int));
+    M0->par = xmalloc((size_t)nv * 2 * sizeof(int));
+    for (int v = 0; v < nv; v++) {
+        for (int a = 0; a < 8; a++) M0->key[8 * v + a] = a == 0 ? v : a == 1 ? 1 : a % 2 == 0 ? -1 : 0;
+        M0->par[2 * v] = M0->par[2 * v + 1] = v;
+    }
+    for (int t = 0; t < nt; t++) {
+        /* reject flat macro tetrahedra (6 x volume = det of the edge vectors) */
+        const int *e = &M0->ev[4 * t];
+        double J[3][3];
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) J[r][c] = xyz[3 * e[c + 1] + r] - xyz[3 * e[0] + r];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(fabs(det) > 0.0)) {
+            ohhg_destroy(p);
+            return NULL;
+        }
+    }
+    /* Bey's regular refinement, as on the cube (children of element e at
+     * 8e..8e+7); midpoints are shared between the elements of an edge */
+    static const int CH[8][4] = {{0, 4, 5, 6}, {4, 1, 7, 8}, {5, 7, 2, 9}, {6, 8, 9, 3},
+                                 {4, 5, 6, 8}, {4, 5, 7, 8}, {5, 6, 8, 9}, {5, 7, 8, 9}};
+    static const int MID[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int l = 1; l <= L; l++) {
+        olevel *C = &p->lev[l - 1], *F = &p->lev[l];
+        pairmap pm;
+        pm_init(&pm, 6 * C->ne + 16);
+        i64 next = C->nnode;
+        F->ne = 8 * C->ne;
+        F->ev = xmalloc((size_t)F->ne * 4 * sizeof(int));
+        int *mid = xmalloc((size_t)C->ne * 6 * sizeof(int));
+        for (i64 e = 0; e < C->ne; e++)
+            for (int q = 0; q < 6; q++)
+                mid[6 * e + q] = (int)pm_get(&pm, C->ev[4 * e + MID[q][0]], C->ev[4 * e + MID[q][1]], &next);
+        F->nnode = next;
+        F->xyz = xmalloc((size_t)F->nnode * 3 * sizeof(double));
+        F->key = xmalloc((size_t)F->nnode * 8 * sizeof(int));
+        F->par = xmalloc((size_t)F->nnode * 2 * sizeof(int));
+        for (i64 v = 0; v < C->nnode; v++) {
+            for (int a = 0; a < 3; a++) F->xyz[3 * v + a] = C->xyz[3 * v + a];
+            for (int a = 0; a < 4; a++) {
+                F->key[8 * v + 2 * a] = C->key[8 * v + 2 * a];
+                F->key[8 * v + 2 * a + 1] = 2 * C->key[8 * v + 2 * a + 1];
+            }
+            F->par[2 * v] = F->par[2 * v + 1] = (int)v;
+        }
+        for (i64 e = 0; e < C->ne; e++) {
+            int node[10];
+            for (int a = 0; a < 4; a++) node[a] = C->ev[4 * e + a];
+            for (int q = 0; q < 6; q++) {
+                const int a = C->ev[4 * e + MID[q][0]], b = C->ev[4 * e + MID[q][1]], v = mid[6 * e + q];
+                node[4 + q] = v;
+                F->par[2 * v] = a;
+                F->par[2 * v + 1] = b;
+                for (int d = 0; d < 3; d++) F->xyz[3 * v + d] = 0.5 * (C->xyz[3 * a + d] + C->xyz[3 * b + d]);
+                key_mid(&C->key[8 * a], &C->key[8 * b], &F->key[8 * v]);
+            }
+            for (int c = 0; c < 8; c++)
+                for (int a = 0; a < 4; a++) F->ev[4 * (8 * e + c) + a] = node[CH[c][a]];
+        }
+        free(mid);
+        free(pm.k);
+        free(pm.v);
+    }
+    int nbf = 0;
+    int *bf = boundary_faces(p, &nbf);
+    for (int l = 0; l <= L; l++) mesh_order(p, l, bf, nbf);
+    free(bf);
+    for (int l = 0; l <= L; l++) {
+        olevel *Lv = &p->lev[l];
+        Lv->k = xmalloc((size_t)Lv->ne * sizeof(double));
+        for (i64 e = 0; e < Lv->ne; e++) Lv->k[e] = 1.0;
+        Lv->ecl = xmalloc((size_t)Lv->ne * sizeof(i64));
+        for (i64 e = 0; e < Lv->ne; e++) Lv->ecl[e] = e;
+    }
+    for (int l = Lc; l <= L; l++) mesh_level_operators(p, l);
+    p->setup_s = now_s() - t0;
+    return p;
+}
+
+/* nodes of level l of a general macro mesh in creation order: positions
+ * (3 each) and user index (-1 on the boundary); returns the node count */
+long long ohhg_mesh_nodes(void *vp, int l, double *xyz, long long *dof) {
+    const olevel *Lv = &((oproblem *)vp)->lev[l];
+    if (xyz) memcpy(xyz, Lv->xyz, (size_t)Lv->nnode * 3 * sizeof(double));
+    if (dof)
+        for (i64 v = 0; v < Lv->nnode; v++) dof[v] = Lv->dof[v];
+    return Lv->nnode;
+}
+
+/* keys of the nodes of level l (8 ints each, see olevel) */
+void ohhg_mesh_keys(void *vp, int l, int *keys) {
+    const olevel *Lv = &((oproblem *)vp)->lev[l];
+    memcpy(keys, Lv->key, (size_t)Lv->nnode * 8 * sizeof(int));
+}
+
+/* ------------------------------------------------------------------------- */
 /* Matrix export (for the tests' independent checks)                          */
 /* ------------------------------------------------------------------------- */
 /* which: 0 = A, 1 = M, 2 = P (level <- level-1); +3 for the variants that keep
@@ -829,6 +1320,20 @@ void *ohhg_matrix(void *vp, int l, int which) {
     csr *m = xcalloc(1, sizeof(csr));
     int interior = which < 3;
     int kind = which % 3;
+    if (p->mesh) {
+        /* general macro mesh: interior rows in user order, or every node in
+         * creation order */
+        if (kind == 2) {
+            if (l < 1) die("no prolongation into level 0");
+            const olevel *C = &p->lev[l - 1];
+            *m = interior ? mesh_prolongation(C, Lv, Lv->dof, Lv->ndof, C->dof, C->ndof)
+                          : mesh_prolongation(C, Lv, NULL, Lv->nnode, NULL, C->nnode);
+        } else {
+            *m = interior ? mesh_assemble(Lv, NULL, kind, Lv->dof, Lv->ndof)
+                          : mesh_assemble(Lv, NULL, kind, NULL, Lv->nnode);
+        }
+        return m;
+    }
     if (kind == 2) {
         if (l < 1) die("no prolongation into level 0");
         *m = prolongation(&p->lev[l - 1], Lv, interior);
@@ -896,10 +1401,30 @@ static int tet_locate(const oproblem *p, int tet, int l, const i64 X[3]) {
     return zero == 0 ? 2 : 1;
 }
 
+/* general macro mesh: 1 if the node's support (the macro vertices with a
+ * nonzero weight in its key) lies in tetrahedron tet; with closure = 0 only
+ * nodes strictly inside it (support = all four of its vertices) count */
+static int mesh_in_tet(const oproblem *p, const int *key, int tet, int closure) {
+    int ns = 0;
+    for (int a = 0; a < 4; a++) {
+        if (key[2 * a] < 0) continue;
+        ns++;
+        int found = 0;
+        for (int r = 0; r < 4; r++) found |= p->tet_v[4 * tet + r] == key[2 * a];
+        if (!found) return 0;
+    }
+    return closure ? 1 : ns == 4;
+}
+
 /* mask over interior dofs of level l: nodes strictly inside (closure=0) or in
  * the closed tetrahedron (closure=1). */
 void ohhg_tet_mask(void *vp, int l, int tet, int closure, unsigned char *mask) {
     oproblem *p = vp;
+    if (p->mesh) {
+        const olevel *Lv = &p->lev[l];
+        for (i64 i = 0; i < Lv->ndof; i++) mask[i] = (unsigned char)mesh_in_tet(p, &Lv->key[8 * Lv->node_of_dof[i]], tet, closure);
+        return;
+    }
     const int N = p->lev[l].N;
 #pragma omp parallel for schedule(static)
     for (i64 i = 0; i < p->lev[l].ndof; i++) {
@@ -917,6 +1442,15 @@ void ohhg_tet_mask(void *vp, int l, int tet, int closure, unsigned char *mask) {
 /* per interior dof: number of macro tetrahedra whose closure contains it */
 void ohhg_containment_counts(void *vp, int l, int *count) {
     oproblem *p = vp;
+    if (p->mesh) {
+        const olevel *Lv = &p->lev[l];
+        for (i64 i = 0; i < Lv->ndof; i++) {
+            int c = 0;
+            for (int q = 0; q < p->nt; q++) c += mesh_in_tet(p, &Lv->key[8 * Lv->node_of_dof[i]], q, 1);
+            count[i] = c;
+        }
+        return;
+    }
     const int N = p->lev[l].N;
     const int nt = (int)p->lev[0].ne;
 #pragma omp parallel for schedule(static)
@@ -1161,7 +1695,7 @@ static double resnorm(const csr *A, const double *u, const double *b) {
 /* ------------------------------------------------------------------------- */
 static void ensure_mass(oproblem *p, int l) {
     olevel *Lv = &p->lev[l];
-    if (Lv->M.ptr == NULL) Lv->M = assemble(Lv, NULL, 1, 1);
+    if (Lv->M.ptr == NULL) Lv->M = p->mesh ? mesh_assemble(Lv, NULL, 1, Lv->dof, Lv->ndof) : assemble(Lv, NULL, 1, 1);
 }
 
 void ohhg_apply_A(void *vp, int l, const double *u, double *out) {
@@ -1393,7 +1927,7 @@ static csr side_matrix(const oproblem *p, int l, const int *tets, int nt, int si
     unsigned char *faulty = xcalloc((size_t)p->lev[0].ne, 1);
     for (int q = 0; q < nt; q++) faulty[tets[q]] = 1;
     double *k = side_coeff(p, l, faulty, side);
-    csr A = assemble(&p->lev[l], k, 0, 1);
+    csr A = p->mesh ? mesh_assemble(&p->lev[l], k, 0, p->lev[l].dof, p->lev[l].ndof) : assemble(&p->lev[l], k, 0, 1);
     free(k);
     free(faulty);
     return A;

@@ -220,3 +220,91 @@ def macro_tet_corners(vertices: np.ndarray, n_sub: int, tet: int) -> np.ndarray:
     n = int(n_sub)
     idx = [v[0] + (n + 1) * (v[1] + (n + 1) * v[2]) for v in macro_tet_vertices(n, tet)]
     return np.asarray(vertices)[idx]
+
+
+# ---------------------------------------------------------------------------
+# Unstructured macro meshes (vertex and tetrahedron lists).  Every tetrahedron
+# lists its vertices by a proper 4-colouring of the mesh: a vertex has the
+# same position (its colour) in every tetrahedron that contains it.
+# ---------------------------------------------------------------------------
+STREAM_MESH_VERTICES = 9
+
+
+def octahedron_mesh(centre: bool = True):
+    """The octahedron |x| + |y| + |z| <= 1.  With ``centre``: 8 tetrahedra
+    around an interior vertex at the origin (colours: origin 0, poles 1,
+    equator vertices 2 and 3 alternately); without: 4 tetrahedra around the
+    polar axis (poles 0 and 1, equator 2 and 3).  Returns (vertices (nv, 3),
+    tets (nt, 4) int32)."""
+    eq = [[1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0]]
+    if centre:
+        v = np.array([[0, 0, 0], [0, 0, 1], [0, 0, -1]] + eq, dtype=np.float64)
+        tets = []
+        for pole in (1, 2):
+            for i in range(4):
+                a, b = 3 + i, 3 + (i + 1) % 4
+                even, odd = (a, b) if i % 2 == 0 else (b, a)
+                tets.append([0, pole, even, odd])
+    else:
+        v = np.array([[0, 0, 1], [0, 0, -1]] + eq, dtype=np.float64)
+        tets = []
+        for i in range(4):
+            a, b = 2 + i, 2 + (i + 1) % 4
+            even, odd = (a, b) if i % 2 == 0 else (b, a)
+            tets.append([0, 1, even, odd])
+    return v, np.asarray(tets, dtype=np.int32)
+
+
+# colour of a grid vertex of the 5-tetrahedra box split, by the parities of
+# its coordinates (x + 2y + 4z bit pattern): a vertex and its antipode in a
+# cube share a colour, the 4 even-parity corners of a cube have 4 colours
+_BOX_COLOUR = {0b000: 0, 0b111: 0, 0b011: 1, 0b100: 1, 0b101: 2, 0b010: 2, 0b110: 3, 0b001: 3}
+
+
+def box_mesh(nx: int, ny: int, nz: int):
+    """The box [0, nx] x [0, ny] x [0, nz] of unit cubes, each split into 5
+    tetrahedra: the central one on the cube's 4 corners of even coordinate
+    sum, and one corner tetrahedron per odd corner with its 3 neighbours.
+    Neighbouring cubes then split their common face along the same diagonal.
+    Vertex id = x + (nx+1) (y + (ny+1) z); tets ordered cube by cube (x
+    fastest), central first, then the corners by ascending vertex id."""
+    def vid(x, y, z):
+        return x + (nx + 1) * (y + (ny + 1) * z)
+
+    def colour(x, y, z):
+        return _BOX_COLOUR[(x & 1) | ((y & 1) << 1) | ((z & 1) << 2)]
+
+    def ordered(vs):
+        out = [None] * 4
+        for p in vs:
+            c = colour(*p)
+            assert out[c] is None
+            out[c] = vid(*p)
+        return out
+
+    tets = []
+    for cz in range(nz):
+        for cy in range(ny):
+            for cx in range(nx):
+                corners = [(cx + a, cy + b, cz + c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+                even = [p for p in corners if sum(p) % 2 == 0]
+                odd = sorted((p for p in corners if sum(p) % 2 == 1), key=lambda p: vid(*p))
+                tets.append(ordered(even))
+                for p in odd:
+                    nb = [q for q in even if sum(abs(q[i] - p[i]) for i in range(3)) == 1]
+                    tets.append(ordered([p] + nb))
+    z, y, x = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    v = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(np.float64)
+    return v, np.asarray(tets, dtype=np.int32)
+
+
+def perturb_mesh(vertices: np.ndarray, seed: int = 0, amplitude: float = 0.15) -> np.ndarray:
+    """Each vertex moved by amplitude times a U[-1, 1]^3 draw (the domain
+    changes with it)."""
+    v = np.asarray(vertices, dtype=np.float64)
+    return np.ascontiguousarray(v + amplitude * rng(seed, STREAM_MESH_VERTICES).uniform(-1.0, 1.0, v.shape))
+
+
+def mesh_fault_tet(n_tets: int, seed: int = 0) -> int:
+    """Macro tetrahedron of an unstructured mesh that fails (uniform)."""
+    return int(rng(seed, STREAM_FAULT_TET).integers(0, int(n_tets)))
