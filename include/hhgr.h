@@ -133,6 +133,39 @@ int hhgr_sizes(const hhgr_ctx *ctx, long long *n_dofs, int *n_tets, long long *n
  * stencil tables for its FP32 cycle. */
 int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
+/* Unstructured macro meshes (Sec. 3.1: the macro mesh is an arbitrary
+ * conforming tetrahedral mesh whose elements are refined regularly; eq. (2)
+ * assembled with P1 elements in physical coordinates, k = 1).  Host arrays,
+ * read during the call: nv vertices (host_xyz, 3 doubles each) and nt
+ * tetrahedra (host_tets, 4 vertex ids each).  Every tetrahedron lists its
+ * vertices by a proper 4-colouring of the mesh: a vertex takes the same
+ * position 0..3 in every tetrahedron that contains it (the smoother's 4
+ * classes are (sum of colour x weight) mod 4 of a refined node, which no
+ * element edge couples to themselves; a sweep visits classes 0, 1, 2, 3).
+ * Closure node (i,j,k) of a tetrahedron has the weights (m-i-j-k, i, j, k),
+ * m = 2^level, on its vertices 0..3.  The Dirichlet boundary (u = 0) is the
+ * union of the faces that belong to one tetrahedron.  Vectors list the
+ * interior nodes in this order: interior macro vertices by id; interior
+ * edges (a < b, by vertex pair) with their nodes by the weight of b; interior
+ * faces (a < b < c) with their nodes by the weight of c, then of b; then the
+ * interiors of the tetrahedra by id, each in plane k, row j, i order (i, j,
+ * k >= 1, i + j + k < m).  desc: level, coarse_level (>= 2), nu_pre, nu_post,
+ * omega, precision and max_faults as above; n_sub and general_geometry are
+ * ignored; variable_coeff must be 0.  The coarsest level is solved with a
+ * dense inverse (at most 2048 unknowns).  A mesh context takes hhgr_set_rhs
+ * with HHGR_RHS_LOAD, hhgr_set_solution/get_solution, hhgr_vcycle,
+ * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_set_graph,
+ * hhgr_kernel_timing/stats and hhgr_debug_op (ops 0, 3 to 5, 7, 8 + class
+ * mask); every other call returns EINVAL for it.  hhgr_sizes reports the
+ * interior unknowns, nt and nt 8^level.  EINVAL for a mesh that is not
+ * coloured that way, has an id out of range, a vertex in no tetrahedron, a
+ * flat tetrahedron, a face of more than two tetrahedra, or a coarsest level
+ * that is too large; the message names the reason. */
+int hhgr_mesh_workspace_bytes(const hhgr_desc *desc, int nv, const double *host_xyz, int nt, const int *host_tets,
+                              size_t *bytes);
+int hhgr_create_mesh(const hhgr_desc *desc, int nv, const double *host_xyz, int nt, const int *host_tets,
+                     void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out);
+
 /* Right-hand side of eq. (2) from a device vector in the vector order above.
  * kind = HHGR_RHS_LOAD: the vector is the load vector b itself;
  * kind = HHGR_RHS_NODAL_F: the vector holds nodal values of f (zero on the

@@ -51,6 +51,8 @@ constexpr int kCoarseMaxit = 2000;
 // largest coarsest level (unknowns) solved with a precomputed dense inverse
 // (k = 1; 512^2 FP64 = 2 MiB of workspace)
 constexpr int kDenseCoarseMax = 512;
+// ... on an unstructured macro mesh, whose coarsest level has no other solver
+constexpr int kDenseCoarseMaxMesh = 2048;
 constexpr int kMaxLevels = 10;
 
 // bump allocator over the caller's workspace; with base == nullptr it only sizes
@@ -77,6 +79,8 @@ struct LevelDev {
     int cpb_res = 1; // ... of the residual, of the prolongation and of the red
     int cpb_prl = 1; // post-smoothing pass that adds the correction (autotuned
     int cpb_fus = 1; // separately)
+    int nbw = 15;    // entries per master of the general-mesh stencil and restriction tables
+    long long vbase = 0, nint = 0;  // unstructured macro meshes: user order of the volume interiors
     int *nbr = nullptr, *gptr = nullptr, *gidx = nullptr, *rst = nullptr, *prl = nullptr, *nb15 = nullptr;
     int *ifc_dof = nullptr, *ifc_xyz = nullptr, *tg_dst = nullptr, *tg_src = nullptr;
     std::vector<int> tg_ptr;
@@ -194,6 +198,7 @@ struct hhgr_ctx {
     double *cinv = nullptr;
     // general macro meshes: 15-point coarsest-level operator
     bool gen = false, geom_set = false;
+    bool mesh = false;  // unstructured macro mesh (hhgr_create_mesh): gen, operator fixed at creation
     int *ccol15 = nullptr;
     double *cval15 = nullptr;
     double *kel = nullptr;  // unit-size element matrices per macro tet and axis order
@@ -288,6 +293,35 @@ bool fused_tables(const TopoLevel &T, LevelDev &D) {
 }
 
 // ----------------------------------------------------------------------------
+// user vector <-> slot space of one level (D of context c).  to_slots sets
+// every slot of the closures (ghost copies from their masters, Dirichlet
+// ghosts zero) and the masters; to_user reads the interior nodes and masters.
+// ----------------------------------------------------------------------------
+VolGeom vgeom(const LevelDev &D, const VolDesc *vd, int nvol, bool full, int bsq, int colour);
+IfcGeom igeom(const LevelDev &D, int i0, int i1, const unsigned char *frozen, bool scatter);
+
+void to_slots(const hhgr_ctx &c, const LevelDev &D, const double *user, double *vec, hipStream_t s) {
+    const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
+    if (c.mesh) {
+        launch_mesh_user_to_slots<double>(s, vgeom(D, D.vd_all, c.n_tets, false, -1, -1), D.vbase, D.nint, ig,
+                                          D.ifc_dof, user, vec);
+        launch_ghost_refresh<double>(s, D.tg_dst, D.tg_src, D.tg_ptr.back(), vec);
+    } else {
+        launch_user_to_slots<double>(s, vgeom(D, D.vd_all, c.n_tets, true, -1, -1), c.tetinfo, D.m, D.N, ig,
+                                     D.ifc_dof, user, vec);
+    }
+}
+
+void to_user(const hhgr_ctx &c, const LevelDev &D, const double *vec, double *user, hipStream_t s) {
+    const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
+    const VolGeom vint = vgeom(D, D.vd_all, c.n_tets, false, -1, -1);
+    if (c.mesh)
+        launch_mesh_slots_to_user<double>(s, vint, D.vbase, D.nint, ig, D.ifc_dof, vec, user);
+    else
+        launch_slots_to_user<double>(s, vint, c.tetinfo, D.m, D.N, ig, D.ifc_dof, vec, user);
+}
+
+// ----------------------------------------------------------------------------
 // layout of the workspace (sizing and carving share this code)
 // ----------------------------------------------------------------------------
 void carve(hhgr_ctx &c, Carver &cv) {
@@ -309,6 +343,10 @@ void carve(hhgr_ctx &c, Carver &cv) {
         D.n_slots = T.n_slots;
         D.n_ifc = T.n_ifc;
         D.n_ifc_red = T.n_ifc_red;
+        D.nbw = tp.nbw;
+        D.vbase = T.vbase;
+        D.nint = T.nint;
+        const size_t W = (size_t)tp.nbw;
         {
             // most blocks of a launch with per-block partial sums: smallest
             // workgroup, one node per thread, the longest node list
@@ -320,8 +358,8 @@ void carve(hhgr_ctx &c, Carver &cv) {
         D.gptr = cv.take<int>(T.n_ifc + 1);
         D.gidx = cv.take<int>(T.gidx.size());
         if (l > c.Lc) D.prl = cv.take<int>(2 * (size_t)T.n_ifc);
-        if (l < c.L) D.rst = cv.take<int>(15 * (size_t)T.n_ifc);
-        if (l == c.L || c.gen) D.nb15 = cv.take<int>(15 * (size_t)T.n_ifc);
+        if (l < c.L) D.rst = cv.take<int>(W * T.n_ifc);
+        if (l == c.L || c.gen) D.nb15 = cv.take<int>(W * T.n_ifc);
         if (c.gen) {
             // the class lists (nodes, masters) back to back, so that classes
             // 0..2 form a prefix of each
@@ -344,15 +382,26 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.w15 = cv.take<double>(15 * (size_t)c.n_tets);
             // distinct master stencils: at most one per primitive (4 faces,
             // 6 edges, 4 vertices per tetrahedron), one zero stencil first
-            D.wtab_cap = 1 + 14 * c.n_tets;
+            D.wtab_cap = c.mesh ? 1 : 1 + 14 * c.n_tets;
             D.wtab = cv.take<double>(15 * (size_t)D.wtab_cap);
             D.sid = cv.take<int>(T.n_ifc);
-            D.wi15_dn = cv.take<double>(15 * (size_t)T.n_ifc);
-            if (l == c.L) {
+            if (c.mesh) {
+                // masters carry their own stencils (no mass matrix, no
+                // Dirichlet-Neumann recovery on a mesh)
+                D.wi15 = cv.take<double>(W * T.n_ifc);
+                if (c.mixed) {
+                    D.w15f = cv.take<float>(15 * (size_t)c.n_tets);
+                    D.wi15f = cv.take<float>(W * T.n_ifc);
+                }
+            } else {
+                D.wi15_dn = cv.take<double>(15 * (size_t)T.n_ifc);
+            }
+            if (l == c.L && !c.mesh) {
                 D.mw15 = cv.take<double>(15 * (size_t)c.n_tets);
                 D.mwtab = cv.take<double>(15 * (size_t)D.wtab_cap);
             }
-            if (c.mixed && c.vk) {
+            if (c.mesh) {
+            } else if (c.mixed && c.vk) {
                 D.wvf = cv.take<float>(8 * (size_t)T.n_slots);
                 D.wi15f = cv.take<float>(15 * (size_t)T.n_ifc);
             } else if (c.mixed) {
@@ -440,7 +489,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.cval_dn = cv.take<double>(7 * (size_t)c.cn);
     c.dn_faulty = cv.take<unsigned char>(c.n_tets);
     c.citers = cv.take<int>(4);
-    if (!c.vk && c.cn <= kDenseCoarseMax) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
+    if (!c.vk && c.cn <= (c.mesh ? kDenseCoarseMaxMesh : kDenseCoarseMax)) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
@@ -477,6 +526,39 @@ std::string get_topology(int n_sub, int L, int Lc, std::shared_ptr<const Topolog
     std::lock_guard<std::mutex> g(mu);
     cache.push_back({key, t});
     if (cache.size() > 6) cache.erase(cache.begin());
+    out = t;
+    return "";
+}
+
+// unstructured macro meshes: the same cache, keyed by a hash of the mesh
+std::string get_mesh_topology(int nv, const double *xyz, int nt, const int *tets, int L, int Lc,
+                              std::shared_ptr<const Topology> &out) {
+    if (!xyz || !tets || nv < 1 || nt < 1) return "null or empty mesh";
+    uint64_t h = 1469598103934665603ULL;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t q = 0; q < n; q++) h = (h ^ b[q]) * 1099511628211ULL;
+    };
+    mix(xyz, 3 * sizeof(double) * (size_t)nv);
+    mix(tets, 4 * sizeof(int) * (size_t)nt);
+    static std::mutex mu;
+    static std::vector<std::pair<std::tuple<uint64_t, int, int, int, int>, std::shared_ptr<const Topology>>> cache;
+    const auto key = std::make_tuple(h, nv, nt, L, Lc);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto &e : cache)
+            if (e.first == key) {
+                out = e.second;
+                return "";
+            }
+    }
+    auto t = std::make_shared<Topology>();
+    std::string err = t->build_mesh(nv, xyz, nt, tets, L, Lc);
+    if (!err.empty()) return err;
+    if (t->coarse.n > kDenseCoarseMaxMesh) return "the coarsest level has more unknowns than the dense solver takes";
+    std::lock_guard<std::mutex> g(mu);
+    cache.push_back({key, t});
+    if (cache.size() > 4) cache.erase(cache.begin());
     out = t;
     return "";
 }
@@ -532,6 +614,7 @@ IfcGeom igeom(const LevelDev &D, int i0, int i1, const unsigned char *frozen, bo
     g.gptr = scatter ? D.gptr : nullptr;
     g.gidx = scatter ? D.gidx : nullptr;
     g.frozen = frozen;
+    g.w = D.nbw;
     return g;
 }
 
@@ -1118,6 +1201,7 @@ int upload(hhgr_ctx &c, void *dst, const void *src, size_t bytes) {
 // the faulty tetrahedra run local cycles; the two share no unknowns
 // ----------------------------------------------------------------------------
 int dd_check(const hhgr_ctx &c, const int *tets, int n_tets, int n_intact, int n_local, std::vector<int> &ft) {
+    if (c.mesh) return fail(HHGR_EINVAL, "Dirichlet-Dirichlet and Dirichlet-Neumann recoveries are not built for unstructured macro meshes");
     if (!tets || n_tets < 1 || n_tets > c.d.max_faults) return fail(HHGR_EINVAL, "need 1..max_faults tets");
     if (n_intact < 0 || n_local < 0) return fail(HHGR_EINVAL, "negative cycle count");
     if (c.Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
@@ -1414,12 +1498,13 @@ namespace {
 // read-back buffer; without them (a context that allocates nothing) the
 // norms are read back into pageable host memory and the context supports
 // set_rhs, solve and get_solution only (no graphs, recoveries or batches).
-int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, bool own_objects,
-               hhgr_ctx **out) {
+int create_ctx(const hhgr_desc *desc, std::shared_ptr<const Topology> mesh_topo, void *dev_ws, size_t ws_bytes,
+               void *hip_stream, bool own_objects, hhgr_ctx **out) {
     if (!out) return fail(HHGR_EINVAL, "null output pointer");
     *out = nullptr;
     std::string e = check_desc(desc);
     if (!e.empty()) return fail(HHGR_EINVAL, e);
+    if (mesh_topo && desc->variable_coeff) return fail(HHGR_EINVAL, "an unstructured macro mesh takes k = 1 only");
     if (!dev_ws) return fail(HHGR_EINVAL, "null workspace");
     if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0) return fail(HHGR_EINVAL, "workspace must be 256-byte aligned");
     hhgr_ctx *c = new hhgr_ctx();
@@ -1434,10 +1519,18 @@ int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_s
     c->mixed = desc->precision == HHGR_MIXED;
     c->gen = desc->general_geometry != 0;
     c->stream = (hipStream_t)hip_stream;
-    std::string te = get_topology(desc->n_sub, c->L, c->Lc, c->topo_hold);
-    if (!te.empty()) {
-        delete c;
-        return fail(HHGR_EINVAL, te);
+    if (mesh_topo) {
+        c->topo_hold = mesh_topo;
+        c->mesh = c->gen = true;
+        c->n_tets = mesh_topo->n_tets;
+        c->n_dofs = mesh_topo->n_dofs;
+        c->n_elems = (long long)c->n_tets << (3 * c->L);
+    } else {
+        std::string te = get_topology(desc->n_sub, c->L, c->Lc, c->topo_hold);
+        if (!te.empty()) {
+            delete c;
+            return fail(HHGR_EINVAL, te);
+        }
     }
     c->topo = c->topo_hold.get();
     Carver sz;
@@ -1511,6 +1604,19 @@ int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_s
                 rc = rc ? rc : upload(*c, D.ifcq[q], T.ifcq[q].data(), T.ifcq[q].size() * sizeof(int));
             }
             rc = rc ? rc : upload(*c, D.rowN15, T.rowN15.data(), T.rowN15.size() * 16 * sizeof(int));
+            if (c->mesh) {
+                // the operator of a mesh comes with its topology
+                rc = rc ? rc : upload(*c, D.w15, T.mesh_w15.data(), T.mesh_w15.size() * sizeof(double));
+                rc = rc ? rc : upload(*c, D.wi15, T.mesh_wi.data(), T.mesh_wi.size() * sizeof(double));
+                launch_fill<double>(c->stream, D.wtab, 15LL * D.wtab_cap, 0.0);
+                launch_fill<unsigned int>(c->stream, reinterpret_cast<unsigned int *>(D.sid), T.n_ifc, 0u);
+                if (c->mixed) {
+                    launch_cast<double, float>(c->stream, D.w15, D.w15f, 15LL * c->n_tets);
+                    launch_cast<double, float>(c->stream, D.wi15, D.wi15f, (long long)tp.nbw * T.n_ifc);
+                }
+            }
+        }
+        if (c->gen && !c->mesh) {
             // no operator until hhgr_set_geometry
             launch_fill<double>(c->stream, D.w15, 15LL * c->n_tets, 0.0);
             launch_fill<double>(c->stream, D.wtab, 15LL * D.wtab_cap, 0.0);
@@ -1551,8 +1657,8 @@ int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_s
                 for (int s = 0; s < 3; s++) launch_fill<float>(c->stream, D.w32[s], T.n_slots, 0.0f);
         }
     }
-    std::vector<int> tinfo(6 * (size_t)c->n_tets);
-    for (int t = 0; t < c->n_tets; t++)
+    std::vector<int> tinfo(6 * (size_t)c->n_tets, 0);  // (cube position and axis order; unused on a mesh)
+    for (int t = 0; t < c->n_tets && !c->mesh; t++)
         for (int a = 0; a < 3; a++) {
             tinfo[6 * t + a] = tp.V0[t][a];
             tinfo[6 * t + 3 + a] = tp.perm[t][a];
@@ -1570,6 +1676,13 @@ int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_s
     if (!c->gen && c->cinv && coarse_inverse(cs.n, 7, cs.col, cs.val, cinv_host)) {
         rc = rc ? rc : upload(*c, c->cinv, cinv_host.data(), cinv_host.size() * sizeof(double));
         c->dense_coarse = true;
+    }
+    if (c->mesh) {
+        if (!c->cinv || !coarse_inverse(cs.n, cs.cw, cs.colw, cs.valw, cinv_host))
+            return bail(fail(HHGR_EINVAL, "the coarsest-level operator of the mesh is not positive definite"));
+        rc = rc ? rc : upload(*c, c->cinv, cinv_host.data(), cinv_host.size() * sizeof(double));
+        c->dense_coarse = true;
+        c->geom_set = true;
     }
     rc = rc ? rc : upload(*c, c->cptr, cs.cptr.data(), cs.cptr.size() * sizeof(int));
     rc = rc ? rc : upload(*c, c->cidx, cs.cidx.data(), cs.cidx.size() * sizeof(int));
@@ -1597,7 +1710,56 @@ int create_ctx(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_s
 extern "C" {
 
 int hhgr_create(const hhgr_desc *desc, void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out) {
-    return create_ctx(desc, dev_ws, ws_bytes, hip_stream, true, out);
+    return create_ctx(desc, nullptr, dev_ws, ws_bytes, hip_stream, true, out);
+}
+
+// a mesh context ignores n_sub and general_geometry
+static hhgr_desc mesh_desc(const hhgr_desc *desc) {
+    hhgr_desc d = *desc;
+    d.n_sub = 1;
+    d.general_geometry = 1;
+    return d;
+}
+
+int hhgr_mesh_workspace_bytes(const hhgr_desc *desc_in, int nv, const double *host_xyz, int nt, const int *host_tets,
+                              size_t *bytes) {
+    if (!desc_in) return fail(HHGR_EINVAL, "null descriptor");
+    const hhgr_desc dd = mesh_desc(desc_in);
+    const hhgr_desc *desc = &dd;
+    std::string e = check_desc(desc);
+    if (!e.empty()) return fail(HHGR_EINVAL, e);
+    if (!bytes) return fail(HHGR_EINVAL, "null bytes pointer");
+    if (desc->variable_coeff) return fail(HHGR_EINVAL, "an unstructured macro mesh takes k = 1 only");
+    hhgr_ctx c;
+    c.d = *desc;
+    c.L = desc->level;
+    c.Lc = desc->coarse_level;
+    c.mixed = desc->precision == HHGR_MIXED;
+    c.gen = c.mesh = true;
+    std::string te = get_mesh_topology(nv, host_xyz, nt, host_tets, c.L, c.Lc, c.topo_hold);
+    if (!te.empty()) return fail(HHGR_EINVAL, te);
+    c.topo = c.topo_hold.get();
+    c.n_tets = c.topo->n_tets;
+    c.n_dofs = c.topo->n_dofs;
+    Carver cv;
+    carve(c, cv);
+    *bytes = cv.off + 256;
+    return HHGR_OK;
+}
+
+int hhgr_create_mesh(const hhgr_desc *desc_in, int nv, const double *host_xyz, int nt, const int *host_tets,
+                     void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out) {
+    if (!out) return fail(HHGR_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!desc_in) return fail(HHGR_EINVAL, "null descriptor");
+    const hhgr_desc dd = mesh_desc(desc_in);
+    const hhgr_desc *desc = &dd;
+    std::string e = check_desc(desc);
+    if (!e.empty()) return fail(HHGR_EINVAL, e);
+    std::shared_ptr<const Topology> tp;
+    std::string te = get_mesh_topology(nv, host_xyz, nt, host_tets, desc->level, desc->coarse_level, tp);
+    if (!te.empty()) return fail(HHGR_EINVAL, te);
+    return create_ctx(desc, tp, dev_ws, ws_bytes, hip_stream, true, out);
 }
 
 void hhgr_destroy(hhgr_ctx *c) {
@@ -1637,8 +1799,10 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     bool aux_used = false;  // aux_u held the load in vector order
+    if (c->mesh && kind != HHGR_RHS_LOAD)
+        return fail(HHGR_EINVAL, "an unstructured macro mesh takes a load vector (HHGR_RHS_LOAD) only");
     if (kind == HHGR_RHS_LOAD) {
-        launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.b);
+        to_slots(*c, D, dev_vec, D.b, c->stream);
     } else if (kind == HHGR_RHS_DIRICHLET && c->gen) {
         launch_gen_dirichlet(c->stream, vint, ig, gen15(D, -1, false), c->tetinfo, D.ifc_xyz, D.N, dev_vec, D.b);
     } else if (kind == HHGR_RHS_DIRICHLET) {
@@ -1709,6 +1873,7 @@ int hhgr_set_coeff(hhgr_ctx *c, const double *dev_k) {
 int hhgr_set_geometry(hhgr_ctx *c, const double *host_xyz) {
     if (!c || !host_xyz) return fail(HHGR_EINVAL, "null argument");
     if (!c->gen) return fail(HHGR_ESTATE, "context created with general_geometry = 0");
+    if (c->mesh) return fail(HHGR_EINVAL, "an unstructured macro mesh takes its geometry at creation");
     const Topology &tp = *c->topo;
     std::string e = check_macro_mesh(tp, host_xyz);
     if (!e.empty()) return fail(HHGR_EINVAL, e);
@@ -1775,8 +1940,7 @@ int hhgr_set_solution(hhgr_ctx *c, const double *dev_u) {
         CHKLAUNCH();
         return HHGR_OK;
     }
-    launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N,
-                                 igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, dev_u, D.u);
+    to_slots(*c, D, dev_u, D.u, c->stream);
     CHKLAUNCH();
     return HHGR_OK;
 }
@@ -1785,8 +1949,7 @@ int hhgr_get_solution(const hhgr_ctx *cc, double *dev_u) {
     hhgr_ctx *c = const_cast<hhgr_ctx *>(cc);
     if (!c || !dev_u) return fail(HHGR_EINVAL, "null argument");
     LevelDev &D = c->lev[c->L];
-    launch_slots_to_user<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N,
-                                 igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, D.u, dev_u);
+    to_user(*c, D, D.u, dev_u, c->stream);
     CHKLAUNCH();
     return HHGR_OK;
 }
@@ -1947,6 +2110,7 @@ int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 
 int hhgr_mass_apply(hhgr_ctx *c, const double *dev_x, double *dev_y) {
     if (!c || !dev_x || !dev_y) return fail(HHGR_EINVAL, "null argument");
+    if (c->mesh) return fail(HHGR_EINVAL, "no mass matrix on an unstructured macro mesh");
     if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     LevelDev &D = c->lev[c->L];
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
@@ -1966,6 +2130,7 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
                       double *dev_dJdk) {
     int rc = check_ready(c);
     if (rc) return rc;
+    if (c->mesh) return fail(HHGR_EINVAL, "no adjoint on an unstructured macro mesh");
     if (!dev_g) return fail(HHGR_EINVAL, "null g");
     if (dev_dJdk && !c->vk) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
     LevelDev &D = c->lev[c->L];
@@ -2106,6 +2271,7 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
 
 int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
     if (!c) return fail(HHGR_EINVAL, "null context");
+    if (c->mesh) return fail(HHGR_EINVAL, "no autotuning on an unstructured macro mesh (default launch shapes)");
     if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     hipDeviceProp_t prop;
     int dev = 0;
@@ -2335,16 +2501,11 @@ int hhgr_debug_op(hhgr_ctx *c, int op, int l, const double *in0, const double *i
     if (c->vk && !c->coeff_set) return fail(HHGR_ESTATE, "no coefficient set");
     if (c->gen && !c->geom_set && op != 4 && op != 5) return fail(HHGR_ESTATE, "no geometry set");
     if (op == 7 && !c->dense_coarse) return fail(HHGR_EINVAL, "no dense coarsest-level inverse in this context");
+    if (op == 6 && c->mesh) return fail(HHGR_EINVAL, "an unstructured macro mesh solves its coarsest level densely (op 7)");
     invalidate_graph(*c);
     hipStream_t s = c->stream;
-    auto to_slots = [&](const double *user, double *vec, LevelDev &D) {
-        launch_user_to_slots<double>(s, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N,
-                                     igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, user, vec);
-    };
-    auto to_user = [&](const double *vec, double *user, LevelDev &D) {
-        launch_slots_to_user<double>(s, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N,
-                                     igeom(D, 0, D.n_ifc, nullptr, false), D.ifc_dof, vec, user);
-    };
+    auto to_slots = [&](const double *user, double *vec, LevelDev &D) { hhgr::to_slots(*c, D, user, vec, s); };
+    auto to_user = [&](const double *vec, double *user, LevelDev &D) { hhgr::to_user(*c, D, vec, user, s); };
     LevelDev &D = c->lev[l];
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const Weights<double> w = weights<double>(D);
@@ -2453,6 +2614,7 @@ int hhgr_batch_create(hhgr_ctx **ctxs, int n, void *hip_stream, hhgr_batch **out
     if (!ctxs || n < 1) return fail(HHGR_EINVAL, "need at least one member");
     for (int q = 0; q < n; q++) {
         if (!ctxs[q]) return fail(HHGR_EINVAL, "null member");
+        if (ctxs[q]->mesh) return fail(HHGR_EINVAL, "batches take cube contexts only");
         for (int p = 0; p < q; p++)
             if (ctxs[p] == ctxs[q]) return fail(HHGR_EINVAL, "a context appears twice in the batch");
     }
@@ -2719,7 +2881,7 @@ int hhgr_solve_static(const hhgr_desc *desc, const double *dev_rhs, int kind, do
     // Dirichlet ghosts, partial sums, counters), so the previous call's
     // contents do not matter
     hhgr_ctx *c = nullptr;
-    rc = create_ctx(desc, S.ptr, kStaticScratchBytes, hip_stream, false, &c);
+    rc = create_ctx(desc, nullptr, S.ptr, kStaticScratchBytes, hip_stream, false, &c);
     if (rc) return rc;
     rc = hhgr_set_rhs(c, dev_rhs, kind);
     hhgr_report rep{0, 0.0, nullptr, 0};

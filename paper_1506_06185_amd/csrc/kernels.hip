@@ -399,6 +399,7 @@ __global__ void __launch_bounds__(512) k_restrict(VolGeom vc, const VolDesc *__r
         T s = T(0);
 #pragma unroll
         for (int e = 1; e < 15; e++) s += rf[rst[(long long)e * ig.stride + t]];
+        for (int e = 15; e < ig.w; e++) s += rf[rst[(long long)e * ig.stride + t]];
         bc[ig.base + t] = rf[rst[t]] + T(0.5) * s;
         return;
     }
@@ -512,6 +513,9 @@ __device__ __forceinline__ T master_Au(const IfcGeom &ig, const Gen15 &g, const 
         diag = wi[t];
 #pragma unroll
         for (int n = 1; n < 15; n++)
+            acc += wi[(long long)n * ig.stride + t] * u[g.nb15[(long long)n * ig.stride + t]];
+        // wider stencils of unstructured macro meshes (vertices of high valence)
+        for (int n = 15; n < ig.w; n++)
             acc += wi[(long long)n * ig.stride + t] * u[g.nb15[(long long)n * ig.stride + t]];
     } else {
         const T *w = gsel<T>(g.wtab, g.wtabf) + 15LL * g.sid[t];
@@ -1005,6 +1009,54 @@ __global__ void __launch_bounds__(512) k_slots_to_user(VolGeom vg, const int *__
             (long long)(X[0] - 1) + (long long)(N - 1) * ((X[1] - 1) + (long long)(N - 1) * (X[2] - 1));
         user[dof] = (double)(vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)];
     }
+}
+
+// rank of interior node (i, j, k) among the interior nodes of a closure with
+// m = M - 1 segments, in plane k, row j, i order: the planes below hold
+// C(p,3) - C(p-k+1,3) nodes (p = m - 1), the rows below in plane k
+// (j - 1)(p - k) - (j - 1) j / 2
+__device__ __forceinline__ long long interior_rank(int M, int i, int j, int k) {
+    const long long p = M - 2, a = p - k + 1;
+    const long long below = (p * (p - 1) * (p - 2) - a * (a - 1) * (a - 2)) / 6;
+    return below + (long long)(j - 1) * (p - k) - (long long)(j - 1) * j / 2 + (i - 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_mesh_user_to_slots(VolGeom vg, long long vbase, long long nint, IfcGeom ig,
+                                                            int nib, const int *__restrict__ ifc_dof,
+                                                            const double *__restrict__ user, T *__restrict__ vec) {
+    const unsigned f = blockIdx.x;
+    if (f < (unsigned)nib) {
+        const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
+        if (t >= ig.i1) return;
+        vec[ig.base + t] = (T)user[ifc_dof[t]];
+        return;
+    }
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    LNode n;
+    if (!list_node<1>(vg, block_order(f - nib, gridDim.x - nib, vg.remap), per_vol, 0, n)) return;
+    const VolDesc d = vg.vd[n.v];
+    const long long dof = vbase + (long long)d.tet * nint + interior_rank(vg.M, n.i, n.j, n.k);
+    (vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)] = (T)user[dof];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_mesh_slots_to_user(VolGeom vg, long long vbase, long long nint, IfcGeom ig,
+                                                            int nib, const int *__restrict__ ifc_dof,
+                                                            const T *__restrict__ vec, double *__restrict__ user) {
+    const unsigned f = blockIdx.x;
+    if (f < (unsigned)nib) {
+        const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
+        if (t >= ig.i1) return;
+        user[ifc_dof[t]] = (double)vec[ig.base + t];
+        return;
+    }
+    const unsigned per_vol = list_blocks_per_vol<1>(vg);
+    LNode n;
+    if (!list_node<1>(vg, block_order(f - nib, gridDim.x - nib, vg.remap), per_vol, 0, n)) return;
+    const VolDesc d = vg.vd[n.v];
+    const long long dof = vbase + (long long)d.tet * nint + interior_rank(vg.M, n.i, n.j, n.k);
+    user[dof] = (double)(vec + d.vec)[lslot(vg.rowC, vg.M, n.i, n.j, n.k)];
 }
 
 // consistent P1 mass matrix on the Kuhn meshes: diagonal 24 h^3/60, axis
@@ -1885,6 +1937,31 @@ void launch_slots_to_user(hipStream_t s, const VolGeom &vint, const int *tetinfo
         hipLaunchKernelGGL((k_slots_to_user<T, 4>), dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, tetinfo, m, N, ig,
                            nib, ifc_dof, vec, user);
 }
+
+template <typename T>
+void launch_mesh_user_to_slots(hipStream_t s, const VolGeom &vint, long long vbase, long long nint, const IfcGeom &ig,
+                               const int *ifc_dof, const double *user, T *vec) {
+    const int nib = ifc_blocks(ig, vint.bs);
+    const long long grid = nib + list_blocks(vint, 1);
+    if (grid == 0) return;
+    hipLaunchKernelGGL((k_mesh_user_to_slots<T>), dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, vbase, nint, ig,
+                       nib, ifc_dof, user, vec);
+}
+
+template <typename T>
+void launch_mesh_slots_to_user(hipStream_t s, const VolGeom &vint, long long vbase, long long nint, const IfcGeom &ig,
+                               const int *ifc_dof, const T *vec, double *user) {
+    const int nib = ifc_blocks(ig, vint.bs);
+    const long long grid = nib + list_blocks(vint, 1);
+    if (grid == 0) return;
+    hipLaunchKernelGGL((k_mesh_slots_to_user<T>), dim3((unsigned)grid), dim3(vint.bs), 0, s, vint, vbase, nint, ig,
+                       nib, ifc_dof, vec, user);
+}
+
+template void launch_mesh_user_to_slots<double>(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &,
+                                                const int *, const double *, double *);
+template void launch_mesh_slots_to_user<double>(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &,
+                                                const int *, const double *, double *);
 
 void launch_mass(hipStream_t s, const VolGeom &vint, const IfcGeom &ig, const int *nb15, const double *x, double *y,
                  double h) {

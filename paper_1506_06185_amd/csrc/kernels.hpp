@@ -40,6 +40,7 @@ struct IfcGeom {
     const int *gptr = nullptr;          // ghost copies (CSR) or nullptr
     const int *gidx = nullptr;
     const unsigned char *frozen = nullptr;  // Dirichlet-frozen nodes or nullptr
+    int w = 15;  // entries per master of the 15-point (general mesh) stencil and restriction tables
 };
 
 // General macro meshes (moved macro vertices): 15-point stencils.  A volume
@@ -224,6 +225,17 @@ void launch_reduce(hipStream_t s, const double *partial, int n, double *out);
 
 template <typename T>
 void launch_fill(hipStream_t s, T *p, long long n, T v);
+
+// unstructured macro meshes: user vector <-> slot space for the interior
+// nodes of the listed volumes (user index vbase + tet nint + the node's rank
+// in plane k, row j, i order) and the masters of ig (ifc_dof); the ghost
+// copies are set separately (launch_ghost_refresh)
+template <typename T>
+void launch_mesh_user_to_slots(hipStream_t s, const VolGeom &vint, long long vbase, long long nint, const IfcGeom &ig,
+                               const int *ifc_dof, const double *user, T *vec);
+template <typename T>
+void launch_mesh_slots_to_user(hipStream_t s, const VolGeom &vint, long long vbase, long long nint, const IfcGeom &ig,
+                               const int *ifc_dof, const T *vec, double *user);
 
 // user vector (global lexicographic interior order) <-> slot space; vfull
 // lists every closure node (ghosts receive the user value or the Dirichlet zero)

@@ -70,6 +70,68 @@ long long Topology::slot_of(int l, int x, int y, int z) const {
     return (long long)t * Lv.C_pad + Lv.lay.index(i, j, k);
 }
 
+// Node lists and row tables of the colour-split closure layout of a level
+// (the same for every tetrahedron and every macro mesh).
+void build_closure_tables(TopoLevel &Lv) {
+    const int m = Lv.m, M = Lv.M;
+    // node lists and row tables (shared by all tetrahedra), in slot order
+    Lv.rlist.clear();
+    Lv.blist.clear();
+    Lv.flist.clear();
+    for (int c = 0; c < 2; c++)
+        for (int k = 0; k <= m; k++)
+            for (int j = 0; j <= m - k; j++)
+                for (int i = (c + k) & 1; i <= m - k - j; i += 2) {
+                    const unsigned w = pack_ijk(i, j, k);
+                    Lv.flist.push_back(w);
+                    if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1) (c == 0 ? Lv.rlist : Lv.blist).push_back(w);
+                }
+    // all interior nodes row by row (plane k, row j; a row's red nodes, then
+    // its black ones): a launch over both colours then reads each row's u and
+    // b once while they are in cache, instead of once per colour half
+    Lv.ilist.clear();
+    for (int k = 1; k <= m - 3; k++)
+        for (int j = 1; j <= m - 2 - k; j++)
+            for (int c = 0; c < 2; c++)
+                for (int i = 1 + ((1 + c + k) & 1); i <= m - 1 - k - j; i += 2) Lv.ilist.push_back(pack_ijk(i, j, k));
+    for (int q = 0; q < 4; q++) Lv.qlist[q].clear();
+    for (int c = 0; c < 2; c++)
+        for (unsigned w : (c ? Lv.blist : Lv.rlist)) {
+            const int i = (int)(w & 1023u), j = (int)((w >> 10) & 1023u), k = (int)(w >> 20);
+            Lv.qlist[(i + 2 * j + 3 * k) & 3].push_back(w);
+        }
+    const int nrows = M * (M + 1) / 2;
+    Lv.rowC.assign(nrows, {0, 0});
+    for (int r = 0; r < nrows; r++) Lv.rowC[r] = {Lv.lay.row0[2 * (size_t)r], Lv.lay.row0[2 * (size_t)r + 1]};
+    Lv.rowN.assign(2 * (size_t)nrows, {0, 0, 0, 0, 0, 0, 0, 0});
+    for (int c = 0; c < 2; c++)
+        for (int k = 1; k <= m - 3; k++)
+            for (int j = 1; j + k <= m - 2; j++) {
+                const int o = 1 - c, odd = (c + k) & 1;
+                auto start = [&](int jj, int kk, int cc) { return Lv.lay.row0[2 * (size_t)row_id(M, jj, kk) + cc]; };
+                Lv.rowN[(size_t)c * nrows + row_id(M, j, k)] = {start(j, k, c),          start(j, k, o) + odd,
+                                                                start(j + 1, k, o) + odd - 1,
+                                                                start(j - 1, k, o) + odd, start(j - 1, k + 1, o),
+                                                                start(j + 1, k - 1, o),   0, 0};
+            }
+    // 15-point bases: node i = 2t + p (p = (c + k) & 1) of row (j, k); its
+    // neighbour at index offset (di, dj, dk) has parity colour (c + di + dk) & 1
+    // and storage index (i + di) >> 1 = t + ((p + di) >> 1)
+    Lv.rowN15.assign(2 * (size_t)nrows, {});
+    for (int c = 0; c < 2; c++)
+        for (int k = 1; k <= m - 3; k++)
+            for (int j = 1; j + k <= m - 2; j++) {
+                const int p = (c + k) & 1;
+                auto &e = Lv.rowN15[(size_t)c * nrows + row_id(M, j, k)];
+                for (int n = 0; n < 15; n++) {
+                    const int di = kIdx15[n][0], dj = kIdx15[n][1], dk = kIdx15[n][2];
+                    const int cc = (c + di + dk) & 1;
+                    e[n] = Lv.lay.row0[2 * (size_t)row_id(M, j + dj, k + dk) + cc] + ((p + di) >> 1);
+                }
+                e[15] = 0;
+            }
+}
+
 void Topology::build_level(int l) {
     TopoLevel &Lv = lev[l];
     Lv.l = l;
@@ -197,67 +259,12 @@ void Topology::build_level(int l) {
             Lv.nb15[(size_t)e * Lv.n_ifc + f] = (int)slot_of(l, X[0] + kGrid15[e][0], X[1] + kGrid15[e][1], X[2] + kGrid15[e][2]);
         }
 
-    // node lists and row tables (shared by all tetrahedra), in slot order
-    Lv.rlist.clear();
-    Lv.blist.clear();
-    Lv.flist.clear();
-    for (int c = 0; c < 2; c++)
-        for (int k = 0; k <= m; k++)
-            for (int j = 0; j <= m - k; j++)
-                for (int i = (c + k) & 1; i <= m - k - j; i += 2) {
-                    const unsigned w = pack_ijk(i, j, k);
-                    Lv.flist.push_back(w);
-                    if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= m - 1) (c == 0 ? Lv.rlist : Lv.blist).push_back(w);
-                }
-    // all interior nodes row by row (plane k, row j; a row's red nodes, then
-    // its black ones): a launch over both colours then reads each row's u and
-    // b once while they are in cache, instead of once per colour half
-    Lv.ilist.clear();
-    for (int k = 1; k <= m - 3; k++)
-        for (int j = 1; j <= m - 2 - k; j++)
-            for (int c = 0; c < 2; c++)
-                for (int i = 1 + ((1 + c + k) & 1); i <= m - 1 - k - j; i += 2) Lv.ilist.push_back(pack_ijk(i, j, k));
-    for (int q = 0; q < 4; q++) Lv.qlist[q].clear();
-    for (int c = 0; c < 2; c++)
-        for (unsigned w : (c ? Lv.blist : Lv.rlist)) {
-            const int i = (int)(w & 1023u), j = (int)((w >> 10) & 1023u), k = (int)(w >> 20);
-            Lv.qlist[(i + 2 * j + 3 * k) & 3].push_back(w);
-        }
     for (int q = 0; q < 4; q++) Lv.ifcq[q].clear();
     for (int f = 0; f < Lv.n_ifc; f++) {
         const auto &X = Lv.ifc_X[f];
         Lv.ifcq[(X[0] + X[1] + X[2]) & 3].push_back(f);
     }
-    const int nrows = M * (M + 1) / 2;
-    Lv.rowC.assign(nrows, {0, 0});
-    for (int r = 0; r < nrows; r++) Lv.rowC[r] = {Lv.lay.row0[2 * (size_t)r], Lv.lay.row0[2 * (size_t)r + 1]};
-    Lv.rowN.assign(2 * (size_t)nrows, {0, 0, 0, 0, 0, 0, 0, 0});
-    for (int c = 0; c < 2; c++)
-        for (int k = 1; k <= m - 3; k++)
-            for (int j = 1; j + k <= m - 2; j++) {
-                const int o = 1 - c, odd = (c + k) & 1;
-                auto start = [&](int jj, int kk, int cc) { return Lv.lay.row0[2 * (size_t)row_id(M, jj, kk) + cc]; };
-                Lv.rowN[(size_t)c * nrows + row_id(M, j, k)] = {start(j, k, c),          start(j, k, o) + odd,
-                                                                start(j + 1, k, o) + odd - 1,
-                                                                start(j - 1, k, o) + odd, start(j - 1, k + 1, o),
-                                                                start(j + 1, k - 1, o),   0, 0};
-            }
-    // 15-point bases: node i = 2t + p (p = (c + k) & 1) of row (j, k); its
-    // neighbour at index offset (di, dj, dk) has parity colour (c + di + dk) & 1
-    // and storage index (i + di) >> 1 = t + ((p + di) >> 1)
-    Lv.rowN15.assign(2 * (size_t)nrows, {});
-    for (int c = 0; c < 2; c++)
-        for (int k = 1; k <= m - 3; k++)
-            for (int j = 1; j + k <= m - 2; j++) {
-                const int p = (c + k) & 1;
-                auto &e = Lv.rowN15[(size_t)c * nrows + row_id(M, j, k)];
-                for (int n = 0; n < 15; n++) {
-                    const int di = kIdx15[n][0], dj = kIdx15[n][1], dk = kIdx15[n][2];
-                    const int cc = (c + di + dk) & 1;
-                    e[n] = Lv.lay.row0[2 * (size_t)row_id(M, j + dj, k + dk) + cc] + ((p + di) >> 1);
-                }
-                e[15] = 0;
-            }
+    build_closure_tables(Lv);
 }
 
 void Topology::build_transfer(int l) {

@@ -112,6 +112,14 @@ struct TopoLevel {
     std::array<std::vector<unsigned>, 4> qlist;
     std::vector<std::array<int, 16>> rowN15;
     std::array<std::vector<int>, 4> ifcq;
+    // unstructured macro meshes (Topology::build_mesh): user index of a
+    // tetrahedron's first interior node is vbase + t nint (interior nodes in
+    // plane k, row j, i order); the stiffness stencil of every tetrahedron's
+    // interior nodes (kIdx15 order, [15 t + n]) and of every master
+    // ([n n_ifc + f], n < Topology::nbw, entry 0 the diagonal, at the slots
+    // nb15 of the same layout; unused entries 0 at the zero slot)
+    long long vbase = 0, nint = 0;
+    std::vector<double> mesh_w15, mesh_wi;
 };
 
 // index-space offsets of the 15-point stencil (centre first); offset n
@@ -138,6 +146,10 @@ struct CoarseSystem {
     std::vector<int> is_vol;         // 1 if volume-interior unknown
     std::vector<int> tet;            // tet of a volume unknown, -1 for interface
     std::vector<int> ifc;            // interface index, -1 for volume
+    // unstructured macro meshes: rows of cw entries (column -1: none)
+    int cw = 0;
+    std::vector<int> colw;
+    std::vector<double> valw;
 };
 
 struct Topology {
@@ -149,6 +161,22 @@ struct Topology {
 
     // Builds everything.  Returns an empty string on success, else the error.
     std::string build(int n_sub, int L, int Lc);
+
+    // Unstructured macro mesh (mesh.cpp): nv vertices (xyz, 3 each) and nt
+    // tetrahedra (tets, 4 vertex ids each, listed by a proper 4-colouring of
+    // the vertices: a vertex has the same position in every tetrahedron that
+    // contains it).  Closure node (i, j, k) of tetrahedron t is the node with
+    // weights (m - i - j - k, i, j, k) on its vertices 0..3; a node is known
+    // by its (macro vertex, weight) pairs.  Interface masters carry their own
+    // stencils (nbw entries), and the user order is: interior macro vertices
+    // by id, interior edges (a < b) by the weight of b, interior faces
+    // (a < b < c) by the weights of c then b, tetrahedron interiors by tet id
+    // in plane k, row j, i order.  Fills the stencils and the coarsest-level
+    // rows too.  Returns an empty string on success, else the error.
+    std::string build_mesh(int nv, const double *xyz, int nt, const int *tets, int L, int Lc);
+    bool mesh = false;
+    int nbw = 15;  // interface stencil and restriction width
+    long long n_dofs = 0;
 
     // slot of grid node X at level l (zero slot for boundary nodes)
     long long slot_of(int l, int x, int y, int z) const;
@@ -163,6 +191,10 @@ struct Topology {
     void build_transfer(int l);
     void build_coarse();
 };
+
+// node lists and row tables of the colour-split closure layout of a level
+// (lay, m, M set)
+void build_closure_tables(TopoLevel &Lv);
 
 // Dense inverse (row-major n x n) of a symmetric coarsest-level operator
 // given as [n][nb] columns and values (-1: no entry): Cholesky factorisation

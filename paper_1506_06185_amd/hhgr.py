@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -58,6 +59,10 @@ def lib():
         "hhgr_desc_default": (None, [C.POINTER(Desc)]),
         "hhgr_workspace_bytes": (C.c_int, [C.POINTER(Desc), C.POINTER(C.c_size_t)]),
         "hhgr_create": (C.c_int, [C.POINTER(Desc), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+        "hhgr_mesh_workspace_bytes": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp,
+                                                C.POINTER(C.c_size_t)]),
+        "hhgr_create_mesh": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp, _vp, C.c_size_t, _vp,
+                                       C.POINTER(_vp)]),
         "hhgr_destroy": (None, [_vp]),
         "hhgr_sizes": (C.c_int, [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
         "hhgr_set_rhs": (C.c_int, [_vp, _vp, C.c_int]),
@@ -102,7 +107,7 @@ EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_de
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_solve_static",
-            "hhgr_last_error")
+            "hhgr_mesh_workspace_bytes", "hhgr_create_mesh", "hhgr_last_error")
 
 
 def _check(rc: int, allow=()):
@@ -131,6 +136,20 @@ def workspace_bytes(desc: Desc) -> int:
     return int(n.value)
 
 
+def _mesh_arrays(vertices, tets):
+    xyz = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64).reshape(-1, 3))
+    tv = np.ascontiguousarray(np.asarray(tets, dtype=np.int32).reshape(-1, 4))
+    return xyz, tv
+
+
+def mesh_workspace_bytes(desc: Desc, vertices, tets) -> int:
+    xyz, tv = _mesh_arrays(vertices, tets)
+    n = C.c_size_t(0)
+    _check(lib().hhgr_mesh_workspace_bytes(C.byref(desc), len(xyz), xyz.ctypes.data, len(tv), tv.ctypes.data,
+                                           C.byref(n)))
+    return int(n.value)
+
+
 def _ptr(t: torch.Tensor) -> int:
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 device tensor")
@@ -140,16 +159,27 @@ def _ptr(t: torch.Tensor) -> int:
 class Context:
     """One solver context; the workspace is a torch uint8 device tensor it keeps alive."""
 
-    def __init__(self, device=None, stream=None, **desc_kw):
+    def __init__(self, device=None, stream=None, mesh=None, **desc_kw):
+        """mesh = (vertices (nv, 3), tets (nt, 4)): an unstructured macro mesh
+        (hhgr_create_mesh); otherwise the unit cube of make_desc(**desc_kw)."""
         self.desc = make_desc(**desc_kw)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        nbytes = workspace_bytes(self.desc)
+        self.mesh = mesh is not None
+        if mesh is not None:
+            xyz, tv = _mesh_arrays(*mesh)
+            nbytes = mesh_workspace_bytes(self.desc, xyz, tv)
+        else:
+            nbytes = workspace_bytes(self.desc)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         h = _vp()
-        _check(lib().hhgr_create(C.byref(self.desc), self._ws_ptr, nbytes, self.stream.cuda_stream, C.byref(h)))
+        if mesh is not None:
+            _check(lib().hhgr_create_mesh(C.byref(self.desc), len(xyz), xyz.ctypes.data, len(tv), tv.ctypes.data,
+                                          self._ws_ptr, nbytes, self.stream.cuda_stream, C.byref(h)))
+        else:
+            _check(lib().hhgr_create(C.byref(self.desc), self._ws_ptr, nbytes, self.stream.cuda_stream, C.byref(h)))
         self._h = h
         nd, nt, ne = C.c_longlong(), C.c_int(), C.c_longlong()
         _check(lib().hhgr_sizes(self._h, C.byref(nd), C.byref(nt), C.byref(ne)))
@@ -296,7 +326,10 @@ def debug_op(ctx: "Context", op: int, level: int, in0: torch.Tensor, in1: torch.
     """One multigrid operator on one level (see hhgr_debug_op); returns the output vector."""
     n_out_level = level - 1 if op == 4 else level
     N = ctx.desc.n_sub << n_out_level
-    out = torch.empty((N - 1) ** 3, dtype=torch.float64, device=ctx.device)
+    # on a mesh context the level's vector fills the front of a finest-level
+    # sized buffer (the caller knows the level's length)
+    n = ctx.n_dofs if ctx.mesh else (N - 1) ** 3
+    out = torch.zeros(n, dtype=torch.float64, device=ctx.device)
     _check(lib().hhgr_debug_op(ctx.handle, int(op), int(level), _ptr(in0), _ptr(in1) if in1 is not None else None,
                                _ptr(out)))
     return out

@@ -232,6 +232,82 @@ int main() {
         CHECK(hhgr_solve_static(&d, rhs.data(), HHGR_RHS_LOAD, 1e-8, 10, u.data(), &rep, nullptr) == HHGR_EINVAL,
               "static solve with variable k rejected");
     }
+    {
+        // unstructured macro mesh: the octahedron |x|+|y|+|z| <= 1 as 8
+        // tetrahedra around its centre (colours: centre 0, poles 1, equator
+        // vertices 2 and 3 alternately)
+        const double vx[7][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, -1}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}};
+        std::vector<double> xyz;
+        for (auto &p : vx)
+            for (double c : p) xyz.push_back(c + 0.01 * c * c);
+        std::vector<int> tv;
+        for (int pole = 1; pole <= 2; pole++)
+            for (int i = 0; i < 4; i++) {
+                const int a = 3 + i, b = 3 + (i + 1) % 4;
+                tv.insert(tv.end(), {0, pole, i % 2 ? b : a, i % 2 ? a : b});
+            }
+        hhgr_desc d;
+        hhgr_desc_default(&d);
+        d.level = 4;
+        d.n_sub = 99;  // ignored for a mesh
+        size_t bytes = 0;
+        CHECK(hhgr_mesh_workspace_bytes(&d, 7, xyz.data(), 8, tv.data(), &bytes) == HHGR_OK, "mesh workspace: %s",
+              hhgr_last_error());
+        void *ws = std::aligned_alloc(256, (bytes + 255) / 256 * 256);
+        hhgr_ctx *g = nullptr;
+        CHECK(hhgr_create_mesh(&d, 7, xyz.data(), 8, tv.data(), ws, bytes, nullptr, &g) == HHGR_OK, "mesh create: %s",
+              hhgr_last_error());
+        long long nd = 0, ne = 0;
+        int nt = 0;
+        hhgr_sizes(g, &nd, &nt, &ne);
+        // interior nodes at m = 16: the centre, 6 interior edges x 15,
+        // 12 interior faces x 105, 8 x 455 tetrahedron interiors
+        CHECK(nd == 1 + 6 * 15 + 12 * 105 + 8 * 455 && nt == 8 && ne == 8LL * 4096, "mesh sizes %lld %d %lld", nd, nt,
+              ne);
+        std::vector<double> v(nd, 1.0), w(nd, 0.0);
+        double rr = 0;
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_EINVAL, "mesh nodal f rejected");
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "mesh rhs: %s", hhgr_last_error());
+        CHECK(hhgr_set_solution(g, v.data()) == HHGR_OK, "mesh set solution");
+        CHECK(hhgr_get_solution(g, w.data()) == HHGR_OK, "mesh get solution");
+        CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "mesh vcycle: %s", hhgr_last_error());
+        CHECK(hhgr_set_graph(g, 1) == HHGR_OK, "mesh graph on");
+        CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "mesh graph vcycle");
+        CHECK(hhgr_inject_fault(g, 3) == HHGR_OK, "mesh fault");
+        CHECK(hhgr_recover_local(g, 3, 2, &rr) == HHGR_OK, "mesh recover_local: %s", hhgr_last_error());
+        const int t2[2] = {1, 6};
+        CHECK(hhgr_recover_dd(g, t2, 2, 2, 3) == HHGR_EINVAL, "mesh dd rejected");
+        CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_EINVAL, "mesh dn rejected");
+        CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_EINVAL, "mesh mass rejected");
+        CHECK(hhgr_autotune(g, nullptr) == HHGR_EINVAL, "mesh autotune rejected");
+        CHECK(hhgr_set_geometry(g, xyz.data()) == HHGR_EINVAL, "mesh geometry rejected");
+        CHECK(hhgr_debug_op(g, 0, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh residual op");
+        CHECK(hhgr_debug_op(g, 8 + 6, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh class op");
+        CHECK(hhgr_debug_op(g, 4, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh restrict op");
+        CHECK(hhgr_debug_op(g, 5, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh prolong op");
+        CHECK(hhgr_debug_op(g, 7, 2, v.data(), v.data(), w.data()) == HHGR_OK, "mesh dense coarse op");
+        CHECK(hhgr_debug_op(g, 6, 2, v.data(), v.data(), w.data()) == HHGR_EINVAL, "mesh pcg op rejected");
+        hhgr_ctx *pair[2] = {g, cs[1].h};
+        hhgr_batch *gb = nullptr;
+        CHECK(hhgr_batch_create(pair, 2, nullptr, &gb) == HHGR_EINVAL, "mesh batch rejected");
+        hhgr_destroy(g);
+        std::free(ws);
+        d.precision = HHGR_MIXED;
+        CHECK(hhgr_mesh_workspace_bytes(&d, 7, xyz.data(), 8, tv.data(), &bytes) == HHGR_OK, "mixed mesh workspace");
+        ws = std::aligned_alloc(256, (bytes + 255) / 256 * 256);
+        CHECK(hhgr_create_mesh(&d, 7, xyz.data(), 8, tv.data(), ws, bytes, nullptr, &g) == HHGR_OK,
+              "mixed mesh create: %s", hhgr_last_error());
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "mixed mesh rhs");
+        CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "mixed mesh vcycle: %s", hhgr_last_error());
+        hhgr_destroy(g);
+        std::free(ws);
+        d.precision = HHGR_FP64;
+        std::swap(tv[2], tv[3]);  // first tetrahedron's colours inconsistent
+        CHECK(hhgr_mesh_workspace_bytes(&d, 7, xyz.data(), 8, tv.data(), &bytes) == HHGR_EINVAL, "bad colouring");
+        std::swap(tv[2], tv[3]);
+        d.variable_coeff = 1;
+        CHECK(hhgr_mesh_workspace_bytes(&d, 7, xyz.data(), 8, tv.data(), &bytes) == HHGR_EINVAL, "mesh vk rejected");
+    }
     for (auto &c : cs) {
         hhgr_destroy(c.h);
         std::free(c.ws);

@@ -1,0 +1,152 @@
+// Host check of the unstructured-mesh topology (mesh.cpp): builds it from a
+// mesh file and writes, per level, the operator that the tables define
+// (volume stencils and master rows) and the interface rows of the transfers,
+// as (row, column, value) triplets in the user order, for comparison with an
+// independent assembly.  Also checks internal invariants and exits nonzero
+// when one fails.
+//
+// usage: mesh_check <mesh file> <output file>
+// mesh file: "nv nt L Lc", then nv lines "x y z", then nt lines "a b c d"
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "../../paper_1506_06185_amd/csrc/topology.hpp"
+
+using namespace hhgr;
+
+static int fails = 0;
+#define CHECK(c)                                                          \
+    do {                                                                  \
+        if (!(c)) {                                                       \
+            std::fprintf(stderr, "check failed: %s (line %d)\n", #c, __LINE__); \
+            fails++;                                                      \
+        }                                                                 \
+    } while (0)
+
+// rank of interior node (i,j,k) in plane k, row j, i order, by enumeration
+static long long rank_enum(int m, int i0, int j0, int k0) {
+    long long r = 0;
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i + j + k <= m - 1; i++) {
+                if (i == i0 && j == j0 && k == k0) return r;
+                r++;
+            }
+    return -1;
+}
+
+int main(int argc, char **argv) {
+    if (argc != 3) return 2;
+    FILE *f = std::fopen(argv[1], "r");
+    if (!f) return 2;
+    int nv, nt, L, Lc;
+    if (std::fscanf(f, "%d %d %d %d", &nv, &nt, &L, &Lc) != 4) return 2;
+    std::vector<double> xyz(3 * (size_t)nv);
+    std::vector<int> tets(4 * (size_t)nt);
+    for (auto &x : xyz)
+        if (std::fscanf(f, "%lf", &x) != 1) return 2;
+    for (auto &t : tets)
+        if (std::fscanf(f, "%d", &t) != 1) return 2;
+    std::fclose(f);
+    Topology tp;
+    std::string e = tp.build_mesh(nv, xyz.data(), nt, tets.data(), L, Lc);
+    if (!e.empty()) {
+        std::printf("error: %s\n", e.c_str());
+        return 3;
+    }
+    FILE *o = std::fopen(argv[2], "w");
+    std::fprintf(o, "nbw %d n_dofs %lld coarse %d cw %d\n", tp.nbw, tp.n_dofs, tp.coarse.n, tp.coarse.cw);
+    std::vector<std::vector<long long>> user_of(L + 1);
+    for (int l = Lc; l <= L; l++) {
+        const TopoLevel &Lv = tp.lev[l];
+        const int m = Lv.m;
+        // slot -> user index (-1: zero slot or Dirichlet ghost)
+        std::vector<long long> &U = user_of[l];
+        U.assign(Lv.n_slots, -1);
+        for (int t = 0; t < nt; t++)
+            for (int k = 1; k < m; k++)
+                for (int j = 1; j < m; j++)
+                    for (int i = 1; i + j + k <= m - 1; i++)
+                        U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)] = Lv.vbase + (long long)t * Lv.nint +
+                                                                            rank_enum(m, i, j, k);
+        for (int q = 0; q < Lv.n_ifc; q++) U[Lv.ifc_base + q] = Lv.ifc_dof[q];
+        for (size_t q = 0; q < Lv.tg_dst.size(); q++) {
+            CHECK(U[Lv.tg_dst[q]] == -1);
+            U[Lv.tg_dst[q]] = Lv.tg_src[q] == Lv.zero_slot ? -1 : U[Lv.tg_src[q]];
+        }
+        // every user index is taken exactly once
+        const long long nd = Lv.vbase + (long long)nt * Lv.nint;
+        std::vector<int> seen(nd, 0);
+        for (int t = 0; t < nt; t++)
+            for (int k = 1; k < m; k++)
+                for (int j = 1; j < m; j++)
+                    for (int i = 1; i + j + k <= m - 1; i++) seen[U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)]]++;
+        for (int q = 0; q < Lv.n_ifc; q++) seen[Lv.ifc_dof[q]]++;
+        for (long long d = 0; d < nd; d++) CHECK(seen[d] == 1);
+        // ghost lists agree with the per-master CSR
+        long long ng = 0;
+        for (size_t q = 0; q < Lv.tg_dst.size(); q++) ng += Lv.tg_src[q] != Lv.zero_slot;
+        CHECK(ng == (long long)Lv.gidx.size());
+        // classes: no stencil entry joins two nodes of one class
+        std::vector<int> cls(Lv.n_slots, -1);
+        for (int q = 0; q < 4; q++)
+            for (int fq : Lv.ifcq[q]) cls[Lv.ifc_base + fq] = q;
+        std::fprintf(o, "A %d %lld\n", l, nd);
+        for (int t = 0; t < nt; t++)
+            for (int k = 1; k < m; k++)
+                for (int j = 1; j < m; j++)
+                    for (int i = 1; i + j + k <= m - 1; i++) {
+                        const long long r = U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)];
+                        const int c0 = (i + 2 * j + 3 * k) & 3;
+                        for (int n = 0; n < 15; n++) {
+                            const int ii = i + kIdx15[n][0], jj = j + kIdx15[n][1], kk = k + kIdx15[n][2];
+                            const long long s = (long long)t * Lv.C_pad + Lv.lay.index(ii, jj, kk);
+                            const long long c = U[s];
+                            const double v = Lv.mesh_w15[15 * (size_t)t + n];
+                            if (n > 0 && v != 0.0) {
+                                const int cn = s >= Lv.ifc_base ? cls[s] : (ii + 2 * jj + 3 * kk) & 3;
+                                const bool ghost = ii == 0 || jj == 0 || kk == 0 || ii + jj + kk == m;
+                                if (!ghost) CHECK(cn != c0);
+                            }
+                            if (c >= 0) std::fprintf(o, "%lld %lld %.17g\n", r, c, v);
+                        }
+                    }
+        for (int q = 0; q < Lv.n_ifc; q++) {
+            const long long r = Lv.ifc_dof[q];
+            for (int n = 0; n < tp.nbw; n++) {
+                const int s = Lv.nb15[(size_t)n * Lv.n_ifc + q];
+                const double v = Lv.mesh_wi[(size_t)n * Lv.n_ifc + q];
+                if (n == 0) CHECK(s == Lv.ifc_base + q);
+                const long long c = U[s];
+                if (c >= 0) std::fprintf(o, "%lld %lld %.17g\n", r, c, v);
+            }
+        }
+        std::fprintf(o, "end\n");
+    }
+    // interface rows of the transfers: P (fine master <- coarse parents) and
+    // R = P^T (coarse master <- its fine twin and the neighbours at 1/2)
+    for (int l = Lc + 1; l <= L; l++) {
+        const TopoLevel &F = tp.lev[l], &Cl = tp.lev[l - 1];
+        std::fprintf(o, "P %d\n", l);
+        for (int q = 0; q < F.n_ifc; q++) {
+            const int s1 = F.prl[q], s2 = F.prl[(size_t)F.n_ifc + q];
+            const long long c1 = user_of[l - 1][s1], c2 = user_of[l - 1][s2];
+            if (c1 >= 0) std::fprintf(o, "%d %lld 0.5\n", F.ifc_dof[q], c1);
+            if (c2 >= 0) std::fprintf(o, "%d %lld 0.5\n", F.ifc_dof[q], c2);
+        }
+        std::fprintf(o, "end\n");
+        std::fprintf(o, "R %d\n", l);
+        for (int q = 0; q < Cl.n_ifc; q++)
+            for (int n = 0; n < tp.nbw; n++) {
+                const int s = Cl.rst[(size_t)n * Cl.n_ifc + q];
+                const long long c = user_of[l][s];
+                if (c >= 0) std::fprintf(o, "%d %lld %s\n", Cl.ifc_dof[q], c, n == 0 ? "1" : "0.5");
+            }
+        std::fprintf(o, "end\n");
+    }
+    std::fclose(o);
+    if (fails) return 1;
+    std::printf("ok\n");
+    return 0;
+}

@@ -105,6 +105,12 @@ void launch_user_to_slots(hipStream_t, const VolGeom &, const int *, int, int, c
 template <typename T>
 void launch_slots_to_user(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &, const int *, const T *,
                           double *) {}
+template <typename T>
+void launch_mesh_user_to_slots(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &, const int *,
+                               const double *, T *) {}
+template <typename T>
+void launch_mesh_slots_to_user(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &, const int *,
+                               const T *, double *) {}
 void launch_mass(hipStream_t, const VolGeom &, const IfcGeom &, const int *, const double *, double *, double) {}
 void launch_update_add(hipStream_t, const VolDesc *, int, long long, const IfcGeom &, double *, const float *) {}
 template <typename T>
@@ -231,6 +237,10 @@ template void launch_user_to_slots<double>(hipStream_t, const VolGeom &, const i
                                            const int *, const double *, double *);
 template void launch_slots_to_user<double>(hipStream_t, const VolGeom &, const int *, int, int, const IfcGeom &,
                                            const int *, const double *, double *);
+template void launch_mesh_user_to_slots<double>(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &,
+                                                const int *, const double *, double *);
+template void launch_mesh_slots_to_user<double>(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &,
+                                                const int *, const double *, double *);
 template void launch_ghost_refresh<double>(hipStream_t, const int *, const int *, int, double *);
 template void launch_ghost_refresh<float>(hipStream_t, const int *, const int *, int, float *);
 template void launch_cast<double, float>(hipStream_t, const double *, float *, long long);

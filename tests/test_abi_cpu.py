@@ -60,6 +60,7 @@ def test_engine_host_logic_under_asan(tmp_path):
     subprocess.run(["g++", "-std=c++17", "-O0", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
                     "-I" + os.path.join(h, "mock"), "-x", "c++", os.path.join(ROOT, "paper_1506_06185_amd/csrc/engine.hip"),
                     "-x", "none", os.path.join(ROOT, "paper_1506_06185_amd/csrc/topology.cpp"),
+                    os.path.join(ROOT, "paper_1506_06185_amd/csrc/mesh.cpp"),
                     os.path.join(ROOT, "paper_1506_06185_amd/csrc/geometry.cpp"),
                     os.path.join(h, "mock/mock_hip.cpp"), os.path.join(h, "mock/mock_kernels.cpp"),
                     os.path.join(h, "engine_host_check.cpp"), "-o", exe], check=True)

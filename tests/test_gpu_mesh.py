@@ -1,0 +1,195 @@
+"""GPU parity on unstructured macro meshes (Sec. 3.1: arbitrary tetrahedra,
+each refined regularly; eq. (2) with P1 elements in physical coordinates),
+through the C ABI (hhgr_create_mesh) against the oracle's element-by-element
+assembly on the same vertex and tetrahedron lists.
+
+Meshes: the octahedron as 8 tetrahedra around an interior vertex (moved
+vertices), the octahedron as 4 tetrahedra around its axis, and a 2 x 2 x 2
+box of cubes split into 5 tetrahedra each (moved vertices): vertices of
+valence 4 to 18, edges shared by 3 to 6 tetrahedra.  Tolerances as for the
+cube: operators and iterates 1e-12 relative, converged solutions 1e-10."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_06185_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+_PROBLEMS = {}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hh():
+    from paper_1506_06185_amd import hhgr
+
+    hhgr.lib()
+    return hhgr
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev)
+
+
+def Nn(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def mesh(name):
+    if name == "octa8":
+        v, t = inputs.octahedron_mesh(True)
+        return inputs.perturb_mesh(v, seed=3, amplitude=0.08), t
+    if name == "octa4":
+        return inputs.octahedron_mesh(False)
+    if name == "box222p":
+        v, t = inputs.box_mesh(2, 2, 2)
+        return inputs.perturb_mesh(v, seed=5, amplitude=0.12), t
+    raise KeyError(name)
+
+
+def problem(name, level):
+    key = (name, level)
+    if key not in _PROBLEMS:
+        _PROBLEMS[key] = oracle.MeshProblem(*mesh(name), level, 2)
+    return _PROBLEMS[key]
+
+
+def context(hh, dev, name, level, **kw):
+    return hh.Context(device=dev, mesh=mesh(name), level=level, coarse_level=2, **kw)
+
+
+CASES = [("octa8", 4), ("octa4", 5), ("box222p", 4)]
+
+
+@pytest.mark.parametrize("name,level", CASES)
+def test_mesh_operators(dev, hh, name, level):
+    print(f"\n[mesh operators] {name} level={level}", flush=True)
+    ctx = context(hh, dev, name, level)
+    p = problem(name, level)
+    assert ctx.n_dofs == p.ndof and ctx.n_tets == p.n_tets
+    g = np.random.default_rng(700 + level)
+    for l in range(2, level + 1):
+        nd = p.ndof_at(l)
+        u, b = g.standard_normal(nd), g.standard_normal(nd)
+        r = Nn(hh.debug_op(ctx, 0, l, T(u, dev), T(b, dev)))[:nd]
+        assert rel(r, p.residual(u, b, level=l)) < 1e-12, l
+        for mask in (1, 2, 4, 8, 15):
+            us = Nn(hh.debug_op(ctx, 8 + mask, l, T(u, dev), T(b, dev)))[:nd]
+            assert rel(us, p.smooth(u, b, omega=1.25, colours=mask, level=l)) < 1e-12, (l, mask)
+        if l > 2:
+            rc = Nn(hh.debug_op(ctx, 4, l, T(u, dev)))[: p.ndof_at(l - 1)]
+            assert rel(rc, p.restrict(u, level=l)) < 1e-13, l
+            ec = g.standard_normal(p.ndof_at(l - 1))
+            up = Nn(hh.debug_op(ctx, 5, l, T(ec, dev), T(u, dev)))[:nd]
+            assert rel(up, p.prolong_add(ec, u, level=l)) < 1e-13, l
+    # the dense coarsest-level solve against a direct solve of the oracle's matrix
+    import scipy.sparse.linalg as spla
+
+    bc = g.standard_normal(p.ndof_at(2))
+    uc = Nn(hh.debug_op(ctx, 7, 2, T(bc, dev)))[: p.ndof_at(2)]
+    assert rel(uc, spla.spsolve(p.matrix(2, "A").tocsc(), bc)) < 1e-11
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,level", CASES)
+def test_mesh_vcycle_iterates_and_solve(dev, hh, name, level):
+    print(f"\n[mesh cycles] {name} level={level}", flush=True)
+    ctx = context(hh, dev, name, level)
+    p = problem(name, level)
+    b = np.random.default_rng(800 + level).uniform(-1, 1, p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    u = np.zeros(p.ndof)
+    for it in range(5):
+        relres = ctx.vcycle(1)
+        u, rn = p.vcycle(u, b)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+        assert relres == pytest.approx(rn / np.linalg.norm(b), rel=1e-10)
+    ctx.set_solution(None)
+    rep = ctx.solve(rel_tol=1e-10, max_cycles=60)
+    uo, cycles, _ = p.solve(b, rtol=1e-10, max_cycles=60)
+    assert rep.cycles == cycles
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,level", [("octa8", 5), ("box222p", 4)])
+def test_mesh_fault_and_local_recovery(dev, hh, name, level):
+    """A fault after a few cycles, the local recovery of Alg. 1 a) on the
+    faulty tetrahedron, then plain cycles: every iterate against the oracle."""
+    print(f"\n[mesh fault] {name} level={level}", flush=True)
+    ctx = context(hh, dev, name, level)
+    p = problem(name, level)
+    b = np.random.default_rng(900 + level).uniform(-1, 1, p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    u = np.zeros(p.ndof)
+    ctx.vcycle(3)
+    for _ in range(3):
+        u, _ = p.vcycle(u, b)
+    tet = inputs.mesh_fault_tet(p.n_tets, seed=2)
+    ctx.inject_fault(tet)
+    u = p.inject_fault(tet, u)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    lr = ctx.recover_local(tet, 3)
+    u, res = p.recover_local([tet], u, b, 3)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    assert lr == pytest.approx(res[-1], rel=1e-6)
+    for it in range(3):
+        ctx.vcycle(1)
+        u, _ = p.vcycle(u, b)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+    ctx.close()
+
+
+def test_mesh_mixed_precision_and_graphs(dev, hh):
+    """Mixed precision (FP32 cycles, FP64 residuals and corrections) reaches
+    the FP64 solution of the oracle; graph-replayed cycles equal eager ones."""
+    name, level = "box222p", 4
+    print(f"\n[mesh mixed, graphs] {name} level={level}", flush=True)
+    p = problem(name, level)
+    b = np.random.default_rng(42).uniform(-1, 1, p.ndof)
+    uo, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+    ctx = context(hh, dev, name, level, precision="mixed")
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.solve(rel_tol=1e-11, max_cycles=60)
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-9
+    ctx.close()
+    eager = context(hh, dev, name, level)
+    graph = context(hh, dev, name, level)
+    graph.set_graph(True)
+    for c in (eager, graph):
+        c.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    for it in range(4):
+        r0 = eager.vcycle(1)
+        r1 = graph.vcycle(1)
+        assert r0 == r1
+        assert np.array_equal(Nn(eager.get_solution()), Nn(graph.get_solution())), it
+    eager.close()
+    graph.close()
+
+
+def test_mesh_context_rejects_unsupported_calls(dev, hh):
+    ctx = context(hh, dev, "octa8", 4)
+    n = ctx.n_dofs
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    with pytest.raises(hh.HHGRError) as e:
+        ctx.set_rhs(x, hh.HHGR_RHS_NODAL_F)
+    assert e.value.code == hh.HHGR_EINVAL
+    ctx.set_rhs(x + 1.0, hh.HHGR_RHS_LOAD)
+    for call in (lambda: ctx.recover_dd([1], 1, 1), lambda: ctx.recover_dn([1], 1, 1), lambda: ctx.mass_apply(x),
+                 lambda: ctx.autotune()):
+        with pytest.raises(hh.HHGRError) as e:
+            call()
+        assert e.value.code == hh.HHGR_EINVAL
+    ctx.close()
