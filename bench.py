@@ -33,6 +33,9 @@ Further legs, each in its own object of the JSON line:
             vertices moved (inputs.perturbed_vertices, seed 0), 15-point
             stencils, 4-colour SOR, load b ~ U[-1,1], in FP64 and in mixed
             precision; its roofline is the finest-level FP64 class pass.
+  unstructured_mesh  the same job on an unstructured macro mesh from vertex
+            and tetrahedron lists (a 3x3x3 box of cubes split into 5
+            tetrahedra each, moved vertices, level 7), FP64 and mixed.
 """
 from __future__ import annotations
 
@@ -315,6 +318,94 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph, tune_cache):
     }
 
 
+def leg_mesh(hh, torch, dev, steps, warmup, graph, nx=3, level=7):
+    """The fault job on an unstructured macro mesh: the box [0, nx]^3 of unit
+    cubes split into 5 tetrahedra each (vertices moved by 0.12 U[-1,1]^3,
+    seed 0), per-master stencils, 4-colour SOR, load b ~ U[-1,1]: 5 cycles,
+    a fault, 3 local recovery cycles, solve to 1e-8, in FP64 and in mixed
+    precision; value = unknowns x cycles / time."""
+    from paper_1506_06185_amd import inputs
+
+    v, t = inputs.box_mesh(nx, nx, nx)
+    v = inputs.perturb_mesh(v, seed=0, amplitude=0.12)
+    out = {"workload": f"unstructured macro mesh: box {nx}x{nx}x{nx} of cubes split into 5 tetrahedra each "
+                       f"({len(t)} macro tets, vertices moved by 0.12 U[-1,1]^3, seed 0), level {level}, load "
+                       f"b ~ U[-1,1]; fault after 5 cycles, 3 local recovery cycles, solve to 1e-8"}
+    u64 = None
+    for precision in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        ctx = hh.Context(device=dev, mesh=(v, t), level=level, precision=precision)
+        t_setup = time.perf_counter() - t0
+        if graph:
+            ctx.set_graph(True)
+        g = torch.Generator().manual_seed(0)
+        b = (2.0 * torch.rand(ctx.n_dofs, generator=g, dtype=torch.float64) - 1.0).to(dev)
+        t_fault = inputs.mesh_fault_tet(ctx.n_tets, seed=0)
+
+        def job():
+            ctx.set_rhs(b)
+            ctx.set_solution(None)
+            ctx.vcycle(5)
+            ctx.inject_fault(t_fault)
+            ctx.recover_local(t_fault, 3)
+            cyc, rel, _ = ctx.solve(1e-8, 80)
+            return 5 + cyc, rel
+
+        ctx.set_rhs(b)
+        k_free, _, hist = ctx.solve(1e-8, 80)
+        for _ in range(warmup):
+            job()
+        timing = precision == "fp64" and not graph
+        if timing:
+            ctx.kernel_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot, rel = 0, None
+        for _ in range(steps):
+            cyc, rel = job()
+            tot += cyc
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        leg = {
+            "value": round(ctx.n_dofs * tot / dt / 1e6, 1),
+            "unit": "MDoF/s",
+            "ms_per_step": round(1e3 * dt / steps, 3),
+            "unknowns": ctx.n_dofs,
+            "cycles_per_job": tot // steps,
+            "k_free": k_free,
+            "fault_free_rate": round(hist[-1] / hist[-2], 3) if len(hist) > 1 else None,
+            "final_rel_res": rel,
+            "fault_tet": t_fault,
+            "setup_s": round(t_setup, 2),
+        }
+        if timing:
+            launches, mean_ms, alg_bytes = ctx.kernel_stats()
+            ctx.kernel_timing(False)
+            if launches > 0:
+                achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
+                leg["roofline"] = {
+                    "bound": "hbm",
+                    "kernel": "k_colour15 (finest-level class pass of the 4-colour SOR on the mesh, FP64)",
+                    "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "launches": launches,
+                    "mean_launch_ms": round(mean_ms, 5),
+                    "algorithmic_bytes_per_launch": alg_bytes,
+                    "count": "12 B per unknown per class pass (u of the other classes, b and u of its own)",
+                }
+        if precision == "fp64":
+            u64 = ctx.get_solution()
+            out.update(leg)
+        else:
+            leg["rel_diff_vs_fp64_job"] = float(torch.linalg.norm(ctx.get_solution() - u64) / torch.linalg.norm(u64))
+            out["mixed"] = leg
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def leg_mixed_l8(hh, torch, dev, tune_cache, n_sub=2, level=8):
     """Mixed-precision refinement on 133 M unknowns against the FP64 solve."""
     from paper_1506_06185_amd import inputs
@@ -464,6 +555,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the level-8, gradient and batched legs")
     ap.add_argument("--no-general", action="store_true", help="skip the general-macro-mesh leg")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the unstructured-macro-mesh leg")
+    ap.add_argument("--fused-sweeps", choices=("auto", "on", "off"), default="auto",
+                    help="finest-level smoother of the headline job: fused red-black sweep pairs or two colour "
+                         "passes per sweep (default: the autotuner's choice)")
     ap.add_argument("--graph", action="store_true", help="replay captured graphs (disables kernel timing)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file, read before and written after tuning and kept (default: a "
@@ -499,6 +594,8 @@ def main():
     log(f"setup n_sub={n_sub} level={level}")
     ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
     ctx.autotune(tune_cache)
+    if args.fused_sweeps != "auto":
+        ctx.set_fused_sweeps(level, args.fused_sweeps == "on")
     tuning = ctx.tuning_info()
     log(f"tuning (level: block size, xcd order, nodes per thread) {tuning}")
     if args.graph:
@@ -573,6 +670,12 @@ def main():
     if not args.no_general:
         log("general macro mesh leg")
         general = leg_general(hh, torch, dev, n_sub, level, args.steps, args.warmup, args.graph, tune_cache)
+    mesh = None
+    if not args.no_mesh:
+        log("unstructured macro mesh leg")
+        t1 = time.perf_counter()
+        mesh = leg_mesh(hh, torch, dev, args.steps, args.warmup, args.graph)
+        log(f"unstructured macro mesh leg done in {time.perf_counter() - t1:.1f} s")
     extra = {}
     if not args.no_extra:
         for name, fn in (("mixed_l8", lambda: leg_mixed_l8(hh, torch, dev, tune_cache)),
@@ -614,6 +717,7 @@ def main():
             "smoother": "red-black SOR omega=1.25, V(2,1), coarse level 2 solved with its dense inverse",
             "fault_tet": t_fault,
             "graph": bool(args.graph),
+            "fused_sweeps": args.fused_sweeps,
             "tuning": {str(k): {"block": v[0], "xcd_order": v[1], "nodes_per_thread": v[2]}
                        for k, v in tuning.items()},
         },
@@ -625,6 +729,7 @@ def main():
         "roofline": roofline,
         "mixed": mixed,
         "general_mesh": general,
+        "unstructured_mesh": mesh,
         **extra,
         "cpu_baseline": cpu,
     }

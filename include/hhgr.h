@@ -308,6 +308,17 @@ int hhgr_autotune(hhgr_ctx *ctx, const char *cache_path);
  * coarse_level+1..level. */
 int hhgr_tuning_info(const hhgr_ctx *ctx, int level, int *block_size, int *xcd_order, int *nodes_per_thread);
 
+/* Fused red-black sweeps (cube, k = 1; Sec. 2.1 smoother): on level
+ * `level` (coarse_level < level <= level of the context), on = 1 runs every
+ * two consecutive sweeps of an unmasked cycle as a pair of single-launch
+ * sweeps (red and black of each plane in one kernel, planes marched through
+ * LDS), on = 0 as two colour passes per sweep.  The iterates are the same
+ * bit for bit.  hhgr_autotune sets it where the pair is faster; this call
+ * overrides that (e.g. to time the kernel).  EINVAL where the fused kernel
+ * cannot take the level (general or unstructured meshes, variable k, levels
+ * with fewer than 8 segments per edge). */
+int hhgr_set_fused_sweeps(hhgr_ctx *ctx, int level, int on);
+
 /* Set the tuning choices of one level (level = 0: every level above the
  * coarsest) instead of the autotuner's: block_size 128, 256 or 512,
  * xcd_order 0 or 1, nodes_per_thread 1 or 4.  Results do not depend on them.

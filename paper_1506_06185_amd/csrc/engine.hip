@@ -2207,6 +2207,16 @@ int hhgr_tuning_info(const hhgr_ctx *c, int level, int *block_size, int *xcd_ord
     return HHGR_OK;
 }
 
+int hhgr_set_fused_sweeps(hhgr_ctx *c, int level, int on) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (level <= c->Lc || level > c->L) return fail(HHGR_EINVAL, "level outside coarse_level+1..level");
+    LevelDev &D = c->lev[level];
+    if (on && !D.fz_ps) return fail(HHGR_EINVAL, "no fused sweeps on this level of this context");
+    D.fz_on = on != 0;
+    invalidate_graph(*c);
+    return HHGR_OK;
+}
+
 int hhgr_set_tuning(hhgr_ctx *c, int level, int block_size, int xcd_order, int nodes_per_thread) {
     if (!c) return fail(HHGR_EINVAL, "null context");
     if (level != 0 && (level <= c->Lc || level > c->L)) return fail(HHGR_EINVAL, "level outside coarse_level+1..level");

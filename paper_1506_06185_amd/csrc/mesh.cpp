@@ -316,13 +316,21 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         Lv.n_slots = round_up(Lv.zero_slot + 1, 64);
         if (Lv.n_slots >= (1LL << 31)) return "level too large for 32-bit slot indices";
         if (Lv.vbase + (long long)nt * Lv.nint >= (1LL << 31)) return "too many unknowns for 32-bit user indices";
-        // slot of closure node (i, j, k) of tetrahedron t
+        // slot of closure node (i, j, k) of tetrahedron t (a closure
+        // boundary node: its master's slot, or the zero slot)
         auto slot = [&](int t, int i, int j, int k) -> long long {
             if (i > 0 && j > 0 && k > 0 && i + j + k < m) return (long long)t * Lv.C_pad + Lv.lay.index(i, j, k);
             const int lam[4] = {m - i - j - k, i, j, k};
             const Support s = support_of(tv[t], lam);
             auto it = km.find(key_of(s));
             return it == km.end() ? Lv.zero_slot : Lv.ifc_base + it->second;
+        };
+        // the same for every node of one closure, looked up once per node
+        std::vector<int> cslot(Lv.C_pad);
+        auto fill_cslot = [&](int t) {
+            for (int k = 0; k <= m; k++)
+                for (int j = 0; j <= m - k; j++)
+                    for (int i = 0; i <= m - k - j; i++) cslot[Lv.lay.index(i, j, k)] = (int)slot(t, i, j, k);
         };
         // ghost copies
         Lv.nbr.assign(6 * (size_t)Lv.n_ifc, (int)Lv.zero_slot);
@@ -381,11 +389,12 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                     Lv.mesh_w15[15 * (size_t)t + n] += K[q][A.self][r];
                 }
             }
+            fill_cslot(t);
             for (int k = 0; k <= m; k++)
                 for (int j = 0; j <= m - k; j++)
                     for (int i = 0; i <= m - k - j; i++) {
                         if (!(i == 0 || j == 0 || k == 0 || i + j + k == m)) continue;
-                        const long long own = slot(t, i, j, k);
+                        const long long own = cslot[Lv.lay.index(i, j, k)];
                         if (own == Lv.zero_slot) continue;
                         auto &row = R[own - Lv.ifc_base];
                         if (row.empty()) row.push_back({(int)own, 0.0});
@@ -401,7 +410,7 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             }
                             if (!in) continue;
                             for (int r = 0; r < 4; r++) {
-                                const int s = (int)slot(t, p[r][0], p[r][1], p[r][2]);
+                                const int s = cslot[Lv.lay.index(p[r][0], p[r][1], p[r][2])];
                                 size_t e = 0;
                                 while (e < row.size() && row[e].first != s) e++;
                                 if (e == row.size()) row.push_back({s, 0.0});

@@ -61,6 +61,7 @@ def lib():
         "hhgr_create": (C.c_int, [C.POINTER(Desc), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
         "hhgr_mesh_workspace_bytes": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp,
                                                 C.POINTER(C.c_size_t)]),
+        "hhgr_set_fused_sweeps": (C.c_int, [_vp, C.c_int, C.c_int]),
         "hhgr_create_mesh": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp, _vp, C.c_size_t, _vp,
                                        C.POINTER(_vp)]),
         "hhgr_destroy": (None, [_vp]),
@@ -107,7 +108,7 @@ EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_de
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_solve_static",
-            "hhgr_mesh_workspace_bytes", "hhgr_create_mesh", "hhgr_last_error")
+            "hhgr_mesh_workspace_bytes", "hhgr_create_mesh", "hhgr_set_fused_sweeps", "hhgr_last_error")
 
 
 def _check(rc: int, allow=()):
@@ -295,6 +296,9 @@ class Context:
 
     def set_graph(self, on: bool = True):
         _check(lib().hhgr_set_graph(self._h, int(bool(on))))
+
+    def set_fused_sweeps(self, level: int, on: bool = True):
+        _check(lib().hhgr_set_fused_sweeps(self._h, int(level), int(bool(on))))
 
     def set_tuning(self, block_size: int = 256, xcd_order: int = 1, nodes_per_thread: int = 1, level: int = 0):
         """Fix the volume-kernel launch shape (level 0 = every level above the coarsest)."""

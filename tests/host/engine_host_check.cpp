@@ -280,6 +280,11 @@ int main() {
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_EINVAL, "mesh dn rejected");
         CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_EINVAL, "mesh mass rejected");
         CHECK(hhgr_autotune(g, nullptr) == HHGR_EINVAL, "mesh autotune rejected");
+        CHECK(hhgr_set_fused_sweeps(g, 4, 1) == HHGR_EINVAL, "mesh fused sweeps rejected");
+        CHECK(hhgr_set_fused_sweeps(cs[0].h, 5, 1) == HHGR_OK, "cube fused sweeps: %s", hhgr_last_error());
+        CHECK(hhgr_vcycle(cs[0].h, 1, &rr) == HHGR_OK, "cube fused vcycle");
+        CHECK(hhgr_set_fused_sweeps(cs[0].h, 5, 0) == HHGR_OK, "cube fused sweeps off");
+        CHECK(hhgr_set_fused_sweeps(cs[0].h, 2, 1) == HHGR_EINVAL, "fused sweeps on the coarsest level rejected");
         CHECK(hhgr_set_geometry(g, xyz.data()) == HHGR_EINVAL, "mesh geometry rejected");
         CHECK(hhgr_debug_op(g, 0, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh residual op");
         CHECK(hhgr_debug_op(g, 8 + 6, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh class op");

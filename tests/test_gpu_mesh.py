@@ -117,9 +117,9 @@ def test_mesh_vcycle_iterates_and_solve(dev, hh, name, level):
         assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
         assert relres == pytest.approx(rn / np.linalg.norm(b), rel=1e-10)
     ctx.set_solution(None)
-    rep = ctx.solve(rel_tol=1e-10, max_cycles=60)
+    gpu_cycles, _, _ = ctx.solve(rel_tol=1e-10, max_cycles=60)
     uo, cycles, _ = p.solve(b, rtol=1e-10, max_cycles=60)
-    assert rep.cycles == cycles
+    assert gpu_cycles == cycles
     assert rel(Nn(ctx.get_solution()), uo) < 1e-10
     ctx.close()
 
@@ -192,4 +192,32 @@ def test_mesh_context_rejects_unsupported_calls(dev, hh):
         with pytest.raises(hh.HHGRError) as e:
             call()
         assert e.value.code == hh.HHGR_EINVAL
+    ctx.close()
+
+
+def test_mesh_fault_job_box333_level5(dev, hh):
+    """The bench's mesh workload (135 tetrahedra of the 3 x 3 x 3 box split,
+    moved vertices, seed 0) at level 5, 710,063 unknowns: 5 cycles, a fault,
+    3 local recovery cycles and the solve to 1e-8, against the oracle's job
+    (same cycle count, solution to 1e-10)."""
+    v, t = inputs.box_mesh(3, 3, 3)
+    v = inputs.perturb_mesh(v, seed=0, amplitude=0.12)
+    level = 5
+    print(f"\n[mesh job] box333 level={level}", flush=True)
+    p = oracle.MeshProblem(v, t, level, 2)
+    ctx = hh.Context(device=dev, mesh=(v, t), level=level)
+    assert ctx.n_dofs == p.ndof == 710063
+    b = np.random.default_rng(17).uniform(-1, 1, p.ndof)
+    tet = inputs.mesh_fault_tet(len(t), seed=0)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.vcycle(5)
+    ctx.inject_fault(tet)
+    ctx.recover_local(tet, 3)
+    cyc, _, _ = ctx.solve(1e-8, 80)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=5)
+    u = p.inject_fault(tet, u)
+    u, _ = p.recover_local([tet], u, b, 3)
+    uo, cyc_o, _ = p.solve(b, u0=u, rtol=1e-8, max_cycles=80, r0=np.linalg.norm(b))
+    assert cyc == cyc_o
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-10
     ctx.close()
