@@ -154,7 +154,9 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * ignored; variable_coeff must be 0.  The coarsest level is solved with a
  * dense inverse (at most 2048 unknowns).  A mesh context takes hhgr_set_rhs
  * with HHGR_RHS_LOAD, hhgr_set_solution/get_solution, hhgr_vcycle,
- * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_set_graph,
+ * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_recover_dd (its
+ * masked coarsest level with a dense inverse of the unfrozen unknowns,
+ * computed on the host for each fault set), hhgr_set_graph,
  * hhgr_kernel_timing/stats and hhgr_debug_op (ops 0, 3 to 5, 7, 8 + class
  * mask); every other call returns EINVAL for it.  hhgr_sizes reports the
  * interior unknowns, nt and nt 8^level.  EINVAL for a mesh that is not

@@ -196,6 +196,10 @@ struct hhgr_ctx {
     // general mesh); the other operators use PCG
     bool dense_coarse = false;
     double *cinv = nullptr;
+    // unstructured macro meshes: dense inverse of the coarsest operator with
+    // the unknowns frozen by a Dirichlet-Dirichlet recovery left out (their
+    // rows and columns zero), set by dd_setup
+    double *cinv_dd = nullptr;
     // general macro meshes: 15-point coarsest-level operator
     bool gen = false, geom_set = false;
     bool mesh = false;  // unstructured macro mesh (hhgr_create_mesh): gen, operator fixed at creation
@@ -490,6 +494,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.dn_faulty = cv.take<unsigned char>(c.n_tets);
     c.citers = cv.take<int>(4);
     if (!c.vk && c.cn <= (c.mesh ? kDenseCoarseMaxMesh : kDenseCoarseMax)) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
+    if (c.mesh && c.d.max_faults > 0) c.cinv_dd = cv.take<double>((size_t)c.cn * c.cn);
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
@@ -956,6 +961,12 @@ void coarse_solve(hhgr_ctx &c, const HView<T> &V, hipStream_t s) {
             launch_coarse_dense<T>(s, c.cn, c.cslot, c.cinv, v.b, v.u, c.cptr, c.cidx);
             return;
         }
+        if (c.mesh && V.cfrozen && !V.cval) {
+            // frozen unknowns: zero rows of the masked inverse (coarse levels
+            // hold corrections, zero at the frozen nodes)
+            launch_coarse_dense<T>(s, c.cn, c.cslot, c.cinv_dd, v.b, v.u, c.cptr, c.cidx);
+            return;
+        }
         launch_coarse_pcg15<T>(s, c.cn, c.cslot, c.ccol15, V.cval ? V.cval : c.cval15, V.cfrozen, v.b, v.u, c.cptr,
                                c.cidx, kCoarseRtol, kCoarseMaxit, c.citers);
         return;
@@ -1201,7 +1212,6 @@ int upload(hhgr_ctx &c, void *dst, const void *src, size_t bytes) {
 // the faulty tetrahedra run local cycles; the two share no unknowns
 // ----------------------------------------------------------------------------
 int dd_check(const hhgr_ctx &c, const int *tets, int n_tets, int n_intact, int n_local, std::vector<int> &ft) {
-    if (c.mesh) return fail(HHGR_EINVAL, "Dirichlet-Dirichlet and Dirichlet-Neumann recoveries are not built for unstructured macro meshes");
     if (!tets || n_tets < 1 || n_tets > c.d.max_faults) return fail(HHGR_EINVAL, "need 1..max_faults tets");
     if (n_intact < 0 || n_local < 0) return fail(HHGR_EINVAL, "negative cycle count");
     if (c.Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
@@ -1243,6 +1253,35 @@ int dd_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     std::vector<unsigned char> cf(cs.n, 0);
     for (int q = 0; q < cs.n; q++) cf[q] = cs.is_vol[q] ? (unsigned char)isf[cs.tet[q]] : frz[c.Lc][cs.ifc[q]];
     rc = rc ? rc : upload(c, c.cfrozen, cf.data(), cf.size());
+    std::vector<double> inv_full;
+    if (c.mesh) {
+        // the coarsest operator on the unfrozen unknowns, inverted densely
+        std::vector<int> keep(cs.n, -1);
+        int nk = 0;
+        for (int q = 0; q < cs.n; q++)
+            if (!cf[q]) keep[q] = nk++;
+        std::vector<int> colk((size_t)nk * cs.cw, -1);
+        std::vector<double> valk((size_t)nk * cs.cw, 0.0);
+        for (int q = 0; q < cs.n; q++) {
+            if (keep[q] < 0) continue;
+            for (int e = 0; e < cs.cw; e++) {
+                const int cq = cs.colw[(size_t)cs.cw * q + e];
+                if (cq < 0 || keep[cq] < 0) continue;
+                colk[(size_t)cs.cw * keep[q] + e] = keep[cq];
+                valk[(size_t)cs.cw * keep[q] + e] = cs.valw[(size_t)cs.cw * q + e];
+            }
+        }
+        std::vector<double> inv;
+        if (nk > 0 && !coarse_inverse(nk, cs.cw, colk, valk, inv)) {
+            HIPCHK(hipStreamSynchronize(c.stream));
+            return fail(HHGR_EINVAL, "the masked coarsest-level operator is not positive definite");
+        }
+        inv_full.assign((size_t)cs.n * cs.n, 0.0);
+        for (int q = 0; q < cs.n; q++)
+            for (int r = 0; r < cs.n; r++)
+                if (keep[q] >= 0 && keep[r] >= 0) inv_full[(size_t)q * cs.n + r] = inv[(size_t)keep[q] * nk + keep[r]];
+        rc = rc ? rc : upload(c, c.cinv_dd, inv_full.data(), inv_full.size() * sizeof(double));
+    }
     // copies already queued read the host vectors above: wait before any return
     HIPCHK(hipStreamSynchronize(c.stream));
     if (rc) return rc;
@@ -2083,6 +2122,7 @@ int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int eta) {
     int rc = check_ready(c);
     if (rc) return rc;
+    if (c->mesh) return fail(HHGR_EINVAL, "no Dirichlet-Neumann recovery on an unstructured macro mesh");
     std::vector<int> ft;
     rc = dd_check(*c, tets, n_tets, n_intact, eta, ft);
     if (rc) return rc;

@@ -276,7 +276,8 @@ int main() {
         CHECK(hhgr_inject_fault(g, 3) == HHGR_OK, "mesh fault");
         CHECK(hhgr_recover_local(g, 3, 2, &rr) == HHGR_OK, "mesh recover_local: %s", hhgr_last_error());
         const int t2[2] = {1, 6};
-        CHECK(hhgr_recover_dd(g, t2, 2, 2, 3) == HHGR_EINVAL, "mesh dd rejected");
+        CHECK(hhgr_recover_dd(g, t2, 2, 2, 3) == HHGR_OK, "mesh dd: %s", hhgr_last_error());
+        CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_OK, "mesh vcycle after dd");
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_EINVAL, "mesh dn rejected");
         CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_EINVAL, "mesh mass rejected");
         CHECK(hhgr_autotune(g, nullptr) == HHGR_EINVAL, "mesh autotune rejected");
@@ -304,6 +305,7 @@ int main() {
               "mixed mesh create: %s", hhgr_last_error());
         CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "mixed mesh rhs");
         CHECK(hhgr_vcycle(g, 2, &rr) == HHGR_OK, "mixed mesh vcycle: %s", hhgr_last_error());
+        CHECK(hhgr_recover_dd(g, t2, 2, 1, 2) == HHGR_OK, "mixed mesh dd: %s", hhgr_last_error());
         hhgr_destroy(g);
         std::free(ws);
         d.precision = HHGR_FP64;

@@ -187,8 +187,8 @@ def test_mesh_context_rejects_unsupported_calls(dev, hh):
         ctx.set_rhs(x, hh.HHGR_RHS_NODAL_F)
     assert e.value.code == hh.HHGR_EINVAL
     ctx.set_rhs(x + 1.0, hh.HHGR_RHS_LOAD)
-    for call in (lambda: ctx.recover_dd([1], 1, 1), lambda: ctx.recover_dn([1], 1, 1), lambda: ctx.mass_apply(x),
-                 lambda: ctx.autotune()):
+    for call in (lambda: ctx.recover_dn([1], 1, 1), lambda: ctx.mass_apply(x), lambda: ctx.autotune(),
+                 lambda: ctx.set_fused_sweeps(4, True)):
         with pytest.raises(hh.HHGRError) as e:
             call()
         assert e.value.code == hh.HHGR_EINVAL
@@ -220,4 +220,44 @@ def test_mesh_fault_job_box333_level5(dev, hh):
     uo, cyc_o, _ = p.solve(b, u0=u, rtol=1e-8, max_cycles=80, r0=np.linalg.norm(b))
     assert cyc == cyc_o
     assert rel(Nn(ctx.get_solution()), uo) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mesh_dirichlet_dirichlet_recovery(dev, hh, precision):
+    """Alg. 1 b) on an unstructured mesh: two faulty tetrahedra, intact
+    cycles with their closures frozen (the masked coarsest level through its
+    own dense inverse) beside local cycles, then plain cycles; against the
+    oracle's Dirichlet-Dirichlet cycles and local recovery, per iterate
+    (FP64) or to FP32 rounding of the corrections (mixed)."""
+    name, level = "box222p", 4
+    print(f"\n[mesh dd] {name} level={level} {precision}", flush=True)
+    p = problem(name, level)
+    ctx = context(hh, dev, name, level, precision=precision)
+    b = np.random.default_rng(31).uniform(-1, 1, p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    tets = [inputs.mesh_fault_tet(p.n_tets, seed=4), inputs.mesh_fault_tet(p.n_tets, seed=5)]
+    assert tets[0] != tets[1]
+    if precision == "fp64":
+        ctx.vcycle(3)
+        u, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    else:
+        ctx.solve(rel_tol=1e-3, max_cycles=10, raise_on_noconv=False)
+        u = Nn(ctx.get_solution())
+    for t in tets:
+        ctx.inject_fault(t)
+        u = p.inject_fault(t, u)
+    ctx.recover_dd(tets, 2, 4)
+    if precision == "fp64":
+        u = p.dd_intact(tets, u, b, 2)
+        u, _ = p.recover_local(tets, u, b, 4)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12
+        ctx.vcycle(2)
+        u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=2)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    else:
+        # the mixed steps refine in FP64: the job still reaches the oracle's solution
+        ctx.solve(rel_tol=1e-11, max_cycles=60)
+        uo, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+        assert rel(Nn(ctx.get_solution()), uo) < 1e-9
     ctx.close()
