@@ -153,7 +153,9 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * omega, precision and max_faults as above; n_sub and general_geometry are
  * ignored; variable_coeff must be 0.  The coarsest level is solved with a
  * dense inverse (at most 2048 unknowns).  A mesh context takes hhgr_set_rhs
- * with HHGR_RHS_LOAD, hhgr_set_solution/get_solution, hhgr_vcycle,
+ * with HHGR_RHS_LOAD or HHGR_RHS_NODAL_F (b = M f with the consistent P1 mass
+ * matrix of the finest level, per-master rows like the stiffness),
+ * hhgr_mass_apply, hhgr_adjoint_grad (dJ/df only), hhgr_set_solution/get_solution, hhgr_vcycle,
  * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_recover_dd (its
  * masked coarsest level with a dense inverse of the unfrozen unknowns,
  * computed on the host for each fault set), hhgr_set_graph,

@@ -122,6 +122,7 @@ struct LevelDev {
     double *wv = nullptr, *wi15 = nullptr;
     double *wi15_dn = nullptr;  // intact-side master entries of a Dirichlet-Neumann recovery
     double *mw15 = nullptr, *mwtab = nullptr;  // finest level: mass stencils (indexed like w15, wtab)
+    double *mwi = nullptr;                     // ... the masters' own mass rows (unstructured meshes)
     float *w15f = nullptr, *wtabf = nullptr, *wvf = nullptr, *wi15f = nullptr;  // FP32 copies (mixed precision)
     // fused red-black sweeps (cube, k = 1, unmasked cycles): a second slot
     // vector of u in the cycle's precision (the pair of sweeps goes u -> ualt
@@ -390,9 +391,14 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.wtab = cv.take<double>(15 * (size_t)D.wtab_cap);
             D.sid = cv.take<int>(T.n_ifc);
             if (c.mesh) {
-                // masters carry their own stencils (no mass matrix, no
-                // Dirichlet-Neumann recovery on a mesh)
+                // masters carry their own stencils (and, on the finest
+                // level, their own mass-matrix rows; no Dirichlet-Neumann
+                // recovery on a mesh)
                 D.wi15 = cv.take<double>(W * T.n_ifc);
+                if (l == c.L) {
+                    D.mw15 = cv.take<double>(15 * (size_t)c.n_tets);
+                    D.mwi = cv.take<double>(W * T.n_ifc);
+                }
                 if (c.mixed) {
                     D.w15f = cv.take<float>(15 * (size_t)c.n_tets);
                     D.wi15f = cv.take<float>(W * T.n_ifc);
@@ -665,6 +671,7 @@ Gen15 gen15mass(const LevelDev &D) {
     g.sid = D.sid;
     g.wtab = D.mwtab;
     g.nb15 = D.nb15;
+    g.wi15 = D.mwi;  // unstructured meshes: per-master rows
     return g;
 }
 
@@ -1647,6 +1654,10 @@ int create_ctx(const hhgr_desc *desc, std::shared_ptr<const Topology> mesh_topo,
                 // the operator of a mesh comes with its topology
                 rc = rc ? rc : upload(*c, D.w15, T.mesh_w15.data(), T.mesh_w15.size() * sizeof(double));
                 rc = rc ? rc : upload(*c, D.wi15, T.mesh_wi.data(), T.mesh_wi.size() * sizeof(double));
+                if (D.mwi) {
+                    rc = rc ? rc : upload(*c, D.mw15, T.mesh_mw15.data(), T.mesh_mw15.size() * sizeof(double));
+                    rc = rc ? rc : upload(*c, D.mwi, T.mesh_mwi.data(), T.mesh_mwi.size() * sizeof(double));
+                }
                 launch_fill<double>(c->stream, D.wtab, 15LL * D.wtab_cap, 0.0);
                 launch_fill<unsigned int>(c->stream, reinterpret_cast<unsigned int *>(D.sid), T.n_ifc, 0u);
                 if (c->mixed) {
@@ -1838,8 +1849,8 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     bool aux_used = false;  // aux_u held the load in vector order
-    if (c->mesh && kind != HHGR_RHS_LOAD)
-        return fail(HHGR_EINVAL, "an unstructured macro mesh takes a load vector (HHGR_RHS_LOAD) only");
+    if (c->mesh && kind == HHGR_RHS_DIRICHLET)
+        return fail(HHGR_EINVAL, "no Dirichlet data on an unstructured macro mesh (u = 0 on its boundary)");
     if (kind == HHGR_RHS_LOAD) {
         to_slots(*c, D, dev_vec, D.b, c->stream);
     } else if (kind == HHGR_RHS_DIRICHLET && c->gen) {
@@ -1851,7 +1862,7 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
         launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, c->aux_u, D.b);
         aux_used = true;
     } else if (c->gen) {
-        launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_vec, D.r);
+        to_slots(*c, D, dev_vec, D.r, c->stream);
         launch_apply15(c->stream, vint, ig, gen15mass(D), D.r, D.b);
     } else {
         // b = M f on the grid in vector order (through aux_u), then into the slots
@@ -2150,18 +2161,15 @@ int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 
 int hhgr_mass_apply(hhgr_ctx *c, const double *dev_x, double *dev_y) {
     if (!c || !dev_x || !dev_y) return fail(HHGR_EINVAL, "null argument");
-    if (c->mesh) return fail(HHGR_EINVAL, "no mass matrix on an unstructured macro mesh");
     if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     LevelDev &D = c->lev[c->L];
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
-    launch_user_to_slots<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, true), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
-                                 dev_x, c->aux_b);
+    to_slots(*c, D, dev_x, c->aux_b, c->stream);
     if (c->gen)
         launch_apply15(c->stream, vgeom(D, D.vd_all, c->n_tets, false), ig, gen15mass(D), c->aux_b, c->aux_u);
     else
         launch_mass(c->stream, vgeom(D, D.vd_all, c->n_tets, false), ig, D.nb15, c->aux_b, c->aux_u, D.h);
-    launch_slots_to_user<double>(c->stream, vgeom(D, D.vd_all, c->n_tets, false), c->tetinfo, D.m, D.N, ig, D.ifc_dof,
-                                 c->aux_u, dev_y);
+    to_user(*c, D, c->aux_u, dev_y, c->stream);
     CHKLAUNCH();
     return HHGR_OK;
 }
@@ -2170,7 +2178,6 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
                       double *dev_dJdk) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (c->mesh) return fail(HHGR_EINVAL, "no adjoint on an unstructured macro mesh");
     if (!dev_g) return fail(HHGR_EINVAL, "null g");
     if (dev_dJdk && !c->vk) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
     LevelDev &D = c->lev[c->L];
@@ -2182,7 +2189,7 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
     HIPCHK(hipMemcpyAsync(c->aux_b, D.b, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (dev_dJdk)
         launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_u);
-    launch_user_to_slots<double>(c->stream, vfull, c->tetinfo, D.m, D.N, ig, D.ifc_dof, dev_g, D.b);
+    to_slots(*c, D, dev_g, D.b, c->stream);
     launch_fill<double>(c->stream, D.u, ns, 0.0);
     const double bnorm_saved = c->bnorm;
     const bool mixed_saved = c->mixed;
@@ -2208,7 +2215,7 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
                 launch_apply15(c->stream, vint, ig, gen15mass(D), D.u, D.r);
             else
                 launch_mass(c->stream, vint, ig, D.nb15, D.u, D.r, D.h);
-            launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.r, dev_dJdf);
+            to_user(*c, D, D.r, dev_dJdf, c->stream);
         }
         if (dev_dJdk) {
             launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_l);

@@ -652,7 +652,8 @@ __global__ void __launch_bounds__(512) k_residual15(VolGeom vg, IfcGeom ig, Gen1
 }
 
 // y = S x at every interior node of vg and every master of ig with the
-// stencils of g (one per tetrahedron and one per primitive; the mass matrix)
+// stencils of g (one per tetrahedron, and one per primitive or, with
+// g.wi15, one per master; the mass matrix)
 __global__ void __launch_bounds__(512) k_apply15(VolGeom vg, IfcGeom ig, Gen15 g, int nib, const double *__restrict__ x,
                                                  double *__restrict__ y) {
     const unsigned f = blockIdx.x;
@@ -660,7 +661,8 @@ __global__ void __launch_bounds__(512) k_apply15(VolGeom vg, IfcGeom ig, Gen15 g
         const int t = ig.i0 + (int)(f * blockDim.x + threadIdx.x);
         if (t >= ig.i1) return;
         double diag;
-        y[ig.base + t] = master_Au<double, false>(ig, g, x, t, x[ig.base + t], diag);
+        y[ig.base + t] = g.wi15 ? master_Au<double, true>(ig, g, x, t, x[ig.base + t], diag)
+                                : master_Au<double, false>(ig, g, x, t, x[ig.base + t], diag);
         return;
     }
     const unsigned per_vol = list_blocks_per_vol<1>(vg);

@@ -148,6 +148,12 @@ void stiffness(const double e[3][3], double K[4][4]) {
 
 inline long long binom3(long long p) { return p >= 3 ? p * (p - 1) * (p - 2) / 6 : 0; }
 
+// one entry of a master's row: slot, stiffness and mass value
+struct Entry {
+    int s;
+    double k, m;
+};
+
 }  // namespace
 
 std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *tets, int L_, int Lc_) {
@@ -241,7 +247,7 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
     lev.assign(L + 1, TopoLevel());
     std::vector<std::unordered_map<NKey, int, NKeyHash>> kmap(L + 1);
     std::vector<std::vector<Master>> mrec(L + 1);
-    std::vector<std::vector<std::vector<std::pair<int, double>>>> rows(L + 1);
+    std::vector<std::vector<std::vector<Entry>>> rows(L + 1);
     const std::vector<Around> around = elements_around();
     if (around.size() != 24) return "internal: element star";
     int width = 1;
@@ -363,13 +369,14 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         // (an element's shape depends only on its tetrahedron and its place
         // in the star), summed over the elements inside the closure
         Lv.mesh_w15.assign(15 * (size_t)nt, 0.0);
+        Lv.mesh_mw15.assign(15 * (size_t)nt, 0.0);
         auto &R = rows[l];
         R.assign(Lv.n_ifc, {});
         for (int t = 0; t < nt; t++) {
             double E[3][3];  // index-space unit steps in physical space
             for (int a = 0; a < 3; a++)
                 for (int c = 0; c < 3; c++) E[a][c] = (xyz[3 * tv[t][a + 1] + c] - xyz[3 * tv[t][0] + c]) / m;
-            double K[24][4][4];
+            double K[24][4][4], Mq[24];  // stiffness; mass |e| / 20 (1 + delta)
             for (int q = 0; q < 24; q++) {
                 const Around &A = around[q];
                 double x[4][3];
@@ -379,6 +386,10 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                 for (int r = 0; r < 3; r++)
                     for (int c = 0; c < 3; c++) e[r][c] = x[r + 1][c] - x[0][c];
                 stiffness(e, K[q]);
+                const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                                   e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                                   e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+                Mq[q] = std::fabs(det) / 6.0 / 20.0;
             }
             for (int q = 0; q < 24; q++) {
                 const Around &A = around[q];
@@ -387,6 +398,7 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                     const int n = idx15_of(d);
                     if (n < 0) return "internal: element star outside the 15-point stencil";
                     Lv.mesh_w15[15 * (size_t)t + n] += K[q][A.self][r];
+                    Lv.mesh_mw15[15 * (size_t)t + n] += Mq[q] * (r == A.self ? 2.0 : 1.0);
                 }
             }
             fill_cslot(t);
@@ -397,7 +409,7 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                         const long long own = cslot[Lv.lay.index(i, j, k)];
                         if (own == Lv.zero_slot) continue;
                         auto &row = R[own - Lv.ifc_base];
-                        if (row.empty()) row.push_back({(int)own, 0.0});
+                        if (row.empty()) row.push_back({(int)own, 0.0, 0.0});
                         for (int q = 0; q < 24; q++) {
                             const Around &A = around[q];
                             int p[4][3];
@@ -412,9 +424,10 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             for (int r = 0; r < 4; r++) {
                                 const int s = cslot[Lv.lay.index(p[r][0], p[r][1], p[r][2])];
                                 size_t e = 0;
-                                while (e < row.size() && row[e].first != s) e++;
-                                if (e == row.size()) row.push_back({s, 0.0});
-                                row[e].second += K[q][A.self][r];
+                                while (e < row.size() && row[e].s != s) e++;
+                                if (e == row.size()) row.push_back({s, 0.0, 0.0});
+                                row[e].k += K[q][A.self][r];
+                                row[e].m += Mq[q] * (r == A.self ? 2.0 : 1.0);
                             }
                         }
                     }
@@ -429,12 +442,14 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         const size_t n = (size_t)Lv.n_ifc;
         Lv.nb15.assign((size_t)nbw * n, (int)Lv.zero_slot);
         Lv.mesh_wi.assign((size_t)nbw * n, 0.0);
+        Lv.mesh_mwi.assign((size_t)nbw * n, 0.0);
         for (size_t f = 0; f < n; f++) {
             auto &row = rows[l][f];
-            std::sort(row.begin() + 1, row.end());
+            std::sort(row.begin() + 1, row.end(), [](const Entry &a, const Entry &b) { return a.s < b.s; });
             for (size_t e = 0; e < row.size(); e++) {
-                Lv.nb15[e * n + f] = row[e].first;
-                Lv.mesh_wi[e * n + f] = row[e].second;
+                Lv.nb15[e * n + f] = row[e].s;
+                Lv.mesh_wi[e * n + f] = row[e].k;
+                Lv.mesh_mwi[e * n + f] = row[e].m;
             }
         }
     }

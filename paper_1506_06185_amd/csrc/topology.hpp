@@ -120,6 +120,7 @@ struct TopoLevel {
     // nb15 of the same layout; unused entries 0 at the zero slot)
     long long vbase = 0, nint = 0;
     std::vector<double> mesh_w15, mesh_wi;
+    std::vector<double> mesh_mw15, mesh_mwi;  // the consistent P1 mass matrix, same layout
 };
 
 // index-space offsets of the 15-point stencil (centre first); offset n

@@ -266,7 +266,8 @@ int main() {
               ne);
         std::vector<double> v(nd, 1.0), w(nd, 0.0);
         double rr = 0;
-        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_EINVAL, "mesh nodal f rejected");
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_DIRICHLET) == HHGR_EINVAL, "mesh Dirichlet data rejected");
+        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_OK, "mesh nodal f: %s", hhgr_last_error());
         CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "mesh rhs: %s", hhgr_last_error());
         CHECK(hhgr_set_solution(g, v.data()) == HHGR_OK, "mesh set solution");
         CHECK(hhgr_get_solution(g, w.data()) == HHGR_OK, "mesh get solution");
@@ -279,7 +280,10 @@ int main() {
         CHECK(hhgr_recover_dd(g, t2, 2, 2, 3) == HHGR_OK, "mesh dd: %s", hhgr_last_error());
         CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_OK, "mesh vcycle after dd");
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_EINVAL, "mesh dn rejected");
-        CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_EINVAL, "mesh mass rejected");
+        CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_OK, "mesh mass: %s", hhgr_last_error());
+        CHECK(hhgr_adjoint_grad(g, v.data(), 1e-10, 5, w.data(), nullptr) == HHGR_ENOCONV, "mesh adjoint: %s",
+              hhgr_last_error());
+        CHECK(hhgr_adjoint_grad(g, v.data(), 1e-10, 5, w.data(), w.data()) == HHGR_ESTATE, "mesh dJ/dk rejected");
         CHECK(hhgr_autotune(g, nullptr) == HHGR_EINVAL, "mesh autotune rejected");
         CHECK(hhgr_set_fused_sweeps(g, 4, 1) == HHGR_EINVAL, "mesh fused sweeps rejected");
         CHECK(hhgr_set_fused_sweeps(cs[0].h, 5, 1) == HHGR_OK, "cube fused sweeps: %s", hhgr_last_error());

@@ -123,6 +123,28 @@ int main(int argc, char **argv) {
             }
         }
         std::fprintf(o, "end\n");
+        if (l == L) {
+            // the consistent mass matrix on the finest level, same layout
+            std::fprintf(o, "M %d %lld\n", l, nd);
+            for (int t = 0; t < nt; t++)
+                for (int k = 1; k < m; k++)
+                    for (int j = 1; j < m; j++)
+                        for (int i = 1; i + j + k <= m - 1; i++) {
+                            const long long r = U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)];
+                            for (int n = 0; n < 15; n++) {
+                                const long long c = U[(long long)t * Lv.C_pad +
+                                                      Lv.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2])];
+                                if (c >= 0) std::fprintf(o, "%lld %lld %.17g\n", r, c, Lv.mesh_mw15[15 * (size_t)t + n]);
+                            }
+                        }
+            for (int q = 0; q < Lv.n_ifc; q++)
+                for (int n = 0; n < tp.nbw; n++) {
+                    const long long c = U[Lv.nb15[(size_t)n * Lv.n_ifc + q]];
+                    if (c >= 0)
+                        std::fprintf(o, "%d %lld %.17g\n", Lv.ifc_dof[q], c, Lv.mesh_mwi[(size_t)n * Lv.n_ifc + q]);
+                }
+            std::fprintf(o, "end\n");
+        }
     }
     // interface rows of the transfers: P (fine master <- coarse parents) and
     // R = P^T (coarse master <- its fine twin and the neighbours at 1/2)

@@ -184,11 +184,10 @@ def test_mesh_context_rejects_unsupported_calls(dev, hh):
     n = ctx.n_dofs
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     with pytest.raises(hh.HHGRError) as e:
-        ctx.set_rhs(x, hh.HHGR_RHS_NODAL_F)
+        ctx.set_rhs(x, hh.HHGR_RHS_DIRICHLET)
     assert e.value.code == hh.HHGR_EINVAL
     ctx.set_rhs(x + 1.0, hh.HHGR_RHS_LOAD)
-    for call in (lambda: ctx.recover_dn([1], 1, 1), lambda: ctx.mass_apply(x), lambda: ctx.autotune(),
-                 lambda: ctx.set_fused_sweeps(4, True)):
+    for call in (lambda: ctx.recover_dn([1], 1, 1), lambda: ctx.autotune(), lambda: ctx.set_fused_sweeps(4, True)):
         with pytest.raises(hh.HHGRError) as e:
             call()
         assert e.value.code == hh.HHGR_EINVAL
@@ -260,4 +259,34 @@ def test_mesh_dirichlet_dirichlet_recovery(dev, hh, precision):
         ctx.solve(rel_tol=1e-11, max_cycles=60)
         uo, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
         assert rel(Nn(ctx.get_solution()), uo) < 1e-9
+    ctx.close()
+
+
+def test_mesh_mass_matrix_nodal_source_and_adjoint(dev, hh):
+    """The consistent P1 mass matrix on an unstructured mesh (per-tetrahedron
+    and per-master rows): its action, b = M f from nodal values of f, and the
+    adjoint dJ/df = M lambda with A lambda = g, against the oracle."""
+    import scipy.sparse.linalg as spla
+
+    name, level = "box222p", 4
+    print(f"\n[mesh mass, adjoint] {name} level={level}", flush=True)
+    p = problem(name, level)
+    ctx = context(hh, dev, name, level)
+    g = np.random.default_rng(77)
+    x = g.standard_normal(p.ndof)
+    assert rel(Nn(ctx.mass_apply(T(x, dev))), p.apply_M(x)) < 1e-13
+    f = g.uniform(-1, 1, p.ndof)
+    ctx.set_rhs(T(f, dev), hh.HHGR_RHS_NODAL_F)
+    b = p.apply_M(f)
+    u = np.zeros(p.ndof)
+    for it in range(3):
+        ctx.vcycle(1)
+        u, _ = p.vcycle(u, b)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+    gv = g.standard_normal(p.ndof)
+    dJdf, _ = ctx.adjoint_grad(T(gv, dev), rel_tol=1e-13, max_cycles=80, want_k=False)
+    lam = spla.spsolve(p.matrix(level, "A").tocsc(), gv)
+    assert rel(Nn(dJdf), p.apply_M(lam)) < 1e-10
+    # the forward state is kept
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
     ctx.close()

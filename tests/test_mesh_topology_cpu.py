@@ -6,7 +6,7 @@ its internal invariants (every user index once, ghost lists, no stencil entry
 inside one colour class), and writes, per level, the operator that the
 topology's tables define (volume stencils and master rows) and the interface
 rows of the transfers, in the user order.  These must equal the oracle's
-element-by-element stiffness matrix and prolongation rows."""
+element-by-element stiffness matrix, mass matrix and prolongation rows."""
 import os
 import subprocess
 
@@ -88,6 +88,10 @@ def test_mesh_topology_operator_equals_oracle(name, mesh_check, tmp_path):
         A = to_csr(mats[("A", l)], (n, n))
         Ao = p.matrix(l, "A")
         assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max(), (l, abs(A - Ao).max())
+    # the consistent mass matrix of the finest level
+    M = to_csr(mats[("M", L)], (p.ndof, p.ndof))
+    Mo = p.matrix(L, "M")
+    assert abs(M - Mo).max() <= 1e-13 * abs(Mo).max(), abs(M - Mo).max()
     for l in range(Lc + 1, L + 1):
         nf, nc = p.ndof_at(l), p.ndof_at(l - 1)
         P = to_csr(mats[("P", l)], (nf, nc))
