@@ -33,6 +33,9 @@ Further legs, each in its own object of the JSON line:
             vertices moved (inputs.perturbed_vertices, seed 0), 15-point
             stencils, 4-colour SOR, load b ~ U[-1,1], in FP64 and in mixed
             precision; its roofline is the finest-level FP64 class pass.
+  vcycle_rates  plain V-cycle rates at levels 5, 6 and 7, eager and
+            graph-replayed, one host read per batch of 20 cycles;
+  uninstrumented  the headline steps timed again without kernel events;
   unstructured_mesh  the same job on an unstructured macro mesh from vertex
             and tetrahedron lists (a 3x3x3 box of cubes split into 5
             tetrahedra each, moved vertices, level 7), FP64 and mixed.
@@ -316,6 +319,35 @@ def leg_general(hh, torch, dev, n_sub, level, steps, warmup, graph, tune_cache):
         "roofline": roofline,
         "mixed": mixed,
     }
+
+
+def leg_vcycle_rates(hh, torch, dev, tune_cache, n_sub=2, levels=(5, 6, 7), cycles=20):
+    """Plain V(2,1) cycle rates (no fault, one host read at the end of each
+    timed batch of cycles), eager and replayed from captured graphs, per
+    level: unknowns x cycles / time.  Level 5 (250,047 unknowns, 2 MB per
+    vector) stays in the Infinity Cache, level 7 streams from HBM."""
+    from paper_1506_06185_amd import inputs
+
+    out = {}
+    for level in levels:
+        ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+        ctx.autotune(tune_cache)
+        ctx.set_rhs(torch.from_numpy(inputs.sine_source(n_sub, level)).to(dev), hh.HHGR_RHS_NODAL_F)
+        row = {"unknowns": ctx.n_dofs}
+        for mode in ("eager", "graph"):
+            ctx.set_graph(mode == "graph")
+            ctx.set_solution(None)
+            ctx.vcycle(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.vcycle(cycles)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row[mode] = {"value": round(ctx.n_dofs * cycles / dt / 1e6, 1), "unit": "MDoF/s",
+                         "ms_per_cycle": round(1e3 * dt / cycles, 4)}
+        out[str(level)] = row
+        ctx.close()
+    return out
 
 
 def leg_mesh(hh, torch, dev, steps, warmup, graph, nx=3, level=7):
@@ -621,6 +653,20 @@ def main():
     log(f"timed {args.steps} steps in {dt:.3f} s")
     launches, mean_ms, alg_bytes = ctx.kernel_stats() if not args.graph else (0, 0.0, 0.0)
     ctx.kernel_timing(False)
+    # the same steps again without the per-launch events of the roofline
+    uninstrumented = None
+    if not args.graph:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cyc_u = 0
+        for s in range(args.steps):
+            c_u, _ = run_job(hh, torch, ctx, f_dev, t_fault)
+            cyc_u += c_u
+        torch.cuda.synchronize()
+        dt_u = time.perf_counter() - t1
+        uninstrumented = {"value": round(ctx.n_dofs * cyc_u / dt_u / 1e6, 1), "unit": "MDoF/s",
+                          "ms_per_step": round(1e3 * dt_u / args.steps, 3),
+                          "note": "the same steps after the timed ones, without kernel events"}
     k_faulty = total_cycles // args.steps
     ms_per_step = 1e3 * dt / args.steps
     value = ctx.n_dofs * total_cycles / dt / 1e6
@@ -670,6 +716,10 @@ def main():
     if not args.no_general:
         log("general macro mesh leg")
         general = leg_general(hh, torch, dev, n_sub, level, args.steps, args.warmup, args.graph, tune_cache)
+    rates = None
+    if not args.no_extra:
+        log("V-cycle rates")
+        rates = leg_vcycle_rates(hh, torch, dev, tune_cache)
     mesh = None
     if not args.no_mesh:
         log("unstructured macro mesh leg")
@@ -727,6 +777,8 @@ def main():
         "kappa": round((k_faulty - k_free) / 5, 3),
         "final_rel_res": rel,
         "roofline": roofline,
+        "uninstrumented": uninstrumented,
+        "vcycle_rates": rates,
         "mixed": mixed,
         "general_mesh": general,
         "unstructured_mesh": mesh,
