@@ -290,3 +290,39 @@ def test_mesh_mass_matrix_nodal_source_and_adjoint(dev, hh):
     # the forward state is kept
     assert rel(Nn(ctx.get_solution()), u) < 1e-12
     ctx.close()
+
+
+def test_mesh_full_size_properties(dev, hh):
+    """The bench's mesh workload at its full size (135 tetrahedra, level 7,
+    46,745,279 unknowns), through properties that hold at any size: the
+    operator is symmetric and positive on random vectors (x.Ay = y.Ax to
+    1e-12, x.Ax > 0), and after a solve to 1e-12 a fault followed by enough
+    local recovery cycles restores the solution (the local Dirichlet problem
+    with exact interface data has the global solution as its solution)."""
+    v, t = inputs.box_mesh(3, 3, 3)
+    v = inputs.perturb_mesh(v, seed=0, amplitude=0.12)
+    level = 7
+    print(f"\n[mesh full size] box333 level={level}", flush=True)
+    ctx = hh.Context(device=dev, mesh=(v, t), level=level)
+    n = ctx.n_dofs
+    assert n == 46745279
+    gen = torch.Generator(device=dev).manual_seed(5)
+    x = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+    y = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+    zero = torch.zeros(n, dtype=torch.float64, device=dev)
+    ax = -hh.debug_op(ctx, 0, level, x, zero)[:n]
+    ay = -hh.debug_op(ctx, 0, level, y, zero)[:n]
+    xay, yax = float(torch.dot(x, ay)), float(torch.dot(y, ax))
+    assert abs(xay - yax) <= 1e-12 * float(torch.linalg.norm(x) * torch.linalg.norm(ay))
+    assert float(torch.dot(x, ax)) > 0
+    b = 2.0 * torch.rand(n, dtype=torch.float64, device=dev, generator=gen) - 1.0
+    ctx.set_rhs(b, hh.HHGR_RHS_LOAD)
+    cyc, relres, _ = ctx.solve(rel_tol=1e-12, max_cycles=80)
+    u = ctx.get_solution().clone()
+    tet = inputs.mesh_fault_tet(len(t), seed=0)
+    ctx.inject_fault(tet)
+    lr = ctx.recover_local(tet, 30)
+    du = float(torch.linalg.norm(ctx.get_solution() - u) / torch.linalg.norm(u))
+    print(f"solve: {cyc} cycles to {relres:.2e}; after fault + 30 local cycles: rel change {du:.2e}, local {lr:.2e}")
+    assert du < 1e-9
+    ctx.close()
