@@ -326,3 +326,51 @@ def test_mesh_full_size_properties(dev, hh):
     print(f"solve: {cyc} cycles to {relres:.2e}; after fault + 30 local cycles: rel change {du:.2e}, local {lr:.2e}")
     assert du < 1e-9
     ctx.close()
+
+
+@pytest.mark.parametrize("level", [3, 5])
+def test_mesh_single_tetrahedron(dev, hh, level):
+    """The smallest unstructured mesh: one tetrahedron, every face on the
+    boundary, so there is no interface master at all (empty master lists
+    and a coarsest level of one unknown).  Operators, iterates and a solve;
+    a fault then wipes every unknown and the local recovery is a full solve."""
+    v = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.2, 1.1, 0.0], [0.3, 0.2, 0.9]])
+    t = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    print(f"\n[mesh single tet] level={level}", flush=True)
+    p = oracle.MeshProblem(v, t, level, 2)
+    ctx = hh.Context(device=dev, mesh=(v, t), level=level)
+    assert ctx.n_dofs == p.ndof == (2 ** level - 1) * (2 ** level - 2) * (2 ** level - 3) // 6
+    g = np.random.default_rng(level)
+    u0, b0 = g.standard_normal(p.ndof), g.standard_normal(p.ndof)
+    r = Nn(hh.debug_op(ctx, 0, level, T(u0, dev), T(b0, dev)))
+    assert rel(r, p.residual(u0, b0)) < 1e-12
+    us = Nn(hh.debug_op(ctx, 8 + 15, level, T(u0, dev), T(b0, dev)))
+    assert rel(us, p.smooth(u0, b0, omega=1.25, colours=15)) < 1e-12
+    for l in range(3, level + 1):
+        x = g.standard_normal(p.ndof_at(l))
+        rc = Nn(hh.debug_op(ctx, 4, l, T(x, dev)))[: p.ndof_at(l - 1)]
+        assert rel(rc, p.restrict(x, level=l)) < 1e-13, ("restrict", l)
+        ec = g.standard_normal(p.ndof_at(l - 1))
+        up = Nn(hh.debug_op(ctx, 5, l, T(ec, dev), T(x, dev)))[: p.ndof_at(l)]
+        assert rel(up, p.prolong_add(ec, x, level=l)) < 1e-13, ("prolong", l)
+    bc = g.standard_normal(1)
+    uc = Nn(hh.debug_op(ctx, 7, 2, T(bc, dev)))[:1]
+    assert rel(uc, bc / p.matrix(2, "A").toarray()[0, 0]) < 1e-13
+    b = g.uniform(-1, 1, p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(None)  # the operator calls above left their inputs in the context's vectors
+    u = np.zeros(p.ndof)
+    for it in range(3):
+        ctx.vcycle(1)
+        u, _ = p.vcycle(u, b)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+    ctx.inject_fault(0)
+    u = p.inject_fault(0, u)
+    assert np.all(Nn(ctx.get_solution()) == 0.0) and np.all(u == 0.0)
+    ctx.recover_local(0, 3)
+    u, _ = p.recover_local([0], u, b, 3)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    cyc, _, _ = ctx.solve(rel_tol=1e-10, max_cycles=60)
+    uo, cyc_o, _ = p.solve(b, u0=u, rtol=1e-10, max_cycles=60, r0=np.linalg.norm(b))
+    assert cyc == cyc_o and rel(Nn(ctx.get_solution()), uo) < 1e-10
+    ctx.close()
