@@ -153,8 +153,12 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * omega, precision and max_faults as above; n_sub and general_geometry are
  * ignored; variable_coeff must be 0.  The coarsest level is solved with a
  * dense inverse (at most 2048 unknowns).  A mesh context takes hhgr_set_rhs
- * with HHGR_RHS_LOAD or HHGR_RHS_NODAL_F (b = M f with the consistent P1 mass
- * matrix of the finest level, per-master rows like the stiffness),
+ * with HHGR_RHS_LOAD, HHGR_RHS_NODAL_F (b = M f with the consistent P1 mass
+ * matrix of the finest level, per-master rows like the stiffness) or
+ * HHGR_RHS_DIRICHLET (Laplace's equation with the boundary values g of
+ * eq. (1): the vector holds g at the boundary nodes in the order of
+ * hhgr_mesh_boundary, and b = -A_IB g, the stiffness couplings of the
+ * interior nodes to the boundary nodes applied to g),
  * hhgr_mass_apply, hhgr_adjoint_grad (dJ/df only), hhgr_set_solution/get_solution, hhgr_vcycle,
  * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_recover_dd (its
  * masked coarsest level with a dense inverse of the unfrozen unknowns,
@@ -167,6 +171,13 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * that is too large; the message names the reason. */
 int hhgr_mesh_workspace_bytes(const hhgr_desc *desc, int nv, const double *host_xyz, int nt, const int *host_tets,
                               size_t *bytes);
+/* Boundary nodes of the finest level of a mesh context (the nodes where u is
+ * prescribed, eq. (1)): their number, and (host_xyz, optional, host memory
+ * of 3 * n doubles) their positions, in this order: boundary macro vertices
+ * by id, then boundary edges (a < b) with their nodes by the weight of b,
+ * then boundary faces (a < b < c) with their nodes by the weight of c, then
+ * of b.  EINVAL for a context not made by hhgr_create_mesh. */
+int hhgr_mesh_boundary(const hhgr_ctx *ctx, long long *n_boundary, double *host_xyz);
 int hhgr_create_mesh(const hhgr_desc *desc, int nv, const double *host_xyz, int nt, const int *host_tets,
                      void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out);
 

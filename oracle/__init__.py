@@ -456,8 +456,38 @@ class MeshProblem(Problem):
     def positions(self, level: int | None = None):
         raise NotImplementedError("a general macro mesh has no grid positions: use nodes()")
 
-    def dirichlet_load(self, g, level: int | None = None):
-        raise NotImplementedError("not defined on a general macro mesh")
+    def boundary_order(self, level: int | None = None) -> np.ndarray:
+        """Node indices (creation order) of the Dirichlet boundary nodes, in
+        the order of the interior ones restricted to boundary primitives:
+        vertices by id, edges (a < b) by the weight of b, faces (a < b < c)
+        by the weight of c, then of b."""
+        level = self.level if level is None else level
+        k = self.keys(level)
+        _, dof = self.nodes(level)
+        recs = []
+        for n in np.flatnonzero(dof < 0):
+            vs = [int(a) for a in k[n, :, 0] if a >= 0]
+            ws = [int(b) for a, b in k[n] if a >= 0]
+            prim = tuple(vs + [-1] * (3 - len(vs)))
+            last = ws[-1] if len(vs) >= 2 else 0
+            mid = ws[1] if len(vs) == 3 else 0
+            recs.append(((len(vs) - 1, prim, last, mid), n))
+        return np.array([n for _, n in sorted(recs)], dtype=np.int64)
+
+    def dirichlet_load(self, g, level: int | None = None) -> np.ndarray:
+        """Right-hand side of eq. (2) for Laplace's equation with the boundary
+        values g of eq. (1) (g in boundary_order): the stiffness matrix over
+        all nodes applied to g on the boundary nodes, negated, on the interior
+        rows in user order."""
+        level = self.level if level is None else level
+        xyz, dof = self.nodes(level)
+        order = self.boundary_order(level)
+        gf = np.zeros(len(xyz))
+        gf[order] = _f64(g)
+        full = -(self.matrix(level, "A", full=True) @ gf)
+        b = np.empty(int((dof >= 0).sum()))
+        b[dof[dof >= 0]] = full[dof >= 0]
+        return b
 
     def grad_k(self, u, lam):
         raise NotImplementedError("not defined on a general macro mesh")

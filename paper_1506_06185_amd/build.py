@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhgr.so")
-SOURCES = ["topology.cpp", "mesh.cpp", "geometry.cpp", "kernels.hip", "fused.hip", "engine.hip"]
+SOURCES = ["topology.cpp", "mesh.cpp", "geometry.cpp", "kernels.hip", "fused.hip", "mesh_kernels.hip", "engine.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -201,6 +201,10 @@ struct hhgr_ctx {
     // the unknowns frozen by a Dirichlet-Dirichlet recovery left out (their
     // rows and columns zero), set by dd_setup
     double *cinv_dd = nullptr;
+    // ... and the couplings of interior rows to Dirichlet boundary nodes
+    int *dir_rows = nullptr, *dir_ptr = nullptr, *dir_col = nullptr;
+    double *dir_val = nullptr;
+    int n_dir_rows = 0;
     // general macro meshes: 15-point coarsest-level operator
     bool gen = false, geom_set = false;
     bool mesh = false;  // unstructured macro mesh (hhgr_create_mesh): gen, operator fixed at creation
@@ -501,6 +505,13 @@ void carve(hhgr_ctx &c, Carver &cv) {
     c.citers = cv.take<int>(4);
     if (!c.vk && c.cn <= (c.mesh ? kDenseCoarseMaxMesh : kDenseCoarseMax)) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
     if (c.mesh && c.d.max_faults > 0) c.cinv_dd = cv.take<double>((size_t)c.cn * c.cn);
+    if (c.mesh) {
+        c.n_dir_rows = (int)tp.dir_rows.size();
+        c.dir_rows = cv.take<int>(tp.dir_rows.size());
+        c.dir_ptr = cv.take<int>(tp.dir_ptr.size());
+        c.dir_col = cv.take<int>(tp.dir_col.size());
+        c.dir_val = cv.take<double>(tp.dir_val.size());
+    }
     if (c.gen) {
         c.ccol15 = cv.take<int>(15 * (size_t)c.cn);
         c.cval15 = cv.take<double>(15 * (size_t)c.cn);
@@ -1728,6 +1739,10 @@ int create_ctx(const hhgr_desc *desc, std::shared_ptr<const Topology> mesh_topo,
         c->dense_coarse = true;
     }
     if (c->mesh) {
+        rc = rc ? rc : upload(*c, c->dir_rows, tp.dir_rows.data(), tp.dir_rows.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, c->dir_ptr, tp.dir_ptr.data(), tp.dir_ptr.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, c->dir_col, tp.dir_col.data(), tp.dir_col.size() * sizeof(int));
+        rc = rc ? rc : upload(*c, c->dir_val, tp.dir_val.data(), tp.dir_val.size() * sizeof(double));
         if (!c->cinv || !coarse_inverse(cs.n, cs.cw, cs.colw, cs.valw, cinv_host))
             return bail(fail(HHGR_EINVAL, "the coarsest-level operator of the mesh is not positive definite"));
         rc = rc ? rc : upload(*c, c->cinv, cinv_host.data(), cinv_host.size() * sizeof(double));
@@ -1769,6 +1784,14 @@ static hhgr_desc mesh_desc(const hhgr_desc *desc) {
     d.n_sub = 1;
     d.general_geometry = 1;
     return d;
+}
+
+int hhgr_mesh_boundary(const hhgr_ctx *c, long long *n_boundary, double *host_xyz) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (!c->mesh) return fail(HHGR_EINVAL, "not an unstructured macro mesh context");
+    if (n_boundary) *n_boundary = c->topo->n_bnd;
+    if (host_xyz) std::copy(c->topo->bnd_xyz.begin(), c->topo->bnd_xyz.end(), host_xyz);
+    return HHGR_OK;
 }
 
 int hhgr_mesh_workspace_bytes(const hhgr_desc *desc_in, int nv, const double *host_xyz, int nt, const int *host_tets,
@@ -1849,9 +1872,12 @@ int hhgr_set_rhs(hhgr_ctx *c, const double *dev_vec, int kind) {
     const VolGeom vint = vgeom(D, D.vd_all, c->n_tets, false);
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
     bool aux_used = false;  // aux_u held the load in vector order
-    if (c->mesh && kind == HHGR_RHS_DIRICHLET)
-        return fail(HHGR_EINVAL, "no Dirichlet data on an unstructured macro mesh (u = 0 on its boundary)");
-    if (kind == HHGR_RHS_LOAD) {
+
+    if (kind == HHGR_RHS_DIRICHLET && c->mesh) {
+        // g at the boundary nodes (hhgr_mesh_boundary order): b = -A_IB g
+        launch_fill<double>(c->stream, D.b, D.n_slots, 0.0);
+        launch_dirichlet_rows(c->stream, c->n_dir_rows, c->dir_rows, c->dir_ptr, c->dir_col, c->dir_val, dev_vec, D.b);
+    } else if (kind == HHGR_RHS_LOAD) {
         to_slots(*c, D, dev_vec, D.b, c->stream);
     } else if (kind == HHGR_RHS_DIRICHLET && c->gen) {
         launch_gen_dirichlet(c->stream, vint, ig, gen15(D, -1, false), c->tetinfo, D.ifc_xyz, D.N, dev_vec, D.b);

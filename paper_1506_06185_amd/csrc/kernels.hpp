@@ -237,6 +237,12 @@ template <typename T>
 void launch_mesh_slots_to_user(hipStream_t s, const VolGeom &vint, long long vbase, long long nint, const IfcGeom &ig,
                                const int *ifc_dof, const T *vec, double *user);
 
+// unstructured macro meshes, eliminated Dirichlet data: b[rows[q]] =
+// -sum over ptr[q] .. ptr[q + 1] of val * g[col] (mesh_kernels.hip); the
+// other slots of b are left as they are
+void launch_dirichlet_rows(hipStream_t s, int nrows, const int *rows, const int *ptr, const int *col,
+                           const double *val, const double *g, double *b);
+
 // user vector (global lexicographic interior order) <-> slot space; vfull
 // lists every closure node (ghosts receive the user value or the Dirichlet zero)
 template <typename T>

@@ -331,13 +331,67 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
             auto it = km.find(key_of(s));
             return it == km.end() ? Lv.zero_slot : Lv.ifc_base + it->second;
         };
-        // the same for every node of one closure, looked up once per node
-        std::vector<int> cslot(Lv.C_pad);
+        // the same for every node of one closure, looked up once per node;
+        // on the finest level also the boundary index of Dirichlet nodes
+        std::vector<int> cslot(Lv.C_pad), cbnd(Lv.C_pad, -1);
+        std::unordered_map<NKey, int, NKeyHash> bmap;
+        if (l == L) {
+            // boundary nodes in the order of the interior ones: vertices by
+            // id, edges (a < b) by the weight of b, faces (a < b < c) by the
+            // weights of c then b
+            std::vector<Master> br;
+            for (int t = 0; t < nt; t++)
+                for (int k = 0; k <= m; k++)
+                    for (int j = 0; j <= m - k; j++)
+                        for (int i = 0; i <= m - k - j; i++) {
+                            if (!(i == 0 || j == 0 || k == 0 || i + j + k == m)) continue;
+                            const int lam[4] = {m - i - j - k, i, j, k};
+                            const Support s = support_of(tv[t], lam);
+                            if (!dirichlet(s)) continue;
+                            const NKey key = key_of(s);
+                            if (bmap.count(key)) continue;
+                            bmap.emplace(key, (int)br.size());
+                            Master r;
+                            r.key = key;
+                            r.dim = s.n - 1;
+                            for (int a = 0; a < s.n; a++) {
+                                r.prim[a] = s.v[a];
+                                r.w[a] = s.w[a];
+                            }
+                            br.push_back(r);
+                        }
+            auto order = [](const Master &r) {
+                // (dim, primitive, weight of the last vertex, then of the middle one)
+                const int wl = r.dim >= 1 ? r.w[r.dim] : 0, wm = r.dim == 2 ? r.w[1] : 0;
+                return std::make_tuple(r.dim, r.prim, wl, wm);
+            };
+            std::sort(br.begin(), br.end(), [&](const Master &a, const Master &b) { return order(a) < order(b); });
+            bnd_xyz.assign(3 * br.size(), 0.0);
+            for (size_t q = 0; q < br.size(); q++) {
+                bmap[br[q].key] = (int)q;
+                for (int a = 0; a <= br[q].dim; a++)
+                    for (int c = 0; c < 3; c++) bnd_xyz[3 * q + c] += br[q].w[a] * xyz[3 * br[q].prim[a] + c] / m;
+            }
+            n_bnd = (long long)br.size();
+        }
         auto fill_cslot = [&](int t) {
             for (int k = 0; k <= m; k++)
                 for (int j = 0; j <= m - k; j++)
-                    for (int i = 0; i <= m - k - j; i++) cslot[Lv.lay.index(i, j, k)] = (int)slot(t, i, j, k);
+                    for (int i = 0; i <= m - k - j; i++) {
+                        const int q = Lv.lay.index(i, j, k);
+                        cslot[q] = (int)slot(t, i, j, k);
+                        if (l == L && cslot[q] == Lv.zero_slot) {
+                            const int lam[4] = {m - i - j - k, i, j, k};
+                            auto it = bmap.find(key_of(support_of(tv[t], lam)));
+                            cbnd[q] = it == bmap.end() ? -1 : it->second;
+                        } else {
+                            cbnd[q] = -1;
+                        }
+                    }
         };
+        // finest level: the couplings of interior nodes (slot, boundary
+        // index, stiffness) to Dirichlet nodes, for eliminated boundary data
+        std::map<std::pair<int, int>, double> dir;
         // ghost copies
         Lv.nbr.assign(6 * (size_t)Lv.n_ifc, (int)Lv.zero_slot);
         Lv.tg_ptr.assign(nt + 1, 0);
@@ -402,6 +456,17 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                 }
             }
             fill_cslot(t);
+            if (l == L)
+                for (int k = 1; k < m; k++)
+                    for (int j = 1; j < m - k; j++)
+                        for (int i = 1; i + j + k <= m - 1; i++) {
+                            if (!(i == 1 || j == 1 || k == 1 || i + j + k == m - 1)) continue;
+                            const int own = cslot[Lv.lay.index(i, j, k)];
+                            for (int n = 1; n < 15; n++) {
+                                const int q = Lv.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2]);
+                                if (cbnd[q] >= 0) dir[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
+                            }
+                        }
             for (int k = 0; k <= m; k++)
                 for (int j = 0; j <= m - k; j++)
                     for (int i = 0; i <= m - k - j; i++) {
@@ -422,7 +487,9 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             }
                             if (!in) continue;
                             for (int r = 0; r < 4; r++) {
-                                const int s = cslot[Lv.lay.index(p[r][0], p[r][1], p[r][2])];
+                                const int pq = Lv.lay.index(p[r][0], p[r][1], p[r][2]);
+                                if (cbnd[pq] >= 0) dir[{(int)own, cbnd[pq]}] += K[q][A.self][r];
+                                const int s = cslot[pq];
                                 size_t e = 0;
                                 while (e < row.size() && row[e].s != s) e++;
                                 if (e == row.size()) row.push_back({s, 0.0, 0.0});
@@ -433,6 +500,22 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                     }
         }
         for (const auto &row : R) width = std::max(width, (int)row.size());
+        if (l == L) {
+            // rows by slot, columns by boundary index (std::map order)
+            dir_rows.clear();
+            dir_ptr.assign(1, 0);
+            dir_col.clear();
+            dir_val.clear();
+            for (const auto &e : dir) {
+                if (dir_rows.empty() || dir_rows.back() != e.first.first) {
+                    if (!dir_rows.empty()) dir_ptr.push_back((int)dir_col.size());
+                    dir_rows.push_back(e.first.first);
+                }
+                dir_col.push_back(e.first.second);
+                dir_val.push_back(e.second);
+            }
+            dir_ptr.push_back((int)dir_col.size());
+        }
         build_closure_tables(Lv);
     }
     // stencil width of every level; neighbours after the diagonal by slot

@@ -178,6 +178,15 @@ struct Topology {
     bool mesh = false;
     int nbw = 15;  // interface stencil and restriction width
     long long n_dofs = 0;
+    // finest level of a mesh: the Dirichlet boundary nodes (their order: the
+    // interior order's rule over boundary vertices, edges and faces) with
+    // their positions, and the stiffness couplings of interior nodes to
+    // them: rows dir_rows (slots) with entries dir_ptr[q] .. dir_ptr[q + 1]
+    // of boundary index dir_col and value dir_val
+    long long n_bnd = 0;
+    std::vector<double> bnd_xyz;
+    std::vector<int> dir_rows, dir_ptr, dir_col;
+    std::vector<double> dir_val;
 
     // slot of grid node X at level l (zero slot for boundary nodes)
     long long slot_of(int l, int x, int y, int z) const;

@@ -62,6 +62,7 @@ def lib():
         "hhgr_mesh_workspace_bytes": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp,
                                                 C.POINTER(C.c_size_t)]),
         "hhgr_set_fused_sweeps": (C.c_int, [_vp, C.c_int, C.c_int]),
+        "hhgr_mesh_boundary": (C.c_int, [_vp, C.POINTER(C.c_longlong), _vp]),
         "hhgr_create_mesh": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp, _vp, C.c_size_t, _vp,
                                        C.POINTER(_vp)]),
         "hhgr_destroy": (None, [_vp]),
@@ -108,7 +109,8 @@ EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_de
             "hhgr_mass_apply", "hhgr_batch_create", "hhgr_batch_run", "hhgr_batch_destroy", "hhgr_batch_arm_dd", "hhgr_set_graph",
             "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_solve_static",
-            "hhgr_mesh_workspace_bytes", "hhgr_create_mesh", "hhgr_set_fused_sweeps", "hhgr_last_error")
+            "hhgr_mesh_workspace_bytes", "hhgr_create_mesh", "hhgr_set_fused_sweeps", "hhgr_mesh_boundary",
+            "hhgr_last_error")
 
 
 def _check(rc: int, allow=()):
@@ -186,6 +188,11 @@ class Context:
         _check(lib().hhgr_sizes(self._h, C.byref(nd), C.byref(nt), C.byref(ne)))
         self.n_dofs, self.n_tets, self.n_elems = int(nd.value), int(nt.value), int(ne.value)
         self.N = self.desc.n_sub << self.desc.level
+        self.n_boundary = 0
+        if self.mesh:
+            nb = C.c_longlong(0)
+            _check(lib().hhgr_mesh_boundary(self._h, C.byref(nb), None))
+            self.n_boundary = int(nb.value)
         self.workspace_nbytes = nbytes
         # incremented by every call that changes the solution, the operator
         # or the right-hand side (HHGSolve checks it before its backward)
@@ -211,7 +218,10 @@ class Context:
 
     def set_rhs(self, vec: torch.Tensor, kind: int = HHGR_RHS_LOAD):
         self.version += 1
-        want = (self.N + 1) ** 3 if kind == HHGR_RHS_DIRICHLET else self.n_dofs
+        if kind == HHGR_RHS_DIRICHLET:
+            want = self.n_boundary if self.mesh else (self.N + 1) ** 3
+        else:
+            want = self.n_dofs
         if vec.numel() != want:
             raise HHGRError(HHGR_EINVAL, f"right-hand side has {vec.numel()} entries, expected {want}")
         _check(lib().hhgr_set_rhs(self._h, _ptr(vec), int(kind)))
@@ -296,6 +306,15 @@ class Context:
 
     def set_graph(self, on: bool = True):
         _check(lib().hhgr_set_graph(self._h, int(bool(on))))
+
+    def mesh_boundary(self) -> np.ndarray:
+        """Positions (n, 3) of the finest level's boundary nodes of a mesh
+        context, in the order HHGR_RHS_DIRICHLET takes the boundary values."""
+        n = C.c_longlong(0)
+        _check(lib().hhgr_mesh_boundary(self._h, C.byref(n), None))
+        xyz = np.empty((int(n.value), 3))
+        _check(lib().hhgr_mesh_boundary(self._h, C.byref(n), xyz.ctypes.data))
+        return xyz
 
     def set_fused_sweeps(self, level: int, on: bool = True):
         _check(lib().hhgr_set_fused_sweeps(self._h, int(level), int(bool(on))))

@@ -266,7 +266,12 @@ int main() {
               ne);
         std::vector<double> v(nd, 1.0), w(nd, 0.0);
         double rr = 0;
-        CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_DIRICHLET) == HHGR_EINVAL, "mesh Dirichlet data rejected");
+        long long nb = 0;
+        CHECK(hhgr_mesh_boundary(g, &nb, nullptr) == HHGR_OK && nb > 0, "mesh boundary count");
+        std::vector<double> bx(3 * nb), gbv(nb, 1.0);
+        CHECK(hhgr_mesh_boundary(g, &nb, bx.data()) == HHGR_OK, "mesh boundary positions");
+        CHECK(hhgr_mesh_boundary(cs[1].h, &nb, nullptr) == HHGR_EINVAL, "cube has no mesh boundary list");
+        CHECK(hhgr_set_rhs(g, gbv.data(), HHGR_RHS_DIRICHLET) == HHGR_OK, "mesh Dirichlet data: %s", hhgr_last_error());
         CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_NODAL_F) == HHGR_OK, "mesh nodal f: %s", hhgr_last_error());
         CHECK(hhgr_set_rhs(g, v.data(), HHGR_RHS_LOAD) == HHGR_OK, "mesh rhs: %s", hhgr_last_error());
         CHECK(hhgr_set_solution(g, v.data()) == HHGR_OK, "mesh set solution");

@@ -144,6 +144,16 @@ int main(int argc, char **argv) {
                         std::fprintf(o, "%d %lld %.17g\n", Lv.ifc_dof[q], c, Lv.mesh_mwi[(size_t)n * Lv.n_ifc + q]);
                 }
             std::fprintf(o, "end\n");
+            // couplings to the Dirichlet boundary nodes, and their positions
+            std::fprintf(o, "D %d %lld\n", l, tp.n_bnd);
+            for (size_t q = 0; q < tp.dir_rows.size(); q++)
+                for (int e = tp.dir_ptr[q]; e < tp.dir_ptr[q + 1]; e++)
+                    std::fprintf(o, "%lld %d %.17g\n", U[tp.dir_rows[q]], tp.dir_col[e], tp.dir_val[e]);
+            std::fprintf(o, "end\n");
+            std::fprintf(o, "X %d\n", l);
+            for (long long q = 0; q < tp.n_bnd; q++)
+                for (int c = 0; c < 3; c++) std::fprintf(o, "%lld %d %.17g\n", q, c, tp.bnd_xyz[3 * q + c]);
+            std::fprintf(o, "end\n");
         }
     }
     // interface rows of the transfers: P (fine master <- coarse parents) and

@@ -112,6 +112,8 @@ template <typename T>
 void launch_mesh_slots_to_user(hipStream_t, const VolGeom &, long long, long long, const IfcGeom &, const int *,
                                const T *, double *) {}
 void launch_mass(hipStream_t, const VolGeom &, const IfcGeom &, const int *, const double *, double *, double) {}
+void launch_dirichlet_rows(hipStream_t, int, const int *, const int *, const int *, const double *, const double *,
+                           double *) {}
 void launch_update_add(hipStream_t, const VolDesc *, int, long long, const IfcGeom &, double *, const float *) {}
 template <typename T>
 void launch_ghost_refresh(hipStream_t, const int *dst, const int *src, int n, T *u) {

@@ -92,6 +92,19 @@ def test_mesh_topology_operator_equals_oracle(name, mesh_check, tmp_path):
     M = to_csr(mats[("M", L)], (p.ndof, p.ndof))
     Mo = p.matrix(L, "M")
     assert abs(M - Mo).max() <= 1e-13 * abs(Mo).max(), abs(M - Mo).max()
+    # the boundary nodes (order and positions) and the interior-boundary block
+    xyz, dof = p.nodes(L)
+    order = p.boundary_order(L)
+    X = mats[("X", L)]
+    assert len(X) == 3 * len(order)
+    pos = np.zeros((len(order), 3))
+    pos[X[:, 0].astype(int), X[:, 1].astype(int)] = X[:, 2]
+    assert np.abs(pos - xyz[order]).max() < 1e-14
+    D = to_csr(mats[("D", L)], (p.ndof, len(order)))
+    Af = p.matrix(L, "A", full=True).tocsr()
+    interior = np.argsort(np.where(dof >= 0, dof, 1 << 40))[: p.ndof]
+    Do = Af[interior][:, order]
+    assert abs(D - Do).max() <= 1e-13 * abs(Do).max()
     for l in range(Lc + 1, L + 1):
         nf, nc = p.ndof_at(l), p.ndof_at(l - 1)
         P = to_csr(mats[("P", l)], (nf, nc))

@@ -314,3 +314,25 @@ def test_dirichlet_neumann_recovery_on_a_mesh():
     uf = p.inject_fault(tet, x)
     errs = [np.abs(p.dn_recover([tet], uf, b, n_intact=n, eta=2) - x).max() for n in (1, 3, 6)]
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-12 * np.abs(x).max(), errs
+
+
+@pytest.mark.parametrize("name", ["octa8", "box222p", "octa4"])
+def test_dirichlet_data_linear_reproduction(name):
+    """eq. (1): Laplace's equation with the boundary values of a linear
+    function has that function as its discrete solution (P1 reproduces
+    linear functions), on any mesh; the boundary order lists every
+    non-interior node once."""
+    v, t = mesh(name)
+    L = 4
+    p = oracle.MeshProblem(v, t, L, 2)
+    xyz, dof = p.nodes(L)
+    order = p.boundary_order(L)
+    assert sorted(order) == sorted(np.flatnonzero(dof < 0))
+    a, c = np.array([0.4, -1.0, 0.7]), 0.3
+    b = p.dirichlet_load(xyz[order] @ a + c)
+    u, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+    assert np.abs(u - (p.interior_positions(L) @ a + c)).max() < 1e-11
+    # a quadratic is not reproduced
+    q = p.dirichlet_load(xyz[order, 0] ** 2)
+    uq, _, _ = p.solve(q, rtol=1e-13, max_cycles=80)
+    assert np.abs(uq - p.interior_positions(L)[:, 0] ** 2).max() > 1e-3
