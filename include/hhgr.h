@@ -162,7 +162,10 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * hhgr_mass_apply, hhgr_adjoint_grad (dJ/df only), hhgr_set_solution/get_solution, hhgr_vcycle,
  * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_recover_dd (its
  * masked coarsest level with a dense inverse of the unfrozen unknowns,
- * computed on the host for each fault set), hhgr_set_graph,
+ * computed on the host for each fault set), hhgr_recover_dn (the intact
+ * side's master rows summed over the elements of intact tetrahedra and its
+ * coarsest level inverted densely, both on the host for each fault set;
+ * eq. (5)), hhgr_set_graph,
  * hhgr_kernel_timing/stats and hhgr_debug_op (ops 0, 3 to 5, 7, 8 + class
  * mask); every other call returns EINVAL for it.  hhgr_sizes reports the
  * interior unknowns, nt and nt 8^level.  EINVAL for a mesh that is not

@@ -396,9 +396,10 @@ void carve(hhgr_ctx &c, Carver &cv) {
             D.sid = cv.take<int>(T.n_ifc);
             if (c.mesh) {
                 // masters carry their own stencils (and, on the finest
-                // level, their own mass-matrix rows; no Dirichlet-Neumann
-                // recovery on a mesh)
+                // level, their own mass-matrix rows), and the intact-side
+                // rows of a Dirichlet-Neumann recovery
                 D.wi15 = cv.take<double>(W * T.n_ifc);
+                if (c.d.max_faults > 0) D.wi15_dn = cv.take<double>(W * T.n_ifc);
                 if (l == c.L) {
                     D.mw15 = cv.take<double>(15 * (size_t)c.n_tets);
                     D.mwi = cv.take<double>(W * T.n_ifc);
@@ -1395,7 +1396,46 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
         return rc;
     }
     // intact-side operators on every level
-    if (c.gen) {
+    if (c.mesh) {
+        // master rows over the elements of intact tetrahedra (host), and the
+        // coarsest-level operator on the unfrozen unknowns, inverted densely
+        std::vector<std::vector<double>> wi;
+        std::vector<double> valw;
+        const std::string e = c.topo->mesh_intact_operators(isf.data(), wi, valw);
+        if (!e.empty()) {
+            HIPCHK(hipStreamSynchronize(c.stream));
+            return fail(HHGR_EINVAL, e);
+        }
+        for (int l = c.Lc; l <= c.L && !rc; l++) rc = upload(c, c.lev[l].wi15_dn, wi[l].data(), wi[l].size() * sizeof(double));
+        std::vector<int> keep(cs.n, -1);
+        int nk = 0;
+        for (int q = 0; q < cs.n; q++)
+            if (!cf[q]) keep[q] = nk++;
+        std::vector<int> colk((size_t)nk * cs.cw, -1);
+        std::vector<double> valk((size_t)nk * cs.cw, 0.0);
+        for (int q = 0; q < cs.n; q++) {
+            if (keep[q] < 0) continue;
+            for (int e2 = 0; e2 < cs.cw; e2++) {
+                const int cq = cs.colw[(size_t)cs.cw * q + e2];
+                if (cq < 0 || keep[cq] < 0) continue;
+                colk[(size_t)cs.cw * keep[q] + e2] = keep[cq];
+                valk[(size_t)cs.cw * keep[q] + e2] = valw[(size_t)cs.cw * q + e2];
+            }
+        }
+        std::vector<double> inv, inv_full;
+        if (nk > 0 && !coarse_inverse(nk, cs.cw, colk, valk, inv)) {
+            HIPCHK(hipStreamSynchronize(c.stream));
+            return fail(HHGR_EINVAL, "the intact side's coarsest-level operator is not positive definite");
+        }
+        inv_full.assign((size_t)cs.n * cs.n, 0.0);
+        for (int q = 0; q < cs.n; q++)
+            for (int r = 0; r < cs.n; r++)
+                if (keep[q] >= 0 && keep[r] >= 0) inv_full[(size_t)q * cs.n + r] = inv[(size_t)keep[q] * nk + keep[r]];
+        rc = rc ? rc : upload(c, c.cinv_dd, inv_full.data(), inv_full.size() * sizeof(double));
+        // the copies read wi and inv_full
+        HIPCHK(hipStreamSynchronize(c.stream));
+        if (rc) return rc;
+    } else if (c.gen) {
         GenK G;
         G.kel = c.kel;
         G.faulty = c.dn_faulty;
@@ -1425,7 +1465,9 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     // static Neumann data from the data at the time of the fault (u_F plays
     // no part: its edges have zero intact-side weight)
     HIPCHK(hipMemcpyAsync(c.aux_b, F.b, F.n_slots * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-    if (c.gen)
+    if (c.mesh)
+        launch_neumann_rhs_w(c.stream, F.n_ifc, F.ifc_base, F.nb15, F.wi15_dn, F.nbw, F.gamma, F.u, c.aux_b);
+    else if (c.gen)
         launch_neumann_rhs15(c.stream, F.n_ifc, F.ifc_base, F.nb15, F.wi15_dn, F.gamma, F.u, c.aux_b);
     else
         launch_neumann_rhs(c.stream, F.n_ifc, F.ifc_base, F.nbr, F.wi_dn, F.gamma, F.u, c.aux_b);
@@ -1454,7 +1496,8 @@ HView<double> dn_view(hhgr_ctx &c) {
         v.gidx = D.gidx_dn;
     }
     V.lv[c.L].b = c.aux_b;
-    V.cval = c.gen ? c.cval15_dn : c.cval_dn;
+    // a mesh's intact-side coarsest level is the dense inverse of dn_setup
+    V.cval = c.mesh ? nullptr : c.gen ? c.cval15_dn : c.cval_dn;
     return V;
 }
 
@@ -2159,7 +2202,6 @@ int hhgr_recover_dd(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
 int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int eta) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (c->mesh) return fail(HHGR_EINVAL, "no Dirichlet-Neumann recovery on an unstructured macro mesh");
     std::vector<int> ft;
     rc = dd_check(*c, tets, n_tets, n_intact, eta, ft);
     if (rc) return rc;

@@ -242,6 +242,11 @@ void launch_mesh_slots_to_user(hipStream_t s, const VolGeom &vint, long long vba
 // other slots of b are left as they are
 void launch_dirichlet_rows(hipStream_t s, int nrows, const int *rows, const int *ptr, const int *col,
                            const double *val, const double *g, double *b);
+// unstructured macro meshes, Dirichlet-Neumann Neumann data: at the masters
+// flagged in gamma, b_out = sum over e < w of wi[e] u[nb[e]] (rows of width
+// w, entry e of master t at e n_ifc + t; mesh_kernels.hip)
+void launch_neumann_rhs_w(hipStream_t s, int n_ifc, long long base, const int *nb, const double *wi, int w,
+                          const unsigned char *gamma, const double *u, double *b_out);
 
 // user vector (global lexicographic interior order) <-> slot space; vfull
 // lists every closure node (ghosts receive the user value or the Dirichlet zero)

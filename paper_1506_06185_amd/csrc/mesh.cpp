@@ -146,6 +146,30 @@ void stiffness(const double e[3][3], double K[4][4]) {
         for (int b = 0; b < 4; b++) K[a][b] = vol * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
 }
 
+// stiffness (K) and mass |e| / 20 (Mq) of the 24 elements around a node of a
+// tetrahedron with corners tv refined to m intervals per edge (an element's
+// shape depends only on the tetrahedron and its place in the star)
+void star_matrices(const double *xyz, const int tv[4], int m, const std::vector<Around> &around, double K[24][4][4],
+                   double Mq[24]) {
+    double E[3][3];  // index-space unit steps in physical space
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) E[a][c] = (xyz[3 * tv[a + 1] + c] - xyz[3 * tv[0] + c]) / m;
+    for (int q = 0; q < 24; q++) {
+        const Around &A = around[q];
+        double x[4][3];
+        for (int r = 0; r < 4; r++)
+            for (int c = 0; c < 3; c++) x[r][c] = A.d[r][0] * E[0][c] + A.d[r][1] * E[1][c] + A.d[r][2] * E[2][c];
+        double e[3][3];
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) e[r][c] = x[r + 1][c] - x[0][c];
+        stiffness(e, K[q]);
+        const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                           e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+        Mq[q] = std::fabs(det) / 6.0 / 20.0;
+    }
+}
+
 inline long long binom3(long long p) { return p >= 3 ? p * (p - 1) * (p - 2) / 6 : 0; }
 
 // one entry of a master's row: slot, stiffness and mass value
@@ -244,6 +268,8 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         return false;
     };
 
+    mesh_xyz.assign(xyz, xyz + 3 * (size_t)nv_);
+    mesh_tets.assign(tets, tets + 4 * (size_t)nt);
     lev.assign(L + 1, TopoLevel());
     std::vector<std::unordered_map<NKey, int, NKeyHash>> kmap(L + 1);
     std::vector<std::vector<Master>> mrec(L + 1);
@@ -427,24 +453,8 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         auto &R = rows[l];
         R.assign(Lv.n_ifc, {});
         for (int t = 0; t < nt; t++) {
-            double E[3][3];  // index-space unit steps in physical space
-            for (int a = 0; a < 3; a++)
-                for (int c = 0; c < 3; c++) E[a][c] = (xyz[3 * tv[t][a + 1] + c] - xyz[3 * tv[t][0] + c]) / m;
             double K[24][4][4], Mq[24];  // stiffness; mass |e| / 20 (1 + delta)
-            for (int q = 0; q < 24; q++) {
-                const Around &A = around[q];
-                double x[4][3];
-                for (int r = 0; r < 4; r++)
-                    for (int c = 0; c < 3; c++) x[r][c] = A.d[r][0] * E[0][c] + A.d[r][1] * E[1][c] + A.d[r][2] * E[2][c];
-                double e[3][3];
-                for (int r = 0; r < 3; r++)
-                    for (int c = 0; c < 3; c++) e[r][c] = x[r + 1][c] - x[0][c];
-                stiffness(e, K[q]);
-                const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
-                                   e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
-                                   e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-                Mq[q] = std::fabs(det) / 6.0 / 20.0;
-            }
+            star_matrices(xyz, tv[t].data(), m, around, K, Mq);
             for (int q = 0; q < 24; q++) {
                 const Around &A = around[q];
                 for (int r = 0; r < 4; r++) {
@@ -686,6 +696,112 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
             for (int g = Lv.gptr[f]; g < Lv.gptr[f + 1]; g++) cs.cidx.push_back(Lv.gidx[g]);
         }
         cs.cptr[q + 1] = (int)cs.cidx.size();
+    }
+    return "";
+}
+
+std::string Topology::mesh_intact_operators(const unsigned char *faulty, std::vector<std::vector<double>> &wi,
+                                            std::vector<double> &valw) const {
+    if (!mesh) return "not an unstructured macro mesh";
+    const int nt = n_tets;
+    const std::vector<Around> around = elements_around();
+    if (around.size() != 24) return "internal: element star";
+    wi.assign(L + 1, {});
+    std::vector<int> cslot;
+    for (int l = Lc; l <= L; l++) {
+        const TopoLevel &Lv = lev[l];
+        const int m = Lv.m;
+        const size_t n = (size_t)Lv.n_ifc;
+        std::vector<double> &W = wi[l];
+        W = Lv.mesh_wi;
+        // masters with a copy in a faulty closure: their rows are summed
+        // again over the intact tetrahedra, in the order of build_mesh
+        std::vector<char> aff(n, 0);
+        for (int t = 0; t < nt; t++)
+            if (faulty[t])
+                for (int q = Lv.tg_ptr[t]; q < Lv.tg_ptr[t + 1]; q++)
+                    if (Lv.tg_src[q] != Lv.zero_slot) aff[Lv.tg_src[q] - Lv.ifc_base] = 1;
+        for (size_t f = 0; f < n; f++)
+            if (aff[f])
+                for (int e = 0; e < nbw; e++) W[e * n + f] = 0.0;
+        cslot.assign(Lv.C_pad, (int)Lv.zero_slot);
+        for (int t = 0; t < nt; t++) {
+            if (faulty[t]) continue;
+            bool touch = false;
+            for (int q = Lv.tg_ptr[t]; q < Lv.tg_ptr[t + 1] && !touch; q++)
+                touch = Lv.tg_src[q] != Lv.zero_slot && aff[Lv.tg_src[q] - Lv.ifc_base];
+            if (!touch) continue;
+            // closure slots: interior nodes in the closure, boundary nodes
+            // from the ghost list (built in the same plane, row, i order)
+            int g = Lv.tg_ptr[t];
+            for (int k = 0; k <= m; k++)
+                for (int j = 0; j <= m - k; j++)
+                    for (int i = 0; i <= m - k - j; i++) {
+                        const int idx = Lv.lay.index(i, j, k);
+                        if (i == 0 || j == 0 || k == 0 || i + j + k == m) {
+                            if (g >= Lv.tg_ptr[t + 1] || Lv.tg_dst[g] != (long long)t * Lv.C_pad + idx)
+                                return "internal: ghost list out of order";
+                            cslot[idx] = Lv.tg_src[g++];
+                        } else {
+                            cslot[idx] = (int)((long long)t * Lv.C_pad + idx);
+                        }
+                    }
+            double K[24][4][4], Mq[24];
+            star_matrices(mesh_xyz.data(), &mesh_tets[4 * (size_t)t], m, around, K, Mq);
+            for (int k = 0; k <= m; k++)
+                for (int j = 0; j <= m - k; j++)
+                    for (int i = 0; i <= m - k - j; i++) {
+                        if (!(i == 0 || j == 0 || k == 0 || i + j + k == m)) continue;
+                        const long long own = cslot[Lv.lay.index(i, j, k)];
+                        if (own == Lv.zero_slot || !aff[own - Lv.ifc_base]) continue;
+                        const size_t f = (size_t)(own - Lv.ifc_base);
+                        for (int q = 0; q < 24; q++) {
+                            const Around &A = around[q];
+                            int p[4][3];
+                            bool in = true;
+                            for (int r = 0; r < 4 && in; r++) {
+                                p[r][0] = i + A.d[r][0] - A.d[A.self][0];
+                                p[r][1] = j + A.d[r][1] - A.d[A.self][1];
+                                p[r][2] = k + A.d[r][2] - A.d[A.self][2];
+                                in = p[r][0] >= 0 && p[r][1] >= 0 && p[r][2] >= 0 && p[r][0] + p[r][1] + p[r][2] <= m;
+                            }
+                            if (!in) continue;
+                            for (int r = 0; r < 4; r++) {
+                                const int s = cslot[Lv.lay.index(p[r][0], p[r][1], p[r][2])];
+                                int e = 0;
+                                while (e < nbw && Lv.nb15[e * n + f] != s) e++;
+                                if (e == nbw) return "internal: intact-side entry outside the master's row";
+                                W[e * n + f] += K[q][A.self][r];
+                            }
+                        }
+                    }
+        }
+    }
+    // coarsest level: master rows from the intact entries, in the order of
+    // build_mesh; volume rows are unchanged (an interior node's elements lie
+    // in its own tetrahedron)
+    const TopoLevel &Lv = lev[Lc];
+    const CoarseSystem &cs = coarse;
+    const size_t n = (size_t)Lv.n_ifc;
+    std::vector<int> unk(Lv.n_slots, -1);
+    for (int q = 0; q < cs.n; q++) unk[cs.slot[q]] = q;
+    for (size_t q = 0; q < Lv.tg_dst.size(); q++)
+        if (Lv.tg_src[q] != Lv.zero_slot) unk[Lv.tg_dst[q]] = unk[Lv.tg_src[q]];
+    valw = cs.valw;
+    for (int q = 0; q < cs.n; q++) {
+        if (cs.is_vol[q]) continue;
+        const size_t f = (size_t)cs.ifc[q];
+        double *row = &valw[(size_t)cs.cw * q];
+        for (int e = 0; e < cs.cw; e++) row[e] = 0.0;
+        for (int e = 0; e < nbw; e++) {
+            const long long s = Lv.nb15[e * n + f];
+            const int c = s == Lv.zero_slot ? -1 : unk[s];
+            if (c < 0) continue;
+            int p = 0;
+            while (p < cs.cw && cs.colw[(size_t)cs.cw * q + p] != c) p++;
+            if (p == cs.cw) return "internal: intact-side coarse entry outside the row";
+            row[p] += wi[Lc][e * n + f];
+        }
     }
     return "";
 }

@@ -175,7 +175,17 @@ struct Topology {
     // in plane k, row j, i order.  Fills the stencils and the coarsest-level
     // rows too.  Returns an empty string on success, else the error.
     std::string build_mesh(int nv, const double *xyz, int nt, const int *tets, int L, int Lc);
+    // Intact side of a Dirichlet-Neumann recovery on a mesh (Sec. 4.3,
+    // eq. (5)): the master rows of every level summed over the elements of
+    // the tetrahedra not flagged in faulty (wi[l], the layout of mesh_wi:
+    // rows of masters no faulty closure holds are mesh_wi's own), and the
+    // coarsest-level rows over the same elements (valw, the layout of
+    // coarse.valw).  Returns an empty string on success, else the error.
+    std::string mesh_intact_operators(const unsigned char *faulty, std::vector<std::vector<double>> &wi,
+                                      std::vector<double> &valw) const;
     bool mesh = false;
+    std::vector<double> mesh_xyz;  // the mesh's vertices (3 each) and tetrahedra (4 vertex ids each)
+    std::vector<int> mesh_tets;
     int nbw = 15;  // interface stencil and restriction width
     long long n_dofs = 0;
     // finest level of a mesh: the Dirichlet boundary nodes (their order: the

@@ -5,8 +5,12 @@
 // independent assembly.  Also checks internal invariants and exits nonzero
 // when one fails.
 //
-// usage: mesh_check <mesh file> <output file>
+// usage: mesh_check <mesh file> <output file> [faulty tet ids, comma-separated]
 // mesh file: "nv nt L Lc", then nv lines "x y z", then nt lines "a b c d"
+// With faulty tetrahedra it also writes the intact side of a
+// Dirichlet-Neumann recovery: per level the operator of the intact volume
+// stencils and the intact master rows ("I"), and the coarsest-level rows over
+// the intact elements ("C").
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -37,7 +41,7 @@ static long long rank_enum(int m, int i0, int j0, int k0) {
 }
 
 int main(int argc, char **argv) {
-    if (argc != 3) return 2;
+    if (argc != 3 && argc != 4) return 2;
     FILE *f = std::fopen(argv[1], "r");
     if (!f) return 2;
     int nv, nt, L, Lc;
@@ -155,6 +159,64 @@ int main(int argc, char **argv) {
                 for (int c = 0; c < 3; c++) std::fprintf(o, "%lld %d %.17g\n", q, c, tp.bnd_xyz[3 * q + c]);
             std::fprintf(o, "end\n");
         }
+    }
+    if (argc == 4) {
+        std::vector<unsigned char> faulty(nt, 0);
+        for (const char *c = argv[3]; *c;) {
+            char *end;
+            const long t = std::strtol(c, &end, 10);
+            if (end == c || t < 0 || t >= nt) return 2;
+            faulty[t] = 1;
+            c = *end == ',' ? end + 1 : end;
+        }
+        std::vector<std::vector<double>> wi;
+        std::vector<double> valw;
+        e = tp.mesh_intact_operators(faulty.data(), wi, valw);
+        if (!e.empty()) {
+            std::printf("error: %s\n", e.c_str());
+            return 4;
+        }
+        for (int l = Lc; l <= L; l++) {
+            const TopoLevel &Lv = tp.lev[l];
+            const int m = Lv.m;
+            const std::vector<long long> &U = user_of[l];
+            std::fprintf(o, "I %d\n", l);
+            for (int t = 0; t < nt; t++) {
+                if (faulty[t]) continue;
+                for (int k = 1; k < m; k++)
+                    for (int j = 1; j < m; j++)
+                        for (int i = 1; i + j + k <= m - 1; i++) {
+                            const long long r = U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)];
+                            for (int n = 0; n < 15; n++) {
+                                const long long c = U[(long long)t * Lv.C_pad +
+                                                      Lv.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2])];
+                                if (c >= 0) std::fprintf(o, "%lld %lld %.17g\n", r, c, Lv.mesh_w15[15 * (size_t)t + n]);
+                            }
+                        }
+            }
+            // unaffected master rows must be the full rows, bit for bit
+            for (int q = 0; q < Lv.n_ifc; q++) {
+                bool touched = false;
+                for (int g = Lv.gptr[q]; g < Lv.gptr[q + 1]; g++) touched |= faulty[Lv.gidx[g] / Lv.C_pad] != 0;
+                for (int n = 0; n < tp.nbw; n++) {
+                    const size_t at = (size_t)n * Lv.n_ifc + q;
+                    if (!touched) CHECK(wi[l][at] == Lv.mesh_wi[at]);
+                    const long long c = U[Lv.nb15[at]];
+                    if (c >= 0) std::fprintf(o, "%d %lld %.17g\n", Lv.ifc_dof[q], c, wi[l][at]);
+                }
+            }
+            std::fprintf(o, "end\n");
+        }
+        const CoarseSystem &cs = tp.coarse;
+        std::fprintf(o, "C %d\n", Lc);
+        for (int q = 0; q < cs.n; q++)
+            for (int e2 = 0; e2 < cs.cw; e2++) {
+                const int c = cs.colw[(size_t)cs.cw * q + e2];
+                if (c >= 0)
+                    std::fprintf(o, "%lld %lld %.17g\n", user_of[Lc][cs.slot[q]], user_of[Lc][cs.slot[c]],
+                                 valw[(size_t)cs.cw * q + e2]);
+            }
+        std::fprintf(o, "end\n");
     }
     // interface rows of the transfers: P (fine master <- coarse parents) and
     // R = P^T (coarse master <- its fine twin and the neighbours at 1/2)

@@ -184,7 +184,7 @@ def test_mesh_context_rejects_unsupported_calls(dev, hh):
     n = ctx.n_dofs
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     ctx.set_rhs(x + 1.0, hh.HHGR_RHS_LOAD)
-    for call in (lambda: ctx.recover_dn([1], 1, 1), lambda: ctx.autotune(), lambda: ctx.set_fused_sweeps(4, True)):
+    for call in (lambda: ctx.autotune(), lambda: ctx.set_fused_sweeps(4, True)):
         with pytest.raises(hh.HHGRError) as e:
             call()
         assert e.value.code == hh.HHGR_EINVAL
@@ -256,6 +256,33 @@ def test_mesh_dirichlet_dirichlet_recovery(dev, hh, precision):
         ctx.solve(rel_tol=1e-11, max_cycles=60)
         uo, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
         assert rel(Nn(ctx.get_solution()), uo) < 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,level,faults", [("box222p", 4, (4, 5)), ("octa8", 4, (0,)), ("octa4", 5, (3,))])
+def test_mesh_dirichlet_neumann_recovery(dev, hh, name, level, faults):
+    """Alg. 2 on an unstructured mesh: the intact side cycles on the Neumann
+    problem of eq. (5) (master rows over the elements of intact tetrahedra,
+    the intact coarsest level through its own dense inverse), the faulty
+    side runs local Dirichlet cycles; against the oracle's rounds per iterate,
+    then plain cycles."""
+    print(f"\n[mesh dn] {name} level={level} faults={faults}", flush=True)
+    p = problem(name, level)
+    ctx = context(hh, dev, name, level, max_faults=2)
+    b = np.random.default_rng(37).uniform(-1, 1, p.ndof)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(None)
+    ctx.vcycle(3)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=3)
+    for t in faults:
+        ctx.inject_fault(t)
+        u = p.inject_fault(t, u)
+    ctx.recover_dn(list(faults), 3, 2)
+    u = p.dn_recover(list(faults), u, b, n_intact=3, eta=2)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    ctx.vcycle(2)
+    u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=2)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
     ctx.close()
 
 

@@ -29,7 +29,7 @@ def mesh_check(tmp_path_factory):
     return exe
 
 
-def run(exe, tmp_path, v, t, L, Lc):
+def run(exe, tmp_path, v, t, L, Lc, faults=None):
     mf, of = str(tmp_path / "mesh.txt"), str(tmp_path / "out.txt")
     with open(mf, "w") as fh:
         fh.write(f"{len(v)} {len(t)} {L} {Lc}\n")
@@ -37,7 +37,8 @@ def run(exe, tmp_path, v, t, L, Lc):
             fh.write("%.17g %.17g %.17g\n" % tuple(x))
         for q in t:
             fh.write("%d %d %d %d\n" % tuple(q))
-    out = subprocess.run([exe, mf, of], capture_output=True, text=True)
+    extra = [",".join(str(q) for q in faults)] if faults else []
+    out = subprocess.run([exe, mf, of] + extra, capture_output=True, text=True)
     return out, of
 
 
@@ -127,3 +128,29 @@ def test_mesh_topology_rejects_bad_meshes(mesh_check, tmp_path):
     flat[:, 2] = 0.0
     out, _ = run(mesh_check, tmp_path, flat, t, 3, 2)
     assert out.returncode == 3 and "flat" in out.stdout
+
+
+@pytest.mark.parametrize("name,faults", [("box222p", (1,)), ("box222p", (2, 9)), ("octa8", (0, 5)), ("octa4", (3,))])
+def test_mesh_intact_side_equals_oracle(name, faults, mesh_check, tmp_path):
+    """The intact side of a Dirichlet-Neumann recovery (Sec. 4.3, eq. (5)):
+    the master rows summed over the elements of intact tetrahedra only, on
+    every level, and the coarsest-level operator built from them, against the
+    oracle's assembly over the intact elements."""
+    v, t = MESHES[name]()
+    L, Lc = 4, 2
+    out, of = run(mesh_check, tmp_path, v, t, L, Lc, faults)
+    assert out.returncode == 0, out.stdout + out.stderr
+    head, mats = parse(of)
+    p = oracle.MeshProblem(v, t, L, Lc)
+    for l in range(Lc, L + 1):
+        n = p.ndof_at(l)
+        I = to_csr(mats[("I", l)], (n, n))
+        Io = p.side_matrix(l, list(faults), "intact")
+        assert abs(I - Io).max() <= 1e-13 * abs(Io).max(), (l, abs(I - Io).max())
+    n = p.ndof_at(Lc)
+    C = to_csr(mats[("C", Lc)], (n, n))
+    Co = p.side_matrix(Lc, list(faults), "intact").tocsr()
+    keep = Co.diagonal() > 0
+    assert keep.sum() < n
+    assert abs(C[keep][:, keep] - Co[keep][:, keep]).max() <= 1e-13 * abs(Co).max()
+    assert abs(C[keep][:, ~keep]).max() == 0.0
