@@ -165,7 +165,7 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * computed on the host for each fault set), hhgr_recover_dn (the intact
  * side's master rows summed over the elements of intact tetrahedra and its
  * coarsest level inverted densely, both on the host for each fault set;
- * eq. (5)), hhgr_set_graph,
+ * eq. (5)), hhgr_set_graph, the hhgr_batch_* calls,
  * hhgr_kernel_timing/stats and hhgr_debug_op (ops 0, 3 to 5, 7, 8 + class
  * mask); every other call returns EINVAL for it.  hhgr_sizes reports the
  * interior unknowns, nt and nt 8^level.  EINVAL for a mesh that is not
@@ -290,7 +290,8 @@ int hhgr_mass_apply(hhgr_ctx *ctx, const double *dev_x, double *dev_y);
  * right-hand side) run their V-cycles as concurrent branches of captured HIP
  * graphs on hip_stream, one graph launch per step of all members; every
  * member stops at its own tolerance.  The batch borrows the contexts (each at
- * most once).  reps: one report per member (may be NULL).
+ * most once); members may be cube, general or unstructured-mesh contexts.
+ * reps: one report per member (may be NULL).
  *
  * hhgr_batch_arm_dd arms a Dirichlet-Dirichlet recovery (Sec. 4.2, Alg. 1)
  * of the listed faulty tetrahedra of one member (after hhgr_inject_fault on

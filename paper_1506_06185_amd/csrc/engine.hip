@@ -2739,7 +2739,6 @@ int hhgr_batch_create(hhgr_ctx **ctxs, int n, void *hip_stream, hhgr_batch **out
     if (!ctxs || n < 1) return fail(HHGR_EINVAL, "need at least one member");
     for (int q = 0; q < n; q++) {
         if (!ctxs[q]) return fail(HHGR_EINVAL, "null member");
-        if (ctxs[q]->mesh) return fail(HHGR_EINVAL, "batches take cube contexts only");
         for (int p = 0; p < q; p++)
             if (ctxs[p] == ctxs[q]) return fail(HHGR_EINVAL, "a context appears twice in the batch");
     }

@@ -286,6 +286,19 @@ int main() {
         CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_OK, "mesh vcycle after dd");
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_OK, "mesh dn: %s", hhgr_last_error());
         CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_OK, "mesh vcycle after dn");
+        {
+            // a batch of the mesh member (armed DD) and a cube member
+            hhgr_ctx *bm[2] = {g, cs[1].h};
+            hhgr_batch *mb = nullptr;
+            CHECK(hhgr_batch_create(bm, 2, nullptr, &mb) == HHGR_OK, "mesh batch: %s", hhgr_last_error());
+            CHECK(hhgr_inject_fault(g, 1) == HHGR_OK && hhgr_inject_fault(g, 6) == HHGR_OK, "mesh batch faults");
+            CHECK(hhgr_batch_arm_dd(mb, 0, t2, 2, 2, 3) == HHGR_OK, "mesh batch arm: %s", hhgr_last_error());
+            std::vector<double> h0(8), h1(8);
+            hhgr_report mr[2] = {{0, 0.0, h0.data(), 8}, {0, 0.0, h1.data(), 8}};
+            const int mrc = hhgr_batch_run(mb, 1e-10, 4, mr);
+            CHECK(mrc == HHGR_OK || mrc == HHGR_ENOCONV, "mesh batch run: %d %s", mrc, hhgr_last_error());
+            hhgr_batch_destroy(mb);
+        }
         CHECK(hhgr_mass_apply(g, v.data(), w.data()) == HHGR_OK, "mesh mass: %s", hhgr_last_error());
         CHECK(hhgr_adjoint_grad(g, v.data(), 1e-10, 5, w.data(), nullptr) == HHGR_ENOCONV, "mesh adjoint: %s",
               hhgr_last_error());
@@ -303,9 +316,6 @@ int main() {
         CHECK(hhgr_debug_op(g, 5, 4, v.data(), v.data(), w.data()) == HHGR_OK, "mesh prolong op");
         CHECK(hhgr_debug_op(g, 7, 2, v.data(), v.data(), w.data()) == HHGR_OK, "mesh dense coarse op");
         CHECK(hhgr_debug_op(g, 6, 2, v.data(), v.data(), w.data()) == HHGR_EINVAL, "mesh pcg op rejected");
-        hhgr_ctx *pair[2] = {g, cs[1].h};
-        hhgr_batch *gb = nullptr;
-        CHECK(hhgr_batch_create(pair, 2, nullptr, &gb) == HHGR_EINVAL, "mesh batch rejected");
         hhgr_destroy(g);
         std::free(ws);
         d.precision = HHGR_MIXED;

@@ -286,6 +286,51 @@ def test_mesh_dirichlet_neumann_recovery(dev, hh, name, level, faults):
     ctx.close()
 
 
+def test_mesh_members_in_a_batch(dev, hh):
+    """A batch (concurrent graph branches) of a mesh member with an armed
+    Dirichlet-Dirichlet recovery, a plain mesh member and a cube member
+    equals the oracle run member by member: same cycle counts, solutions to
+    1e-12 (the iterates agree cycle by cycle)."""
+    print("\n[mesh batch]", flush=True)
+    members = [
+        dict(ctx=context(hh, dev, "box222p", 4), p=problem("box222p", 4), pre=3, dd=([4, 5], 2, 3)),
+        dict(ctx=context(hh, dev, "octa4", 5), p=problem("octa4", 5), pre=0, dd=None),
+        dict(ctx=hh.Context(device=dev, n_sub=1, level=5), p=oracle.Problem(1, 5), pre=0, dd=None),
+    ]
+    for q, m in enumerate(members):
+        m["b"] = np.random.default_rng(740 + q).uniform(-1.0, 1.0, m["p"].ndof)
+        m["ctx"].set_rhs(T(m["b"], dev), hh.HHGR_RHS_LOAD)
+        m["ctx"].set_solution(None)
+        if m["pre"]:
+            m["ctx"].vcycle(m["pre"])
+        if m["dd"]:
+            for t in m["dd"][0]:
+                m["ctx"].inject_fault(t)
+    batch = hh.Batch([m["ctx"] for m in members])
+    for q, m in enumerate(members):
+        if m["dd"]:
+            batch.arm_dd(q, *m["dd"])
+    out = batch.run(1e-10, 80)
+    for q, m in enumerate(members):
+        p, bb = m["p"], m["b"]
+        bn = float(np.linalg.norm(bb))
+        u = p.solve(bb, rtol=0.0, max_cycles=m["pre"])[0] if m["pre"] else np.zeros_like(bb)
+        done = 0
+        if m["dd"]:
+            tets, n_i, n_f = m["dd"]
+            for t in tets:
+                u = p.inject_fault(t, u)
+            u = p.dd_intact(tets, u, bb, n_i)
+            u, _ = p.recover_local(tets, u, bb, n_f)
+            done = n_i
+        u, co, _ = p.solve(bb, u0=u, rtol=1e-10, max_cycles=80 - done, r0=bn)
+        assert out[q][0] == co + done, (q, out[q][0], co, done)
+        assert rel(Nn(m["ctx"].get_solution()), u) < 1e-12, q
+    batch.close()
+    for m in members:
+        m["ctx"].close()
+
+
 def test_mesh_mass_matrix_nodal_source_and_adjoint(dev, hh):
     """The consistent P1 mass matrix on an unstructured mesh (per-tetrahedron
     and per-master rows): its action, b = M f from nodal values of f, and the
