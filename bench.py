@@ -350,7 +350,7 @@ def leg_vcycle_rates(hh, torch, dev, tune_cache, n_sub=2, levels=(5, 6, 7), cycl
     return out
 
 
-def leg_mesh(hh, torch, dev, steps, warmup, graph, nx=3, level=7):
+def leg_mesh(hh, torch, dev, steps, warmup, graph, tune_cache, nx=3, level=7):
     """The fault job on an unstructured macro mesh: the box [0, nx]^3 of unit
     cubes split into 5 tetrahedra each (vertices moved by 0.12 U[-1,1]^3,
     seed 0), per-master stencils, 4-colour SOR, load b ~ U[-1,1]: 5 cycles,
@@ -368,6 +368,7 @@ def leg_mesh(hh, torch, dev, steps, warmup, graph, nx=3, level=7):
         t0 = time.perf_counter()
         ctx = hh.Context(device=dev, mesh=(v, t), level=level, precision=precision)
         t_setup = time.perf_counter() - t0
+        ctx.autotune(tune_cache)
         if graph:
             ctx.set_graph(True)
         g = torch.Generator().manual_seed(0)
@@ -724,7 +725,7 @@ def main():
     if not args.no_mesh:
         log("unstructured macro mesh leg")
         t1 = time.perf_counter()
-        mesh = leg_mesh(hh, torch, dev, args.steps, args.warmup, args.graph)
+        mesh = leg_mesh(hh, torch, dev, args.steps, args.warmup, args.graph, tune_cache)
         log(f"unstructured macro mesh leg done in {time.perf_counter() - t1:.1f} s")
     extra = {}
     if not args.no_extra:

@@ -165,7 +165,9 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * computed on the host for each fault set), hhgr_recover_dn (the intact
  * side's master rows summed over the elements of intact tetrahedra and its
  * coarsest level inverted densely, both on the host for each fault set;
- * eq. (5)), hhgr_set_graph, the hhgr_batch_* calls,
+ * eq. (5)), hhgr_set_graph, the hhgr_batch_* calls, hhgr_autotune (the
+ * class pass, as on a general mesh; cache entries keyed by a hash of the
+ * vertex and tetrahedron lists),
  * hhgr_kernel_timing/stats and hhgr_debug_op (ops 0, 3 to 5, 7, 8 + class
  * mask); every other call returns EINVAL for it.  hhgr_sizes reports the
  * interior unknowns, nt and nt 8^level.  EINVAL for a mesh that is not

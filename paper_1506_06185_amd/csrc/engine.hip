@@ -579,6 +579,7 @@ std::string get_mesh_topology(int nv, const double *xyz, int nt, const int *tets
     std::string err = t->build_mesh(nv, xyz, nt, tets, L, Lc);
     if (!err.empty()) return err;
     if (t->coarse.n > kDenseCoarseMaxMesh) return "the coarsest level has more unknowns than the dense solver takes";
+    t->mesh_hash = h;
     std::lock_guard<std::mutex> g(mu);
     cache.push_back({key, t});
     if (cache.size() > 4) cache.erase(cache.begin());
@@ -2396,7 +2397,6 @@ int hhgr_kernel_stats(hhgr_ctx *c, long long *launches, double *mean_ms, double 
 
 int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
     if (!c) return fail(HHGR_EINVAL, "null context");
-    if (c->mesh) return fail(HHGR_EINVAL, "no autotuning on an unstructured macro mesh (default launch shapes)");
     if (c->gen && !c->geom_set) return fail(HHGR_ESTATE, "no geometry set");
     hipDeviceProp_t prop;
     int dev = 0;
@@ -2419,6 +2419,7 @@ int hhgr_autotune(hhgr_ctx *c, const char *cache_path) {
         std::ostringstream ks;
         ks << devname << ":n" << c->d.n_sub << ":l" << l << ":" << (c->mixed ? "f32" : "f64") << ":vk" << c->vk
            << (c->gen ? ":g15" : "");
+        if (c->mesh) ks << ":mesh" << std::hex << c->topo->mesh_hash << std::dec << ":t" << c->n_tets;
         auto it = cache.find(ks.str());
         auto itr = cache.find(ks.str() + ":remap");
         auto itc = cache.find(ks.str() + ":cpb");

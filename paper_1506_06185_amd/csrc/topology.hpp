@@ -184,6 +184,7 @@ struct Topology {
     std::string mesh_intact_operators(const unsigned char *faulty, std::vector<std::vector<double>> &wi,
                                       std::vector<double> &valw) const;
     bool mesh = false;
+    unsigned long long mesh_hash = 0;  // hash of the vertex and tetrahedron lists (set by the engine)
     std::vector<double> mesh_xyz;  // the mesh's vertices (3 each) and tetrahedra (4 vertex ids each)
     std::vector<int> mesh_tets;
     int nbw = 15;  // interface stencil and restriction width

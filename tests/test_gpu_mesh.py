@@ -184,7 +184,7 @@ def test_mesh_context_rejects_unsupported_calls(dev, hh):
     n = ctx.n_dofs
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     ctx.set_rhs(x + 1.0, hh.HHGR_RHS_LOAD)
-    for call in (lambda: ctx.autotune(), lambda: ctx.set_fused_sweeps(4, True)):
+    for call in (lambda: ctx.set_fused_sweeps(4, True),):
         with pytest.raises(hh.HHGRError) as e:
             call()
         assert e.value.code == hh.HHGR_EINVAL
@@ -284,6 +284,27 @@ def test_mesh_dirichlet_neumann_recovery(dev, hh, name, level, faults):
     u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=2)
     assert rel(Nn(ctx.get_solution()), u) < 1e-12
     ctx.close()
+
+
+def test_mesh_autotune_keeps_the_iterates(dev, hh):
+    """The autotuned launch shapes of the class pass change no iterate: every
+    node's update is independent of the workgroup that runs it (the cycle's
+    norm is summed per workgroup, so it may change by rounding only)."""
+    name, level = "octa4", 5
+    print(f"\n[mesh autotune] {name} level={level}", flush=True)
+    b = np.random.default_rng(43).uniform(-1, 1, problem(name, level).ndof)
+    out = []
+    for tune in (False, True):
+        ctx = context(hh, dev, name, level)
+        if tune:
+            ctx.autotune()
+        ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+        ctx.set_solution(None)
+        rr = ctx.vcycle(3)
+        out.append((Nn(ctx.get_solution()), rr))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[1][1] == pytest.approx(out[0][1], rel=1e-12)
 
 
 def test_mesh_members_in_a_batch(dev, hh):
