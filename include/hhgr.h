@@ -248,8 +248,11 @@ int hhgr_inject_fault(hhgr_ctx *ctx, int tet);
  * tetrahedron's interior on every level for A_FF u_F = f_F - A_FG u_G (a
  * Dirichlet problem; coarsest level: one unknown, solved exactly).
  * local_rel_res_out (optional) receives the local residual relative to the
- * local right-hand side.  ESTATE without a right-hand side or with
- * coarse_level != 2. */
+ * local right-hand side.  The restore, the residuals and the cycles run as
+ * one captured HIP graph, captured on the first call for a (tet, n_cycles)
+ * pair and replayed while later calls repeat that pair (calls that change
+ * launch shapes or run other recoveries drop it).  ESTATE without a
+ * right-hand side or with coarse_level != 2. */
 int hhgr_recover_local(hhgr_ctx *ctx, int tet, int n_cycles, double *local_rel_res_out);
 
 /* Dirichlet-Dirichlet recovery (Alg. 1): for the listed faulty tetrahedra,

@@ -222,6 +222,12 @@ struct hhgr_ctx {
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;
     bool graph_ok = false;
+    // local recovery: its kernels are small enough that launching them one
+    // by one leaves the GPU waiting for the host, so its cycles replay a
+    // captured graph, kept for one (tetrahedron, cycle count)
+    hipGraphExec_t lgexec = nullptr;
+    int lg_tet = -1, lg_n = -1;
+    std::vector<int> loc_tets;  // the tetrahedra whose local hierarchy vd_loc holds
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tev;
@@ -1154,6 +1160,9 @@ void invalidate_graph(hhgr_ctx &c) {
     if (c.gexec) hipGraphExecDestroy(c.gexec);
     c.gexec = nullptr;
     c.graph_ok = false;
+    if (c.lgexec) hipGraphExecDestroy(c.lgexec);
+    c.lgexec = nullptr;
+    c.lg_tet = c.lg_n = -1;
 }
 
 // enqueue one global step (FP64 cycle or mixed refinement step) ending with
@@ -1196,19 +1205,22 @@ void prime_mixed(hhgr_ctx &c, hipStream_t s) {
 }
 
 void set_loc(hhgr_ctx &c, const std::vector<int> &tets) {
+    if (tets == c.loc_tets) return;  // vd_loc already holds them
+    std::vector<std::vector<VolDesc>> h(c.L + 1);
     for (int l = c.Lc; l <= c.L; l++) {
         LevelDev &D = c.lev[l];
-        std::vector<VolDesc> h(tets.size());
+        h[l].resize(tets.size());
         for (size_t f = 0; f < tets.size(); f++) {
-            h[f].vec = (l == c.L ? (long long)tets[f] : (long long)f) * D.C_pad;
-            h[f].w = (long long)tets[f] * D.C_pad;
-            h[f].tet = tets[f];
-            h[f].pad = 0;
+            h[l][f].vec = (l == c.L ? (long long)tets[f] : (long long)f) * D.C_pad;
+            h[l][f].w = (long long)tets[f] * D.C_pad;
+            h[l][f].tet = tets[f];
+            h[l][f].pad = 0;
         }
-        hipMemcpyAsync(D.vd_loc, h.data(), h.size() * sizeof(VolDesc), hipMemcpyHostToDevice, c.stream);
-        hipStreamSynchronize(c.stream);
+        hipMemcpyAsync(D.vd_loc, h[l].data(), h[l].size() * sizeof(VolDesc), hipMemcpyHostToDevice, c.stream);
         D.n_loc = (int)tets.size();
     }
+    hipStreamSynchronize(c.stream);  // the copies read h
+    c.loc_tets = tets;
 }
 
 // restore ghost copies of tet t on the finest level from the interface masters,
@@ -1891,6 +1903,7 @@ void hhgr_destroy(hhgr_ctx *c) {
     if (c->ev_join) hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->tev) hipEventDestroy(e);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->lgexec) hipGraphExecDestroy(c->lgexec);
     if (c->hnorm && c->hnorm != c->hnorm_local) hipHostFree(c->hnorm);
     delete c;
 }
@@ -2163,11 +2176,34 @@ int hhgr_recover_local(hhgr_ctx *c, int tet, int n_cycles, double *local_rel) {
     if (c->d.max_faults < 1) return fail(HHGR_ESTATE, "context created with max_faults = 0");
     if (c->Lc != 2) return fail(HHGR_ESTATE, "local recovery needs coarse_level = 2 (one unknown per tetrahedron)");
     set_loc(*c, {tet});
-    restore_tet(*c, tet, c->stream);
-    HView<double> V = local_view(*c, 0);
-    finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm + 2);
-    for (int q = 0; q < n_cycles; q++) vcycle<double>(*c, V, c->L, false, c->stream);
-    finest_residual<double>(*c, V, (double *)nullptr, c->stream, c->dnorm + 3);
+    // restored ghosts, the local residual before and after the cycles
+    auto enqueue = [&](hipStream_t s) {
+        restore_tet(*c, tet, s);
+        HView<double> V = local_view(*c, 0);
+        finest_residual<double>(*c, V, (double *)nullptr, s, c->dnorm + 2);
+        for (int q = 0; q < n_cycles; q++) vcycle<double>(*c, V, c->L, false, s);
+        finest_residual<double>(*c, V, (double *)nullptr, s, c->dnorm + 3);
+    };
+    if (!c->cap) {
+        enqueue(c->stream);  // a context without a capture stream
+    } else if (!(c->lgexec && c->lg_tet == tet && c->lg_n == n_cycles)) {
+        if (c->lgexec) hipGraphExecDestroy(c->lgexec);
+        c->lgexec = nullptr;
+        c->lg_tet = c->lg_n = -1;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+        enqueue(c->cap);
+        HIPCHK(hipStreamEndCapture(c->cap, &g));
+        hipError_t e = hipGraphInstantiate(&c->lgexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->lgexec = nullptr;
+            return fail(HHGR_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        c->lg_tet = tet;
+        c->lg_n = n_cycles;
+    }
+    if (c->lgexec) HIPCHK(hipGraphLaunch(c->lgexec, c->stream));
     CHKLAUNCH();
     double r0, r1;
     rc = read_norm(*c, 2, &r0);

@@ -246,6 +246,40 @@ def test_fault_and_local_recovery(dev, hh, oracle_problem):
     ctx.close()
 
 
+def test_local_recovery_graph_reuse(dev, hh, oracle_problem):
+    """The local recovery cycles replay a captured graph kept for one
+    (tetrahedron, cycle count): a repeated recovery replays it, another
+    tetrahedron or count captures anew, and a Dirichlet-Dirichlet recovery
+    in between (another local hierarchy, graphs dropped) leaves the next
+    local recovery right; every step against the oracle per iterate."""
+    n_sub, level = 2, 4
+    print("\n[local recovery graph reuse]", flush=True)
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    p = oracle_problem(n_sub, level)
+    b = inputs.uniform_load(n_sub, level, seed=8)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.vcycle(2)
+    u, _, _ = p.solve(b, rtol=0.0, max_cycles=2)
+    t1, t2 = 25, 7
+    steps = [("lr", t1, 3), ("lr", t1, 3), ("lr", t2, 3), ("lr", t2, 2), ("dd", t1, 2), ("lr", t1, 3), ("lr", t2, 2)]
+    for kind, t, n in steps:
+        ctx.inject_fault(t)
+        u = p.inject_fault(t, u)
+        if kind == "lr":
+            lr = ctx.recover_local(t, n)
+            u, res = p.recover_local(t, u, b, n_cycles=n)
+            assert lr == pytest.approx(res[-1], rel=1e-8), (kind, t, n)
+        else:
+            ctx.recover_dd([t], 1, n)
+            u = p.dd_intact([t], u, b, 1)
+            u, _ = p.recover_local([t], u, b, n)
+        assert rel(N(ctx.get_solution()), u) < 1e-12, (kind, t, n)
+        ctx.vcycle(1)
+        u, _, _ = p.solve(b, u0=u, rtol=0.0, max_cycles=1)
+        assert rel(N(ctx.get_solution()), u) < 1e-12, (kind, t, n)
+    ctx.close()
+
+
 @pytest.mark.parametrize("vk", [False, True])
 def test_fault_then_plain_cycles(dev, hh, vk):
     # the do-nothing strategy (Sec. 2.2): cycles continue right after the
