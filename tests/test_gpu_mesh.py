@@ -388,7 +388,8 @@ def test_mesh_full_size_properties(dev, hh):
     operator is symmetric and positive on random vectors (x.Ay = y.Ax to
     1e-12, x.Ax > 0), and after a solve to 1e-12 a fault followed by enough
     local recovery cycles restores the solution (the local Dirichlet problem
-    with exact interface data has the global solution as its solution)."""
+    with exact interface data has the global solution as its solution), and
+    so do the Dirichlet-Dirichlet and Dirichlet-Neumann recoveries."""
     v, t = inputs.box_mesh(3, 3, 3)
     v = inputs.perturb_mesh(v, seed=0, amplitude=0.12)
     level = 7
@@ -415,6 +416,16 @@ def test_mesh_full_size_properties(dev, hh):
     du = float(torch.linalg.norm(ctx.get_solution() - u) / torch.linalg.norm(u))
     print(f"solve: {cyc} cycles to {relres:.2e}; after fault + 30 local cycles: rel change {du:.2e}, local {lr:.2e}")
     assert du < 1e-9
+    # the same for the other two recoveries: with exact interface data the
+    # intact side stays at the solution (frozen closure, or Neumann data
+    # A^I u of eq. (5)) and the faulty side's local cycles converge to it
+    for name, recover in (("dd", lambda: ctx.recover_dd([tet], 2, 30)), ("dn", lambda: ctx.recover_dn([tet], 4, 8))):
+        ctx.set_solution(u)
+        ctx.inject_fault(tet)
+        recover()
+        du = float(torch.linalg.norm(ctx.get_solution() - u) / torch.linalg.norm(u))
+        print(f"after fault + {name} recovery: rel change {du:.2e}")
+        assert du < 1e-9, name
     ctx.close()
 
 
