@@ -91,6 +91,7 @@ def lib():
         "ohhg_side_matrix": (_vp, [_vp, C.c_int, _ip, C.c_int, C.c_int]),
         "ohhg_grad_k": (None, [_vp, _dp, _dp, _dp]),
         "ohhg_create_mesh": (_vp, [C.c_int, _dp, C.c_int, _ip, C.c_int, C.c_int]),
+        "ohhg_create_mesh_k": (_vp, [C.c_int, _dp, C.c_int, _ip, C.c_int, C.c_int, _dp]),
         "ohhg_mesh_nodes": (C.c_longlong, [_vp, C.c_int, _dp, _lp]),
         "ohhg_mesh_keys": (None, [_vp, C.c_int, _ip]),
     }
@@ -411,9 +412,12 @@ class MeshProblem(Problem):
     id, then edges (a < b) by the weight of b, faces (a < b < c) by the weight
     of c then b, tetrahedron interiors by tet id and the weights of the
     tetrahedron's vertices 3, 2, 1.
+
+    ``k_tet`` (optional, one value > 0 per macro tetrahedron): the coefficient
+    k of eq. (2), constant on each macro tetrahedron (on every level).
     """
 
-    def __init__(self, vertices, tets, level: int, coarse_level: int = 2):
+    def __init__(self, vertices, tets, level: int, coarse_level: int = 2, k_tet=None):
         self._xyz = _f64(vertices).reshape(-1)
         self._tets = np.ascontiguousarray(np.asarray(tets, dtype=np.int32).reshape(-1))
         self.nv, self.n_tets = self._xyz.size // 3, self._tets.size // 4
@@ -421,10 +425,14 @@ class MeshProblem(Problem):
             raise ValueError("vertices must be (nv, 3) and tets (nt, 4)")
         self.level, self.coarse_level = int(level), int(coarse_level)
         self.n_sub, self.general, self._k = None, True, None
-        self._h = lib().ohhg_create_mesh(self.nv, _d(self._xyz), self.n_tets, self._tets.ctypes.data_as(_ip),
-                                         self.level, self.coarse_level)
+        self.k_tet = None if k_tet is None else _f64(k_tet)
+        if self.k_tet is not None and self.k_tet.size != self.n_tets:
+            raise ValueError("k_tet needs one value per tetrahedron")
+        self._h = lib().ohhg_create_mesh_k(self.nv, _d(self._xyz), self.n_tets, self._tets.ctypes.data_as(_ip),
+                                           self.level, self.coarse_level,
+                                           None if self.k_tet is None else _d(self.k_tet))
         if not self._h:
-            raise ValueError("invalid macro mesh (colouring, ids, flat tetrahedra) or levels")
+            raise ValueError("invalid macro mesh (colouring, ids, flat tetrahedra), levels or k_tet")
         self.ndof = int(lib().ohhg_ndof(self._h, self.level))
 
     def nodes(self, level: int | None = None):

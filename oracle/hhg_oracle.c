@@ -1144,7 +1144,7 @@ static csr mesh_prolongation(const olevel *C, const olevel *F, const i64 *mapf, 
 
 static void mesh_level_operators(oproblem *p, int l) {
     olevel *Lv = &p->lev[l];
-    Lv->A = mesh_assemble(Lv, NULL, 0, Lv->dof, Lv->ndof);
+    Lv->A = mesh_assemble(Lv, p->var_k ? Lv->k : NULL, 0, Lv->dof, Lv->ndof);
     Lv->diag = xmalloc((size_t)(Lv->ndof ? Lv->ndof : 1) * sizeof(double));
     for (i64 i = 0; i < Lv->ndof; i++) {
         Lv->diag[i] = 0.0;
@@ -1180,8 +1180,14 @@ static void mesh_level_operators(oproblem *p, int l) {
     Lv->built = 1;
 }
 
-void *ohhg_create_mesh(int nv, const double *xyz, int nt, const int *tets, int L, int Lc) {
+/* k_tet (NULL: k = 1): the coefficient of eq. (2) on each macro
+ * tetrahedron, so element e of level l (a descendant of macro element
+ * e >> 3l) has k = k_tet[e >> 3l] on every level */
+void *ohhg_create_mesh_k(int nv, const double *xyz, int nt, const int *tets, int L, int Lc, const double *k_tet) {
     if (nv < 4 || nt < 1 || !xyz || !tets || L < 1 || L >= MAXLEV || Lc < 1 || Lc > L) return NULL;
+    if (k_tet)
+        for (int t = 0; t < nt; t++)
+            if (!(k_tet[t] > 0.0) || !isfinite(k_tet[t])) return NULL;
     double t0 = now_s();
     oproblem *p = xcalloc(1, sizeof(oproblem));
     p->mesh = 1;
@@ -1281,16 +1287,21 @@ void *ohhg_create_mesh(int nv, const double *xyz, int nt, const int *tets, int L
     int *bf = boundary_faces(p, &nbf);
     for (int l = 0; l <= L; l++) mesh_order(p, l, bf, nbf);
     free(bf);
+    p->var_k = k_tet != NULL;
     for (int l = 0; l <= L; l++) {
         olevel *Lv = &p->lev[l];
         Lv->k = xmalloc((size_t)Lv->ne * sizeof(double));
-        for (i64 e = 0; e < Lv->ne; e++) Lv->k[e] = 1.0;
+        for (i64 e = 0; e < Lv->ne; e++) Lv->k[e] = k_tet ? k_tet[e >> (3 * l)] : 1.0;
         Lv->ecl = xmalloc((size_t)Lv->ne * sizeof(i64));
         for (i64 e = 0; e < Lv->ne; e++) Lv->ecl[e] = e;
     }
     for (int l = Lc; l <= L; l++) mesh_level_operators(p, l);
     p->setup_s = now_s() - t0;
     return p;
+}
+
+void *ohhg_create_mesh(int nv, const double *xyz, int nt, const int *tets, int L, int Lc) {
+    return ohhg_create_mesh_k(nv, xyz, nt, tets, L, Lc, NULL);
 }
 
 /* nodes of level l of a general macro mesh in creation order: positions
@@ -1329,8 +1340,9 @@ void *ohhg_matrix(void *vp, int l, int which) {
             *m = interior ? mesh_prolongation(C, Lv, Lv->dof, Lv->ndof, C->dof, C->ndof)
                           : mesh_prolongation(C, Lv, NULL, Lv->nnode, NULL, C->nnode);
         } else {
-            *m = interior ? mesh_assemble(Lv, NULL, kind, Lv->dof, Lv->ndof)
-                          : mesh_assemble(Lv, NULL, kind, NULL, Lv->nnode);
+            const double *k = kind == 0 && p->var_k ? Lv->k : NULL;
+            *m = interior ? mesh_assemble(Lv, k, kind, Lv->dof, Lv->ndof)
+                          : mesh_assemble(Lv, k, kind, NULL, Lv->nnode);
         }
         return m;
     }

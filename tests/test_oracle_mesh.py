@@ -336,3 +336,60 @@ def test_dirichlet_data_linear_reproduction(name):
     q = p.dirichlet_load(xyz[order, 0] ** 2)
     uq, _, _ = p.solve(q, rtol=1e-13, max_cycles=80)
     assert np.abs(uq - p.interior_positions(L)[:, 0] ** 2).max() > 1e-3
+
+
+def layered_k(v, t, k_low, k_high, z0):
+    """k per tetrahedron: k_low below the plane z = z0, k_high above it."""
+    zc = np.asarray(v)[np.asarray(t)][:, :, 2].mean(axis=1)
+    return np.where(zc < z0, k_low, k_high).astype(np.float64)
+
+
+def test_mesh_coefficient_per_tetrahedron_transmission():
+    """eq. (2) with k constant on each macro tetrahedron: two layers of the
+    box [0,2]^2 x [0,2] with k = 1 below z = 1 and k = 5 above.  A function
+    that is linear on each layer, continuous, with the same x and y slopes
+    and the normal fluxes k du/dz equal on z = 1, has zero weak Laplacian;
+    P1 elements reproduce it (the layers meet on element faces), so the
+    solve from its boundary values returns it at every interior node.  With
+    one k the kink is not reproduced."""
+    v, t = inputs.box_mesh(2, 2, 2)
+    L = 4
+    k = layered_k(v, t, 1.0, 5.0, 1.0)
+    assert 0 < (k == 5.0).sum() < len(t)
+    p = oracle.MeshProblem(v, t, L, 2, k_tet=k)
+
+    def exact(x):
+        z = x[:, 2]
+        return 0.3 * x[:, 0] - 0.7 * x[:, 1] + np.where(z < 1.0, 2.0 * z, 2.0 + 0.4 * (z - 1.0)) + 0.1
+
+    xyz, dof = p.nodes(L)
+    order = p.boundary_order(L)
+    u, _, _ = p.solve(p.dirichlet_load(exact(xyz[order])), rtol=1e-13, max_cycles=80)
+    xi = p.interior_positions(L)
+    assert np.abs(u - exact(xi)).max() < 1e-11
+    p1 = oracle.MeshProblem(v, t, L, 2)
+    u1, _, _ = p1.solve(p1.dirichlet_load(exact(xyz[order])), rtol=1e-13, max_cycles=80)
+    assert np.abs(u1 - exact(xi)).max() > 1e-3
+
+
+def test_mesh_coefficient_per_tetrahedron_scaling_and_sides():
+    """A constant k scales the operator of every level; a piecewise k splits
+    it into the one-sided matrices of eq. (5), which keep their k."""
+    v, t = mesh("box222p")
+    L = 3
+    p1 = oracle.MeshProblem(v, t, L, 2)
+    pc = oracle.MeshProblem(v, t, L, 2, k_tet=np.full(len(t), 2.5))
+    for l in (2, 3):
+        A1, Ac = p1.matrix(l, "A"), pc.matrix(l, "A")
+        assert abs(Ac - 2.5 * A1).max() <= 1e-14 * abs(Ac).max()
+    k = np.random.default_rng(3).uniform(0.5, 4.0, len(t))
+    pk = oracle.MeshProblem(v, t, L, 2, k_tet=k)
+    tet = inputs.mesh_fault_tet(len(t), seed=2)
+    Ai, Af = pk.side_matrix(L, [tet], "intact"), pk.side_matrix(L, [tet], "faulty")
+    Ak = pk.matrix(L, "A")
+    assert abs(Ai + Af - Ak).max() <= 1e-14 * abs(Ak).max()
+    # the faulty side is k of that tetrahedron times its unit-k part
+    Af1 = p1.side_matrix(L, [tet], "faulty")
+    assert abs(Af - k[tet] * Af1).max() <= 1e-14 * abs(Af).max()
+    with pytest.raises(ValueError):
+        oracle.MeshProblem(v, t, L, 2, k_tet=np.zeros(len(t)))
