@@ -151,7 +151,8 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * interiors of the tetrahedra by id, each in plane k, row j, i order (i, j,
  * k >= 1, i + j + k < m).  desc: level, coarse_level (>= 2), nu_pre, nu_post,
  * omega, precision and max_faults as above; n_sub and general_geometry are
- * ignored; variable_coeff must be 0.  The coarsest level is solved with a
+ * ignored; variable_coeff must be 0 (a coefficient per tetrahedron comes
+ * with hhgr_mesh_set_coeff).  The coarsest level is solved with a
  * dense inverse (at most 2048 unknowns).  A mesh context takes hhgr_set_rhs
  * with HHGR_RHS_LOAD, HHGR_RHS_NODAL_F (b = M f with the consistent P1 mass
  * matrix of the finest level, per-master rows like the stiffness) or
@@ -183,6 +184,19 @@ int hhgr_mesh_workspace_bytes(const hhgr_desc *desc, int nv, const double *host_
  * then boundary faces (a < b < c) with their nodes by the weight of c, then
  * of b.  EINVAL for a context not made by hhgr_create_mesh. */
 int hhgr_mesh_boundary(const hhgr_ctx *ctx, long long *n_boundary, double *host_xyz);
+/* Coefficient of eq. (2) constant on each macro tetrahedron of a mesh
+ * context (Sec. 2.1: other scalar elliptic problems; HHG keeps one stencil
+ * per macro element): host_k holds nt values > 0, read during the call
+ * (NULL: back to k = 1).  Every level takes the same k (the mean of 8
+ * children of a constant), so the volume stencils are scaled per
+ * tetrahedron, and the host sums the master rows, the coarsest-level
+ * operator (inverted again densely) and the Dirichlet couplings A_IB again
+ * with k times each element matrix.  Later cycles, solves, recoveries
+ * (the intact side of Dirichlet-Neumann keeps its k), batches and
+ * HHGR_RHS_DIRICHLET use it; a right-hand side set before is not
+ * recomputed.  hhgr_adjoint_grad gives dJ/df only.  EINVAL for a context
+ * not made by hhgr_create_mesh or a k that is not positive and finite. */
+int hhgr_mesh_set_coeff(hhgr_ctx *ctx, const double *host_k);
 int hhgr_create_mesh(const hhgr_desc *desc, int nv, const double *host_xyz, int nt, const int *host_tets,
                      void *dev_ws, size_t ws_bytes, void *hip_stream, hhgr_ctx **out);
 

@@ -228,6 +228,11 @@ struct hhgr_ctx {
     hipGraphExec_t lgexec = nullptr;
     int lg_tet = -1, lg_n = -1;
     std::vector<int> loc_tets;  // the tetrahedra whose local hierarchy vd_loc holds
+    // unstructured mesh with a coefficient per tetrahedron (empty: k = 1):
+    // the values, the master rows of every level and the coarsest rows
+    std::vector<double> mesh_k;
+    std::vector<std::vector<double>> mesh_k_wi;
+    std::vector<double> mesh_k_valw;
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tev;
@@ -1288,6 +1293,7 @@ int dd_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     std::vector<double> inv_full;
     if (c.mesh) {
         // the coarsest operator on the unfrozen unknowns, inverted densely
+        const std::vector<double> &valw = c.mesh_k.empty() ? cs.valw : c.mesh_k_valw;
         std::vector<int> keep(cs.n, -1);
         int nk = 0;
         for (int q = 0; q < cs.n; q++)
@@ -1300,7 +1306,7 @@ int dd_setup(hhgr_ctx &c, const std::vector<int> &ft) {
                 const int cq = cs.colw[(size_t)cs.cw * q + e];
                 if (cq < 0 || keep[cq] < 0) continue;
                 colk[(size_t)cs.cw * keep[q] + e] = keep[cq];
-                valk[(size_t)cs.cw * keep[q] + e] = cs.valw[(size_t)cs.cw * q + e];
+                valk[(size_t)cs.cw * keep[q] + e] = valw[(size_t)cs.cw * q + e];
             }
         }
         std::vector<double> inv;
@@ -1412,13 +1418,17 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
     if (c.mesh) {
         // master rows over the elements of intact tetrahedra (host), and the
         // coarsest-level operator on the unfrozen unknowns, inverted densely
-        std::vector<std::vector<double>> wi;
-        std::vector<double> valw;
-        const std::string e = c.topo->mesh_intact_operators(isf.data(), wi, valw);
+        std::vector<double> wt(c.n_tets);
+        for (int t = 0; t < c.n_tets; t++) wt[t] = isf[t] ? 0.0 : c.mesh_k.empty() ? 1.0 : c.mesh_k[t];
+        Topology::MeshOps I;
+        const std::string e =
+            c.topo->mesh_weighted_operators(wt.data(), isf.data(), c.mesh_k.empty() ? nullptr : &c.mesh_k_wi, I);
         if (!e.empty()) {
             HIPCHK(hipStreamSynchronize(c.stream));
             return fail(HHGR_EINVAL, e);
         }
+        const std::vector<std::vector<double>> &wi = I.wi;
+        const std::vector<double> &valw = I.valw;
         for (int l = c.Lc; l <= c.L && !rc; l++) rc = upload(c, c.lev[l].wi15_dn, wi[l].data(), wi[l].size() * sizeof(double));
         std::vector<int> keep(cs.n, -1);
         int nk = 0;
@@ -1847,6 +1857,61 @@ int hhgr_mesh_boundary(const hhgr_ctx *c, long long *n_boundary, double *host_xy
     if (!c->mesh) return fail(HHGR_EINVAL, "not an unstructured macro mesh context");
     if (n_boundary) *n_boundary = c->topo->n_bnd;
     if (host_xyz) std::copy(c->topo->bnd_xyz.begin(), c->topo->bnd_xyz.end(), host_xyz);
+    return HHGR_OK;
+}
+
+int hhgr_mesh_set_coeff(hhgr_ctx *c, const double *host_k) {
+    if (!c) return fail(HHGR_EINVAL, "null context");
+    if (!c->mesh) return fail(HHGR_EINVAL, "not an unstructured macro mesh context");
+    const Topology &tp = *c->topo;
+    const CoarseSystem &cs = tp.coarse;
+    Topology::MeshOps K;
+    if (host_k) {
+        for (int t = 0; t < c->n_tets; t++)
+            if (!(host_k[t] > 0.0) || !std::isfinite(host_k[t]))
+                return fail(HHGR_EINVAL, "the coefficient must be positive and finite on every tetrahedron");
+        const std::vector<unsigned char> all(c->n_tets, 1);
+        const std::string e = tp.mesh_weighted_operators(host_k, all.data(), nullptr, K);
+        if (!e.empty()) return fail(HHGR_EINVAL, e);
+    } else {
+        // back to k = 1: the topology's own tables
+        K.w15.assign(c->L + 1, {});
+        K.wi.assign(c->L + 1, {});
+        for (int l = c->Lc; l <= c->L; l++) {
+            K.w15[l] = tp.lev[l].mesh_w15;
+            K.wi[l] = tp.lev[l].mesh_wi;
+        }
+        K.valw = cs.valw;
+        K.dir_val = tp.dir_val;
+    }
+    std::vector<double> inv;
+    if (!coarse_inverse(cs.n, cs.cw, cs.colw, K.valw, inv))
+        return fail(HHGR_EINVAL, "the coarsest-level operator is not positive definite");
+    invalidate_graph(*c);
+    int rc = HHGR_OK;
+    for (int l = c->Lc; l <= c->L; l++) {
+        LevelDev &D = c->lev[l];
+        rc = rc ? rc : upload(*c, D.w15, K.w15[l].data(), K.w15[l].size() * sizeof(double));
+        rc = rc ? rc : upload(*c, D.wi15, K.wi[l].data(), K.wi[l].size() * sizeof(double));
+        if (c->mixed) {
+            launch_cast<double, float>(c->stream, D.w15, D.w15f, 15LL * c->n_tets);
+            launch_cast<double, float>(c->stream, D.wi15, D.wi15f, (long long)tp.nbw * D.n_ifc);
+        }
+    }
+    rc = rc ? rc : upload(*c, c->cinv, inv.data(), inv.size() * sizeof(double));
+    rc = rc ? rc : upload(*c, c->dir_val, K.dir_val.data(), K.dir_val.size() * sizeof(double));
+    CHKLAUNCH();
+    HIPCHK(hipStreamSynchronize(c->stream));  // the copies read K and inv
+    if (rc) return rc;
+    if (host_k) {
+        c->mesh_k.assign(host_k, host_k + c->n_tets);
+        c->mesh_k_wi = std::move(K.wi);
+        c->mesh_k_valw = std::move(K.valw);
+    } else {
+        c->mesh_k.clear();
+        c->mesh_k_wi.clear();
+        c->mesh_k_valw.clear();
+    }
     return HHGR_OK;
 }
 

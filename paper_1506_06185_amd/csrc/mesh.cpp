@@ -418,6 +418,10 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         // finest level: the couplings of interior nodes (slot, boundary
         // index, stiffness) to Dirichlet nodes, for eliminated boundary data
         std::map<std::pair<int, int>, double> dir;
+        // the same couplings summed per tetrahedron (for a coefficient
+        // constant on each tetrahedron): (row slot, boundary index, tet, value)
+        std::vector<std::tuple<int, int, int, double>> dparts;
+        std::map<std::pair<int, int>, double> dtet;
         // ghost copies
         Lv.nbr.assign(6 * (size_t)Lv.n_ifc, (int)Lv.zero_slot);
         Lv.tg_ptr.assign(nt + 1, 0);
@@ -474,7 +478,10 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             const int own = cslot[Lv.lay.index(i, j, k)];
                             for (int n = 1; n < 15; n++) {
                                 const int q = Lv.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2]);
-                                if (cbnd[q] >= 0) dir[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
+                                if (cbnd[q] >= 0) {
+                                    dir[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
+                                    dtet[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
+                                }
                             }
                         }
             for (int k = 0; k <= m; k++)
@@ -498,7 +505,10 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             if (!in) continue;
                             for (int r = 0; r < 4; r++) {
                                 const int pq = Lv.lay.index(p[r][0], p[r][1], p[r][2]);
-                                if (cbnd[pq] >= 0) dir[{(int)own, cbnd[pq]}] += K[q][A.self][r];
+                                if (cbnd[pq] >= 0) {
+                                    dir[{(int)own, cbnd[pq]}] += K[q][A.self][r];
+                                    dtet[{(int)own, cbnd[pq]}] += K[q][A.self][r];
+                                }
                                 const int s = cslot[pq];
                                 size_t e = 0;
                                 while (e < row.size() && row[e].s != s) e++;
@@ -508,6 +518,8 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             }
                         }
                     }
+            for (const auto &e : dtet) dparts.emplace_back(e.first.first, e.first.second, t, e.second);
+            dtet.clear();
         }
         for (const auto &row : R) width = std::max(width, (int)row.size());
         if (l == L) {
@@ -525,6 +537,16 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                 dir_val.push_back(e.second);
             }
             dir_ptr.push_back((int)dir_col.size());
+            std::map<std::pair<int, int>, int> at;
+            for (const auto &e : dir) at.emplace(e.first, (int)at.size());
+            dir_part_e.clear();
+            dir_part_t.clear();
+            dir_part_v.clear();
+            for (const auto &d : dparts) {
+                dir_part_e.push_back(at.at({std::get<0>(d), std::get<1>(d)}));
+                dir_part_t.push_back(std::get<2>(d));
+                dir_part_v.push_back(std::get<3>(d));
+            }
         }
         build_closure_tables(Lv);
     }
@@ -700,25 +722,30 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
     return "";
 }
 
-std::string Topology::mesh_intact_operators(const unsigned char *faulty, std::vector<std::vector<double>> &wi,
-                                            std::vector<double> &valw) const {
+std::string Topology::mesh_weighted_operators(const double *wt, const unsigned char *dirty,
+                                              const std::vector<std::vector<double>> *base, MeshOps &out) const {
     if (!mesh) return "not an unstructured macro mesh";
     const int nt = n_tets;
     const std::vector<Around> around = elements_around();
     if (around.size() != 24) return "internal: element star";
-    wi.assign(L + 1, {});
+    out.w15.assign(L + 1, {});
+    out.wi.assign(L + 1, {});
     std::vector<int> cslot;
     for (int l = Lc; l <= L; l++) {
         const TopoLevel &Lv = lev[l];
         const int m = Lv.m;
         const size_t n = (size_t)Lv.n_ifc;
-        std::vector<double> &W = wi[l];
-        W = Lv.mesh_wi;
-        // masters with a copy in a faulty closure: their rows are summed
-        // again over the intact tetrahedra, in the order of build_mesh
+        out.w15[l].resize(15 * (size_t)nt);
+        for (int t = 0; t < nt; t++)
+            for (int q = 0; q < 15; q++) out.w15[l][15 * (size_t)t + q] = wt[t] * Lv.mesh_w15[15 * (size_t)t + q];
+        std::vector<double> &W = out.wi[l];
+        W = base ? (*base)[l] : Lv.mesh_wi;
+        if (W.size() != (size_t)nbw * n) return "internal: base rows of the wrong size";
+        // masters with a copy in a flagged closure: their rows are summed
+        // again, k times each element matrix, in the order of build_mesh
         std::vector<char> aff(n, 0);
         for (int t = 0; t < nt; t++)
-            if (faulty[t])
+            if (dirty[t])
                 for (int q = Lv.tg_ptr[t]; q < Lv.tg_ptr[t + 1]; q++)
                     if (Lv.tg_src[q] != Lv.zero_slot) aff[Lv.tg_src[q] - Lv.ifc_base] = 1;
         for (size_t f = 0; f < n; f++)
@@ -726,7 +753,7 @@ std::string Topology::mesh_intact_operators(const unsigned char *faulty, std::ve
                 for (int e = 0; e < nbw; e++) W[e * n + f] = 0.0;
         cslot.assign(Lv.C_pad, (int)Lv.zero_slot);
         for (int t = 0; t < nt; t++) {
-            if (faulty[t]) continue;
+            if (wt[t] == 0.0) continue;
             bool touch = false;
             for (int q = Lv.tg_ptr[t]; q < Lv.tg_ptr[t + 1] && !touch; q++)
                 touch = Lv.tg_src[q] != Lv.zero_slot && aff[Lv.tg_src[q] - Lv.ifc_base];
@@ -770,16 +797,14 @@ std::string Topology::mesh_intact_operators(const unsigned char *faulty, std::ve
                                 const int s = cslot[Lv.lay.index(p[r][0], p[r][1], p[r][2])];
                                 int e = 0;
                                 while (e < nbw && Lv.nb15[e * n + f] != s) e++;
-                                if (e == nbw) return "internal: intact-side entry outside the master's row";
-                                W[e * n + f] += K[q][A.self][r];
+                                if (e == nbw) return "internal: weighted entry outside the master's row";
+                                W[e * n + f] += wt[t] * K[q][A.self][r];
                             }
                         }
                     }
         }
     }
-    // coarsest level: master rows from the intact entries, in the order of
-    // build_mesh; volume rows are unchanged (an interior node's elements lie
-    // in its own tetrahedron)
+    // coarsest level: the rows of build_mesh from the weighted stencils
     const TopoLevel &Lv = lev[Lc];
     const CoarseSystem &cs = coarse;
     const size_t n = (size_t)Lv.n_ifc;
@@ -787,22 +812,40 @@ std::string Topology::mesh_intact_operators(const unsigned char *faulty, std::ve
     for (int q = 0; q < cs.n; q++) unk[cs.slot[q]] = q;
     for (size_t q = 0; q < Lv.tg_dst.size(); q++)
         if (Lv.tg_src[q] != Lv.zero_slot) unk[Lv.tg_dst[q]] = unk[Lv.tg_src[q]];
-    valw = cs.valw;
+    std::vector<std::array<int, 3>> ijk(Lv.C_pad, {-1, -1, -1});
+    for (int k = 0; k <= Lv.m; k++)
+        for (int j = 0; j <= Lv.m - k; j++)
+            for (int i = 0; i <= Lv.m - k - j; i++) ijk[Lv.lay.index(i, j, k)] = {i, j, k};
+    out.valw.assign(cs.valw.size(), 0.0);
     for (int q = 0; q < cs.n; q++) {
-        if (cs.is_vol[q]) continue;
-        const size_t f = (size_t)cs.ifc[q];
-        double *row = &valw[(size_t)cs.cw * q];
-        for (int e = 0; e < cs.cw; e++) row[e] = 0.0;
-        for (int e = 0; e < nbw; e++) {
-            const long long s = Lv.nb15[e * n + f];
-            const int c = s == Lv.zero_slot ? -1 : unk[s];
-            if (c < 0) continue;
+        double *row = &out.valw[(size_t)cs.cw * q];
+        auto add = [&](long long s, double v) -> bool {
+            const int c = s < 0 || s == Lv.zero_slot ? -1 : unk[s];
+            if (c < 0) return true;
             int p = 0;
             while (p < cs.cw && cs.colw[(size_t)cs.cw * q + p] != c) p++;
-            if (p == cs.cw) return "internal: intact-side coarse entry outside the row";
-            row[p] += wi[Lc][e * n + f];
+            if (p == cs.cw) return false;
+            row[p] += v;
+            return true;
+        };
+        if (cs.is_vol[q]) {
+            const int t = cs.tet[q];
+            const std::array<int, 3> &x = ijk[cs.slot[q] - (long long)t * Lv.C_pad];
+            for (int e = 0; e < 15; e++)
+                if (!add((long long)t * Lv.C_pad + Lv.lay.index(x[0] + kIdx15[e][0], x[1] + kIdx15[e][1],
+                                                                 x[2] + kIdx15[e][2]),
+                         out.w15[Lc][15 * (size_t)t + e]))
+                    return "internal: weighted coarse entry outside the row";
+        } else {
+            const size_t f = (size_t)cs.ifc[q];
+            for (int e = 0; e < nbw; e++)
+                if (!add(Lv.nb15[e * n + f], out.wi[Lc][e * n + f]))
+                    return "internal: weighted coarse entry outside the row";
         }
     }
+    // finest level: the couplings to the Dirichlet boundary nodes
+    out.dir_val.assign(dir_val.size(), 0.0);
+    for (size_t q = 0; q < dir_part_e.size(); q++) out.dir_val[dir_part_e[q]] += wt[dir_part_t[q]] * dir_part_v[q];
     return "";
 }
 

@@ -175,14 +175,23 @@ struct Topology {
     // in plane k, row j, i order.  Fills the stencils and the coarsest-level
     // rows too.  Returns an empty string on success, else the error.
     std::string build_mesh(int nv, const double *xyz, int nt, const int *tets, int L, int Lc);
-    // Intact side of a Dirichlet-Neumann recovery on a mesh (Sec. 4.3,
-    // eq. (5)): the master rows of every level summed over the elements of
-    // the tetrahedra not flagged in faulty (wi[l], the layout of mesh_wi:
-    // rows of masters no faulty closure holds are mesh_wi's own), and the
-    // coarsest-level rows over the same elements (valw, the layout of
-    // coarse.valw).  Returns an empty string on success, else the error.
-    std::string mesh_intact_operators(const unsigned char *faulty, std::vector<std::vector<double>> &wi,
-                                      std::vector<double> &valw) const;
+    // Operators of a mesh whose elements in tetrahedron t carry the weight
+    // wt[t] (eq. (2) with k constant on each macro tetrahedron; 0 drops the
+    // tetrahedron's elements, as the intact side of a Dirichlet-Neumann
+    // recovery does, Sec. 4.3, eq. (5)): per level the volume stencils
+    // (15 per tetrahedron) and the master rows (the layout of mesh_wi), the
+    // coarsest-level rows (the layout of coarse.valw) and the finest level's
+    // Dirichlet couplings (the layout of dir_val).  Master rows are summed
+    // again only for masters with a copy in a closure flagged in dirty;
+    // the others are taken from base (per level; null: the k = 1 rows), which
+    // must hold them for the same weights.  Returns an empty string on
+    // success, else the error.
+    struct MeshOps {
+        std::vector<std::vector<double>> w15, wi;
+        std::vector<double> valw, dir_val;
+    };
+    std::string mesh_weighted_operators(const double *wt, const unsigned char *dirty,
+                                        const std::vector<std::vector<double>> *base, MeshOps &out) const;
     bool mesh = false;
     unsigned long long mesh_hash = 0;  // hash of the vertex and tetrahedron lists (set by the engine)
     std::vector<double> mesh_xyz;  // the mesh's vertices (3 each) and tetrahedra (4 vertex ids each)
@@ -198,6 +207,10 @@ struct Topology {
     std::vector<double> bnd_xyz;
     std::vector<int> dir_rows, dir_ptr, dir_col;
     std::vector<double> dir_val;
+    // the same couplings per tetrahedron: entry dir_part_e, tetrahedron
+    // dir_part_t, value dir_part_v (entries in summation order)
+    std::vector<int> dir_part_e, dir_part_t;
+    std::vector<double> dir_part_v;
 
     // slot of grid node X at level l (zero slot for boundary nodes)
     long long slot_of(int l, int x, int y, int z) const;

@@ -63,6 +63,7 @@ def lib():
                                                 C.POINTER(C.c_size_t)]),
         "hhgr_set_fused_sweeps": (C.c_int, [_vp, C.c_int, C.c_int]),
         "hhgr_mesh_boundary": (C.c_int, [_vp, C.POINTER(C.c_longlong), _vp]),
+        "hhgr_mesh_set_coeff": (C.c_int, [_vp, _vp]),
         "hhgr_create_mesh": (C.c_int, [C.POINTER(Desc), C.c_int, _vp, C.c_int, _vp, _vp, C.c_size_t, _vp,
                                        C.POINTER(_vp)]),
         "hhgr_destroy": (None, [_vp]),
@@ -110,6 +111,7 @@ EXPORTED = ("hhgr_desc_default", "hhgr_workspace_bytes", "hhgr_create", "hhgr_de
             "hhgr_tuning_info", "hhgr_set_tuning",
             "hhgr_autotune", "hhgr_kernel_timing", "hhgr_kernel_stats", "hhgr_debug_op", "hhgr_solve_static",
             "hhgr_mesh_workspace_bytes", "hhgr_create_mesh", "hhgr_set_fused_sweeps", "hhgr_mesh_boundary",
+            "hhgr_mesh_set_coeff",
             "hhgr_last_error")
 
 
@@ -315,6 +317,19 @@ class Context:
         xyz = np.empty((int(n.value), 3))
         _check(lib().hhgr_mesh_boundary(self._h, C.byref(n), xyz.ctypes.data))
         return xyz
+
+    def set_mesh_coeff(self, k_tet=None):
+        """Coefficient k of eq. (2) constant on each macro tetrahedron of a
+        mesh context (host values, one per tetrahedron; None: k = 1)."""
+        if k_tet is None:
+            _check(lib().hhgr_mesh_set_coeff(self._h, None))
+            return
+        import numpy as np
+
+        k = np.ascontiguousarray(np.asarray(k_tet, dtype=np.float64).reshape(-1))
+        if k.size != self.n_tets:
+            raise ValueError("k_tet needs one value per tetrahedron")
+        _check(lib().hhgr_mesh_set_coeff(self._h, k.ctypes.data))
 
     def set_fused_sweeps(self, level: int, on: bool = True):
         _check(lib().hhgr_set_fused_sweeps(self._h, int(level), int(bool(on))))

@@ -287,6 +287,19 @@ int main() {
         CHECK(hhgr_recover_dn(g, t2, 2, 2, 1) == HHGR_OK, "mesh dn: %s", hhgr_last_error());
         CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_OK, "mesh vcycle after dn");
         {
+            // a coefficient per tetrahedron, with recoveries over it, then k = 1 again
+            const double kt[8] = {1.0, 2.0, 0.5, 3.0, 1.5, 4.0, 0.25, 1.0};
+            CHECK(hhgr_mesh_set_coeff(g, kt) == HHGR_OK, "mesh coeff: %s", hhgr_last_error());
+            CHECK(hhgr_vcycle(g, 1, &rr) == HHGR_OK, "mesh vcycle with k");
+            CHECK(hhgr_recover_dd(g, t2, 2, 1, 2) == HHGR_OK, "mesh dd with k: %s", hhgr_last_error());
+            CHECK(hhgr_recover_dn(g, t2, 2, 1, 1) == HHGR_OK, "mesh dn with k: %s", hhgr_last_error());
+            CHECK(hhgr_set_rhs(g, gbv.data(), HHGR_RHS_DIRICHLET) == HHGR_OK, "mesh Dirichlet with k");
+            const double bad[8] = {1.0, 2.0, 0.0, 3.0, 1.5, 4.0, 0.25, 1.0};
+            CHECK(hhgr_mesh_set_coeff(g, bad) == HHGR_EINVAL, "mesh coeff zero rejected");
+            CHECK(hhgr_mesh_set_coeff(cs[0].h, kt) == HHGR_EINVAL, "cube takes no mesh coefficient");
+            CHECK(hhgr_mesh_set_coeff(g, nullptr) == HHGR_OK, "mesh coeff reset: %s", hhgr_last_error());
+        }
+        {
             // a batch of the mesh member (armed DD) and a cube member
             hhgr_ctx *bm[2] = {g, cs[1].h};
             hhgr_batch *mb = nullptr;

@@ -5,12 +5,14 @@
 // independent assembly.  Also checks internal invariants and exits nonzero
 // when one fails.
 //
-// usage: mesh_check <mesh file> <output file> [faulty tet ids, comma-separated]
+// usage: mesh_check <mesh file> <output file> [faulty tet ids, comma-separated, or -]
+//                   [coefficient per tetrahedron, comma-separated]
 // mesh file: "nv nt L Lc", then nv lines "x y z", then nt lines "a b c d"
-// With faulty tetrahedra it also writes the intact side of a
-// Dirichlet-Neumann recovery: per level the operator of the intact volume
-// stencils and the intact master rows ("I"), and the coarsest-level rows over
-// the intact elements ("C").
+// With the optional arguments it also writes the operators of a coefficient
+// constant on each tetrahedron ("W", "WC", "WD") and the intact side of a
+// Dirichlet-Neumann recovery over it: per level the operator of the intact
+// volume stencils and the intact master rows ("I"), and the coarsest-level
+// rows over the intact elements ("C").
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -41,7 +43,7 @@ static long long rank_enum(int m, int i0, int j0, int k0) {
 }
 
 int main(int argc, char **argv) {
-    if (argc != 3 && argc != 4) return 2;
+    if (argc < 3 || argc > 5) return 2;
     FILE *f = std::fopen(argv[1], "r");
     if (!f) return 2;
     int nv, nt, L, Lc;
@@ -160,63 +162,108 @@ int main(int argc, char **argv) {
             std::fprintf(o, "end\n");
         }
     }
-    if (argc == 4) {
+    if (argc >= 4) {
+        // optional: faulty tetrahedra ("-" for none) and a coefficient per
+        // tetrahedron; the weighted operator of every level ("W"), its
+        // coarsest rows ("WC") and Dirichlet couplings ("WD"), then with
+        // faults the intact side over the same coefficient ("I", "C")
         std::vector<unsigned char> faulty(nt, 0);
-        for (const char *c = argv[3]; *c;) {
+        bool any_fault = false;
+        for (const char *c = argv[3]; *c && std::string(argv[3]) != "-";) {
             char *end;
             const long t = std::strtol(c, &end, 10);
             if (end == c || t < 0 || t >= nt) return 2;
             faulty[t] = 1;
+            any_fault = true;
             c = *end == ',' ? end + 1 : end;
         }
-        std::vector<std::vector<double>> wi;
-        std::vector<double> valw;
-        e = tp.mesh_intact_operators(faulty.data(), wi, valw);
+        std::vector<double> kt(nt, 1.0);
+        if (argc == 5) {
+            const char *c = argv[4];
+            for (int t = 0; t < nt; t++) {
+                char *end;
+                kt[t] = std::strtod(c, &end);
+                if (end == c) return 2;
+                c = *end == ',' ? end + 1 : end;
+            }
+        }
+        const std::vector<unsigned char> all(nt, 1);
+        Topology::MeshOps K, I;
+        e = tp.mesh_weighted_operators(kt.data(), all.data(), nullptr, K);
+        if (e.empty() && any_fault) {
+            std::vector<double> wi(nt);
+            for (int t = 0; t < nt; t++) wi[t] = faulty[t] ? 0.0 : kt[t];
+            e = tp.mesh_weighted_operators(wi.data(), faulty.data(), &K.wi, I);
+        }
         if (!e.empty()) {
             std::printf("error: %s\n", e.c_str());
             return 4;
         }
-        for (int l = Lc; l <= L; l++) {
-            const TopoLevel &Lv = tp.lev[l];
-            const int m = Lv.m;
-            const std::vector<long long> &U = user_of[l];
-            std::fprintf(o, "I %d\n", l);
-            for (int t = 0; t < nt; t++) {
-                if (faulty[t]) continue;
-                for (int k = 1; k < m; k++)
-                    for (int j = 1; j < m; j++)
-                        for (int i = 1; i + j + k <= m - 1; i++) {
-                            const long long r = U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)];
-                            for (int n = 0; n < 15; n++) {
-                                const long long c = U[(long long)t * Lv.C_pad +
-                                                      Lv.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2])];
-                                if (c >= 0) std::fprintf(o, "%lld %lld %.17g\n", r, c, Lv.mesh_w15[15 * (size_t)t + n]);
+        const CoarseSystem &cs = tp.coarse;
+        auto write_ops = [&](const char *tag, const char *ctag, const Topology::MeshOps &W, bool skip_faulty) {
+            for (int l = Lc; l <= L; l++) {
+                const TopoLevel &Lv = tp.lev[l];
+                const int m = Lv.m;
+                const std::vector<long long> &U = user_of[l];
+                std::fprintf(o, "%s %d\n", tag, l);
+                for (int t = 0; t < nt; t++) {
+                    if (skip_faulty && faulty[t]) continue;
+                    for (int k = 1; k < m; k++)
+                        for (int j = 1; j < m; j++)
+                            for (int i = 1; i + j + k <= m - 1; i++) {
+                                const long long r = U[(long long)t * Lv.C_pad + Lv.lay.index(i, j, k)];
+                                for (int n = 0; n < 15; n++) {
+                                    const long long c = U[(long long)t * Lv.C_pad + Lv.lay.index(i + kIdx15[n][0],
+                                                                                                j + kIdx15[n][1],
+                                                                                                k + kIdx15[n][2])];
+                                    if (c >= 0) std::fprintf(o, "%lld %lld %.17g\n", r, c, W.w15[l][15 * (size_t)t + n]);
+                                }
                             }
-                        }
+                }
+                for (int q = 0; q < Lv.n_ifc; q++)
+                    for (int n = 0; n < tp.nbw; n++) {
+                        const size_t at = (size_t)n * Lv.n_ifc + q;
+                        const long long c = U[Lv.nb15[at]];
+                        if (c >= 0) std::fprintf(o, "%d %lld %.17g\n", Lv.ifc_dof[q], c, W.wi[l][at]);
+                    }
+                std::fprintf(o, "end\n");
             }
-            // unaffected master rows must be the full rows, bit for bit
-            for (int q = 0; q < Lv.n_ifc; q++) {
-                bool touched = false;
-                for (int g = Lv.gptr[q]; g < Lv.gptr[q + 1]; g++) touched |= faulty[Lv.gidx[g] / Lv.C_pad] != 0;
-                for (int n = 0; n < tp.nbw; n++) {
-                    const size_t at = (size_t)n * Lv.n_ifc + q;
-                    if (!touched) CHECK(wi[l][at] == Lv.mesh_wi[at]);
-                    const long long c = U[Lv.nb15[at]];
-                    if (c >= 0) std::fprintf(o, "%d %lld %.17g\n", Lv.ifc_dof[q], c, wi[l][at]);
+            std::fprintf(o, "%s %d\n", ctag, Lc);
+            for (int q = 0; q < cs.n; q++)
+                for (int e2 = 0; e2 < cs.cw; e2++) {
+                    const int c = cs.colw[(size_t)cs.cw * q + e2];
+                    if (c >= 0)
+                        std::fprintf(o, "%lld %lld %.17g\n", user_of[Lc][cs.slot[q]], user_of[Lc][cs.slot[c]],
+                                     W.valw[(size_t)cs.cw * q + e2]);
+                }
+            std::fprintf(o, "end\n");
+        };
+        write_ops("W", "WC", K, false);
+        std::fprintf(o, "WD %d %lld\n", L, tp.n_bnd);
+        for (size_t q = 0; q < tp.dir_rows.size(); q++)
+            for (int e2 = tp.dir_ptr[q]; e2 < tp.dir_ptr[q + 1]; e2++)
+                std::fprintf(o, "%lld %d %.17g\n", user_of[L][tp.dir_rows[q]], tp.dir_col[e2], K.dir_val[e2]);
+        std::fprintf(o, "end\n");
+        // with k = 1 the weighted tables are the plain ones, bit for bit
+        // (the Dirichlet couplings are summed per tetrahedron first)
+        if (argc == 4)
+            for (int l = Lc; l <= L; l++) {
+                CHECK(K.wi[l] == tp.lev[l].mesh_wi);
+                CHECK(K.w15[l] == tp.lev[l].mesh_w15);
+            }
+        if (any_fault) {
+            write_ops("I", "C", I, true);
+            // masters that no faulty closure holds keep the weighted rows
+            for (int l = Lc; l <= L; l++) {
+                const TopoLevel &Lv = tp.lev[l];
+                for (int q = 0; q < Lv.n_ifc; q++) {
+                    bool touched = false;
+                    for (int g = Lv.gptr[q]; g < Lv.gptr[q + 1]; g++) touched |= faulty[Lv.gidx[g] / Lv.C_pad] != 0;
+                    for (int n = 0; n < tp.nbw && !touched; n++)
+                        CHECK(I.wi[l][(size_t)n * Lv.n_ifc + q] == K.wi[l][(size_t)n * Lv.n_ifc + q]);
                 }
             }
-            std::fprintf(o, "end\n");
         }
-        const CoarseSystem &cs = tp.coarse;
-        std::fprintf(o, "C %d\n", Lc);
-        for (int q = 0; q < cs.n; q++)
-            for (int e2 = 0; e2 < cs.cw; e2++) {
-                const int c = cs.colw[(size_t)cs.cw * q + e2];
-                if (c >= 0)
-                    std::fprintf(o, "%lld %lld %.17g\n", user_of[Lc][cs.slot[q]], user_of[Lc][cs.slot[c]],
-                                 valw[(size_t)cs.cw * q + e2]);
-            }
-        std::fprintf(o, "end\n");
     }
     // interface rows of the transfers: P (fine master <- coarse parents) and
     // R = P^T (coarse master <- its fine twin and the neighbours at 1/2)

@@ -352,6 +352,101 @@ def test_mesh_members_in_a_batch(dev, hh):
         m["ctx"].close()
 
 
+@pytest.mark.parametrize("name,level", [("box222p", 4), ("octa8", 4)])
+def test_mesh_coefficient_per_tetrahedron(dev, hh, name, level):
+    """eq. (2) with k constant on each macro tetrahedron (hhgr_mesh_set_coeff):
+    V-cycle iterates, the solve, a fault with local recovery, and the
+    Dirichlet-Dirichlet and Dirichlet-Neumann recoveries over that k, per
+    iterate against the oracle assembled with the same k; mixed precision
+    to the oracle's solution; back to k = 1 the plain context's iterates."""
+    print(f"\n[mesh k per tet] {name} level={level}", flush=True)
+    v, t = mesh(name)
+    k = np.random.default_rng(19).uniform(0.2, 5.0, len(t))
+    p = oracle.MeshProblem(v, t, level, 2, k_tet=k)
+    b = np.random.default_rng(47).uniform(-1, 1, p.ndof)
+    ctx = context(hh, dev, name, level)
+    ctx.set_mesh_coeff(k)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.set_solution(None)
+    u = np.zeros(p.ndof)
+    for it in range(3):
+        ctx.vcycle(1)
+        u, _ = p.vcycle(u, b)
+        assert rel(Nn(ctx.get_solution()), u) < 1e-12, it
+    tets = [inputs.mesh_fault_tet(len(t), seed=4), inputs.mesh_fault_tet(len(t), seed=6)]
+    tets = sorted(set(tets))
+    ctx.inject_fault(tets[0])
+    u = p.inject_fault(tets[0], u)
+    ctx.recover_local(tets[0], 2)
+    u, _ = p.recover_local(tets[0], u, b, 2)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    for q in tets:
+        ctx.inject_fault(q)
+        u = p.inject_fault(q, u)
+    ctx.recover_dd(tets, 2, 3)
+    u = p.dd_intact(tets, u, b, 2)
+    u, _ = p.recover_local(tets, u, b, 3)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    for q in tets:
+        ctx.inject_fault(q)
+        u = p.inject_fault(q, u)
+    ctx.recover_dn(tets, 3, 2)
+    u = p.dn_recover(tets, u, b, 3, 2)
+    assert rel(Nn(ctx.get_solution()), u) < 1e-12
+    cyc, _, _ = ctx.solve(rel_tol=1e-10, max_cycles=60)
+    uo, co, _ = p.solve(b, u0=u, rtol=1e-10, max_cycles=60, r0=np.linalg.norm(b))
+    assert cyc == co
+    assert rel(Nn(ctx.get_solution()), uo) < 1e-11
+    ctx.close()
+    # mixed precision reaches the oracle's solution
+    cm = context(hh, dev, name, level, precision="mixed")
+    cm.set_mesh_coeff(k)
+    cm.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    cm.solve(rel_tol=1e-11, max_cycles=60)
+    ux, _, _ = p.solve(b, rtol=1e-13, max_cycles=80)
+    assert rel(Nn(cm.get_solution()), ux) < 1e-9
+    # k = 1 again: the plain operator
+    cm.close()
+    c1 = context(hh, dev, name, level)
+    c1.set_mesh_coeff(k)
+    c1.set_mesh_coeff(None)
+    c1.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    c1.set_solution(None)
+    c1.vcycle(2)
+    p1 = problem(name, level)
+    u1 = np.zeros(p.ndof)
+    for _ in range(2):
+        u1, _ = p1.vcycle(u1, b)
+    assert rel(Nn(c1.get_solution()), u1) < 1e-12
+    with pytest.raises(hh.HHGRError):
+        c1.set_mesh_coeff(np.zeros(len(t)))
+    c1.close()
+
+
+def test_mesh_coefficient_transmission(dev, hh):
+    """Two layers of k (1 below z = 1, 5 above) on the unmoved 2 x 2 x 2 box:
+    the function that is linear on each layer with equal normal fluxes
+    k du/dz on z = 1 is the discrete solution for its own boundary values
+    (eq. (1)); the GPU solve returns it at every interior node."""
+    v, t = inputs.box_mesh(2, 2, 2)
+    level = 5
+    print(f"\n[mesh transmission] box222 level={level}", flush=True)
+    zc = np.asarray(v)[np.asarray(t)][:, :, 2].mean(axis=1)
+    k = np.where(zc < 1.0, 1.0, 5.0)
+    ctx = hh.Context(device=dev, mesh=(v, t), level=level, coarse_level=2)
+    ctx.set_mesh_coeff(k)
+
+    def exact(x):
+        z = x[:, 2]
+        return 0.3 * x[:, 0] - 0.7 * x[:, 1] + np.where(z < 1.0, 2.0 * z, 2.0 + 0.4 * (z - 1.0)) + 0.1
+
+    ctx.set_rhs(T(exact(ctx.mesh_boundary()), dev), hh.HHGR_RHS_DIRICHLET)
+    ctx.solve(rel_tol=1e-12, max_cycles=100)
+    p = oracle.MeshProblem(v, t, level, 2)
+    assert np.abs(Nn(ctx.get_solution()) - exact(p.interior_positions(level))).max() < 1e-9
+    ctx.close()
+
+
 def test_mesh_mass_matrix_nodal_source_and_adjoint(dev, hh):
     """The consistent P1 mass matrix on an unstructured mesh (per-tetrahedron
     and per-master rows): its action, b = M f from nodal values of f, and the

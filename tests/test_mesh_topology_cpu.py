@@ -29,7 +29,7 @@ def mesh_check(tmp_path_factory):
     return exe
 
 
-def run(exe, tmp_path, v, t, L, Lc, faults=None):
+def run(exe, tmp_path, v, t, L, Lc, faults=None, k=None):
     mf, of = str(tmp_path / "mesh.txt"), str(tmp_path / "out.txt")
     with open(mf, "w") as fh:
         fh.write(f"{len(v)} {len(t)} {L} {Lc}\n")
@@ -37,7 +37,9 @@ def run(exe, tmp_path, v, t, L, Lc, faults=None):
             fh.write("%.17g %.17g %.17g\n" % tuple(x))
         for q in t:
             fh.write("%d %d %d %d\n" % tuple(q))
-    extra = [",".join(str(q) for q in faults)] if faults else []
+    extra = [",".join(str(q) for q in faults) if faults else "-"] if faults or k is not None else []
+    if k is not None:
+        extra.append(",".join("%.17g" % x for x in k))
     out = subprocess.run([exe, mf, of] + extra, capture_output=True, text=True)
     return out, of
 
@@ -154,3 +156,45 @@ def test_mesh_intact_side_equals_oracle(name, faults, mesh_check, tmp_path):
     assert keep.sum() < n
     assert abs(C[keep][:, keep] - Co[keep][:, keep]).max() <= 1e-13 * abs(Co).max()
     assert abs(C[keep][:, ~keep]).max() == 0.0
+
+
+@pytest.mark.parametrize("name,faults", [("box222p", (1,)), ("octa8", (0, 5)), ("octa4", None)])
+def test_mesh_coefficient_per_tetrahedron_equals_oracle(name, faults, mesh_check, tmp_path):
+    """eq. (2) with k constant on each macro tetrahedron: the volume
+    stencils, master rows, coarsest-level rows and Dirichlet couplings that
+    the host builds, and the intact side of a Dirichlet-Neumann recovery
+    over the same k (eq. (5)), against the oracle's assembly with that k."""
+    v, t = MESHES[name]()
+    L, Lc = 4, 2
+    k = np.random.default_rng(11).uniform(0.2, 5.0, len(t))
+    out, of = run(mesh_check, tmp_path, v, t, L, Lc, faults, k)
+    assert out.returncode == 0, out.stdout + out.stderr
+    head, mats = parse(of)
+    p = oracle.MeshProblem(v, t, L, Lc, k_tet=k)
+    for l in range(Lc, L + 1):
+        n = p.ndof_at(l)
+        W = to_csr(mats[("W", l)], (n, n))
+        Wo = p.matrix(l, "A")
+        assert abs(W - Wo).max() <= 1e-13 * abs(Wo).max(), (l, abs(W - Wo).max())
+    n = p.ndof_at(Lc)
+    WC = to_csr(mats[("WC", Lc)], (n, n))
+    Wo = p.matrix(Lc, "A")
+    assert abs(WC - Wo).max() <= 1e-13 * abs(Wo).max()
+    xyz, dof = p.nodes(L)
+    order = p.boundary_order(L)
+    D = to_csr(mats[("WD", L)], (p.ndof, len(order)))
+    Af = p.matrix(L, "A", full=True).tocsr()
+    interior = np.argsort(np.where(dof >= 0, dof, 1 << 40))[: p.ndof]
+    Do = Af[interior][:, order]
+    assert abs(D - Do).max() <= 1e-13 * abs(Do).max()
+    if faults:
+        for l in range(Lc, L + 1):
+            n = p.ndof_at(l)
+            I = to_csr(mats[("I", l)], (n, n))
+            Io = p.side_matrix(l, list(faults), "intact")
+            assert abs(I - Io).max() <= 1e-13 * abs(Io).max(), (l, abs(I - Io).max())
+        n = p.ndof_at(Lc)
+        C = to_csr(mats[("C", Lc)], (n, n))
+        Co = p.side_matrix(Lc, list(faults), "intact").tocsr()
+        keep = Co.diagonal() > 0
+        assert abs(C[keep][:, keep] - Co[keep][:, keep]).max() <= 1e-13 * abs(Co).max()
