@@ -92,6 +92,7 @@ def lib():
         "ohhg_grad_k": (None, [_vp, _dp, _dp, _dp]),
         "ohhg_create_mesh": (_vp, [C.c_int, _dp, C.c_int, _ip, C.c_int, C.c_int]),
         "ohhg_create_mesh_k": (_vp, [C.c_int, _dp, C.c_int, _ip, C.c_int, C.c_int, _dp]),
+        "ohhg_mesh_grad_k": (None, [_vp, _dp, _dp, _dp]),
         "ohhg_mesh_nodes": (C.c_longlong, [_vp, C.c_int, _dp, _lp]),
         "ohhg_mesh_keys": (None, [_vp, C.c_int, _ip]),
     }
@@ -498,4 +499,14 @@ class MeshProblem(Problem):
         return b
 
     def grad_k(self, u, lam):
-        raise NotImplementedError("not defined on a general macro mesh")
+        raise NotImplementedError("per-element k is not defined on a general macro mesh; see grad_k_tet")
+
+    def grad_k_tet(self, u, lam) -> np.ndarray:
+        """dJ/dk_t = -lambda^T A_t u for a coefficient constant on each macro
+        tetrahedron (A_t: the unit-k stiffness of its elements), summed over
+        the tetrahedron's elements in element order."""
+        u, lam = _f64(u), _f64(lam)
+        ne = self.n_tets * 8 ** self.level
+        out = np.empty(ne)
+        lib().ohhg_mesh_grad_k(self._h, _d(u), _d(lam), _d(out))
+        return out.reshape(self.n_tets, -1).sum(axis=1)

@@ -2083,6 +2083,30 @@ void *ohhg_side_matrix(void *vp, int l, const int *tets, int nt, int side) {
     return A;
 }
 
+/* The same on a general macro mesh (Sec. 3.1): dJ/dk_e = -lambda^T A_e u for
+ * every element e of the finest level, in element order (children of
+ * element e at 8e..8e+7, so macro tetrahedron t owns elements
+ * t 8^L .. (t+1) 8^L - 1); A_e in physical coordinates, u = lambda = 0 at
+ * Dirichlet nodes. */
+void ohhg_mesh_grad_k(void *vp, const double *u, const double *lam, double *out) {
+    oproblem *p = vp;
+    olevel *Lv = &p->lev[p->L];
+#pragma omp parallel for schedule(static)
+    for (i64 e = 0; e < Lv->ne; e++) {
+        double K[4][4], Mm[4][4], ul[4], ll[4];
+        elem_mats_xyz(Lv->xyz, &Lv->ev[4 * e], K, Mm);
+        for (int a = 0; a < 4; a++) {
+            const i64 d = Lv->dof[Lv->ev[4 * e + a]];
+            ul[a] = d >= 0 ? u[d] : 0.0;
+            ll[a] = d >= 0 ? lam[d] : 0.0;
+        }
+        double g = 0.0;
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) g += ll[a] * K[a][b] * ul[b];
+        out[e] = -g;
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Mixed precision: FP32 V-cycle inside an FP64 residual-correction loop      */
 /* ------------------------------------------------------------------------- */

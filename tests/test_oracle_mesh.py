@@ -393,3 +393,34 @@ def test_mesh_coefficient_per_tetrahedron_scaling_and_sides():
     assert abs(Af - k[tet] * Af1).max() <= 1e-14 * abs(Af).max()
     with pytest.raises(ValueError):
         oracle.MeshProblem(v, t, L, 2, k_tet=np.zeros(len(t)))
+
+
+def test_mesh_gradient_per_tetrahedron_matches_finite_differences():
+    """J(k) = 1/2 |u(k) - u_obs|^2 with A(k) u = b and k constant on each
+    macro tetrahedron: the adjoint gradient dJ/dk_t = -lambda^T A_t u
+    (A lambda = u - u_obs) against central differences of direct sparse
+    solves with k_t moved by +-1e-5."""
+    v, t = mesh("octa8")
+    L = 3
+    k = np.random.default_rng(23).uniform(0.5, 3.0, len(t))
+    b = np.random.default_rng(29).uniform(-1, 1, oracle.MeshProblem(v, t, L, 2).ndof)
+    u_obs = np.random.default_rng(31).uniform(-0.1, 0.1, b.size)
+
+    def solve(kk):
+        A = oracle.MeshProblem(v, t, L, 2, k_tet=kk).matrix(L, "A").tocsc()
+        return spla.spsolve(A, b), A
+
+    u, A = solve(k)
+    lam = spla.spsolve(A, u - u_obs)
+    g = oracle.MeshProblem(v, t, L, 2, k_tet=k).grad_k_tet(u, lam)
+    d = 1e-5
+    for q in (0, 3, 6):
+        kp, km = k.copy(), k.copy()
+        kp[q] += d
+        km[q] -= d
+        jp = 0.5 * np.sum((solve(kp)[0] - u_obs) ** 2)
+        jm = 0.5 * np.sum((solve(km)[0] - u_obs) ** 2)
+        fd = (jp - jm) / (2 * d)
+        assert abs(g[q] - fd) <= 1e-6 * max(abs(fd), 1e-12) + 1e-12, (q, g[q], fd)
+    # sum over tetrahedra of k_t dJ/dk_t = -lambda^T A u
+    assert abs(np.dot(k, g) + lam @ (A @ u)) <= 1e-12 * abs(lam @ (A @ u))
