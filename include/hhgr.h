@@ -160,7 +160,8 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * eq. (1): the vector holds g at the boundary nodes in the order of
  * hhgr_mesh_boundary, and b = -A_IB g, the stiffness couplings of the
  * interior nodes to the boundary nodes applied to g),
- * hhgr_mass_apply, hhgr_adjoint_grad (dJ/df only), hhgr_set_solution/get_solution, hhgr_vcycle,
+ * hhgr_mass_apply, hhgr_adjoint_grad (dJ/df, and dJ/dk per macro
+ * tetrahedron), hhgr_set_solution/get_solution, hhgr_vcycle,
  * hhgr_solve, hhgr_inject_fault, hhgr_recover_local, hhgr_recover_dd (its
  * masked coarsest level with a dense inverse of the unfrozen unknowns,
  * computed on the host for each fault set), hhgr_recover_dn (the intact
@@ -194,7 +195,8 @@ int hhgr_mesh_boundary(const hhgr_ctx *ctx, long long *n_boundary, double *host_
  * with k times each element matrix.  Later cycles, solves, recoveries
  * (the intact side of Dirichlet-Neumann keeps its k), batches and
  * HHGR_RHS_DIRICHLET use it; a right-hand side set before is not
- * recomputed.  hhgr_adjoint_grad gives dJ/df only.  EINVAL for a context
+ * recomputed.  hhgr_adjoint_grad gives dJ/df and dJ/dk per tetrahedron.
+ * EINVAL for a context
  * not made by hhgr_create_mesh or a k that is not positive and finite. */
 int hhgr_mesh_set_coeff(hhgr_ctx *ctx, const double *host_k);
 int hhgr_create_mesh(const hhgr_desc *desc, int nv, const double *host_xyz, int nt, const int *host_tets,
@@ -297,8 +299,12 @@ int hhgr_recover_dn(hhgr_ctx *ctx, const int *tets, int n_tets, int n_intact, in
  * multigrid (A is symmetric) to rel_tol and returns dJ/df = M lambda (vector
  * order) and, when variable_coeff = 1 and dev_dJdk != NULL,
  * dJ/dk_T = -lambda^T A_T u (element order, A_T the unit-coefficient element
- * stiffness).  The current solution u is used and left unchanged.  ENOCONV
- * if the adjoint solve did not converge in max_cycles. */
+ * stiffness).  On a mesh context dev_dJdk (optional) receives one value per
+ * macro tetrahedron, dJ/dk_t = -lambda^T A_t u with A_t the unit-coefficient
+ * stiffness of its elements (the coefficient of hhgr_mesh_set_coeff, or
+ * k = 1).  Dirichlet nodes count with u = lambda = 0.  The current solution
+ * u is used and left unchanged.  ENOCONV if the adjoint solve did not
+ * converge in max_cycles. */
 int hhgr_adjoint_grad(hhgr_ctx *ctx, const double *dev_g, double rel_tol, int max_cycles, double *dev_dJdf,
                       double *dev_dJdk);
 

@@ -233,6 +233,7 @@ struct hhgr_ctx {
     std::vector<double> mesh_k;
     std::vector<std::vector<double>> mesh_k_wi;
     std::vector<double> mesh_k_valw;
+    double *mesh_kel = nullptr;  // unit-k matrices of the 6 element types per tetrahedron (finest level)
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tev;
@@ -518,6 +519,7 @@ void carve(hhgr_ctx &c, Carver &cv) {
     if (!c.vk && c.cn <= (c.mesh ? kDenseCoarseMaxMesh : kDenseCoarseMax)) c.cinv = cv.take<double>((size_t)c.cn * c.cn);
     if (c.mesh && c.d.max_faults > 0) c.cinv_dd = cv.take<double>((size_t)c.cn * c.cn);
     if (c.mesh) {
+        c.mesh_kel = cv.take<double>(96 * (size_t)c.n_tets);
         c.n_dir_rows = (int)tp.dir_rows.size();
         c.dir_rows = cv.take<int>(tp.dir_rows.size());
         c.dir_ptr = cv.take<int>(tp.dir_ptr.size());
@@ -1809,6 +1811,11 @@ int create_ctx(const hhgr_desc *desc, std::shared_ptr<const Topology> mesh_topo,
         rc = rc ? rc : upload(*c, c->dir_ptr, tp.dir_ptr.data(), tp.dir_ptr.size() * sizeof(int));
         rc = rc ? rc : upload(*c, c->dir_col, tp.dir_col.data(), tp.dir_col.size() * sizeof(int));
         rc = rc ? rc : upload(*c, c->dir_val, tp.dir_val.data(), tp.dir_val.size() * sizeof(double));
+        std::vector<double> kel;
+        tp.mesh_kuhn_matrices(c->L, kel);
+        rc = rc ? rc : upload(*c, c->mesh_kel, kel.data(), kel.size() * sizeof(double));
+        // the copies read kel before it goes out of scope
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(fail(HHGR_EHIP, "stream synchronize"));
         if (!c->cinv || !coarse_inverse(cs.n, cs.cw, cs.colw, cs.valw, cinv_host))
             return bail(fail(HHGR_EINVAL, "the coarsest-level operator of the mesh is not positive definite"));
         rc = rc ? rc : upload(*c, c->cinv, cinv_host.data(), cinv_host.size() * sizeof(double));
@@ -2349,7 +2356,7 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
     int rc = check_ready(c);
     if (rc) return rc;
     if (!dev_g) return fail(HHGR_EINVAL, "null g");
-    if (dev_dJdk && !c->vk) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
+    if (dev_dJdk && !c->vk && !c->mesh) return fail(HHGR_ESTATE, "dJ/dk needs variable_coeff = 1");
     LevelDev &D = c->lev[c->L];
     const long long ns = D.n_slots;
     const IfcGeom ig = igeom(D, 0, D.n_ifc, nullptr, false);
@@ -2357,7 +2364,7 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
     // save u and b, solve A lambda = g from zero in FP64
     HIPCHK(hipMemcpyAsync(c->aux_u, D.u, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->aux_b, D.b, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if (dev_dJdk)
+    if (dev_dJdk && !c->mesh)
         launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_u);
     to_slots(*c, D, dev_g, D.b, c->stream);
     launch_fill<double>(c->stream, D.u, ns, 0.0);
@@ -2387,7 +2394,12 @@ int hhgr_adjoint_grad(hhgr_ctx *c, const double *dev_g, double rel_tol, int max_
                 launch_mass(c->stream, vint, ig, D.nb15, D.u, D.r, D.h);
             to_user(*c, D, D.r, dev_dJdf, c->stream);
         }
-        if (dev_dJdk) {
+        if (dev_dJdk && c->mesh) {
+            // per macro tetrahedron from the saved u and lambda in slot space
+            // (D.r is free here: it serves as the partial sums)
+            launch_mesh_grad_tet(c->stream, c->n_tets, D.m, D.M, D.rowC, D.C_pad, c->mesh_kel, c->aux_u, D.u, D.r,
+                                 dev_dJdk);
+        } else if (dev_dJdk) {
             launch_slots_to_user<double>(c->stream, vint, c->tetinfo, D.m, D.N, ig, D.ifc_dof, D.u, c->user_l);
             if (c->gen)
                 launch_grad_k15(c->stream, D.N, D.m, c->d.n_sub, c->kel, c->user_u, c->user_l, dev_dJdk);

@@ -247,6 +247,13 @@ void launch_dirichlet_rows(hipStream_t s, int nrows, const int *rows, const int 
 // w, entry e of master t at e n_ifc + t; mesh_kernels.hip)
 void launch_neumann_rhs_w(hipStream_t s, int n_ifc, long long base, const int *nb, const double *wi, int w,
                           const unsigned char *gamma, const double *u, double *b_out);
+// unstructured macro meshes, dJ/dk_t = -lambda^T A_t u per tetrahedron (a
+// coefficient constant on each): u and lam in slot space of the finest
+// level (ghost copies current), kel the unit-k matrices of the 6 element
+// types per tetrahedron (Topology::mesh_kuhn_matrices), partial scratch of
+// nt m (m + 1) / 2 doubles, out nt values (mesh_kernels.hip)
+void launch_mesh_grad_tet(hipStream_t s, int nt, int m, int M, const int2 *rowC, long long C_pad, const double *kel,
+                          const double *u, const double *lam, double *partial, double *out);
 
 // user vector (global lexicographic interior order) <-> slot space; vfull
 // lists every closure node (ghosts receive the user value or the Dirichlet zero)

@@ -722,6 +722,34 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
     return "";
 }
 
+void Topology::mesh_kuhn_matrices(int l, std::vector<double> &kel) const {
+    static const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int m = 1 << l;
+    kel.assign(96 * (size_t)n_tets, 0.0);
+    for (int t = 0; t < n_tets; t++) {
+        const int *tv = &mesh_tets[4 * (size_t)t];
+        double E[3][3];  // index-space unit steps (i, j, k) in physical space
+        for (int a = 0; a < 3; a++)
+            for (int c = 0; c < 3; c++) E[a][c] = (mesh_xyz[3 * tv[a + 1] + c] - mesh_xyz[3 * tv[0] + c]) / m;
+        for (int p = 0; p < 6; p++) {
+            int X[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+            X[1][P[p][0]] = 1;
+            X[2][P[p][0]] = X[2][P[p][1]] = 1;
+            double x[4][3];
+            for (int r = 0; r < 4; r++) {
+                const int ijk[3] = {X[r][0] - X[r][1], X[r][1] - X[r][2], X[r][2]};
+                for (int c = 0; c < 3; c++) x[r][c] = ijk[0] * E[0][c] + ijk[1] * E[1][c] + ijk[2] * E[2][c];
+            }
+            double e[3][3], K[4][4];
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) e[r][c] = x[r + 1][c] - x[0][c];
+            stiffness(e, K);
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) kel[96 * (size_t)t + 16 * p + 4 * a + b] = K[a][b];
+        }
+    }
+}
+
 std::string Topology::mesh_weighted_operators(const double *wt, const unsigned char *dirty,
                                               const std::vector<std::vector<double>> *base, MeshOps &out) const {
     if (!mesh) return "not an unstructured macro mesh";

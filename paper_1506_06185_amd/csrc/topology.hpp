@@ -192,6 +192,13 @@ struct Topology {
     };
     std::string mesh_weighted_operators(const double *wt, const unsigned char *dirty,
                                         const std::vector<std::vector<double>> *base, MeshOps &out) const;
+    // Unit-k stiffness matrices of the 6 element types of a mesh level (kel,
+    // 96 per tetrahedron: type p at 16 p, row-major): the element of type p
+    // with lowest corner X has the index-space corners X, X + e_a, X + e_a +
+    // e_b, X + (1, 1, 1) with (a, b) the first two axes of permutation p in
+    // the order (0,1,2), (0,2,1), (1,0,2), (1,2,0), (2,0,1), (2,1,0), where
+    // closure node (i, j, k) sits at X = (i + j + k, j + k, k).
+    void mesh_kuhn_matrices(int l, std::vector<double> &kel) const;
     bool mesh = false;
     unsigned long long mesh_hash = 0;  // hash of the vertex and tetrahedron lists (set by the engine)
     std::vector<double> mesh_xyz;  // the mesh's vertices (3 each) and tetrahedra (4 vertex ids each)

@@ -295,7 +295,9 @@ class Context:
 
     def adjoint_grad(self, g: torch.Tensor, rel_tol: float = 1e-13, max_cycles: int = 100, want_k: bool = True):
         dJdf = self._vec()
-        dJdk = torch.empty(self.n_elems, dtype=torch.float64, device=self.device) if want_k else None
+        # dJ/dk per element on the cube, per macro tetrahedron on a mesh
+        nk = self.n_tets if self.mesh else self.n_elems
+        dJdk = torch.empty(nk, dtype=torch.float64, device=self.device) if want_k else None
         _check(lib().hhgr_adjoint_grad(self._h, _ptr(g), float(rel_tol), int(max_cycles), _ptr(dJdf),
                                        _ptr(dJdk) if dJdk is not None else None))
         return dJdf, dJdk

@@ -114,6 +114,8 @@ void launch_mesh_slots_to_user(hipStream_t, const VolGeom &, long long, long lon
 void launch_mass(hipStream_t, const VolGeom &, const IfcGeom &, const int *, const double *, double *, double) {}
 void launch_dirichlet_rows(hipStream_t, int, const int *, const int *, const int *, const double *, const double *,
                            double *) {}
+void launch_mesh_grad_tet(hipStream_t, int, int, int, const int2 *, long long, const double *, const double *,
+                          const double *, double *, double *) {}
 void launch_neumann_rhs_w(hipStream_t, int, long long, const int *, const double *, int, const unsigned char *,
                           const double *, double *) {}
 void launch_update_add(hipStream_t, const VolDesc *, int, long long, const IfcGeom &, double *, const float *) {}

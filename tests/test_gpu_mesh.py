@@ -423,6 +423,36 @@ def test_mesh_coefficient_per_tetrahedron(dev, hh, name, level):
     c1.close()
 
 
+@pytest.mark.parametrize("name,level", [("box222p", 4), ("octa8", 5)])
+def test_mesh_gradient_per_tetrahedron(dev, hh, name, level):
+    """The adjoint on a mesh with k constant on each macro tetrahedron:
+    dJ/dk_t = -lambda^T A_t u per tetrahedron (and dJ/df = M lambda) from
+    the GPU's adjoint solve, against the oracle's element sums with the
+    oracle's lambda for the same u; the sum of k_t dJ/dk_t equals
+    -lambda^T A u = -lambda^T b."""
+    print(f"\n[mesh dJ/dk per tet] {name} level={level}", flush=True)
+    v, t = mesh(name)
+    k = np.random.default_rng(53).uniform(0.3, 3.0, len(t))
+    p = oracle.MeshProblem(v, t, level, 2, k_tet=k)
+    b = np.random.default_rng(59).uniform(-1, 1, p.ndof)
+    ctx = context(hh, dev, name, level)
+    ctx.set_mesh_coeff(k)
+    ctx.set_rhs(T(b, dev), hh.HHGR_RHS_LOAD)
+    ctx.solve(rel_tol=1e-13, max_cycles=80, raise_on_noconv=False)
+    u = Nn(ctx.get_solution())
+    g = u - np.random.default_rng(61).uniform(-0.1, 0.1, p.ndof)
+    dJdf, dJdk = ctx.adjoint_grad(T(g, dev), rel_tol=1e-12, max_cycles=100)
+    lam, _, _ = p.solve(g, rtol=1e-14, max_cycles=100)
+    go = p.grad_k_tet(u, lam)
+    assert dJdk.shape == (len(t),)
+    assert rel(Nn(dJdk), go) < 1e-9
+    assert rel(Nn(dJdf), p.apply_M(lam)) < 1e-10
+    assert abs(np.dot(k, Nn(dJdk)) + lam @ b) <= 1e-9 * abs(lam @ b)
+    # the forward state is kept
+    assert rel(Nn(ctx.get_solution()), u) == 0.0
+    ctx.close()
+
+
 def test_mesh_coefficient_transmission(dev, hh):
     """Two layers of k (1 below z = 1, 5 above) on the unmoved 2 x 2 x 2 box:
     the function that is linear on each layer with equal normal fluxes
