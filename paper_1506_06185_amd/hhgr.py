@@ -323,11 +323,14 @@ class Context:
     def set_mesh_coeff(self, k_tet=None):
         """Coefficient k of eq. (2) constant on each macro tetrahedron of a
         mesh context (host values, one per tetrahedron; None: k = 1)."""
+        self.version += 1
         if k_tet is None:
             _check(lib().hhgr_mesh_set_coeff(self._h, None))
             return
         import numpy as np
 
+        if isinstance(k_tet, torch.Tensor):
+            k_tet = k_tet.detach().cpu().numpy()
         k = np.ascontiguousarray(np.asarray(k_tet, dtype=np.float64).reshape(-1))
         if k.size != self.n_tets:
             raise ValueError("k_tet needs one value per tetrahedron")
@@ -433,7 +436,8 @@ class Batch:
 
 
 class HHGSolve(torch.autograd.Function):
-    """u = A(k)^{-1} M f on a context created with variable_coeff=True.
+    """u = A(k)^{-1} M f on a context created with variable_coeff=True (k per
+    element), or on a mesh context (k per macro tetrahedron).
 
     forward(ctx_obj, f, k) -> u; backward returns dJ/df = M lambda and
     dJ/dk_T = -lambda^T A_T u with A lambda = dJ/du (adjoint multigrid solve).
@@ -445,7 +449,10 @@ class HHGSolve(torch.autograd.Function):
     @staticmethod
     def forward(fctx, ctx_obj: Context, f: torch.Tensor, k: torch.Tensor, rel_tol: float = 1e-13,
                 max_cycles: int = 100):
-        ctx_obj.set_coeff(k.contiguous())
+        if ctx_obj.mesh:
+            ctx_obj.set_mesh_coeff(k)
+        else:
+            ctx_obj.set_coeff(k.contiguous())
         ctx_obj.set_rhs(f.contiguous(), HHGR_RHS_NODAL_F)
         ctx_obj.set_solution(None)
         ctx_obj.solve(rel_tol, max_cycles)
@@ -461,7 +468,10 @@ class HHGSolve(torch.autograd.Function):
         c = fctx.ctx_obj
         u, k = fctx.saved_tensors
         if c.version != fctx.version:
-            c.set_coeff(k.detach().contiguous())
+            if c.mesh:
+                c.set_mesh_coeff(k)
+            else:
+                c.set_coeff(k.detach().contiguous())
             c.set_solution(u.detach().contiguous())
             fctx.version = c.version
         dJdf, dJdk = c.adjoint_grad(g.contiguous(), fctx.rel_tol, fctx.max_cycles, want_k=True)

@@ -453,6 +453,40 @@ def test_mesh_gradient_per_tetrahedron(dev, hh, name, level):
     ctx.close()
 
 
+def test_mesh_autograd_function(dev, hh):
+    """HHGSolve on a mesh context: u = A(k)^-1 M f with k per macro
+    tetrahedron inside torch.autograd; the gradients of J = 1/2 |u - u_obs|^2
+    with respect to k agree with central differences of GPU solves, and
+    two forwards before one backward still give the first one's gradient."""
+    name, level = "octa4", 4
+    print(f"\n[mesh autograd] {name} level={level}", flush=True)
+    v, t = mesh(name)
+    ctx = context(hh, dev, name, level)
+    n = ctx.n_dofs
+    f = T(np.random.default_rng(67).uniform(0.5, 1.5, n), dev)
+    u_obs = T(np.random.default_rng(71).uniform(-0.01, 0.01, n), dev)
+    k0 = np.random.default_rng(73).uniform(0.5, 2.0, len(t))
+
+    def J(kk):
+        u = hh.HHGSolve.apply(ctx, f, T(kk, dev), 1e-13, 100)
+        return 0.5 * float(((u - u_obs) ** 2).sum())
+
+    kT = T(k0, dev).requires_grad_(True)
+    u = hh.HHGSolve.apply(ctx, f, kT, 1e-13, 100)
+    loss = 0.5 * ((u - u_obs) ** 2).sum()
+    J(k0 * 1.5)  # the context is used in between
+    loss.backward()
+    g = Nn(kT.grad)
+    d = 1e-5
+    for q in range(len(t)):
+        kp, km = k0.copy(), k0.copy()
+        kp[q] += d
+        km[q] -= d
+        fd = (J(kp) - J(km)) / (2 * d)
+        assert abs(g[q] - fd) <= 1e-5 * abs(fd) + 1e-14, (q, g[q], fd)
+    ctx.close()
+
+
 def test_mesh_coefficient_transmission(dev, hh):
     """Two layers of k (1 below z = 1, 5 above) on the unmoved 2 x 2 x 2 box:
     the function that is linear on each layer with equal normal fluxes
