@@ -2324,8 +2324,10 @@ int hhgr_recover_dn(hhgr_ctx *c, const int *tets, int n_tets, int n_intact, int 
         refresh_faulty_ghosts(*c, ft, c->stream);
         HIPCHK(hipEventRecord(c->ev_fork, c->stream));
         HIPCHK(hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
-        for (int e = 0; e < eta; e++) vcycle<double>(*c, VL, c->L, false, c->stream2);
+        // the intact cycle first: its launches then reach the GPU while the
+        // host is still launching the many small local kernels
         vcycle<double>(*c, VI, c->L, false, c->stream);
+        for (int e = 0; e < eta; e++) vcycle<double>(*c, VL, c->L, false, c->stream2);
         HIPCHK(hipEventRecord(c->ev_join, c->stream2));
         HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
     }
@@ -3003,16 +3005,22 @@ int hhgr_batch_run(hhgr_batch *b, double rel_tol, int max_cycles, hhgr_report *r
             if (ce != hipSuccess) return fail(HHGR_EHIP, std::string("batch instantiate: ") + hipGetErrorString(ce));
             b->sig_in_graph = sig;
         }
-        // local cycles of recoveries starting now, concurrent with the graph
+        // local cycles of recoveries starting now, concurrent with the graph:
+        // forked before the graph launch, launched after it (the host then
+        // launches the many small local kernels while the graph runs)
         for (size_t a = 0; a < active.size(); a++) {
             const int q = sig[2 * a], mode = sig[2 * a + 1];
             if (!(mode & kModeLocal)) continue;
             HIPCHK(hipEventRecord(b->evl[2 * q], b->stream));
             HIPCHK(hipStreamWaitEvent(b->branch2[q], b->evl[2 * q], 0));
+        }
+        HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        for (size_t a = 0; a < active.size(); a++) {
+            const int q = sig[2 * a], mode = sig[2 * a + 1];
+            if (!(mode & kModeLocal)) continue;
             dd_local(*b->ctx[q], b->dd[q].n_local, b->branch2[q]);
             HIPCHK(hipEventRecord(b->evl[2 * q + 1], b->branch2[q]));
         }
-        HIPCHK(hipGraphLaunch(b->gexec, b->stream));
         for (size_t a = 0; a < active.size(); a++) {
             const int q = sig[2 * a], mode = sig[2 * a + 1];
             if (!(mode & kModeLocal)) continue;
