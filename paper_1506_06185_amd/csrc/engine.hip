@@ -1424,7 +1424,7 @@ int dn_setup(hhgr_ctx &c, const std::vector<int> &ft) {
         for (int t = 0; t < c.n_tets; t++) wt[t] = isf[t] ? 0.0 : c.mesh_k.empty() ? 1.0 : c.mesh_k[t];
         Topology::MeshOps I;
         const std::string e =
-            c.topo->mesh_weighted_operators(wt.data(), isf.data(), c.mesh_k.empty() ? nullptr : &c.mesh_k_wi, I);
+            c.topo->mesh_weighted_operators(wt.data(), isf.data(), c.mesh_k.empty() ? nullptr : &c.mesh_k_wi, I, false);
         if (!e.empty()) {
             HIPCHK(hipStreamSynchronize(c.stream));
             return fail(HHGR_EINVAL, e);

@@ -418,10 +418,11 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
         // finest level: the couplings of interior nodes (slot, boundary
         // index, stiffness) to Dirichlet nodes, for eliminated boundary data
         std::map<std::pair<int, int>, double> dir;
-        // the same couplings summed per tetrahedron (for a coefficient
-        // constant on each tetrahedron): (row slot, boundary index, tet, value)
-        std::vector<std::tuple<int, int, int, double>> dparts;
-        std::map<std::pair<int, int>, double> dtet;
+        if (l == L) {
+            dir_bnd_ptr.assign(nt + 1, 0);
+            dir_bnd_pos.clear();
+            dir_bnd_idx.clear();
+        }
         // ghost copies
         Lv.nbr.assign(6 * (size_t)Lv.n_ifc, (int)Lv.zero_slot);
         Lv.tg_ptr.assign(nt + 1, 0);
@@ -470,6 +471,14 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                 }
             }
             fill_cslot(t);
+            if (l == L) {
+                for (int q = 0; q < Lv.C_pad; q++)
+                    if (cbnd[q] >= 0) {
+                        dir_bnd_pos.push_back(q);
+                        dir_bnd_idx.push_back(cbnd[q]);
+                    }
+                dir_bnd_ptr[t + 1] = (int)dir_bnd_pos.size();
+            }
             if (l == L)
                 for (int k = 1; k < m; k++)
                     for (int j = 1; j < m - k; j++)
@@ -478,10 +487,7 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             const int own = cslot[Lv.lay.index(i, j, k)];
                             for (int n = 1; n < 15; n++) {
                                 const int q = Lv.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2]);
-                                if (cbnd[q] >= 0) {
-                                    dir[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
-                                    dtet[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
-                                }
+                                if (cbnd[q] >= 0) dir[{own, cbnd[q]}] += Lv.mesh_w15[15 * (size_t)t + n];
                             }
                         }
             for (int k = 0; k <= m; k++)
@@ -505,10 +511,7 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             if (!in) continue;
                             for (int r = 0; r < 4; r++) {
                                 const int pq = Lv.lay.index(p[r][0], p[r][1], p[r][2]);
-                                if (cbnd[pq] >= 0) {
-                                    dir[{(int)own, cbnd[pq]}] += K[q][A.self][r];
-                                    dtet[{(int)own, cbnd[pq]}] += K[q][A.self][r];
-                                }
+                                if (cbnd[pq] >= 0) dir[{(int)own, cbnd[pq]}] += K[q][A.self][r];
                                 const int s = cslot[pq];
                                 size_t e = 0;
                                 while (e < row.size() && row[e].s != s) e++;
@@ -518,8 +521,6 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                             }
                         }
                     }
-            for (const auto &e : dtet) dparts.emplace_back(e.first.first, e.first.second, t, e.second);
-            dtet.clear();
         }
         for (const auto &row : R) width = std::max(width, (int)row.size());
         if (l == L) {
@@ -537,16 +538,6 @@ std::string Topology::build_mesh(int nv_, const double *xyz, int nt, const int *
                 dir_val.push_back(e.second);
             }
             dir_ptr.push_back((int)dir_col.size());
-            std::map<std::pair<int, int>, int> at;
-            for (const auto &e : dir) at.emplace(e.first, (int)at.size());
-            dir_part_e.clear();
-            dir_part_t.clear();
-            dir_part_v.clear();
-            for (const auto &d : dparts) {
-                dir_part_e.push_back(at.at({std::get<0>(d), std::get<1>(d)}));
-                dir_part_t.push_back(std::get<2>(d));
-                dir_part_v.push_back(std::get<3>(d));
-            }
         }
         build_closure_tables(Lv);
     }
@@ -751,7 +742,8 @@ void Topology::mesh_kuhn_matrices(int l, std::vector<double> &kel) const {
 }
 
 std::string Topology::mesh_weighted_operators(const double *wt, const unsigned char *dirty,
-                                              const std::vector<std::vector<double>> *base, MeshOps &out) const {
+                                              const std::vector<std::vector<double>> *base, MeshOps &out,
+                                              bool with_dir) const {
     if (!mesh) return "not an unstructured macro mesh";
     const int nt = n_tets;
     const std::vector<Around> around = elements_around();
@@ -871,9 +863,70 @@ std::string Topology::mesh_weighted_operators(const double *wt, const unsigned c
                     return "internal: weighted coarse entry outside the row";
         }
     }
-    // finest level: the couplings to the Dirichlet boundary nodes
-    out.dir_val.assign(dir_val.size(), 0.0);
-    for (size_t q = 0; q < dir_part_e.size(); q++) out.dir_val[dir_part_e[q]] += wt[dir_part_t[q]] * dir_part_v[q];
+    // finest level: the couplings to the Dirichlet boundary nodes, summed
+    // in the order of build_mesh (same keys, so the same entries)
+    if (!with_dir) return "";
+    const TopoLevel &F = lev[L];
+    const int m = F.m;
+    std::map<std::pair<int, int>, double> dir;
+    std::vector<int> cbnd(F.C_pad, -1);
+    cslot.assign(F.C_pad, (int)F.zero_slot);
+    for (int t = 0; t < nt; t++) {
+        if (dir_bnd_ptr[t] == dir_bnd_ptr[t + 1]) continue;
+        int g = F.tg_ptr[t];
+        for (int k = 0; k <= m; k++)
+            for (int j = 0; j <= m - k; j++)
+                for (int i = 0; i <= m - k - j; i++) {
+                    const int idx = F.lay.index(i, j, k);
+                    if (i == 0 || j == 0 || k == 0 || i + j + k == m) {
+                        if (g >= F.tg_ptr[t + 1] || F.tg_dst[g] != (long long)t * F.C_pad + idx)
+                            return "internal: ghost list out of order";
+                        cslot[idx] = F.tg_src[g++];
+                    } else {
+                        cslot[idx] = (int)((long long)t * F.C_pad + idx);
+                    }
+                }
+        for (int q = dir_bnd_ptr[t]; q < dir_bnd_ptr[t + 1]; q++) cbnd[dir_bnd_pos[q]] = dir_bnd_idx[q];
+        for (int k = 1; k < m; k++)
+            for (int j = 1; j < m - k; j++)
+                for (int i = 1; i + j + k <= m - 1; i++) {
+                    if (!(i == 1 || j == 1 || k == 1 || i + j + k == m - 1)) continue;
+                    const int own = cslot[F.lay.index(i, j, k)];
+                    for (int n = 1; n < 15; n++) {
+                        const int q = F.lay.index(i + kIdx15[n][0], j + kIdx15[n][1], k + kIdx15[n][2]);
+                        if (cbnd[q] >= 0) dir[{own, cbnd[q]}] += wt[t] * F.mesh_w15[15 * (size_t)t + n];
+                    }
+                }
+        double K[24][4][4], Mq[24];
+        star_matrices(mesh_xyz.data(), &mesh_tets[4 * (size_t)t], m, around, K, Mq);
+        for (int k = 0; k <= m; k++)
+            for (int j = 0; j <= m - k; j++)
+                for (int i = 0; i <= m - k - j; i++) {
+                    if (!(i == 0 || j == 0 || k == 0 || i + j + k == m)) continue;
+                    const long long own = cslot[F.lay.index(i, j, k)];
+                    if (own == F.zero_slot) continue;
+                    for (int q = 0; q < 24; q++) {
+                        const Around &A = around[q];
+                        int p[4][3];
+                        bool in = true;
+                        for (int r = 0; r < 4 && in; r++) {
+                            p[r][0] = i + A.d[r][0] - A.d[A.self][0];
+                            p[r][1] = j + A.d[r][1] - A.d[A.self][1];
+                            p[r][2] = k + A.d[r][2] - A.d[A.self][2];
+                            in = p[r][0] >= 0 && p[r][1] >= 0 && p[r][2] >= 0 && p[r][0] + p[r][1] + p[r][2] <= m;
+                        }
+                        if (!in) continue;
+                        for (int r = 0; r < 4; r++) {
+                            const int pq = F.lay.index(p[r][0], p[r][1], p[r][2]);
+                            if (cbnd[pq] >= 0) dir[{(int)own, cbnd[pq]}] += wt[t] * K[q][A.self][r];
+                        }
+                    }
+                }
+        for (int q = dir_bnd_ptr[t]; q < dir_bnd_ptr[t + 1]; q++) cbnd[dir_bnd_pos[q]] = -1;
+    }
+    if (dir.size() != dir_val.size()) return "internal: Dirichlet couplings of a different pattern";
+    out.dir_val.clear();
+    for (const auto &e : dir) out.dir_val.push_back(e.second);
     return "";
 }
 

@@ -180,8 +180,8 @@ struct Topology {
     // tetrahedron's elements, as the intact side of a Dirichlet-Neumann
     // recovery does, Sec. 4.3, eq. (5)): per level the volume stencils
     // (15 per tetrahedron) and the master rows (the layout of mesh_wi), the
-    // coarsest-level rows (the layout of coarse.valw) and the finest level's
-    // Dirichlet couplings (the layout of dir_val).  Master rows are summed
+    // coarsest-level rows (the layout of coarse.valw) and, with with_dir, the
+    // finest level's Dirichlet couplings (the layout of dir_val).  Master rows are summed
     // again only for masters with a copy in a closure flagged in dirty;
     // the others are taken from base (per level; null: the k = 1 rows), which
     // must hold them for the same weights.  Returns an empty string on
@@ -191,7 +191,8 @@ struct Topology {
         std::vector<double> valw, dir_val;
     };
     std::string mesh_weighted_operators(const double *wt, const unsigned char *dirty,
-                                        const std::vector<std::vector<double>> *base, MeshOps &out) const;
+                                        const std::vector<std::vector<double>> *base, MeshOps &out,
+                                        bool with_dir = true) const;
     // Unit-k stiffness matrices of the 6 element types of a mesh level (kel,
     // 96 per tetrahedron: type p at 16 p, row-major): the element of type p
     // with lowest corner X has the index-space corners X, X + e_a, X + e_a +
@@ -214,10 +215,9 @@ struct Topology {
     std::vector<double> bnd_xyz;
     std::vector<int> dir_rows, dir_ptr, dir_col;
     std::vector<double> dir_val;
-    // the same couplings per tetrahedron: entry dir_part_e, tetrahedron
-    // dir_part_t, value dir_part_v (entries in summation order)
-    std::vector<int> dir_part_e, dir_part_t;
-    std::vector<double> dir_part_v;
+    // per tetrahedron (CSR over dir_bnd_ptr): the closure positions of its
+    // Dirichlet boundary nodes and their boundary indices
+    std::vector<int> dir_bnd_ptr, dir_bnd_pos, dir_bnd_idx;
 
     // slot of grid node X at level l (zero slot for boundary nodes)
     long long slot_of(int l, int x, int y, int z) const;

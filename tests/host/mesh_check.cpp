@@ -193,7 +193,7 @@ int main(int argc, char **argv) {
         if (e.empty() && any_fault) {
             std::vector<double> wi(nt);
             for (int t = 0; t < nt; t++) wi[t] = faulty[t] ? 0.0 : kt[t];
-            e = tp.mesh_weighted_operators(wi.data(), faulty.data(), &K.wi, I);
+            e = tp.mesh_weighted_operators(wi.data(), faulty.data(), &K.wi, I, false);
         }
         if (!e.empty()) {
             std::printf("error: %s\n", e.c_str());
@@ -245,12 +245,14 @@ int main(int argc, char **argv) {
                 std::fprintf(o, "%lld %d %.17g\n", user_of[L][tp.dir_rows[q]], tp.dir_col[e2], K.dir_val[e2]);
         std::fprintf(o, "end\n");
         // with k = 1 the weighted tables are the plain ones, bit for bit
-        // (the Dirichlet couplings are summed per tetrahedron first)
-        if (argc == 4)
+        if (argc == 4) {
             for (int l = Lc; l <= L; l++) {
                 CHECK(K.wi[l] == tp.lev[l].mesh_wi);
                 CHECK(K.w15[l] == tp.lev[l].mesh_w15);
             }
+            CHECK(K.dir_val == tp.dir_val);
+            CHECK(K.valw == tp.coarse.valw);
+        }
         if (any_fault) {
             write_ops("I", "C", I, true);
             // masters that no faulty closure holds keep the weighted rows
