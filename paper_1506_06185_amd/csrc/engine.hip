@@ -1907,8 +1907,9 @@ int hhgr_mesh_set_coeff(hhgr_ctx *c, const double *host_k) {
     }
     rc = rc ? rc : upload(*c, c->cinv, inv.data(), inv.size() * sizeof(double));
     rc = rc ? rc : upload(*c, c->dir_val, K.dir_val.data(), K.dir_val.size() * sizeof(double));
-    CHKLAUNCH();
+    const hipError_t le = hipGetLastError();
     HIPCHK(hipStreamSynchronize(c->stream));  // the copies read K and inv
+    if (le != hipSuccess) return fail(HHGR_EHIP, std::string("kernel launch: ") + hipGetErrorString(le));
     if (rc) return rc;
     if (host_k) {
         c->mesh_k.assign(host_k, host_k + c->n_tets);
