@@ -350,6 +350,45 @@ def leg_vcycle_rates(hh, torch, dev, tune_cache, n_sub=2, levels=(5, 6, 7), cycl
     return out
 
 
+def leg_recoveries(hh, torch, dev, tune_cache, n_sub=2, level=7, reps=5):
+    """Time of one recovery call on the headline problem after 5 cycles
+    (nodal sine source), median over reps, each after a fresh fault of the
+    same tetrahedra: local recovery (Alg. 1 a), 3 cycles on one
+    tetrahedron), Dirichlet-Dirichlet (Alg. 1 b), 1 intact cycle beside 3
+    local cycles on two tetrahedra) and Dirichlet-Neumann (Alg. 2, 2 rounds
+    of 1 intact cycle beside 2 local ones), with one plain global cycle for
+    comparison (DD overlaps its sides, so it costs about max(intact, local)
+    plus its set-up)."""
+    from paper_1506_06185_amd import inputs
+
+    ctx = hh.Context(device=dev, n_sub=n_sub, level=level)
+    ctx.autotune(tune_cache)
+    ctx.set_rhs(torch.from_numpy(inputs.sine_source(n_sub, level)).to(dev), hh.HHGR_RHS_NODAL_F)
+    ctx.vcycle(5)
+    t1 = inputs.fault_tet(n_sub, seed=0)
+    t2 = inputs.second_fault_tet(n_sub, t1)
+    calls = {
+        "global_cycle": ([], lambda: ctx.vcycle(1)),
+        "local_3_cycles_1_tet": ([t1], lambda: ctx.recover_local(t1, 3)),
+        "dd_1_intact_3_local_2_tets": ([t1, t2], lambda: ctx.recover_dd([t1, t2], 1, 3)),
+        "dn_2_rounds_eta_2_2_tets": ([t1, t2], lambda: ctx.recover_dn([t1, t2], 2, 2)),
+    }
+    out = {"workload": f"n_sub={n_sub} level={level}, nodal sine source, after 5 cycles; faulty tets {t1}, {t2}"}
+    for name, (tets, fn) in calls.items():
+        ts = []
+        for _ in range(reps + 1):
+            for t in tets:
+                ctx.inject_fault(t)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out[name] = {"ms": round(1e3 * float(sorted(ts[1:])[len(ts[1:]) // 2]), 3)}
+    ctx.close()
+    return out
+
+
 def leg_mesh(hh, torch, dev, steps, warmup, graph, tune_cache, nx=3, level=7):
     """The fault job on an unstructured macro mesh: the box [0, nx]^3 of unit
     cubes split into 5 tetrahedra each (vertices moved by 0.12 U[-1,1]^3,
@@ -721,6 +760,10 @@ def main():
     if not args.no_extra:
         log("V-cycle rates")
         rates = leg_vcycle_rates(hh, torch, dev, tune_cache)
+    recoveries = None
+    if not args.no_extra:
+        log("recovery times")
+        recoveries = leg_recoveries(hh, torch, dev, tune_cache)
     mesh = None
     if not args.no_mesh:
         log("unstructured macro mesh leg")
@@ -780,6 +823,7 @@ def main():
         "roofline": roofline,
         "uninstrumented": uninstrumented,
         "vcycle_rates": rates,
+        "recoveries": recoveries,
         "mixed": mixed,
         "general_mesh": general,
         "unstructured_mesh": mesh,
