@@ -135,7 +135,8 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
 
 /* Unstructured macro meshes (Sec. 3.1: the macro mesh is an arbitrary
  * conforming tetrahedral mesh whose elements are refined regularly; eq. (2)
- * assembled with P1 elements in physical coordinates, k = 1).  Host arrays,
+ * assembled with P1 elements in physical coordinates, k = 1 until
+ * hhgr_mesh_set_coeff).  Host arrays,
  * read during the call: nv vertices (host_xyz, 3 doubles each) and nt
  * tetrahedra (host_tets, 4 vertex ids each).  Every tetrahedron lists its
  * vertices by a proper 4-colouring of the mesh: a vertex takes the same
@@ -169,7 +170,7 @@ int hhgr_set_geometry(hhgr_ctx *ctx, const double *host_xyz);
  * coarsest level inverted densely, both on the host for each fault set;
  * eq. (5)), hhgr_set_graph, the hhgr_batch_* calls, hhgr_autotune (the
  * class pass, as on a general mesh; cache entries keyed by a hash of the
- * vertex and tetrahedron lists),
+ * vertex and tetrahedron lists), hhgr_mesh_set_coeff,
  * hhgr_kernel_timing/stats and hhgr_debug_op (ops 0, 3 to 5, 7, 8 + class
  * mask); every other call returns EINVAL for it.  hhgr_sizes reports the
  * interior unknowns, nt and nt 8^level.  EINVAL for a mesh that is not
