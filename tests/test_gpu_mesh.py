@@ -548,7 +548,8 @@ def test_mesh_full_size_properties(dev, hh):
     1e-12, x.Ax > 0), and after a solve to 1e-12 a fault followed by enough
     local recovery cycles restores the solution (the local Dirichlet problem
     with exact interface data has the global solution as its solution), and
-    so do the Dirichlet-Dirichlet and Dirichlet-Neumann recoveries."""
+    so do the Dirichlet-Dirichlet and Dirichlet-Neumann recoveries, also with
+    a coefficient per macro tetrahedron."""
     v, t = inputs.box_mesh(3, 3, 3)
     v = inputs.perturb_mesh(v, seed=0, amplitude=0.12)
     level = 7
@@ -584,6 +585,19 @@ def test_mesh_full_size_properties(dev, hh):
         recover()
         du = float(torch.linalg.norm(ctx.get_solution() - u) / torch.linalg.norm(u))
         print(f"after fault + {name} recovery: rel change {du:.2e}")
+        assert du < 1e-9, name
+    # the same with a coefficient per tetrahedron (k in [0.2, 5])
+    ctx.set_mesh_coeff(np.random.default_rng(79).uniform(0.2, 5.0, len(t)))
+    ctx.set_solution(None)
+    cyc, relres, _ = ctx.solve(rel_tol=1e-12, max_cycles=100)
+    u = ctx.get_solution().clone()
+    for name, recover in (("local", lambda: ctx.recover_local(tet, 30)),
+                          ("dd", lambda: ctx.recover_dd([tet], 2, 30)), ("dn", lambda: ctx.recover_dn([tet], 4, 8))):
+        ctx.set_solution(u)
+        ctx.inject_fault(tet)
+        recover()
+        du = float(torch.linalg.norm(ctx.get_solution() - u) / torch.linalg.norm(u))
+        print(f"k per tet: solve {cyc} cycles to {relres:.2e}; after fault + {name} recovery: rel change {du:.2e}")
         assert du < 1e-9, name
     ctx.close()
 
